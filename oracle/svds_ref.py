@@ -1,0 +1,268 @@
+"""FP64 CPU oracle of the augmented, restarted Lanczos-bidiagonalization
+truncated SVD (the method of Sec. 2.1: Alg. 1, Proposition 1, eqs. (2)-(7),
+Alg. 2).
+
+TEST INFRASTRUCTURE: this package is the CPU oracle.  Only the test suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it; the
+product path never does.  Plain NumPy/SciPy in float64, written for
+readability, not speed: every step is done the way the paper states it, with
+library primitives (sparse mat-vec, dense mat-vec, LAPACK gesvd) as the steps.
+
+Readings of the paper used here (where it is silent or ambiguous):
+
+* Re-orthogonalisation (Sec. 2.1, text after Alg. 1, and the remark after
+  Alg. 2 that step 10 needs it too): classical Gram-Schmidt applied twice
+  (CGS2) to the unnormalised vector, before its norm becomes alpha or beta.
+* LBP(A, t+1) (Alg. 2 step 2) is run until v_{t+1} and beta_t exist; u_{t+1}
+  and alpha_{t+1} are never used, so they are not formed.  Mat-vec count:
+  2t for the first LBP, 2(t-k) per restart.
+* An SVD of T(1:t,1:t) follows every Lanczos cycle; at most ``maxit`` cycles
+  (maxit-1 restarts).  The output is formed from the last SVD.
+* Convergence test (eq. (4), Alg. 2 step 5): |beta_t Uh(t,j)| / sigma_j < tol
+  for every j <= k, strict; sigma_j is floored at max(2^-52 sigma_1,
+  smallest normal) so a zero singular value cannot divide by zero.
+* Breakdown (norm after CGS2 <= 1e-14 * sigma_est, sigma_est = largest
+  alpha, beta or sigma_1 seen so far): the vector is replaced by a Philox
+  normal vector (stream 1 + number of earlier breakdowns), re-orthogonalised
+  by CGS2 against the same basis, normalised, and 0 is stored in T.
+* Signs: each output pair (u_j, v_j) is flipped so that the entry of v_j of
+  largest magnitude (lowest index on ties) is positive.
+
+t (the paper's Lanczos dimension) is called p here.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from .philox import normal_vector
+
+BREAKDOWN_REL = 1e-14
+TINY = np.finfo(np.float64).tiny
+EPS = 2.0 ** -52
+
+
+@dataclass
+class SvdsInfo:
+    cycles: int = 0
+    restarts: int = 0
+    n_spmv: int = 0        # products A x
+    n_spmvT: int = 0       # products A^T y
+    breakdowns: int = 0
+    converged: bool = False
+    nconv: int = 0
+    res_est: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    sigma_est: float = 0.0
+
+
+class _Op:
+    """A as the two products the method needs; counts every call."""
+
+    def __init__(self, A, info: SvdsInfo):
+        self.A = A
+        self.AT = A.T
+        self.info = info
+        self.m, self.n = A.shape
+
+    def mv(self, x):
+        self.info.n_spmv += 1
+        return np.asarray(self.A @ x, dtype=np.float64).ravel()
+
+    def rmv(self, y):
+        self.info.n_spmvT += 1
+        return np.asarray(self.AT @ y, dtype=np.float64).ravel()
+
+
+def cgs2(w: np.ndarray, Q: np.ndarray) -> np.ndarray:
+    """Full re-orthogonalisation w <- (I - Q Q^T) w, done twice (CGS2)."""
+    if Q.shape[1] == 0:
+        return w
+    for _ in range(2):
+        h = Q.T @ w
+        w = w - Q @ h
+    return w
+
+
+class _State:
+    """Workspace of one solve: U (m x p), V (n x (p+1)), T ((p+1) x (p+1))."""
+
+    def __init__(self, op: _Op, p: int, seed: int, info: SvdsInfo):
+        self.op = op
+        self.p = p
+        self.seed = seed
+        self.info = info
+        self.U = np.zeros((op.m, p), order="F")
+        self.V = np.zeros((op.n, p + 1), order="F")
+        self.T = np.zeros((p + 1, p + 1))
+
+    def _finish(self, w, Q):
+        """CGS2 against Q, norm, breakdown handling; returns (vector, norm)."""
+        w = cgs2(w, Q)
+        nrm = float(np.linalg.norm(w))
+        if nrm <= BREAKDOWN_REL * self.info.sigma_est:
+            self.info.breakdowns += 1
+            r = normal_vector(w.shape[0], self.seed, self.info.breakdowns)
+            r = cgs2(r, Q)
+            return r / np.linalg.norm(r), 0.0
+        self.info.sigma_est = max(self.info.sigma_est, nrm)
+        return w / nrm, nrm
+
+    def u_step(self, i, w):
+        """u_i from w (0-based column i): re-orthogonalise against U[:, :i]."""
+        self.U[:, i], a = self._finish(w, self.U[:, :i])
+        self.T[i, i] = a
+
+    def v_step(self, i):
+        """Alg. 1 steps 5-6: v_{i+1} = A^T u_i - alpha_i v_i, reorth, beta_i."""
+        w = self.op.rmv(self.U[:, i]) - self.T[i, i] * self.V[:, i]
+        self.V[:, i + 1], b = self._finish(w, self.V[:, :i + 1])
+        self.T[i, i + 1] = b
+
+    def lanczos(self, i0):
+        """Alg. 1 loop from 0-based column i0 (u_{i0}, v_{i0} already set)
+        until v_p and beta_{p-1} (0-based) exist."""
+        p = self.p
+        for i in range(i0, p):
+            self.v_step(i)
+            if i == p - 1:
+                break
+            # Alg. 1 steps 7-8: u_{i+1} = A v_{i+1} - beta_i u_i, reorth, alpha.
+            w = self.op.mv(self.V[:, i + 1]) - self.T[i, i + 1] * self.U[:, i]
+            self.u_step(i + 1, w)
+
+
+def validate(m, n, k, p):
+    if k < 1 or p <= k or p > m or p + 1 > n:
+        raise ValueError(f"need 1 <= k < p <= m and p + 1 <= n (m={m}, n={n}, k={k}, p={p})")
+
+
+def small_svd(Tp: np.ndarray):
+    """SVD of T(1:t,1:t) by LAPACK gesvd (as LAPACKE_dgesvd in Sec. 2.2.2)."""
+    Uh, s, Vht = sla.svd(Tp, lapack_driver="gesvd")
+    return Uh, s, Vht.T
+
+
+def residual_estimates(beta, Uh_last_row, s, k):
+    """eq. (4): |beta_t Uh(t, j)| / sigma_j, j < k, with the sigma floor."""
+    floor = max(EPS * s[0], TINY) if s.size else TINY
+    return np.abs(beta * Uh_last_row[:k]) / np.maximum(s[:k], floor)
+
+
+def sign_normalize(U, V):
+    """Flip (u_j, v_j) so the largest-|.| entry of v_j is positive."""
+    idx = np.argmax(np.abs(V), axis=0)          # first index on ties
+    sgn = np.sign(V[idx, np.arange(V.shape[1])])
+    sgn[sgn == 0] = 1.0
+    return U * sgn, V * sgn
+
+
+def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
+         v0: np.ndarray | None = None, seed: int = 0, callback=None):
+    """k largest singular triplets of A (scipy sparse matrix or dense array).
+
+    Defaults follow Alg. 2 and Sec. 3: p = max(15, 3k), tol = 1e-10; the paper
+    fixes no default for r, 10 (its experiments' value) is used.
+    ``callback(stage, state, extra)`` sees the internal state after the first
+    LBP ("lbp"), after every small SVD ("svd") and after every restart vector
+    ("restart"), for invariant tests.
+
+    Returns (U m x k, s (k,), V n x k, SvdsInfo).
+    """
+    m, n = A.shape
+    p = p or max(15, 3 * k)
+    tol = tol or 1e-10
+    maxit = maxit or 10
+    validate(m, n, k, p)
+    info = SvdsInfo()
+    op = _Op(A, info)
+    st = _State(op, p, seed, info)
+
+    # Alg. 1 step 1: v_1 = randn / norm.
+    v = np.asarray(v0, dtype=np.float64).copy() if v0 is not None else normal_vector(n, seed, 0)
+    st.V[:, 0] = v / np.linalg.norm(v)
+    # Alg. 1 steps 2-3: u_1 = A v_1, alpha_1 = norm.
+    st.u_step(0, op.mv(st.V[:, 0]))
+    # Alg. 2 step 2: LBP(A, t+1).
+    st.lanczos(0)
+    if callback:
+        callback("lbp", st, None)
+
+    while True:
+        info.cycles += 1
+        # Alg. 2 step 4: SVD of T(1:t, 1:t).
+        Uh, s, Vh = small_svd(st.T[:p, :p])
+        info.sigma_est = max(info.sigma_est, float(s[0]))
+        beta = st.T[p - 1, p]
+        # Alg. 2 step 5 / eq. (4).
+        res = residual_estimates(beta, Uh[p - 1], s, k)
+        info.res_est = res
+        info.nconv = int(np.argmin(np.append(res < tol, False)))
+        if callback:
+            callback("svd", st, dict(Uh=Uh, s=s, Vh=Vh, beta=beta, res=res))
+        if np.all(res < tol):
+            info.converged = True
+            break
+        if info.cycles >= maxit:
+            break
+        # Alg. 2 step 8: Ritz vectors (Proposition 1, eq. (2)).
+        Uk = st.U[:, :p] @ Uh[:, :k]
+        Vk = st.V[:, :p] @ Vh[:, :k]
+        # Alg. 2 step 9: new T = [Sigma_k, rho] with rho = beta_t Uh(t, 1:k)^T (eq. (6)).
+        rho = beta * Uh[p - 1, :k]
+        vnext = st.V[:, p].copy()
+        st.T[:] = 0.0
+        st.T[np.arange(k), np.arange(k)] = s[:k]
+        st.T[:k, k] = rho
+        st.U[:, :k] = Uk
+        st.V[:, :k] = Vk
+        # Alg. 2 step 10: v_{k+1} = v_{t+1}; u_{k+1} = A v_{k+1} - Uk rho (eq. (7)).
+        st.V[:, k] = vnext
+        w = op.mv(st.V[:, k]) - Uk @ rho
+        # Alg. 2 step 11 (with re-orthogonalisation, as the text after Alg. 2 asks).
+        st.u_step(k, w)
+        info.restarts += 1
+        if callback:
+            callback("restart", st, dict(Uk=Uk, rho=rho))
+        # Alg. 2 step 12: continue the Lanczos loop from column k+1.
+        st.lanczos(k)
+
+    # Alg. 2 steps 15-16.
+    S = s[:k].copy()
+    U = st.U[:, :p] @ Uh[:, :k]
+    V = st.V[:, :p] @ Vh[:, :k]
+    U, V = sign_normalize(U, V)
+    return U, S, V, info
+
+
+def lbp(A, p: int, v0: np.ndarray, seed: int = 0):
+    """Alg. 1 alone (with CGS2) for p steps: returns (U m x p, T p x p, V n x p,
+    beta_p, info).  Allows p = min(m, n) (complete bidiagonalisation, where
+    the last beta is a breakdown)."""
+    m, n = A.shape
+    info = SvdsInfo()
+    op = _Op(A, info)
+    st = _State(op, p, seed, info)
+    st.V[:, 0] = v0 / np.linalg.norm(v0)
+    st.u_step(0, op.mv(st.V[:, 0]))
+    st.lanczos(0)
+    return st.U, st.T[:p, :p].copy(), st.V[:, :p], st.T[p - 1, p], info
+
+
+def explicit_residuals(A, U, S, V):
+    """FP64 |A v_j - s_j u_j| and |A^T u_j - s_j v_j| for each output triplet."""
+    AV = np.asarray(A @ V)
+    ATU = np.asarray(A.T @ U)
+    r1 = np.linalg.norm(AV - U * S, axis=0)
+    r2 = np.linalg.norm(ATU - V * S, axis=0)
+    return r1, r2
+
+
+def as_operator(csr_or_dense):
+    """scipy CSR from an ``inputs.CSR``-like object, or a dense ndarray."""
+    if isinstance(csr_or_dense, np.ndarray):
+        return csr_or_dense
+    c = csr_or_dense
+    return sp.csr_matrix((np.asarray(c.val, dtype=np.float64), c.col_idx, c.row_ptr),
+                         shape=(c.m, c.n))

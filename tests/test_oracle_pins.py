@@ -1,0 +1,351 @@
+"""Pins of the CPU oracle against facts fixed outside it (no GPU needed).
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, closed-form spectra, textbook special cases, an
+independent hand-written Jacobi SVD, LAPACK on the dense matrix, and the
+identities of Proposition 1 / eqs. (2)-(7).
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2405_18966_amd import inputs
+from oracle import jacobi, philox, svds_ref
+from oracle.svds_ref import svds, lbp, explicit_residuals, as_operator
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --- Philox4x32-10 -----------------------------------------------------------
+
+def _kat_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            rows.append([int(x, 16) for x in line.split()])
+    return rows
+
+
+def test_philox_known_answers():
+    rows = _kat_rows()
+    assert len(rows) == 3
+    for r in rows:
+        out = philox.philox4x32_10(*[np.array([x], dtype=np.uint64) for x in r[:6]])
+        assert [int(o[0]) for o in out] == r[6:]
+
+
+def test_philox_normal_statistics_and_layout():
+    z = philox.normal_vector(400001, seed=12345, stream=3)
+    assert z.shape == (400001,)
+    assert abs(z.mean()) < 5 / np.sqrt(z.size)
+    assert abs(z.var() - 1) < 0.02
+    # prefix property: a shorter vector is the prefix of a longer one
+    np.testing.assert_array_equal(philox.normal_vector(7, 12345, 3), z[:7])
+    # streams and seeds give different vectors
+    assert not np.allclose(philox.normal_vector(8, 12345, 4), z[:8])
+    assert not np.allclose(philox.normal_vector(8, 12346, 3), z[:8])
+    # Box-Muller pair from block 0, recomputed from the raw words
+    x = philox.philox4x32_10(0, 0, 3, 0, 12345, 0)
+    u1 = ((((int(x[1][()]) << 32) | int(x[0][()])) >> 11) + 1) * 2.0**-53
+    u2 = ((((int(x[3][()]) << 32) | int(x[2][()])) >> 11)) * 2.0**-53
+    rad = np.sqrt(-2 * np.log(u1))
+    np.testing.assert_allclose(z[:2], [rad * np.cos(2 * np.pi * u2), rad * np.sin(2 * np.pi * u2)],
+                               rtol=1e-15)
+
+
+# --- the hand-written Jacobi checker ------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 5, 8, 13])
+def test_round_robin_covers_every_pair_once(n):
+    ne = n + (n & 1)
+    seen = []
+    for I, J in jacobi._round_robin(ne):
+        step = set(I.tolist()) | set(J.tolist())
+        assert len(step) == ne  # disjoint pairs cover every column
+        seen += [tuple(sorted(x)) for x in zip(I.tolist(), J.tolist())]
+    assert sorted(seen) == sorted((i, j) for i in range(ne) for j in range(i + 1, ne))
+
+
+def test_jacobi_diagonal_closed_form():
+    d = np.array([3.0, -7.0, 0.5, 0.0, 2.0, -2.0])
+    U, s, V, _ = jacobi.jacobi_svd(np.diag(d))
+    np.testing.assert_array_equal(s, np.sort(np.abs(d))[::-1])
+
+
+def test_jacobi_2x2_closed_form():
+    # [[a, b], [0, c]]: sigma1*sigma2 = |a c|, sigma1^2 + sigma2^2 = a^2+b^2+c^2
+    a, b, c = 3.0, 4.0, 2.0
+    _, s, _, _ = jacobi.jacobi_svd(np.array([[a, b], [0.0, c]]))
+    assert abs(s[0] * s[1] - abs(a * c)) < 1e-14 * s[0] ** 2
+    assert abs(s[0] ** 2 + s[1] ** 2 - (a * a + b * b + c * c)) < 1e-13 * s[0] ** 2
+
+
+@pytest.mark.parametrize("shape", [(60, 40), (40, 60), (31, 31)])
+def test_jacobi_prescribed_spectrum_and_factorisation(shape):
+    m, n = shape
+    r = min(m, n)
+    sig = np.sort(np.random.default_rng(5).uniform(0.1, 10, r))[::-1]
+    A = inputs.prescribed_dense(m, n, sig, seed=11)
+    U, s, V, sweeps = jacobi.jacobi_svd(A)
+    np.testing.assert_allclose(s, sig, rtol=1e-13)
+    np.testing.assert_allclose((U * s) @ V.T, A, atol=1e-13 * sig[0])
+    assert np.abs(U.T @ U - np.eye(r)).max() < 1e-13
+    assert np.abs(V.T @ V - np.eye(r)).max() < 1e-13
+    assert sweeps < 20
+
+
+def test_jacobi_matches_lapack():
+    A = np.random.default_rng(3).standard_normal((50, 35))
+    _, s, _, _ = jacobi.jacobi_svd(A)
+    np.testing.assert_allclose(s, np.linalg.svd(A, compute_uv=False), rtol=1e-13)
+
+
+# --- helpers -------------------------------------------------------------------
+
+def _subspace_err(X, Y):
+    """sin of the largest principal angle between span(X) and span(Y)."""
+    qx, _ = np.linalg.qr(X)
+    qy, _ = np.linalg.qr(Y)
+    return np.linalg.norm(qx - qy @ (qy.T @ qx), 2)
+
+
+def _check_vectors(U, S, V, Ur, Vr, Sr_all, tol, k):
+    """Vectors agree column-wise up to sign, within the Davis-Kahan style bound
+    10 * tol * sigma_j / gap_j (floor 1e-12); multiple values are compared as
+    subspaces."""
+    for j in range(k):
+        gap = min(abs(Sr_all[j] - Sr_all[i]) for i in range(len(Sr_all)) if i != j)
+        bound = max(10 * tol * Sr_all[j] / max(gap, 1e-300), 1e-12)
+        if gap < 1e-12 * Sr_all[0]:
+            continue
+        for X, Y in ((U, Ur), (V, Vr)):
+            err = min(np.linalg.norm(X[:, j] - Y[:, j]), np.linalg.norm(X[:, j] + Y[:, j]))
+            assert err <= bound, (j, err, bound)
+
+
+# --- P1: brute force, tiny -----------------------------------------------------
+
+@pytest.mark.parametrize("shape,k,p", [((120, 80), 5, 15), ((80, 120), 4, 12), ((60, 60), 1, 2)])
+def test_oracle_against_jacobi_bruteforce(shape, k, p):
+    m, n = shape
+    A = inputs.sparse_uniform(m, n, m * n // 5, seed=17)
+    Asp = as_operator(A)
+    v0 = inputs.start_vector(n, 18)
+    U, S, V, info = svds(Asp, k, p, 1e-12, 2000, v0=v0)
+    assert info.converged
+    Uj, Sj, Vj, _ = jacobi.jacobi_svd(Asp.toarray())
+    np.testing.assert_allclose(S, Sj[:k], rtol=1e-12)
+    _check_vectors(U, S, V, Uj, Vj, Sj, 1e-12, k)
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-12
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-12
+
+
+# --- P2: complete bidiagonalisation (Golub-Kahan) -----------------------------
+
+@pytest.mark.parametrize("shape", [(50, 30), (40, 40)])
+def test_complete_bidiagonalisation_reproduces_spectrum(shape):
+    m, n = shape
+    A = np.random.default_rng(2).standard_normal(shape)
+    v0 = inputs.start_vector(n, 3)
+    U, T, V, beta, info = lbp(A, n, v0)
+    # T is upper bidiagonal, its singular values are those of A
+    assert np.all(np.tril(T, -1) == 0) and np.all(np.triu(T, 2) == 0)
+    np.testing.assert_allclose(np.linalg.svd(T, compute_uv=False),
+                               np.linalg.svd(A, compute_uv=False), rtol=1e-12)
+    # v_{n+1} cannot exist in R^n: the last beta is a breakdown
+    assert beta == 0.0 and info.breakdowns == 1
+    # Lanczos relation A V = U T (Alg. 1 output)
+    assert np.abs(A @ V - U @ T).max() < 1e-13 * np.abs(T).max()
+
+
+# --- P3: prescribed spectra (decay laws of Sec. 3.1) ---------------------------
+
+@pytest.mark.parametrize("law", ["decay1", "decay2", "decay3"])
+def test_prescribed_sparse_spectrum(law):
+    nb, bs = 120, 5
+    sig = getattr(inputs, law)(nb * bs)
+    A = inputs.prescribed_sparse(nb, bs, sig, seed=7)
+    assert np.all(np.diff(A.row_ptr) == bs)
+    k = 8
+    U, S, V, info = svds(as_operator(A), k, 0, 1e-10, 500, v0=inputs.start_vector(A.n, 8))
+    assert info.converged
+    np.testing.assert_allclose(S, np.sort(sig)[::-1][:k], rtol=1e-10)
+
+
+def test_prescribed_dense_spectrum():
+    sig = inputs.decay1(300)
+    A = inputs.prescribed_dense(400, 300, sig, seed=9)
+    U, S, V, info = svds(A, 20, 0, 1e-10, 500, v0=inputs.start_vector(300, 10))
+    assert info.converged
+    np.testing.assert_allclose(S, sig[:20], rtol=1e-10)
+    r1, r2 = explicit_residuals(A, U, S, V)
+    assert r1.max() < 1e-10 * S[0] and (r2 / S).max() < 1e-10
+
+
+# --- P4: library routine (LAPACK on the dense matrix), workload 1 ---------------
+
+def test_workload1_against_lapack():
+    A = inputs.config_matrix(1)
+    Asp = as_operator(A)
+    cfg = inputs.CONFIG_SOLVE[1]
+    U, S, V, info = svds(Asp, cfg["k"], cfg["p"], cfg["tol"], 2000,
+                         v0=inputs.start_vector(A.n, inputs.CONFIG_SEEDS[1] + 1))
+    assert info.converged
+    Ur, Sr, Vrt = np.linalg.svd(Asp.toarray(), full_matrices=False)
+    np.testing.assert_allclose(S, Sr[:cfg["k"]], rtol=1e-12)
+    _check_vectors(U, S, V, Ur, Vrt.T, Sr, cfg["tol"], cfg["k"])
+
+
+# --- P5: diagonal with repeated values (breakdowns, multiple sigma) ------------
+
+def test_diagonal_with_repeats_breaks_down_and_stays_exact():
+    d = np.repeat([5.0, 4.0, 3.0, 2.0, 1.0, 0.5], [4, 3, 3, 2, 3, 35])
+    A = inputs.diag_matrix(60, 50, d)
+    k = 8
+    U, S, V, info = svds(as_operator(A), k, 20, 1e-10, 200, v0=inputs.start_vector(50, 4))
+    assert info.breakdowns > 0
+    np.testing.assert_allclose(S, np.sort(d)[::-1][:k], rtol=1e-12)
+    # multiple singular values: compare subspaces of each cluster
+    D = as_operator(A).toarray()
+    for val in (5.0, 4.0):
+        cols = np.nonzero(np.abs(S - val) < 1e-9)[0]
+        exact = np.eye(50)[:, np.nonzero(np.abs(np.abs(np.diag(D[:50, :50])) - val) < 1e-12)[0]]
+        assert len(cols) == exact.shape[1]
+        assert _subspace_err(V[:, cols], exact) < 1e-9
+    r1, r2 = explicit_residuals(as_operator(A), U, S, V)
+    assert r1.max() < 1e-10 * S[0] and r2.max() < 1e-10 * S[0]
+
+
+def test_zero_matrix():
+    A = inputs.CSR(30, 20, np.zeros(31, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    U, S, V, info = svds(as_operator(A), 2, 5, 1e-10, 3, v0=inputs.start_vector(20, 1))
+    assert np.all(S == 0) and info.converged and info.breakdowns >= 1
+
+
+# --- P6: invariants of Proposition 1 and eqs. (2)-(7) ---------------------------
+
+def test_lanczos_invariants_every_cycle():
+    A = inputs.sparse_uniform(300, 200, 3000, seed=21)
+    Asp = as_operator(A)
+    k, p = 6, 18
+    checked = {"lbp": 0, "svd": 0, "restart": 0}
+
+    def cb(stage, st, ex):
+        U, V, T = st.U, st.V, st.T
+        scale = max(abs(T).max(), 1.0)
+        if stage in ("lbp", "svd"):
+            # A V_p = U_p T_p ;  A^T U_p = V_p T_p^T + beta_p v_{p+1} e_p^T
+            assert np.abs(Asp @ V[:, :p] - U @ T[:p, :p]).max() < 1e-13 * scale
+            E = np.zeros((p, p)); E[p - 1, p - 1] = 1
+            lhs = Asp.T @ U - V[:, :p] @ T[:p, :p].T - T[p - 1, p] * np.outer(V[:, p], E[p - 1])
+            assert np.abs(lhs).max() < 1e-13 * scale
+            assert np.abs(U.T @ U - np.eye(p)).max() < 1e-12
+            assert np.abs(V.T @ V - np.eye(p + 1)).max() < 1e-12
+        if stage == "svd":
+            # eq. (4): estimate equals the explicit residual of A^T u~ - s v~
+            Ut = U @ ex["Uh"][:, :k]
+            Vt = V[:, :p] @ ex["Vh"][:, :k]
+            expl = np.linalg.norm(Asp.T @ Ut - Vt * ex["s"][:k], axis=0) / ex["s"][:k]
+            np.testing.assert_allclose(expl, ex["res"], atol=1e-12)
+            # eq. (2) first identity: A v~ = s u~
+            assert np.abs(Asp @ Vt - Ut * ex["s"][:k]).max() < 1e-12 * scale
+        if stage == "restart":
+            # eq. (6): u~_j^T A v_{t+1} = beta_t Uh(t, j) = rho_j
+            np.testing.assert_allclose(ex["Uk"].T @ (Asp @ V[:, k]), ex["rho"], atol=1e-12 * scale)
+            # restarted T: diag(Sigma_k) with the arrow column rho
+            np.testing.assert_array_equal(T[:k, k], ex["rho"])
+        checked[stage] += 1
+
+    U, S, V, info = svds(Asp, k, p, 1e-12, 50, v0=inputs.start_vector(200, 22), callback=cb)
+    assert checked["svd"] == info.cycles and checked["restart"] == info.restarts >= 1
+
+
+# --- P7: mat-vec counts ---------------------------------------------------------
+
+@pytest.mark.parametrize("maxit", [1, 2, 5])
+def test_matvec_counts(maxit):
+    A = inputs.sparse_uniform(200, 150, 2000, seed=31)
+    k, p = 5, 15
+    _, _, _, info = svds(as_operator(A), k, p, 1e-14, maxit, v0=inputs.start_vector(150, 32))
+    R = info.restarts
+    assert info.cycles == R + 1 <= maxit
+    assert info.n_spmv == p + R * (p - k)
+    assert info.n_spmvT == p + R * (p - k)
+
+
+def test_not_converged_reports_partial():
+    A = inputs.config_matrix(1)
+    _, S, _, info = svds(as_operator(A), 10, 30, 1e-10, 1,
+                         v0=inputs.start_vector(1000, inputs.CONFIG_SEEDS[1] + 1))
+    assert not info.converged and info.cycles == 1 and 0 <= info.nconv < 10
+
+
+def test_validation_errors():
+    A = as_operator(inputs.sparse_uniform(20, 10, 50, seed=1))
+    for k, p in [(0, 5), (5, 5), (3, 10), (3, 21)]:
+        with pytest.raises(ValueError):
+            svds(A, k, p)
+
+
+def test_default_start_vector_is_philox_stream0():
+    A = as_operator(inputs.sparse_uniform(100, 80, 800, seed=41))
+    seen = {}
+
+    def cb(stage, st, ex):
+        if stage == "lbp":
+            seen["v1"] = st.V[:, 0].copy()
+    svds(A, 3, 10, 1e-10, 30, seed=99, callback=cb)
+    z = philox.normal_vector(80, 99, 0)
+    np.testing.assert_allclose(seen["v1"], z / np.linalg.norm(z), rtol=1e-15)
+
+
+def test_sign_normalisation():
+    U = np.array([[1.0, 2.0], [3.0, -1.0]])
+    V = np.array([[0.2, -0.9], [-0.8, 0.9], [0.1, 0.1]])
+    Un, Vn = svds_ref.sign_normalize(U, V)
+    np.testing.assert_array_equal(Vn[:, 0], -V[:, 0])  # largest |.| is -0.8
+    np.testing.assert_array_equal(Vn[:, 1], -V[:, 1])  # tie -0.9 / 0.9: lowest index
+    np.testing.assert_array_equal(Un, U * [-1, -1])
+
+
+# --- planted mistakes: the pins above must catch them ----------------------------
+
+def test_planted_wrong_arrow_column_is_caught(monkeypatch):
+    """A sign error in rho (eq. (6)) leaves u_{k+1} unchanged (CGS2 removes the
+    Uk components anyway) but corrupts T; the Lanczos relation pin fails."""
+    orig = svds_ref.svds
+    A = inputs.sparse_uniform(300, 200, 3000, seed=21)
+    Asp = as_operator(A)
+    k, p = 6, 18
+
+    def bad_cb(stage, st, ex):
+        if stage == "restart":
+            st.T[:k, k] = -st.T[:k, k]
+
+    failures = []
+
+    def check(stage, st, ex):
+        if stage == "svd":
+            err = np.abs(Asp.T @ st.U - st.V[:, :p] @ st.T[:p, :p].T
+                         - st.T[p - 1, p] * np.outer(st.V[:, p], np.eye(p)[p - 1])).max()
+            failures.append(err)
+
+    def both(stage, st, ex):
+        bad_cb(stage, st, ex)
+        check(stage, st, ex)
+
+    orig(Asp, k, p, 1e-12, 3, v0=inputs.start_vector(200, 22), callback=both)
+    assert failures[0] < 1e-12 and max(failures[1:]) > 1e-6
+
+
+def test_planted_single_pass_without_reorth_is_caught(monkeypatch):
+    """Without re-orthogonalisation the bases lose orthogonality (the reason
+    the paper gives for full re-orthogonalisation, Sec. 2.1)."""
+    monkeypatch.setattr(svds_ref, "cgs2", lambda w, Q: w)
+    A = inputs.prescribed_dense(200, 150, inputs.decay2(150), seed=3)
+    U, T, V, beta, info = svds_ref.lbp(A, 60, inputs.start_vector(150, 4))
+    assert np.abs(V.T @ V - np.eye(60)).max() > 1e-6
