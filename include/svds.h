@@ -1,0 +1,183 @@
+/*
+ * svds.h -- C ABI of the MI355X (gfx950) truncated-SVD library.
+ *
+ * The library computes the k largest singular triplets of a sparse (CSR) or
+ * dense m x n matrix A by the augmented, restarted Lanczos bidiagonalization
+ * with full re-orthogonalization that the svds-C paper (Feng, Yu, Xie,
+ * arXiv 2405.18966) re-implements from Matlab's svds:
+ *   - Alg. 1 (Lanczos bidiagonalization, LBP) builds orthonormal bases
+ *     U (m x t), V (n x (t+1)) and the projected matrix T with
+ *     T(i,i) = alpha_i, T(i,i+1) = beta_i; every new basis vector is
+ *     re-orthogonalized against the previous ones (Sec. 2.1, after Alg. 1;
+ *     done here as classical Gram-Schmidt applied twice);
+ *   - Proposition 1 / eq. (4) gives the residual estimate
+ *     |beta_t Uh(t,j)| / sigma_j used as the stopping test (Alg. 2 step 5);
+ *   - the augmented restart (eqs. (5)-(7), Alg. 2 steps 8-12) keeps the k
+ *     Ritz vectors and the arrow column rho_j = beta_t Uh(t,j).
+ * The paper's Lanczos dimension t is called p here.
+ *
+ * Conventions for every entry point:
+ *   - All matrix/vector pointers are DEVICE pointers (hipMalloc'd or torch
+ *     CUDA tensors) on the device that is current when the call is made.
+ *     Work is enqueued on opts->stream (a hipStream_t; NULL = default stream)
+ *     and the call returns after the stream has finished the solve.
+ *   - Dense matrices and the U, V outputs are column-major (the paper's `mat`,
+ *     Sec. 2.3), leading dimension = number of rows unless stated.
+ *   - CSR is 0-based, three arrays: row i holds entries
+ *     [row_ptr[i], row_ptr[i+1]) of col_idx/val, column indices strictly
+ *     increasing within a row (the paper's `mat_csr` is the 1-based,
+ *     pointerB/pointerE form of the same thing).
+ *   - The caller owns every input and output buffer.  The library owns only
+ *     the workspace of a plan (bases, transposed copy of A, T, scratch),
+ *     allocated once at plan creation (as the paper allocates all buffers at
+ *     the start, Sec. 2.2.2) and freed by svds_plan_destroy.
+ *   - Return codes: 0 = success, 1 = SVDS_NOT_CONVERGED (outputs hold the
+ *     current Ritz triplets; info->nconv of the leading ones meet tol),
+ *     negative = error, outputs untouched.  Nothing is thrown across the ABI.
+ */
+#ifndef SVDS_H
+#define SVDS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SVDS_OK = 0,
+  SVDS_NOT_CONVERGED = 1,
+  SVDS_EINVAL = -1,      /* bad sizes, null pointers, k/p out of range      */
+  SVDS_ENOMEM = -2,      /* device workspace allocation failed              */
+  SVDS_EDEVICE = -3,     /* a HIP runtime call failed                       */
+  SVDS_EUNSUPPORTED = -4 /* valid request this build does not implement     */
+};
+
+/* Storage type of A's values. */
+enum { SVDS_F64 = 0, SVDS_F32 = 1, SVDS_BF16 = 2 };
+
+/* Arithmetic of the solve.
+ * SVDS_PREC_FP64 : bases, mat-vecs, re-orthogonalization in FP64.
+ * SVDS_PREC_MIXED: FP32 cycles (bases, mat-vecs, re-orthogonalization in
+ *                  FP32) until the eq. (4) estimate reaches max(tol, 1e-5),
+ *                  then FP64 cycles restarted from the FP32 Ritz vectors.
+ * The small SVD of T, T itself and the final residuals are FP64 always.
+ * A stored in FP32/BF16 is widened exactly; that widened matrix is the
+ * matrix whose SVD is computed. */
+enum { SVDS_PREC_FP64 = 0, SVDS_PREC_MIXED = 1 };
+
+/* Option flags. */
+enum {
+  SVDS_FLAG_TIMING = 1,       /* record per-kernel-class device time in info   */
+  SVDS_FLAG_NO_RESIDUALS = 2, /* skip the explicit FP64 residuals at the end   */
+  SVDS_FLAG_NO_SIGNFIX = 4    /* leave the signs of (u_j, v_j) as computed     */
+};
+
+typedef struct {
+  int64_t m, n, nnz;
+  const int32_t *row_ptr; /* m+1 entries, row_ptr[0] = 0, row_ptr[m] = nnz   */
+  const int32_t *col_idx; /* nnz entries in [0, n)                          */
+  const void *val;        /* nnz values of type `dtype` (SVDS_F64/SVDS_F32) */
+  int32_t dtype;
+} svds_csr;
+
+typedef struct {
+  int64_t m, n, ld;       /* ld >= m                                        */
+  const void *a;          /* column-major, type `dtype` (F64, F32 or BF16)  */
+  int32_t dtype;
+} svds_dense;
+
+typedef struct {
+  int32_t k;        /* number of triplets, 1 <= k                           */
+  int32_t p;        /* Lanczos dimension t; 0 -> max(15, 3k) (Alg. 2 step 1)*/
+  double tol;       /* eq. (4) tolerance; 0 -> 1e-10 (Sec. 3)               */
+  int32_t maxit;    /* max Lanczos cycles (= max restarts + 1); 0 -> 10     */
+  int32_t precision;/* SVDS_PREC_FP64 or SVDS_PREC_MIXED                    */
+  uint64_t seed;    /* Philox4x32-10 seed of v1 (if v0 == NULL) and of
+                       breakdown replacement vectors                         */
+  const double *v0; /* optional device start vector, n entries (Alg. 1 step 1
+                       draws randn(n,1)); need not be normalized, nonzero    */
+  void *stream;     /* hipStream_t, NULL = default stream                    */
+  int32_t flags;    /* SVDS_FLAG_*                                           */
+} svds_opts;
+
+/* Kernel classes reported by SVDS_FLAG_TIMING. */
+enum {
+  SVDS_KC_SPMV = 0,      /* w = A x - beta u          (Alg. 1 step 7)       */
+  SVDS_KC_SPMVT,         /* w = A^T y - alpha v       (Alg. 1 step 5)       */
+  SVDS_KC_CGS_PROJ,      /* h1 = Q^T w                (first CGS pass)      */
+  SVDS_KC_CGS_UPDPROJ,   /* w1 = w - Q h1, h2 = Q^T w1                      */
+  SVDS_KC_CGS_UPDNORM,   /* w2 = w1 - Q h2, |w2|      (alpha/beta)          */
+  SVDS_KC_SMALLSVD,      /* SVD of T, test, restart set-up (Alg. 2 4-9)     */
+  SVDS_KC_ROTATE,        /* U Uh_k, V Vh_k            (Alg. 2 steps 8, 16)  */
+  SVDS_KC_OTHER,         /* restart update, residuals, signs, casts         */
+  SVDS_KC_COUNT
+};
+
+typedef struct {
+  int32_t nconv;        /* leading triplets with eq. (4) estimate < tol     */
+  int32_t cycles;       /* Lanczos cycles run (FP32 + FP64)                 */
+  int32_t cycles_fp32, cycles_fp64;
+  int32_t breakdowns;   /* invariant-subspace replacements                  */
+  int32_t converged;    /* 1 if every estimate < tol at the end             */
+  int64_t n_spmv, n_spmvT;    /* products A x and A^T y (excl. residuals)   */
+  double max_res_est;   /* max_j eq. (4) estimate at the last small SVD     */
+  double max_res_true;  /* max_j |A^T u_j - s_j v_j| / s_j, FP64 explicit   */
+  double max_res_av;    /* max_j |A v_j - s_j u_j| / s_1,  FP64 explicit    */
+  double ms_total;      /* wall time of the execute call                    */
+  double bytes_alg;     /* algorithmic HBM bytes of SpMV + CGS kernels      */
+  double kc_ms[SVDS_KC_COUNT];     /* device ms per class (TIMING flag)     */
+  double kc_bytes[SVDS_KC_COUNT];  /* algorithmic bytes per class           */
+  double kc_flops[SVDS_KC_COUNT];  /* algorithmic flops per class           */
+  int64_t kc_launches[SVDS_KC_COUNT];
+  int64_t workspace_bytes;         /* device arena of the plan              */
+} svds_info;
+
+typedef struct svds_plan svds_plan;
+
+/* Plan creation: validates the input (EINVAL when k < 1, p <= k, p > m,
+ * p + 1 > n, a null pointer, or nnz != row_ptr[m] cannot be checked cheaply
+ * and is trusted), allocates the device workspace once (Sec. 2.2.2: all
+ * buffers are allocated at the start), and for CSR builds the transposed
+ * copy A^T (CSR of A^T, entries of each column in increasing row order) on
+ * the device.  `A` and the buffers it points to must stay alive and
+ * unchanged until svds_plan_destroy.  `opts` is copied. */
+int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, svds_plan **plan);
+int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts, svds_plan **plan);
+
+/* Runs Alg. 2 to convergence or opts->maxit cycles and writes
+ * U (m x k, ld = m), S (k, descending), V (n x k, ld = n), all FP64 device
+ * buffers owned by the caller (Alg. 2 steps 15-16).  `info` may be NULL. */
+int svds_plan_execute(svds_plan *plan, double *U, double *S, double *V, svds_info *info);
+
+void svds_plan_destroy(svds_plan *plan);
+
+/* create + execute + destroy. */
+int svds_csr_solve(const svds_csr *A, const svds_opts *opts,
+                   double *U, double *S, double *V, svds_info *info);
+int svds_dense_solve(const svds_dense *A, const svds_opts *opts,
+                     double *U, double *S, double *V, svds_info *info);
+
+/* Many independent CSR problems with the same options (k, p, tol, ...).
+ * U[i], S[i], V[i] are per-instance device buffers; infos may be NULL. */
+int svds_csr_solve_batched(int32_t count, const svds_csr *As, const svds_opts *opts,
+                           double *const *U, double *const *S, double *const *V,
+                           svds_info *infos);
+
+/* Explicit FP64 residuals of given triplets (Proposition 1, eq. (2)):
+ * res_av[j] = |A v_j - s_j u_j|_2 and res_atu[j] = |A^T u_j - s_j v_j|_2,
+ * j < k, for device U (m x k), S (k), V (n x k); outputs are device arrays
+ * of k doubles.  Synchronous on `stream`. */
+int svds_residuals_csr(const svds_csr *A, int32_t k, const double *U, const double *S,
+                       const double *V, double *res_av, double *res_atu, void *stream);
+
+const char *svds_strerror(int code);
+
+/* Library version string. */
+const char *svds_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVDS_H */

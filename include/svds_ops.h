@@ -1,0 +1,76 @@
+/*
+ * svds_ops.h -- single steps of the truncated-SVD hot path, exposed through
+ * the same C ABI conventions as svds.h (device pointers, caller-owned
+ * buffers, integer return codes, synchronous on `stream`).  They run the very
+ * kernels the solver runs, so each step can be checked and timed alone.
+ */
+#ifndef SVDS_OPS_H
+#define SVDS_OPS_H
+
+#include <stdint.h>
+#include "svds.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Mat-vec of Alg. 1 steps 2/5/7 with the fused Lanczos term:
+ *   y = x_scale * (A x) - coef * yprev
+ * x (A->n), yprev and y (A->m) are device vectors of `basis_dtype`
+ * (SVDS_F64 or SVDS_F32; A's values F64 or F32 are widened to it).
+ * x_scale and coef are DEVICE pointers to one double each, or NULL
+ * (x_scale NULL = 1, coef NULL = no yprev term).  For A^T x pass the CSR of
+ * A^T (see svds_op_csc_build).  EINVAL on null pointers or bad row_ptr. */
+int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *x_scale, const double *coef,
+                     const void *yprev, void *y, int32_t basis_dtype, void *stream);
+
+/* Dense mat-vec (column-major A, F64/F32/BF16 storage widened exactly):
+ *   y = x_scale * op(A) x - coef * yprev, op(A) = A or A^T (transpose != 0). */
+int svds_op_dense_matvec(const svds_dense *A, int32_t transpose, const void *x, const double *x_scale,
+                         const double *coef, const void *yprev, void *y, int32_t basis_dtype,
+                         void *stream);
+
+/* CSR of A^T (n rows): t_row_ptr (n+1), t_col_idx (nnz, the row index of A,
+ * increasing within each row of A^T), t_val (nnz, A's value type).
+ * Bit-exact and deterministic (stable radix sort of the column keys). */
+int svds_op_csc_build(const svds_csr *A, int32_t *t_row_ptr, int32_t *t_col_idx, void *t_val,
+                      void *stream);
+
+/* Full re-orthogonalization (Sec. 2.1, after Alg. 1) as CGS2:
+ *   out = (I - Q Q^T)(I - Q Q^T) w, *norm_out = |out|_2 (host double),
+ * Q (L x j, column-major, ld ldq >= L), w, out of length L, all `dtype`
+ * (SVDS_F64 / SVDS_F32).  j = 0 gives out = w.  j <= 1024. */
+int svds_op_cgs2(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
+                 double *norm_out, int32_t dtype, void *stream);
+
+/* Alg. 2 steps 4-9 on the device: T is the (p+1) x (p+1) row-major FP64
+ * matrix of the Lanczos process (T(i,i) = alpha, T(i,i+1) = beta); its
+ * leading p x p block is decomposed by the one-sided Jacobi SVD.  Outputs:
+ * Uk (p x k, ld p), Vext ((p+1) x (k+1), ld p+1: leading right vectors,
+ * zero last row, last column e_{p+1}), sig (k, descending), res (k, eq. (4)
+ * estimates |beta_p Uh(p,j)| / sigma_j), rho (k, beta_p Uh(p,j), eq. (6)),
+ * flags_host[0..2] = {all res < tol, leading count < tol, Jacobi sweeps}.
+ * T is overwritten by the restarted matrix [diag(sig), rho] (step 9). */
+int svds_op_small_svd(int32_t p, int32_t k, double tol, double *T, double *Uk, double *Vext,
+                      double *sig, double *res, double *rho, int32_t *flags_host, void *stream);
+
+/* Restart rotation (Alg. 2 steps 8 and 16): out(:, 0:kc) = B(:, 0:pc) Y,
+ * B L x pc of `btype` (F64/F32, ld ldb), Y pc x kc FP64 (ld ldy),
+ * out L x kc FP64 (ld ldo). */
+int svds_op_rotate(int64_t L, int32_t pc, int32_t kc, const void *B, int64_t ldb, int32_t btype,
+                   const double *Y, int64_t ldy, double *out, int64_t ldo, void *stream);
+
+/* Philox4x32-10 normal vector (the start vector of Alg. 1 step 1 when none
+ * is given): block b of stream q gives out[2b], out[2b+1] by Box-Muller from
+ * counter (b_lo, b_hi, q, 0) and key (seed_lo, seed_hi). */
+int svds_op_philox_normal(int64_t L, uint64_t seed, uint32_t stream_id, double *out, void *stream);
+
+/* Plain device copy dst = src (L doubles): the bandwidth reference used to
+ * calibrate hardware traffic counters. */
+int svds_op_copy_f64(int64_t L, const double *src, double *dst, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVDS_OPS_H */

@@ -1,0 +1,295 @@
+// C ABI entry points that wrap plans (solve = create + execute + destroy),
+// the batched form, explicit residuals, single-step operations (for parity
+// tests and measurements of individual kernels) and error strings.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/svds.h"
+#include "../../include/svds_ops.h"
+#include "plan.hpp"
+#include "kernels_cgs.hpp"
+#include "kernels_csc.hpp"
+#include "kernels_jacobi.hpp"
+#include "kernels_misc.hpp"
+
+using namespace svds;
+
+extern "C" int svds_csr_solve(const svds_csr *A, const svds_opts *opts, double *U, double *S,
+                              double *V, svds_info *info) {
+  svds_plan *P = nullptr;
+  int rc = svds_plan_create_csr(A, opts, &P);
+  if (rc) return rc;
+  rc = svds_plan_execute(P, U, S, V, info);
+  svds_plan_destroy(P);
+  return rc;
+}
+
+extern "C" int svds_dense_solve(const svds_dense *A, const svds_opts *opts, double *U, double *S,
+                                double *V, svds_info *info) {
+  svds_plan *P = nullptr;
+  int rc = svds_plan_create_dense(A, opts, &P);
+  if (rc) return rc;
+  rc = svds_plan_execute(P, U, S, V, info);
+  svds_plan_destroy(P);
+  return rc;
+}
+
+extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const svds_opts *opts,
+                                      double *const *U, double *const *S, double *const *V,
+                                      svds_info *infos) {
+  if (count < 0 || (count > 0 && (!As || !opts || !U || !S || !V))) return SVDS_EINVAL;
+  int worst = SVDS_OK;
+  for (int32_t i = 0; i < count; ++i) {
+    const int rc = svds_csr_solve(&As[i], opts, U[i], S[i], V[i], infos ? &infos[i] : nullptr);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+  }
+  return worst;
+}
+
+extern "C" int svds_residuals_csr(const svds_csr *A, int32_t k, const double *U, const double *S,
+                                  const double *V, double *res_av, double *res_atu, void *stream) {
+  if (!A || k < 1 || !U || !S || !V || !res_av || !res_atu) return SVDS_EINVAL;
+  svds_opts o{};
+  o.k = 1;
+  o.p = 2;
+  o.stream = stream;
+  if (A->m < 2 || A->n < 3) return SVDS_EINVAL;
+  svds_plan *P = nullptr;
+  int rc = svds_plan_create_csr(A, &o, &P);
+  if (rc) return rc;
+  rc = svds_plan_residuals(P, k, U, S, V, res_av, res_atu);
+  svds_plan_destroy(P);
+  return rc;
+}
+
+extern "C" const char *svds_strerror(int code) {
+  switch (code) {
+    case SVDS_OK: return "ok";
+    case SVDS_NOT_CONVERGED: return "not converged within maxit cycles (outputs hold current Ritz triplets)";
+    case SVDS_EINVAL: return "invalid argument";
+    case SVDS_ENOMEM: return "device workspace allocation failed";
+    case SVDS_EDEVICE: {
+      static thread_local char buf[600];
+      snprintf(buf, sizeof buf, "HIP runtime error: %s", last_error_text());
+      return buf;
+    }
+    case SVDS_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown error code";
+  }
+}
+
+extern "C" const char *svds_version(void) { return "svds-mi355x 0.1 (gfx950)"; }
+
+// ===========================================================================
+// Single-step operations
+// ===========================================================================
+namespace {
+struct Scratch {
+  void *p = nullptr;
+  ~Scratch() {
+    if (p) (void)hipFree(p);
+  }
+};
+}  // namespace
+
+extern "C" int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *x_scale,
+                                const double *coef, const void *yprev, void *y, int32_t basis_dtype,
+                                void *stream) {
+  if (!A || !x || !y || A->m < 1 || A->n < 1) return SVDS_EINVAL;
+  if (A->dtype != SVDS_F64 && A->dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
+  if (basis_dtype != SVDS_F64 && basis_dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int32_t> hrp(A->m + 1);
+  HIP_TRY(hipMemcpy(hrp.data(), A->row_ptr, sizeof(int32_t) * (A->m + 1), hipMemcpyDeviceToHost));
+  if (hrp[0] != 0 || hrp[A->m] != A->nnz) return SVDS_EINVAL;
+  SpmvPlan sp;
+  build_spmv_items(hrp.data(), A->m, sp);
+  Scratch s;
+  const size_t bi = sizeof(int4) * sp.nitems, bl = sizeof(LongRow) * std::max(1, sp.nlong),
+               bp = sizeof(double) * std::max(1, sp.npieces), bc = sizeof(unsigned) * std::max(1, sp.nlong);
+  HIP_TRY(hipMalloc(&s.p, bi + bl + bp + bc + 1024));
+  char *b = static_cast<char *>(s.p);
+  int4 *items = reinterpret_cast<int4 *>(b);
+  LongRow *lr = reinterpret_cast<LongRow *>(b + ((bi + 255) & ~size_t(255)));
+  double *parts = reinterpret_cast<double *>(reinterpret_cast<char *>(lr) + ((bl + 255) & ~size_t(255)));
+  unsigned *cnt = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(parts) + ((bp + 255) & ~size_t(255)));
+  HIP_TRY(hipMemcpy(items, sp.h_items.data(), bi, hipMemcpyHostToDevice));
+  if (sp.nlong) HIP_TRY(hipMemcpy(lr, sp.h_long.data(), sizeof(LongRow) * sp.nlong, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(cnt, 0, bc));
+#define SPMV_GO(TV, TB)                                                                            \
+  hipLaunchKernelGGL((spmv_csr_kernel<TV, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0, st, items, \
+                     lr, A->row_ptr, A->col_idx, static_cast<const TV *>(A->val),                  \
+                     static_cast<const TB *>(x), x_scale, coef, static_cast<const TB *>(yprev),    \
+                     static_cast<TB *>(y), reinterpret_cast<TB *>(parts), cnt, nullptr, 0)
+  if (A->dtype == SVDS_F64 && basis_dtype == SVDS_F64) SPMV_GO(double, double);
+  else if (A->dtype == SVDS_F32 && basis_dtype == SVDS_F64) SPMV_GO(float, double);
+  else if (A->dtype == SVDS_F64 && basis_dtype == SVDS_F32) SPMV_GO(double, float);
+  else SPMV_GO(float, float);
+#undef SPMV_GO
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return SVDS_OK;
+}
+
+extern "C" int svds_op_dense_matvec(const svds_dense *A, int32_t transpose, const void *x,
+                                    const double *x_scale, const double *coef, const void *yprev,
+                                    void *y, int32_t basis_dtype, void *stream) {
+  if (!A || !x || !y || A->m < 1 || A->n < 1 || A->ld < A->m) return SVDS_EINVAL;
+  svds_opts o{};
+  o.k = 1;
+  o.p = 2;
+  o.stream = stream;
+  o.precision = basis_dtype == SVDS_F32 ? SVDS_PREC_MIXED : SVDS_PREC_FP64;
+  if (A->m < 2 || A->n < 3) return SVDS_EINVAL;
+  svds_plan *P = nullptr;
+  int rc = svds_plan_create_dense(A, &o, &P);
+  if (rc) return rc;
+  rc = svds_plan_matvec(P, transpose, x, x_scale, coef, yprev, y, basis_dtype);
+  svds_plan_destroy(P);
+  return rc;
+}
+
+extern "C" int svds_op_csc_build(const svds_csr *A, int32_t *t_row_ptr, int32_t *t_col_idx,
+                                 void *t_val, void *stream) {
+  if (!A || !t_row_ptr || (A->nnz > 0 && (!t_col_idx || !t_val))) return SVDS_EINVAL;
+  if (A->m < 2 || A->n < 3) return SVDS_EINVAL;
+  svds_opts o{};
+  o.k = 1;
+  o.p = 2;
+  o.stream = stream;
+  svds_plan *P = nullptr;
+  int rc = svds_plan_create_csr(A, &o, &P);
+  if (rc) return rc;
+  rc = svds_plan_transpose_copy(P, t_row_ptr, t_col_idx, t_val);
+  svds_plan_destroy(P);
+  return rc;
+}
+
+extern "C" int svds_op_cgs2(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
+                            double *norm_out, int32_t dtype, void *stream) {
+  if (L < 1 || j < 0 || j > CGS_MAXJ || (j > 0 && (!Q || ldq < L)) || !w || !out) return SVDS_EINVAL;
+  if (dtype != SVDS_F64 && dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t tb = dtype == SVDS_F64 ? 8 : 4;
+  Scratch s;
+  // partials (CGS_MAXJ * GMAX), h1, h2 (CGS_MAXJ), w1 (L), npart (GMAX), xs, t, sig, cnt
+  const size_t bytes = tb * (static_cast<size_t>(CGS_MAXJ) * GMAX + 2 * CGS_MAXJ + L) + 8 * (GMAX + 8) + 64;
+  HIP_TRY(hipMalloc(&s.p, bytes));
+  HIP_TRY(hipMemset(s.p, 0, bytes));
+  char *b = static_cast<char *>(s.p);
+  char *parts = b;
+  char *h1 = parts + tb * CGS_MAXJ * GMAX;
+  char *h2 = h1 + tb * CGS_MAXJ;
+  char *w1 = h2 + tb * CGS_MAXJ;
+  double *npart = reinterpret_cast<double *>(w1 + ((tb * L + 7) & ~size_t(7)));
+  double *dx = npart + GMAX;  // xs, t_entry, sigma_est
+  unsigned *cnt = reinterpret_cast<unsigned *>(dx + 4);
+  int *bd = reinterpret_cast<int *>(cnt + 4);
+  auto grid = [](int64_t Lx) {
+    return static_cast<unsigned>(std::min<int64_t>(GMAX, std::max<int64_t>(1, ceil_div(Lx, 2048))));
+  };
+  const int nw = std::max(1, std::min(16, static_cast<int>(ceil_div(std::max(j, 1), CGS_CPW))));
+  FinishArgs fa{dx + 1, dx, dx + 2, bd, 0};
+#define CGS_GO(T)                                                                                   \
+  do {                                                                                              \
+    const T *src = static_cast<const T *>(w);                                                       \
+    if (j > 0) {                                                                                    \
+      hipLaunchKernelGGL((cgs_proj_kernel<T>), dim3(grid(L)), dim3(CGS_THREADS), 0, st,             \
+                         static_cast<const T *>(Q), ldq, L, j, src, reinterpret_cast<T *>(parts),   \
+                         reinterpret_cast<T *>(h1), cnt);                                           \
+      hipLaunchKernelGGL((cgs_upd_proj_kernel<T>), dim3(grid(L)), dim3(nw * WAVE), 0, st,           \
+                         static_cast<const T *>(Q), ldq, L, j, src, reinterpret_cast<T *>(h1),      \
+                         reinterpret_cast<T *>(w1), reinterpret_cast<T *>(parts),                   \
+                         reinterpret_cast<T *>(h2), cnt + 1);                                       \
+      src = reinterpret_cast<const T *>(w1);                                                        \
+    }                                                                                               \
+    hipLaunchKernelGGL((cgs_upd_norm_kernel<T>), dim3(grid(L)), dim3(CGS_THREADS), 0, st,           \
+                       static_cast<const T *>(Q), ldq, L, j, src, reinterpret_cast<T *>(h2),        \
+                       static_cast<T *>(out), npart, cnt + 2, static_cast<int>(MODE_NORM), fa);     \
+  } while (0)
+  if (dtype == SVDS_F64) CGS_GO(double);
+  else CGS_GO(float);
+#undef CGS_GO
+  HIP_TRY(hipGetLastError());
+  double xs = 0;
+  HIP_TRY(hipMemcpyAsync(&xs, dx, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (norm_out) *norm_out = 1.0 / xs;
+  return SVDS_OK;
+}
+
+extern "C" int svds_op_small_svd(int32_t p, int32_t k, double tol, double *T, double *Uk, double *Vext,
+                                 double *sig, double *res, double *rho, int32_t *flags_host,
+                                 void *stream) {
+  if (p < 2 || k < 1 || k >= p || !T || !Uk || !Vext || !sig || !res || !rho) return SVDS_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int pe = p + (p & 1);
+  const int64_t wb = jacobi_work_bytes(p);
+  const bool use_lds = wb <= 64 * 1024;
+  const int rpl = static_cast<int>(ceil_div(pe, WAVE));
+  if (rpl > 16) return SVDS_EUNSUPPORTED;
+  Scratch s;
+  HIP_TRY(hipMalloc(&s.p, wb + 256));
+  double *sigma_est = static_cast<double *>(s.p);
+  double *jac = sigma_est + 8;
+  int *flags = reinterpret_cast<int *>(sigma_est + 4);
+  HIP_TRY(hipMemsetAsync(s.p, 0, 64, st));
+  const int nthr = std::min(JAC_THREADS, std::max(WAVE, (pe / 2) * WAVE));
+  const size_t shm = use_lds ? static_cast<size_t>(wb) : 0;
+#define JAC_GO(R)                                                                                    \
+  hipLaunchKernelGGL((small_svd_kernel<R>), dim3(1), dim3(nthr), shm, st, T, p, k, tol, jac, Uk, Vext, \
+                     sig, res, rho, flags, sigma_est, use_lds ? 1 : 0)
+  if (rpl <= 1) JAC_GO(1);
+  else if (rpl <= 2) JAC_GO(2);
+  else if (rpl <= 4) JAC_GO(4);
+  else if (rpl <= 8) JAC_GO(8);
+  else JAC_GO(16);
+#undef JAC_GO
+  HIP_TRY(hipGetLastError());
+  int hf[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (flags_host) std::memcpy(flags_host, hf, 3 * sizeof(int));
+  return SVDS_OK;
+}
+
+extern "C" int svds_op_rotate(int64_t L, int32_t pc, int32_t kc, const void *B, int64_t ldb,
+                              int32_t btype, const double *Y, int64_t ldy, double *out, int64_t ldo,
+                              void *stream) {
+  if (L < 1 || pc < 1 || kc < 1 || !B || !Y || !out || ldb < L || ldy < pc || ldo < L) return SVDS_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const unsigned g = static_cast<unsigned>(ceil_div(L, ROT_THREADS));
+  if (btype == SVDS_F64)
+    hipLaunchKernelGGL((rotate_kernel<double, double>), dim3(g), dim3(ROT_THREADS), 0, st, L, pc, kc,
+                       static_cast<const double *>(B), ldb, Y, ldy, out, ldo);
+  else if (btype == SVDS_F32)
+    hipLaunchKernelGGL((rotate_kernel<float, double>), dim3(g), dim3(ROT_THREADS), 0, st, L, pc, kc,
+                       static_cast<const float *>(B), ldb, Y, ldy, out, ldo);
+  else
+    return SVDS_EUNSUPPORTED;
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return SVDS_OK;
+}
+
+extern "C" int svds_op_philox_normal(int64_t L, uint64_t seed, uint32_t stream_id, double *out,
+                                     void *stream) {
+  if (L < 1 || !out) return SVDS_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL((philox_fill_kernel<double>), dim3(ceil_div(ceil_div(L, 2), 256)), dim3(256), 0, st,
+                     L, seed, stream_id, out);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return SVDS_OK;
+}
+
+extern "C" int svds_op_copy_f64(int64_t L, const double *src, double *dst, void *stream) {
+  if (L < 1 || !src || !dst) return SVDS_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(copy_f64_kernel, dim3(ceil_div(L, 256)), dim3(256), 0, st, L, src, dst);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return SVDS_OK;
+}

@@ -1,0 +1,135 @@
+// Shared device/host helpers of the HIP implementation (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace svds {
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------------------
+// Error handling: every HIP call in host code goes through HIP_TRY, which
+// returns SVDS_EDEVICE from the enclosing int-returning function.
+// ---------------------------------------------------------------------------
+#define HIP_TRY(expr)                                                         \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      ::svds::set_last_error(e_, #expr, __FILE__, __LINE__);                  \
+      return SVDS_EDEVICE;                                                    \
+    }                                                                         \
+  } while (0)
+
+void set_last_error(hipError_t e, const char *what, const char *file, int line);
+const char *last_error_text();
+
+// ---------------------------------------------------------------------------
+// Value loads: every stored type widens exactly to the accumulation type.
+// ---------------------------------------------------------------------------
+template <typename Acc, typename V> __device__ __forceinline__ Acc widen(V v) {
+  return static_cast<Acc>(v);
+}
+template <> __device__ __forceinline__ float widen<float, uint16_t>(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+template <> __device__ __forceinline__ double widen<double, uint16_t>(uint16_t b) {
+  return static_cast<double>(__uint_as_float(static_cast<uint32_t>(b) << 16));
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.  xor-butterflies are commutative at every level, so every lane
+// ends with the bitwise-same sum; block sums combine waves in index order.
+// All reductions in this library are deterministic (no float atomics).
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+template <typename T> __device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+
+// Sum over the block; result valid in every thread.  `sh` holds >= 16 T.
+template <typename T> __device__ __forceinline__ T block_sum(T v, T *sh) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int nw = (blockDim.x + WAVE - 1) / WAVE;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  T s = 0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// Grid "last block" election: every block calls this once after writing its
+// partial results; returns true in exactly one block (the last to arrive),
+// after which that block may read all partials.  The counter is reset by the
+// elected block, so it is ready for the next launch.
+__device__ __forceinline__ bool elect_last_block(unsigned int *counter, int *sh_flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int ticket = atomicAdd(counter, 1u);
+    *sh_flag = (ticket == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  bool last = *sh_flag != 0;
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
+  }
+  return last;
+}
+
+__host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the library's normal
+// vector encoding: block b of stream q under seed s gives two normals by
+// Box-Muller from counter (b_lo, b_hi, q, 0), key (s_lo, s_hi).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c[0];
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
+    const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+    const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__device__ __forceinline__ void philox_normal_pair(uint64_t seed, uint32_t stream, uint64_t block,
+                                                   double &z0, double &z1) {
+  uint32_t c[4] = {static_cast<uint32_t>(block), static_cast<uint32_t>(block >> 32), stream, 0u};
+  philox4x32_10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+  const uint64_t a = ((static_cast<uint64_t>(c[1]) << 32) | c[0]) >> 11;
+  const uint64_t b = ((static_cast<uint64_t>(c[3]) << 32) | c[2]) >> 11;
+  const double u1 = (static_cast<double>(a) + 1.0) * 0x1.0p-53;
+  const double u2 = static_cast<double>(b) * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  double s, co;
+  sincos(2.0 * 3.141592653589793238462643383279502884 * u2, &s, &co);
+  z0 = rad * co;
+  z1 = rad * s;
+}
+
+}  // namespace svds

@@ -1,0 +1,119 @@
+// Sparse matrix-vector product y = xs * (A x) - coef * yprev over 0-based CSR.
+//
+// The product is the mat-vec of Alg. 1 steps 2, 5 and 7 (A v and A^T u with
+// the -beta u / -alpha v terms fused); A^T u runs the same kernel over the
+// CSR of A^T built on the device.
+//
+// Work decomposition (fixed at plan time, so results are deterministic):
+//  * MULTI item: a run of consecutive rows whose total nnz <= SPMV_NNZ_BLK and
+//    whose count <= SPMV_ROWS_BLK.  The block stages the products val*x[col]
+//    in LDS with coalesced loads, then reduces each row from LDS, one thread
+//    per row (short rows) or one wave per row (long rows).
+//  * PIECE item: a slice of SPMV_PIECE nonzeros of a row longer than
+//    SPMV_NNZ_BLK.  The block writes its partial sum; the last piece of the
+//    row to finish (per-row arrival counter) adds the partials in piece
+//    order and writes y.  Power-law rows (e.g. the heaviest columns of a Zipf
+//    matrix seen through A^T) are spread over many blocks this way.
+//  * Optional side task: dst[i] = src[i] * xs for i < side_len, spread over
+//    the grid.  The solver uses it to write the normalized previous Lanczos
+//    vector into its basis column while the product consumes the
+//    unnormalized copy.
+#pragma once
+#include "common.hpp"
+
+namespace svds {
+
+constexpr int SPMV_THREADS = 256;
+constexpr int SPMV_NNZ_BLK = 2048;
+constexpr int SPMV_ROWS_BLK = 256;
+constexpr int SPMV_PIECE = 4096;
+
+// item.x >= 0: MULTI rows [x, y).   item.x < 0: PIECE of long row id -x-1,
+// nonzeros [z, w), written to partials[item.y].
+struct LongRow {
+  int32_t row, first_piece, npieces, pad;
+};
+
+template <typename TV, typename TB>
+__global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
+    const int4 *__restrict__ items, const LongRow *__restrict__ longrows,
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const TV *__restrict__ val, const TB *__restrict__ x, const double *__restrict__ xs_ptr,
+    const double *__restrict__ coef_ptr, const TB *__restrict__ yprev, TB *__restrict__ y,
+    TB *__restrict__ partials, unsigned int *__restrict__ counters,
+    TB *__restrict__ side_dst, int64_t side_len) {
+  __shared__ TB prod[SPMV_NNZ_BLK];
+  __shared__ TB red[SPMV_THREADS / WAVE];
+  __shared__ int flag;
+  const int tid = threadIdx.x;
+  const int lane = tid & (WAVE - 1);
+  const int wv = tid / WAVE;
+  const TB xs = xs_ptr ? static_cast<TB>(*xs_ptr) : TB(1);
+  const TB coef = coef_ptr ? static_cast<TB>(*coef_ptr) : TB(0);
+
+  if (side_dst) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * SPMV_THREADS + tid; i < side_len;
+         i += static_cast<int64_t>(gridDim.x) * SPMV_THREADS)
+      side_dst[i] = x[i] * xs;
+  }
+
+  const int4 it = items[blockIdx.x];
+  if (it.x >= 0) {
+    const int r0 = it.x, r1 = it.y;
+    const int base = row_ptr[r0];
+    const int cnt = row_ptr[r1] - base;
+    for (int z = tid; z < cnt; z += SPMV_THREADS)
+      prod[z] = widen<TB>(val[base + z]) * x[col[base + z]];
+    __syncthreads();
+    const int nrows = r1 - r0;
+    if (cnt >= 32 * nrows) {
+      // few long rows: one wave per row
+      for (int r = wv; r < nrows; r += SPMV_THREADS / WAVE) {
+        const int a = row_ptr[r0 + r] - base, b = row_ptr[r0 + r + 1] - base;
+        TB s = 0;
+        for (int z = a + lane; z < b; z += WAVE) s += prod[z];
+        s = wave_sum(s);
+        if (lane == 0) {
+          const int64_t row = r0 + r;
+          y[row] = xs * s - (yprev ? coef * yprev[row] : TB(0));
+        }
+      }
+    } else {
+      for (int r = tid; r < nrows; r += SPMV_THREADS) {
+        const int a = row_ptr[r0 + r] - base, b = row_ptr[r0 + r + 1] - base;
+        TB s = 0;
+        for (int z = a; z < b; ++z) s += prod[z];
+        const int64_t row = r0 + r;
+        y[row] = xs * s - (yprev ? coef * yprev[row] : TB(0));
+      }
+    }
+  } else {
+    const int lr = -it.x - 1;
+    const int z0 = it.z, z1 = it.w;
+    TB s = 0;
+    for (int z = z0 + tid; z < z1; z += SPMV_THREADS) s += widen<TB>(val[z]) * x[col[z]];
+    s = wave_sum(s);
+    if (lane == 0) red[wv] = s;
+    __syncthreads();
+    if (tid == 0) {
+      TB t = 0;
+      for (int i = 0; i < SPMV_THREADS / WAVE; ++i) t += red[i];
+      partials[it.y] = t;
+      __threadfence();
+      const LongRow L = longrows[lr];
+      const unsigned int ticket = atomicAdd(&counters[lr], 1u);
+      flag = (ticket == static_cast<unsigned int>(L.npieces - 1));
+    }
+    __syncthreads();
+    if (flag && tid == 0) {
+      __threadfence();
+      const LongRow L = longrows[lr];
+      TB t = 0;
+      for (int q = 0; q < L.npieces; ++q) t += partials[L.first_piece + q];
+      y[L.row] = xs * t - (yprev ? coef * yprev[L.row] : TB(0));
+      atomicExch(&counters[lr], 0u);
+    }
+  }
+}
+
+}  // namespace svds

@@ -1,0 +1,99 @@
+// Host-side plan: device workspace arena, operator (A and A^T), per-kernel
+// timing, and the Lanczos cycle driver of Alg. 2.
+#pragma once
+#include <vector>
+#include <string>
+#include <chrono>
+
+#include "../../include/svds.h"
+#include "common.hpp"
+#include "kernels_spmv.hpp"
+
+namespace svds {
+
+constexpr int GMAX = 1024;  // largest grid of the reduction kernels
+
+// ---------------------------------------------------------------------------
+// Device arena: one hipMalloc, carved in 256-byte aligned pieces.
+// ---------------------------------------------------------------------------
+struct Arena {
+  char *base = nullptr;
+  size_t size = 0, used = 0;
+  bool counting = true;
+  template <typename T> T *take(size_t count) {
+    const size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    T *p = counting ? nullptr : reinterpret_cast<T *>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+// Work decomposition of one CSR product (see kernels_spmv.hpp).
+struct SpmvPlan {
+  int nitems = 0, nlong = 0, npieces = 0;
+  int4 *items = nullptr;
+  LongRow *longrows = nullptr;
+  double *partials = nullptr;  // npieces (TB <= 8 bytes)
+  unsigned int *counters = nullptr;
+  std::vector<int4> h_items;
+  std::vector<LongRow> h_long;
+};
+
+void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp);
+
+// ---------------------------------------------------------------------------
+// Per-kernel-class accounting and optional device timing with event pairs.
+// ---------------------------------------------------------------------------
+struct Accounting {
+  bool timing = false;
+  hipStream_t stream = nullptr;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  std::vector<int> cls;  // class of each recorded pair
+  double ms[SVDS_KC_COUNT] = {};
+  double bytes[SVDS_KC_COUNT] = {};
+  double flops[SVDS_KC_COUNT] = {};
+  int64_t launches[SVDS_KC_COUNT] = {};
+
+  void reset() {
+    for (int i = 0; i < SVDS_KC_COUNT; ++i) ms[i] = bytes[i] = flops[i] = 0, launches[i] = 0;
+    next = 0;
+    cls.clear();
+  }
+  int harvest();
+  int before(int kc);
+  int after(int kc, double b, double f);
+  void destroy() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+  }
+};
+
+// ---------------------------------------------------------------------------
+// The matrix operator: y = xs * A x - coef * yprev and the transpose.
+// ---------------------------------------------------------------------------
+struct Operator {
+  bool dense = false;
+  int64_t m = 0, n = 0, nnz = 0;
+  int vt = SVDS_F64;  // stored value type
+  // CSR of A (caller's) and of A^T (plan-owned)
+  const int32_t *rp = nullptr, *ci = nullptr;
+  const void *val = nullptr;
+  int32_t *trp = nullptr, *tci = nullptr;
+  void *tval = nullptr;
+  SpmvPlan fwd, bwd;
+  // dense
+  const void *a = nullptr;
+  int64_t lda = 0;
+  double *dpart = nullptr;        // slab partials of A x
+  unsigned int *dcnt = nullptr;   // row-tile arrival counters
+};
+
+}  // namespace svds
+
+// Internal entry points (C++ linkage) used by the single-step operations.
+int svds_plan_residuals(svds_plan *P, int k, const double *U, const double *S, const double *V,
+                        double *res_av, double *res_atu);
+int svds_plan_matvec(svds_plan *P, int trans, const void *x, const double *xs, const double *coef,
+                     const void *yprev, void *y, int basis_dtype);
+int svds_plan_transpose_copy(svds_plan *P, int32_t *t_row_ptr, int32_t *t_col_idx, void *t_val);

@@ -1,0 +1,946 @@
+// Alg. 2 driver: plan creation (workspace, transposed copy of A), the
+// Lanczos cycles with CGS2 re-orthogonalization, small SVD, restart and
+// output (Alg. 1, Proposition 1, eqs. (4)-(7), Alg. 2), plus the mixed
+// FP32 -> FP64 form.  Everything that touches vectors of length m or n runs in
+// the kernels of kernels_*.hpp; the host only enqueues kernels and reads one
+// convergence flag per cycle.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "plan.hpp"
+#include "kernels_cgs.hpp"
+#include "kernels_csc.hpp"
+#include "kernels_jacobi.hpp"
+#include "kernels_misc.hpp"
+#include "kernels_dense.hpp"
+
+namespace svds {
+
+// ---------------------------------------------------------------------------
+// error text
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512] = "";
+void set_last_error(hipError_t e, const char *what, const char *file, int line) {
+  snprintf(g_err, sizeof g_err, "%s: %s (%s:%d)", hipGetErrorString(e), what, file, line);
+}
+const char *last_error_text() { return g_err; }
+
+#define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+static inline unsigned grid_for(int64_t work, int64_t per_block, int64_t gmax = GMAX) {
+  int64_t g = ceil_div(std::max<int64_t>(work, 1), per_block);
+  return static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>(g, 1), gmax));
+}
+
+// ---------------------------------------------------------------------------
+// SpMV work items (host, at plan time)
+// ---------------------------------------------------------------------------
+void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp) {
+  sp.h_items.clear();
+  sp.h_long.clear();
+  int npieces = 0;
+  int64_t r = 0;
+  while (r < m) {
+    const int64_t len = rp[r + 1] - rp[r];
+    if (len > SPMV_NNZ_BLK) {
+      const int np = static_cast<int>(ceil_div(len, SPMV_PIECE));
+      const int lr = static_cast<int>(sp.h_long.size());
+      sp.h_long.push_back(LongRow{static_cast<int32_t>(r), npieces, np, 0});
+      for (int q = 0; q < np; ++q) {
+        const int64_t z0 = rp[r] + static_cast<int64_t>(q) * SPMV_PIECE;
+        const int64_t z1 = std::min<int64_t>(rp[r + 1], z0 + SPMV_PIECE);
+        sp.h_items.push_back(make_int4(-lr - 1, npieces + q, static_cast<int>(z0), static_cast<int>(z1)));
+      }
+      npieces += np;
+      ++r;
+      continue;
+    }
+    const int64_t r0 = r;
+    int64_t z = 0;
+    while (r < m && r - r0 < SPMV_ROWS_BLK) {
+      const int64_t l = rp[r + 1] - rp[r];
+      if (l > SPMV_NNZ_BLK || z + l > SPMV_NNZ_BLK) break;
+      z += l;
+      ++r;
+    }
+    sp.h_items.push_back(make_int4(static_cast<int>(r0), static_cast<int>(r), 0, 0));
+  }
+  sp.nitems = static_cast<int>(sp.h_items.size());
+  sp.nlong = static_cast<int>(sp.h_long.size());
+  sp.npieces = npieces;
+}
+
+// ---------------------------------------------------------------------------
+// Accounting
+// ---------------------------------------------------------------------------
+int Accounting::harvest() {
+  if (!timing || next == 0) return SVDS_OK;
+  HIP_TRY(hipEventSynchronize(pool[next - 1]));
+  for (size_t i = 0; i + 1 < next; i += 2) {
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, pool[i], pool[i + 1]));
+    ms[cls[i / 2]] += t;
+  }
+  next = 0;
+  cls.clear();
+  return SVDS_OK;
+}
+
+int Accounting::before(int kc) {
+  if (!timing) return SVDS_OK;
+  if (next + 2 > pool.size()) {
+    if (pool.size() < 16384) {
+      for (int i = 0; i < 1024; ++i) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        pool.push_back(e);
+      }
+    } else {
+      int rc = harvest();
+      if (rc) return rc;
+    }
+  }
+  cls.push_back(kc);
+  HIP_TRY(hipEventRecord(pool[next++], stream));
+  return SVDS_OK;
+}
+
+int Accounting::after(int kc, double b, double f) {
+  bytes[kc] += b;
+  flops[kc] += f;
+  launches[kc] += 1;
+  if (!timing) return SVDS_OK;
+  HIP_TRY(hipEventRecord(pool[next++], stream));
+  return SVDS_OK;
+}
+
+#define ACC_BEFORE(kc)                      \
+  do {                                      \
+    int rc_ = P->acc.before(kc);            \
+    if (rc_) return rc_;                    \
+  } while (0)
+#define ACC_AFTER(kc, b, f)                 \
+  do {                                      \
+    int rc_ = P->acc.after(kc, (b), (f));   \
+    if (rc_) return rc_;                    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Workspace of one precision: bases (ping-pong) and vectors.
+// ---------------------------------------------------------------------------
+template <typename TB> struct Lanczos {
+  int64_t m = 0, n = 0, ldu = 0, ldv = 0;
+  TB *U[2] = {}, *V[2] = {};
+  int cur = 0;
+  TB *wu = nullptr, *w1u = nullptr, *bu = nullptr;
+  TB *wv = nullptr, *w1v = nullptr, *bv = nullptr;
+  TB *h1 = nullptr, *h2 = nullptr, *partials = nullptr;
+  void carve(Arena &a, int64_t m_, int64_t n_, int p) {
+    m = m_;
+    n = n_;
+    ldu = ceil_div(m, 64) * 64;
+    ldv = ceil_div(n, 64) * 64;
+    for (int i = 0; i < 2; ++i) {
+      U[i] = a.take<TB>(static_cast<size_t>(ldu) * (p + 1));
+      V[i] = a.take<TB>(static_cast<size_t>(ldv) * (p + 1));
+    }
+    wu = a.take<TB>(m);
+    w1u = a.take<TB>(m);
+    bu = a.take<TB>(m);
+    wv = a.take<TB>(n);
+    w1v = a.take<TB>(n);
+    bv = a.take<TB>(n);
+    h1 = a.take<TB>(CGS_MAXJ);
+    h2 = a.take<TB>(CGS_MAXJ);
+    partials = a.take<TB>(static_cast<size_t>(CGS_MAXJ) * GMAX);
+  }
+};
+
+// Device scalars and small arrays shared by both precisions (FP64 always).
+struct Small {
+  double *T, *xs_u, *xs_v, *one, *sigma_est, *rho, *sig, *res, *Uk, *Vext, *jac, *npart;
+  double *resid_av, *resid_atu;
+  unsigned int *cnt;  // [0] proj, [1] upd_proj, [2] upd_norm, [3] norm
+  int *bd, *flags;
+};
+
+}  // namespace svds
+
+using namespace svds;
+
+struct svds_plan {
+  Operator op;
+  svds_opts opts{};
+  int k = 0, p = 0, maxit = 0;
+  double tol = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Arena arena;
+  Lanczos<double> L64;
+  Lanczos<float> L32;
+  bool mixed = false;
+  Small sc{};
+  double *tmp_nk = nullptr;  // n x k FP64 (mixed warm start), m-vector scratch
+  double *tmp_m = nullptr, *tmp_n = nullptr;
+  int *h_flags = nullptr;    // pinned
+  Accounting acc;
+  int64_t n_spmv = 0, n_spmvT = 0;
+  int cycles32 = 0, cycles64 = 0, jac_sweeps = 0;
+  int32_t *own_blocks[4] = {};
+};
+
+namespace svds {
+
+// ---------------------------------------------------------------------------
+// Products with A
+// ---------------------------------------------------------------------------
+static inline double vsize(int vt) { return vt == SVDS_F64 ? 8.0 : vt == SVDS_F32 ? 4.0 : 2.0; }
+
+template <typename TV, typename TB>
+static void dense_launch(svds_plan *P, bool trans, const TB *x, const double *xs, const double *coef,
+                         const TB *yprev, TB *y, TB *side_dst, int64_t side_len) {
+  const Operator &op = P->op;
+  const TV *A = static_cast<const TV *>(op.a);
+  if (trans) {
+    hipLaunchKernelGGL((gemv_t_kernel<TV, TB>), dim3(ceil_div(op.n, DN_THREADS / WAVE)),
+                       dim3(DN_THREADS), 0, P->stream, op.m, op.n, A, op.lda, x, xs, coef, yprev, y,
+                       side_dst, side_len);
+  } else {
+    hipLaunchKernelGGL((gemv_n_kernel<TV, TB>), dim3(ceil_div(op.m, DN_ROWS), ceil_div(op.n, DN_SLAB)),
+                       dim3(DN_THREADS), 0, P->stream, op.m, op.n, A, op.lda, x, xs, coef, yprev, y,
+                       reinterpret_cast<TB *>(op.dpart), op.dcnt, side_dst, side_len);
+  }
+}
+
+template <typename TB>
+static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const double *coef,
+                  const TB *yprev, TB *y, TB *side_dst, int64_t side_len, int kc_over = -1) {
+  const Operator &op = P->op;
+  const int64_t rows = trans ? op.n : op.m, cols = trans ? op.m : op.n;
+  const int kc = kc_over >= 0 ? kc_over : (trans ? SVDS_KC_SPMVT : SVDS_KC_SPMV);
+  const double sb = sizeof(TB);
+  ACC_BEFORE(kc);
+  double bytes;
+  if (op.dense) {
+    if (op.vt == SVDS_F64) dense_launch<double, TB>(P, trans, x, xs, coef, yprev, y, side_dst, side_len);
+    else if (op.vt == SVDS_F32) dense_launch<float, TB>(P, trans, x, xs, coef, yprev, y, side_dst, side_len);
+    else dense_launch<uint16_t, TB>(P, trans, x, xs, coef, yprev, y, side_dst, side_len);
+    LAUNCH_CHECK();
+    bytes = vsize(op.vt) * op.m * op.n + sb * cols + (yprev ? 2.0 : 1.0) * sb * rows;
+  } else {
+    const SpmvPlan &sp = trans ? op.bwd : op.fwd;
+    const int32_t *rp = trans ? op.trp : op.rp;
+    const int32_t *ci = trans ? op.tci : op.ci;
+    const void *val = trans ? op.tval : op.val;
+    TB *parts = reinterpret_cast<TB *>(sp.partials);
+    if (op.vt == SVDS_F64)
+      hipLaunchKernelGGL((spmv_csr_kernel<double, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
+                         P->stream, sp.items, sp.longrows, rp, ci,
+                         static_cast<const double *>(val), x, xs, coef, yprev, y, parts,
+                         sp.counters, side_dst, side_len);
+    else
+      hipLaunchKernelGGL((spmv_csr_kernel<float, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
+                         P->stream, sp.items, sp.longrows, rp, ci,
+                         static_cast<const float *>(val), x, xs, coef, yprev, y, parts,
+                         sp.counters, side_dst, side_len);
+    LAUNCH_CHECK();
+    bytes = 4.0 * (rows + 1) + (4.0 + vsize(op.vt)) * op.nnz + sb * cols +
+            (yprev ? 2.0 : 1.0) * sb * rows;
+  }
+  if (side_dst) bytes += 2.0 * sb * side_len;
+  ACC_AFTER(kc, bytes, 2.0 * (op.dense ? op.m * op.n : op.nnz));
+  if (kc_over < 0) {
+    if (trans) ++P->n_spmvT;
+    else ++P->n_spmv;
+  }
+  return SVDS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// CGS2 against Q[:, 0:j] and the norm/finish step.
+// w is the input; w1 is scratch; out receives the re-orthogonalized vector.
+// ---------------------------------------------------------------------------
+template <typename TB>
+static int cgs2_finish(svds_plan *P, Lanczos<TB> &Lz, const TB *Q, int64_t ldq, int64_t L, int j,
+                       const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs) {
+  const double sb = sizeof(TB);
+  const Small &s = P->sc;
+  const TB *src = w;
+  if (j > 0) {
+    const unsigned gp = grid_for(L, 2048);
+    ACC_BEFORE(SVDS_KC_CGS_PROJ);
+    hipLaunchKernelGGL((cgs_proj_kernel<TB>), dim3(gp), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
+                       L, j, w, Lz.partials, Lz.h1, s.cnt + 0);
+    LAUNCH_CHECK();
+    ACC_AFTER(SVDS_KC_CGS_PROJ, sb * L * j + sb * L, 2.0 * L * j);
+
+    const int nw = std::max(1, std::min(16, static_cast<int>(ceil_div(j, CGS_CPW))));
+    const unsigned gu = grid_for(L, 2048);
+    ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
+    hipLaunchKernelGGL((cgs_upd_proj_kernel<TB>), dim3(gu), dim3(nw * WAVE), 0, P->stream, Q, ldq,
+                       L, j, w, Lz.h1, w1, Lz.partials, Lz.h2, s.cnt + 1);
+    LAUNCH_CHECK();
+    ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 4.0 * L * j);
+    src = w1;
+  }
+  const unsigned gn = grid_for(L, 2048);
+  FinishArgs fa{t_entry, xs, s.sigma_est, s.bd, P->opts.seed};
+  ACC_BEFORE(SVDS_KC_CGS_UPDNORM);
+  hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(gn), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
+                     L, j, src, Lz.h2, out, s.npart, s.cnt + 2, mode, fa);
+  LAUNCH_CHECK();
+  ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * j + 2 * sb * L, 2.0 * L * j + 2.0 * L);
+  return SVDS_OK;
+}
+
+// Update only: out = w - Q h (restart, eq. (7)).
+template <typename TB>
+static int gemv_update(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, int j, const TB *w,
+                       const TB *h, TB *out) {
+  const double sb = sizeof(TB);
+  FinishArgs fa{nullptr, nullptr, nullptr, nullptr, 0};
+  const unsigned gn = grid_for(L, 2048);
+  ACC_BEFORE(SVDS_KC_OTHER);
+  hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(gn), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
+                     L, j, w, h, out, P->sc.npart, P->sc.cnt + 2, static_cast<int>(MODE_UPDATE), fa);
+  LAUNCH_CHECK();
+  ACC_AFTER(SVDS_KC_OTHER, sb * L * j + 2 * sb * L, 2.0 * L * j);
+  return SVDS_OK;
+}
+
+template <typename TB, typename TO>
+static int rotate(svds_plan *P, int64_t L, int pc, int kc, const TB *B, int64_t ldb,
+                  const double *Y, int64_t ldy, TO *out, int64_t ldo) {
+  const unsigned g = static_cast<unsigned>(ceil_div(L, ROT_THREADS));
+  ACC_BEFORE(SVDS_KC_ROTATE);
+  hipLaunchKernelGGL((rotate_kernel<TB, TO>), dim3(g), dim3(ROT_THREADS), 0, P->stream, L, pc, kc,
+                     B, ldb, Y, ldy, out, ldo);
+  LAUNCH_CHECK();
+  ACC_AFTER(SVDS_KC_ROTATE, sizeof(TB) * double(L) * pc + sizeof(TO) * double(L) * kc,
+            2.0 * L * pc * kc);
+  return SVDS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1 loop from 0-based column i0 until v_p and beta_{p-1} exist.
+// On entry: V[:, i0] is in the basis; the unnormalized u_{i0} is in bu with
+// reciprocal norm xs_u and T(i0, i0) set.
+// ---------------------------------------------------------------------------
+template <typename TB> static int lanczos(svds_plan *P, Lanczos<TB> &Lz, int i0) {
+  const int p = P->p;
+  const int64_t m = Lz.m, n = Lz.n;
+  const int ld = p + 1;
+  const Small &s = P->sc;
+  TB *U = Lz.U[Lz.cur], *V = Lz.V[Lz.cur];
+  for (int i = i0; i < p; ++i) {
+    // Alg. 1 steps 5-6: v_{i+1} = A^T u_i - alpha_i v_i, CGS2 against V[:, 0..i], beta_i.
+    // The product also writes the normalized u_i into U[:, i].
+    int rc = matvec<TB>(P, true, Lz.bu, s.xs_u, s.T + i * ld + i, V + i * Lz.ldv, Lz.wv,
+                        U + i * Lz.ldu, m);
+    if (rc) return rc;
+    rc = cgs2_finish<TB>(P, Lz, V, Lz.ldv, n, i + 1, Lz.wv, Lz.w1v, Lz.bv, MODE_LANCZOS,
+                         s.T + i * ld + i + 1, s.xs_v);
+    if (rc) return rc;
+    if (i == p - 1) {
+      // v_{p+1}: normalized into V[:, p] (no product consumes it in this cycle)
+      hipLaunchKernelGGL((scale_copy_kernel<TB>), dim3(ceil_div(n, 256)), dim3(256), 0, P->stream,
+                         n, Lz.bv, s.xs_v, V + p * Lz.ldv);
+      LAUNCH_CHECK();
+      break;
+    }
+    // Alg. 1 steps 7-8: u_{i+1} = A v_{i+1} - beta_i u_i, CGS2 against U[:, 0..i], alpha_{i+1}.
+    rc = matvec<TB>(P, false, Lz.bv, s.xs_v, s.T + i * ld + i + 1, U + i * Lz.ldu, Lz.wu,
+                    V + (i + 1) * Lz.ldv, n);
+    if (rc) return rc;
+    rc = cgs2_finish<TB>(P, Lz, U, Lz.ldu, m, i + 1, Lz.wu, Lz.w1u, Lz.bu, MODE_LANCZOS,
+                         s.T + (i + 1) * ld + i + 1, s.xs_u);
+    if (rc) return rc;
+  }
+  return SVDS_OK;
+}
+
+// Alg. 1 steps 1-3: v_1 = v0 / |v0| (v0 given as FP64 or drawn from Philox),
+// u_1 = A v_1, alpha_1.  `v0` may be FP64 device data of length n.
+template <typename TB> static int start(svds_plan *P, Lanczos<TB> &Lz, const double *v0) {
+  const int64_t n = Lz.n, m = Lz.m;
+  const Small &s = P->sc;
+  Lz.cur = 0;
+  if (v0) {
+    hipLaunchKernelGGL((cast_copy_kernel<double, TB>), dim3(ceil_div(n, 256)), dim3(256), 0,
+                       P->stream, n, v0, Lz.w1v);
+  } else {
+    hipLaunchKernelGGL((philox_fill_kernel<TB>), dim3(ceil_div(ceil_div(n, 2), 256)), dim3(256), 0,
+                       P->stream, n, P->opts.seed, 0u, Lz.w1v);
+  }
+  LAUNCH_CHECK();
+  // bv = v0, xs_v = 1/|v0| (no basis: the finish kernel only normalizes)
+  int rc = cgs2_finish<TB>(P, Lz, nullptr, 0, n, 0, Lz.w1v, nullptr, Lz.bv, MODE_NORM, nullptr, s.xs_v);
+  if (rc) return rc;
+  // u = A v_1; V[:, 0] = v0 * xs_v written by the product
+  rc = matvec<TB>(P, false, Lz.bv, s.xs_v, nullptr, nullptr, Lz.wu, Lz.V[0], n);
+  if (rc) return rc;
+  // alpha_1 (no re-orthogonalization for the first vector)
+  return cgs2_finish<TB>(P, Lz, nullptr, 0, m, 0, Lz.wu, nullptr, Lz.bu, MODE_LANCZOS, s.T, s.xs_u);
+}
+
+// Alg. 2 steps 4-7: small SVD, eq. (4) test; returns converged flag via h_flags.
+static int small_svd(svds_plan *P) {
+  const int p = P->p;
+  const int pe = p + (p & 1);
+  const int64_t wb = jacobi_work_bytes(p);
+  const bool use_lds = wb <= 64 * 1024;
+  const int rpl = static_cast<int>(ceil_div(pe, WAVE));
+  const size_t shm = use_lds ? static_cast<size_t>(wb) : 0;
+  const Small &s = P->sc;
+  const int nthr = std::min(JAC_THREADS, std::max(WAVE, static_cast<int>(ceil_div(pe / 2, 1)) * WAVE));
+  ACC_BEFORE(SVDS_KC_SMALLSVD);
+#define JAC_LAUNCH(R)                                                                           \
+  hipLaunchKernelGGL((small_svd_kernel<R>), dim3(1), dim3(nthr), shm, P->stream, s.T, p, P->k,  \
+                     P->tol, s.jac, s.Uk, s.Vext, s.sig, s.res, s.rho, s.flags, s.sigma_est,   \
+                     use_lds ? 1 : 0)
+  if (rpl <= 1) JAC_LAUNCH(1);
+  else if (rpl <= 2) JAC_LAUNCH(2);
+  else if (rpl <= 4) JAC_LAUNCH(4);
+  else if (rpl <= 8) JAC_LAUNCH(8);
+  else if (rpl <= 16) JAC_LAUNCH(16);
+  else return SVDS_EUNSUPPORTED;
+#undef JAC_LAUNCH
+  LAUNCH_CHECK();
+  ACC_AFTER(SVDS_KC_SMALLSVD, 16.0 * (p + 1) * (p + 1), 0.0);
+  HIP_TRY(hipMemcpyAsync(P->h_flags, s.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  P->jac_sweeps += P->h_flags[2];
+  return P->acc.harvest();
+}
+
+// Alg. 2 steps 8-12: Ritz vectors into the other ping-pong buffer, v_{k+1} =
+// v_{p+1}, u_{k+1} = A v_{k+1} - Uk rho (eq. (7)) re-orthogonalized, alpha_{k+1}.
+template <typename TB> static int restart(svds_plan *P, Lanczos<TB> &Lz) {
+  const int p = P->p, k = P->k, ld = p + 1;
+  const Small &s = P->sc;
+  const int nxt = 1 - Lz.cur;
+  TB *U = Lz.U[Lz.cur], *V = Lz.V[Lz.cur];
+  TB *Un = Lz.U[nxt], *Vn = Lz.V[nxt];
+  int rc = rotate<TB, TB>(P, Lz.m, p, k, U, Lz.ldu, s.Uk, p, Un, Lz.ldu);
+  if (rc) return rc;
+  rc = rotate<TB, TB>(P, Lz.n, p + 1, k + 1, V, Lz.ldv, s.Vext, ld, Vn, Lz.ldv);
+  if (rc) return rc;
+  Lz.cur = nxt;
+  // w = A v_{k+1}
+  rc = matvec<TB>(P, false, Vn + k * Lz.ldv, s.one, nullptr, nullptr, Lz.wu, nullptr, 0);
+  if (rc) return rc;
+  // w1 = w - Uk rho   (rho in FP64 -> basis type)
+  TB *rho_b = Lz.h1;
+  hipLaunchKernelGGL((cast_copy_kernel<double, TB>), dim3(1), dim3(256), 0, P->stream,
+                     static_cast<int64_t>(k), s.rho, rho_b);
+  LAUNCH_CHECK();
+  rc = gemv_update<TB>(P, Un, Lz.ldu, Lz.m, k, Lz.wu, rho_b, Lz.w1u);
+  if (rc) return rc;
+  // CGS2 against Uk, alpha_{k+1} = T(k, k)
+  return cgs2_finish<TB>(P, Lz, Un, Lz.ldu, Lz.m, k, Lz.w1u, Lz.wu, Lz.bu, MODE_LANCZOS,
+                         s.T + k * ld + k, s.xs_u);
+}
+
+// Runs cycles of one precision until the test passes with `tol_c`, maxit is
+// reached, or (stagnate > 0) the largest estimate stops decreasing.
+template <typename TB>
+static int run_cycles(svds_plan *P, Lanczos<TB> &Lz, double tol_c, int maxit, bool stagnate,
+                      int &cycles, bool &conv) {
+  cycles = 0;
+  conv = false;
+  double best = INFINITY;
+  int nodec = 0;
+  const double tol_save = P->tol;
+  P->tol = tol_c;
+  int rc = lanczos<TB>(P, Lz, 0);
+  while (rc == SVDS_OK) {
+    ++cycles;
+    rc = small_svd(P);
+    if (rc) break;
+    conv = P->h_flags[0] != 0;
+    if (conv || cycles >= maxit) break;
+    if (stagnate) {
+      double mx = 0;
+      std::vector<double> r(P->k);
+      HIP_TRY(hipMemcpy(r.data(), P->sc.res, sizeof(double) * P->k, hipMemcpyDeviceToHost));
+      for (double v : r) mx = std::max(mx, v);
+      if (mx < best) best = mx, nodec = 0;
+      else if (++nodec >= 2) break;
+    }
+    rc = restart<TB>(P, Lz);
+    if (rc) break;
+    rc = lanczos<TB>(P, Lz, P->k);
+  }
+  P->tol = tol_save;
+  return rc;
+}
+
+static int residuals_impl(svds_plan *P, int k, const double *U, const double *S, const double *V,
+                          double *res_av, double *res_atu);
+
+}  // namespace svds
+
+// ===========================================================================
+// Plan creation
+// ===========================================================================
+static int fill_defaults(const svds_opts *o, int64_t m, int64_t n, svds_plan *P) {
+  if (!o) return SVDS_EINVAL;
+  P->opts = *o;
+  P->k = o->k;
+  P->p = o->p > 0 ? o->p : std::max(15, 3 * o->k);
+  P->tol = o->tol > 0 ? o->tol : 1e-10;
+  P->maxit = o->maxit > 0 ? o->maxit : 10;
+  P->stream = static_cast<hipStream_t>(o->stream);
+  P->mixed = o->precision == SVDS_PREC_MIXED;
+  if (o->precision != SVDS_PREC_FP64 && o->precision != SVDS_PREC_MIXED) return SVDS_EINVAL;
+  if (P->k < 1 || P->p <= P->k || P->p > m || P->p + 1 > n) return SVDS_EINVAL;
+  if (P->p + 1 > CGS_MAXJ) return SVDS_EUNSUPPORTED;
+  return SVDS_OK;
+}
+
+static int carve_all(svds_plan *P, Arena &a) {
+  const int p = P->p, k = P->k;
+  const int64_t m = P->op.m, n = P->op.n;
+  P->L64.carve(a, m, n, p);
+  if (P->mixed) P->L32.carve(a, m, n, p);
+  Small &s = P->sc;
+  s.T = a.take<double>(static_cast<size_t>(p + 1) * (p + 1));
+  s.xs_u = a.take<double>(1);
+  s.xs_v = a.take<double>(1);
+  s.one = a.take<double>(1);
+  s.sigma_est = a.take<double>(1);
+  s.rho = a.take<double>(k);
+  s.sig = a.take<double>(k);
+  s.res = a.take<double>(k);
+  s.Uk = a.take<double>(static_cast<size_t>(p) * k);
+  s.Vext = a.take<double>(static_cast<size_t>(p + 1) * (k + 1));
+  s.jac = a.take<double>(jacobi_work_bytes(p) / 8 + 8);
+  s.npart = a.take<double>(GMAX);
+  s.resid_av = a.take<double>(k);
+  s.resid_atu = a.take<double>(k);
+  s.cnt = a.take<unsigned int>(8);
+  s.bd = a.take<int>(4);
+  s.flags = a.take<int>(4);
+  P->tmp_m = a.take<double>(m);
+  P->tmp_n = a.take<double>(n);
+  if (P->mixed) P->tmp_nk = a.take<double>(static_cast<size_t>(n) * k);
+  if (P->op.dense) {
+    P->op.dpart = a.take<double>(dense_partial_doubles(m, n));
+    P->op.dcnt = a.take<unsigned int>(dense_counter_count(m));
+  } else {
+    P->op.fwd.partials = a.take<double>(std::max(1, P->op.fwd.npieces));
+    P->op.fwd.counters = a.take<unsigned int>(std::max(1, P->op.fwd.nlong));
+    P->op.fwd.items = a.take<int4>(P->op.fwd.nitems);
+    P->op.fwd.longrows = a.take<LongRow>(std::max(1, P->op.fwd.nlong));
+    P->op.bwd.partials = a.take<double>(std::max(1, P->op.bwd.npieces));
+    P->op.bwd.counters = a.take<unsigned int>(std::max(1, P->op.bwd.nlong));
+    P->op.bwd.items = a.take<int4>(P->op.bwd.nitems);
+    P->op.bwd.longrows = a.take<LongRow>(std::max(1, P->op.bwd.nlong));
+    P->op.trp = a.take<int32_t>(n + 1);
+    P->op.tci = a.take<int32_t>(std::max<int64_t>(1, P->op.nnz));
+    P->op.tval = a.take<char>(std::max<int64_t>(1, P->op.nnz) * static_cast<size_t>(vsize(P->op.vt)));
+  }
+  return SVDS_OK;
+}
+
+static int alloc_arena(svds_plan *P) {
+  Arena a;
+  a.counting = true;
+  carve_all(P, a);
+  const size_t bytes = a.used;
+  void *base = nullptr;
+  if (hipMalloc(&base, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return SVDS_ENOMEM;
+  }
+  P->arena.base = static_cast<char *>(base);
+  P->arena.size = bytes;
+  P->arena.used = 0;
+  P->arena.counting = false;
+  carve_all(P, P->arena);
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&P->h_flags), 16 * sizeof(int), hipHostMallocDefault));
+  const double one = 1.0;
+  HIP_TRY(hipMemcpyAsync(P->sc.one, &one, sizeof one, hipMemcpyHostToDevice, P->stream));
+  HIP_TRY(hipMemsetAsync(P->sc.cnt, 0, 8 * sizeof(unsigned int), P->stream));
+  if (P->op.dense)
+    HIP_TRY(hipMemsetAsync(P->op.dcnt, 0, sizeof(unsigned int) * dense_counter_count(P->op.m), P->stream));
+  return SVDS_OK;
+}
+
+// Transposed copy: stable LSD radix sort of column keys (see kernels_csc.hpp).
+static int build_transpose(svds_plan *P) {
+  Operator &op = P->op;
+  const int64_t m = op.m, n = op.n, nnz = op.nnz;
+  hipStream_t st = P->stream;
+  if (nnz == 0) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0, st, n + 1, 0, op.trp);
+    LAUNCH_CHECK();
+    return SVDS_OK;
+  }
+  const int64_t ntiles = ceil_div(nnz, RS_TILE);
+  const int64_t nh = ntiles * RS_BINS;
+  const int64_t nsum = ceil_div(nh, SCAN_TILE);
+  int32_t *buf = nullptr;
+  const size_t words = 5 * static_cast<size_t>(nnz) + 2 * static_cast<size_t>(nh) + nsum + 64;
+  HIP_TRY(hipMalloc(&buf, words * sizeof(int32_t)));
+  int32_t *rowof = buf, *k0 = buf + nnz, *v0 = buf + 2 * nnz, *k1 = buf + 3 * nnz, *v1 = buf + 4 * nnz;
+  int32_t *hist = buf + 5 * nnz, *offs = hist + nh, *sums = offs + nh;
+  int rc = SVDS_OK;
+  do {
+    hipLaunchKernelGGL(csc_expand_kernel, dim3(ceil_div(m, 256)), dim3(256), 0, st, m, op.rp, op.ci,
+                       rowof, k0, v0);
+    if (hipGetLastError() != hipSuccess) { rc = SVDS_EDEVICE; break; }
+    int bits = 1;
+    while ((int64_t(1) << bits) < n) ++bits;
+    int32_t *kin = k0, *vin = v0, *kout = k1, *vout = v1;
+    for (int shift = 0; shift < bits; shift += RS_BITS) {
+      hipLaunchKernelGGL(radix_hist_kernel, dim3(ntiles), dim3(RS_THREADS), 0, st, kin, nnz, shift,
+                         hist, ntiles);
+      hipLaunchKernelGGL(scan_tile_sums_kernel, dim3(nsum), dim3(SCAN_THREADS), 0, st, hist, nh, sums);
+      hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_THREADS), 0, st, sums, nsum);
+      hipLaunchKernelGGL(scan_apply_kernel, dim3(nsum), dim3(SCAN_THREADS), 0, st, hist, nh, sums, offs);
+      hipLaunchKernelGGL(radix_scatter_kernel, dim3(ntiles), dim3(RS_THREADS), 0, st, kin, vin, nnz,
+                         shift, offs, ntiles, kout, vout);
+      if (hipGetLastError() != hipSuccess) { rc = SVDS_EDEVICE; break; }
+      std::swap(kin, kout);
+      std::swap(vin, vout);
+    }
+    if (rc) break;
+    if (op.vt == SVDS_F64)
+      hipLaunchKernelGGL((csc_gather_kernel<double>), dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz,
+                         vin, rowof, static_cast<const double *>(op.val), op.tci,
+                         static_cast<double *>(op.tval));
+    else
+      hipLaunchKernelGGL((csc_gather_kernel<float>), dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz,
+                         vin, rowof, static_cast<const float *>(op.val), op.tci,
+                         static_cast<float *>(op.tval));
+    hipLaunchKernelGGL(csc_colptr_kernel, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz, n, kin, op.trp);
+    if (hipGetLastError() != hipSuccess) { rc = SVDS_EDEVICE; break; }
+    if (hipStreamSynchronize(st) != hipSuccess) { rc = SVDS_EDEVICE; break; }
+  } while (0);
+  (void)hipFree(buf);
+  return rc;
+}
+
+static int upload_spmv(svds_plan *P, SpmvPlan &sp) {
+  HIP_TRY(hipMemcpyAsync(sp.items, sp.h_items.data(), sizeof(int4) * sp.nitems, hipMemcpyHostToDevice,
+                         P->stream));
+  if (sp.nlong) {
+    HIP_TRY(hipMemcpyAsync(sp.longrows, sp.h_long.data(), sizeof(LongRow) * sp.nlong,
+                           hipMemcpyHostToDevice, P->stream));
+    HIP_TRY(hipMemsetAsync(sp.counters, 0, sizeof(unsigned int) * sp.nlong, P->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return SVDS_OK;
+}
+
+namespace {
+// Destroys a partially built plan on every early return of plan creation.
+struct PlanGuard {
+  svds_plan *p;
+  ~PlanGuard() {
+    if (p) svds_plan_destroy(p);
+  }
+  svds_plan *release() {
+    svds_plan *q = p;
+    p = nullptr;
+    return q;
+  }
+};
+}  // namespace
+
+extern "C" int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, svds_plan **plan) {
+  if (!A || !opts || !plan) return SVDS_EINVAL;
+  *plan = nullptr;
+  if (A->m < 1 || A->n < 1 || A->nnz < 0 || A->nnz >= (int64_t(1) << 31) || A->m >= (int64_t(1) << 31) ||
+      A->n >= (int64_t(1) << 31))
+    return SVDS_EINVAL;
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val))) return SVDS_EINVAL;
+  if (A->dtype != SVDS_F64 && A->dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
+  svds_plan *P = new (std::nothrow) svds_plan();
+  if (!P) return SVDS_ENOMEM;
+  PlanGuard guard{P};
+  int rc = fill_defaults(opts, A->m, A->n, P);
+  if (rc) return rc;
+  HIP_TRY(hipGetDevice(&P->device));
+  Operator &op = P->op;
+  op.dense = false;
+  op.m = A->m;
+  op.n = A->n;
+  op.nnz = A->nnz;
+  op.vt = A->dtype;
+  op.rp = A->row_ptr;
+  op.ci = A->col_idx;
+  op.val = A->val;
+  P->acc.stream = P->stream;
+  P->acc.timing = (opts->flags & SVDS_FLAG_TIMING) != 0;
+  // work items of A (row pointers read back once)
+  std::vector<int32_t> hrp(A->m + 1);
+  HIP_TRY(hipMemcpy(hrp.data(), A->row_ptr, sizeof(int32_t) * (A->m + 1), hipMemcpyDeviceToHost));
+  if (hrp[0] != 0 || hrp[A->m] != A->nnz) return SVDS_EINVAL;
+  for (int64_t i = 0; i < A->m; ++i)
+    if (hrp[i + 1] < hrp[i]) return SVDS_EINVAL;
+  build_spmv_items(hrp.data(), A->m, op.fwd);
+  // A^T items need the column counts: computed after the device transpose,
+  // so size the arena with a bound first (one item per column is the max).
+  op.bwd.nitems = static_cast<int>(std::max<int64_t>(1, A->n + ceil_div(A->nnz, SPMV_PIECE) + 1));
+  op.bwd.nlong = static_cast<int>(std::max<int64_t>(1, ceil_div(A->nnz, SPMV_NNZ_BLK) + 1));
+  op.bwd.npieces = static_cast<int>(std::max<int64_t>(1, ceil_div(A->nnz, SPMV_PIECE) + op.bwd.nlong));
+  const int bwd_items_cap = op.bwd.nitems, bwd_long_cap = op.bwd.nlong, bwd_pieces_cap = op.bwd.npieces;
+  if ((rc = alloc_arena(P))) return rc;
+  if ((rc = build_transpose(P))) return rc;
+  std::vector<int32_t> htrp(A->n + 1);
+  HIP_TRY(hipMemcpy(htrp.data(), op.trp, sizeof(int32_t) * (A->n + 1), hipMemcpyDeviceToHost));
+  int4 *bi = op.bwd.items;
+  LongRow *bl = op.bwd.longrows;
+  double *bp = op.bwd.partials;
+  unsigned int *bc = op.bwd.counters;
+  build_spmv_items(htrp.data(), A->n, op.bwd);
+  if (op.bwd.nitems > bwd_items_cap || op.bwd.nlong > bwd_long_cap || op.bwd.npieces > bwd_pieces_cap)
+    return SVDS_EDEVICE;
+  op.bwd.items = bi;
+  op.bwd.longrows = bl;
+  op.bwd.partials = bp;
+  op.bwd.counters = bc;
+  if ((rc = upload_spmv(P, op.fwd)) || (rc = upload_spmv(P, op.bwd))) return rc;
+  *plan = guard.release();
+  return SVDS_OK;
+}
+
+extern "C" int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts, svds_plan **plan) {
+  if (!A || !opts || !plan) return SVDS_EINVAL;
+  *plan = nullptr;
+  if (A->m < 1 || A->n < 1 || A->ld < A->m || !A->a) return SVDS_EINVAL;
+  if (A->dtype != SVDS_F64 && A->dtype != SVDS_F32 && A->dtype != SVDS_BF16) return SVDS_EUNSUPPORTED;
+  svds_plan *P = new (std::nothrow) svds_plan();
+  if (!P) return SVDS_ENOMEM;
+  PlanGuard guard{P};
+  int rc = fill_defaults(opts, A->m, A->n, P);
+  if (rc) return rc;
+  HIP_TRY(hipGetDevice(&P->device));
+  Operator &op = P->op;
+  op.dense = true;
+  op.m = A->m;
+  op.n = A->n;
+  op.vt = A->dtype;
+  op.a = A->a;
+  op.lda = A->ld;
+  P->acc.stream = P->stream;
+  P->acc.timing = (opts->flags & SVDS_FLAG_TIMING) != 0;
+  if ((rc = alloc_arena(P))) return rc;
+  *plan = guard.release();
+  return SVDS_OK;
+}
+
+extern "C" void svds_plan_destroy(svds_plan *P) {
+  if (!P) return;
+  if (P->arena.base) (void)hipFree(P->arena.base);
+  if (P->h_flags) (void)hipHostFree(P->h_flags);
+  P->acc.destroy();
+  delete P;
+}
+
+// ===========================================================================
+// Execute
+// ===========================================================================
+namespace svds {
+
+template <typename TB>
+static int outputs(svds_plan *P, Lanczos<TB> &Lz, double *U, double *S, double *V) {
+  const int p = P->p, k = P->k;
+  const int64_t m = P->op.m, n = P->op.n;
+  // Alg. 2 steps 15-16
+  int rc = rotate<TB, double>(P, m, p, k, Lz.U[Lz.cur], Lz.ldu, P->sc.Uk, p, U, m);
+  if (rc) return rc;
+  rc = rotate<TB, double>(P, n, p, k, Lz.V[Lz.cur], Lz.ldv, P->sc.Vext, p + 1, V, n);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(S, P->sc.sig, sizeof(double) * k, hipMemcpyDeviceToDevice, P->stream));
+  return SVDS_OK;
+}
+
+// v1 of the FP64 phase from the FP32 Ritz vectors: sum_j Vk(:, j) / sqrt(k).
+static int warm_start_vector(svds_plan *P) {
+  const int p = P->p, k = P->k;
+  const int64_t n = P->op.n;
+  int rc = rotate<float, double>(P, n, p, k, P->L32.V[P->L32.cur], P->L32.ldv, P->sc.Vext, p + 1,
+                                 P->tmp_nk, n);
+  if (rc) return rc;
+  // tmp_n = Vk * (1/sqrt(k) * ones): a rotation with a k x 1 panel
+  std::vector<double> w(k, 1.0 / std::sqrt(static_cast<double>(k)));
+  HIP_TRY(hipMemcpyAsync(P->tmp_m, w.data(), sizeof(double) * k, hipMemcpyHostToDevice, P->stream));
+  rc = rotate<double, double>(P, n, k, 1, P->tmp_nk, n, P->tmp_m, k, P->tmp_n, n);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return SVDS_OK;
+}
+
+}  // namespace svds
+
+extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, svds_info *info) {
+  if (!P || !U || !S || !V) return SVDS_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  HIP_TRY(hipSetDevice(P->device));
+  P->acc.reset();
+  P->n_spmv = P->n_spmvT = 0;
+  P->cycles32 = P->cycles64 = P->jac_sweeps = 0;
+  HIP_TRY(hipMemsetAsync(P->sc.sigma_est, 0, sizeof(double), P->stream));
+  HIP_TRY(hipMemsetAsync(P->sc.bd, 0, 4 * sizeof(int), P->stream));
+  HIP_TRY(hipMemsetAsync(P->sc.T, 0, sizeof(double) * (P->p + 1) * (P->p + 1), P->stream));
+  int rc = SVDS_OK;
+  bool conv = false;
+  int cyc = 0;
+  if (P->mixed) {
+    const double tol32 = std::max(P->tol, 1e-5);
+    rc = start<float>(P, P->L32, P->opts.v0);
+    if (!rc) rc = run_cycles<float>(P, P->L32, tol32, P->maxit, true, cyc, conv);
+    P->cycles32 = cyc;
+    if (!rc) rc = warm_start_vector(P);
+    if (!rc) {
+      HIP_TRY(hipMemsetAsync(P->sc.sigma_est, 0, sizeof(double), P->stream));
+      HIP_TRY(hipMemsetAsync(P->sc.T, 0, sizeof(double) * (P->p + 1) * (P->p + 1), P->stream));
+      rc = start<double>(P, P->L64, P->tmp_n);
+    }
+    if (!rc) rc = run_cycles<double>(P, P->L64, P->tol, std::max(1, P->maxit - cyc), false, cyc, conv);
+    P->cycles64 = cyc;
+  } else {
+    rc = start<double>(P, P->L64, P->opts.v0);
+    if (!rc) rc = run_cycles<double>(P, P->L64, P->tol, P->maxit, false, cyc, conv);
+    P->cycles64 = cyc;
+  }
+  if (rc) return rc;
+  rc = outputs<double>(P, P->L64, U, S, V);
+  if (rc) return rc;
+  if (!(P->opts.flags & SVDS_FLAG_NO_SIGNFIX)) {
+    hipLaunchKernelGGL(signfix_kernel, dim3(P->k), dim3(256), 0, P->stream, P->op.m, P->op.n, U,
+                       P->op.m, V, P->op.n);
+    LAUNCH_CHECK();
+  }
+  double res_true = 0, res_av = 0;
+  if (!(P->opts.flags & SVDS_FLAG_NO_RESIDUALS)) {
+    rc = residuals_impl(P, P->k, U, S, V, P->sc.resid_av, P->sc.resid_atu);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  rc = P->acc.harvest();
+  if (rc) return rc;
+  const int k = P->k;
+  std::vector<double> hs(k), hres(k), hav(k), hatu(k);
+  int bd = 0;
+  HIP_TRY(hipMemcpy(hs.data(), P->sc.sig, sizeof(double) * k, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hres.data(), P->sc.res, sizeof(double) * k, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(&bd, P->sc.bd, sizeof(int), hipMemcpyDeviceToHost));
+  if (!(P->opts.flags & SVDS_FLAG_NO_RESIDUALS)) {
+    HIP_TRY(hipMemcpy(hav.data(), P->sc.resid_av, sizeof(double) * k, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hatu.data(), P->sc.resid_atu, sizeof(double) * k, hipMemcpyDeviceToHost));
+    for (int j = 0; j < k; ++j) {
+      const double sj = std::max(hs[j], std::max(0x1.0p-52 * hs[0], 2.2250738585072014e-308));
+      res_true = std::max(res_true, hatu[j] / sj);
+      res_av = std::max(res_av, hav[j] / std::max(hs[0], 2.2250738585072014e-308));
+    }
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    std::memset(info, 0, sizeof *info);
+    info->nconv = P->h_flags[1];
+    info->converged = conv ? 1 : 0;
+    info->cycles = P->cycles32 + P->cycles64;
+    info->cycles_fp32 = P->cycles32;
+    info->cycles_fp64 = P->cycles64;
+    info->breakdowns = bd;
+    info->n_spmv = P->n_spmv;
+    info->n_spmvT = P->n_spmvT;
+    double mx = 0;
+    for (double v : hres) mx = std::max(mx, v);
+    info->max_res_est = mx;
+    info->max_res_true = res_true;
+    info->max_res_av = res_av;
+    info->ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    double ba = 0;
+    for (int c : {SVDS_KC_SPMV, SVDS_KC_SPMVT, SVDS_KC_CGS_PROJ, SVDS_KC_CGS_UPDPROJ, SVDS_KC_CGS_UPDNORM})
+      ba += P->acc.bytes[c];
+    info->bytes_alg = ba;
+    for (int c = 0; c < SVDS_KC_COUNT; ++c) {
+      info->kc_ms[c] = P->acc.ms[c];
+      info->kc_bytes[c] = P->acc.bytes[c];
+      info->kc_flops[c] = P->acc.flops[c];
+      info->kc_launches[c] = P->acc.launches[c];
+    }
+    info->workspace_bytes = static_cast<int64_t>(P->arena.size);
+  }
+  return conv ? SVDS_OK : SVDS_NOT_CONVERGED;
+}
+
+// ===========================================================================
+// Residuals (Proposition 1, eq. (2), evaluated explicitly in FP64)
+// ===========================================================================
+namespace svds {
+static int residuals_impl(svds_plan *P, int k, const double *U, const double *S, const double *V,
+                          double *res_av, double *res_atu) {
+  const int64_t m = P->op.m, n = P->op.n;
+  const int64_t sv = P->n_spmv, st = P->n_spmvT;
+  for (int j = 0; j < k; ++j) {
+    // tmp_m = A v_j - s_j u_j
+    int rc = matvec<double>(P, false, V + j * n, P->sc.one, S + j, U + j * m, P->tmp_m, nullptr, 0,
+                            SVDS_KC_OTHER);
+    if (rc) return rc;
+    hipLaunchKernelGGL((norm_kernel<double>), dim3(grid_for(m, 4096)), dim3(256), 0, P->stream, m,
+                       P->tmp_m, P->sc.npart, P->sc.cnt + 3, res_av + j);
+    LAUNCH_CHECK();
+    rc = matvec<double>(P, true, U + j * m, P->sc.one, S + j, V + j * n, P->tmp_n, nullptr, 0,
+                        SVDS_KC_OTHER);
+    if (rc) return rc;
+    hipLaunchKernelGGL((norm_kernel<double>), dim3(grid_for(n, 4096)), dim3(256), 0, P->stream, n,
+                       P->tmp_n, P->sc.npart, P->sc.cnt + 3, res_atu + j);
+    LAUNCH_CHECK();
+  }
+  // residual products are not Lanczos steps (booked under OTHER, not counted)
+  (void)sv;
+  (void)st;
+  return SVDS_OK;
+}
+}  // namespace svds
+
+// ===========================================================================
+// Internal entry points of the single-step operations
+// ===========================================================================
+int svds_plan_residuals(svds_plan *P, int k, const double *U, const double *S, const double *V,
+                        double *res_av, double *res_atu) {
+  int rc = residuals_impl(P, k, U, S, V, res_av, res_atu);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return SVDS_OK;
+}
+
+int svds_plan_matvec(svds_plan *P, int trans, const void *x, const double *xs, const double *coef,
+                     const void *yprev, void *y, int basis_dtype) {
+  int rc;
+  if (basis_dtype == SVDS_F64)
+    rc = matvec<double>(P, trans != 0, static_cast<const double *>(x), xs, coef,
+                        static_cast<const double *>(yprev), static_cast<double *>(y), nullptr, 0,
+                        SVDS_KC_OTHER);
+  else if (basis_dtype == SVDS_F32)
+    rc = matvec<float>(P, trans != 0, static_cast<const float *>(x), xs, coef,
+                       static_cast<const float *>(yprev), static_cast<float *>(y), nullptr, 0,
+                       SVDS_KC_OTHER);
+  else
+    return SVDS_EUNSUPPORTED;
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return SVDS_OK;
+}
+
+int svds_plan_transpose_copy(svds_plan *P, int32_t *t_row_ptr, int32_t *t_col_idx, void *t_val) {
+  const Operator &op = P->op;
+  if (op.dense) return SVDS_EINVAL;
+  HIP_TRY(hipMemcpyAsync(t_row_ptr, op.trp, sizeof(int32_t) * (op.n + 1), hipMemcpyDeviceToDevice, P->stream));
+  if (op.nnz > 0) {
+    HIP_TRY(hipMemcpyAsync(t_col_idx, op.tci, sizeof(int32_t) * op.nnz, hipMemcpyDeviceToDevice, P->stream));
+    HIP_TRY(hipMemcpyAsync(t_val, op.tval, static_cast<size_t>(vsize(op.vt)) * op.nnz,
+                           hipMemcpyDeviceToDevice, P->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return SVDS_OK;
+}

@@ -1,0 +1,337 @@
+"""Thin Python binding of the C ABI (include/svds.h, include/svds_ops.h).
+
+Argument marshalling only: the functions below take torch tensors that live
+on the GPU (device memory and streams come from PyTorch), build the C structs
+and call libsvds.so, whose HIP kernels do all the work.  Names follow the C
+entry points.  The library is loaded from this package directory; if it is
+missing the import fails with an explicit error -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsvds.so")
+
+SVDS_OK, SVDS_NOT_CONVERGED = 0, 1
+SVDS_EINVAL, SVDS_ENOMEM, SVDS_EDEVICE, SVDS_EUNSUPPORTED = -1, -2, -3, -4
+SVDS_F64, SVDS_F32, SVDS_BF16 = 0, 1, 2
+SVDS_PREC_FP64, SVDS_PREC_MIXED = 0, 1
+SVDS_FLAG_TIMING, SVDS_FLAG_NO_RESIDUALS, SVDS_FLAG_NO_SIGNFIX = 1, 2, 4
+KERNEL_CLASSES = ["spmv", "spmvT", "cgs_proj", "cgs_updproj", "cgs_updnorm", "smallsvd", "rotate", "other"]
+KC_COUNT = len(KERNEL_CLASSES)
+
+
+class svds_csr(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("dtype", C.c_int32)]
+
+
+class svds_dense(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("ld", C.c_int64),
+                ("a", C.c_void_p), ("dtype", C.c_int32)]
+
+
+class svds_opts(C.Structure):
+    _fields_ = [("k", C.c_int32), ("p", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32),
+                ("precision", C.c_int32), ("seed", C.c_uint64), ("v0", C.c_void_p),
+                ("stream", C.c_void_p), ("flags", C.c_int32)]
+
+
+class svds_info(C.Structure):
+    _fields_ = [("nconv", C.c_int32), ("cycles", C.c_int32), ("cycles_fp32", C.c_int32),
+                ("cycles_fp64", C.c_int32), ("breakdowns", C.c_int32), ("converged", C.c_int32),
+                ("n_spmv", C.c_int64), ("n_spmvT", C.c_int64),
+                ("max_res_est", C.c_double), ("max_res_true", C.c_double), ("max_res_av", C.c_double),
+                ("ms_total", C.c_double), ("bytes_alg", C.c_double),
+                ("kc_ms", C.c_double * KC_COUNT), ("kc_bytes", C.c_double * KC_COUNT),
+                ("kc_flops", C.c_double * KC_COUNT), ("kc_launches", C.c_int64 * KC_COUNT),
+                ("workspace_bytes", C.c_int64)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("kc_")}
+        for f in ("kc_ms", "kc_bytes", "kc_flops", "kc_launches"):
+            d[f] = dict(zip(KERNEL_CLASSES, list(getattr(self, f))))
+        return d
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"native library {LIB_PATH} not built: run "
+                           "`python -c 'import __graft_entry__ as g; g.build()'` first")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, d, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64
+    P = C.POINTER
+    sig = {
+        "svds_plan_create_csr": (i32, [P(svds_csr), P(svds_opts), P(vp)]),
+        "svds_plan_create_dense": (i32, [P(svds_dense), P(svds_opts), P(vp)]),
+        "svds_plan_execute": (i32, [vp, vp, vp, vp, P(svds_info)]),
+        "svds_plan_destroy": (None, [vp]),
+        "svds_csr_solve": (i32, [P(svds_csr), P(svds_opts), vp, vp, vp, P(svds_info)]),
+        "svds_dense_solve": (i32, [P(svds_dense), P(svds_opts), vp, vp, vp, P(svds_info)]),
+        "svds_csr_solve_batched": (i32, [i32, P(svds_csr), P(svds_opts), P(vp), P(vp), P(vp),
+                                         P(svds_info)]),
+        "svds_residuals_csr": (i32, [P(svds_csr), i32, vp, vp, vp, vp, vp, vp]),
+        "svds_strerror": (C.c_char_p, [i32]),
+        "svds_version": (C.c_char_p, []),
+        "svds_op_spmv_csr": (i32, [P(svds_csr), vp, vp, vp, vp, vp, i32, vp]),
+        "svds_op_dense_matvec": (i32, [P(svds_dense), i32, vp, vp, vp, vp, vp, i32, vp]),
+        "svds_op_csc_build": (i32, [P(svds_csr), vp, vp, vp, vp]),
+        "svds_op_cgs2": (i32, [i64, i32, vp, i64, vp, vp, P(d), i32, vp]),
+        "svds_op_small_svd": (i32, [i32, i32, d, vp, vp, vp, vp, vp, vp, P(i32), vp]),
+        "svds_op_rotate": (i32, [i64, i32, i32, vp, i64, i32, vp, i64, vp, i64, vp]),
+        "svds_op_philox_normal": (i32, [i64, u64, C.c_uint32, vp, vp]),
+        "svds_op_copy_f64": (i32, [i64, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class SvdsError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {lib.svds_strerror(code).decode()} (code {code})")
+        self.code = code
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise SvdsError(rc, where)
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+_VT = {torch.float64: SVDS_F64, torch.float32: SVDS_F32, torch.uint16: SVDS_BF16,
+       torch.bfloat16: SVDS_BF16}
+
+
+def make_csr(row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, m: int, n: int) -> svds_csr:
+    """C struct for a device CSR (int32 row_ptr/col_idx, FP64/FP32 values)."""
+    assert row_ptr.dtype == torch.int32 and col_idx.dtype == torch.int32
+    assert row_ptr.is_cuda and col_idx.is_cuda and val.is_cuda
+    assert row_ptr.numel() == m + 1
+    return svds_csr(m, n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr(), val.data_ptr(),
+                    _VT[val.dtype])
+
+
+def make_dense(a: torch.Tensor, m: int, n: int) -> svds_dense:
+    """C struct for a column-major device matrix given as a 1-D tensor of
+    m*n (ld = m) FP64/FP32 values or BF16 bit patterns (uint16/bfloat16)."""
+    assert a.is_cuda and a.numel() == m * n
+    return svds_dense(m, n, m, a.data_ptr(), _VT[a.dtype])
+
+
+def make_opts(k, p=0, tol=0.0, maxit=0, precision=SVDS_PREC_FP64, seed=0, v0=None, flags=0,
+              stream=None) -> svds_opts:
+    return svds_opts(k, p, tol, maxit, precision, seed, None if v0 is None else v0.data_ptr(),
+                     _stream(stream), flags)
+
+
+def _outputs(m, n, k, device):
+    U = torch.empty((k, m), dtype=torch.float64, device=device)  # column j = U[j]
+    S = torch.empty(k, dtype=torch.float64, device=device)
+    V = torch.empty((k, n), dtype=torch.float64, device=device)
+    return U, S, V
+
+
+@dataclass
+class Result:
+    U: torch.Tensor   # m x k (a transposed view of column-major storage)
+    S: torch.Tensor   # k
+    V: torch.Tensor   # n x k
+    info: dict
+    status: int
+
+
+def svds_csr_solve(A: svds_csr, opts: svds_opts) -> Result:
+    """k largest singular triplets of a device CSR matrix (create + execute +
+    destroy of a plan)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    U, S, V = _outputs(A.m, A.n, opts.k, dev)
+    info = svds_info()
+    rc = _check(lib.svds_csr_solve(C.byref(A), C.byref(opts), _ptr(U), _ptr(S), _ptr(V),
+                                   C.byref(info)), "svds_csr_solve")
+    return Result(U.T, S, V.T, info.as_dict(), rc)
+
+
+def svds_dense_solve(A: svds_dense, opts: svds_opts) -> Result:
+    dev = torch.device("cuda", torch.cuda.current_device())
+    U, S, V = _outputs(A.m, A.n, opts.k, dev)
+    info = svds_info()
+    rc = _check(lib.svds_dense_solve(C.byref(A), C.byref(opts), _ptr(U), _ptr(S), _ptr(V),
+                                     C.byref(info)), "svds_dense_solve")
+    return Result(U.T, S, V.T, info.as_dict(), rc)
+
+
+class Plan:
+    """svds_plan_create_* / svds_plan_execute / svds_plan_destroy."""
+
+    def __init__(self, A, opts: svds_opts):
+        self._A = A      # keep the struct (and its tensors, held by the caller) alive
+        self._opts = opts
+        self.m, self.n, self.k = A.m, A.n, opts.k
+        h = C.c_void_p()
+        if isinstance(A, svds_csr):
+            _check(lib.svds_plan_create_csr(C.byref(A), C.byref(opts), C.byref(h)), "svds_plan_create_csr")
+        else:
+            _check(lib.svds_plan_create_dense(C.byref(A), C.byref(opts), C.byref(h)), "svds_plan_create_dense")
+        self._h = h
+
+    def execute(self, out=None) -> Result:
+        dev = torch.device("cuda", torch.cuda.current_device())
+        U, S, V = out if out is not None else _outputs(self.m, self.n, self.k, dev)
+        info = svds_info()
+        rc = _check(lib.svds_plan_execute(self._h, _ptr(U), _ptr(S), _ptr(V), C.byref(info)),
+                    "svds_plan_execute")
+        return Result(U.T, S, V.T, info.as_dict(), rc)
+
+    def destroy(self):
+        if self._h:
+            lib.svds_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+svds_plan_create_csr = Plan
+svds_plan_create_dense = Plan
+
+
+def svds_csr_solve_batched(As, opts: svds_opts):
+    dev = torch.device("cuda", torch.cuda.current_device())
+    outs = [_outputs(A.m, A.n, opts.k, dev) for A in As]
+    arr = (svds_csr * len(As))(*As)
+    Up = (C.c_void_p * len(As))(*[o[0].data_ptr() for o in outs])
+    Sp = (C.c_void_p * len(As))(*[o[1].data_ptr() for o in outs])
+    Vp = (C.c_void_p * len(As))(*[o[2].data_ptr() for o in outs])
+    infos = (svds_info * len(As))()
+    rc = _check(lib.svds_csr_solve_batched(len(As), arr, C.byref(opts), Up, Sp, Vp, infos),
+                "svds_csr_solve_batched")
+    return [Result(o[0].T, o[1], o[2].T, infos[i].as_dict(), rc) for i, o in enumerate(outs)], rc
+
+
+def svds_residuals_csr(A: svds_csr, U: torch.Tensor, S: torch.Tensor, V: torch.Tensor, stream=None):
+    """(|A v_j - s_j u_j|, |A^T u_j - s_j v_j|) for column-major U (m x k), V (n x k)."""
+    k = S.numel()
+    Uc = U.T.contiguous()
+    Vc = V.T.contiguous()
+    r1 = torch.empty(k, dtype=torch.float64, device=S.device)
+    r2 = torch.empty(k, dtype=torch.float64, device=S.device)
+    _check(lib.svds_residuals_csr(C.byref(A), k, _ptr(Uc), _ptr(S), _ptr(Vc), _ptr(r1), _ptr(r2),
+                                  _stream(stream)), "svds_residuals_csr")
+    return r1, r2
+
+
+# --- single steps -------------------------------------------------------------
+
+def svds_op_spmv_csr(A: svds_csr, x, x_scale=None, coef=None, yprev=None, y=None, stream=None):
+    dt = SVDS_F64 if x.dtype == torch.float64 else SVDS_F32
+    if y is None:
+        y = torch.empty(A.m, dtype=x.dtype, device=x.device)
+    _check(lib.svds_op_spmv_csr(C.byref(A), _ptr(x), _ptr(x_scale), _ptr(coef), _ptr(yprev), _ptr(y), dt,
+                                _stream(stream)), "svds_op_spmv_csr")
+    return y
+
+
+def svds_op_dense_matvec(A: svds_dense, transpose: bool, x, x_scale=None, coef=None, yprev=None,
+                         y=None, stream=None):
+    dt = SVDS_F64 if x.dtype == torch.float64 else SVDS_F32
+    if y is None:
+        y = torch.empty(A.n if transpose else A.m, dtype=x.dtype, device=x.device)
+    _check(lib.svds_op_dense_matvec(C.byref(A), int(transpose), _ptr(x), _ptr(x_scale), _ptr(coef),
+                                    _ptr(yprev), _ptr(y), dt, _stream(stream)), "svds_op_dense_matvec")
+    return y
+
+
+def svds_op_csc_build(A: svds_csr, val_dtype=torch.float64, stream=None):
+    dev = torch.device("cuda", torch.cuda.current_device())
+    trp = torch.empty(A.n + 1, dtype=torch.int32, device=dev)
+    tci = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)
+    tv = torch.empty(max(A.nnz, 1), dtype=val_dtype, device=dev)
+    _check(lib.svds_op_csc_build(C.byref(A), _ptr(trp), _ptr(tci), _ptr(tv), _stream(stream)),
+           "svds_op_csc_build")
+    return trp, tci[:A.nnz], tv[:A.nnz]
+
+
+def svds_op_cgs2(Q: torch.Tensor, j: int, w: torch.Tensor, ldq: int | None = None, stream=None):
+    """Q: column-major basis given as a (cols, ldq) tensor (column c = Q[c])."""
+    dt = SVDS_F64 if w.dtype == torch.float64 else SVDS_F32
+    L = w.numel()
+    out = torch.empty_like(w)
+    nrm = C.c_double()
+    _check(lib.svds_op_cgs2(L, j, _ptr(Q) if j > 0 else None, ldq or (Q.shape[1] if j > 0 else L), _ptr(w),
+                            _ptr(out), C.byref(nrm), dt, _stream(stream)), "svds_op_cgs2")
+    return out, nrm.value
+
+
+def svds_op_small_svd(T: torch.Tensor, p: int, k: int, tol: float, stream=None):
+    """T: (p+1) x (p+1) row-major FP64 device tensor (overwritten by the
+    restarted matrix).  Returns Uk (k x p: row j = left vector j), Vext
+    ((k+1) x (p+1)), sig, res, rho, flags."""
+    dev = T.device
+    Uk = torch.empty((k, p), dtype=torch.float64, device=dev)
+    Vext = torch.empty((k + 1, p + 1), dtype=torch.float64, device=dev)
+    sig = torch.empty(k, dtype=torch.float64, device=dev)
+    res = torch.empty(k, dtype=torch.float64, device=dev)
+    rho = torch.empty(k, dtype=torch.float64, device=dev)
+    flags = (C.c_int32 * 3)()
+    _check(lib.svds_op_small_svd(p, k, tol, _ptr(T), _ptr(Uk), _ptr(Vext), _ptr(sig), _ptr(res), _ptr(rho),
+                                 flags, _stream(stream)), "svds_op_small_svd")
+    return Uk, Vext, sig, res, rho, list(flags)
+
+
+def svds_op_rotate(B: torch.Tensor, pc: int, Y: torch.Tensor, kc: int, stream=None):
+    """B: (pc, L) tensor (column-major L x pc), Y: (kc, pc) FP64 (column-major
+    pc x kc).  Returns out as (kc, L)."""
+    L = B.shape[1]
+    out = torch.empty((kc, L), dtype=torch.float64, device=B.device)
+    bt = SVDS_F64 if B.dtype == torch.float64 else SVDS_F32
+    _check(lib.svds_op_rotate(L, pc, kc, _ptr(B), L, bt, _ptr(Y), Y.shape[1], _ptr(out), L, _stream(stream)),
+           "svds_op_rotate")
+    return out
+
+
+def svds_op_philox_normal(L: int, seed: int, stream_id: int, stream=None):
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty(L, dtype=torch.float64, device=dev)
+    _check(lib.svds_op_philox_normal(L, seed, stream_id, _ptr(out), _stream(stream)), "svds_op_philox_normal")
+    return out
+
+
+def svds_op_copy_f64(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    _check(lib.svds_op_copy_f64(src.numel(), _ptr(src), _ptr(dst), _stream(stream)), "svds_op_copy_f64")
+    return dst
+
+
+# --- conveniences ---------------------------------------------------------------
+
+def csr_to_device(A, dtype=None, device="cuda"):
+    """Upload an ``inputs.CSR`` to the device; returns (struct, tensors)."""
+    val = torch.from_numpy(A.val)
+    if dtype is not None:
+        val = val.to(dtype)
+    t = (torch.from_numpy(A.row_ptr).to(device), torch.from_numpy(A.col_idx).to(device), val.to(device))
+    return make_csr(t[0], t[1], t[2], A.m, A.n), t

@@ -1,0 +1,219 @@
+"""End-to-end parity of the HIP solver (C ABI) against the FP64 CPU oracle on
+the same seeded inputs and start vector: singular values to a relative
+error, vectors up to sign (and as subspaces for multiple values), residuals,
+orthogonality, mat-vec counts, edge cases and determinism."""
+import numpy as np
+import pytest
+
+from paper_2405_18966_amd import inputs
+from oracle import svds_ref
+from oracle.svds_ref import as_operator
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_18966_amd import svds
+    return svds
+
+
+def _gpu_solve(S, A, k, p, tol, maxit, v0=None, seed=0, precision=0, flags=0):
+    import torch
+    Ad, keep = S.csr_to_device(A)
+    v0d = None if v0 is None else torch.from_numpy(v0).cuda()
+    r = S.svds_csr_solve(Ad, S.make_opts(k, p, tol, maxit, precision=precision, seed=seed, v0=v0d,
+                                         flags=flags))
+    torch.cuda.synchronize()
+    return r.U.cpu().numpy(), r.S.cpu().numpy(), r.V.cpu().numpy(), r.info, r.status
+
+
+def _compare(Ug, Sg, Vg, Ur, Sr, Vr, s_all, tol_sigma, vec_tol_scale):
+    np.testing.assert_allclose(Sg, Sr, rtol=tol_sigma)
+    k = len(Sr)
+    for j in range(k):
+        gap = min(abs(s_all[j] - s_all[i]) for i in range(len(s_all)) if i != j)
+        if gap < 1e-9 * s_all[0]:
+            continue
+        bound = max(vec_tol_scale * s_all[j] / gap, 1e-10)
+        for X, Y in ((Ug, Ur), (Vg, Vr)):
+            d = np.linalg.norm(X[:, j] - Y[:, j])  # both sign-normalized
+            assert d <= bound, (j, d, bound)
+
+
+def _invariants(A, Ug, Sg, Vg, tol):
+    Asp = as_operator(A)
+    k = len(Sg)
+    assert np.abs(Ug.T @ Ug - np.eye(k)).max() <= 1e-12
+    assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-12
+    r1, r2 = svds_ref.explicit_residuals(Asp, Ug, Sg, Vg)
+    assert r1.max() <= 1e-12 * Sg[0]
+    assert (r2 / np.maximum(Sg, 1e-300 + 2**-52 * Sg[0])).max() <= 2 * tol
+
+
+def _counts_ok(info, p, k):
+    R = info["cycles"] - 1
+    assert info["n_spmv"] == p + R * (p - k)
+    assert info["n_spmvT"] == p + R * (p - k)
+
+
+@pytest.mark.parametrize("case", ["w1", "tall", "wide", "square_small"])
+def test_parity_with_oracle(S, case):
+    if case == "w1":
+        A = inputs.config_matrix(1)
+        k, p, tol = 10, 30, 1e-10
+        v0 = inputs.start_vector(A.n, inputs.CONFIG_SEEDS[1] + 1)
+    elif case == "tall":
+        A = inputs.sparse_uniform(5000, 800, 40000, seed=3)
+        k, p, tol = 8, 24, 1e-10
+        v0 = inputs.start_vector(A.n, 4)
+    elif case == "wide":
+        A = inputs.sparse_uniform(700, 3000, 30000, seed=5)
+        k, p, tol = 5, 15, 1e-10
+        v0 = inputs.start_vector(A.n, 6)
+    else:
+        A = inputs.sparse_uniform(60, 60, 900, seed=7)
+        k, p, tol = 3, 9, 1e-12
+        v0 = inputs.start_vector(A.n, 8)
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), k, p, tol, 3000, v0=v0)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, tol, 3000, v0=v0)
+    assert st == 0 and info["converged"] == 1 and info_r.converged
+    s_all = np.linalg.svd(as_operator(A).toarray(), compute_uv=False)
+    _compare(Ug, Sg, Vg, Ur, Sr, Vr, s_all, 1e-10, 10 * tol)
+    _invariants(A, Ug, Sg, Vg, tol)
+    _counts_ok(info, p, k)
+    assert abs(info["cycles"] - info_r.cycles) <= 1
+    assert info["max_res_true"] <= 2 * tol and info["max_res_est"] < tol
+
+
+@pytest.mark.parametrize("law", ["decay1", "decay2", "decay3"])
+def test_prescribed_spectrum(S, law):
+    nb, bs = 400, 5
+    sig = getattr(inputs, law)(nb * bs)
+    A = inputs.prescribed_sparse(nb, bs, sig, seed=17)
+    k, p = 12, 36
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, 1e-10, 2000, v0=inputs.start_vector(A.n, 18))
+    assert st == 0
+    np.testing.assert_allclose(Sg, np.sort(sig)[::-1][:k], rtol=1e-10)
+    _invariants(A, Ug, Sg, Vg, 1e-10)
+
+
+def test_repeated_values_and_breakdowns(S):
+    d = np.repeat([5.0, 4.0, 3.0, 2.0, 1.0, 0.5], [4, 3, 3, 2, 3, 35])
+    A = inputs.diag_matrix(60, 50, d)
+    k, p = 8, 20
+    v0 = inputs.start_vector(50, 4)
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), k, p, 1e-10, 200, v0=v0)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, 1e-10, 200, v0=v0)
+    assert info["breakdowns"] > 0 and info_r.breakdowns > 0
+    np.testing.assert_allclose(Sg, np.sort(d)[::-1][:k], rtol=1e-12)
+    # multiple singular values: compare invariant subspaces
+    for val in (5.0, 4.0):
+        cols = np.nonzero(np.abs(Sg - val) < 1e-9)[0]
+        colsr = np.nonzero(np.abs(Sr - val) < 1e-9)[0]
+        qg, _ = np.linalg.qr(Vg[:, cols])
+        qr, _ = np.linalg.qr(Vr[:, colsr])
+        assert np.linalg.norm(qg - qr @ (qr.T @ qg), 2) < 1e-9
+    _invariants(A, Ug, Sg, Vg, 1e-10)
+
+
+def test_default_start_vector_matches_oracle_philox(S):
+    A = inputs.sparse_uniform(400, 300, 4000, seed=21)
+    k, p = 4, 14
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), k, p, 1e-10, 500, seed=2405)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, 1e-10, 500, v0=None, seed=2405)
+    np.testing.assert_allclose(Sg, Sr, rtol=1e-10)
+    assert abs(info["cycles"] - info_r.cycles) <= 1
+
+
+def test_not_converged_status(S):
+    A = inputs.config_matrix(1)
+    v0 = inputs.start_vector(A.n, inputs.CONFIG_SEEDS[1] + 1)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, 10, 30, 1e-10, 1, v0=v0)
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), 10, 30, 1e-10, 1, v0=v0)
+    assert st == 1 and info["converged"] == 0 and info["cycles"] == 1
+    assert info["nconv"] == info_r.nconv
+    # one cycle, same Krylov space: the Ritz values agree to rounding
+    np.testing.assert_allclose(Sg, Sr, rtol=1e-12)
+    assert info["n_spmv"] == 30 and info["n_spmvT"] == 30
+
+
+@pytest.mark.parametrize("m,n,k,p", [(40, 31, 1, 2), (40, 31, 29, 30), (30, 50, 10, 30), (31, 32, 2, 31)])
+def test_extreme_dimensions(S, m, n, k, p):
+    """p = k+1, p = m, p + 1 = n, k = 1: the boundaries of the validation."""
+    A = inputs.sparse_uniform(m, n, m * n // 3, seed=m * n)
+    v0 = inputs.start_vector(n, 1)
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), k, p, 1e-10, 3000, v0=v0)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, 1e-10, 3000, v0=v0)
+    assert st == 0 and info_r.converged
+    s_all = np.linalg.svd(as_operator(A).toarray(), compute_uv=False)
+    np.testing.assert_allclose(Sg, s_all[:k], rtol=1e-10)
+    _invariants(A, Ug, Sg, Vg, 1e-10)
+
+
+def test_empty_rows_and_columns(S):
+    A = inputs.sparse_uniform(500, 400, 800, seed=31)  # many empty rows and columns
+    assert (np.diff(A.row_ptr) == 0).sum() > 50
+    k, p = 5, 16
+    v0 = inputs.start_vector(400, 32)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, 1e-10, 3000, v0=v0)
+    s_all = np.linalg.svd(as_operator(A).toarray(), compute_uv=False)
+    np.testing.assert_allclose(Sg, s_all[:k], rtol=1e-10)
+    _invariants(A, Ug, Sg, Vg, 1e-10)
+
+
+def test_zero_matrix(S):
+    A = inputs.CSR(30, 20, np.zeros(31, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, 2, 5, 1e-10, 3, v0=inputs.start_vector(20, 1))
+    assert np.all(Sg == 0) and st == 0 and info["breakdowns"] >= 1
+    assert np.all(np.isfinite(Ug)) and np.all(np.isfinite(Vg))
+
+
+def test_bitwise_deterministic(S):
+    A = inputs.sparse_zipf(20000, 8000, 10, 1.1, seed=41)
+    v0 = inputs.start_vector(A.n, 42)
+    a = _gpu_solve(S, A, 6, 18, 1e-10, 300, v0=v0)
+    b = _gpu_solve(S, A, 6, 18, 1e-10, 300, v0=v0)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+
+
+def test_plan_reuse(S):
+    import torch
+    A = inputs.config_matrix(1)
+    v0 = torch.from_numpy(inputs.start_vector(A.n, inputs.CONFIG_SEEDS[1] + 1)).cuda()
+    Ad, keep = S.csr_to_device(A)
+    plan = S.Plan(Ad, S.make_opts(10, 30, 1e-10, 3000, v0=v0))
+    r1 = plan.execute()
+    r2 = plan.execute()
+    torch.cuda.synchronize()
+    assert torch.equal(r1.S, r2.S) and torch.equal(r1.U, r2.U) and torch.equal(r1.V, r2.V)
+    plan.destroy()
+
+
+def test_fp32_stored_values_fp64_path(S):
+    """FP32-stored CSR values widen exactly: the matrix of record is the
+    widened one, and the FP64 path matches the oracle on it."""
+    A = inputs.round_values_f32(inputs.sparse_uniform(1500, 900, 15000, seed=51))
+    A64 = inputs.CSR(A.m, A.n, A.row_ptr, A.col_idx, A.val.astype(np.float64))
+    v0 = inputs.start_vector(A.n, 52)
+    Ur, Sr, Vr, _ = svds_ref.svds(as_operator(A64), 6, 18, 1e-10, 2000, v0=v0)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, 6, 18, 1e-10, 2000, v0=v0)
+    np.testing.assert_allclose(Sg, Sr, rtol=1e-10)
+
+
+def test_dense_fp64_matches_oracle(S):
+    import torch
+    sig = inputs.decay1(300)
+    A = inputs.prescribed_dense(500, 300, sig, seed=61)
+    v0 = inputs.start_vector(300, 62)
+    k, p = 20, 60
+    Ur, Sr, Vr, info_r = svds_ref.svds(A, k, p, 1e-10, 500, v0=v0)
+    Ad = S.make_dense(torch.from_numpy(A.ravel(order="F")).cuda(), 500, 300)
+    r = S.svds_dense_solve(Ad, S.make_opts(k, p, 1e-10, 500, v0=torch.from_numpy(v0).cuda()))
+    np.testing.assert_allclose(r.S.cpu().numpy(), sig[:k], rtol=1e-10)
+    np.testing.assert_allclose(r.S.cpu().numpy(), Sr, rtol=1e-10)
+    assert r.status == 0
