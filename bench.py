@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark: k-triplet truncated-SVD solves per second on one MI355X.
+
+Workload (one "step" = one complete solve through the C ABI: device transpose,
+Lanczos cycles with CGS2, small SVDs, restarts, outputs, residuals):
+  sparse CSR A 1,000,000 x 500,000, 10 Zipf(1.1) column draws per row
+  (~9.15 nnz/row, power-law column degrees), U(0,1) values, FP64;
+  k = 50, p = 150, tol = 1e-8.  Inputs are seeded and synthetic and are
+  resident in HBM before the timed region.
+
+Prints ONE JSON line.  Besides solves/s it reports the roofline of the
+dominant kernel (device time from HIP events recorded by the library on the
+stream the kernels run on), the headline SpMV+CGS2 GB/s, parity of the
+singular values against stored oracle values, and the CPU oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "k-triplet solves/s at rel.err≤1e-8; SpMV+CGS2 HBM GB/s; mixed vs FP64 x"
+HBM_PEAK_GBS = 8000.0
+GOLDEN_W2 = os.path.join(ROOT, "tests", "golden", "workload2_sigma.txt")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_workload2.json")
+WORKLOAD = dict(workload="zipf-sparse-svds", m=1_000_000, n=500_000, draws_per_row=10, zipf_a=1.1,
+                values="U(0,1)", k=50, p=150, tol=1e-8, storage="fp64 CSR")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def load_golden():
+    if not os.path.exists(GOLDEN_W2):
+        return None
+    import numpy as np
+    vals = [float(x) for x in open(GOLDEN_W2) if x.strip() and not x.startswith("#")]
+    return np.array(vals)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels_cgs.hpp", "kernels_spmv.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2405_18966_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(A, v0, k, p, schedule_steps):
+    """Times the CPU oracle on a bounded sample of the workload and scales it
+    to one solve.  Sample: the oracle's Lanczos bidiagonalization (Alg. 1 with
+    CGS2) on the full matrix for P1 and P2 steps; the per-step cost a + b*j
+    (j = basis width) is fitted from the two runs and summed over the step
+    schedule of a full solve (widths of every executed step)."""
+    import numpy as np
+    from oracle import svds_ref
+
+    Asp = svds_ref.as_operator(A)
+    P1, P2 = 12, 28
+    t = {}
+    for P in (P1, P2):
+        t0 = time.perf_counter()
+        svds_ref.lbp(Asp, P, v0)
+        t[P] = time.perf_counter() - t0
+        log(f"cpu oracle: lbp {P} steps {t[P]:.2f} s")
+    # T(P) = a P + b P (P + 1) / 2
+    M = np.array([[P1, P1 * (P1 + 1) / 2], [P2, P2 * (P2 + 1) / 2]])
+    a, b = np.linalg.solve(M, np.array([t[P1], t[P2]]))
+    est = float(sum(a + b * j for j in schedule_steps))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle Lanczos bidiagonalization with CGS2 on the full workload for "
+                       f"{P1} and {P2} steps ({t[P1] + t[P2]:.1f} s of CPU work), per-step cost "
+                       f"a+b*j fitted (a={a:.3g} s, b={b:.3g} s) and summed over the "
+                       f"{len(schedule_steps)} steps of one solve (est. {est:.1f} s); "
+                       f"sparse products single-threaded (scipy), dense BLAS on {threads} threads")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of this solver is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2405_18966_amd import inputs
+    from paper_2405_18966_amd import svds as S
+
+    rank = int(os.environ.get("RANK", "0"))
+    torch.cuda.set_device(0)
+    log("generating workload ...")
+    A = inputs.config_matrix(2)
+    v0 = inputs.start_vector(A.n, inputs.CONFIG_SEEDS[2] + 1)
+    k, p, tol = WORKLOAD["k"], WORKLOAD["p"], WORKLOAD["tol"]
+    Ad, keep = S.csr_to_device(A)
+    v0d = torch.from_numpy(v0).cuda()
+    stream = torch.cuda.current_stream()
+    maxit = 2000
+    log(f"nnz = {A.nnz}")
+
+    def solve(flags=0):
+        return S.svds_csr_solve(Ad, S.make_opts(k, p, tol, maxit, v0=v0d, flags=flags, stream=stream))
+
+    if args.profile_run:
+        r = solve()
+        torch.cuda.synchronize()
+        src = torch.empty(64 << 20, dtype=torch.float64, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        S.svds_op_copy_f64(src, dst)
+        torch.cuda.synchronize()
+        log(f"profile run done: cycles {r.info['cycles']} status {r.status}")
+        return
+
+    for i in range(args.warmup):
+        r = solve()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {r.info['ms_total']:.1f} ms, cycles {r.info['cycles']}, status {r.status}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        r = solve(S.SVDS_FLAG_TIMING)
+        results.append(r)
+        log(f"step {i}: {r.info['ms_total']:.1f} ms, cycles {r.info['cycles']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = args.steps / elapsed
+    last = results[-1]
+    info = last.info
+
+    # parity of the singular values against stored oracle values
+    golden = load_golden()
+    s = last.S.cpu().numpy()
+    parity = {"status": last.status, "converged": info["converged"], "cycles": info["cycles"],
+              "max_res_true": info["max_res_true"], "max_res_av": info["max_res_av"]}
+    if golden is not None and len(golden) >= k:
+        parity["sigma_rel_err_vs_oracle"] = float(np.max(np.abs(s - golden[:k]) / golden[:k]))
+    valid = info["converged"] == 1 and info["max_res_true"] <= 2 * tol
+    if "sigma_rel_err_vs_oracle" in parity:
+        valid = valid and parity["sigma_rel_err_vs_oracle"] <= 1e-8
+    parity["valid"] = bool(valid)
+
+    # roofline of the dominant kernel (summed over the timed steps)
+    kc_ms = {c: sum(r.info["kc_ms"][c] for r in results) for c in S.KERNEL_CLASSES}
+    kc_b = {c: sum(r.info["kc_bytes"][c] for r in results) for c in S.KERNEL_CLASSES}
+    kc_n = {c: sum(r.info["kc_launches"][c] for r in results) for c in S.KERNEL_CLASSES}
+    dom = max(kc_ms, key=lambda c: kc_ms[c])
+    achieved = kc_b[dom] / (kc_ms[dom] * 1e-3) / 1e9 if kc_ms[dom] > 0 else 0.0
+    traffic = None
+    if os.path.exists(TRAFFIC):
+        tr = json.load(open(TRAFFIC))
+        if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("kernels", {}):
+            traffic = tr["kernels"][dom]
+    hot = ["spmv", "spmvT", "cgs_proj", "cgs_updproj", "cgs_updnorm"]
+    hot_gbs = sum(kc_b[c] for c in hot) / (sum(kc_ms[c] for c in hot) * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "avg_launch_us": round(kc_ms[dom] * 1e3 / max(kc_n[dom], 1), 2),
+                "alg_bytes_per_launch": round(kc_b[dom] / max(kc_n[dom], 1)),
+                "spmv_cgs2_gbs": round(hot_gbs, 1),
+                "per_class": {c: {"ms": round(kc_ms[c] / args.steps, 3),
+                                  "gbs": round(kc_b[c] / (kc_ms[c] * 1e-3) / 1e9, 1) if kc_ms[c] else None,
+                                  "launches": kc_n[c] // args.steps} for c in S.KERNEL_CLASSES}}
+
+    cpu = None
+    if not args.no_cpu and rank == 0:
+        R = info["cycles"] - 1
+        sched = list(range(1, p + 1)) + [j for _ in range(R) for j in range(k + 1, p + 1)]
+        cpu = cpu_baseline(A, v0, k, p, sched)
+
+    out = {"metric": METRIC, "value": round(value, 5), "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": dict(WORKLOAD, parallelism="single GPU"),
+           "roofline": roofline, "cpu_baseline": cpu, "parity": parity}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
