@@ -173,41 +173,47 @@ extern "C" int svds_op_cgs2(int64_t L, int32_t j, const void *Q, int64_t ldq, co
   if (dtype != SVDS_F64 && dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t tb = dtype == SVDS_F64 ? 8 : 4;
-  Scratch s;
-  // partials (CGS_MAXJ * GMAX), h1, h2 (CGS_MAXJ), w1 (L), npart (GMAX), xs, t, sig, cnt
-  const size_t bytes = tb * (static_cast<size_t>(CGS_MAXJ) * GMAX + 2 * CGS_MAXJ + L) + 8 * (GMAX + 8) + 64;
-  HIP_TRY(hipMalloc(&s.p, bytes));
-  HIP_TRY(hipMemset(s.p, 0, bytes));
-  char *b = static_cast<char *>(s.p);
-  char *parts = b;
-  char *h1 = parts + tb * CGS_MAXJ * GMAX;
-  char *h2 = h1 + tb * CGS_MAXJ;
-  char *w1 = h2 + tb * CGS_MAXJ;
-  double *npart = reinterpret_cast<double *>(w1 + ((tb * L + 7) & ~size_t(7)));
-  double *dx = npart + GMAX;  // xs, t_entry, sigma_est
-  unsigned *cnt = reinterpret_cast<unsigned *>(dx + 4);
-  int *bd = reinterpret_cast<int *>(cnt + 4);
-  auto grid = [](int64_t Lx) {
-    return static_cast<unsigned>(std::min<int64_t>(GMAX, std::max<int64_t>(1, ceil_div(Lx, 2048))));
+  // scratch: partials, group sums, h1, h2, w1, norm partials, scalars, counters
+  const size_t n_parts = static_cast<size_t>(CGS_MAXJ) * GMAX, n_p2 = static_cast<size_t>(CGS_MAXJ) * CGS_CNT_STRIDE;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
   };
+  const size_t o_parts = take(tb * n_parts), o_p2 = take(tb * n_p2), o_h1 = take(tb * CGS_MAXJ),
+               o_h2 = take(tb * CGS_MAXJ), o_w1 = take(tb * L), o_np = take(8 * 8192), o_dx = take(8 * 8),
+               o_cnt = take(4 * (CGS_CNT_WORDS + CGS_CNT_STRIDE + 4)), o_bd = take(16);
+  Scratch s;
+  HIP_TRY(hipMalloc(&s.p, off));
+  HIP_TRY(hipMemsetAsync(s.p, 0, off, st));
+  char *b = static_cast<char *>(s.p);
+  void *parts = b + o_parts, *p2 = b + o_p2, *h1 = b + o_h1, *h2 = b + o_h2, *w1 = b + o_w1;
+  double *npart = reinterpret_cast<double *>(b + o_np);
+  double *dx = reinterpret_cast<double *>(b + o_dx);  // xs, t_entry, sigma_est
+  unsigned *cnt = reinterpret_cast<unsigned *>(b + o_cnt);
+  int *bd = reinterpret_cast<int *>(b + o_bd);
   const int nw = std::max(1, std::min(16, static_cast<int>(ceil_div(std::max(j, 1), CGS_CPW))));
   FinishArgs fa{dx + 1, dx, dx + 2, bd, 0};
-#define CGS_GO(T)                                                                                   \
-  do {                                                                                              \
-    const T *src = static_cast<const T *>(w);                                                       \
-    if (j > 0) {                                                                                    \
-      hipLaunchKernelGGL((cgs_proj_kernel<T>), dim3(grid(L)), dim3(CGS_THREADS), 0, st,             \
-                         static_cast<const T *>(Q), ldq, L, j, src, reinterpret_cast<T *>(parts),   \
-                         reinterpret_cast<T *>(h1), cnt);                                           \
-      hipLaunchKernelGGL((cgs_upd_proj_kernel<T>), dim3(grid(L)), dim3(nw * WAVE), 0, st,           \
-                         static_cast<const T *>(Q), ldq, L, j, src, reinterpret_cast<T *>(h1),      \
-                         reinterpret_cast<T *>(w1), reinterpret_cast<T *>(parts),                   \
-                         reinterpret_cast<T *>(h2), cnt + 1);                                       \
-      src = reinterpret_cast<const T *>(w1);                                                        \
-    }                                                                                               \
-    hipLaunchKernelGGL((cgs_upd_norm_kernel<T>), dim3(grid(L)), dim3(CGS_THREADS), 0, st,           \
-                       static_cast<const T *>(Q), ldq, L, j, src, reinterpret_cast<T *>(h2),        \
-                       static_cast<T *>(out), npart, cnt + 2, static_cast<int>(MODE_NORM), fa);     \
+  int nslab = 1, ngc = 1;
+  if (j > 0) cgs_proj_shape(L, j, nslab, ngc);
+#define CGS_GO(T)                                                                                    \
+  do {                                                                                               \
+    const T *src = static_cast<const T *>(w);                                                        \
+    if (j > 0) {                                                                                     \
+      hipLaunchKernelGGL((cgs_proj_kernel<T>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, st,           \
+                         static_cast<const T *>(Q), ldq, L, j, src, static_cast<T *>(parts),         \
+                         static_cast<T *>(p2), static_cast<T *>(h1), cnt);                           \
+      hipLaunchKernelGGL((cgs_upd_proj_kernel<T>), dim3(cgs_updproj_blocks(L)), dim3(nw * WAVE), 0,  \
+                         st, static_cast<const T *>(Q), ldq, L, j, src, static_cast<T *>(h1),        \
+                         static_cast<T *>(w1), static_cast<T *>(parts), static_cast<T *>(p2),        \
+                         static_cast<T *>(h2), cnt + CGS_CNT_WORDS);                                 \
+      src = static_cast<const T *>(w1);                                                              \
+    }                                                                                                \
+    hipLaunchKernelGGL((cgs_upd_norm_kernel<T>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,  \
+                       st, static_cast<const T *>(Q), ldq, L, j, src, static_cast<T *>(h2),          \
+                       static_cast<T *>(out), npart, cnt + CGS_CNT_WORDS + CGS_CNT_STRIDE,           \
+                       static_cast<int>(MODE_NORM), fa);                                             \
   } while (0)
   if (dtype == SVDS_F64) CGS_GO(double);
   else CGS_GO(float);

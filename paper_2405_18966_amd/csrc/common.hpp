@@ -40,14 +40,19 @@ template <> __device__ __forceinline__ double widen<double, uint16_t>(uint16_t b
 }
 
 // ---------------------------------------------------------------------------
-// Reductions.  xor-butterflies are commutative at every level, so every lane
-// ends with the bitwise-same sum; block sums combine waves in index order.
-// All reductions in this library are deterministic (no float atomics).
+// Reductions.  Block sums combine waves in index order; all reductions in
+// this library are deterministic (no float atomics).
+//
+// The xor butterfly alone does NOT leave every lane with the same bits: the
+// compiler may fuse the caller's product into the first butterfly add
+// (fma(x, x, partner's rounded x*x)), so partners round differently.  Code
+// that branches on a reduced value (the Jacobi rotation test) needs a
+// wave-uniform result, so the sum of lane 0 is broadcast to all lanes.
 // ---------------------------------------------------------------------------
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
+  return __shfl(v, 0, WAVE);
 }
 
 template <typename T> __device__ __forceinline__ T wave_max(T v) {

@@ -10,150 +10,238 @@
 //   cgs_upd_norm  : w2 = w1 - Q h2, |w2|; the last block turns the norm into
 //                   T(i,i) / T(i,i+1), the reciprocal scale of the vector,
 //                   and handles breakdown.
-// Reductions across blocks: each block writes per-column partial sums, the
-// last block to finish (arrival counter) adds them in block order.  No float
-// atomics anywhere, so every run gives bitwise the same result.
+// All three kernels are HBM-bound; each keeps many independent 512-byte
+// column segments in flight per wave.
+//
+// Cross-block reductions are deterministic and two-level: blocks write
+// per-column partial sums, the last block of every group of RED_GROUP blocks
+// (arrival counter) adds its group's partials in block order, and the last
+// group reducer adds the group sums in group order.  No float atomics.
 #pragma once
+#include <algorithm>
 #include "common.hpp"
 
 namespace svds {
 
 constexpr int CGS_THREADS = 256;
-constexpr int CGS_CC = 8;       // columns per chunk in cgs_proj
+constexpr int CGS_PCG = 32;     // columns per block column-group in cgs_proj
 constexpr int CGS_CPW = 16;     // columns per wave in cgs_upd_proj
 constexpr int CGS_MAXJ = 1024;  // largest basis width supported
+constexpr int RED_GROUP = 16;   // blocks per first-level reduction group
+constexpr int CGS_MAX_BLOCKS = 2048;
+// counters: per column group (<= CGS_MAXJ / CGS_PCG) one row of
+// (CGS_MAX_BLOCKS / RED_GROUP + 1) counters
+constexpr int CGS_CNT_STRIDE = CGS_MAX_BLOCKS / RED_GROUP + 1;
+constexpr int CGS_CNT_WORDS = (CGS_MAXJ / CGS_PCG) * CGS_CNT_STRIDE;
 constexpr double BREAKDOWN_REL = 1e-14;
 
-// Row slab [r0, r1) of block g out of G for vectors of length L, 64-aligned.
-__device__ __forceinline__ void block_slab(int64_t L, int64_t &r0, int64_t &r1) {
-  const int64_t tiles = ceil_div(L, WAVE);
-  const int64_t per = ceil_div(tiles, gridDim.x);
-  r0 = static_cast<int64_t>(blockIdx.x) * per * WAVE;
-  r1 = r0 + per * WAVE;
-  if (r1 > L) r1 = L;
-  if (r0 > L) r0 = L;
-}
-
-// Last block: out[c] = sum_g partials[c*G + g], c < j.  One wave per column,
-// lanes stride over g, fixed-order wave reduction.
+// out[c] = sum_{i < nv} src[c * ld + i], c < nc, in index order, using all
+// threads of the block: tpc threads per column take interleaved indices and
+// combine with a fixed xor pattern (deterministic for a given launch shape).
 template <typename T>
-__device__ __forceinline__ void reduce_partials(const T *__restrict__ partials, int j,
-                                                T *__restrict__ out) {
-  const int G = gridDim.x;
-  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-  const int nw = blockDim.x / WAVE;
-  for (int c = wv; c < j; c += nw) {
+__device__ __forceinline__ void reduce_columns(const T *__restrict__ src, int64_t ld, int nv, int nc,
+                                               T *__restrict__ out, int64_t out_stride) {
+  const int nt = blockDim.x;
+  int tpc = 1;
+  while (tpc * 2 * nc <= nt && tpc < 32) tpc *= 2;
+  const int lanes = nc * tpc;
+  for (int base = 0; base < lanes; base += nt) {
+    const int id = base + threadIdx.x;
+    const int c = id / tpc, sub = id % tpc;
     T s = 0;
-    for (int g = lane; g < G; g += WAVE) s += partials[static_cast<int64_t>(c) * G + g];
-    s = wave_sum(s);
-    if (lane == 0) out[c] = s;
+    if (c < nc) {
+      const T *p = src + static_cast<int64_t>(c) * ld;
+      for (int i = sub; i < nv; i += tpc) s += p[i];
+    }
+    // combine the tpc partials of a column (consecutive lanes of one wave)
+    for (int o = 1; o < tpc; o <<= 1) s += __shfl_xor(s, o, WAVE);
+    if (c < nc && sub == 0) out[static_cast<int64_t>(c) * out_stride] = s;
   }
 }
 
+// Two-level completion of a per-column partial-sum array.
+//   part  : [nc][nblk] partials of this block's column range (ld nblk)
+//   part2 : [nc][ngrp] group sums (ld ngrp), ngrp = ceil(nblk / RED_GROUP)
+//   cnt   : ngrp + 1 arrival counters (self-resetting)
+// The block with index `blk` (0..nblk-1) calls this after writing its
+// partials; the final sums land in out[c].
+template <typename T>
+__device__ __forceinline__ void finish_columns(T *__restrict__ part, T *__restrict__ part2, int nblk,
+                                               int blk, int nc, T *__restrict__ out,
+                                               unsigned int *__restrict__ cnt, int *sh_flag) {
+  const int ngrp = (nblk + RED_GROUP - 1) / RED_GROUP;
+  const int g = blk / RED_GROUP;
+  const int gsize = min(RED_GROUP, nblk - g * RED_GROUP);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int t = atomicAdd(&cnt[g], 1u);
+    *sh_flag = (t == static_cast<unsigned int>(gsize - 1));
+  }
+  __syncthreads();
+  if (!*sh_flag) return;
+  __threadfence();
+  if (threadIdx.x == 0) atomicExch(&cnt[g], 0u);
+  if (ngrp == 1) {
+    reduce_columns(part + g * RED_GROUP, nblk, gsize, nc, out, 1);
+    return;
+  }
+  reduce_columns(part + g * RED_GROUP, nblk, gsize, nc, part2 + g, ngrp);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int t = atomicAdd(&cnt[ngrp], 1u);
+    *sh_flag = (t == static_cast<unsigned int>(ngrp - 1));
+  }
+  __syncthreads();
+  if (!*sh_flag) return;
+  __threadfence();
+  if (threadIdx.x == 0) atomicExch(&cnt[ngrp], 0u);
+  reduce_columns(part2, ngrp, ngrp, nc, out, 1);
+}
+
 // ---------------------------------------------------------------------------
-// Pass 1: h = Q^T w.
+// Pass 1: h = Q^T w.  Grid (row slabs, column groups of 32).  Each wave walks
+// 64-row tiles of its block's slab keeping 32 column accumulators per lane.
+// part: [j][nslab], part2: [j][ceil(nslab/16)].
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(
     const T *__restrict__ Q, int64_t ldq, int64_t L, int j, const T *__restrict__ w,
-    T *__restrict__ partials, T *__restrict__ h, unsigned int *__restrict__ counter) {
+    T *__restrict__ part, T *__restrict__ part2, T *__restrict__ h, unsigned int *__restrict__ cnt) {
   constexpr int NW = CGS_THREADS / WAVE;
-  __shared__ T red[NW][CGS_CC];
+  __shared__ T red[NW][CGS_PCG + 1];
   __shared__ int flag;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-  int64_t r0, r1;
-  block_slab(L, r0, r1);
-  const int G = gridDim.x;
-  for (int c0 = 0; c0 < j; c0 += CGS_CC) {
-    const int nc = min(CGS_CC, j - c0);
-    T acc[CGS_CC];
+  const int nslab = gridDim.x, slab = blockIdx.x;
+  const int c0 = blockIdx.y * CGS_PCG;
+  const int nc = min(CGS_PCG, j - c0);
+  const int64_t tiles = ceil_div(L, WAVE);
+  const int64_t per = ceil_div(tiles, nslab);
+  const int64_t t0 = slab * per, t1 = min(tiles, t0 + per);
+  const T *Qc = Q + c0 * ldq;
+  T acc[CGS_PCG];
 #pragma unroll
-    for (int c = 0; c < CGS_CC; ++c) acc[c] = 0;
-    for (int64_t r = r0 + tid; r < r1; r += CGS_THREADS) {
-      const T wr = w[r];
+  for (int c = 0; c < CGS_PCG; ++c) acc[c] = 0;
+  if (nc == CGS_PCG) {
+    for (int64_t t = t0 + wv; t < t1; t += NW) {
+      const int64_t r = t * WAVE + lane;
+      if (r < L) {
+        const T wr = w[r];
 #pragma unroll
-      for (int c = 0; c < CGS_CC; ++c)
-        if (c < nc) acc[c] += Q[(c0 + c) * ldq + r] * wr;
+        for (int c = 0; c < CGS_PCG; ++c) acc[c] += Qc[c * ldq + r] * wr;
+      }
     }
+  } else {
+    for (int64_t t = t0 + wv; t < t1; t += NW) {
+      const int64_t r = t * WAVE + lane;
+      if (r < L) {
+        const T wr = w[r];
 #pragma unroll
-    for (int c = 0; c < CGS_CC; ++c) {
-      const T s = wave_sum(acc[c]);
-      if (lane == 0) red[wv][c] = s;
+        for (int c = 0; c < CGS_PCG; ++c)
+          if (c < nc) acc[c] += Qc[c * ldq + r] * wr;
+      }
     }
-    __syncthreads();
-    if (tid < nc) {
-      T s = 0;
-      for (int v = 0; v < NW; ++v) s += red[v][tid];
-      partials[static_cast<int64_t>(c0 + tid) * G + blockIdx.x] = s;
-    }
-    __syncthreads();
   }
-  if (elect_last_block(counter, &flag)) reduce_partials(partials, j, h);
+#pragma unroll
+  for (int c = 0; c < CGS_PCG; ++c) {
+    const T s = wave_sum(acc[c]);
+    if (lane == 0) red[wv][c] = s;
+  }
+  __syncthreads();
+  if (tid < nc) {
+    T s = 0;
+    for (int v = 0; v < NW; ++v) s += red[v][tid];
+    part[static_cast<int64_t>(c0 + tid) * nslab + slab] = s;
+  }
+  const int ngrp = (nslab + RED_GROUP - 1) / RED_GROUP;
+  finish_columns(part + static_cast<int64_t>(c0) * nslab, part2 + static_cast<int64_t>(c0) * ngrp, nslab,
+                 slab, nc, h + c0, cnt + blockIdx.y * CGS_CNT_STRIDE, &flag);
 }
 
 // ---------------------------------------------------------------------------
 // Pass 2 fused with the update of pass 1: w1 = w - Q h1 (written out) and
-// h2 = Q^T w1.  Block = NW waves; a block walks 64-row tiles, wave v holds
-// columns [16v, 16v+16) of the tile in registers, so Q is read once for both
-// the update and the projection.  NW = ceil(j/16) <= 16 (j <= 256) -- wider
-// bases loop over column groups of 256.
+// h2 = Q^T w1.  Block = NW = ceil(j/16) waves (<= 16, so j <= 256); a block
+// walks 64-row tiles; wave v holds columns [16v, 16v+16) of the tile in
+// registers, so Q is read once for both the update and the projection.  The
+// next tile is loaded before the current one is consumed, and the
+// cross-wave sums go through a double-buffered LDS array (one barrier per
+// tile).  Wider bases (j > 256) take a generic two-sweep path.
+// part: [j][nblk], part2: [j][ceil(nblk/16)].
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(
     const T *__restrict__ Q, int64_t ldq, int64_t L, int j, const T *__restrict__ w,
-    const T *__restrict__ h1, T *__restrict__ w1out, T *__restrict__ partials,
-    T *__restrict__ h2, unsigned int *__restrict__ counter) {
+    const T *__restrict__ h1, T *__restrict__ w1out, T *__restrict__ part, T *__restrict__ part2,
+    T *__restrict__ h2, unsigned int *__restrict__ cnt) {
   __shared__ T sh_h[CGS_MAXJ];
-  __shared__ T part[16][WAVE];
+  __shared__ T xch[2][16][WAVE];
   __shared__ int flag;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int NW = blockDim.x / WAVE;
-  const int G = gridDim.x;
+  const int nblk = gridDim.x, blk = blockIdx.x;
   for (int c = tid; c < j; c += blockDim.x) sh_h[c] = h1[c];
   __syncthreads();
   const int64_t tiles = ceil_div(L, WAVE);
-  const int64_t per = ceil_div(tiles, G);
-  const int64_t t0 = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t per = ceil_div(tiles, nblk);
+  const int64_t t0 = static_cast<int64_t>(blk) * per;
   const int64_t t1 = min(tiles, t0 + per);
-  // Basis wider than the block's register tile: fall back to the generic
-  // path below (two sweeps of the block's rows, still one launch).
-  const bool tiled = j <= NW * CGS_CPW;
-  if (tiled) {
+  if (j <= NW * CGS_CPW) {
     const int c0 = wv * CGS_CPW;
     const int nc = max(0, min(CGS_CPW, j - c0));
-    T acc[CGS_CPW];
+    const T *Qc = Q + c0 * ldq;
+    T hc[CGS_CPW];
 #pragma unroll
-    for (int c = 0; c < CGS_CPW; ++c) acc[c] = 0;
+    for (int c = 0; c < CGS_CPW; ++c) hc[c] = c < nc ? sh_h[c0 + c] : T(0);
+    T acc[CGS_CPW], q[CGS_CPW], qn[CGS_CPW];
+#pragma unroll
+    for (int c = 0; c < CGS_CPW; ++c) acc[c] = 0, qn[c] = 0;
+    T wn = 0;
+    // prefetch the first tile
+    if (t0 < t1) {
+      const int64_t r = t0 * WAVE + lane;
+      if (r < L) {
+#pragma unroll
+        for (int c = 0; c < CGS_CPW; ++c)
+          if (c < nc) qn[c] = Qc[c * ldq + r];
+        wn = w[r];
+      }
+    }
+    int buf = 0;
     for (int64_t t = t0; t < t1; ++t) {
       const int64_t r = t * WAVE + lane;
       const bool valid = r < L;
-      T q[CGS_CPW];
+      T wr = wn;
+#pragma unroll
+      for (int c = 0; c < CGS_CPW; ++c) q[c] = qn[c];
+      if (t + 1 < t1) {
+        const int64_t rn = r + WAVE;
+        if (rn < L) {
+#pragma unroll
+          for (int c = 0; c < CGS_CPW; ++c)
+            if (c < nc) qn[c] = Qc[c * ldq + rn];
+          wn = w[rn];
+        }
+      }
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < CGS_CPW; ++c) {
-        q[c] = (valid && c < nc) ? Q[(c0 + c) * ldq + r] : T(0);
-        s += q[c] * sh_h[c0 + c < j ? c0 + c : 0];
-      }
-      part[wv][lane] = s;
+      for (int c = 0; c < CGS_CPW; ++c) s += q[c] * hc[c];
+      xch[buf][wv][lane] = s;
       __syncthreads();
-      T w1 = 0;
-      if (valid) {
-        T u = 0;
-        for (int v = 0; v < NW; ++v) u += part[v][lane];
-        w1 = w[r] - u;
-        if (wv == 0) w1out[r] = w1;
-      }
+      T u = 0;
+      for (int v = 0; v < NW; ++v) u += xch[buf][v][lane];
+      const T w1 = valid ? wr - u : T(0);
+      if (wv == 0 && valid) w1out[r] = w1;
 #pragma unroll
       for (int c = 0; c < CGS_CPW; ++c) acc[c] += q[c] * w1;
-      __syncthreads();
+      buf ^= 1;
     }
 #pragma unroll
     for (int c = 0; c < CGS_CPW; ++c) {
       const T s = wave_sum(acc[c]);
-      if (lane == 0 && c < nc) partials[static_cast<int64_t>(c0 + c) * G + blockIdx.x] = s;
+      if (lane == 0 && c < nc) part[static_cast<int64_t>(c0 + c) * nblk + blk] = s;
     }
-  }
-  if (!tiled) {
+  } else {
     // generic path: thread-per-row update, then column-chunked projection
     const int64_t r0 = t0 * WAVE, r1 = min(L, t1 * WAVE);
     for (int64_t r = r0 + tid; r < r1; r += blockDim.x) {
@@ -161,35 +249,35 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(
       for (int c = 0; c < j; ++c) u += Q[c * ldq + r] * sh_h[c];
       w1out[r] = w[r] - u;
     }
-    __syncthreads();
     __threadfence_block();
-    T *red = &part[0][0];
-    for (int c0 = 0; c0 < j; c0 += CGS_CC) {
-      const int nc = min(CGS_CC, j - c0);
-      T acc[CGS_CC];
+    __syncthreads();
+    T *red = &xch[0][0][0];
+    for (int c0 = 0; c0 < j; c0 += 8) {
+      const int nc = min(8, j - c0);
+      T acc[8];
 #pragma unroll
-      for (int c = 0; c < CGS_CC; ++c) acc[c] = 0;
+      for (int c = 0; c < 8; ++c) acc[c] = 0;
       for (int64_t r = r0 + tid; r < r1; r += blockDim.x) {
         const T x = w1out[r];
 #pragma unroll
-        for (int c = 0; c < CGS_CC; ++c)
+        for (int c = 0; c < 8; ++c)
           if (c < nc) acc[c] += Q[(c0 + c) * ldq + r] * x;
       }
 #pragma unroll
-      for (int c = 0; c < CGS_CC; ++c) {
+      for (int c = 0; c < 8; ++c) {
         const T s = wave_sum(acc[c]);
-        if (lane == 0) red[wv * CGS_CC + c] = s;
+        if (lane == 0) red[wv * 8 + c] = s;
       }
       __syncthreads();
       if (tid < nc) {
         T s = 0;
-        for (int v = 0; v < NW; ++v) s += red[v * CGS_CC + tid];
-        partials[static_cast<int64_t>(c0 + tid) * G + blockIdx.x] = s;
+        for (int v = 0; v < NW; ++v) s += red[v * 8 + tid];
+        part[static_cast<int64_t>(c0 + tid) * nblk + blk] = s;
       }
       __syncthreads();
     }
   }
-  if (elect_last_block(counter, &flag)) reduce_partials(partials, j, h2);
+  finish_columns(part, part2, nblk, blk, j, h2, cnt, &flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -197,6 +285,7 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(
 //   MODE_UPDATE : nothing else (restart: u_{k+1} = A v_{k+1} - Uk rho, eq. (7))
 //   MODE_NORM   : xs = 1 / |w2|                              (start vector)
 //   MODE_LANCZOS: T entry = |w2|, xs = 1/|w2|, breakdown handling
+// One row per thread, the column loop unrolled 8-wide for loads in flight.
 // ---------------------------------------------------------------------------
 enum { MODE_UPDATE = 0, MODE_NORM = 1, MODE_LANCZOS = 2 };
 
@@ -253,41 +342,39 @@ template <typename T>
 __global__ __launch_bounds__(CGS_THREADS) void cgs_upd_norm_kernel(
     const T *__restrict__ Q, int64_t ldq, int64_t L, int j, const T *__restrict__ w1,
     const T *__restrict__ h, T *__restrict__ out, double *__restrict__ partials,
-    unsigned int *__restrict__ counter, int mode, FinishArgs fa) {
+    unsigned int *__restrict__ cnt, int mode, FinishArgs fa) {
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ double sh_d[CGS_THREADS / WAVE];
   __shared__ int flag;
   const int tid = threadIdx.x;
   for (int c = tid; c < j; c += CGS_THREADS) sh_h[c] = h[c];
   __syncthreads();
-  int64_t r0, r1;
-  block_slab(L, r0, r1);
   double nrm2 = 0;
-  for (int64_t r = r0 + tid; r < r1; r += CGS_THREADS) {
-    T u0 = 0, u1 = 0, u2 = 0, u3 = 0;
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * CGS_THREADS + tid; r < L;
+       r += static_cast<int64_t>(gridDim.x) * CGS_THREADS) {
+    T u[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) u[i] = 0;
     int c = 0;
-    for (; c + 4 <= j; c += 4) {
-      u0 += Q[(c + 0) * ldq + r] * sh_h[c + 0];
-      u1 += Q[(c + 1) * ldq + r] * sh_h[c + 1];
-      u2 += Q[(c + 2) * ldq + r] * sh_h[c + 2];
-      u3 += Q[(c + 3) * ldq + r] * sh_h[c + 3];
+    for (; c + 8 <= j; c += 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) u[i] += Q[(c + i) * ldq + r] * sh_h[c + i];
     }
-    for (; c < j; ++c) u0 += Q[c * ldq + r] * sh_h[c];
-    const T x = w1[r] - ((u0 + u1) + (u2 + u3));
+    for (; c < j; ++c) u[0] += Q[c * ldq + r] * sh_h[c];
+    const T x = w1[r] - (((u[0] + u[1]) + (u[2] + u[3])) + ((u[4] + u[5]) + (u[6] + u[7])));
     out[r] = x;
     nrm2 += static_cast<double>(x) * static_cast<double>(x);
   }
   if (mode == MODE_UPDATE) return;
   nrm2 = block_sum(nrm2, sh_d);
   if (tid == 0) partials[blockIdx.x] = nrm2;
-  if (!elect_last_block(counter, &flag)) return;
+  if (!elect_last_block(cnt, &flag)) return;
+  // ordered sum of the block partials: thread i adds i, i+256, ..., then the
+  // fixed-order block reduction
   double tot = 0;
-  if (tid == 0)
-    for (int g = 0; g < static_cast<int>(gridDim.x); ++g) tot += partials[g];
-  if (tid == 0) sh_d[0] = tot;
-  __syncthreads();
-  const double nrm = sqrt(sh_d[0]);
-  __syncthreads();
+  for (int g = tid; g < static_cast<int>(gridDim.x); g += CGS_THREADS) tot += partials[g];
+  tot = block_sum(tot, sh_d);
+  const double nrm = sqrt(tot);
   if (mode == MODE_NORM) {
     if (tid == 0) *fa.xs = 1.0 / nrm;
     return;
@@ -312,6 +399,24 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_upd_norm_kernel(
   }
   __syncthreads();
   breakdown_repair<T>(Q, ldq, L, j, out, static_cast<uint32_t>(bd), fa.seed, sh_d, sh_h);
+}
+
+// Launch shapes (host side).
+inline void cgs_proj_shape(int64_t L, int j, int &nslab, int &ngrp_c) {
+  ngrp_c = static_cast<int>(ceil_div(j, CGS_PCG));
+  const int64_t tiles = ceil_div(L, WAVE);
+  int64_t s = ceil_div(2048, ngrp_c);
+  s = std::min<int64_t>(s, ceil_div(tiles, 8));  // >= 8 tiles (2 per wave) per block
+  s = std::max<int64_t>(s, 1);
+  s = std::min<int64_t>(s, CGS_MAX_BLOCKS);
+  nslab = static_cast<int>(s);
+}
+inline int cgs_updproj_blocks(int64_t L) {
+  const int64_t tiles = ceil_div(L, WAVE);
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(tiles, 4))));
+}
+inline int cgs_updnorm_blocks(int64_t L) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(8192, ceil_div(L, CGS_THREADS))));
 }
 
 }  // namespace svds

@@ -137,7 +137,7 @@ template <typename TB> struct Lanczos {
   int cur = 0;
   TB *wu = nullptr, *w1u = nullptr, *bu = nullptr;
   TB *wv = nullptr, *w1v = nullptr, *bv = nullptr;
-  TB *h1 = nullptr, *h2 = nullptr, *partials = nullptr;
+  TB *h1 = nullptr, *h2 = nullptr, *partials = nullptr, *part2 = nullptr;
   void carve(Arena &a, int64_t m_, int64_t n_, int p) {
     m = m_;
     n = n_;
@@ -156,6 +156,7 @@ template <typename TB> struct Lanczos {
     h1 = a.take<TB>(CGS_MAXJ);
     h2 = a.take<TB>(CGS_MAXJ);
     partials = a.take<TB>(static_cast<size_t>(CGS_MAXJ) * GMAX);
+    part2 = a.take<TB>(static_cast<size_t>(CGS_MAXJ) * CGS_CNT_STRIDE);
   }
 };
 
@@ -163,9 +164,17 @@ template <typename TB> struct Lanczos {
 struct Small {
   double *T, *xs_u, *xs_v, *one, *sigma_est, *rho, *sig, *res, *Uk, *Vext, *jac, *npart;
   double *resid_av, *resid_atu;
-  unsigned int *cnt;  // [0] proj, [1] upd_proj, [2] upd_norm, [3] norm
+  unsigned int *cnt;  // arrival counters, offsets CNT_*
   int *bd, *flags;
 };
+
+// offsets into Small::cnt
+constexpr int CNT_PROJ = 0;
+constexpr int CNT_UPDPROJ = CGS_CNT_WORDS;
+constexpr int CNT_UPDNORM = CNT_UPDPROJ + CGS_CNT_STRIDE;
+constexpr int CNT_NORM = CNT_UPDNORM + 1;
+constexpr int CNT_WORDS = CNT_NORM + 1;
+constexpr int NPART = 8192;  // norm partials (cgs_upd_norm blocks <= 8192)
 
 }  // namespace svds
 
@@ -270,27 +279,27 @@ static int cgs2_finish(svds_plan *P, Lanczos<TB> &Lz, const TB *Q, int64_t ldq, 
   const Small &s = P->sc;
   const TB *src = w;
   if (j > 0) {
-    const unsigned gp = grid_for(L, 2048);
+    int nslab, ngc;
+    cgs_proj_shape(L, j, nslab, ngc);
     ACC_BEFORE(SVDS_KC_CGS_PROJ);
-    hipLaunchKernelGGL((cgs_proj_kernel<TB>), dim3(gp), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
-                       L, j, w, Lz.partials, Lz.h1, s.cnt + 0);
+    hipLaunchKernelGGL((cgs_proj_kernel<TB>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q,
+                       ldq, L, j, w, Lz.partials, Lz.part2, Lz.h1, s.cnt + CNT_PROJ);
     LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_CGS_PROJ, sb * L * j + sb * L, 2.0 * L * j);
 
     const int nw = std::max(1, std::min(16, static_cast<int>(ceil_div(j, CGS_CPW))));
-    const unsigned gu = grid_for(L, 2048);
     ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
-    hipLaunchKernelGGL((cgs_upd_proj_kernel<TB>), dim3(gu), dim3(nw * WAVE), 0, P->stream, Q, ldq,
-                       L, j, w, Lz.h1, w1, Lz.partials, Lz.h2, s.cnt + 1);
+    hipLaunchKernelGGL((cgs_upd_proj_kernel<TB>), dim3(cgs_updproj_blocks(L)), dim3(nw * WAVE), 0,
+                       P->stream, Q, ldq, L, j, w, Lz.h1, w1, Lz.partials, Lz.part2, Lz.h2,
+                       s.cnt + CNT_UPDPROJ);
     LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 4.0 * L * j);
     src = w1;
   }
-  const unsigned gn = grid_for(L, 2048);
   FinishArgs fa{t_entry, xs, s.sigma_est, s.bd, P->opts.seed};
   ACC_BEFORE(SVDS_KC_CGS_UPDNORM);
-  hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(gn), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
-                     L, j, src, Lz.h2, out, s.npart, s.cnt + 2, mode, fa);
+  hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
+                     P->stream, Q, ldq, L, j, src, Lz.h2, out, s.npart, s.cnt + CNT_UPDNORM, mode, fa);
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * j + 2 * sb * L, 2.0 * L * j + 2.0 * L);
   return SVDS_OK;
@@ -302,10 +311,10 @@ static int gemv_update(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, int j,
                        const TB *h, TB *out) {
   const double sb = sizeof(TB);
   FinishArgs fa{nullptr, nullptr, nullptr, nullptr, 0};
-  const unsigned gn = grid_for(L, 2048);
   ACC_BEFORE(SVDS_KC_OTHER);
-  hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(gn), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
-                     L, j, w, h, out, P->sc.npart, P->sc.cnt + 2, static_cast<int>(MODE_UPDATE), fa);
+  hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
+                     P->stream, Q, ldq, L, j, w, h, out, P->sc.npart, P->sc.cnt + CNT_UPDNORM,
+                     static_cast<int>(MODE_UPDATE), fa);
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_OTHER, sb * L * j + 2 * sb * L, 2.0 * L * j);
   return SVDS_OK;
@@ -518,10 +527,10 @@ static int carve_all(svds_plan *P, Arena &a) {
   s.Uk = a.take<double>(static_cast<size_t>(p) * k);
   s.Vext = a.take<double>(static_cast<size_t>(p + 1) * (k + 1));
   s.jac = a.take<double>(jacobi_work_bytes(p) / 8 + 8);
-  s.npart = a.take<double>(GMAX);
+  s.npart = a.take<double>(NPART);
   s.resid_av = a.take<double>(k);
   s.resid_atu = a.take<double>(k);
-  s.cnt = a.take<unsigned int>(8);
+  s.cnt = a.take<unsigned int>(CNT_WORDS);
   s.bd = a.take<int>(4);
   s.flags = a.take<int>(4);
   P->tmp_m = a.take<double>(m);
@@ -564,7 +573,7 @@ static int alloc_arena(svds_plan *P) {
   HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&P->h_flags), 16 * sizeof(int), hipHostMallocDefault));
   const double one = 1.0;
   HIP_TRY(hipMemcpyAsync(P->sc.one, &one, sizeof one, hipMemcpyHostToDevice, P->stream));
-  HIP_TRY(hipMemsetAsync(P->sc.cnt, 0, 8 * sizeof(unsigned int), P->stream));
+  HIP_TRY(hipMemsetAsync(P->sc.cnt, 0, CNT_WORDS * sizeof(unsigned int), P->stream));
   if (P->op.dense)
     HIP_TRY(hipMemsetAsync(P->op.dcnt, 0, sizeof(unsigned int) * dense_counter_count(P->op.m), P->stream));
   return SVDS_OK;
@@ -887,13 +896,13 @@ static int residuals_impl(svds_plan *P, int k, const double *U, const double *S,
                             SVDS_KC_OTHER);
     if (rc) return rc;
     hipLaunchKernelGGL((norm_kernel<double>), dim3(grid_for(m, 4096)), dim3(256), 0, P->stream, m,
-                       P->tmp_m, P->sc.npart, P->sc.cnt + 3, res_av + j);
+                       P->tmp_m, P->sc.npart, P->sc.cnt + CNT_NORM, res_av + j);
     LAUNCH_CHECK();
     rc = matvec<double>(P, true, U + j * m, P->sc.one, S + j, V + j * n, P->tmp_n, nullptr, 0,
                         SVDS_KC_OTHER);
     if (rc) return rc;
     hipLaunchKernelGGL((norm_kernel<double>), dim3(grid_for(n, 4096)), dim3(256), 0, P->stream, n,
-                       P->tmp_n, P->sc.npart, P->sc.cnt + 3, res_atu + j);
+                       P->tmp_n, P->sc.npart, P->sc.cnt + CNT_NORM, res_atu + j);
     LAUNCH_CHECK();
   }
   // residual products are not Lanczos steps (booked under OTHER, not counted)

@@ -280,3 +280,24 @@ def test_dense_matvec_matches_numpy(S, m, n, store):
     ref = rec.T @ u + yp_n
     sc = np.abs(rec.T) @ np.abs(u) + np.abs(yp_n)
     assert np.all(np.abs(z - ref) <= (m + 3) * 2.0**-53 * sc)
+
+
+def test_small_svd_near_degenerate_pair(S):
+    """Decay1 has sigma_20 = sigma_21 exactly; T of the first Lanczos cycle has
+    a pair of Ritz values 1e-13 apart whose inner product sits at the rounding
+    floor.  Every lane of a wave must take the same rotation decision and
+    angle, or the accumulated right vectors lose orthogonality."""
+    sig = inputs.decay1(300)
+    A = inputs.prescribed_dense(500, 300, sig, seed=61)
+    seen = []
+    svds_ref.svds(A, 20, 60, 1e-10, 1, v0=inputs.start_vector(300, 62),
+                  callback=lambda st, s, ex: seen.append(s.T.copy()) if st == "svd" else None)
+    T = seen[0]
+    p, k = 60, 20
+    s_ref = sla.svd(T[:p, :p], compute_uv=False, lapack_driver="gesvd")
+    Uk, Vext, sg, res, rho, flags = S.svds_op_small_svd(_t(T.copy()), p, k, 1e-10)
+    Uk = Uk.cpu().numpy().T
+    Vk = Vext.cpu().numpy().T[:p, :k]
+    np.testing.assert_allclose(sg.cpu().numpy(), s_ref[:k], rtol=1e-13)
+    assert np.abs(Vk.T @ Vk - np.eye(k)).max() < 1e-13
+    assert np.abs(Uk.T @ Uk - np.eye(k)).max() < 1e-13
