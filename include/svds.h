@@ -108,6 +108,7 @@ enum {
   SVDS_KC_CGS_PROJ,      /* h1 = Q^T w                (first CGS pass)      */
   SVDS_KC_CGS_UPDPROJ,   /* w1 = w - Q h1, h2 = Q^T w1                      */
   SVDS_KC_CGS_UPDNORM,   /* w2 = w1 - Q h2, |w2|      (alpha/beta)          */
+  SVDS_KC_CGS_REDUCE,    /* cross-block sums of the CGS passes, norm finish */
   SVDS_KC_SMALLSVD,      /* SVD of T, test, restart set-up (Alg. 2 4-9)     */
   SVDS_KC_ROTATE,        /* U Uh_k, V Vh_k            (Alg. 2 steps 8, 16)  */
   SVDS_KC_OTHER,         /* restart update, residuals, signs, casts         */

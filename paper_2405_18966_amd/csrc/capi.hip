@@ -108,21 +108,25 @@ extern "C" int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *
   build_spmv_items(hrp.data(), A->m, sp);
   Scratch s;
   const size_t bi = sizeof(int4) * sp.nitems, bl = sizeof(LongRow) * std::max(1, sp.nlong),
-               bp = sizeof(double) * std::max(1, sp.npieces), bc = sizeof(unsigned) * std::max(1, sp.nlong);
-  HIP_TRY(hipMalloc(&s.p, bi + bl + bp + bc + 1024));
+               bp = sizeof(double) * std::max(1, sp.npieces);
+  HIP_TRY(hipMalloc(&s.p, bi + bl + bp + 1024));
   char *b = static_cast<char *>(s.p);
   int4 *items = reinterpret_cast<int4 *>(b);
   LongRow *lr = reinterpret_cast<LongRow *>(b + ((bi + 255) & ~size_t(255)));
   double *parts = reinterpret_cast<double *>(reinterpret_cast<char *>(lr) + ((bl + 255) & ~size_t(255)));
-  unsigned *cnt = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(parts) + ((bp + 255) & ~size_t(255)));
   HIP_TRY(hipMemcpy(items, sp.h_items.data(), bi, hipMemcpyHostToDevice));
   if (sp.nlong) HIP_TRY(hipMemcpy(lr, sp.h_long.data(), sizeof(LongRow) * sp.nlong, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemset(cnt, 0, bc));
-#define SPMV_GO(TV, TB)                                                                            \
-  hipLaunchKernelGGL((spmv_csr_kernel<TV, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0, st, items, \
-                     lr, A->row_ptr, A->col_idx, static_cast<const TV *>(A->val),                  \
-                     static_cast<const TB *>(x), x_scale, coef, static_cast<const TB *>(yprev),    \
-                     static_cast<TB *>(y), reinterpret_cast<TB *>(parts), cnt, nullptr, 0)
+#define SPMV_GO(TV, TB)                                                                             \
+  do {                                                                                              \
+    hipLaunchKernelGGL((spmv_csr_kernel<TV, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0, st, items, \
+                       A->row_ptr, A->col_idx, static_cast<const TV *>(A->val),                     \
+                       static_cast<const TB *>(x), x_scale, coef, static_cast<const TB *>(yprev),   \
+                       static_cast<TB *>(y), reinterpret_cast<TB *>(parts), nullptr, 0);             \
+    if (sp.nlong)                                                                                   \
+      hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(ceil_div(sp.nlong, 64)), dim3(64), 0, \
+                         st, lr, sp.nlong, reinterpret_cast<TB *>(parts), x_scale, coef,            \
+                         static_cast<const TB *>(yprev), static_cast<TB *>(y));                     \
+  } while (0)
   if (A->dtype == SVDS_F64 && basis_dtype == SVDS_F64) SPMV_GO(double, double);
   else if (A->dtype == SVDS_F32 && basis_dtype == SVDS_F64) SPMV_GO(float, double);
   else if (A->dtype == SVDS_F64 && basis_dtype == SVDS_F32) SPMV_GO(double, float);
@@ -173,47 +177,51 @@ extern "C" int svds_op_cgs2(int64_t L, int32_t j, const void *Q, int64_t ldq, co
   if (dtype != SVDS_F64 && dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t tb = dtype == SVDS_F64 ? 8 : 4;
-  // scratch: partials, group sums, h1, h2, w1, norm partials, scalars, counters
-  const size_t n_parts = static_cast<size_t>(CGS_MAXJ) * GMAX, n_p2 = static_cast<size_t>(CGS_MAXJ) * CGS_CNT_STRIDE;
+  // scratch: partials, h1, h2, w1, norm partials, scalars
+  const size_t n_parts = static_cast<size_t>(CGS_MAXJ) * CGS_MAX_SLABS;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
     off += (bytes + 255) & ~size_t(255);
     return o;
   };
-  const size_t o_parts = take(tb * n_parts), o_p2 = take(tb * n_p2), o_h1 = take(tb * CGS_MAXJ),
-               o_h2 = take(tb * CGS_MAXJ), o_w1 = take(tb * L), o_np = take(8 * 8192), o_dx = take(8 * 8),
-               o_cnt = take(4 * (CGS_CNT_WORDS + CGS_CNT_STRIDE + 4)), o_bd = take(16);
+  const size_t o_parts = take(tb * n_parts), o_h1 = take(tb * CGS_MAXJ), o_h2 = take(tb * CGS_MAXJ),
+               o_w1 = take(tb * L), o_np = take(8 * NORM_MAX_BLOCKS), o_dx = take(8 * 8), o_bd = take(16);
   Scratch s;
   HIP_TRY(hipMalloc(&s.p, off));
   HIP_TRY(hipMemsetAsync(s.p, 0, off, st));
   char *b = static_cast<char *>(s.p);
-  void *parts = b + o_parts, *p2 = b + o_p2, *h1 = b + o_h1, *h2 = b + o_h2, *w1 = b + o_w1;
+  void *parts = b + o_parts, *h1 = b + o_h1, *h2 = b + o_h2, *w1 = b + o_w1;
   double *npart = reinterpret_cast<double *>(b + o_np);
   double *dx = reinterpret_cast<double *>(b + o_dx);  // xs, t_entry, sigma_est
-  unsigned *cnt = reinterpret_cast<unsigned *>(b + o_cnt);
   int *bd = reinterpret_cast<int *>(b + o_bd);
   const int nw = std::max(1, std::min(16, static_cast<int>(ceil_div(std::max(j, 1), CGS_CPW))));
   FinishArgs fa{dx + 1, dx, dx + 2, bd, 0};
   int nslab = 1, ngc = 1;
   if (j > 0) cgs_proj_shape(L, j, nslab, ngc);
+  const int nb = cgs_updproj_blocks(L), nn = cgs_updnorm_blocks(L);
 #define CGS_GO(T)                                                                                    \
   do {                                                                                               \
     const T *src = static_cast<const T *>(w);                                                        \
+    T *pp = static_cast<T *>(parts);                                                                 \
     if (j > 0) {                                                                                     \
       hipLaunchKernelGGL((cgs_proj_kernel<T>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, st,           \
-                         static_cast<const T *>(Q), ldq, L, j, src, static_cast<T *>(parts),         \
-                         static_cast<T *>(p2), static_cast<T *>(h1), cnt);                           \
-      hipLaunchKernelGGL((cgs_upd_proj_kernel<T>), dim3(cgs_updproj_blocks(L)), dim3(nw * WAVE), 0,  \
-                         st, static_cast<const T *>(Q), ldq, L, j, src, static_cast<T *>(h1),        \
-                         static_cast<T *>(w1), static_cast<T *>(parts), static_cast<T *>(p2),        \
-                         static_cast<T *>(h2), cnt + CGS_CNT_WORDS);                                 \
+                         static_cast<const T *>(Q), ldq, L, j, src, pp);                             \
+      hipLaunchKernelGGL((reduce_cols_kernel<T>), dim3(ceil_div(j, 4)), dim3(256), 0, st, pp,        \
+                         static_cast<int64_t>(nslab), nslab, j, static_cast<T *>(h1));               \
+      hipLaunchKernelGGL((cgs_upd_proj_kernel<T>), dim3(nb), dim3(nw * WAVE), 0, st,                 \
+                         static_cast<const T *>(Q), ldq, L, j, src, static_cast<T *>(h1),            \
+                         static_cast<T *>(w1), pp);                                                  \
+      hipLaunchKernelGGL((reduce_cols_kernel<T>), dim3(ceil_div(j, 4)), dim3(256), 0, st, pp,        \
+                         static_cast<int64_t>(nb), nb, j, static_cast<T *>(h2));                     \
       src = static_cast<const T *>(w1);                                                              \
     }                                                                                                \
-    hipLaunchKernelGGL((cgs_upd_norm_kernel<T>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,  \
-                       st, static_cast<const T *>(Q), ldq, L, j, src, static_cast<T *>(h2),          \
-                       static_cast<T *>(out), npart, cnt + CGS_CNT_WORDS + CGS_CNT_STRIDE,           \
-                       static_cast<int>(MODE_NORM), fa);                                             \
+    hipLaunchKernelGGL((cgs_upd_norm_kernel<T>), dim3(nn), dim3(CGS_THREADS), 0, st,                 \
+                       static_cast<const T *>(Q), ldq, L, j, src, static_cast<T *>(h2),              \
+                       static_cast<T *>(out), npart);                                                \
+    hipLaunchKernelGGL((finish_norm_kernel<T>), dim3(1), dim3(CGS_THREADS), 0, st, npart, nn,        \
+                       static_cast<int>(MODE_NORM), fa, static_cast<const T *>(Q), ldq, L, j,        \
+                       static_cast<T *>(out));                                                       \
   } while (0)
   if (dtype == SVDS_F64) CGS_GO(double);
   else CGS_GO(float);

@@ -76,26 +76,6 @@ template <typename T> __device__ __forceinline__ T block_sum(T v, T *sh) {
   return s;
 }
 
-// Grid "last block" election: every block calls this once after writing its
-// partial results; returns true in exactly one block (the last to arrive),
-// after which that block may read all partials.  The counter is reset by the
-// elected block, so it is ready for the next launch.
-__device__ __forceinline__ bool elect_last_block(unsigned int *counter, int *sh_flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int ticket = atomicAdd(counter, 1u);
-    *sh_flag = (ticket == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  bool last = *sh_flag != 0;
-  if (last) {
-    __threadfence();
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
-  }
-  return last;
-}
-
 __host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------------------

@@ -5,18 +5,14 @@
 //
 // Q is the basis, column-major with leading dimension ldq, columns [0, j);
 // w has L entries.  Three passes over Q, the minimum with Q in HBM:
-//   cgs_proj      : h1 = Q^T w
-//   cgs_upd_proj  : w1 = w - Q h1 and h2 = Q^T w1 from the same read of Q
-//   cgs_upd_norm  : w2 = w1 - Q h2, |w2|; the last block turns the norm into
-//                   T(i,i) / T(i,i+1), the reciprocal scale of the vector,
-//                   and handles breakdown.
-// All three kernels are HBM-bound; each keeps many independent 512-byte
-// column segments in flight per wave.
-//
-// Cross-block reductions are deterministic and two-level: blocks write
-// per-column partial sums, the last block of every group of RED_GROUP blocks
-// (arrival counter) adds its group's partials in block order, and the last
-// group reducer adds the group sums in group order.  No float atomics.
+//   cgs_proj      : partials of h1 = Q^T w
+//   cgs_upd_proj  : w1 = w - Q h1 and partials of h2 = Q^T w1 from the same
+//                   read of Q
+//   cgs_upd_norm  : w2 = w1 - Q h2 and partials of |w2|^2
+// Cross-block sums are finished by small kernels at the kernel boundary
+// (reduce_cols_kernel, finish_norm_kernel): on MI355X a device-scope fence or
+// a shared arrival counter in every block costs ~0.1 us per block, serialized,
+// far more than one extra launch.  Sums are in fixed order (deterministic).
 #pragma once
 #include <algorithm>
 #include "common.hpp"
@@ -27,91 +23,36 @@ constexpr int CGS_THREADS = 256;
 constexpr int CGS_PCG = 32;     // columns per block column-group in cgs_proj
 constexpr int CGS_CPW = 16;     // columns per wave in cgs_upd_proj
 constexpr int CGS_MAXJ = 1024;  // largest basis width supported
-constexpr int RED_GROUP = 16;   // blocks per first-level reduction group
-constexpr int CGS_MAX_BLOCKS = 2048;
-// counters: per column group (<= CGS_MAXJ / CGS_PCG) one row of
-// (CGS_MAX_BLOCKS / RED_GROUP + 1) counters
-constexpr int CGS_CNT_STRIDE = CGS_MAX_BLOCKS / RED_GROUP + 1;
-constexpr int CGS_CNT_WORDS = (CGS_MAXJ / CGS_PCG) * CGS_CNT_STRIDE;
+constexpr int CGS_MAX_SLABS = 1024;  // partials per column (cgs_proj / cgs_upd_proj)
+constexpr int NORM_MAX_BLOCKS = 2048;
 constexpr double BREAKDOWN_REL = 1e-14;
 
-// out[c] = sum_{i < nv} src[c * ld + i], c < nc, in index order, using all
-// threads of the block: tpc threads per column take interleaved indices and
-// combine with a fixed xor pattern (deterministic for a given launch shape).
+// out[c] = sum_{i < nv} src[c * ld + i] for c < nc.  One wave per column,
+// lanes take interleaved indices, fixed-order wave reduction.
 template <typename T>
-__device__ __forceinline__ void reduce_columns(const T *__restrict__ src, int64_t ld, int nv, int nc,
-                                               T *__restrict__ out, int64_t out_stride) {
-  const int nt = blockDim.x;
-  int tpc = 1;
-  while (tpc * 2 * nc <= nt && tpc < 32) tpc *= 2;
-  const int lanes = nc * tpc;
-  for (int base = 0; base < lanes; base += nt) {
-    const int id = base + threadIdx.x;
-    const int c = id / tpc, sub = id % tpc;
-    T s = 0;
-    if (c < nc) {
-      const T *p = src + static_cast<int64_t>(c) * ld;
-      for (int i = sub; i < nv; i += tpc) s += p[i];
-    }
-    // combine the tpc partials of a column (consecutive lanes of one wave)
-    for (int o = 1; o < tpc; o <<= 1) s += __shfl_xor(s, o, WAVE);
-    if (c < nc && sub == 0) out[static_cast<int64_t>(c) * out_stride] = s;
-  }
-}
-
-// Two-level completion of a per-column partial-sum array.
-//   part  : [nc][nblk] partials of this block's column range (ld nblk)
-//   part2 : [nc][ngrp] group sums (ld ngrp), ngrp = ceil(nblk / RED_GROUP)
-//   cnt   : ngrp + 1 arrival counters (self-resetting)
-// The block with index `blk` (0..nblk-1) calls this after writing its
-// partials; the final sums land in out[c].
-template <typename T>
-__device__ __forceinline__ void finish_columns(T *__restrict__ part, T *__restrict__ part2, int nblk,
-                                               int blk, int nc, T *__restrict__ out,
-                                               unsigned int *__restrict__ cnt, int *sh_flag) {
-  const int ngrp = (nblk + RED_GROUP - 1) / RED_GROUP;
-  const int g = blk / RED_GROUP;
-  const int gsize = min(RED_GROUP, nblk - g * RED_GROUP);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int t = atomicAdd(&cnt[g], 1u);
-    *sh_flag = (t == static_cast<unsigned int>(gsize - 1));
-  }
-  __syncthreads();
-  if (!*sh_flag) return;
-  __threadfence();
-  if (threadIdx.x == 0) atomicExch(&cnt[g], 0u);
-  if (ngrp == 1) {
-    reduce_columns(part + g * RED_GROUP, nblk, gsize, nc, out, 1);
-    return;
-  }
-  reduce_columns(part + g * RED_GROUP, nblk, gsize, nc, part2 + g, ngrp);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int t = atomicAdd(&cnt[ngrp], 1u);
-    *sh_flag = (t == static_cast<unsigned int>(ngrp - 1));
-  }
-  __syncthreads();
-  if (!*sh_flag) return;
-  __threadfence();
-  if (threadIdx.x == 0) atomicExch(&cnt[ngrp], 0u);
-  reduce_columns(part2, ngrp, ngrp, nc, out, 1);
+__global__ __launch_bounds__(256) void reduce_cols_kernel(const T *__restrict__ src, int64_t ld, int nv,
+                                                          int nc, T *__restrict__ out) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int c = blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+  if (c >= nc) return;
+  const T *p = src + static_cast<int64_t>(c) * ld;
+  T s = 0;
+  for (int i = lane; i < nv; i += WAVE) s += p[i];
+  s = wave_sum(s);
+  if (lane == 0) out[c] = s;
 }
 
 // ---------------------------------------------------------------------------
-// Pass 1: h = Q^T w.  Grid (row slabs, column groups of 32).  Each wave walks
-// 64-row tiles of its block's slab keeping 32 column accumulators per lane.
-// part: [j][nslab], part2: [j][ceil(nslab/16)].
+// Pass 1: partials of h = Q^T w.  Grid (row slabs, column groups of 32).
+// Each wave walks 64-row tiles of its block's slab keeping 32 column
+// accumulators per lane.  part: [j][nslab].
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(
-    const T *__restrict__ Q, int64_t ldq, int64_t L, int j, const T *__restrict__ w,
-    T *__restrict__ part, T *__restrict__ part2, T *__restrict__ h, unsigned int *__restrict__ cnt) {
+__global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restrict__ Q, int64_t ldq,
+                                                              int64_t L, int j, const T *__restrict__ w,
+                                                              T *__restrict__ part) {
   constexpr int NW = CGS_THREADS / WAVE;
   __shared__ T red[NW][CGS_PCG + 1];
-  __shared__ int flag;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int nslab = gridDim.x, slab = blockIdx.x;
   const int c0 = blockIdx.y * CGS_PCG;
@@ -154,29 +95,25 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(
     for (int v = 0; v < NW; ++v) s += red[v][tid];
     part[static_cast<int64_t>(c0 + tid) * nslab + slab] = s;
   }
-  const int ngrp = (nslab + RED_GROUP - 1) / RED_GROUP;
-  finish_columns(part + static_cast<int64_t>(c0) * nslab, part2 + static_cast<int64_t>(c0) * ngrp, nslab,
-                 slab, nc, h + c0, cnt + blockIdx.y * CGS_CNT_STRIDE, &flag);
 }
 
 // ---------------------------------------------------------------------------
 // Pass 2 fused with the update of pass 1: w1 = w - Q h1 (written out) and
-// h2 = Q^T w1.  Block = NW = ceil(j/16) waves (<= 16, so j <= 256); a block
-// walks 64-row tiles; wave v holds columns [16v, 16v+16) of the tile in
-// registers, so Q is read once for both the update and the projection.  The
-// next tile is loaded before the current one is consumed, and the
-// cross-wave sums go through a double-buffered LDS array (one barrier per
-// tile).  Wider bases (j > 256) take a generic two-sweep path.
-// part: [j][nblk], part2: [j][ceil(nblk/16)].
+// partials of h2 = Q^T w1.  Block = NW = ceil(j/16) waves (<= 16, so
+// j <= 256); a block walks 64-row tiles; wave v holds columns [16v, 16v+16)
+// of the tile in registers, so Q is read once for both the update and the
+// projection.  The next tile is loaded before the current one is consumed,
+// and the cross-wave sums go through a double-buffered LDS array (one
+// barrier per tile).  Wider bases (j > 256) take a generic two-sweep path.
+// part: [j][nblk].
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(
-    const T *__restrict__ Q, int64_t ldq, int64_t L, int j, const T *__restrict__ w,
-    const T *__restrict__ h1, T *__restrict__ w1out, T *__restrict__ part, T *__restrict__ part2,
-    T *__restrict__ h2, unsigned int *__restrict__ cnt) {
+__global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict__ Q, int64_t ldq,
+                                                           int64_t L, int j, const T *__restrict__ w,
+                                                           const T *__restrict__ h1,
+                                                           T *__restrict__ w1out, T *__restrict__ part) {
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ T xch[2][16][WAVE];
-  __shared__ int flag;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int NW = blockDim.x / WAVE;
   const int nblk = gridDim.x, blk = blockIdx.x;
@@ -197,8 +134,7 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(
 #pragma unroll
     for (int c = 0; c < CGS_CPW; ++c) acc[c] = 0, qn[c] = 0;
     T wn = 0;
-    // prefetch the first tile
-    if (t0 < t1) {
+    if (t0 < t1) {  // prefetch the first tile
       const int64_t r = t0 * WAVE + lane;
       if (r < L) {
 #pragma unroll
@@ -211,7 +147,7 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(
     for (int64_t t = t0; t < t1; ++t) {
       const int64_t r = t * WAVE + lane;
       const bool valid = r < L;
-      T wr = wn;
+      const T wr = wn;
 #pragma unroll
       for (int c = 0; c < CGS_CPW; ++c) q[c] = qn[c];
       if (t + 1 < t1) {
@@ -277,17 +213,51 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(
       __syncthreads();
     }
   }
-  finish_columns(part, part2, nblk, blk, j, h2, cnt, &flag);
 }
 
 // ---------------------------------------------------------------------------
-// Pass 3: w2 = w1 - Q h (written to out), then, by mode:
-//   MODE_UPDATE : nothing else (restart: u_{k+1} = A v_{k+1} - Uk rho, eq. (7))
-//   MODE_NORM   : xs = 1 / |w2|                              (start vector)
-//   MODE_LANCZOS: T entry = |w2|, xs = 1/|w2|, breakdown handling
-// One row per thread, the column loop unrolled 8-wide for loads in flight.
+// Pass 3: out = w1 - Q h; with `npart` non-null, partials of |out|^2 (FP64).
+// Grid-stride rows, the column loop unrolled 8-wide for loads in flight.
 // ---------------------------------------------------------------------------
-enum { MODE_UPDATE = 0, MODE_NORM = 1, MODE_LANCZOS = 2 };
+template <typename T>
+__global__ __launch_bounds__(CGS_THREADS) void cgs_upd_norm_kernel(
+    const T *__restrict__ Q, int64_t ldq, int64_t L, int j, const T *__restrict__ w1,
+    const T *__restrict__ h, T *__restrict__ out, double *__restrict__ npart) {
+  __shared__ T sh_h[CGS_MAXJ];
+  __shared__ double sh_d[CGS_THREADS / WAVE];
+  const int tid = threadIdx.x;
+  for (int c = tid; c < j; c += CGS_THREADS) sh_h[c] = h[c];
+  __syncthreads();
+  double nrm2 = 0;
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * CGS_THREADS + tid; r < L;
+       r += static_cast<int64_t>(gridDim.x) * CGS_THREADS) {
+    T u[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) u[i] = 0;
+    int c = 0;
+    for (; c + 8 <= j; c += 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) u[i] += Q[(c + i) * ldq + r] * sh_h[c + i];
+    }
+    for (; c < j; ++c) u[0] += Q[c * ldq + r] * sh_h[c];
+    const T x = w1[r] - (((u[0] + u[1]) + (u[2] + u[3])) + ((u[4] + u[5]) + (u[6] + u[7])));
+    out[r] = x;
+    nrm2 += static_cast<double>(x) * static_cast<double>(x);
+  }
+  if (!npart) return;
+  nrm2 = block_sum(nrm2, sh_d);
+  if (tid == 0) npart[blockIdx.x] = nrm2;
+}
+
+// ---------------------------------------------------------------------------
+// Norm finish (one block): adds the norm partials in block order, then by mode
+//   MODE_NORM   : xs = 1 / |w|                               (start vector)
+//   MODE_LANCZOS: T entry = |w|, xs = 1/|w|, sigma_est update; on breakdown
+//                 (|w| <= 1e-14 sigma_est) the vector is replaced in place by
+//                 a Philox normal vector re-orthogonalized against Q (CGS2)
+//                 and normalized, T entry = 0, xs = 1.
+// ---------------------------------------------------------------------------
+enum { MODE_NORM = 1, MODE_LANCZOS = 2 };
 
 struct FinishArgs {
   double *t_entry;      // T(i,i) or T(i,i+1)
@@ -297,9 +267,6 @@ struct FinishArgs {
   uint64_t seed;
 };
 
-// Single-block CGS2 of the Philox vector that replaces a vector lost to a
-// breakdown: out <- normalize(CGS2(z, Q)).  Only the elected last block of
-// cgs_upd_norm runs this, and only on breakdown.
 template <typename T>
 __device__ void breakdown_repair(const T *__restrict__ Q, int64_t ldq, int64_t L, int j,
                                  T *__restrict__ out, uint32_t stream, uint64_t seed,
@@ -334,45 +301,19 @@ __device__ void breakdown_repair(const T *__restrict__ Q, int64_t ldq, int64_t L
   s = block_sum(s, sh_d);
   const double inv = 1.0 / sqrt(s);
   for (int64_t r = tid; r < L; r += blockDim.x) out[r] = static_cast<T>(out[r] * inv);
-  __threadfence_block();
-  __syncthreads();
 }
 
 template <typename T>
-__global__ __launch_bounds__(CGS_THREADS) void cgs_upd_norm_kernel(
-    const T *__restrict__ Q, int64_t ldq, int64_t L, int j, const T *__restrict__ w1,
-    const T *__restrict__ h, T *__restrict__ out, double *__restrict__ partials,
-    unsigned int *__restrict__ cnt, int mode, FinishArgs fa) {
-  __shared__ T sh_h[CGS_MAXJ];
+__global__ __launch_bounds__(CGS_THREADS) void finish_norm_kernel(const double *__restrict__ npart,
+                                                                 int nparts, int mode, FinishArgs fa,
+                                                                 const T *__restrict__ Q, int64_t ldq,
+                                                                 int64_t L, int j, T *__restrict__ out) {
   __shared__ double sh_d[CGS_THREADS / WAVE];
-  __shared__ int flag;
+  __shared__ T sh_h[CGS_MAXJ];
+  __shared__ int bd;
   const int tid = threadIdx.x;
-  for (int c = tid; c < j; c += CGS_THREADS) sh_h[c] = h[c];
-  __syncthreads();
-  double nrm2 = 0;
-  for (int64_t r = static_cast<int64_t>(blockIdx.x) * CGS_THREADS + tid; r < L;
-       r += static_cast<int64_t>(gridDim.x) * CGS_THREADS) {
-    T u[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) u[i] = 0;
-    int c = 0;
-    for (; c + 8 <= j; c += 8) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) u[i] += Q[(c + i) * ldq + r] * sh_h[c + i];
-    }
-    for (; c < j; ++c) u[0] += Q[c * ldq + r] * sh_h[c];
-    const T x = w1[r] - (((u[0] + u[1]) + (u[2] + u[3])) + ((u[4] + u[5]) + (u[6] + u[7])));
-    out[r] = x;
-    nrm2 += static_cast<double>(x) * static_cast<double>(x);
-  }
-  if (mode == MODE_UPDATE) return;
-  nrm2 = block_sum(nrm2, sh_d);
-  if (tid == 0) partials[blockIdx.x] = nrm2;
-  if (!elect_last_block(cnt, &flag)) return;
-  // ordered sum of the block partials: thread i adds i, i+256, ..., then the
-  // fixed-order block reduction
   double tot = 0;
-  for (int g = tid; g < static_cast<int>(gridDim.x); g += CGS_THREADS) tot += partials[g];
+  for (int g = tid; g < nparts; g += CGS_THREADS) tot += npart[g];
   tot = block_sum(tot, sh_d);
   const double nrm = sqrt(tot);
   if (mode == MODE_NORM) {
@@ -390,7 +331,6 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_upd_norm_kernel(
   }
   // Breakdown: the new vector lies in the span of Q (an invariant subspace was
   // found).  Replace it by a re-orthogonalized random vector, store 0 in T.
-  __shared__ int bd;
   if (tid == 0) {
     bd = *fa.breakdowns + 1;
     *fa.breakdowns = bd;
@@ -408,15 +348,15 @@ inline void cgs_proj_shape(int64_t L, int j, int &nslab, int &ngrp_c) {
   int64_t s = ceil_div(2048, ngrp_c);
   s = std::min<int64_t>(s, ceil_div(tiles, 8));  // >= 8 tiles (2 per wave) per block
   s = std::max<int64_t>(s, 1);
-  s = std::min<int64_t>(s, CGS_MAX_BLOCKS);
+  s = std::min<int64_t>(s, CGS_MAX_SLABS);
   nslab = static_cast<int>(s);
 }
 inline int cgs_updproj_blocks(int64_t L) {
   const int64_t tiles = ceil_div(L, WAVE);
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(tiles, 4))));
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(CGS_MAX_SLABS, ceil_div(tiles, 4))));
 }
 inline int cgs_updnorm_blocks(int64_t L) {
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(8192, ceil_div(L, CGS_THREADS))));
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(NORM_MAX_BLOCKS, ceil_div(L, CGS_THREADS))));
 }
 
 }  // namespace svds

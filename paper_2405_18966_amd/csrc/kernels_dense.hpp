@@ -4,10 +4,10 @@
 // or BF16 and widened exactly in registers; accumulation in the basis type.
 //
 // A x  : 2-D grid of (row tile of 512 rows) x (column slab of 256 columns);
-//        each thread owns 2 rows and walks a quarter of the slab's columns,
-//        waves combine in LDS, the slab partial goes to global memory and the
-//        last slab of each row tile (arrival counter) adds the slab partials
-//        in slab order.  Deterministic.
+//        each lane owns 8 rows and walks a quarter of the slab's columns,
+//        waves combine in LDS, the slab partial goes to global memory, and
+//        gemv_n_fixup_kernel (next launch) adds the slab partials in slab
+//        order.  Deterministic.
 // A^T x: one wave per column (the column is contiguous), lanes stride the
 //        rows with vector loads, fixed-order wave reduction.
 #pragma once
@@ -22,15 +22,11 @@ constexpr int DN_THREADS = 256;
 template <typename TV, typename TB>
 __global__ __launch_bounds__(DN_THREADS) void gemv_n_kernel(
     int64_t m, int64_t n, const TV *__restrict__ A, int64_t lda, const TB *__restrict__ x,
-    const double *__restrict__ xs_ptr, const double *__restrict__ coef_ptr,
-    const TB *__restrict__ yprev, TB *__restrict__ y, TB *__restrict__ partials,
-    unsigned int *__restrict__ counters, TB *__restrict__ side_dst, int64_t side_len) {
+    const double *__restrict__ xs_ptr,
+    TB *__restrict__ partials, TB *__restrict__ side_dst, int64_t side_len) {
   __shared__ TB red[DN_THREADS / WAVE][DN_ROWS];
-  __shared__ int flag;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const TB xs = xs_ptr ? static_cast<TB>(*xs_ptr) : TB(1);
-  const TB coef = coef_ptr ? static_cast<TB>(*coef_ptr) : TB(0);
-  const int64_t nslab = gridDim.y;
   const int64_t bid = static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x;
   if (side_dst) {
     const int64_t nb = static_cast<int64_t>(gridDim.x) * gridDim.y;
@@ -71,23 +67,20 @@ __global__ __launch_bounds__(DN_THREADS) void gemv_n_kernel(
     const int64_t r = rbase + i;
     if (r < m) partials[static_cast<int64_t>(blockIdx.y) * m + r] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned int t = atomicAdd(&counters[blockIdx.x], 1u);
-    flag = (t == static_cast<unsigned int>(nslab - 1));
-  }
-  __syncthreads();
-  if (!flag) return;
-  __threadfence();
-  for (int i = tid; i < DN_ROWS; i += DN_THREADS) {
-    const int64_t r = rbase + i;
-    if (r >= m) continue;
-    TB s = 0;
-    for (int64_t sl = 0; sl < nslab; ++sl) s += partials[sl * m + r];
-    y[r] = xs * s - (yprev ? coef * yprev[r] : TB(0));
-  }
-  if (tid == 0) atomicExch(&counters[blockIdx.x], 0u);
+}
+
+// y[r] = xs * sum_slab partials[slab][r] - coef * yprev[r]
+template <typename TB>
+__global__ void gemv_n_fixup_kernel(int64_t m, int nslab, const TB *__restrict__ partials,
+                                    const double *__restrict__ xs_ptr, const double *__restrict__ coef_ptr,
+                                    const TB *__restrict__ yprev, TB *__restrict__ y) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  const TB xs = xs_ptr ? static_cast<TB>(*xs_ptr) : TB(1);
+  const TB coef = coef_ptr ? static_cast<TB>(*coef_ptr) : TB(0);
+  TB s = 0;
+  for (int sl = 0; sl < nslab; ++sl) s += partials[static_cast<int64_t>(sl) * m + r];
+  y[r] = xs * s - (yprev ? coef * yprev[r] : TB(0));
 }
 
 template <typename TV, typename TB>
@@ -119,8 +112,7 @@ __global__ __launch_bounds__(DN_THREADS) void gemv_t_kernel(
   if (lane == 0) y[c] = xs * s - (yprev ? coef * yprev[c] : TB(0));
 }
 
-// scratch of the A x kernel: partials (slabs x m of TB <= 8 bytes), counters
+// scratch of the A x kernel: partials (slabs x m of TB <= 8 bytes)
 inline int64_t dense_partial_doubles(int64_t m, int64_t n) { return ceil_div(n, DN_SLAB) * m; }
-inline int64_t dense_counter_count(int64_t m) { return ceil_div(m, DN_ROWS); }
 
 }  // namespace svds

@@ -139,27 +139,27 @@ static __global__ __launch_bounds__(256) void signfix_kernel(int64_t m, int64_t 
   }
 }
 
-// out[idx] = |x|_2 with x of length L (FP64 accumulation), for the explicit
-// residuals.  Multi-block with last-block reduction.
+// |x|_2 of a length-L vector (FP64 accumulation) for the explicit residuals:
+// block partials, then one block adds them in block order.
 template <typename T>
-static __global__ __launch_bounds__(256) void norm_kernel(int64_t L, const T *__restrict__ x,
-                                                  double *__restrict__ partials,
-                                                  unsigned int *__restrict__ counter,
-                                                  double *__restrict__ out) {
+static __global__ __launch_bounds__(256) void norm_partials_kernel(int64_t L, const T *__restrict__ x,
+                                                                  double *__restrict__ partials) {
   __shared__ double sh[256 / WAVE];
-  __shared__ int flag;
   double s = 0;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < L;
        i += static_cast<int64_t>(gridDim.x) * 256)
     s += static_cast<double>(x[i]) * static_cast<double>(x[i]);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  if (!elect_last_block(counter, &flag)) return;
-  if (threadIdx.x == 0) {
-    double t = 0;
-    for (int g = 0; g < static_cast<int>(gridDim.x); ++g) t += partials[g];
-    *out = sqrt(t);
-  }
+}
+
+static __global__ __launch_bounds__(256) void norm_finish_kernel(const double *__restrict__ partials,
+                                                                int n, double *__restrict__ out) {
+  __shared__ double sh[256 / WAVE];
+  double s = 0;
+  for (int g = threadIdx.x; g < n; g += 256) s += partials[g];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) *out = sqrt(s);
 }
 
 }  // namespace svds

@@ -10,10 +10,10 @@
 //    in LDS with coalesced loads, then reduces each row from LDS, one thread
 //    per row (short rows) or one wave per row (long rows).
 //  * PIECE item: a slice of SPMV_PIECE nonzeros of a row longer than
-//    SPMV_NNZ_BLK.  The block writes its partial sum; the last piece of the
-//    row to finish (per-row arrival counter) adds the partials in piece
-//    order and writes y.  Power-law rows (e.g. the heaviest columns of a Zipf
-//    matrix seen through A^T) are spread over many blocks this way.
+//    SPMV_NNZ_BLK; the block writes its partial sum, and
+//    spmv_longrow_fixup_kernel (next launch) adds the partials of each long
+//    row in piece order and writes y.  Power-law rows (the heaviest columns of
+//    a Zipf matrix seen through A^T) are spread over many blocks this way.
 //  * Optional side task: dst[i] = src[i] * xs for i < side_len, spread over
 //    the grid.  The solver uses it to write the normalized previous Lanczos
 //    vector into its basis column while the product consumes the
@@ -36,15 +36,12 @@ struct LongRow {
 
 template <typename TV, typename TB>
 __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
-    const int4 *__restrict__ items, const LongRow *__restrict__ longrows,
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const int4 *__restrict__ items, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const TV *__restrict__ val, const TB *__restrict__ x, const double *__restrict__ xs_ptr,
     const double *__restrict__ coef_ptr, const TB *__restrict__ yprev, TB *__restrict__ y,
-    TB *__restrict__ partials, unsigned int *__restrict__ counters,
-    TB *__restrict__ side_dst, int64_t side_len) {
+    TB *__restrict__ partials, TB *__restrict__ side_dst, int64_t side_len) {
   __shared__ TB prod[SPMV_NNZ_BLK];
   __shared__ TB red[SPMV_THREADS / WAVE];
-  __shared__ int flag;
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1);
   const int wv = tid / WAVE;
@@ -88,7 +85,6 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
       }
     }
   } else {
-    const int lr = -it.x - 1;
     const int z0 = it.z, z1 = it.w;
     TB s = 0;
     for (int z = z0 + tid; z < z1; z += SPMV_THREADS) s += widen<TB>(val[z]) * x[col[z]];
@@ -99,21 +95,25 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
       TB t = 0;
       for (int i = 0; i < SPMV_THREADS / WAVE; ++i) t += red[i];
       partials[it.y] = t;
-      __threadfence();
-      const LongRow L = longrows[lr];
-      const unsigned int ticket = atomicAdd(&counters[lr], 1u);
-      flag = (ticket == static_cast<unsigned int>(L.npieces - 1));
-    }
-    __syncthreads();
-    if (flag && tid == 0) {
-      __threadfence();
-      const LongRow L = longrows[lr];
-      TB t = 0;
-      for (int q = 0; q < L.npieces; ++q) t += partials[L.first_piece + q];
-      y[L.row] = xs * t - (yprev ? coef * yprev[L.row] : TB(0));
-      atomicExch(&counters[lr], 0u);
     }
   }
+}
+
+// y[row] = xs * (sum of the row's piece partials, in piece order) - coef * yprev[row]
+template <typename TB>
+__global__ void spmv_longrow_fixup_kernel(const LongRow *__restrict__ longrows, int nlong,
+                                          const TB *__restrict__ partials,
+                                          const double *__restrict__ xs_ptr,
+                                          const double *__restrict__ coef_ptr,
+                                          const TB *__restrict__ yprev, TB *__restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nlong) return;
+  const TB xs = xs_ptr ? static_cast<TB>(*xs_ptr) : TB(1);
+  const TB coef = coef_ptr ? static_cast<TB>(*coef_ptr) : TB(0);
+  const LongRow L = longrows[i];
+  TB t = 0;
+  for (int q = 0; q < L.npieces; ++q) t += partials[L.first_piece + q];
+  y[L.row] = xs * t - (yprev ? coef * yprev[L.row] : TB(0));
 }
 
 }  // namespace svds

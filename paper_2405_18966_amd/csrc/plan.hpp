@@ -34,7 +34,6 @@ struct SpmvPlan {
   int4 *items = nullptr;
   LongRow *longrows = nullptr;
   double *partials = nullptr;  // npieces (TB <= 8 bytes)
-  unsigned int *counters = nullptr;
   std::vector<int4> h_items;
   std::vector<LongRow> h_long;
 };
@@ -86,7 +85,6 @@ struct Operator {
   const void *a = nullptr;
   int64_t lda = 0;
   double *dpart = nullptr;        // slab partials of A x
-  unsigned int *dcnt = nullptr;   // row-tile arrival counters
 };
 
 }  // namespace svds

@@ -137,7 +137,7 @@ template <typename TB> struct Lanczos {
   int cur = 0;
   TB *wu = nullptr, *w1u = nullptr, *bu = nullptr;
   TB *wv = nullptr, *w1v = nullptr, *bv = nullptr;
-  TB *h1 = nullptr, *h2 = nullptr, *partials = nullptr, *part2 = nullptr;
+  TB *h1 = nullptr, *h2 = nullptr, *partials = nullptr;
   void carve(Arena &a, int64_t m_, int64_t n_, int p) {
     m = m_;
     n = n_;
@@ -155,8 +155,7 @@ template <typename TB> struct Lanczos {
     bv = a.take<TB>(n);
     h1 = a.take<TB>(CGS_MAXJ);
     h2 = a.take<TB>(CGS_MAXJ);
-    partials = a.take<TB>(static_cast<size_t>(CGS_MAXJ) * GMAX);
-    part2 = a.take<TB>(static_cast<size_t>(CGS_MAXJ) * CGS_CNT_STRIDE);
+    partials = a.take<TB>(static_cast<size_t>(CGS_MAXJ) * CGS_MAX_SLABS);
   }
 };
 
@@ -164,17 +163,10 @@ template <typename TB> struct Lanczos {
 struct Small {
   double *T, *xs_u, *xs_v, *one, *sigma_est, *rho, *sig, *res, *Uk, *Vext, *jac, *npart;
   double *resid_av, *resid_atu;
-  unsigned int *cnt;  // arrival counters, offsets CNT_*
   int *bd, *flags;
 };
 
-// offsets into Small::cnt
-constexpr int CNT_PROJ = 0;
-constexpr int CNT_UPDPROJ = CGS_CNT_WORDS;
-constexpr int CNT_UPDNORM = CNT_UPDPROJ + CGS_CNT_STRIDE;
-constexpr int CNT_NORM = CNT_UPDNORM + 1;
-constexpr int CNT_WORDS = CNT_NORM + 1;
-constexpr int NPART = 8192;  // norm partials (cgs_upd_norm blocks <= 8192)
+constexpr int NPART = NORM_MAX_BLOCKS;  // norm partials
 
 }  // namespace svds
 
@@ -218,9 +210,12 @@ static void dense_launch(svds_plan *P, bool trans, const TB *x, const double *xs
                        dim3(DN_THREADS), 0, P->stream, op.m, op.n, A, op.lda, x, xs, coef, yprev, y,
                        side_dst, side_len);
   } else {
-    hipLaunchKernelGGL((gemv_n_kernel<TV, TB>), dim3(ceil_div(op.m, DN_ROWS), ceil_div(op.n, DN_SLAB)),
-                       dim3(DN_THREADS), 0, P->stream, op.m, op.n, A, op.lda, x, xs, coef, yprev, y,
-                       reinterpret_cast<TB *>(op.dpart), op.dcnt, side_dst, side_len);
+    const int nslab = static_cast<int>(ceil_div(op.n, DN_SLAB));
+    TB *part = reinterpret_cast<TB *>(op.dpart);
+    hipLaunchKernelGGL((gemv_n_kernel<TV, TB>), dim3(ceil_div(op.m, DN_ROWS), nslab), dim3(DN_THREADS), 0,
+                       P->stream, op.m, op.n, A, op.lda, x, xs, part, side_dst, side_len);
+    hipLaunchKernelGGL((gemv_n_fixup_kernel<TB>), dim3(ceil_div(op.m, 256)), dim3(256), 0, P->stream,
+                       op.m, nslab, part, xs, coef, yprev, y);
   }
 }
 
@@ -247,14 +242,15 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     TB *parts = reinterpret_cast<TB *>(sp.partials);
     if (op.vt == SVDS_F64)
       hipLaunchKernelGGL((spmv_csr_kernel<double, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-                         P->stream, sp.items, sp.longrows, rp, ci,
-                         static_cast<const double *>(val), x, xs, coef, yprev, y, parts,
-                         sp.counters, side_dst, side_len);
+                         P->stream, sp.items, rp, ci, static_cast<const double *>(val), x, xs, coef,
+                         yprev, y, parts, side_dst, side_len);
     else
       hipLaunchKernelGGL((spmv_csr_kernel<float, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-                         P->stream, sp.items, sp.longrows, rp, ci,
-                         static_cast<const float *>(val), x, xs, coef, yprev, y, parts,
-                         sp.counters, side_dst, side_len);
+                         P->stream, sp.items, rp, ci, static_cast<const float *>(val), x, xs, coef,
+                         yprev, y, parts, side_dst, side_len);
+    if (sp.nlong > 0)
+      hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(ceil_div(sp.nlong, 64)), dim3(64), 0,
+                         P->stream, sp.longrows, sp.nlong, parts, xs, coef, yprev, y);
     LAUNCH_CHECK();
     bytes = 4.0 * (rows + 1) + (4.0 + vsize(op.vt)) * op.nnz + sb * cols +
             (yprev ? 2.0 : 1.0) * sb * rows;
@@ -283,25 +279,41 @@ static int cgs2_finish(svds_plan *P, Lanczos<TB> &Lz, const TB *Q, int64_t ldq, 
     cgs_proj_shape(L, j, nslab, ngc);
     ACC_BEFORE(SVDS_KC_CGS_PROJ);
     hipLaunchKernelGGL((cgs_proj_kernel<TB>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q,
-                       ldq, L, j, w, Lz.partials, Lz.part2, Lz.h1, s.cnt + CNT_PROJ);
+                       ldq, L, j, w, Lz.partials);
     LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_CGS_PROJ, sb * L * j + sb * L, 2.0 * L * j);
+    ACC_BEFORE(SVDS_KC_CGS_REDUCE);
+    hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j, 4)), dim3(256), 0, P->stream,
+                       Lz.partials, static_cast<int64_t>(nslab), nslab, j, Lz.h1);
+    LAUNCH_CHECK();
+    ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * j * nslab, 0.0);
 
     const int nw = std::max(1, std::min(16, static_cast<int>(ceil_div(j, CGS_CPW))));
+    const int nb = cgs_updproj_blocks(L);
     ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
-    hipLaunchKernelGGL((cgs_upd_proj_kernel<TB>), dim3(cgs_updproj_blocks(L)), dim3(nw * WAVE), 0,
-                       P->stream, Q, ldq, L, j, w, Lz.h1, w1, Lz.partials, Lz.part2, Lz.h2,
-                       s.cnt + CNT_UPDPROJ);
+    hipLaunchKernelGGL((cgs_upd_proj_kernel<TB>), dim3(nb), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j,
+                       w, Lz.h1, w1, Lz.partials);
     LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 4.0 * L * j);
+    ACC_BEFORE(SVDS_KC_CGS_REDUCE);
+    hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j, 4)), dim3(256), 0, P->stream,
+                       Lz.partials, static_cast<int64_t>(nb), nb, j, Lz.h2);
+    LAUNCH_CHECK();
+    ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * j * nb, 0.0);
     src = w1;
   }
-  FinishArgs fa{t_entry, xs, s.sigma_est, s.bd, P->opts.seed};
+  const int nn = cgs_updnorm_blocks(L);
   ACC_BEFORE(SVDS_KC_CGS_UPDNORM);
-  hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
-                     P->stream, Q, ldq, L, j, src, Lz.h2, out, s.npart, s.cnt + CNT_UPDNORM, mode, fa);
+  hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
+                     src, Lz.h2, out, s.npart);
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * j + 2 * sb * L, 2.0 * L * j + 2.0 * L);
+  FinishArgs fa{t_entry, xs, s.sigma_est, s.bd, P->opts.seed};
+  ACC_BEFORE(SVDS_KC_CGS_REDUCE);
+  hipLaunchKernelGGL((finish_norm_kernel<TB>), dim3(1), dim3(CGS_THREADS), 0, P->stream, s.npart, nn,
+                     mode, fa, Q, ldq, L, j, out);
+  LAUNCH_CHECK();
+  ACC_AFTER(SVDS_KC_CGS_REDUCE, 8.0 * nn, 0.0);
   return SVDS_OK;
 }
 
@@ -310,11 +322,9 @@ template <typename TB>
 static int gemv_update(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, int j, const TB *w,
                        const TB *h, TB *out) {
   const double sb = sizeof(TB);
-  FinishArgs fa{nullptr, nullptr, nullptr, nullptr, 0};
   ACC_BEFORE(SVDS_KC_OTHER);
   hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
-                     P->stream, Q, ldq, L, j, w, h, out, P->sc.npart, P->sc.cnt + CNT_UPDNORM,
-                     static_cast<int>(MODE_UPDATE), fa);
+                     P->stream, Q, ldq, L, j, w, h, out, static_cast<double *>(nullptr));
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_OTHER, sb * L * j + 2 * sb * L, 2.0 * L * j);
   return SVDS_OK;
@@ -530,7 +540,6 @@ static int carve_all(svds_plan *P, Arena &a) {
   s.npart = a.take<double>(NPART);
   s.resid_av = a.take<double>(k);
   s.resid_atu = a.take<double>(k);
-  s.cnt = a.take<unsigned int>(CNT_WORDS);
   s.bd = a.take<int>(4);
   s.flags = a.take<int>(4);
   P->tmp_m = a.take<double>(m);
@@ -538,14 +547,11 @@ static int carve_all(svds_plan *P, Arena &a) {
   if (P->mixed) P->tmp_nk = a.take<double>(static_cast<size_t>(n) * k);
   if (P->op.dense) {
     P->op.dpart = a.take<double>(dense_partial_doubles(m, n));
-    P->op.dcnt = a.take<unsigned int>(dense_counter_count(m));
   } else {
     P->op.fwd.partials = a.take<double>(std::max(1, P->op.fwd.npieces));
-    P->op.fwd.counters = a.take<unsigned int>(std::max(1, P->op.fwd.nlong));
     P->op.fwd.items = a.take<int4>(P->op.fwd.nitems);
     P->op.fwd.longrows = a.take<LongRow>(std::max(1, P->op.fwd.nlong));
     P->op.bwd.partials = a.take<double>(std::max(1, P->op.bwd.npieces));
-    P->op.bwd.counters = a.take<unsigned int>(std::max(1, P->op.bwd.nlong));
     P->op.bwd.items = a.take<int4>(P->op.bwd.nitems);
     P->op.bwd.longrows = a.take<LongRow>(std::max(1, P->op.bwd.nlong));
     P->op.trp = a.take<int32_t>(n + 1);
@@ -573,9 +579,6 @@ static int alloc_arena(svds_plan *P) {
   HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&P->h_flags), 16 * sizeof(int), hipHostMallocDefault));
   const double one = 1.0;
   HIP_TRY(hipMemcpyAsync(P->sc.one, &one, sizeof one, hipMemcpyHostToDevice, P->stream));
-  HIP_TRY(hipMemsetAsync(P->sc.cnt, 0, CNT_WORDS * sizeof(unsigned int), P->stream));
-  if (P->op.dense)
-    HIP_TRY(hipMemsetAsync(P->op.dcnt, 0, sizeof(unsigned int) * dense_counter_count(P->op.m), P->stream));
   return SVDS_OK;
 }
 
@@ -640,7 +643,6 @@ static int upload_spmv(svds_plan *P, SpmvPlan &sp) {
   if (sp.nlong) {
     HIP_TRY(hipMemcpyAsync(sp.longrows, sp.h_long.data(), sizeof(LongRow) * sp.nlong,
                            hipMemcpyHostToDevice, P->stream));
-    HIP_TRY(hipMemsetAsync(sp.counters, 0, sizeof(unsigned int) * sp.nlong, P->stream));
   }
   HIP_TRY(hipStreamSynchronize(P->stream));
   return SVDS_OK;
@@ -706,14 +708,12 @@ extern "C" int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, sv
   int4 *bi = op.bwd.items;
   LongRow *bl = op.bwd.longrows;
   double *bp = op.bwd.partials;
-  unsigned int *bc = op.bwd.counters;
   build_spmv_items(htrp.data(), A->n, op.bwd);
   if (op.bwd.nitems > bwd_items_cap || op.bwd.nlong > bwd_long_cap || op.bwd.npieces > bwd_pieces_cap)
     return SVDS_EDEVICE;
   op.bwd.items = bi;
   op.bwd.longrows = bl;
   op.bwd.partials = bp;
-  op.bwd.counters = bc;
   if ((rc = upload_spmv(P, op.fwd)) || (rc = upload_spmv(P, op.bwd))) return rc;
   *plan = guard.release();
   return SVDS_OK;
@@ -868,7 +868,8 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
     info->max_res_av = res_av;
     info->ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
     double ba = 0;
-    for (int c : {SVDS_KC_SPMV, SVDS_KC_SPMVT, SVDS_KC_CGS_PROJ, SVDS_KC_CGS_UPDPROJ, SVDS_KC_CGS_UPDNORM})
+    for (int c : {SVDS_KC_SPMV, SVDS_KC_SPMVT, SVDS_KC_CGS_PROJ, SVDS_KC_CGS_UPDPROJ, SVDS_KC_CGS_UPDNORM,
+                  SVDS_KC_CGS_REDUCE})
       ba += P->acc.bytes[c];
     info->bytes_alg = ba;
     for (int c = 0; c < SVDS_KC_COUNT; ++c) {
@@ -895,14 +896,18 @@ static int residuals_impl(svds_plan *P, int k, const double *U, const double *S,
     int rc = matvec<double>(P, false, V + j * n, P->sc.one, S + j, U + j * m, P->tmp_m, nullptr, 0,
                             SVDS_KC_OTHER);
     if (rc) return rc;
-    hipLaunchKernelGGL((norm_kernel<double>), dim3(grid_for(m, 4096)), dim3(256), 0, P->stream, m,
-                       P->tmp_m, P->sc.npart, P->sc.cnt + CNT_NORM, res_av + j);
+    hipLaunchKernelGGL((norm_partials_kernel<double>), dim3(grid_for(m, 4096)), dim3(256), 0, P->stream, m,
+                       P->tmp_m, P->sc.npart);
+    hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(256), 0, P->stream, P->sc.npart,
+                       static_cast<int>(grid_for(m, 4096)), res_av + j);
     LAUNCH_CHECK();
     rc = matvec<double>(P, true, U + j * m, P->sc.one, S + j, V + j * n, P->tmp_n, nullptr, 0,
                         SVDS_KC_OTHER);
     if (rc) return rc;
-    hipLaunchKernelGGL((norm_kernel<double>), dim3(grid_for(n, 4096)), dim3(256), 0, P->stream, n,
-                       P->tmp_n, P->sc.npart, P->sc.cnt + CNT_NORM, res_atu + j);
+    hipLaunchKernelGGL((norm_partials_kernel<double>), dim3(grid_for(n, 4096)), dim3(256), 0, P->stream, n,
+                       P->tmp_n, P->sc.npart);
+    hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(256), 0, P->stream, P->sc.npart,
+                       static_cast<int>(grid_for(n, 4096)), res_atu + j);
     LAUNCH_CHECK();
   }
   // residual products are not Lanczos steps (booked under OTHER, not counted)
