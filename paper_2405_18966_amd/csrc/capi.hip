@@ -123,7 +123,7 @@ extern "C" int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *
                        static_cast<const TB *>(x), x_scale, coef, static_cast<const TB *>(yprev),   \
                        static_cast<TB *>(y), reinterpret_cast<TB *>(parts), nullptr, 0);             \
     if (sp.nlong)                                                                                   \
-      hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(ceil_div(sp.nlong, 64)), dim3(64), 0, \
+      hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(sp.nlong), dim3(WAVE), 0, \
                          st, lr, sp.nlong, reinterpret_cast<TB *>(parts), x_scale, coef,            \
                          static_cast<const TB *>(yprev), static_cast<TB *>(y));                     \
   } while (0)
@@ -175,63 +175,7 @@ extern "C" int svds_op_cgs2(int64_t L, int32_t j, const void *Q, int64_t ldq, co
                             double *norm_out, int32_t dtype, void *stream) {
   if (L < 1 || j < 0 || j > CGS_MAXJ || (j > 0 && (!Q || ldq < L)) || !w || !out) return SVDS_EINVAL;
   if (dtype != SVDS_F64 && dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t tb = dtype == SVDS_F64 ? 8 : 4;
-  // scratch: partials, h1, h2, w1, norm partials, scalars
-  const size_t n_parts = static_cast<size_t>(CGS_MAXJ) * CGS_MAX_SLABS;
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t o = off;
-    off += (bytes + 255) & ~size_t(255);
-    return o;
-  };
-  const size_t o_parts = take(tb * n_parts), o_h1 = take(tb * CGS_MAXJ), o_h2 = take(tb * CGS_MAXJ),
-               o_w1 = take(tb * L), o_np = take(8 * NORM_MAX_BLOCKS), o_dx = take(8 * 8), o_bd = take(16);
-  Scratch s;
-  HIP_TRY(hipMalloc(&s.p, off));
-  HIP_TRY(hipMemsetAsync(s.p, 0, off, st));
-  char *b = static_cast<char *>(s.p);
-  void *parts = b + o_parts, *h1 = b + o_h1, *h2 = b + o_h2, *w1 = b + o_w1;
-  double *npart = reinterpret_cast<double *>(b + o_np);
-  double *dx = reinterpret_cast<double *>(b + o_dx);  // xs, t_entry, sigma_est
-  int *bd = reinterpret_cast<int *>(b + o_bd);
-  const int nw = std::max(1, std::min(16, static_cast<int>(ceil_div(std::max(j, 1), CGS_CPW))));
-  FinishArgs fa{dx + 1, dx, dx + 2, bd, 0};
-  int nslab = 1, ngc = 1;
-  if (j > 0) cgs_proj_shape(L, j, nslab, ngc);
-  const int nb = cgs_updproj_blocks(L), nn = cgs_updnorm_blocks(L);
-#define CGS_GO(T)                                                                                    \
-  do {                                                                                               \
-    const T *src = static_cast<const T *>(w);                                                        \
-    T *pp = static_cast<T *>(parts);                                                                 \
-    if (j > 0) {                                                                                     \
-      hipLaunchKernelGGL((cgs_proj_kernel<T>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, st,           \
-                         static_cast<const T *>(Q), ldq, L, j, src, pp);                             \
-      hipLaunchKernelGGL((reduce_cols_kernel<T>), dim3(ceil_div(j, 4)), dim3(256), 0, st, pp,        \
-                         static_cast<int64_t>(nslab), nslab, j, static_cast<T *>(h1));               \
-      hipLaunchKernelGGL((cgs_upd_proj_kernel<T>), dim3(nb), dim3(nw * WAVE), 0, st,                 \
-                         static_cast<const T *>(Q), ldq, L, j, src, static_cast<T *>(h1),            \
-                         static_cast<T *>(w1), pp);                                                  \
-      hipLaunchKernelGGL((reduce_cols_kernel<T>), dim3(ceil_div(j, 4)), dim3(256), 0, st, pp,        \
-                         static_cast<int64_t>(nb), nb, j, static_cast<T *>(h2));                     \
-      src = static_cast<const T *>(w1);                                                              \
-    }                                                                                                \
-    hipLaunchKernelGGL((cgs_upd_norm_kernel<T>), dim3(nn), dim3(CGS_THREADS), 0, st,                 \
-                       static_cast<const T *>(Q), ldq, L, j, src, static_cast<T *>(h2),              \
-                       static_cast<T *>(out), npart);                                                \
-    hipLaunchKernelGGL((finish_norm_kernel<T>), dim3(1), dim3(CGS_THREADS), 0, st, npart, nn,        \
-                       static_cast<int>(MODE_NORM), fa, static_cast<const T *>(Q), ldq, L, j,        \
-                       static_cast<T *>(out));                                                       \
-  } while (0)
-  if (dtype == SVDS_F64) CGS_GO(double);
-  else CGS_GO(float);
-#undef CGS_GO
-  HIP_TRY(hipGetLastError());
-  double xs = 0;
-  HIP_TRY(hipMemcpyAsync(&xs, dx, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  if (norm_out) *norm_out = 1.0 / xs;
-  return SVDS_OK;
+  return svds_cgs2_op(L, j, Q, ldq, w, out, norm_out, dtype, stream);
 }
 
 extern "C" int svds_op_small_svd(int32_t p, int32_t k, double tol, double *T, double *Uk, double *Vext,

@@ -20,8 +20,8 @@
 namespace svds {
 
 constexpr int CGS_THREADS = 256;
-constexpr int CGS_PCG = 32;     // columns per block column-group in cgs_proj
-constexpr int CGS_CPW = 16;     // columns per wave in cgs_upd_proj
+constexpr int CGS_PCG = 8;      // columns per block column-group in cgs_proj
+constexpr int CGS_FUSED_MAXJ = 160;  // widest basis of the fused pass (16 waves x 10 columns)
 constexpr int CGS_MAXJ = 1024;  // largest basis width supported
 constexpr int CGS_MAX_SLABS = 1024;  // partials per column (cgs_proj / cgs_upd_proj)
 constexpr int NORM_MAX_BLOCKS = 2048;
@@ -43,9 +43,10 @@ __global__ __launch_bounds__(256) void reduce_cols_kernel(const T *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Pass 1: partials of h = Q^T w.  Grid (row slabs, column groups of 32).
-// Each wave walks 64-row tiles of its block's slab keeping 32 column
-// accumulators per lane.  part: [j][nslab].
+// Pass 1: partials of h = Q^T w.  Grid (row slabs, column groups of 8).
+// Each wave walks 64-row tiles of its block's slab keeping 8 column
+// accumulators per lane (narrow groups and many blocks stream at ~5 TB/s on
+// MI355X; 32-column groups reach half that).  part: [j][nslab].
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restrict__ Q, int64_t ldq,
@@ -99,15 +100,16 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restri
 
 // ---------------------------------------------------------------------------
 // Pass 2 fused with the update of pass 1: w1 = w - Q h1 (written out) and
-// partials of h2 = Q^T w1.  Block = NW = ceil(j/16) waves (<= 16, so
-// j <= 256); a block walks 64-row tiles; wave v holds columns [16v, 16v+16)
-// of the tile in registers, so Q is read once for both the update and the
-// projection.  The next tile is loaded before the current one is consumed,
-// and the cross-wave sums go through a double-buffered LDS array (one
-// barrier per tile).  Wider bases (j > 256) take a generic two-sweep path.
+// partials of h2 = Q^T w1.  Block = ceil(j/CPW) waves (<= 16); a block walks
+// 64-row tiles; wave v holds columns [CPW v, CPW v + CPW) of the tile in
+// registers, so Q is read once for both the update and the projection.  The
+// cross-wave row sums go through a double-buffered LDS array (one barrier per
+// tile).  Narrow register tiles (CPW <= 10) keep occupancy high: measured on
+// MI355X, 8-10 columns per wave stream at 4-5 TB/s, 12-16 at half that.
+// Bases wider than 16 * CPW use a separate update pass plus cgs_proj instead.
 // part: [j][nblk].
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int CPW, bool PF>
 __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict__ Q, int64_t ldq,
                                                            int64_t L, int j, const T *__restrict__ w,
                                                            const T *__restrict__ h1,
@@ -118,100 +120,55 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict_
   const int NW = blockDim.x / WAVE;
   const int nblk = gridDim.x, blk = blockIdx.x;
   for (int c = tid; c < j; c += blockDim.x) sh_h[c] = h1[c];
+  const int c0 = wv * CPW;
+  const int nc = max(0, min(CPW, j - c0));
+  for (int c = j + tid; c < NW * CPW; c += blockDim.x) sh_h[c] = T(0);  // padding columns
   __syncthreads();
   const int64_t tiles = ceil_div(L, WAVE);
   const int64_t per = ceil_div(tiles, nblk);
   const int64_t t0 = static_cast<int64_t>(blk) * per;
   const int64_t t1 = min(tiles, t0 + per);
-  if (j <= NW * CGS_CPW) {
-    const int c0 = wv * CGS_CPW;
-    const int nc = max(0, min(CGS_CPW, j - c0));
-    const T *Qc = Q + c0 * ldq;
-    T hc[CGS_CPW];
+  const T *Qc = Q + c0 * ldq;
+  T acc[CPW], q[CPW], qn[CPW];
+  T wn = 0;
 #pragma unroll
-    for (int c = 0; c < CGS_CPW; ++c) hc[c] = c < nc ? sh_h[c0 + c] : T(0);
-    T acc[CGS_CPW], q[CGS_CPW], qn[CGS_CPW];
+  for (int c = 0; c < CPW; ++c) acc[c] = 0, qn[c] = 0;
+  auto load = [&](int64_t t) {
+    const int64_t r = t * WAVE + lane;
+    if (r < L) {
 #pragma unroll
-    for (int c = 0; c < CGS_CPW; ++c) acc[c] = 0, qn[c] = 0;
-    T wn = 0;
-    if (t0 < t1) {  // prefetch the first tile
-      const int64_t r = t0 * WAVE + lane;
-      if (r < L) {
-#pragma unroll
-        for (int c = 0; c < CGS_CPW; ++c)
-          if (c < nc) qn[c] = Qc[c * ldq + r];
-        wn = w[r];
-      }
+      for (int c = 0; c < CPW; ++c)
+        if (c < nc) qn[c] = Qc[c * ldq + r];
+      wn = w[r];
     }
-    int buf = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-      const int64_t r = t * WAVE + lane;
-      const bool valid = r < L;
-      const T wr = wn;
+  };
+  if (PF && t0 < t1) load(t0);
+  int buf = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t r = t * WAVE + lane;
+    if (!PF) load(t);
+    const T wr = wn;
 #pragma unroll
-      for (int c = 0; c < CGS_CPW; ++c) q[c] = qn[c];
-      if (t + 1 < t1) {
-        const int64_t rn = r + WAVE;
-        if (rn < L) {
+    for (int c = 0; c < CPW; ++c) q[c] = qn[c];
+    if (PF && t + 1 < t1) load(t + 1);
+    T s = 0;
 #pragma unroll
-          for (int c = 0; c < CGS_CPW; ++c)
-            if (c < nc) qn[c] = Qc[c * ldq + rn];
-          wn = w[rn];
-        }
-      }
-      T s = 0;
-#pragma unroll
-      for (int c = 0; c < CGS_CPW; ++c) s += q[c] * hc[c];
-      xch[buf][wv][lane] = s;
-      __syncthreads();
-      T u = 0;
-      for (int v = 0; v < NW; ++v) u += xch[buf][v][lane];
-      const T w1 = valid ? wr - u : T(0);
-      if (wv == 0 && valid) w1out[r] = w1;
-#pragma unroll
-      for (int c = 0; c < CGS_CPW; ++c) acc[c] += q[c] * w1;
-      buf ^= 1;
-    }
-#pragma unroll
-    for (int c = 0; c < CGS_CPW; ++c) {
-      const T s = wave_sum(acc[c]);
-      if (lane == 0 && c < nc) part[static_cast<int64_t>(c0 + c) * nblk + blk] = s;
-    }
-  } else {
-    // generic path: thread-per-row update, then column-chunked projection
-    const int64_t r0 = t0 * WAVE, r1 = min(L, t1 * WAVE);
-    for (int64_t r = r0 + tid; r < r1; r += blockDim.x) {
-      T u = 0;
-      for (int c = 0; c < j; ++c) u += Q[c * ldq + r] * sh_h[c];
-      w1out[r] = w[r] - u;
-    }
-    __threadfence_block();
+    for (int c = 0; c < CPW; ++c) s += q[c] * sh_h[c0 + c];
+    xch[buf][wv][lane] = s;
     __syncthreads();
-    T *red = &xch[0][0][0];
-    for (int c0 = 0; c0 < j; c0 += 8) {
-      const int nc = min(8, j - c0);
-      T acc[8];
+    T u = 0;
+    for (int v = 0; v < NW; ++v) u += xch[buf][v][lane];
+    const bool valid = r < L;
+    const T w1 = valid ? wr - u : T(0);
+    if (wv == 0 && valid) w1out[r] = w1;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c] = 0;
-      for (int64_t r = r0 + tid; r < r1; r += blockDim.x) {
-        const T x = w1out[r];
+    for (int c = 0; c < CPW; ++c) acc[c] += q[c] * w1;
+    buf ^= 1;
+  }
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-          if (c < nc) acc[c] += Q[(c0 + c) * ldq + r] * x;
-      }
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const T s = wave_sum(acc[c]);
-        if (lane == 0) red[wv * 8 + c] = s;
-      }
-      __syncthreads();
-      if (tid < nc) {
-        T s = 0;
-        for (int v = 0; v < NW; ++v) s += red[v * 8 + tid];
-        part[static_cast<int64_t>(c0 + tid) * nblk + blk] = s;
-      }
-      __syncthreads();
-    }
+  for (int c = 0; c < CPW; ++c) {
+    const T s = wave_sum(acc[c]);
+    if (lane == 0 && c < nc) part[static_cast<int64_t>(c0 + c) * nblk + blk] = s;
   }
 }
 
@@ -343,18 +300,17 @@ __global__ __launch_bounds__(CGS_THREADS) void finish_norm_kernel(const double *
 
 // Launch shapes (host side).
 inline void cgs_proj_shape(int64_t L, int j, int &nslab, int &ngrp_c) {
+  // 8-column groups x row slabs of >= 32 tiles, at most 512 slabs
   ngrp_c = static_cast<int>(ceil_div(j, CGS_PCG));
   const int64_t tiles = ceil_div(L, WAVE);
-  int64_t s = ceil_div(2048, ngrp_c);
-  s = std::min<int64_t>(s, ceil_div(tiles, 8));  // >= 8 tiles (2 per wave) per block
-  s = std::max<int64_t>(s, 1);
-  s = std::min<int64_t>(s, CGS_MAX_SLABS);
-  nslab = static_cast<int>(s);
+  nslab = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(512, tiles / 32)));
 }
 inline int cgs_updproj_blocks(int64_t L) {
   const int64_t tiles = ceil_div(L, WAVE);
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(CGS_MAX_SLABS, ceil_div(tiles, 4))));
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(512, ceil_div(tiles, 4))));
 }
+// columns per wave of the fused pass for a basis of width j (0: use the split path)
+inline int cgs_fused_cpw(int j) { return j <= 128 ? 8 : (j <= CGS_FUSED_MAXJ ? 10 : 0); }
 inline int cgs_updnorm_blocks(int64_t L) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(NORM_MAX_BLOCKS, ceil_div(L, CGS_THREADS))));
 }

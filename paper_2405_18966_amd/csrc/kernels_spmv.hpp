@@ -99,21 +99,24 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
   }
 }
 
-// y[row] = xs * (sum of the row's piece partials, in piece order) - coef * yprev[row]
+// y[row] = xs * (sum of the row's piece partials) - coef * yprev[row]; one
+// wave per long row (lanes take interleaved pieces, fixed-order reduction).
 template <typename TB>
-__global__ void spmv_longrow_fixup_kernel(const LongRow *__restrict__ longrows, int nlong,
-                                          const TB *__restrict__ partials,
-                                          const double *__restrict__ xs_ptr,
-                                          const double *__restrict__ coef_ptr,
-                                          const TB *__restrict__ yprev, TB *__restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(WAVE) void spmv_longrow_fixup_kernel(const LongRow *__restrict__ longrows,
+                                                                  int nlong, const TB *__restrict__ partials,
+                                                                  const double *__restrict__ xs_ptr,
+                                                                  const double *__restrict__ coef_ptr,
+                                                                  const TB *__restrict__ yprev,
+                                                                  TB *__restrict__ y) {
+  const int i = blockIdx.x;
   if (i >= nlong) return;
   const TB xs = xs_ptr ? static_cast<TB>(*xs_ptr) : TB(1);
   const TB coef = coef_ptr ? static_cast<TB>(*coef_ptr) : TB(0);
   const LongRow L = longrows[i];
   TB t = 0;
-  for (int q = 0; q < L.npieces; ++q) t += partials[L.first_piece + q];
-  y[L.row] = xs * t - (yprev ? coef * yprev[L.row] : TB(0));
+  for (int q = threadIdx.x; q < L.npieces; q += WAVE) t += partials[L.first_piece + q];
+  t = wave_sum(t);
+  if (threadIdx.x == 0) y[L.row] = xs * t - (yprev ? coef * yprev[L.row] : TB(0));
 }
 
 }  // namespace svds

@@ -95,3 +95,5 @@ int svds_plan_residuals(svds_plan *P, int k, const double *U, const double *S, c
 int svds_plan_matvec(svds_plan *P, int trans, const void *x, const double *xs, const double *coef,
                      const void *yprev, void *y, int basis_dtype);
 int svds_plan_transpose_copy(svds_plan *P, int32_t *t_row_ptr, int32_t *t_col_idx, void *t_val);
+int svds_cgs2_op(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
+                 double *norm_out, int32_t dtype, void *stream);

@@ -249,7 +249,7 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
                          P->stream, sp.items, rp, ci, static_cast<const float *>(val), x, xs, coef,
                          yprev, y, parts, side_dst, side_len);
     if (sp.nlong > 0)
-      hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(ceil_div(sp.nlong, 64)), dim3(64), 0,
+      hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(sp.nlong), dim3(WAVE), 0,
                          P->stream, sp.longrows, sp.nlong, parts, xs, coef, yprev, y);
     LAUNCH_CHECK();
     bytes = 4.0 * (rows + 1) + (4.0 + vsize(op.vt)) * op.nnz + sb * cols +
@@ -269,43 +269,69 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
 // w is the input; w1 is scratch; out receives the re-orthogonalized vector.
 // ---------------------------------------------------------------------------
 template <typename TB>
-static int cgs2_finish(svds_plan *P, Lanczos<TB> &Lz, const TB *Q, int64_t ldq, int64_t L, int j,
+static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int64_t L, int j,
+                           const TB *w, TB *h, int kc) {
+  const double sb = sizeof(TB);
+  int nslab, ngc;
+  cgs_proj_shape(L, j, nslab, ngc);
+  ACC_BEFORE(kc);
+  hipLaunchKernelGGL((cgs_proj_kernel<TB>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
+                     L, j, w, part);
+  LAUNCH_CHECK();
+  ACC_AFTER(kc, sb * L * j + sb * L, 2.0 * L * j);
+  ACC_BEFORE(SVDS_KC_CGS_REDUCE);
+  hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j, 4)), dim3(256), 0, P->stream, part,
+                     static_cast<int64_t>(nslab), nslab, j, h);
+  LAUNCH_CHECK();
+  ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * j * nslab, 0.0);
+  return SVDS_OK;
+}
+
+template <typename TB>
+static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int64_t ldq, int64_t L, int j,
                        const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs) {
   const double sb = sizeof(TB);
   const Small &s = P->sc;
   const TB *src = w;
+  int rc;
   if (j > 0) {
-    int nslab, ngc;
-    cgs_proj_shape(L, j, nslab, ngc);
-    ACC_BEFORE(SVDS_KC_CGS_PROJ);
-    hipLaunchKernelGGL((cgs_proj_kernel<TB>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q,
-                       ldq, L, j, w, Lz.partials);
-    LAUNCH_CHECK();
-    ACC_AFTER(SVDS_KC_CGS_PROJ, sb * L * j + sb * L, 2.0 * L * j);
-    ACC_BEFORE(SVDS_KC_CGS_REDUCE);
-    hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j, 4)), dim3(256), 0, P->stream,
-                       Lz.partials, static_cast<int64_t>(nslab), nslab, j, Lz.h1);
-    LAUNCH_CHECK();
-    ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * j * nslab, 0.0);
-
-    const int nw = std::max(1, std::min(16, static_cast<int>(ceil_div(j, CGS_CPW))));
-    const int nb = cgs_updproj_blocks(L);
-    ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
-    hipLaunchKernelGGL((cgs_upd_proj_kernel<TB>), dim3(nb), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j,
-                       w, Lz.h1, w1, Lz.partials);
-    LAUNCH_CHECK();
-    ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 4.0 * L * j);
-    ACC_BEFORE(SVDS_KC_CGS_REDUCE);
-    hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j, 4)), dim3(256), 0, P->stream,
-                       Lz.partials, static_cast<int64_t>(nb), nb, j, Lz.h2);
-    LAUNCH_CHECK();
-    ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * j * nb, 0.0);
+    // pass 1: h1 = Q^T w
+    if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ))) return rc;
+    // pass 2: w1 = w - Q h1, h2 = Q^T w1
+    const int cpw = cgs_fused_cpw(j);
+    if (cpw) {
+      const int nb = cgs_updproj_blocks(L);
+      const int nw = static_cast<int>(ceil_div(j, cpw));
+      ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
+      if (cpw == 8)
+        hipLaunchKernelGGL((cgs_upd_proj_kernel<TB, 8, true>), dim3(nb), dim3(nw * WAVE), 0, P->stream, Q,
+                           ldq, L, j, w, h1, w1, part);
+      else
+        hipLaunchKernelGGL((cgs_upd_proj_kernel<TB, 10, false>), dim3(nb), dim3(nw * WAVE), 0, P->stream,
+                           Q, ldq, L, j, w, h1, w1, part);
+      LAUNCH_CHECK();
+      ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 4.0 * L * j);
+      ACC_BEFORE(SVDS_KC_CGS_REDUCE);
+      hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j, 4)), dim3(256), 0, P->stream, part,
+                         static_cast<int64_t>(nb), nb, j, h2);
+      LAUNCH_CHECK();
+      ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * j * nb, 0.0);
+    } else {
+      // wide basis: separate update and projection passes
+      ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
+      hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
+                         P->stream, Q, ldq, L, j, w, h1, w1, static_cast<double *>(nullptr));
+      LAUNCH_CHECK();
+      ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 2.0 * L * j);
+      if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w1, h2, SVDS_KC_CGS_UPDPROJ))) return rc;
+    }
     src = w1;
   }
+  // pass 3: out = w1 - Q h2 and its norm
   const int nn = cgs_updnorm_blocks(L);
   ACC_BEFORE(SVDS_KC_CGS_UPDNORM);
   hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
-                     src, Lz.h2, out, s.npart);
+                     src, h2, out, s.npart);
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * j + 2 * sb * L, 2.0 * L * j + 2.0 * L);
   FinishArgs fa{t_entry, xs, s.sigma_est, s.bd, P->opts.seed};
@@ -315,6 +341,12 @@ static int cgs2_finish(svds_plan *P, Lanczos<TB> &Lz, const TB *Q, int64_t ldq, 
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_REDUCE, 8.0 * nn, 0.0);
   return SVDS_OK;
+}
+
+template <typename TB>
+static int cgs2_finish(svds_plan *P, Lanczos<TB> &Lz, const TB *Q, int64_t ldq, int64_t L, int j,
+                       const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs) {
+  return cgs2_finish<TB>(P, Lz.partials, Lz.h1, Lz.h2, Q, ldq, L, j, w, w1, out, mode, t_entry, xs);
 }
 
 // Update only: out = w - Q h (restart, eq. (7)).
@@ -956,5 +988,52 @@ int svds_plan_transpose_copy(svds_plan *P, int32_t *t_row_ptr, int32_t *t_col_id
                            hipMemcpyDeviceToDevice, P->stream));
   }
   HIP_TRY(hipStreamSynchronize(P->stream));
+  return SVDS_OK;
+}
+
+// CGS2 of one vector against a caller basis, with the solver's own kernels
+// (single-step operation).  Scratch is allocated for the call.
+int svds_cgs2_op(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
+                 double *norm_out, int32_t dtype, void *stream) {
+  svds_plan tmp;
+  tmp.stream = static_cast<hipStream_t>(stream);
+  tmp.acc.stream = tmp.stream;
+  const size_t tb = dtype == SVDS_F64 ? 8 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t o_parts = take(tb * CGS_MAXJ * CGS_MAX_SLABS), o_h1 = take(tb * CGS_MAXJ),
+               o_h2 = take(tb * CGS_MAXJ), o_w1 = take(tb * L), o_np = take(8 * NPART), o_dx = take(64),
+               o_bd = take(16);
+  char *b = nullptr;
+  HIP_TRY(hipMalloc(reinterpret_cast<void **>(&b), off));
+  struct Free {
+    char *p;
+    ~Free() { (void)hipFree(p); }
+  } guard{b};
+  HIP_TRY(hipMemsetAsync(b, 0, off, tmp.stream));
+  double *dx = reinterpret_cast<double *>(b + o_dx);  // xs, t_entry, sigma_est
+  tmp.sc.npart = reinterpret_cast<double *>(b + o_np);
+  tmp.sc.sigma_est = dx + 2;
+  tmp.sc.bd = reinterpret_cast<int *>(b + o_bd);
+  int rc;
+  if (dtype == SVDS_F64)
+    rc = cgs2_finish<double>(&tmp, reinterpret_cast<double *>(b + o_parts), reinterpret_cast<double *>(b + o_h1),
+                             reinterpret_cast<double *>(b + o_h2), static_cast<const double *>(Q), ldq, L, j,
+                             static_cast<const double *>(w), reinterpret_cast<double *>(b + o_w1),
+                             static_cast<double *>(out), MODE_NORM, dx + 1, dx);
+  else
+    rc = cgs2_finish<float>(&tmp, reinterpret_cast<float *>(b + o_parts), reinterpret_cast<float *>(b + o_h1),
+                            reinterpret_cast<float *>(b + o_h2), static_cast<const float *>(Q), ldq, L, j,
+                            static_cast<const float *>(w), reinterpret_cast<float *>(b + o_w1),
+                            static_cast<float *>(out), MODE_NORM, dx + 1, dx);
+  if (rc) return rc;
+  double xs = 0;
+  HIP_TRY(hipMemcpyAsync(&xs, dx, sizeof(double), hipMemcpyDeviceToHost, tmp.stream));
+  HIP_TRY(hipStreamSynchronize(tmp.stream));
+  if (norm_out) *norm_out = 1.0 / xs;
   return SVDS_OK;
 }
