@@ -101,6 +101,10 @@ typedef struct {
   int32_t flags;    /* SVDS_FLAG_*                                           */
 } svds_opts;
 
+/* With SVDS_FLAG_TIMING, one launch in SVDS_TIMING_SAMPLE of each kernel
+ * class is bracketed by HIP events (the first, then every 4th). */
+enum { SVDS_TIMING_SAMPLE = 4 };
+
 /* Kernel classes reported by SVDS_FLAG_TIMING. */
 enum {
   SVDS_KC_SPMV = 0,      /* w = A x - beta u          (Alg. 1 step 7)       */
@@ -127,10 +131,16 @@ typedef struct {
   double max_res_av;    /* max_j |A v_j - s_j u_j| / s_1,  FP64 explicit    */
   double ms_total;      /* wall time of the execute call                    */
   double bytes_alg;     /* algorithmic HBM bytes of SpMV + CGS kernels      */
-  double kc_ms[SVDS_KC_COUNT];     /* device ms per class (TIMING flag)     */
-  double kc_bytes[SVDS_KC_COUNT];  /* algorithmic bytes per class           */
-  double kc_flops[SVDS_KC_COUNT];  /* algorithmic flops per class           */
+  /* Per kernel class.  With SVDS_FLAG_TIMING every SVDS_TIMING_SAMPLE-th
+   * launch of a class is bracketed by HIP events on the solve's stream:
+   * kc_ms is the device time of those sampled launches, kc_sampled_* their
+   * count and algorithmic bytes; kc_bytes/kc_flops/kc_launches cover all. */
+  double kc_ms[SVDS_KC_COUNT];
+  double kc_bytes[SVDS_KC_COUNT];
+  double kc_flops[SVDS_KC_COUNT];
   int64_t kc_launches[SVDS_KC_COUNT];
+  int64_t kc_sampled_launches[SVDS_KC_COUNT];
+  double kc_sampled_bytes[SVDS_KC_COUNT];
   int64_t workspace_bytes;         /* device arena of the plan              */
 } svds_info;
 

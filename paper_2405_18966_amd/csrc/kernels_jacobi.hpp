@@ -80,47 +80,65 @@ __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
 
   // tolJ: orthogonality to working precision, scaled by sqrt(rows)
   const double tolJ = 0x1.0p-52 * sqrt(static_cast<double>(pe));
+  const int npairs = pe / 2;
+  // pairs per batch: a wave issues the loads of B pairs (W and Vh columns)
+  // before any of them is reduced, so one memory round trip serves B pairs
+  constexpr int B = RPL <= 2 ? 4 : (RPL <= 4 ? 3 : 1);
   int sweeps = 0;
   for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
     if (tid == 0) rot_count = 0;
     __syncthreads();
     for (int step = 0; step < pe - 1; ++step) {
-      for (int pi = wv; pi < pe / 2; pi += nwaves) {
-        int ci, cj;
-        rr_pair(pe, step, pi, ci, cj);
-        double *wi = W + static_cast<int64_t>(ci) * pe, *wj = W + static_cast<int64_t>(cj) * pe;
-        double xi[RPL], xj[RPL];
-        double a = 0, b = 0, c = 0;
+      for (int base = wv; base < npairs; base += nwaves * B) {
+        double xi[B][RPL], xj[B][RPL], yi[B][RPL], yj[B][RPL];
+        int ci[B], cj[B];
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int r = lane + t * WAVE;
-          xi[t] = r < pe ? wi[r] : 0.0;
-          xj[t] = r < pe ? wj[r] : 0.0;
-          a += xi[t] * xi[t];
-          b += xj[t] * xj[t];
-          c += xi[t] * xj[t];
-        }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        c = wave_sum(c);
-        if (fabs(c) > tolJ * sqrt(a * b)) {
-          const double z = (b - a) / (2.0 * c);
-          const double tt = (z >= 0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt);
-          const double sn = cs * tt;
-          double *vi = Vh + static_cast<int64_t>(ci) * pe, *vj = Vh + static_cast<int64_t>(cj) * pe;
+        for (int q = 0; q < B; ++q) {
+          const int pi = base + q * nwaves;
+          ci[q] = cj[q] = -1;
+          if (pi < npairs) rr_pair(pe, step, pi, ci[q], cj[q]);
 #pragma unroll
           for (int t = 0; t < RPL; ++t) {
             const int r = lane + t * WAVE;
-            if (r < pe) {
-              wi[r] = cs * xi[t] - sn * xj[t];
-              wj[r] = sn * xi[t] + cs * xj[t];
-              const double yi = vi[r], yj = vj[r];
-              vi[r] = cs * yi - sn * yj;
-              vj[r] = sn * yi + cs * yj;
-            }
+            const bool ok = ci[q] >= 0 && r < pe;
+            xi[q][t] = ok ? W[static_cast<int64_t>(ci[q]) * pe + r] : 0.0;
+            xj[q][t] = ok ? W[static_cast<int64_t>(cj[q]) * pe + r] : 0.0;
+            yi[q][t] = ok ? Vh[static_cast<int64_t>(ci[q]) * pe + r] : 0.0;
+            yj[q][t] = ok ? Vh[static_cast<int64_t>(cj[q]) * pe + r] : 0.0;
           }
-          if (lane == 0) atomicAdd(&rot_count, 1);
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          if (ci[q] < 0) continue;  // wave-uniform
+          double a = 0, bb = 0, c = 0;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            a += xi[q][t] * xi[q][t];
+            bb += xj[q][t] * xj[q][t];
+            c += xi[q][t] * xj[q][t];
+          }
+          a = wave_sum(a);
+          bb = wave_sum(bb);
+          c = wave_sum(c);
+          if (fabs(c) > tolJ * sqrt(a * bb)) {
+            const double z = (bb - a) / (2.0 * c);
+            const double tt = (z >= 0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+            const double cs = 1.0 / sqrt(1.0 + tt * tt);
+            const double sn = cs * tt;
+            double *wi = W + static_cast<int64_t>(ci[q]) * pe, *wj = W + static_cast<int64_t>(cj[q]) * pe;
+            double *vi = Vh + static_cast<int64_t>(ci[q]) * pe, *vj = Vh + static_cast<int64_t>(cj[q]) * pe;
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              const int r = lane + t * WAVE;
+              if (r < pe) {
+                wi[r] = cs * xi[q][t] - sn * xj[q][t];
+                wj[r] = sn * xi[q][t] + cs * xj[q][t];
+                vi[r] = cs * yi[q][t] - sn * yj[q][t];
+                vj[r] = sn * yi[q][t] + cs * yj[q][t];
+              }
+            }
+            if (lane == 0) atomicAdd(&rot_count, 1);
+          }
         }
       }
       __syncthreads();

@@ -53,11 +53,16 @@ struct Accounting {
   double bytes[SVDS_KC_COUNT] = {};
   double flops[SVDS_KC_COUNT] = {};
   int64_t launches[SVDS_KC_COUNT] = {};
+  int64_t sampled[SVDS_KC_COUNT] = {};
+  double sampled_bytes[SVDS_KC_COUNT] = {};
+  bool sampling = false;  // the launch between before() and after() is timed
 
   void reset() {
-    for (int i = 0; i < SVDS_KC_COUNT; ++i) ms[i] = bytes[i] = flops[i] = 0, launches[i] = 0;
+    for (int i = 0; i < SVDS_KC_COUNT; ++i)
+      ms[i] = bytes[i] = flops[i] = sampled_bytes[i] = 0, launches[i] = sampled[i] = 0;
     next = 0;
     cls.clear();
+    sampling = false;
   }
   int harvest();
   int before(int kc);

@@ -90,7 +90,8 @@ int Accounting::harvest() {
 }
 
 int Accounting::before(int kc) {
-  if (!timing) return SVDS_OK;
+  sampling = timing && (launches[kc] % SVDS_TIMING_SAMPLE == 0);
+  if (!sampling) return SVDS_OK;
   if (next + 2 > pool.size()) {
     if (pool.size() < 16384) {
       for (int i = 0; i < 1024; ++i) {
@@ -112,7 +113,10 @@ int Accounting::after(int kc, double b, double f) {
   bytes[kc] += b;
   flops[kc] += f;
   launches[kc] += 1;
-  if (!timing) return SVDS_OK;
+  if (!sampling) return SVDS_OK;
+  sampling = false;
+  sampled[kc] += 1;
+  sampled_bytes[kc] += b;
   HIP_TRY(hipEventRecord(pool[next++], stream));
   return SVDS_OK;
 }
@@ -909,6 +913,8 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
       info->kc_bytes[c] = P->acc.bytes[c];
       info->kc_flops[c] = P->acc.flops[c];
       info->kc_launches[c] = P->acc.launches[c];
+      info->kc_sampled_launches[c] = P->acc.sampled[c];
+      info->kc_sampled_bytes[c] = P->acc.sampled_bytes[c];
     }
     info->workspace_bytes = static_cast<int64_t>(P->arena.size);
   }

@@ -52,11 +52,12 @@ class svds_info(C.Structure):
                 ("ms_total", C.c_double), ("bytes_alg", C.c_double),
                 ("kc_ms", C.c_double * KC_COUNT), ("kc_bytes", C.c_double * KC_COUNT),
                 ("kc_flops", C.c_double * KC_COUNT), ("kc_launches", C.c_int64 * KC_COUNT),
+                ("kc_sampled_launches", C.c_int64 * KC_COUNT), ("kc_sampled_bytes", C.c_double * KC_COUNT),
                 ("workspace_bytes", C.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("kc_")}
-        for f in ("kc_ms", "kc_bytes", "kc_flops", "kc_launches"):
+        for f in ("kc_ms", "kc_bytes", "kc_flops", "kc_launches", "kc_sampled_launches", "kc_sampled_bytes"):
             d[f] = dict(zip(KERNEL_CLASSES, list(getattr(self, f))))
         return d
 

@@ -62,3 +62,33 @@ def test_validation_rejects_bad_sizes_before_touching_the_device(lib):
         assert mod.lib.svds_plan_create_csr(ctypes.byref(A), ctypes.byref(o), ctypes.byref(h)) == -1
     o = mod.svds_opts(2, 4, 0.0, 0, 7, 0, None, None, 0)  # unknown precision
     assert mod.lib.svds_plan_create_csr(ctypes.byref(A), ctypes.byref(o), ctypes.byref(h)) == -1
+
+
+def test_ctypes_structs_match_the_c_header(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets that a
+    C compiler gives the header's structs (a field added on one side only
+    would shift every later field)."""
+    import shutil
+    import subprocess
+    mod = __import__("paper_2405_18966_amd.svds", fromlist=["x"])
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"svds_csr": mod.svds_csr, "svds_dense": mod.svds_dense, "svds_opts": mod.svds_opts,
+               "svds_info": mod.svds_info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "svds.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "sizes"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.split("\n") if l)
+    for name, cls in structs.items():
+        assert int(out[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"
