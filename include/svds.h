@@ -101,8 +101,9 @@ typedef struct {
   int32_t flags;    /* SVDS_FLAG_*                                           */
 } svds_opts;
 
-/* With SVDS_FLAG_TIMING, one launch in SVDS_TIMING_SAMPLE of each kernel
- * class is bracketed by HIP events (the first, then every 4th). */
+/* With SVDS_FLAG_TIMING, one launch in each group of SVDS_TIMING_SAMPLE
+ * consecutive launches of a kernel class is bracketed by HIP events (launch
+ * i is sampled when i mod 4 == (i / 4) mod 4). */
 enum { SVDS_TIMING_SAMPLE = 4 };
 
 /* Kernel classes reported by SVDS_FLAG_TIMING. */

@@ -182,30 +182,18 @@ extern "C" int svds_op_small_svd(int32_t p, int32_t k, double tol, double *T, do
                                  double *sig, double *res, double *rho, int32_t *flags_host,
                                  void *stream) {
   if (p < 2 || k < 1 || k >= p || !T || !Uk || !Vext || !sig || !res || !rho) return SVDS_EINVAL;
+  if (p > 1023) return SVDS_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int pe = p + (p & 1);
   const int64_t wb = jacobi_work_bytes(p);
-  const bool use_lds = wb <= 64 * 1024;
-  const int rpl = static_cast<int>(ceil_div(pe, WAVE));
-  if (rpl > 16) return SVDS_EUNSUPPORTED;
   Scratch s;
   HIP_TRY(hipMalloc(&s.p, wb + 256));
   double *sigma_est = static_cast<double *>(s.p);
-  double *jac = sigma_est + 8;
   int *flags = reinterpret_cast<int *>(sigma_est + 4);
+  double *jac = sigma_est + 8;
   HIP_TRY(hipMemsetAsync(s.p, 0, 64, st));
-  const int nthr = std::min(JAC_THREADS, std::max(WAVE, (pe / 2) * WAVE));
-  const size_t shm = use_lds ? static_cast<size_t>(wb) : 0;
-#define JAC_GO(R)                                                                                    \
-  hipLaunchKernelGGL((small_svd_kernel<R>), dim3(1), dim3(nthr), shm, st, T, p, k, tol, jac, Uk, Vext, \
-                     sig, res, rho, flags, sigma_est, use_lds ? 1 : 0)
-  if (rpl <= 1) JAC_GO(1);
-  else if (rpl <= 2) JAC_GO(2);
-  else if (rpl <= 4) JAC_GO(4);
-  else if (rpl <= 8) JAC_GO(8);
-  else JAC_GO(16);
-#undef JAC_GO
-  HIP_TRY(hipGetLastError());
+  std::vector<int> counts(JAC_MAX_SWEEPS);
+  int rc = svds_small_svd_run(st, T, p, k, tol, jac, Uk, Vext, sig, res, rho, flags, sigma_est, counts.data());
+  if (rc) return rc;
   int hf[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -218,13 +206,15 @@ extern "C" int svds_op_rotate(int64_t L, int32_t pc, int32_t kc, const void *B, 
                               void *stream) {
   if (L < 1 || pc < 1 || kc < 1 || !B || !Y || !out || ldb < L || ldy < pc || ldo < L) return SVDS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const unsigned g = static_cast<unsigned>(ceil_div(L, ROT_THREADS));
+  Scratch yt;
+  HIP_TRY(hipMalloc(&yt.p, sizeof(double) * rot_yt_doubles(pc, kc)));
+  double *Yt = static_cast<double *>(yt.p);
   if (btype == SVDS_F64)
-    hipLaunchKernelGGL((rotate_kernel<double, double>), dim3(g), dim3(ROT_THREADS), 0, st, L, pc, kc,
-                       static_cast<const double *>(B), ldb, Y, ldy, out, ldo);
+    HIP_TRY((rotate_launch<double, double>(st, L, pc, kc, static_cast<const double *>(B), ldb, Y, ldy, Yt,
+                                           out, ldo)));
   else if (btype == SVDS_F32)
-    hipLaunchKernelGGL((rotate_kernel<float, double>), dim3(g), dim3(ROT_THREADS), 0, st, L, pc, kc,
-                       static_cast<const float *>(B), ldb, Y, ldy, out, ldo);
+    HIP_TRY((rotate_launch<float, double>(st, L, pc, kc, static_cast<const float *>(B), ldb, Y, ldy, Yt,
+                                          out, ldo)));
   else
     return SVDS_EUNSUPPORTED;
   HIP_TRY(hipGetLastError());

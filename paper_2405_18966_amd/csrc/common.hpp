@@ -55,6 +55,36 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
   return __shfl(v, 0, WAVE);
 }
 
+// Full-wave sum in a fixed order with the result held in a scalar register,
+// so every lane sees the same bits by construction.  DPP steps: swap lanes
+// within quads (xor 1, xor 2), mirror half-rows and rows (row sums in all 16
+// lanes), then row_bcast:15 / row_bcast:31 accumulate the four row sums into
+// row 3; lane 63 holds the total and is read out.  Every lane of the wave must
+// be active at the call.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROW_MASK, 0xF, false));
+}
+template <int CTRL, int ROW_MASK = 0xF> __device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+  const uint32_t lo = dpp_u32<CTRL, ROW_MASK>(static_cast<uint32_t>(u));
+  const uint32_t hi = dpp_u32<CTRL, ROW_MASK>(static_cast<uint32_t>(u >> 32));
+  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+__device__ __forceinline__ double wave_sum_u(double v) {
+  v += dpp_f64<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);       // row_half_mirror
+  v += dpp_f64<0x140>(v);       // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 -> rows 1, 3
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 -> rows 2, 3
+  const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u)), WAVE - 1);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u >> 32)), WAVE - 1);
+  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
 template <typename T> __device__ __forceinline__ T wave_max(T v) {
 #pragma unroll
   for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));

@@ -1,18 +1,32 @@
 // Small SVD of T(1:p,1:p), convergence test and restart set-up
-// (Alg. 2 steps 4-9, eq. (4), eq. (6)) in ONE workgroup, FP64.
+// (Alg. 2 steps 4-9, eq. (4), eq. (6)), FP64.
 //
 // SVD method: one-sided Jacobi (Hestenes 1958).  W <- T, Vh <- I; column
 // pairs (i, j) are rotated from the right until every pair is orthogonal to
 // working precision: with a = |w_i|^2, b = |w_j|^2, c = w_i . w_j the pair is
 // rotated when |c| > tolJ * sqrt(a b), by t = sign(z)/(|z| + sqrt(1+z^2)),
-// z = (b - a)/(2c), cs = 1/sqrt(1+t^2), sn = cs t (Rutishauser).  Pairs are
-// scheduled in round-robin (tournament) order: each step rotates p/2
-// disjoint pairs, one wave per pair; a sweep is p-1 steps.  Then
+// z = (b - a)/(2c), cs = 1/sqrt(1+t^2), sn = cs t (Rutishauser).  A sweep
+// visits every pair once; the iteration stops after a sweep without a
+// rotation (then every pair passed the test on the final W).  Then
 // sigma_i = |w_i|, Uh_i = w_i / sigma_i, sorted descending.
 //
 // T is upper triangular (bidiagonal after the first LBP; diagonal block,
 // arrow column k+1, then bidiagonal after a restart, Alg. 2 step 9), so the
 // general dense SVD is needed.
+//
+// Two schedules of the same iteration:
+//  * p <= JAC_SMALL_P: one workgroup, W and Vh in LDS, pairs in round-robin
+//    (tournament) order, p/2 disjoint pairs per step.
+//  * larger p: block Jacobi over several workgroups.  The columns are cut
+//    into nb (even) blocks of c columns; a sweep is nb-1 rounds of a
+//    round-robin over blocks, each round one kernel in which workgroup g
+//    stages its two blocks (W and Vh columns) in LDS and rotates, one pair
+//    per wave per step: in round 0 every pair of its 2c columns (this covers
+//    the pairs inside each block, as every block appears once per round), in
+//    later rounds the c*c pairs across its two blocks.  W and Vh live in
+//    global memory between rounds; each round adds its rotation count to a
+//    per-sweep counter, and kernels of a sweep that follows a sweep without
+//    rotations return at once.
 //
 // Outputs (all device, FP64):
 //   Uk   p x k   (ld p)     leading left singular vectors of T
@@ -31,13 +45,26 @@
 namespace svds {
 
 constexpr int JAC_THREADS = 1024;
-
-// bytes of the Jacobi work area for a p x p problem
-__host__ __device__ inline int64_t jacobi_work_bytes(int p) {
-  const int64_t pe = p + (p & 1);
-  return (2 * pe * pe + pe) * 8 + pe * 4;
-}
 constexpr int JAC_MAX_SWEEPS = 30;
+constexpr int JAC_SMALL_P = 62;          // single-workgroup schedule up to here
+constexpr int BJ_LDS = 160 * 1024 - 1024; // dynamic LDS of a block-Jacobi round
+constexpr int BJ_LU = 8;                  // loads in flight per thread when staging
+
+// block shape of the multi-workgroup schedule: c columns per block (16, 8 or
+// 4, the largest whose two blocks of W and Vh fit in LDS), nb blocks (even)
+__host__ __device__ inline void bjac_shape(int p, int &c, int &nb) {
+  c = (2 * 16 * p * 16 <= BJ_LDS) ? 16 : ((2 * 8 * p * 16 <= BJ_LDS) ? 8 : 4);
+  nb = static_cast<int>(ceil_div(p, c));
+  nb += nb & 1;
+}
+
+// bytes of the Jacobi work area in global memory (block schedule): W and Vh
+// (p rows x nb*c columns each) and the per-sweep rotation counters
+__host__ __device__ inline int64_t jacobi_work_bytes(int p) {
+  int c, nb;
+  bjac_shape(p, c, nb);
+  return 2 * static_cast<int64_t>(p) * nb * c * 8 + JAC_MAX_SWEEPS * 8;
+}
 
 __device__ __forceinline__ void rr_pair(int pe, int step, int i, int &a, int &b) {
   // players 1..pe-1 on a ring rotated by `step`; player 0 is fixed
@@ -51,110 +78,65 @@ __device__ __forceinline__ void rr_pair(int pe, int step, int i, int &a, int &b)
   }
 }
 
+// One Jacobi pair (columns of `rows` entries, rows spread over the lanes,
+// RPL per lane).  Every lane of the wave takes part; returns 1 if rotated
+// (wave-uniform).
 template <int RPL>
-__global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
-    double *__restrict__ T, int p, int k, double tol, double *__restrict__ scratch,
-    double *__restrict__ Uk, double *__restrict__ Vext,
-    double *__restrict__ sig, double *__restrict__ res, double *__restrict__ rho,
-    int *__restrict__ flags, double *__restrict__ sigma_est, int use_lds) {
-  extern __shared__ double smem[];
-  __shared__ int rot_count;
-  __shared__ double s_beta;
+__device__ __forceinline__ int jacobi_pair(double *__restrict__ wi, double *__restrict__ wj,
+                                           double *__restrict__ vi, double *__restrict__ vj, int rows,
+                                           int lane, double tolJ) {
+  double xi[RPL], xj[RPL], yi[RPL], yj[RPL];
+  double a = 0, b = 0, c = 0;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = lane + t * WAVE;
+    const bool ok = r < rows;
+    xi[t] = ok ? wi[r] : 0.0;
+    xj[t] = ok ? wj[r] : 0.0;
+    yi[t] = ok ? vi[r] : 0.0;
+    yj[t] = ok ? vj[r] : 0.0;
+    a += xi[t] * xi[t];
+    b += xj[t] * xj[t];
+    c += xi[t] * xj[t];
+  }
+  a = wave_sum_u(a);
+  b = wave_sum_u(b);
+  c = wave_sum_u(c);
+  if (!(fabs(c) > tolJ * sqrt(a * b))) return 0;
+  const double z = (b - a) / (2.0 * c);
+  const double tt = (z >= 0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+  const double cs = 1.0 / sqrt(1.0 + tt * tt);
+  const double sn = cs * tt;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = lane + t * WAVE;
+    if (r < rows) {
+      wi[r] = cs * xi[t] - sn * xj[t];
+      wj[r] = sn * xi[t] + cs * xj[t];
+      vi[r] = cs * yi[t] - sn * yj[t];
+      vj[r] = sn * yi[t] + cs * yj[t];
+    }
+  }
+  return 1;
+}
+
+// Singular values from the converged W (column norms), descending order
+// (ties: lower column first), outputs, eq. (4) estimates, restarted T.
+// W, Vh: p rows, leading dimensions ldw, ldv.  sv/rank: block-shared
+// scratch of p entries.  beta = T(p, p+1) read before T is rewritten.
+__device__ inline void jacobi_finish(const double *W, int64_t ldw, const double *Vh, int64_t ldv, int p,
+                                     int k, double tol, double beta, int sweeps, double *__restrict__ T,
+                                     double *__restrict__ Uk, double *__restrict__ Vext,
+                                     double *__restrict__ sig, double *__restrict__ res,
+                                     double *__restrict__ rho, int *__restrict__ flags,
+                                     double *__restrict__ sigma_est, double *sv, int *rank) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int nwaves = blockDim.x / WAVE;
-  const int pe = p + (p & 1);
   const int ld = p + 1;
-  // layout of the work area (LDS when it fits, else global scratch):
-  // W pe x pe | Vh pe x pe | sigma pe | rank pe (int)
-  double *base = use_lds ? smem : scratch;
-  double *W = base;
-  double *Vh = base + static_cast<int64_t>(pe) * pe;
-
-  if (tid == 0) s_beta = T[(p - 1) * ld + p];
-  for (int idx = tid; idx < pe * pe; idx += blockDim.x) {
-    const int r = idx % pe, c = idx / pe;
-    W[idx] = (r < p && c < p) ? T[r * ld + c] : 0.0;
-    Vh[idx] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-
-  // tolJ: orthogonality to working precision, scaled by sqrt(rows)
-  const double tolJ = 0x1.0p-52 * sqrt(static_cast<double>(pe));
-  const int npairs = pe / 2;
-  // pairs per batch: a wave issues the loads of B pairs (W and Vh columns)
-  // before any of them is reduced, so one memory round trip serves B pairs
-  constexpr int B = RPL <= 2 ? 4 : (RPL <= 4 ? 3 : 1);
-  int sweeps = 0;
-  for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
-    if (tid == 0) rot_count = 0;
-    __syncthreads();
-    for (int step = 0; step < pe - 1; ++step) {
-      for (int base = wv; base < npairs; base += nwaves * B) {
-        double xi[B][RPL], xj[B][RPL], yi[B][RPL], yj[B][RPL];
-        int ci[B], cj[B];
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
-          const int pi = base + q * nwaves;
-          ci[q] = cj[q] = -1;
-          if (pi < npairs) rr_pair(pe, step, pi, ci[q], cj[q]);
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            const int r = lane + t * WAVE;
-            const bool ok = ci[q] >= 0 && r < pe;
-            xi[q][t] = ok ? W[static_cast<int64_t>(ci[q]) * pe + r] : 0.0;
-            xj[q][t] = ok ? W[static_cast<int64_t>(cj[q]) * pe + r] : 0.0;
-            yi[q][t] = ok ? Vh[static_cast<int64_t>(ci[q]) * pe + r] : 0.0;
-            yj[q][t] = ok ? Vh[static_cast<int64_t>(cj[q]) * pe + r] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
-          if (ci[q] < 0) continue;  // wave-uniform
-          double a = 0, bb = 0, c = 0;
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            a += xi[q][t] * xi[q][t];
-            bb += xj[q][t] * xj[q][t];
-            c += xi[q][t] * xj[q][t];
-          }
-          a = wave_sum(a);
-          bb = wave_sum(bb);
-          c = wave_sum(c);
-          if (fabs(c) > tolJ * sqrt(a * bb)) {
-            const double z = (bb - a) / (2.0 * c);
-            const double tt = (z >= 0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-            const double cs = 1.0 / sqrt(1.0 + tt * tt);
-            const double sn = cs * tt;
-            double *wi = W + static_cast<int64_t>(ci[q]) * pe, *wj = W + static_cast<int64_t>(cj[q]) * pe;
-            double *vi = Vh + static_cast<int64_t>(ci[q]) * pe, *vj = Vh + static_cast<int64_t>(cj[q]) * pe;
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-              const int r = lane + t * WAVE;
-              if (r < pe) {
-                wi[r] = cs * xi[q][t] - sn * xj[q][t];
-                wj[r] = sn * xi[q][t] + cs * xj[q][t];
-                vi[r] = cs * yi[q][t] - sn * yj[q][t];
-                vj[r] = sn * yi[q][t] + cs * yj[q][t];
-              }
-            }
-            if (lane == 0) atomicAdd(&rot_count, 1);
-          }
-        }
-      }
-      __syncthreads();
-    }
-    sweeps = sweep + 1;
-    if (rot_count == 0) break;
-    __syncthreads();
-  }
-
-  // singular values and descending order (ties: lower column first)
-  double *sv = base + 2 * static_cast<int64_t>(pe) * pe;
-  int *rank = reinterpret_cast<int *>(sv + pe);
   for (int c = wv; c < p; c += nwaves) {
     double s = 0;
-    for (int r = lane; r < pe; r += WAVE) s += W[c * pe + r] * W[c * pe + r];
-    s = wave_sum(s);
+    for (int r = lane; r < p; r += WAVE) s += W[c * ldw + r] * W[c * ldw + r];
+    s = wave_sum_u(s);
     if (lane == 0) sv[c] = sqrt(s);
   }
   __syncthreads();
@@ -165,15 +147,14 @@ __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
     rank[c] = rk;
   }
   __syncthreads();
-  const double beta = s_beta;
   for (int c = wv; c < p; c += nwaves) {
     const int rk = rank[c];
     if (rk >= k) continue;
     const double s = sv[c];
     const double inv = s > 0 ? 1.0 / s : 0.0;
     for (int r = lane; r < p; r += WAVE) {
-      Uk[rk * p + r] = W[c * pe + r] * inv;
-      Vext[rk * ld + r] = Vh[c * pe + r];
+      Uk[rk * p + r] = W[c * ldw + r] * inv;
+      Vext[rk * ld + r] = Vh[c * ldv + r];
     }
     if (lane == 0) {
       Vext[rk * ld + p] = 0.0;
@@ -182,7 +163,6 @@ __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
   }
   for (int r = tid; r <= p; r += blockDim.x) Vext[k * ld + r] = (r == p) ? 1.0 : 0.0;
   __syncthreads();
-  __threadfence_block();
   if (tid == 0) {
     const double s1 = sig[0];
     const double floor_ = fmax(0x1.0p-52 * s1, 2.2250738585072014e-308);
@@ -211,6 +191,176 @@ __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
     else if (r < k && c == k) v = rho[r];
     T[idx] = v;
   }
+}
+
+// tolJ: orthogonality to working precision, scaled by sqrt(rows)
+__device__ __forceinline__ double jacobi_tol(int rows) {
+  return 0x1.0p-52 * sqrt(static_cast<double>(rows));
+}
+
+// ---------------------------------------------------------------------------
+// Single-workgroup schedule (p <= JAC_SMALL_P, one row per lane).  Dynamic
+// LDS: W and Vh (pe x pe each, pe = p rounded up to even), sv, rank.
+// ---------------------------------------------------------------------------
+static __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
+    double *__restrict__ T, int p, int k, double tol, double *__restrict__ Uk, double *__restrict__ Vext,
+    double *__restrict__ sig, double *__restrict__ res, double *__restrict__ rho, int *__restrict__ flags,
+    double *__restrict__ sigma_est) {
+  extern __shared__ double smem[];
+  __shared__ int rot_count;
+  __shared__ double s_beta;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int nwaves = blockDim.x / WAVE;
+  const int pe = p + (p & 1);
+  const int ld = p + 1;
+  double *W = smem;
+  double *Vh = smem + pe * pe;
+  double *sv = Vh + pe * pe;
+  int *rank = reinterpret_cast<int *>(sv + pe);
+
+  if (tid == 0) s_beta = T[(p - 1) * ld + p];
+  for (int idx = tid; idx < pe * pe; idx += blockDim.x) {
+    const int r = idx % pe, c = idx / pe;
+    W[idx] = (r < p && c < p) ? T[r * ld + c] : 0.0;
+    Vh[idx] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const double tolJ = jacobi_tol(pe);
+  const int npairs = pe / 2;
+  int sweeps = 0;
+  for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    if (tid == 0) rot_count = 0;
+    __syncthreads();
+    for (int step = 0; step < pe - 1; ++step) {
+      int nrot = 0;
+      for (int q = wv; q < npairs; q += nwaves) {
+        int i, j;
+        rr_pair(pe, step, q, i, j);
+        nrot += jacobi_pair<1>(W + i * pe, W + j * pe, Vh + i * pe, Vh + j * pe, pe, lane, tolJ);
+      }
+      if (lane == 0 && nrot) atomicAdd(&rot_count, nrot);
+      __syncthreads();
+    }
+    sweeps = sweep + 1;
+    if (rot_count == 0) break;
+    __syncthreads();
+  }
+  jacobi_finish(W, pe, Vh, pe, p, k, tol, s_beta, sweeps, T, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
+                rank);
+}
+
+__host__ __device__ inline size_t small_svd_lds_bytes(int p) {
+  const int pe = p + (p & 1);
+  return static_cast<size_t>(2 * pe * pe + pe) * 8 + pe * 4;
+}
+
+// ---------------------------------------------------------------------------
+// Block schedule: one round.  Grid nb/2 workgroups of c waves; dynamic LDS
+// 2c columns of W then 2c columns of Vh, p rows each.  Block b holds global
+// columns [b c, b c + c); W and Vh in global memory are column-major with
+// ld = p and nb*c columns.  In the first round of the first sweep the blocks
+// are loaded from T (row-major, ld p+1) and the identity instead.
+// ---------------------------------------------------------------------------
+template <int RPL>
+__global__ __launch_bounds__(JAC_THREADS) void bjac_round_kernel(const double *__restrict__ T, int from_T,
+                                                                 double *__restrict__ W,
+                                                                 double *__restrict__ Vh, int p, int c,
+                                                                 int nb, int round, int sweep,
+                                                                 int *__restrict__ counters) {
+  extern __shared__ double smem[];
+  __shared__ int s_rot;
+  if (sweep > 0 && counters[sweep - 1] == 0) return;  // converged earlier
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int c2 = 2 * c;
+  double *X = smem;
+  double *Y = smem + static_cast<int64_t>(c2) * p;
+  int ba, bb;
+  rr_pair(nb, round, blockIdx.x, ba, bb);
+  if (tid == 0) s_rot = 0;
+  const int ldt = p + 1;
+  // staging: a thread issues BJ_LU loads of each matrix before it writes
+  // any of them to LDS, so the global-memory latency is paid once per batch
+  const int ntot = c2 * p;
+  for (int base = tid; base < ntot; base += BJ_LU * blockDim.x) {
+    double vx[BJ_LU], vy[BJ_LU];
+#pragma unroll
+    for (int u = 0; u < BJ_LU; ++u) {
+      const int idx = base + u * blockDim.x;
+      vx[u] = vy[u] = 0.0;
+      if (idx < ntot) {
+        const int lc = idx / p, r = idx - lc * p;
+        const int gc = lc < c ? ba * c + lc : bb * c + (lc - c);
+        if (from_T) {
+          vx[u] = gc < p ? T[static_cast<int64_t>(r) * ldt + gc] : 0.0;
+          vy[u] = (r == gc) ? 1.0 : 0.0;
+        } else {
+          vx[u] = W[static_cast<int64_t>(gc) * p + r];
+          vy[u] = Vh[static_cast<int64_t>(gc) * p + r];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < BJ_LU; ++u) {
+      const int idx = base + u * blockDim.x;
+      if (idx < ntot) {
+        X[idx] = vx[u];
+        Y[idx] = vy[u];
+      }
+    }
+  }
+  __syncthreads();
+  const double tolJ = jacobi_tol(p + (p & 1));
+  int nrot = 0;
+  if (round == 0) {
+    for (int step = 0; step < c2 - 1; ++step) {
+      int i, j;
+      rr_pair(c2, step, wv, i, j);
+      nrot += jacobi_pair<RPL>(X + i * p, X + j * p, Y + i * p, Y + j * p, p, lane, tolJ);
+      __syncthreads();
+    }
+  } else {
+    for (int step = 0; step < c; ++step) {
+      const int i = wv, j = c + (wv + step) % c;
+      nrot += jacobi_pair<RPL>(X + i * p, X + j * p, Y + i * p, Y + j * p, p, lane, tolJ);
+      __syncthreads();
+    }
+  }
+  for (int idx = tid; idx < c2 * p; idx += blockDim.x) {
+    const int lc = idx / p, r = idx - lc * p;
+    const int gc = lc < c ? ba * c + lc : bb * c + (lc - c);
+    W[static_cast<int64_t>(gc) * p + r] = X[idx];
+    Vh[static_cast<int64_t>(gc) * p + r] = Y[idx];
+  }
+  if (lane == 0 && nrot) atomicAdd(&s_rot, nrot);
+  __syncthreads();
+  if (tid == 0 && s_rot) atomicAdd(&counters[sweep], s_rot);
+}
+
+// Block schedule: outputs after the last round (one workgroup).  `nsw` =
+// sweeps enqueued; the sweeps used are up to the first without rotations.
+static __global__ __launch_bounds__(JAC_THREADS) void bjac_finish_kernel(
+    const double *__restrict__ W, const double *__restrict__ Vh, const int *__restrict__ counters, int nsw,
+    double *__restrict__ T, int p, int k, double tol, double *__restrict__ Uk, double *__restrict__ Vext,
+    double *__restrict__ sig, double *__restrict__ res, double *__restrict__ rho, int *__restrict__ flags,
+    double *__restrict__ sigma_est) {
+  extern __shared__ double smem[];
+  __shared__ double s_beta;
+  __shared__ int s_sweeps;
+  double *sv = smem;
+  int *rank = reinterpret_cast<int *>(sv + p);
+  if (threadIdx.x == 0) {
+    s_beta = T[(p - 1) * (p + 1) + p];
+    int s = nsw;
+    for (int i = 0; i < nsw; ++i)
+      if (counters[i] == 0) {
+        s = i + 1;
+        break;
+      }
+    s_sweeps = s;
+  }
+  __syncthreads();
+  jacobi_finish(W, p, Vh, p, p, k, tol, s_beta, s_sweeps, T, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
+                rank);
 }
 
 }  // namespace svds

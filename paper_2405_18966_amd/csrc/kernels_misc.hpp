@@ -2,57 +2,102 @@
 // V(:,1:p) Vh(:,1:k)), start vector, sign normalization, norms and small
 // helpers.
 #pragma once
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace svds {
 
 // ---------------------------------------------------------------------------
 // out(:, 0:kc) = B(:, 0:pc) * Y(0:pc, 0:kc), B L x pc (ld ldb), Y column-major
-// FP64 (ld ldy), out L x kc (ld ldo).  Tall-skinny: each wave owns 64 rows,
-// columns of the output in groups of ROT_CG accumulated in registers; the
-// Y panel of a group is staged in LDS and read as broadcasts.
+// FP64 (ld ldy), out L x kc (ld ldo).  Tall-skinny and bound by reading B:
+// each thread owns one row of B and accumulates up to ROT_KC output columns
+// in registers, so B is read once per group of ROT_KC columns (once for
+// kc <= 64).  Y is first transposed into a row-major, zero-padded copy Yt;
+// the kernel's loads of Yt are uniform across the wave (same q, same c) and
+// compile to scalar loads, so no LDS is involved.  Accumulation in q order.
 // ---------------------------------------------------------------------------
 constexpr int ROT_THREADS = 256;
-constexpr int ROT_CG = 16;
-constexpr int ROT_QMAX = 512;  // rows of Y staged per pass
+constexpr int ROT_KC = 64;  // output columns per launch
 
-template <typename TB, typename TO>
-static __global__ __launch_bounds__(ROT_THREADS) void rotate_kernel(int64_t L, int pc, int kc,
-                                                            const TB *__restrict__ B, int64_t ldb,
-                                                            const double *__restrict__ Y,
-                                                            int64_t ldy, TO *__restrict__ out,
-                                                            int64_t ldo) {
-  __shared__ TB ys[ROT_QMAX * ROT_CG];
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-  const int64_t r = (static_cast<int64_t>(blockIdx.x) * (ROT_THREADS / WAVE) + wv) * WAVE + lane;
-  const bool valid = r < L;
-  for (int g0 = 0; g0 < kc; g0 += ROT_CG) {
-    const int ng = min(ROT_CG, kc - g0);
-    TB acc[ROT_CG];
+// row stride of Yt for kc columns: kc rounded up to 8, plus ROT_KC of zero
+// padding so a launch for the last column group may read ROT_KC columns
+__host__ __device__ inline int rot_ldyt(int kc) { return ((kc + 7) / 8) * 8 + ROT_KC; }
+__host__ __device__ inline int64_t rot_yt_doubles(int pc, int kc) {
+  return static_cast<int64_t>(pc) * rot_ldyt(kc);
+}
+
+static __global__ void rot_transpose_kernel(int pc, int kc, const double *__restrict__ Y, int64_t ldy,
+                                            double *__restrict__ Yt, int ldyt) {
+  const int64_t n = static_cast<int64_t>(pc) * ldyt;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int q = static_cast<int>(i / ldyt), c = static_cast<int>(i % ldyt);
+    Yt[i] = c < kc ? Y[c * ldy + q] : 0.0;
+  }
+}
+
+template <typename TB, typename TO, int KC>
+static __global__ __launch_bounds__(ROT_THREADS) void rotate_kernel(int64_t L, int pc, int kcv,
+                                                                    const TB *__restrict__ B, int64_t ldb,
+                                                                    const double *__restrict__ Yt, int ldyt,
+                                                                    TO *__restrict__ out, int64_t ldo) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * ROT_THREADS + threadIdx.x;
+  if (r >= L) return;
+  TB acc[KC];
 #pragma unroll
-    for (int c = 0; c < ROT_CG; ++c) acc[c] = 0;
-    for (int q0 = 0; q0 < pc; q0 += ROT_QMAX) {
-      const int nq = min(ROT_QMAX, pc - q0);
-      __syncthreads();
-      for (int idx = tid; idx < nq * ROT_CG; idx += ROT_THREADS) {
-        const int q = idx / ROT_CG, c = idx % ROT_CG;
-        ys[idx] = c < ng ? static_cast<TB>(Y[(g0 + c) * ldy + q0 + q]) : TB(0);
-      }
-      __syncthreads();
-      if (valid) {
-        for (int q = 0; q < nq; ++q) {
-          const TB b = B[(q0 + q) * ldb + r];
+  for (int c = 0; c < KC; ++c) acc[c] = TB(0);
+  int q = 0;
+  for (; q + 4 <= pc; q += 4) {
+    TB b[4];
 #pragma unroll
-          for (int c = 0; c < ROT_CG; ++c) acc[c] += b * ys[q * ROT_CG + c];
-        }
-      }
-    }
-    if (valid) {
+    for (int u = 0; u < 4; ++u) b[u] = B[static_cast<int64_t>(q + u) * ldb + r];
 #pragma unroll
-      for (int c = 0; c < ROT_CG; ++c)
-        if (c < ng) out[(g0 + c) * ldo + r] = static_cast<TO>(acc[c]);
+    for (int u = 0; u < 4; ++u) {
+      const double *y = Yt + static_cast<int64_t>(q + u) * ldyt;
+#pragma unroll
+      for (int c = 0; c < KC; ++c) acc[c] += b[u] * static_cast<TB>(y[c]);
     }
   }
+  for (; q < pc; ++q) {
+    const TB bq = B[static_cast<int64_t>(q) * ldb + r];
+    const double *y = Yt + static_cast<int64_t>(q) * ldyt;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] += bq * static_cast<TB>(y[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < KC; ++c)
+    if (c < kcv) out[c * ldo + r] = static_cast<TO>(acc[c]);
+}
+
+// Enqueues Yt = Y^T (padded) and the launches of all column groups.  Yt holds
+// rot_yt_doubles(pc, kc) doubles of device scratch.
+template <typename TB, typename TO>
+inline hipError_t rotate_launch(hipStream_t st, int64_t L, int pc, int kc, const TB *B, int64_t ldb,
+                                const double *Y, int64_t ldy, double *Yt, TO *out, int64_t ldo) {
+  const int ldyt = rot_ldyt(kc);
+  hipLaunchKernelGGL(rot_transpose_kernel, dim3(static_cast<unsigned>(
+                                               std::min<int64_t>(1024, ceil_div(rot_yt_doubles(pc, kc), 256)))),
+                     dim3(256), 0, st, pc, kc, Y, ldy, Yt, ldyt);
+  const unsigned g = static_cast<unsigned>(ceil_div(L, ROT_THREADS));
+  for (int g0 = 0; g0 < kc; g0 += ROT_KC) {
+    const int kcv = std::min(ROT_KC, kc - g0);
+    const double *yt = Yt + g0;
+    TO *o = out + g0 * ldo;
+#define ROT_GO(K)                                                                                         \
+  hipLaunchKernelGGL((rotate_kernel<TB, TO, K>), dim3(g), dim3(ROT_THREADS), 0, st, L, pc, kcv, B, ldb, yt, \
+                     ldyt, o, ldo)
+    if (kcv <= 8) ROT_GO(8);
+    else if (kcv <= 16) ROT_GO(16);
+    else if (kcv <= 24) ROT_GO(24);
+    else if (kcv <= 32) ROT_GO(32);
+    else if (kcv <= 40) ROT_GO(40);
+    else if (kcv <= 48) ROT_GO(48);
+    else if (kcv <= 56) ROT_GO(56);
+    else ROT_GO(64);
+#undef ROT_GO
+  }
+  return hipGetLastError();
 }
 
 // Philox normal vector (stream `stream` of `seed`), the library's v1 when the
@@ -88,19 +133,34 @@ static __global__ void copy_f64_kernel(int64_t L, const double *__restrict__ src
 }
 
 // Sign convention: flip (u_j, v_j) so the entry of v_j of largest magnitude
-// (lowest index on ties) is positive.  One block per column j.
-static __global__ __launch_bounds__(256) void signfix_kernel(int64_t m, int64_t n, double *__restrict__ U,
-                                                     int64_t ldu, double *__restrict__ V,
-                                                     int64_t ldv) {
+// (lowest index on ties) is positive.  Three steps over V (n x k):
+//  absmax_partials_kernel  grid (nslab, k): max |v| and its first index per
+//                          slab of SIGN_SLAB rows of a column;
+//  sign_pick_kernel        one wave per column: the column's winner in slab
+//                          order, sgn[j] = -1 if that entry is negative, and
+//                          column j of Uk scaled by sgn[j] (so U = U_basis Uk
+//                          formed afterwards carries the sign);
+//  flip_cols_kernel        V(:, j) *= -1 where sgn[j] < 0 (other columns are
+//                          not touched).
+constexpr int SIGN_SLAB = 8192;
+constexpr int SIGN_MAX_SLABS = 256;
+__host__ __device__ inline int64_t sign_slab_rows(int64_t n) {
+  return std::max<int64_t>(SIGN_SLAB, ceil_div(n, SIGN_MAX_SLABS));
+}
+
+static __global__ __launch_bounds__(256) void absmax_partials_kernel(int64_t n, int64_t slab,
+                                                                     const double *__restrict__ V, int64_t ldv,
+                                                                     double *__restrict__ pval,
+                                                                     int64_t *__restrict__ pidx) {
   __shared__ double smax[256 / WAVE];
   __shared__ int64_t sidx[256 / WAVE];
-  __shared__ double sgn;
-  const int j = blockIdx.x;
+  const int j = blockIdx.y, sl = blockIdx.x, nslab = gridDim.x;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-  double *v = V + j * ldv;
+  const double *v = V + j * ldv;
+  const int64_t i0 = sl * slab, i1 = std::min<int64_t>(n, i0 + slab);
   double best = -1.0;
   int64_t bi = INT64_MAX;
-  for (int64_t i = tid; i < n; i += 256) {
+  for (int64_t i = i0 + tid; i < i1; i += 256) {
     const double a = fabs(v[i]);
     if (a > best) {  // strictly greater keeps the lowest index of this thread
       best = a;
@@ -129,14 +189,56 @@ static __global__ __launch_bounds__(256) void signfix_kernel(int64_t m, int64_t 
         b = smax[w];
         id = sidx[w];
       }
-    sgn = (id < n && v[id] < 0) ? -1.0 : 1.0;
+    pval[j * nslab + sl] = b;
+    pidx[j * nslab + sl] = id;
+  }
+}
+
+static __global__ __launch_bounds__(WAVE) void sign_pick_kernel(int nslab, const double *__restrict__ pval,
+                                                                const int64_t *__restrict__ pidx,
+                                                                const double *__restrict__ V, int64_t ldv,
+                                                                int64_t n, double *__restrict__ sgn,
+                                                                double *__restrict__ Uk, int p) {
+  __shared__ double s_sign;
+  const int j = blockIdx.x, lane = threadIdx.x;
+  double best = -1.0;
+  int64_t bi = INT64_MAX;
+  for (int s = lane; s < nslab; s += WAVE) {
+    const double b = pval[j * nslab + s];
+    const int64_t id = pidx[j * nslab + s];
+    if (b > best || (b == best && id < bi)) {
+      best = b;
+      bi = id;
+    }
+  }
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, WAVE);
+    const int64_t oi = __shfl_xor(bi, o, WAVE);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    const double sg = (bi < n && V[j * ldv + bi] < 0) ? -1.0 : 1.0;
+    sgn[j] = sg;
+    s_sign = sg;
   }
   __syncthreads();
-  if (sgn < 0) {
-    for (int64_t i = tid; i < n; i += 256) v[i] = -v[i];
-    double *u = U + j * ldu;
-    for (int64_t i = tid; i < m; i += 256) u[i] = -u[i];
-  }
+  const double sg = s_sign;
+  if (sg < 0)
+    for (int r = lane; r < p; r += WAVE) Uk[j * p + r] = -Uk[j * p + r];
+}
+
+static __global__ __launch_bounds__(256) void flip_cols_kernel(int64_t n, double *__restrict__ V, int64_t ldv,
+                                                               const double *__restrict__ sgn) {
+  const int j = blockIdx.y;
+  if (!(sgn[j] < 0)) return;
+  double *v = V + j * ldv;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * 256)
+    v[i] = -v[i];
 }
 
 // |x|_2 of a length-L vector (FP64 accumulation) for the explicit residuals:

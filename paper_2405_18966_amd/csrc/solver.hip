@@ -90,7 +90,11 @@ int Accounting::harvest() {
 }
 
 int Accounting::before(int kc) {
-  sampling = timing && (launches[kc] % SVDS_TIMING_SAMPLE == 0);
+  // one launch in each group of SVDS_TIMING_SAMPLE, at an offset that
+  // rotates from group to group, so launches that alternate between two
+  // shapes (U side / V side) are both sampled
+  const int64_t i = launches[kc];
+  sampling = timing && (i % SVDS_TIMING_SAMPLE == (i / SVDS_TIMING_SAMPLE) % SVDS_TIMING_SAMPLE);
   if (!sampling) return SVDS_OK;
   if (next + 2 > pool.size()) {
     if (pool.size() < 16384) {
@@ -167,6 +171,9 @@ template <typename TB> struct Lanczos {
 struct Small {
   double *T, *xs_u, *xs_v, *one, *sigma_est, *rho, *sig, *res, *Uk, *Vext, *jac, *npart;
   double *resid_av, *resid_atu;
+  double *yt;                       // transposed rotation panel
+  double *sgn, *sgn_val;            // sign normalization
+  int64_t *sgn_idx;
   int *bd, *flags;
 };
 
@@ -369,12 +376,9 @@ static int gemv_update(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, int j,
 template <typename TB, typename TO>
 static int rotate(svds_plan *P, int64_t L, int pc, int kc, const TB *B, int64_t ldb,
                   const double *Y, int64_t ldy, TO *out, int64_t ldo) {
-  const unsigned g = static_cast<unsigned>(ceil_div(L, ROT_THREADS));
   ACC_BEFORE(SVDS_KC_ROTATE);
-  hipLaunchKernelGGL((rotate_kernel<TB, TO>), dim3(g), dim3(ROT_THREADS), 0, P->stream, L, pc, kc,
-                     B, ldb, Y, ldy, out, ldo);
-  LAUNCH_CHECK();
-  ACC_AFTER(SVDS_KC_ROTATE, sizeof(TB) * double(L) * pc + sizeof(TO) * double(L) * kc,
+  HIP_TRY((rotate_launch<TB, TO>(P->stream, L, pc, kc, B, ldb, Y, ldy, P->sc.yt, out, ldo)));
+  ACC_AFTER(SVDS_KC_ROTATE, sizeof(TB) * double(L) * pc * ceil_div(kc, ROT_KC) + sizeof(TO) * double(L) * kc,
             2.0 * L * pc * kc);
   return SVDS_OK;
 }
@@ -444,26 +448,11 @@ template <typename TB> static int start(svds_plan *P, Lanczos<TB> &Lz, const dou
 // Alg. 2 steps 4-7: small SVD, eq. (4) test; returns converged flag via h_flags.
 static int small_svd(svds_plan *P) {
   const int p = P->p;
-  const int pe = p + (p & 1);
-  const int64_t wb = jacobi_work_bytes(p);
-  const bool use_lds = wb <= 64 * 1024;
-  const int rpl = static_cast<int>(ceil_div(pe, WAVE));
-  const size_t shm = use_lds ? static_cast<size_t>(wb) : 0;
   const Small &s = P->sc;
-  const int nthr = std::min(JAC_THREADS, std::max(WAVE, static_cast<int>(ceil_div(pe / 2, 1)) * WAVE));
   ACC_BEFORE(SVDS_KC_SMALLSVD);
-#define JAC_LAUNCH(R)                                                                           \
-  hipLaunchKernelGGL((small_svd_kernel<R>), dim3(1), dim3(nthr), shm, P->stream, s.T, p, P->k,  \
-                     P->tol, s.jac, s.Uk, s.Vext, s.sig, s.res, s.rho, s.flags, s.sigma_est,   \
-                     use_lds ? 1 : 0)
-  if (rpl <= 1) JAC_LAUNCH(1);
-  else if (rpl <= 2) JAC_LAUNCH(2);
-  else if (rpl <= 4) JAC_LAUNCH(4);
-  else if (rpl <= 8) JAC_LAUNCH(8);
-  else if (rpl <= 16) JAC_LAUNCH(16);
-  else return SVDS_EUNSUPPORTED;
-#undef JAC_LAUNCH
-  LAUNCH_CHECK();
+  int rc = svds_small_svd_run(P->stream, s.T, p, P->k, P->tol, s.jac, s.Uk, s.Vext, s.sig, s.res, s.rho,
+                              s.flags, s.sigma_est, P->h_flags + 16);
+  if (rc) return rc;
   ACC_AFTER(SVDS_KC_SMALLSVD, 16.0 * (p + 1) * (p + 1), 0.0);
   HIP_TRY(hipMemcpyAsync(P->h_flags, s.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
@@ -578,6 +567,10 @@ static int carve_all(svds_plan *P, Arena &a) {
   s.resid_atu = a.take<double>(k);
   s.bd = a.take<int>(4);
   s.flags = a.take<int>(4);
+  s.yt = a.take<double>(rot_yt_doubles(p + 1, k + 1));
+  s.sgn = a.take<double>(k);
+  s.sgn_val = a.take<double>(static_cast<size_t>(k) * SIGN_MAX_SLABS);
+  s.sgn_idx = a.take<int64_t>(static_cast<size_t>(k) * SIGN_MAX_SLABS);
   P->tmp_m = a.take<double>(m);
   P->tmp_n = a.take<double>(n);
   if (P->mixed) P->tmp_nk = a.take<double>(static_cast<size_t>(n) * k);
@@ -612,7 +605,8 @@ static int alloc_arena(svds_plan *P) {
   P->arena.used = 0;
   P->arena.counting = false;
   carve_all(P, P->arena);
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&P->h_flags), 16 * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&P->h_flags), (16 + JAC_MAX_SWEEPS) * sizeof(int),
+                        hipHostMallocDefault));
   const double one = 1.0;
   HIP_TRY(hipMemcpyAsync(P->sc.one, &one, sizeof one, hipMemcpyHostToDevice, P->stream));
   return SVDS_OK;
@@ -797,12 +791,29 @@ template <typename TB>
 static int outputs(svds_plan *P, Lanczos<TB> &Lz, double *U, double *S, double *V) {
   const int p = P->p, k = P->k;
   const int64_t m = P->op.m, n = P->op.n;
-  // Alg. 2 steps 15-16
-  int rc = rotate<TB, double>(P, m, p, k, Lz.U[Lz.cur], Lz.ldu, P->sc.Uk, p, U, m);
+  const Small &s = P->sc;
+  // Alg. 2 steps 15-16; V first, so that its sign normalization can be
+  // folded into Uk before U is formed
+  int rc = rotate<TB, double>(P, n, p, k, Lz.V[Lz.cur], Lz.ldv, s.Vext, p + 1, V, n);
   if (rc) return rc;
-  rc = rotate<TB, double>(P, n, p, k, Lz.V[Lz.cur], Lz.ldv, P->sc.Vext, p + 1, V, n);
+  if (!(P->opts.flags & SVDS_FLAG_NO_SIGNFIX)) {
+    const int64_t slab = sign_slab_rows(n);
+    const int nslab = static_cast<int>(ceil_div(n, slab));
+    ACC_BEFORE(SVDS_KC_OTHER);
+    hipLaunchKernelGGL(absmax_partials_kernel, dim3(nslab, k), dim3(256), 0, P->stream, n, slab, V, n,
+                       s.sgn_val, s.sgn_idx);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(sign_pick_kernel, dim3(k), dim3(WAVE), 0, P->stream, nslab, s.sgn_val, s.sgn_idx, V, n,
+                       n, s.sgn, s.Uk, p);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(flip_cols_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(256, ceil_div(n, 2048))), k),
+                       dim3(256), 0, P->stream, n, V, n, s.sgn);
+    LAUNCH_CHECK();
+    ACC_AFTER(SVDS_KC_OTHER, 8.0 * n * k * 2, 0.0);
+  }
+  rc = rotate<TB, double>(P, m, p, k, Lz.U[Lz.cur], Lz.ldu, s.Uk, p, U, m);
   if (rc) return rc;
-  HIP_TRY(hipMemcpyAsync(S, P->sc.sig, sizeof(double) * k, hipMemcpyDeviceToDevice, P->stream));
+  HIP_TRY(hipMemcpyAsync(S, s.sig, sizeof(double) * k, hipMemcpyDeviceToDevice, P->stream));
   return SVDS_OK;
 }
 
@@ -858,11 +869,6 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
   if (rc) return rc;
   rc = outputs<double>(P, P->L64, U, S, V);
   if (rc) return rc;
-  if (!(P->opts.flags & SVDS_FLAG_NO_SIGNFIX)) {
-    hipLaunchKernelGGL(signfix_kernel, dim3(P->k), dim3(256), 0, P->stream, P->op.m, P->op.n, U,
-                       P->op.m, V, P->op.n);
-    LAUNCH_CHECK();
-  }
   double res_true = 0, res_av = 0;
   if (!(P->opts.flags & SVDS_FLAG_NO_RESIDUALS)) {
     rc = residuals_impl(P, P->k, U, S, V, P->sc.resid_av, P->sc.resid_atu);
@@ -1041,5 +1047,87 @@ int svds_cgs2_op(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w
   HIP_TRY(hipMemcpyAsync(&xs, dx, sizeof(double), hipMemcpyDeviceToHost, tmp.stream));
   HIP_TRY(hipStreamSynchronize(tmp.stream));
   if (norm_out) *norm_out = 1.0 / xs;
+  return SVDS_OK;
+}
+
+namespace {
+template <int R>
+int bjac_launch_round(hipStream_t st, const double *T, int from_T, double *W, double *Vh, int p, int c, int nb,
+                      int round, int sweep, int *counters) {
+  const size_t shm = static_cast<size_t>(4 * c) * p * sizeof(double);
+  static bool attr_set = false;  // benign race: every caller sets the same value
+  if (!attr_set) {
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&bjac_round_kernel<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, BJ_LDS));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((bjac_round_kernel<R>), dim3(nb / 2), dim3(c * WAVE), shm, st, T, from_T, W, Vh, p, c, nb,
+                     round, sweep, counters);
+  HIP_TRY(hipGetLastError());
+  return SVDS_OK;
+}
+
+int bjac_round(hipStream_t st, int rpl, const double *T, int from_T, double *W, double *Vh, int p, int c,
+               int nb, int round, int sweep, int *counters) {
+  switch (rpl) {
+    case 1: return bjac_launch_round<1>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+    case 2: return bjac_launch_round<2>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+    case 3: return bjac_launch_round<3>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+    case 4: return bjac_launch_round<4>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+    case 5: case 6: return bjac_launch_round<6>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+    case 7: case 8: return bjac_launch_round<8>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+    case 9: case 10: case 11: case 12:
+      return bjac_launch_round<12>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+    case 13: case 14: case 15: case 16:
+      return bjac_launch_round<16>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+    default: return SVDS_EUNSUPPORTED;
+  }
+}
+
+static __global__ void zero_i32_kernel(int n, int *__restrict__ out) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = 0;
+}
+}  // namespace
+
+int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, double *work, double *Uk,
+                       double *Vext, double *sig, double *res, double *rho, int *flags, double *sigma_est,
+                       int *h_counts) {
+  if (p < 2 || k < 1 || k >= p || p > 1023) return SVDS_EINVAL;
+  if (p <= JAC_SMALL_P) {
+    const int pe = p + (p & 1);
+    const int nthr = std::min(JAC_THREADS, (pe / 2) * WAVE);
+    hipLaunchKernelGGL(small_svd_kernel, dim3(1), dim3(nthr), small_svd_lds_bytes(p), st, T, p, k, tol, Uk,
+                       Vext, sig, res, rho, flags, sigma_est);
+    HIP_TRY(hipGetLastError());
+    return SVDS_OK;
+  }
+  int c, nb;
+  bjac_shape(p, c, nb);
+  const int rpl = static_cast<int>(ceil_div(p, WAVE));
+  double *W = work;
+  double *Vh = work + static_cast<int64_t>(p) * nb * c;
+  int *counters = reinterpret_cast<int *>(Vh + static_cast<int64_t>(p) * nb * c);
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, JAC_MAX_SWEEPS, counters);
+  HIP_TRY(hipGetLastError());
+  // sweeps are enqueued in chunks (10, then 2 at a time) and the rotation
+  // counters read back after each chunk
+  int enq = 0;
+  bool done = false;
+  while (!done && enq < JAC_MAX_SWEEPS) {
+    const int chunk = std::min(enq == 0 ? 10 : 2, JAC_MAX_SWEEPS - enq);
+    for (int sw = enq; sw < enq + chunk; ++sw)
+      for (int r = 0; r < nb - 1; ++r) {
+        const int rc = bjac_round(st, rpl, T, sw == 0 && r == 0, W, Vh, p, c, nb, r, sw, counters);
+        if (rc) return rc;
+      }
+    enq += chunk;
+    HIP_TRY(hipMemcpyAsync(h_counts, counters, sizeof(int) * enq, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < enq; ++i)
+      if (h_counts[i] == 0) done = true;
+  }
+  hipLaunchKernelGGL(bjac_finish_kernel, dim3(1), dim3(JAC_THREADS), static_cast<size_t>(p) * 12, st, W, Vh,
+                     counters, enq, T, p, k, tol, Uk, Vext, sig, res, rho, flags, sigma_est);
+  HIP_TRY(hipGetLastError());
   return SVDS_OK;
 }
