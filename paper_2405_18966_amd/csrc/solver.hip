@@ -285,9 +285,14 @@ static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int
   const double sb = sizeof(TB);
   int nslab, ngc;
   cgs_proj_shape(L, j, nslab, ngc);
+  constexpr int NV = 16 / sizeof(TB);
   ACC_BEFORE(kc);
-  hipLaunchKernelGGL((cgs_proj_kernel<TB>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
-                     L, j, w, part);
+  if (cgs_rows_per_lane<TB>(Q, ldq, w, nullptr, nullptr) == NV)
+    hipLaunchKernelGGL((cgs_proj_kernel<TB, NV>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
+                       L, j, w, part);
+  else
+    hipLaunchKernelGGL((cgs_proj_kernel<TB, 1>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
+                       L, j, w, part);
   LAUNCH_CHECK();
   ACC_AFTER(kc, sb * L * j + sb * L, 2.0 * L * j);
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
@@ -304,6 +309,8 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
   const double sb = sizeof(TB);
   const Small &s = P->sc;
   const TB *src = w;
+  constexpr int NV = 16 / sizeof(TB);
+  const bool vec = cgs_rows_per_lane<TB>(Q, ldq, w, w1, out) == NV;
   int rc;
   if (j > 0) {
     // pass 1: h1 = Q^T w
@@ -314,11 +321,16 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
       const int nb = cgs_updproj_blocks(L);
       const int nw = static_cast<int>(ceil_div(j, cpw));
       ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
+      // 8 columns per wave with prefetch: one row per lane (two rows per lane
+      // raise register pressure and lose ~30%); 10 columns: 16-byte rows
       if (cpw == 8)
-        hipLaunchKernelGGL((cgs_upd_proj_kernel<TB, 8, true>), dim3(nb), dim3(nw * WAVE), 0, P->stream, Q,
+        hipLaunchKernelGGL((cgs_upd_proj_kernel<TB, 8, true, 1>), dim3(nb), dim3(nw * WAVE), 0, P->stream, Q,
                            ldq, L, j, w, h1, w1, part);
+      else if (vec)
+        hipLaunchKernelGGL((cgs_upd_proj_kernel<TB, 10, false, NV>), dim3(nb), dim3(nw * WAVE), 0, P->stream,
+                           Q, ldq, L, j, w, h1, w1, part);
       else
-        hipLaunchKernelGGL((cgs_upd_proj_kernel<TB, 10, false>), dim3(nb), dim3(nw * WAVE), 0, P->stream,
+        hipLaunchKernelGGL((cgs_upd_proj_kernel<TB, 10, false, 1>), dim3(nb), dim3(nw * WAVE), 0, P->stream,
                            Q, ldq, L, j, w, h1, w1, part);
       LAUNCH_CHECK();
       ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 4.0 * L * j);
@@ -330,8 +342,12 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     } else {
       // wide basis: separate update and projection passes
       ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
-      hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
-                         P->stream, Q, ldq, L, j, w, h1, w1, static_cast<double *>(nullptr));
+      if (vec)
+        hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, NV>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
+                           P->stream, Q, ldq, L, j, w, h1, w1, static_cast<double *>(nullptr));
+      else
+        hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, 1>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
+                           P->stream, Q, ldq, L, j, w, h1, w1, static_cast<double *>(nullptr));
       LAUNCH_CHECK();
       ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 2.0 * L * j);
       if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w1, h2, SVDS_KC_CGS_UPDPROJ))) return rc;
@@ -341,8 +357,12 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
   // pass 3: out = w1 - Q h2 and its norm
   const int nn = cgs_updnorm_blocks(L);
   ACC_BEFORE(SVDS_KC_CGS_UPDNORM);
-  hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
-                     src, h2, out, s.npart);
+  if (vec)
+    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, NV>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
+                       src, h2, out, s.npart);
+  else
+    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, 1>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
+                       src, h2, out, s.npart);
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * j + 2 * sb * L, 2.0 * L * j + 2.0 * L);
   FinishArgs fa{t_entry, xs, s.sigma_est, s.bd, P->opts.seed};
@@ -366,8 +386,13 @@ static int gemv_update(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, int j,
                        const TB *h, TB *out) {
   const double sb = sizeof(TB);
   ACC_BEFORE(SVDS_KC_OTHER);
-  hipLaunchKernelGGL((cgs_upd_norm_kernel<TB>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
-                     P->stream, Q, ldq, L, j, w, h, out, static_cast<double *>(nullptr));
+  constexpr int NV = 16 / sizeof(TB);
+  if (cgs_rows_per_lane<TB>(Q, ldq, w, out, nullptr) == NV)
+    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, NV>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
+                       P->stream, Q, ldq, L, j, w, h, out, static_cast<double *>(nullptr));
+  else
+    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, 1>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
+                       P->stream, Q, ldq, L, j, w, h, out, static_cast<double *>(nullptr));
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_OTHER, sb * L * j + 2 * sb * L, 2.0 * L * j);
   return SVDS_OK;

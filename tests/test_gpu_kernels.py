@@ -148,6 +148,23 @@ def test_cgs2_matches_oracle(S, L, j):
         assert np.abs(Q.T @ out).max() <= 1e-14 * np.linalg.norm(w)
 
 
+@pytest.mark.parametrize("L,ld,j", [(2049, 2050, 100), (100003, 100004, 150), (999, 1000, 20)])
+def test_cgs2_ragged_tail_padded_ld(S, L, ld, j):
+    """Odd length with an even leading dimension: the 16-byte row accesses
+    run with a one-row tail in the last tile."""
+    rng = np.random.default_rng(L + 7 * j)
+    Q = np.linalg.qr(rng.standard_normal((L, j)))[0]
+    w = rng.standard_normal(L) + Q @ rng.standard_normal(j) * 10
+    ref = svds_ref.cgs2(w, Q)
+    Qp = np.zeros((j, ld))
+    Qp[:, :L] = Q.T
+    out, nrm = S.svds_op_cgs2(_t(Qp), j, _t(w), ldq=ld)
+    out = out.cpu().numpy()
+    assert np.linalg.norm(out - ref) <= 1e-14 * np.linalg.norm(w) * np.sqrt(j)
+    assert abs(nrm - np.linalg.norm(ref)) <= 1e-13 * np.linalg.norm(w)
+    assert np.abs(Q.T @ out).max() <= 1e-14 * np.linalg.norm(w)
+
+
 def test_cgs2_fp32(S):
     import torch
     rng = np.random.default_rng(3)

@@ -349,3 +349,20 @@ def test_planted_single_pass_without_reorth_is_caught(monkeypatch):
     A = inputs.prescribed_dense(200, 150, inputs.decay2(150), seed=3)
     U, T, V, beta, info = svds_ref.lbp(A, 60, inputs.start_vector(150, 4))
     assert np.abs(V.T @ V - np.eye(60)).max() > 1e-6
+
+
+def test_planted_transposed_operand_is_caught(monkeypatch):
+    """A^T u computed with A itself (square, non-symmetric A): the complete
+    bidiagonalization pin (sigma(T) = sigma(A), P2) fails."""
+    orig_init = svds_ref._Op.__init__
+
+    def bad_init(self, A, info):
+        orig_init(self, A, info)
+        self.AT = A  # the planted mistake: the transpose is dropped
+
+    monkeypatch.setattr(svds_ref._Op, "__init__", bad_init)
+    A = np.random.default_rng(2).standard_normal((40, 40))
+    U, T, V, beta, info = lbp(A, 40, inputs.start_vector(40, 3))
+    s_T = np.linalg.svd(T, compute_uv=False)
+    s_A = np.linalg.svd(A, compute_uv=False)
+    assert np.max(np.abs(s_T - s_A) / s_A[0]) > 1e-3
