@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 METRIC = "k-triplet solves/s at rel.err≤1e-8; SpMV+CGS2 HBM GB/s; mixed vs FP64 x"
 HBM_PEAK_GBS = 8000.0
 GOLDEN_W2 = os.path.join(ROOT, "tests", "golden", "workload2_sigma.txt")
+GOLDEN_W3 = os.path.join(ROOT, "tests", "golden", "workload3_sigma_bf16.txt")
+GOLDEN_W4 = os.path.join(ROOT, "tests", "golden", "workload4_sigma.txt")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_workload2.json")
 WORKLOAD = dict(workload="zipf-sparse-svds", m=1_000_000, n=500_000, draws_per_row=10, zipf_a=1.1,
                 values="U(0,1)", k=50, p=150, tol=1e-8, storage="fp64 CSR")
@@ -40,11 +42,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def load_golden():
-    if not os.path.exists(GOLDEN_W2):
+def load_golden(path=GOLDEN_W2):
+    if not os.path.exists(path):
         return None
     import numpy as np
-    vals = [float(x) for x in open(GOLDEN_W2) if x.strip() and not x.startswith("#")]
+    vals = [float(x) for x in open(path) if x.strip() and not x.startswith("#")]
     return np.array(vals)
 
 
@@ -74,12 +76,60 @@ def cpu_baseline(A, v0, k, p, tol):
             "sigma": S.tolist()}
 
 
+def mixed_vs_fp64(S, inputs, np, torch):
+    """Mixed (FP32 cycles + FP64 refinement) against the plain FP64 GPU path,
+    same stored matrix, same start vector, tol=1e-8: median solve time of 3
+    after one warm-up each.  The dense 20000 x 10000 BF16 workload and the
+    2000 x 1000 sparse workload with FP32 values (k=50, p=150)."""
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts, r = [], None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[1] * 1e3, r
+
+    d = inputs.config_matrix(3)
+    t = torch.from_numpy(d["bf16"].a.ravel(order="F").view(np.int16)).view(torch.uint16).cuda()
+    Ad = S.make_dense(t, 20000, 10000)
+    v0 = torch.from_numpy(inputs.start_vector(10000, inputs.CONFIG_SEEDS[3] + 1)).cuda()
+    gold = load_golden(GOLDEN_W3)
+    res = {}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        ms, r = timed(lambda: S.svds_dense_solve(Ad, S.make_opts(100, 250, 1e-8, 2000, precision=prec, v0=v0)))
+        s = r.S.cpu().numpy()
+        res[name] = {"ms": round(ms, 2), "cycles_fp32": r.info["cycles_fp32"], "cycles_fp64": r.info["cycles_fp64"],
+                     "sigma_rel_err_vs_oracle": float(np.max(np.abs(s - gold[:100]) / gold[:100]))
+                     if gold is not None else None, "status": r.status}
+    out["dense_20000x10000_bf16_k100_p250"] = dict(res, x=round(res["fp64"]["ms"] / res["mixed"]["ms"], 3))
+    del d, t, Ad
+    A = inputs.config_matrix(4)
+    Ad4, keep = S.csr_to_device(A)
+    v0 = torch.from_numpy(inputs.start_vector(A.n, inputs.CONFIG_SEEDS[4] + 1)).cuda()
+    gold = load_golden(GOLDEN_W4)
+    res = {}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        ms, r = timed(lambda: S.svds_csr_solve(Ad4, S.make_opts(50, 150, 1e-8, 2000, precision=prec, v0=v0)))
+        s = r.S.cpu().numpy()
+        res[name] = {"ms": round(ms, 2), "cycles_fp32": r.info["cycles_fp32"], "cycles_fp64": r.info["cycles_fp64"],
+                     "sigma_rel_err_vs_oracle": float(np.max(np.abs(s - gold[:50]) / gold[:50]))
+                     if gold is not None else None, "status": r.status}
+    out["sparse_2000x1000_fp32_k50_p150"] = dict(res, x=round(res["fp64"]["ms"] / res["mixed"]["ms"], 3))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed vs FP64 comparison")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
     args = ap.parse_args()
@@ -163,11 +213,14 @@ def main():
     if os.path.exists(TRAFFIC):
         tr = json.load(open(TRAFFIC))
         if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("kernels", {}):
-            traffic = tr["kernels"][dom]
+            traffic = tr["kernels"][dom]["bytes_per_launch"] / 1e9  # GB per launch, PMC-scaled
     hot = ["spmv", "spmvT", "cgs_proj", "cgs_updproj", "cgs_updnorm"]
     hot_gbs = sum(kc_b[c] for c in hot) / (sum(kc_ms[c] for c in hot) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "GB per launch",
+                "traffic_note": "rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-kernel calibrated, averaged over all "
+                                "launches of the class in one solve; null when the kernel sources changed",
+                "kernel": dom,
                 "avg_launch_us": round(kc_ms[dom] * 1e3 / max(kc_n[dom], 1), 2),
                 "alg_bytes_per_launch": round(kc_b[dom] / max(kc_n[dom], 1)),
                 "spmv_cgs2_gbs": round(hot_gbs, 1),
@@ -175,6 +228,11 @@ def main():
                 "per_class": {c: {"est_ms": round(kc_est[c] / args.steps, 3),
                                   "gbs": round(kc_b[c] / (kc_ms[c] * 1e-3) / 1e9, 1) if kc_ms[c] else None,
                                   "launches": kc_all[c] // args.steps} for c in S.KERNEL_CLASSES}}
+
+    mixed = None
+    if not args.no_mixed:
+        log("mixed vs FP64 ...")
+        mixed = mixed_vs_fp64(S, inputs, np, torch)
 
     cpu = None
     if not args.no_cpu and rank == 0:
@@ -186,7 +244,7 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 2),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic", "config": dict(WORKLOAD, parallelism="single GPU"),
-           "roofline": roofline, "cpu_baseline": cpu, "parity": parity}
+           "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "mixed_vs_fp64": mixed}
     print(json.dumps(out), flush=True)
 
 
