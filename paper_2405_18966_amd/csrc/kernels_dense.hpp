@@ -3,23 +3,49 @@
 // y = xs * A^T x - coef * yprev, A column-major (ld >= m) stored as FP64, FP32
 // or BF16 and widened exactly in registers; accumulation in the basis type.
 //
-// A x  : 2-D grid of (row tile of 512 rows) x (column slab of 256 columns);
-//        each lane owns 8 rows and walks a quarter of the slab's columns,
-//        waves combine in LDS, the slab partial goes to global memory, and
-//        gemv_n_fixup_kernel (next launch) adds the slab partials in slab
-//        order.  Deterministic.
-// A^T x: one wave per column (the column is contiguous), lanes stride the
-//        rows with vector loads, fixed-order wave reduction.
+// Both products stream A once; every lane owns 8 consecutive rows of a
+// column, read as 16-byte accesses (one for BF16, two for FP32, four for
+// FP64) when the operands are aligned (VEC), element by element otherwise.
+//
+// A x  : 2-D grid of (row tile of 512 rows) x (column slab of DN_SLAB
+//        columns); each wave covers the tile's 512 rows for a quarter of the
+//        slab's columns (x[c] is a uniform scalar load), waves combine in
+//        LDS, the slab partial goes to global memory, and gemv_n_fixup_kernel
+//        (next launch) adds the slab partials in slab order.  Deterministic.
+// A^T x: one block per group of DN_TCOLS columns; its waves take alternate
+//        512-row chunks, a lane loads its 8 entries of x once per chunk and
+//        uses them for all the group's columns; fixed-order wave and block
+//        reductions.
 #pragma once
 #include "common.hpp"
 
 namespace svds {
 
-constexpr int DN_ROWS = 512;     // rows per tile (2 per thread)
-constexpr int DN_SLAB = 256;     // columns per slab
+constexpr int DN_ROWS = 512;     // rows per tile (8 per lane)
+constexpr int DN_SLAB = 256;     // columns per slab (A x)
 constexpr int DN_THREADS = 256;
+constexpr int DN_TCOLS = 8;      // columns per block (A^T x)
 
-template <typename TV, typename TB>
+// 8 consecutive entries of a column starting at row r (r + 8 <= m when VEC)
+template <typename TV, typename TB, bool VEC>
+__device__ __forceinline__ void load8(const TV *__restrict__ p, int64_t rem, TB (&v)[8]) {
+  if (VEC && rem >= 8) {
+    TV t[8];
+    constexpr int CH = static_cast<int>(8 * sizeof(TV) / 16);  // 16-byte chunks
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const uint4 u = reinterpret_cast<const uint4 *>(p)[q];
+      __builtin_memcpy(&t[q * (16 / sizeof(TV))], &u, 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = widen<TB>(t[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = i < rem ? widen<TB>(p[i]) : TB(0);
+  }
+}
+
+template <typename TV, typename TB, bool VEC>
 __global__ __launch_bounds__(DN_THREADS) void gemv_n_kernel(
     int64_t m, int64_t n, const TV *__restrict__ A, int64_t lda, const TB *__restrict__ x,
     const double *__restrict__ xs_ptr,
@@ -32,44 +58,35 @@ __global__ __launch_bounds__(DN_THREADS) void gemv_n_kernel(
     const int64_t nb = static_cast<int64_t>(gridDim.x) * gridDim.y;
     for (int64_t i = bid * DN_THREADS + tid; i < side_len; i += nb * DN_THREADS) side_dst[i] = x[i] * xs;
   }
-  // a lane owns rows rbase + t*128 + 2*lane + {0,1}, t = 0..3
-  const int64_t rbase = static_cast<int64_t>(blockIdx.x) * DN_ROWS;
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * DN_ROWS + lane * 8;
   const int64_t c0 = static_cast<int64_t>(blockIdx.y) * DN_SLAB;
   const int64_t c1 = min(n, c0 + DN_SLAB);
-  // each wave covers all 512 rows (8 rows per lane: 4 strips of 128) for a
-  // quarter of the slab's columns
   TB acc[8];
 #pragma unroll
   for (int t = 0; t < 8; ++t) acc[t] = 0;
-  for (int64_t c = c0 + wv; c < c1; c += DN_THREADS / WAVE) {
-    const TB xc = x[c];
-    const TV *col = A + c * lda;
+  if (r < m) {
+    for (int64_t c = c0 + wv; c < c1; c += DN_THREADS / WAVE) {
+      const TB xc = x[c];
+      TB a[8];
+      load8<TV, TB, VEC>(A + c * lda + r, m - r, a);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int64_t r = rbase + t * 128 + 2 * lane;
-      if (r + 1 < m) {
-        acc[2 * t] += widen<TB>(col[r]) * xc;
-        acc[2 * t + 1] += widen<TB>(col[r + 1]) * xc;
-      } else if (r < m) {
-        acc[2 * t] += widen<TB>(col[r]) * xc;
-      }
+      for (int t = 0; t < 8; ++t) acc[t] += a[t] * xc;
     }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    red[wv][t * 128 + 2 * lane] = acc[2 * t];
-    red[wv][t * 128 + 2 * lane + 1] = acc[2 * t + 1];
-  }
+  for (int t = 0; t < 8; ++t) red[wv][lane * 8 + t] = acc[t];
   __syncthreads();
   for (int i = tid; i < DN_ROWS; i += DN_THREADS) {
     TB s = 0;
+#pragma unroll
     for (int w = 0; w < DN_THREADS / WAVE; ++w) s += red[w][i];
-    const int64_t r = rbase + i;
-    if (r < m) partials[static_cast<int64_t>(blockIdx.y) * m + r] = s;
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * DN_ROWS + i;
+    if (row < m) partials[static_cast<int64_t>(blockIdx.y) * m + row] = s;
   }
 }
 
-// y[r] = xs * sum_slab partials[slab][r] - coef * yprev[r]
+// y[r] = xs * sum_slab partials[slab][r] - coef * yprev[r]; the slab loop
+// keeps 8 loads in flight and adds in slab order.
 template <typename TB>
 __global__ void gemv_n_fixup_kernel(int64_t m, int nslab, const TB *__restrict__ partials,
                                     const double *__restrict__ xs_ptr, const double *__restrict__ coef_ptr,
@@ -79,15 +96,25 @@ __global__ void gemv_n_fixup_kernel(int64_t m, int nslab, const TB *__restrict__
   const TB xs = xs_ptr ? static_cast<TB>(*xs_ptr) : TB(1);
   const TB coef = coef_ptr ? static_cast<TB>(*coef_ptr) : TB(0);
   TB s = 0;
-  for (int sl = 0; sl < nslab; ++sl) s += partials[static_cast<int64_t>(sl) * m + r];
+  int sl = 0;
+  for (; sl + 8 <= nslab; sl += 8) {
+    TB v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = partials[static_cast<int64_t>(sl + i) * m + r];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += v[i];
+  }
+  for (; sl < nslab; ++sl) s += partials[static_cast<int64_t>(sl) * m + r];
   y[r] = xs * s - (yprev ? coef * yprev[r] : TB(0));
 }
 
-template <typename TV, typename TB>
+template <typename TV, typename TB, bool VEC>
 __global__ __launch_bounds__(DN_THREADS) void gemv_t_kernel(
     int64_t m, int64_t n, const TV *__restrict__ A, int64_t lda, const TB *__restrict__ x,
     const double *__restrict__ xs_ptr, const double *__restrict__ coef_ptr,
     const TB *__restrict__ yprev, TB *__restrict__ y, TB *__restrict__ side_dst, int64_t side_len) {
+  constexpr int NW = DN_THREADS / WAVE;
+  __shared__ TB red[NW][DN_TCOLS];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const TB xs = xs_ptr ? static_cast<TB>(*xs_ptr) : TB(1);
   const TB coef = coef_ptr ? static_cast<TB>(*coef_ptr) : TB(0);
@@ -96,23 +123,59 @@ __global__ __launch_bounds__(DN_THREADS) void gemv_t_kernel(
          i += static_cast<int64_t>(gridDim.x) * DN_THREADS)
       side_dst[i] = x[i] * xs;
   }
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * (DN_THREADS / WAVE) + wv;
-  if (c >= n) return;
-  const TV *col = A + c * lda;
-  TB s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  int64_t r = 4 * lane;
-  for (; r + 3 < m; r += 4 * WAVE) {
-    s0 += widen<TB>(col[r]) * x[r];
-    s1 += widen<TB>(col[r + 1]) * x[r + 1];
-    s2 += widen<TB>(col[r + 2]) * x[r + 2];
-    s3 += widen<TB>(col[r + 3]) * x[r + 3];
+  // block: DN_TCOLS columns; wave w takes the 512-row chunks w, w + NW, ...
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * DN_TCOLS;
+  const int nc = static_cast<int>(min<int64_t>(DN_TCOLS, n - c0));
+  TB acc[DN_TCOLS];
+#pragma unroll
+  for (int c = 0; c < DN_TCOLS; ++c) acc[c] = 0;
+  for (int64_t r = static_cast<int64_t>(wv) * DN_ROWS + lane * 8; r < m; r += NW * DN_ROWS) {
+    TB xv[8];
+    if (VEC && m - r >= 8) {
+#pragma unroll
+      for (int q = 0; q < static_cast<int>(8 * sizeof(TB) / 16); ++q) {
+        const uint4 u = reinterpret_cast<const uint4 *>(x + r)[q];
+        __builtin_memcpy(&xv[q * (16 / sizeof(TB))], &u, 16);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) xv[i] = r + i < m ? x[r + i] : TB(0);
+    }
+#pragma unroll
+    for (int c = 0; c < DN_TCOLS; ++c) {
+      if (c < nc) {
+        TB a[8];
+        load8<TV, TB, VEC>(A + (c0 + c) * lda + r, m - r, a);
+        TB s = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += a[i] * xv[i];
+        acc[c] += s;
+      }
+    }
   }
-  for (; r < m; ++r) s0 += widen<TB>(col[r]) * x[r];
-  TB s = wave_sum((s0 + s1) + (s2 + s3));
-  if (lane == 0) y[c] = xs * s - (yprev ? coef * yprev[c] : TB(0));
+#pragma unroll
+  for (int c = 0; c < DN_TCOLS; ++c) {
+    const TB s = wave_sum(acc[c]);
+    if (lane == 0) red[wv][c] = s;
+  }
+  __syncthreads();
+  if (tid < nc) {
+    TB s = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[w][tid];
+    const int64_t c = c0 + tid;
+    y[c] = xs * s - (yprev ? coef * yprev[c] : TB(0));
+  }
 }
 
 // scratch of the A x kernel: partials (slabs x m of TB <= 8 bytes)
 inline int64_t dense_partial_doubles(int64_t m, int64_t n) { return ceil_div(n, DN_SLAB) * m; }
+
+// 16-byte accesses are legal: A, x, and every column start 16-byte aligned
+template <typename TV, typename TB>
+inline bool dense_vec_ok(const void *A, int64_t lda, const void *x) {
+  auto al = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  return al(A) && al(x) && (lda * static_cast<int64_t>(sizeof(TV))) % 16 == 0;
+}
 
 }  // namespace svds

@@ -216,15 +216,25 @@ static void dense_launch(svds_plan *P, bool trans, const TB *x, const double *xs
                          const TB *yprev, TB *y, TB *side_dst, int64_t side_len) {
   const Operator &op = P->op;
   const TV *A = static_cast<const TV *>(op.a);
+  const bool vec = dense_vec_ok<TV, TB>(A, op.lda, x);
   if (trans) {
-    hipLaunchKernelGGL((gemv_t_kernel<TV, TB>), dim3(ceil_div(op.n, DN_THREADS / WAVE)),
-                       dim3(DN_THREADS), 0, P->stream, op.m, op.n, A, op.lda, x, xs, coef, yprev, y,
-                       side_dst, side_len);
+    const dim3 g(static_cast<unsigned>(ceil_div(op.n, DN_TCOLS)));
+    if (vec)
+      hipLaunchKernelGGL((gemv_t_kernel<TV, TB, true>), g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A, op.lda,
+                         x, xs, coef, yprev, y, side_dst, side_len);
+    else
+      hipLaunchKernelGGL((gemv_t_kernel<TV, TB, false>), g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A,
+                         op.lda, x, xs, coef, yprev, y, side_dst, side_len);
   } else {
     const int nslab = static_cast<int>(ceil_div(op.n, DN_SLAB));
     TB *part = reinterpret_cast<TB *>(op.dpart);
-    hipLaunchKernelGGL((gemv_n_kernel<TV, TB>), dim3(ceil_div(op.m, DN_ROWS), nslab), dim3(DN_THREADS), 0,
-                       P->stream, op.m, op.n, A, op.lda, x, xs, part, side_dst, side_len);
+    const dim3 g(static_cast<unsigned>(ceil_div(op.m, DN_ROWS)), nslab);
+    if (vec)
+      hipLaunchKernelGGL((gemv_n_kernel<TV, TB, true>), g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A,
+                         op.lda, x, xs, part, side_dst, side_len);
+    else
+      hipLaunchKernelGGL((gemv_n_kernel<TV, TB, false>), g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A,
+                         op.lda, x, xs, part, side_dst, side_len);
     hipLaunchKernelGGL((gemv_n_fixup_kernel<TB>), dim3(ceil_div(op.m, 256)), dim3(256), 0, P->stream,
                        op.m, nslab, part, xs, coef, yprev, y);
   }

@@ -266,7 +266,7 @@ def test_rotate_matches_numpy(S, L, pc, kc):
 
 # --- dense mat-vecs -------------------------------------------------------------------
 
-@pytest.mark.parametrize("m,n", [(1000, 700), (513, 257), (64, 3000), (20000, 300)])
+@pytest.mark.parametrize("m,n", [(1000, 700), (513, 257), (64, 3000), (20000, 300), (1002, 300), (1004, 33)])
 @pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
 def test_dense_matvec_matches_numpy(S, m, n, store):
     import torch
