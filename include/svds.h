@@ -170,8 +170,23 @@ int svds_csr_solve(const svds_csr *A, const svds_opts *opts,
 int svds_dense_solve(const svds_dense *A, const svds_opts *opts,
                      double *U, double *S, double *V, svds_info *info);
 
-/* Many independent CSR problems with the same options (k, p, tol, ...).
- * U[i], S[i], V[i] are per-instance device buffers; infos may be NULL. */
+/* Many independent CSR problems with the same options (k, p, tol, maxit,
+ * precision, flags), solved in lockstep: the problems are stacked as one
+ * block-diagonal matrix (each padded to a multiple of 256 rows and columns)
+ * and every kernel launch serves all of them; projections, norms and
+ * residuals are reduced per problem, the small SVDs run one workgroup per
+ * problem.  Problems that converge early keep iterating until all have
+ * converged or maxit cycles ran; each reports its own estimates, breakdowns
+ * and residuals, the cycle counts are those of the batch.
+ *   - U[i] (m_i x k, ld m_i), S[i] (k), V[i] (n_i x k, ld n_i): per-problem
+ *     FP64 device outputs; infos (count entries) may be NULL.
+ *   - All problems must share the value type (F64 or F32).
+ *   - Start vectors: opts->v0, if given, is the concatenation of the
+ *     problems' start vectors (sum of n_i doubles, unpadded); otherwise
+ *     problem i draws Philox stream 0 of seed opts->seed + i.
+ *   - Limits: p <= 62 (one-workgroup small SVD) and k + 1 <= 64, else
+ *     SVDS_EUNSUPPORTED; sums of padded rows, columns and nnz < 2^31.
+ * Returns SVDS_NOT_CONVERGED if any problem did not converge. */
 int svds_csr_solve_batched(int32_t count, const svds_csr *As, const svds_opts *opts,
                            double *const *U, double *const *S, double *const *V,
                            svds_info *infos);

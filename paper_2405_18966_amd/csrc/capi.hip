@@ -35,19 +35,6 @@ extern "C" int svds_dense_solve(const svds_dense *A, const svds_opts *opts, doub
   return rc;
 }
 
-extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const svds_opts *opts,
-                                      double *const *U, double *const *S, double *const *V,
-                                      svds_info *infos) {
-  if (count < 0 || (count > 0 && (!As || !opts || !U || !S || !V))) return SVDS_EINVAL;
-  int worst = SVDS_OK;
-  for (int32_t i = 0; i < count; ++i) {
-    const int rc = svds_csr_solve(&As[i], opts, U[i], S[i], V[i], infos ? &infos[i] : nullptr);
-    if (rc < 0) return rc;
-    worst = std::max(worst, rc);
-  }
-  return worst;
-}
-
 extern "C" int svds_residuals_csr(const svds_csr *A, int32_t k, const double *U, const double *S,
                                   const double *V, double *res_av, double *res_atu, void *stream) {
   if (!A || k < 1 || !U || !S || !V || !res_av || !res_atu) return SVDS_EINVAL;
@@ -121,7 +108,7 @@ extern "C" int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *
     hipLaunchKernelGGL((spmv_csr_kernel<TV, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0, st, items, \
                        A->row_ptr, A->col_idx, static_cast<const TV *>(A->val),                     \
                        static_cast<const TB *>(x), x_scale, coef, static_cast<const TB *>(yprev),   \
-                       static_cast<TB *>(y), reinterpret_cast<TB *>(parts), nullptr, 0);             \
+                       static_cast<TB *>(y), reinterpret_cast<TB *>(parts), nullptr, 0, nullptr);    \
     if (sp.nlong)                                                                                   \
       hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(sp.nlong), dim3(WAVE), 0, \
                          st, lr, sp.nlong, reinterpret_cast<TB *>(parts), x_scale, coef,            \

@@ -124,8 +124,11 @@ __device__ __forceinline__ int jacobi_pair(double *__restrict__ wi, double *__re
 // (ties: lower column first), outputs, eq. (4) estimates, restarted T.
 // W, Vh: p rows, leading dimensions ldw, ldv.  sv/rank: block-shared
 // scratch of p entries.  beta = T(p, p+1) read before T is rewritten.
+// Entry (r, c) of T is T[(r (p+1) + c) ts] (ts = 1, or the number of
+// problems of a batch whose projected matrices are interleaved).
 __device__ inline void jacobi_finish(const double *W, int64_t ldw, const double *Vh, int64_t ldv, int p,
                                      int k, double tol, double beta, int sweeps, double *__restrict__ T,
+                                     int64_t ts,
                                      double *__restrict__ Uk, double *__restrict__ Vext,
                                      double *__restrict__ sig, double *__restrict__ res,
                                      double *__restrict__ rho, int *__restrict__ flags,
@@ -189,7 +192,7 @@ __device__ inline void jacobi_finish(const double *W, int64_t ldw, const double 
     double v = 0.0;
     if (r < k && c == r) v = sig[r];
     else if (r < k && c == k) v = rho[r];
-    T[idx] = v;
+    T[idx * ts] = v;
   }
 }
 
@@ -202,10 +205,11 @@ __device__ __forceinline__ double jacobi_tol(int rows) {
 // Single-workgroup schedule (p <= JAC_SMALL_P, one row per lane).  Dynamic
 // LDS: W and Vh (pe x pe each, pe = p rounded up to even), sv, rank.
 // ---------------------------------------------------------------------------
-static __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
-    double *__restrict__ T, int p, int k, double tol, double *__restrict__ Uk, double *__restrict__ Vext,
-    double *__restrict__ sig, double *__restrict__ res, double *__restrict__ rho, int *__restrict__ flags,
-    double *__restrict__ sigma_est) {
+__device__ inline void small_svd_body(double *__restrict__ T, int64_t ts, int p, int k, double tol,
+                                      double *__restrict__ Uk, double *__restrict__ Vext,
+                                      double *__restrict__ sig, double *__restrict__ res,
+                                      double *__restrict__ rho, int *__restrict__ flags,
+                                      double *__restrict__ sigma_est) {
   extern __shared__ double smem[];
   __shared__ int rot_count;
   __shared__ double s_beta;
@@ -218,10 +222,10 @@ static __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
   double *sv = Vh + pe * pe;
   int *rank = reinterpret_cast<int *>(sv + pe);
 
-  if (tid == 0) s_beta = T[(p - 1) * ld + p];
+  if (tid == 0) s_beta = T[((p - 1) * ld + p) * ts];
   for (int idx = tid; idx < pe * pe; idx += blockDim.x) {
     const int r = idx % pe, c = idx / pe;
-    W[idx] = (r < p && c < p) ? T[r * ld + c] : 0.0;
+    W[idx] = (r < p && c < p) ? T[(r * ld + c) * ts] : 0.0;
     Vh[idx] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -245,8 +249,26 @@ static __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
     if (rot_count == 0) break;
     __syncthreads();
   }
-  jacobi_finish(W, pe, Vh, pe, p, k, tol, s_beta, sweeps, T, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
+  jacobi_finish(W, pe, Vh, pe, p, k, tol, s_beta, sweeps, T, ts, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
                 rank);
+}
+
+static __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
+    double *__restrict__ T, int p, int k, double tol, double *__restrict__ Uk, double *__restrict__ Vext,
+    double *__restrict__ sig, double *__restrict__ res, double *__restrict__ rho, int *__restrict__ flags,
+    double *__restrict__ sigma_est) {
+  small_svd_body(T, 1, p, k, tol, Uk, Vext, sig, res, rho, flags, sigma_est);
+}
+
+// One workgroup per problem of a batch (interleaved T, per-problem outputs
+// at fixed strides: Uk p*k, Vext (p+1)(k+1), sig/res/rho k, flags 4).
+static __global__ __launch_bounds__(JAC_THREADS) void bsmall_svd_kernel(
+    double *__restrict__ T, int nb, int p, int k, double tol, double *__restrict__ Uk, double *__restrict__ Vext,
+    double *__restrict__ sig, double *__restrict__ res, double *__restrict__ rho, int *__restrict__ flags,
+    double *__restrict__ sigma_est) {
+  const int64_t b = blockIdx.x;
+  small_svd_body(T + b, nb, p, k, tol, Uk + b * p * k, Vext + b * (p + 1) * (k + 1), sig + b * k, res + b * k,
+                 rho + b * k, flags + 4 * b, sigma_est + b);
 }
 
 __host__ __device__ inline size_t small_svd_lds_bytes(int p) {
@@ -359,7 +381,7 @@ static __global__ __launch_bounds__(JAC_THREADS) void bjac_finish_kernel(
     s_sweeps = s;
   }
   __syncthreads();
-  jacobi_finish(W, p, Vh, p, p, k, tol, s_beta, s_sweeps, T, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
+  jacobi_finish(W, p, Vh, p, p, k, tol, s_beta, s_sweeps, T, 1, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
                 rank);
 }
 

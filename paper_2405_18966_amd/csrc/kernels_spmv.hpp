@@ -18,6 +18,13 @@
 //    the grid.  The solver uses it to write the normalized previous Lanczos
 //    vector into its basis column while the product consumes the
 //    unnormalized copy.
+//
+// Several independent problems can share one launch as the blocks of a
+// block-diagonal matrix (the batched solver): every item then carries its
+// problem's index (item.z of a MULTI item, LongRow::inst of a long row) and
+// the scale factors xs, coef are per-problem arrays; the side task finds the
+// problem of entry i from x_tile_inst[i / 256] (problems are padded to
+// multiples of 256 rows).  A single problem has index 0 everywhere.
 #pragma once
 #include "common.hpp"
 
@@ -28,34 +35,38 @@ constexpr int SPMV_NNZ_BLK = 2048;
 constexpr int SPMV_ROWS_BLK = 256;
 constexpr int SPMV_PIECE = 4096;
 
-// item.x >= 0: MULTI rows [x, y).   item.x < 0: PIECE of long row id -x-1,
-// nonzeros [z, w), written to partials[item.y].
+// item.x >= 0: MULTI rows [x, y) of problem z.   item.x < 0: PIECE of long
+// row id -x-1, nonzeros [z, w), written to partials[item.y].
 struct LongRow {
-  int32_t row, first_piece, npieces, pad;
+  int32_t row, first_piece, npieces, inst;
 };
+constexpr int SPMV_TILE_SHIFT = 8;  // 256-row tiles of the problem map
 
 template <typename TV, typename TB>
 __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     const int4 *__restrict__ items, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const TV *__restrict__ val, const TB *__restrict__ x, const double *__restrict__ xs_ptr,
     const double *__restrict__ coef_ptr, const TB *__restrict__ yprev, TB *__restrict__ y,
-    TB *__restrict__ partials, TB *__restrict__ side_dst, int64_t side_len) {
+    TB *__restrict__ partials, TB *__restrict__ side_dst, int64_t side_len,
+    const int32_t *__restrict__ x_tile_inst) {
   __shared__ TB prod[SPMV_NNZ_BLK];
   __shared__ TB red[SPMV_THREADS / WAVE];
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1);
   const int wv = tid / WAVE;
-  const TB xs = xs_ptr ? static_cast<TB>(*xs_ptr) : TB(1);
-  const TB coef = coef_ptr ? static_cast<TB>(*coef_ptr) : TB(0);
 
   if (side_dst) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * SPMV_THREADS + tid; i < side_len;
-         i += static_cast<int64_t>(gridDim.x) * SPMV_THREADS)
-      side_dst[i] = x[i] * xs;
+         i += static_cast<int64_t>(gridDim.x) * SPMV_THREADS) {
+      const int inst = x_tile_inst ? x_tile_inst[i >> SPMV_TILE_SHIFT] : 0;
+      side_dst[i] = x[i] * (xs_ptr ? static_cast<TB>(xs_ptr[inst]) : TB(1));
+    }
   }
 
   const int4 it = items[blockIdx.x];
   if (it.x >= 0) {
+    const TB xs = xs_ptr ? static_cast<TB>(xs_ptr[it.z]) : TB(1);
+    const TB coef = coef_ptr ? static_cast<TB>(coef_ptr[it.z]) : TB(0);
     const int r0 = it.x, r1 = it.y;
     const int base = row_ptr[r0];
     const int cnt = row_ptr[r1] - base;
@@ -110,9 +121,9 @@ __global__ __launch_bounds__(WAVE) void spmv_longrow_fixup_kernel(const LongRow 
                                                                   TB *__restrict__ y) {
   const int i = blockIdx.x;
   if (i >= nlong) return;
-  const TB xs = xs_ptr ? static_cast<TB>(*xs_ptr) : TB(1);
-  const TB coef = coef_ptr ? static_cast<TB>(*coef_ptr) : TB(0);
   const LongRow L = longrows[i];
+  const TB xs = xs_ptr ? static_cast<TB>(xs_ptr[L.inst]) : TB(1);
+  const TB coef = coef_ptr ? static_cast<TB>(coef_ptr[L.inst]) : TB(0);
   TB t = 0;
   for (int q = threadIdx.x; q < L.npieces; q += WAVE) t += partials[L.first_piece + q];
   t = wave_sum(t);

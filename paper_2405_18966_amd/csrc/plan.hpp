@@ -36,9 +36,14 @@ struct SpmvPlan {
   double *partials = nullptr;  // npieces (TB <= 8 bytes)
   std::vector<int4> h_items;
   std::vector<LongRow> h_long;
+  const int32_t *x_tile_inst = nullptr;  // problem of each 256-entry tile of x (batched), or null
 };
 
-void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp);
+// Work items of a CSR product.  With seg_end (nseg consecutive row ranges
+// ending at seg_end[g], one per problem of a batch) items never cross a range
+// and carry the range index g; without it there is one range, index 0.
+void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp, const int64_t *seg_end = nullptr,
+                      int nseg = 1);
 
 // ---------------------------------------------------------------------------
 // Per-kernel-class accounting and optional device timing with event pairs.

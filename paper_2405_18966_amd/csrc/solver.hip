@@ -16,6 +16,7 @@
 #include "kernels_jacobi.hpp"
 #include "kernels_misc.hpp"
 #include "kernels_dense.hpp"
+#include "kernels_batch.hpp"
 
 namespace svds {
 
@@ -38,35 +39,38 @@ static inline unsigned grid_for(int64_t work, int64_t per_block, int64_t gmax = 
 // ---------------------------------------------------------------------------
 // SpMV work items (host, at plan time)
 // ---------------------------------------------------------------------------
-void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp) {
+void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp, const int64_t *seg_end, int nseg) {
   sp.h_items.clear();
   sp.h_long.clear();
   int npieces = 0;
   int64_t r = 0;
-  while (r < m) {
-    const int64_t len = rp[r + 1] - rp[r];
-    if (len > SPMV_NNZ_BLK) {
-      const int np = static_cast<int>(ceil_div(len, SPMV_PIECE));
-      const int lr = static_cast<int>(sp.h_long.size());
-      sp.h_long.push_back(LongRow{static_cast<int32_t>(r), npieces, np, 0});
-      for (int q = 0; q < np; ++q) {
-        const int64_t z0 = rp[r] + static_cast<int64_t>(q) * SPMV_PIECE;
-        const int64_t z1 = std::min<int64_t>(rp[r + 1], z0 + SPMV_PIECE);
-        sp.h_items.push_back(make_int4(-lr - 1, npieces + q, static_cast<int>(z0), static_cast<int>(z1)));
+  for (int g = 0; g < (seg_end ? nseg : 1); ++g) {
+    const int64_t e = seg_end ? seg_end[g] : m;  // items never cross a problem boundary
+    while (r < e) {
+      const int64_t len = rp[r + 1] - rp[r];
+      if (len > SPMV_NNZ_BLK) {
+        const int np = static_cast<int>(ceil_div(len, SPMV_PIECE));
+        const int lr = static_cast<int>(sp.h_long.size());
+        sp.h_long.push_back(LongRow{static_cast<int32_t>(r), npieces, np, g});
+        for (int q = 0; q < np; ++q) {
+          const int64_t z0 = rp[r] + static_cast<int64_t>(q) * SPMV_PIECE;
+          const int64_t z1 = std::min<int64_t>(rp[r + 1], z0 + SPMV_PIECE);
+          sp.h_items.push_back(make_int4(-lr - 1, npieces + q, static_cast<int>(z0), static_cast<int>(z1)));
+        }
+        npieces += np;
+        ++r;
+        continue;
       }
-      npieces += np;
-      ++r;
-      continue;
+      const int64_t r0 = r;
+      int64_t z = 0;
+      while (r < e && r - r0 < SPMV_ROWS_BLK) {
+        const int64_t l = rp[r + 1] - rp[r];
+        if (l > SPMV_NNZ_BLK || z + l > SPMV_NNZ_BLK) break;
+        z += l;
+        ++r;
+      }
+      sp.h_items.push_back(make_int4(static_cast<int>(r0), static_cast<int>(r), g, 0));
     }
-    const int64_t r0 = r;
-    int64_t z = 0;
-    while (r < m && r - r0 < SPMV_ROWS_BLK) {
-      const int64_t l = rp[r + 1] - rp[r];
-      if (l > SPMV_NNZ_BLK || z + l > SPMV_NNZ_BLK) break;
-      z += l;
-      ++r;
-    }
-    sp.h_items.push_back(make_int4(static_cast<int>(r0), static_cast<int>(r), 0, 0));
   }
   sp.nitems = static_cast<int>(sp.h_items.size());
   sp.nlong = static_cast<int>(sp.h_long.size());
@@ -264,11 +268,11 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     if (op.vt == SVDS_F64)
       hipLaunchKernelGGL((spmv_csr_kernel<double, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
                          P->stream, sp.items, rp, ci, static_cast<const double *>(val), x, xs, coef,
-                         yprev, y, parts, side_dst, side_len);
+                         yprev, y, parts, side_dst, side_len, sp.x_tile_inst);
     else
       hipLaunchKernelGGL((spmv_csr_kernel<float, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
                          P->stream, sp.items, rp, ci, static_cast<const float *>(val), x, xs, coef,
-                         yprev, y, parts, side_dst, side_len);
+                         yprev, y, parts, side_dst, side_len, sp.x_tile_inst);
     if (sp.nlong > 0)
       hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(sp.nlong), dim3(WAVE), 0,
                          P->stream, sp.longrows, sp.nlong, parts, xs, coef, yprev, y);
@@ -728,7 +732,11 @@ struct PlanGuard {
 };
 }  // namespace
 
-extern "C" int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, svds_plan **plan) {
+// Plan of a CSR matrix.  seg_rows / seg_cols (nseg entries, or null): ends of
+// the row ranges of A and of A^T that belong to the problems of a batch
+// stacked block-diagonally; product work items never cross them.
+static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_plan **plan,
+                                const int64_t *seg_rows, const int64_t *seg_cols, int nseg) {
   if (!A || !opts || !plan) return SVDS_EINVAL;
   *plan = nullptr;
   if (A->m < 1 || A->n < 1 || A->nnz < 0 || A->nnz >= (int64_t(1) << 31) || A->m >= (int64_t(1) << 31) ||
@@ -759,7 +767,7 @@ extern "C" int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, sv
   if (hrp[0] != 0 || hrp[A->m] != A->nnz) return SVDS_EINVAL;
   for (int64_t i = 0; i < A->m; ++i)
     if (hrp[i + 1] < hrp[i]) return SVDS_EINVAL;
-  build_spmv_items(hrp.data(), A->m, op.fwd);
+  build_spmv_items(hrp.data(), A->m, op.fwd, seg_rows, nseg);
   // A^T items need the column counts: computed after the device transpose,
   // so size the arena with a bound first (one item per column is the max).
   op.bwd.nitems = static_cast<int>(std::max<int64_t>(1, A->n + ceil_div(A->nnz, SPMV_PIECE) + 1));
@@ -773,7 +781,7 @@ extern "C" int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, sv
   int4 *bi = op.bwd.items;
   LongRow *bl = op.bwd.longrows;
   double *bp = op.bwd.partials;
-  build_spmv_items(htrp.data(), A->n, op.bwd);
+  build_spmv_items(htrp.data(), A->n, op.bwd, seg_cols, nseg);
   if (op.bwd.nitems > bwd_items_cap || op.bwd.nlong > bwd_long_cap || op.bwd.npieces > bwd_pieces_cap)
     return SVDS_EDEVICE;
   op.bwd.items = bi;
@@ -782,6 +790,10 @@ extern "C" int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, sv
   if ((rc = upload_spmv(P, op.fwd)) || (rc = upload_spmv(P, op.bwd))) return rc;
   *plan = guard.release();
   return SVDS_OK;
+}
+
+extern "C" int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, svds_plan **plan) {
+  return plan_create_csr_impl(A, opts, plan, nullptr, nullptr, 0);
 }
 
 extern "C" int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts, svds_plan **plan) {
@@ -1166,3 +1178,5 @@ int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, doub
   HIP_TRY(hipGetLastError());
   return SVDS_OK;
 }
+
+#include "batched_impl.hpp"

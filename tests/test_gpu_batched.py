@@ -1,0 +1,142 @@
+"""Batched (lockstep) solver: many uneven CSR problems in one call, each
+against the FP64 CPU oracle run on that problem alone with the same start
+vector (Philox stream 0 of seed + problem index)."""
+import numpy as np
+import pytest
+
+from paper_2405_18966_amd import inputs
+from oracle import svds_ref
+from oracle.svds_ref import as_operator
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_18966_amd import svds
+    return svds
+
+
+def _batch(S, As, k, p, tol, maxit=2000, precision=0, seed=0, v0=None, flags=0):
+    import torch
+    dev = [S.csr_to_device(A) for A in As]
+    v0d = None if v0 is None else torch.from_numpy(v0).cuda()
+    opts = S.make_opts(k, p, tol, maxit, precision=precision, seed=seed, v0=v0d, flags=flags)
+    res, rc = S.svds_csr_solve_batched([d[0] for d in dev], opts)
+    torch.cuda.synchronize()
+    return res, rc
+
+
+def _check_problem(A, r, Sr, tol, rtol):
+    Ug, Sg, Vg = r.U.cpu().numpy(), r.S.cpu().numpy(), r.V.cpu().numpy()
+    k = len(Sg)
+    np.testing.assert_allclose(Sg, Sr, rtol=rtol)
+    assert np.abs(Ug.T @ Ug - np.eye(k)).max() <= 1e-12
+    assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-12
+    r1, r2 = svds_ref.explicit_residuals(as_operator(A), Ug, Sg, Vg)
+    assert (r2 / Sg).max() <= 2 * tol
+    # the library's own FP64 residuals agree with the CPU ones
+    assert abs(r.info["max_res_true"] - (r2 / Sg).max()) <= 1e-12 + 1e-6 * (r2 / Sg).max()
+
+
+def _uneven(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        m = int(rng.integers(300, 3000))
+        n = int(rng.integers(m // 2 + 20, m + 1))
+        out.append(inputs.sparse_uniform(m, n, int(0.01 * m * n), int(rng.integers(2**62))))
+    return out
+
+
+def test_batched_fp64_matches_oracle_per_problem(S):
+    As = _uneven(7, 11)
+    k, p, tol, seed = 5, 15, 1e-10, 100
+    res, rc = _batch(S, As, k, p, tol, seed=seed)
+    assert rc == 0
+    for b, (A, r) in enumerate(zip(As, res)):
+        Ur, Sr, Vr, info = svds_ref.svds(as_operator(A), k, p, tol, 2000, seed=seed + b)
+        assert r.info["converged"] == 1
+        _check_problem(A, r, Sr, tol, 1e-10)
+
+
+def test_batched_agrees_with_single_solves(S):
+    import torch
+    As = _uneven(4, 12)
+    k, p, tol, seed = 4, 12, 1e-10, 7
+    res, rc = _batch(S, As, k, p, tol, seed=seed)
+    for b, (A, r) in enumerate(zip(As, res)):
+        Ad, keep = S.csr_to_device(A)
+        one = S.svds_csr_solve(Ad, S.make_opts(k, p, tol, 2000, seed=seed + b))
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(r.S.cpu().numpy(), one.S.cpu().numpy(), rtol=1e-11)
+
+
+def test_batched_explicit_start_vectors(S):
+    As = _uneven(3, 13)
+    k, p, tol = 3, 10, 1e-10
+    v0s = [inputs.start_vector(A.n, 500 + b) for b, A in enumerate(As)]
+    res, rc = _batch(S, As, k, p, tol, v0=np.concatenate(v0s))
+    assert rc == 0
+    for A, v0, r in zip(As, v0s, res):
+        Ur, Sr, Vr, info = svds_ref.svds(as_operator(A), k, p, tol, 2000, v0=v0)
+        _check_problem(A, r, Sr, tol, 1e-10)
+
+
+def test_batched_mixed_precision(S):
+    """FP32 cycles then FP64 refinement, per problem, against the FP64 oracle."""
+    As = _uneven(6, 14)
+    k, p, tol, seed = 8, 24, 1e-8, 3
+    res, rc = _batch(S, As, k, p, tol, precision=1, seed=seed)
+    assert rc == 0
+    for b, (A, r) in enumerate(zip(As, res)):
+        Ur, Sr, Vr, info = svds_ref.svds(as_operator(A), k, p, 1e-12, 2000, seed=seed + b)
+        assert r.info["cycles_fp32"] >= 1 and r.info["cycles_fp64"] >= 1
+        _check_problem(A, r, Sr, tol, 1e-8)
+
+
+def test_batched_rank_deficient_and_empty_rows(S):
+    """A problem with empty rows/columns and a repeated spectrum beside
+    ordinary ones: breakdowns stay inside their problem."""
+    d = np.zeros(40)
+    d[:12] = [5, 5, 5, 4, 4, 3, 3, 2, 2, 1, 1, 1]
+    Adiag = inputs.diag_matrix(60, 40, d)
+    As = [inputs.sparse_uniform(500, 300, 3000, 21), Adiag, inputs.sparse_uniform(700, 690, 5000, 22)]
+    k, p, tol = 4, 14, 1e-10
+    res, rc = _batch(S, As, k, p, tol, seed=9)
+    assert rc == 0
+    np.testing.assert_allclose(res[1].S.cpu().numpy(), [5, 5, 5, 4], rtol=1e-12)
+    assert res[1].info["breakdowns"] >= 1
+    for b in (0, 2):
+        Ur, Sr, Vr, info = svds_ref.svds(as_operator(As[b]), k, p, tol, 2000, seed=9 + b)
+        _check_problem(As[b], res[b], Sr, tol, 1e-10)
+
+
+def test_batched_validation(S):
+    As = _uneven(2, 15)
+    with pytest.raises(S.SvdsError):
+        _batch(S, As, 5, 70, 1e-8)  # p > 62: one-workgroup small SVD only
+
+
+def test_batched_full_size_256_problems(S):
+    """The 256-problem workload (m ~ U{500..20000}, n ~ U{m/2..m}, 0.5%
+    density, k=8, p=24, mixed): every problem's outputs checked by
+    orthogonality and by the library's FP64 residuals, a sample of problems
+    against the oracle."""
+    As = inputs.config_matrix(5)
+    k, p, tol, seed = 8, 24, 1e-8, 2405005
+    res, rc = _batch(S, As, k, p, tol, precision=1, seed=seed)
+    assert rc == 0
+    for r in res:
+        assert r.info["converged"] == 1 and r.info["max_res_true"] <= 2 * tol
+    import torch
+    for b in [0, 1, 37, 128, 255]:
+        Ug, Vg = res[b].U, res[b].V
+        eye = torch.eye(k, dtype=torch.float64, device=Ug.device)
+        assert float((Ug.T @ Ug - eye).abs().max()) <= 1e-12
+        assert float((Vg.T @ Vg - eye).abs().max()) <= 1e-12
+        Ur, Sr, Vr, info = svds_ref.svds(as_operator(As[b]), k, p, 1e-12, 2000, seed=seed + b)
+        np.testing.assert_allclose(res[b].S.cpu().numpy(), Sr, rtol=1e-8)
