@@ -123,6 +123,44 @@ def mixed_vs_fp64(S, inputs, np, torch):
     return out
 
 
+def batched_vs_loop(S, inputs, np, torch):
+    """The 256-problem workload (m ~ U{500..20000}, n ~ U{m/2..m}, 0.5%
+    density, N(0,1), k=8, p=24, tol=1e-8): one lockstep batched call against
+    a loop of single-problem solves, mixed and FP64; median of 3 after one
+    warm-up each (the loop: one timed pass).  Problems/s = 256 / wall time."""
+    As = inputs.config_matrix(5)
+    dev = [S.csr_to_device(A) for A in As]
+    seed = inputs.CONFIG_SEEDS[5]
+    out = {"problems": len(As), "nnz_total": int(sum(A.nnz for A in As))}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        opts = S.make_opts(8, 24, 1e-8, 2000, precision=prec, seed=seed)
+        res, rc = S.svds_csr_solve_batched([d[0] for d in dev], opts)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            res, rc = S.svds_csr_solve_batched([d[0] for d in dev], opts)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        tb = sorted(ts)[1]
+        sig_b = [r.S.cpu().numpy() for r in res]
+        ok = rc == 0 and all(r.info["converged"] == 1 and r.info["max_res_true"] <= 2e-8 for r in res)
+        t0 = time.perf_counter()
+        worst = 0.0
+        for b, d in enumerate(dev):
+            one = S.svds_csr_solve(d[0], S.make_opts(8, 24, 1e-8, 2000, precision=prec, seed=seed + b))
+            torch.cuda.synchronize()
+            s1 = one.S.cpu().numpy()
+            worst = max(worst, float(np.max(np.abs(s1 - sig_b[b]) / s1)))
+        tl = time.perf_counter() - t0
+        out[name] = {"batched_ms": round(tb * 1e3, 2), "looped_ms": round(tl * 1e3, 2),
+                     "batched_problems_per_s": round(len(As) / tb, 2),
+                     "looped_problems_per_s": round(len(As) / tl, 2), "x": round(tl / tb, 2),
+                     "cycles": res[0].info["cycles"], "all_converged": bool(ok),
+                     "sigma_rel_diff_batched_vs_looped": worst}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +168,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed vs FP64 comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched vs looped comparison")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
     args = ap.parse_args()
@@ -234,6 +273,11 @@ def main():
         log("mixed vs FP64 ...")
         mixed = mixed_vs_fp64(S, inputs, np, torch)
 
+    batched = None
+    if not args.no_batched:
+        log("batched vs looped ...")
+        batched = batched_vs_loop(S, inputs, np, torch)
+
     cpu = None
     if not args.no_cpu and rank == 0:
         cpu = cpu_baseline(A, v0, k, p, tol)
@@ -244,7 +288,8 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 2),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic", "config": dict(WORKLOAD, parallelism="single GPU"),
-           "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "mixed_vs_fp64": mixed}
+           "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "mixed_vs_fp64": mixed,
+           "batched_vs_looped": batched}
     print(json.dumps(out), flush=True)
 
 

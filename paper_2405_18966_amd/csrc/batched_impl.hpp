@@ -8,9 +8,11 @@
 // bases and the vectors; products therefore run unchanged, with per-problem
 // scale factors.  Everything that reduces over a vector (CGS2 projections,
 // norms, residuals) is segmented per problem; the small SVDs run one
-// workgroup per problem.  Problems that converge early keep iterating with
-// the rest (their Ritz values only sharpen); every problem reports the
-// estimates of the final cycle.
+// workgroup per problem.  A problem whose test passes is frozen at the next
+// restart: the restart rotation puts its Ritz vectors in the leading basis
+// columns, its restart panels become the identity (later rotations copy those
+// columns exactly) and every kernel skips its work from then on; the outputs
+// are formed for all problems at the end.
 namespace svds {
 
 struct BSrc {
@@ -60,8 +62,11 @@ struct Batch {
   double *tmp_m = nullptr, *tmp_n = nullptr, *ones_k = nullptr;
   double *h1 = nullptr, *h2 = nullptr, *part = nullptr, *rho_b = nullptr;  // basis-typed scratch (<= 8 B)
   int *flags = nullptr, *bd = nullptr;
+  int32_t *active = nullptr, *freeze = nullptr;  // per-problem work mask, problems to freeze
   double **optr = nullptr;  // output pointer tables U[nb], V[nb], S[nb]
   int *h_flags = nullptr;   // pinned, 4 per problem
+  std::vector<int32_t> h_active;
+  std::vector<int> conv_cycle;  // cycle (of the current phase) at which each problem converged
   ~Batch() {
     if (P) svds_plan_destroy(P);
     if (mem) (void)hipFree(mem);
@@ -111,38 +116,38 @@ static int b_cgs2(Batch &Bt, Lanczos<TB> &Lz, int side_v, const TB *Q, int j, co
   const TB *src = w;
   if (j > 0) {
     ACC_BEFORE(SVDS_KC_CGS_PROJ);
-    hipLaunchKernelGGL((bproj_kernel<TB>), dim3(nt), dim3(BT), 0, P->stream, Q, ldq, j, w, part);
+    hipLaunchKernelGGL((bproj_kernel<TB>), dim3(nt), dim3(BT), 0, P->stream, Q, ldq, j, w, tile, Bt.active, part);
     B_LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_CGS_PROJ, sb * L * (j + 1), 2.0 * L * j);
     ACC_BEFORE(SVDS_KC_CGS_REDUCE);
-    hipLaunchKernelGGL((bseg_sum_kernel<TB>), dim3(Bt.nb), dim3(BHJ), 0, P->stream, part, nt, j, Bt.dp, side_v, h1,
-                       BHJ);
+    hipLaunchKernelGGL((bseg_sum_kernel<TB>), dim3(Bt.nb), dim3(BHJ), 0, P->stream, part, nt, j, Bt.dp, side_v,
+                       Bt.active, h1, BHJ);
     B_LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * nt * j, 0.0);
     ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
     if (j <= 32)
       hipLaunchKernelGGL((bupd_proj_kernel<TB, 32>), dim3(nt), dim3(BT), 0, P->stream, Q, ldq, j, w, h1, BHJ, tile,
-                         w1, part);
+                         Bt.active, w1, part);
     else
       hipLaunchKernelGGL((bupd_proj_kernel<TB, 64>), dim3(nt), dim3(BT), 0, P->stream, Q, ldq, j, w, h1, BHJ, tile,
-                         w1, part);
+                         Bt.active, w1, part);
     B_LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * (j + 2), 4.0 * L * j);
     ACC_BEFORE(SVDS_KC_CGS_REDUCE);
-    hipLaunchKernelGGL((bseg_sum_kernel<TB>), dim3(Bt.nb), dim3(BHJ), 0, P->stream, part, nt, j, Bt.dp, side_v, h2,
-                       BHJ);
+    hipLaunchKernelGGL((bseg_sum_kernel<TB>), dim3(Bt.nb), dim3(BHJ), 0, P->stream, part, nt, j, Bt.dp, side_v,
+                       Bt.active, h2, BHJ);
     B_LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * nt * j, 0.0);
     src = w1;
   }
   ACC_BEFORE(SVDS_KC_CGS_UPDNORM);
-  hipLaunchKernelGGL((bupd_norm_kernel<TB>), dim3(nt), dim3(BT), 0, P->stream, Q, ldq, j, src, h2, BHJ, tile, out,
-                     Bt.npart);
+  hipLaunchKernelGGL((bupd_norm_kernel<TB>), dim3(nt), dim3(BT), 0, P->stream, Q, ldq, j, src, h2, BHJ, tile,
+                     Bt.active, out, Bt.npart);
   B_LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * (j + 2), 2.0 * L * j + 2.0 * L);
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
   hipLaunchKernelGGL((bfinish_norm_kernel<TB>), dim3(Bt.nb), dim3(CGS_THREADS), 0, P->stream, Bt.npart, Bt.dp,
-                     side_v, mode, t_off >= 0 ? Bt.T + t_off * Bt.nb : nullptr, xs, Bt.sigma_est, Bt.bd,
+                     side_v, Bt.active, mode, t_off >= 0 ? Bt.T + t_off * Bt.nb : nullptr, xs, Bt.sigma_est, Bt.bd,
                      P->opts.seed, Q, ldq, j, out);
   B_LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_REDUCE, 8.0 * nt, 0.0);
@@ -162,7 +167,7 @@ template <typename TB> static int b_lanczos(Batch &Bt, Lanczos<TB> &Lz, int i0) 
     if (rc) return rc;
     if (i == p - 1) {
       hipLaunchKernelGGL((bscale_copy_kernel<TB>), dim3(static_cast<unsigned>(std::min<int64_t>(4096, Bt.NT))),
-                         dim3(BT), 0, P->stream, Bt.Ntot, Bt.tile_v, Lz.bv, Bt.xs_v, V + p * Lz.ldv);
+                         dim3(BT), 0, P->stream, Bt.Ntot, Bt.tile_v, Bt.active, Lz.bv, Bt.xs_v, V + p * Lz.ldv);
       B_LAUNCH_CHECK();
       break;
     }
@@ -202,7 +207,7 @@ static int b_small_svd(Batch &Bt, double tol, bool &all_conv) {
   ACC_BEFORE(SVDS_KC_SMALLSVD);
   hipLaunchKernelGGL(bsmall_svd_kernel, dim3(Bt.nb), dim3(std::min(JAC_THREADS, (pe / 2) * WAVE)),
                      small_svd_lds_bytes(p), P->stream, Bt.T, Bt.nb, p, k, tol, Bt.Uk, Bt.Vext, Bt.sig, Bt.res,
-                     Bt.rho, Bt.flags, Bt.sigma_est);
+                     Bt.rho, Bt.flags, Bt.sigma_est, Bt.active);
   B_LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_SMALLSVD, 16.0 * (p + 1) * (p + 1) * Bt.nb, 0.0);
   HIP_TRY(hipMemcpyAsync(Bt.h_flags, Bt.flags, sizeof(int) * 4 * Bt.nb, hipMemcpyDeviceToHost, P->stream));
@@ -210,6 +215,32 @@ static int b_small_svd(Batch &Bt, double tol, bool &all_conv) {
   all_conv = true;
   for (int b = 0; b < Bt.nb; ++b) all_conv = all_conv && Bt.h_flags[4 * b] != 0;
   return P->acc.harvest();
+}
+
+// Problems whose test passed at the last small SVD and that are still
+// active: their Ritz vectors are now in the leading basis columns (the
+// restart rotation just ran); freeze them.
+static int b_freeze_converged(Batch &Bt) {
+  svds_plan *P = Bt.P;
+  std::vector<int32_t> fz(Bt.nb, 0);
+  bool any = false;
+  for (int b = 0; b < Bt.nb; ++b)
+    if (Bt.h_active[b] && Bt.h_flags[4 * b]) fz[b] = 1, Bt.h_active[b] = 0, any = true;
+  if (!any) return SVDS_OK;
+  HIP_TRY(hipMemcpyAsync(Bt.freeze, fz.data(), sizeof(int32_t) * Bt.nb, hipMemcpyHostToDevice, P->stream));
+  hipLaunchKernelGGL(bfreeze_kernel, dim3(Bt.nb), dim3(256), 0, P->stream, Bt.nb, Bt.freeze, Bt.active, Bt.Uk, Bt.Vext,
+                     P->p, P->k);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(P->stream));  // fz is a host temporary
+  return SVDS_OK;
+}
+
+static int b_activate_all(Batch &Bt) {
+  svds_plan *P = Bt.P;
+  Bt.h_active.assign(Bt.nb, 1);
+  HIP_TRY(hipMemcpyAsync(Bt.active, Bt.h_active.data(), sizeof(int32_t) * Bt.nb, hipMemcpyHostToDevice, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return SVDS_OK;
 }
 
 template <typename TB> static int b_restart(Batch &Bt, Lanczos<TB> &Lz) {
@@ -224,6 +255,8 @@ template <typename TB> static int b_restart(Batch &Bt, Lanczos<TB> &Lz) {
                         Lz.ldv);
   if (rc) return rc;
   Lz.cur = nxt;
+  rc = b_freeze_converged(Bt);
+  if (rc) return rc;
   rc = matvec<TB>(P, false, Vn + k * Lz.ldv, Bt.ones, nullptr, nullptr, Lz.wu, nullptr, 0);
   if (rc) return rc;
   TB *rho_b = reinterpret_cast<TB *>(Bt.rho_b);
@@ -231,7 +264,7 @@ template <typename TB> static int b_restart(Batch &Bt, Lanczos<TB> &Lz) {
                      0, P->stream, static_cast<int64_t>(Bt.nb) * k, Bt.rho, rho_b);
   ACC_BEFORE(SVDS_KC_OTHER);
   hipLaunchKernelGGL((bupd_norm_kernel<TB>), dim3(Bt.MT), dim3(BT), 0, P->stream, Un, Lz.ldu, k, Lz.wu, rho_b, k,
-                     Bt.tile_u, Lz.w1u, static_cast<double *>(nullptr));
+                     Bt.tile_u, Bt.active, Lz.w1u, static_cast<double *>(nullptr));
   B_LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_OTHER, sizeof(TB) * double(Bt.Mtot) * (k + 2), 2.0 * Bt.Mtot * k);
   return b_cgs2<TB>(Bt, Lz, 0, Un, k, Lz.w1u, Lz.wu, Lz.bu, MODE_LANCZOS, static_cast<int64_t>(k) * ld + k, Bt.xs_u);
@@ -246,11 +279,16 @@ static int b_run_cycles(Batch &Bt, Lanczos<TB> &Lz, double tol_c, int maxit, boo
   double best = INFINITY;
   int nodec = 0;
   const int k = P->k;
-  int rc = b_lanczos<TB>(Bt, Lz, 0);
+  Bt.conv_cycle.assign(Bt.nb, 0);
+  int rc = b_activate_all(Bt);
+  if (rc) return rc;
+  rc = b_lanczos<TB>(Bt, Lz, 0);
   while (rc == SVDS_OK) {
     ++cycles;
     rc = b_small_svd(Bt, tol_c, conv);
     if (rc) break;
+    for (int b = 0; b < Bt.nb; ++b)
+      if (Bt.h_active[b]) Bt.conv_cycle[b] = cycles;
     if (conv || cycles >= maxit) break;
     if (stagnate) {
       std::vector<double> r(static_cast<size_t>(Bt.nb) * k);
@@ -353,6 +391,8 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
     Bt.part = a.take<double>(static_cast<size_t>(BHJ) * std::max(Bt.MT, Bt.NT));
     Bt.flags = a.take<int>(4 * nb);
     Bt.bd = a.take<int>(nb);
+    Bt.active = a.take<int32_t>(nb);
+    Bt.freeze = a.take<int32_t>(nb);
     Bt.optr = a.take<double *>(3 * nb);
     if (pass == 0) {
       const size_t bytes = a.used;
@@ -421,6 +461,8 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
   svds_plan *P = Bt.P;
   P->op.fwd.x_tile_inst = Bt.tile_v;
   P->op.bwd.x_tile_inst = Bt.tile_u;
+  P->op.fwd.active = Bt.active;
+  P->op.bwd.active = Bt.active;
   HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&Bt.h_flags), sizeof(int) * 4 * count, hipHostMallocDefault));
   P->acc.reset();
   // ---- Alg. 2 for every problem ----
@@ -429,11 +471,14 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
   HIP_TRY(hipMemsetAsync(Bt.T, 0, sizeof(double) * (p + 1) * (p + 1) * count, st));
   bool conv = false;
   int cyc = 0;
+  std::vector<int> cyc32(count, 0);
   if (P->mixed) {
     const double tol32 = std::max(P->tol, 1e-5);
-    rc = b_start<float>(Bt, P->L32, opts->v0, false);
+    rc = b_activate_all(Bt);
+    if (!rc) rc = b_start<float>(Bt, P->L32, opts->v0, false);
     if (!rc) rc = b_run_cycles<float>(Bt, P->L32, tol32, P->maxit, true, cyc, conv);
     P->cycles32 = cyc;
+    cyc32 = Bt.conv_cycle;
     if (!rc) {
       // v1 of the FP64 phase: sum_j Vk(:, j) / sqrt(k) per problem, in FP64
       // (Vk = V32 Vh_k into Vc, then Vc times the constant k-vector)
@@ -445,15 +490,20 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
     if (!rc) {
       HIP_TRY(hipMemsetAsync(Bt.sigma_est, 0, sizeof(double) * count, st));
       HIP_TRY(hipMemsetAsync(Bt.T, 0, sizeof(double) * (p + 1) * (p + 1) * count, st));
-      rc = b_start<double>(Bt, P->L64, Bt.tmp_n, true);
+      rc = b_activate_all(Bt);
+      if (!rc) rc = b_start<double>(Bt, P->L64, Bt.tmp_n, true);
     }
     if (!rc) rc = b_run_cycles<double>(Bt, P->L64, P->tol, std::max(1, P->maxit - cyc), false, cyc, conv);
     P->cycles64 = cyc;
   } else {
-    rc = b_start<double>(Bt, P->L64, opts->v0, false);
+    rc = b_activate_all(Bt);
+    if (!rc) rc = b_start<double>(Bt, P->L64, opts->v0, false);
     if (!rc) rc = b_run_cycles<double>(Bt, P->L64, P->tol, P->maxit, false, cyc, conv);
     P->cycles64 = cyc;
   }
+  if (rc) return rc;
+  std::vector<int> cyc64 = Bt.conv_cycle;
+  rc = b_activate_all(Bt);  // outputs and residuals for every problem
   if (rc) return rc;
   // ---- outputs (Alg. 2 steps 15-16), signs, FP64 residuals ----
   Lanczos<double> &Lz = P->L64;
@@ -516,9 +566,9 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
     svds_info &in = infos[b];
     in = svds_info{};
     in.nconv = Bt.h_flags[4 * b + 1];
-    in.cycles = P->cycles32 + P->cycles64;
-    in.cycles_fp32 = P->cycles32;
-    in.cycles_fp64 = P->cycles64;
+    in.cycles = cyc32[b] + cyc64[b];
+    in.cycles_fp32 = cyc32[b];
+    in.cycles_fp64 = cyc64[b];
     in.breakdowns = hbd[b];
     in.converged = cb ? 1 : 0;
     in.n_spmv = P->n_spmv;

@@ -8,7 +8,8 @@
 // vector and in every work vector, so they change no dot product or norm.
 // A 256-row tile therefore belongs to exactly one problem (tile maps
 // tile_inst); per-tile partial sums are added per problem in tile order
-// (deterministic).  Per-problem FP64 scalars are arrays indexed by problem;
+// (deterministic).  Problems that have converged are masked out (active[b]
+// = 0): kernels skip their tiles.  Per-problem FP64 scalars are arrays indexed by problem;
 // the projected matrices are interleaved: entry (r, c) of problem b's T is
 // T[(r (p+1) + c) B + b], so one pointer per entry serves every problem.
 #pragma once
@@ -39,10 +40,12 @@ __device__ __forceinline__ void bside(const BProb &q, int side_v, int64_t &off, 
 // part[c][tile] = sum over the tile's rows of Q[r, c] w[r], c < j.
 template <typename T>
 __global__ __launch_bounds__(BT) void bproj_kernel(const T *__restrict__ Q, int64_t ldq, int j,
-                                                  const T *__restrict__ w, T *__restrict__ part) {
+                                                  const T *__restrict__ w, const int32_t *__restrict__ tile_inst,
+                                                  const int32_t *__restrict__ active, T *__restrict__ part) {
   __shared__ T red[BT / WAVE][BHJ];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int64_t ntiles = gridDim.x, tile = blockIdx.x;
+  if (!active[tile_inst[tile]]) return;
   const int64_t r = tile * BT + tid;
   const T wr = w[r];
   for (int c0 = 0; c0 < j; c0 += 8) {
@@ -67,14 +70,23 @@ __global__ __launch_bounds__(BT) void bproj_kernel(const T *__restrict__ Q, int6
 // h[b * hs + c] = sum over the problem's tiles of part[c][tile] (tile order).
 template <typename T>
 __global__ void bseg_sum_kernel(const T *__restrict__ part, int64_t ntiles, int j, const BProb *__restrict__ pr,
-                                int side_v, T *__restrict__ h, int hs) {
+                                int side_v, const int32_t *__restrict__ active, T *__restrict__ h, int hs) {
   const int b = blockIdx.x, c = threadIdx.x;
-  if (c >= j) return;
+  if (c >= j || !active[b]) return;
   int64_t off;
   int32_t len, t0, nt;
   bside(pr[b], side_v, off, len, t0, nt);
+  // tile order; 8 loads in flight
   T s = 0;
-  for (int t = 0; t < nt; ++t) s += part[c * ntiles + t0 + t];
+  int t = 0;
+  for (; t + 8 <= nt; t += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[c * ntiles + t0 + t + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; t < nt; ++t) s += part[c * ntiles + t0 + t];
   h[static_cast<int64_t>(b) * hs + c] = s;
 }
 
@@ -84,12 +96,14 @@ template <typename T, int JM>
 __global__ __launch_bounds__(BT) void bupd_proj_kernel(const T *__restrict__ Q, int64_t ldq, int j,
                                                       const T *__restrict__ w, const T *__restrict__ h, int hs,
                                                       const int32_t *__restrict__ tile_inst,
+                                                      const int32_t *__restrict__ active,
                                                       T *__restrict__ w1out, T *__restrict__ part) {
   __shared__ T sh[BHJ];
   __shared__ T red[BT / WAVE][BHJ];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int64_t ntiles = gridDim.x, tile = blockIdx.x;
   const int inst = tile_inst[tile];
+  if (!active[inst]) return;
   if (tid < j) sh[tid] = h[static_cast<int64_t>(inst) * hs + tid];
   __syncthreads();
   const int64_t r = tile * BT + tid;
@@ -123,12 +137,14 @@ template <typename T>
 __global__ __launch_bounds__(BT) void bupd_norm_kernel(const T *__restrict__ Q, int64_t ldq, int j,
                                                       const T *__restrict__ w1, const T *__restrict__ h, int hs,
                                                       const int32_t *__restrict__ tile_inst,
+                                                      const int32_t *__restrict__ active,
                                                       T *__restrict__ out, double *__restrict__ npart) {
   __shared__ T sh[BHJ];
   __shared__ double shd[BT / WAVE];
   const int tid = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int inst = tile_inst[tile];
+  if (!active[inst]) return;
   if (tid < j) sh[tid] = h[static_cast<int64_t>(inst) * hs + tid];
   __syncthreads();
   const int64_t r = tile * BT + tid;
@@ -154,14 +170,15 @@ __global__ __launch_bounds__(BT) void bupd_norm_kernel(const T *__restrict__ Q, 
 //                 (seed + b, stream 1 + breakdowns) and T entry = 0, xs = 1.
 template <typename T>
 __global__ __launch_bounds__(CGS_THREADS) void bfinish_norm_kernel(
-    const double *__restrict__ npart, const BProb *__restrict__ pr, int side_v, int mode,
-    double *__restrict__ t_entry, double *__restrict__ xs, double *__restrict__ sigma_est,
+    const double *__restrict__ npart, const BProb *__restrict__ pr, int side_v, const int32_t *__restrict__ active,
+    int mode, double *__restrict__ t_entry, double *__restrict__ xs, double *__restrict__ sigma_est,
     int *__restrict__ breakdowns, uint64_t seed, const T *__restrict__ Q, int64_t ldq, int j,
     T *__restrict__ out) {
   __shared__ double sh_d[CGS_THREADS / WAVE];
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ int bd;
   const int b = blockIdx.x, tid = threadIdx.x;
+  if (!active[b]) return;
   int64_t off;
   int32_t len, t0, nt;
   bside(pr[b], side_v, off, len, t0, nt);
@@ -218,11 +235,32 @@ __global__ void bstart_kernel(int64_t Ntot, const int32_t *__restrict__ tile_ins
 
 // Per-problem scaled copy: dst[i] = src[i] * xs[problem of i].
 template <typename T>
-__global__ void bscale_copy_kernel(int64_t L, const int32_t *__restrict__ tile_inst, const T *__restrict__ src,
+__global__ void bscale_copy_kernel(int64_t L, const int32_t *__restrict__ tile_inst,
+                                   const int32_t *__restrict__ active, const T *__restrict__ src,
                                    const double *__restrict__ xs, T *__restrict__ dst) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < L;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    dst[i] = src[i] * static_cast<T>(xs[tile_inst[i / BT]]);
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int b = tile_inst[i / BT];
+    if (active[b]) dst[i] = src[i] * static_cast<T>(xs[b]);
+  }
+}
+
+// Problems flagged in `freeze` stop: their restart panels become the identity
+// (Uk_b = [I_k; 0], Vext_b = [I_k 0; 0 1] in its leading columns), so every
+// later rotation copies their first k basis columns, which the restart that
+// preceded hold their Ritz vectors; active[b] = 0.
+static __global__ void bfreeze_kernel(int nb, const int32_t *__restrict__ freeze, int32_t *__restrict__ active,
+                                      double *__restrict__ Uk, double *__restrict__ Vext, int p, int k) {
+  const int b = blockIdx.x;
+  if (b >= nb || !freeze[b]) return;
+  double *u = Uk + static_cast<int64_t>(b) * p * k;
+  double *v = Vext + static_cast<int64_t>(b) * (p + 1) * (k + 1);
+  for (int i = threadIdx.x; i < p * k; i += blockDim.x) u[i] = (i % p == i / p) ? 1.0 : 0.0;
+  for (int i = threadIdx.x; i < (p + 1) * (k + 1); i += blockDim.x) {
+    const int r = i % (p + 1), c = i / (p + 1);
+    v[i] = (c < k) ? (r == c ? 1.0 : 0.0) : (r == p ? 1.0 : 0.0);
+  }
+  if (threadIdx.x == 0) active[b] = 0;
 }
 
 // Yt_b = Y_b^T zero-padded (row stride ldyt), for every problem b:

@@ -261,12 +261,14 @@ static __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
 }
 
 // One workgroup per problem of a batch (interleaved T, per-problem outputs
-// at fixed strides: Uk p*k, Vext (p+1)(k+1), sig/res/rho k, flags 4).
+// at fixed strides: Uk p*k, Vext (p+1)(k+1), sig/res/rho k, flags 4);
+// problems with active[b] = 0 are skipped.
 static __global__ __launch_bounds__(JAC_THREADS) void bsmall_svd_kernel(
     double *__restrict__ T, int nb, int p, int k, double tol, double *__restrict__ Uk, double *__restrict__ Vext,
     double *__restrict__ sig, double *__restrict__ res, double *__restrict__ rho, int *__restrict__ flags,
-    double *__restrict__ sigma_est) {
+    double *__restrict__ sigma_est, const int32_t *__restrict__ active) {
   const int64_t b = blockIdx.x;
+  if (!active[b]) return;  // converged and frozen: outputs of its last small SVD stay
   small_svd_body(T + b, nb, p, k, tol, Uk + b * p * k, Vext + b * (p + 1) * (k + 1), sig + b * k, res + b * k,
                  rho + b * k, flags + 4 * b, sigma_est + b);
 }

@@ -48,9 +48,11 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     const TV *__restrict__ val, const TB *__restrict__ x, const double *__restrict__ xs_ptr,
     const double *__restrict__ coef_ptr, const TB *__restrict__ yprev, TB *__restrict__ y,
     TB *__restrict__ partials, TB *__restrict__ side_dst, int64_t side_len,
-    const int32_t *__restrict__ x_tile_inst) {
+    const int32_t *__restrict__ x_tile_inst, const int32_t *__restrict__ active) {
   __shared__ TB prod[SPMV_NNZ_BLK];
   __shared__ TB red[SPMV_THREADS / WAVE];
+  __shared__ int rps[SPMV_ROWS_BLK + 1];
+  __shared__ TB rsum[SPMV_ROWS_BLK];
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1);
   const int wv = tid / WAVE;
@@ -59,46 +61,84 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * SPMV_THREADS + tid; i < side_len;
          i += static_cast<int64_t>(gridDim.x) * SPMV_THREADS) {
       const int inst = x_tile_inst ? x_tile_inst[i >> SPMV_TILE_SHIFT] : 0;
+      if (active && !active[inst]) continue;
       side_dst[i] = x[i] * (xs_ptr ? static_cast<TB>(xs_ptr[inst]) : TB(1));
     }
   }
 
   const int4 it = items[blockIdx.x];
+  if (active && it.x >= 0 && !active[it.z]) return;  // problem already converged (batched)
   if (it.x >= 0) {
     const TB xs = xs_ptr ? static_cast<TB>(xs_ptr[it.z]) : TB(1);
     const TB coef = coef_ptr ? static_cast<TB>(coef_ptr[it.z]) : TB(0);
     const int r0 = it.x, r1 = it.y;
-    const int base = row_ptr[r0];
-    const int cnt = row_ptr[r1] - base;
-    for (int z = tid; z < cnt; z += SPMV_THREADS)
-      prod[z] = widen<TB>(val[base + z]) * x[col[base + z]];
-    __syncthreads();
     const int nrows = r1 - r0;
+    // the item's row pointers go to LDS first: the row loops below then read
+    // no global memory (a global load per row serializes a wave per row)
+    for (int i = tid; i <= nrows; i += SPMV_THREADS) rps[i] = row_ptr[r0 + i];
+    __syncthreads();
+    const int base = rps[0];
+    const int cnt = rps[nrows] - base;
+    // staging: all index and value loads of the thread first, then all the
+    // gathers of x, so each thread has SPMV_NNZ_BLK / SPMV_THREADS loads in
+    // flight per round trip instead of one dependent pair per iteration
+    constexpr int UPT = SPMV_NNZ_BLK / SPMV_THREADS;
+    int ci[UPT];
+    TV cv[UPT];
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+      const int z = tid + u * SPMV_THREADS;
+      // indices and values are streamed once: non-temporal loads keep them
+      // from displacing the gathered x in L2
+      ci[u] = z < cnt ? __builtin_nontemporal_load(col + base + z) : 0;
+      cv[u] = z < cnt ? __builtin_nontemporal_load(val + base + z) : TV(0);
+    }
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+      const int z = tid + u * SPMV_THREADS;
+      if (z < cnt) prod[z] = widen<TB>(cv[u]) * x[ci[u]];
+    }
+    __syncthreads();
     if (cnt >= 32 * nrows) {
       // few long rows: one wave per row
       for (int r = wv; r < nrows; r += SPMV_THREADS / WAVE) {
-        const int a = row_ptr[r0 + r] - base, b = row_ptr[r0 + r + 1] - base;
+        const int a = rps[r] - base, b = rps[r + 1] - base;
         TB s = 0;
         for (int z = a + lane; z < b; z += WAVE) s += prod[z];
         s = wave_sum(s);
-        if (lane == 0) {
-          const int64_t row = r0 + r;
-          y[row] = xs * s - (yprev ? coef * yprev[row] : TB(0));
-        }
+        if (lane == 0) rsum[r] = s;
       }
     } else {
       for (int r = tid; r < nrows; r += SPMV_THREADS) {
-        const int a = row_ptr[r0 + r] - base, b = row_ptr[r0 + r + 1] - base;
+        const int a = rps[r] - base, b = rps[r + 1] - base;
         TB s = 0;
         for (int z = a; z < b; ++z) s += prod[z];
-        const int64_t row = r0 + r;
-        y[row] = xs * s - (yprev ? coef * yprev[row] : TB(0));
+        rsum[r] = s;
       }
+    }
+    __syncthreads();
+    for (int r = tid; r < nrows; r += SPMV_THREADS) {
+      const int64_t row = r0 + r;
+      y[row] = xs * rsum[r] - (yprev ? coef * yprev[row] : TB(0));
     }
   } else {
     const int z0 = it.z, z1 = it.w;
     TB s = 0;
-    for (int z = z0 + tid; z < z1; z += SPMV_THREADS) s += widen<TB>(val[z]) * x[col[z]];
+    for (int zb = z0 + tid; zb < z1; zb += 4 * SPMV_THREADS) {
+      int ci[4];
+      TV cv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int z = zb + u * SPMV_THREADS;
+        ci[u] = z < z1 ? __builtin_nontemporal_load(col + z) : 0;
+        cv[u] = z < z1 ? __builtin_nontemporal_load(val + z) : TV(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int z = zb + u * SPMV_THREADS;
+        if (z < z1) s += widen<TB>(cv[u]) * x[ci[u]];
+      }
+    }
     s = wave_sum(s);
     if (lane == 0) red[wv] = s;
     __syncthreads();
@@ -118,10 +158,12 @@ __global__ __launch_bounds__(WAVE) void spmv_longrow_fixup_kernel(const LongRow 
                                                                   const double *__restrict__ xs_ptr,
                                                                   const double *__restrict__ coef_ptr,
                                                                   const TB *__restrict__ yprev,
-                                                                  TB *__restrict__ y) {
+                                                                  TB *__restrict__ y,
+                                                                  const int32_t *__restrict__ active) {
   const int i = blockIdx.x;
   if (i >= nlong) return;
   const LongRow L = longrows[i];
+  if (active && !active[L.inst]) return;
   const TB xs = xs_ptr ? static_cast<TB>(xs_ptr[L.inst]) : TB(1);
   const TB coef = coef_ptr ? static_cast<TB>(coef_ptr[L.inst]) : TB(0);
   TB t = 0;

@@ -37,6 +37,7 @@ struct SpmvPlan {
   std::vector<int4> h_items;
   std::vector<LongRow> h_long;
   const int32_t *x_tile_inst = nullptr;  // problem of each 256-entry tile of x (batched), or null
+  const int32_t *active = nullptr;       // per-problem work mask (batched), or null
 };
 
 // Work items of a CSR product.  With seg_end (nseg consecutive row ranges

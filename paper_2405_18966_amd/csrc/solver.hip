@@ -268,14 +268,14 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     if (op.vt == SVDS_F64)
       hipLaunchKernelGGL((spmv_csr_kernel<double, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
                          P->stream, sp.items, rp, ci, static_cast<const double *>(val), x, xs, coef,
-                         yprev, y, parts, side_dst, side_len, sp.x_tile_inst);
+                         yprev, y, parts, side_dst, side_len, sp.x_tile_inst, sp.active);
     else
       hipLaunchKernelGGL((spmv_csr_kernel<float, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
                          P->stream, sp.items, rp, ci, static_cast<const float *>(val), x, xs, coef,
-                         yprev, y, parts, side_dst, side_len, sp.x_tile_inst);
+                         yprev, y, parts, side_dst, side_len, sp.x_tile_inst, sp.active);
     if (sp.nlong > 0)
       hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(sp.nlong), dim3(WAVE), 0,
-                         P->stream, sp.longrows, sp.nlong, parts, xs, coef, yprev, y);
+                         P->stream, sp.longrows, sp.nlong, parts, xs, coef, yprev, y, sp.active);
     LAUNCH_CHECK();
     bytes = 4.0 * (rows + 1) + (4.0 + vsize(op.vt)) * op.nnz + sb * cols +
             (yprev ? 2.0 : 1.0) * sb * rows;
