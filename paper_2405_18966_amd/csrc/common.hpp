@@ -85,6 +85,18 @@ __device__ __forceinline__ double wave_sum_u(double v) {
   return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
 }
 
+// Sum over each row of 16 lanes (DPP rows): quad swaps, half-row and row
+// mirrors.  Every add combines two values in both orders on the two lanes
+// involved, so all 16 lanes of a row end with the same bits.  Every lane of
+// the wave must be active.
+__device__ __forceinline__ double row16_sum(double v) {
+  v = __dadd_rn(v, dpp_f64<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = __dadd_rn(v, dpp_f64<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = __dadd_rn(v, dpp_f64<0x141>(v));  // row_half_mirror
+  v = __dadd_rn(v, dpp_f64<0x140>(v));  // row_mirror
+  return v;
+}
+
 template <typename T> __device__ __forceinline__ T wave_max(T v) {
 #pragma unroll
   for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));

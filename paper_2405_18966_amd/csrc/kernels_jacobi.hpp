@@ -21,7 +21,7 @@
 //    into nb (even) blocks of c columns; a sweep is nb-1 rounds of a
 //    round-robin over blocks, each round one kernel in which workgroup g
 //    stages its two blocks (W and Vh columns) in LDS and rotates, one pair
-//    per wave per step: in round 0 every pair of its 2c columns (this covers
+//    per group of 16 lanes per step: in round 0 every pair of its 2c columns (this covers
 //    the pairs inside each block, as every block appears once per round), in
 //    later rounds the c*c pairs across its two blocks.  W and Vh live in
 //    global memory between rounds; each round adds its rotation count to a
@@ -110,6 +110,50 @@ __device__ __forceinline__ int jacobi_pair(double *__restrict__ wi, double *__re
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
     const int r = lane + t * WAVE;
+    if (r < rows) {
+      wi[r] = cs * xi[t] - sn * xj[t];
+      wj[r] = sn * xi[t] + cs * xj[t];
+      vi[r] = cs * yi[t] - sn * yj[t];
+      vj[r] = sn * yi[t] + cs * yj[t];
+    }
+  }
+  return 1;
+}
+
+// Same rotation for one pair per group of 16 lanes (4 pairs per wave, RPL
+// rows per lane): the four pairs' sums and rotation parameters are computed
+// by the same instructions.  Every lane of the wave takes part (a group with
+// no pair passes null columns); returns 1 if this lane's pair rotated.
+template <int RPL>
+__device__ __forceinline__ int jacobi_pair16(double *__restrict__ wi, double *__restrict__ wj,
+                                             double *__restrict__ vi, double *__restrict__ vj, int rows,
+                                             int sl, double tolJ) {
+  double xi[RPL], xj[RPL], yi[RPL], yj[RPL];
+  double a = 0, b = 0, c = 0;
+  const bool has = wi != nullptr;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = sl + t * 16;
+    const bool ok = has && r < rows;
+    xi[t] = ok ? wi[r] : 0.0;
+    xj[t] = ok ? wj[r] : 0.0;
+    yi[t] = ok ? vi[r] : 0.0;
+    yj[t] = ok ? vj[r] : 0.0;
+    a += xi[t] * xi[t];
+    b += xj[t] * xj[t];
+    c += xi[t] * xj[t];
+  }
+  a = row16_sum(a);
+  b = row16_sum(b);
+  c = row16_sum(c);
+  if (!has || !(fabs(c) > tolJ * sqrt(a * b))) return 0;
+  const double z = (b - a) / (2.0 * c);
+  const double tt = (z >= 0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+  const double cs = 1.0 / sqrt(1.0 + tt * tt);
+  const double sn = cs * tt;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = sl + t * 16;
     if (r < rows) {
       wi[r] = cs * xi[t] - sn * xj[t];
       wj[r] = sn * xi[t] + cs * xj[t];
@@ -279,14 +323,15 @@ __host__ __device__ inline size_t small_svd_lds_bytes(int p) {
 }
 
 // ---------------------------------------------------------------------------
-// Block schedule: one round.  Grid nb/2 workgroups of c waves; dynamic LDS
+// Block schedule: one round.  Grid nb/2 workgroups of c/4 waves (one pair per
+// 16-lane group, RPL rows per lane); dynamic LDS
 // 2c columns of W then 2c columns of Vh, p rows each.  Block b holds global
 // columns [b c, b c + c); W and Vh in global memory are column-major with
 // ld = p and nb*c columns.  In the first round of the first sweep the blocks
 // are loaded from T (row-major, ld p+1) and the identity instead.
 // ---------------------------------------------------------------------------
 template <int RPL>
-__global__ __launch_bounds__(JAC_THREADS) void bjac_round_kernel(const double *__restrict__ T, int from_T,
+__global__ __launch_bounds__(256) void bjac_round_kernel(const double *__restrict__ T, int from_T,
                                                                  double *__restrict__ W,
                                                                  double *__restrict__ Vh, int p, int c,
                                                                  int nb, int round, int sweep,
@@ -334,18 +379,21 @@ __global__ __launch_bounds__(JAC_THREADS) void bjac_round_kernel(const double *_
   }
   __syncthreads();
   const double tolJ = jacobi_tol(p + (p & 1));
+  // pair q of a step is handled by the 16-lane group q (4 per wave)
+  const int q = wv * 4 + (lane >> 4), sl = lane & 15;
+  const bool own = q < c;
   int nrot = 0;
   if (round == 0) {
     for (int step = 0; step < c2 - 1; ++step) {
-      int i, j;
-      rr_pair(c2, step, wv, i, j);
-      nrot += jacobi_pair<RPL>(X + i * p, X + j * p, Y + i * p, Y + j * p, p, lane, tolJ);
+      int i = 0, j = 0;
+      if (own) rr_pair(c2, step, q, i, j);
+      nrot += jacobi_pair16<RPL>(own ? X + i * p : nullptr, X + j * p, Y + i * p, Y + j * p, p, sl, tolJ);
       __syncthreads();
     }
   } else {
     for (int step = 0; step < c; ++step) {
-      const int i = wv, j = c + (wv + step) % c;
-      nrot += jacobi_pair<RPL>(X + i * p, X + j * p, Y + i * p, Y + j * p, p, lane, tolJ);
+      const int i = q, j = c + (q + step) % c;
+      nrot += jacobi_pair16<RPL>(own ? X + i * p : nullptr, X + j * p, Y + i * p, Y + j * p, p, sl, tolJ);
       __syncthreads();
     }
   }
@@ -355,7 +403,7 @@ __global__ __launch_bounds__(JAC_THREADS) void bjac_round_kernel(const double *_
     W[static_cast<int64_t>(gc) * p + r] = X[idx];
     Vh[static_cast<int64_t>(gc) * p + r] = Y[idx];
   }
-  if (lane == 0 && nrot) atomicAdd(&s_rot, nrot);
+  if (sl == 0 && nrot) atomicAdd(&s_rot, nrot);
   __syncthreads();
   if (tid == 0 && s_rot) atomicAdd(&counters[sweep], s_rot);
 }

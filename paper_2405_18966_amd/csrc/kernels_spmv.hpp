@@ -21,7 +21,7 @@
 //
 // Several independent problems can share one launch as the blocks of a
 // block-diagonal matrix (the batched solver): every item then carries its
-// problem's index (item.z of a MULTI item, LongRow::inst of a long row) and
+// problem's index (in item.w of a MULTI item, LongRow::inst of a long row) and
 // the scale factors xs, coef are per-problem arrays; the side task finds the
 // problem of entry i from x_tile_inst[i / 256] (problems are padded to
 // multiples of 256 rows).  A single problem has index 0 everywhere.
@@ -34,9 +34,14 @@ constexpr int SPMV_THREADS = 256;
 constexpr int SPMV_NNZ_BLK = 2048;
 constexpr int SPMV_ROWS_BLK = 256;
 constexpr int SPMV_PIECE = 4096;
+constexpr int SPMV_CNT_BITS = 12;   // MULTI item: w = nnz count | problem << 12
+static_assert(SPMV_NNZ_BLK < (1 << SPMV_CNT_BITS), "item count field");
+constexpr int SPMV_WAVE_ROW = 128;  // mean row length from which a MULTI item reduces a wave per row
+static_assert(SPMV_ROWS_BLK <= SPMV_THREADS, "one thread per row of an item");
 
-// item.x >= 0: MULTI rows [x, y) of problem z.   item.x < 0: PIECE of long
-// row id -x-1, nonzeros [z, w), written to partials[item.y].
+// item.x >= 0: MULTI rows [x, y), nonzeros from z, w = count | problem << 12.
+// item.x < 0: PIECE of long row id -x-1, nonzeros [z, w), written to
+// partials[item.y].
 struct LongRow {
   int32_t row, first_piece, npieces, inst;
 };
@@ -67,18 +72,20 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
   }
 
   const int4 it = items[blockIdx.x];
-  if (active && it.x >= 0 && !active[it.z]) return;  // problem already converged (batched)
+  if (active && it.x >= 0 && !active[it.w >> SPMV_CNT_BITS]) return;  // problem already converged (batched)
   if (it.x >= 0) {
-    const TB xs = xs_ptr ? static_cast<TB>(xs_ptr[it.z]) : TB(1);
-    const TB coef = coef_ptr ? static_cast<TB>(coef_ptr[it.z]) : TB(0);
+    const int inst = it.w >> SPMV_CNT_BITS;
+    const TB xs = xs_ptr ? static_cast<TB>(xs_ptr[inst]) : TB(1);
+    const TB coef = coef_ptr ? static_cast<TB>(coef_ptr[inst]) : TB(0);
     const int r0 = it.x, r1 = it.y;
     const int nrows = r1 - r0;
-    // the item's row pointers go to LDS first: the row loops below then read
-    // no global memory (a global load per row serializes a wave per row)
+    const int base = it.z;                                   // first nonzero of the item
+    const int cnt = it.w & ((1 << SPMV_CNT_BITS) - 1);       // its nonzero count
+    // The descriptor carries the nonzero range, so the index/value loads, the
+    // row pointers (to LDS: the row loops below then read no global memory)
+    // and yprev are all issued at once.
     for (int i = tid; i <= nrows; i += SPMV_THREADS) rps[i] = row_ptr[r0 + i];
-    __syncthreads();
-    const int base = rps[0];
-    const int cnt = rps[nrows] - base;
+    const TB yp = (yprev && tid < nrows) ? yprev[r0 + tid] : TB(0);
     // staging: all index and value loads of the thread first, then all the
     // gathers of x, so each thread has SPMV_NNZ_BLK / SPMV_THREADS loads in
     // flight per round trip instead of one dependent pair per iteration
@@ -98,9 +105,10 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
       const int z = tid + u * SPMV_THREADS;
       if (z < cnt) prod[z] = widen<TB>(cv[u]) * x[ci[u]];
     }
-    __syncthreads();
-    if (cnt >= 32 * nrows) {
-      // few long rows: one wave per row
+    __syncthreads();  // products and row pointers in LDS
+    if (cnt >= SPMV_WAVE_ROW * nrows) {
+      // few long rows: one wave per row (a wave reduces its rows one after the
+      // other, so rows of moderate length go to one thread each instead)
       for (int r = wv; r < nrows; r += SPMV_THREADS / WAVE) {
         const int a = rps[r] - base, b = rps[r + 1] - base;
         TB s = 0;
@@ -117,10 +125,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
       }
     }
     __syncthreads();
-    for (int r = tid; r < nrows; r += SPMV_THREADS) {
-      const int64_t row = r0 + r;
-      y[row] = xs * rsum[r] - (yprev ? coef * yprev[row] : TB(0));
-    }
+    if (tid < nrows) y[r0 + tid] = xs * rsum[tid] - coef * yp;  // nrows <= SPMV_THREADS
   } else {
     const int z0 = it.z, z1 = it.w;
     TB s = 0;
@@ -170,6 +175,157 @@ __global__ __launch_bounds__(WAVE) void spmv_longrow_fixup_kernel(const LongRow 
   for (int q = threadIdx.x; q < L.npieces; q += WAVE) t += partials[L.first_piece + q];
   t = wave_sum(t);
   if (threadIdx.x == 0) y[L.row] = xs * t - (yprev ? coef * yprev[L.row] : TB(0));
+}
+
+}  // namespace svds
+
+namespace svds {
+
+// ---------------------------------------------------------------------------
+// Explicit residual norms of RG output triplets at once (Proposition 1,
+// eq. (2)): for g < RG, |A x_g - s_g y_g|^2 over the rows of this launch.
+// X (ncols x RG) and Y (nrows x RG) are row-major panels of the triplets'
+// vectors (RG consecutive doubles per row: one 64-byte line per gathered
+// row for RG = 8).  Same work items as the product: a MULTI item gives one
+// thread per row (one wave per row for long rows) and writes the item's
+// partial squared norms to part[item][g]; a PIECE item writes its partial
+// row sums to pieces[piece][g] and resid_longrow_kernel finishes long rows.
+// ---------------------------------------------------------------------------
+constexpr int RG = 8;
+
+template <typename TV>
+__global__ __launch_bounds__(SPMV_THREADS) void resid_spmm_kernel(
+    const int4 *__restrict__ items, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const TV *__restrict__ val, const double *__restrict__ X, const double *__restrict__ Y,
+    const double *__restrict__ s, double *__restrict__ part, double *__restrict__ pieces) {
+  __shared__ double red[SPMV_THREADS / WAVE][RG];
+  __shared__ double wsum[SPMV_THREADS / WAVE][RG];
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int4 it = items[blockIdx.x];
+  double sg[RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) sg[g] = s[g];
+  double sq[RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) sq[g] = 0.0;
+  auto gather = [&](int c, double (&acc)[RG], double a) {
+    const double4 *xr = reinterpret_cast<const double4 *>(X + static_cast<int64_t>(c) * RG);
+    const double4 x0 = xr[0], x1 = xr[1];
+    acc[0] += a * x0.x; acc[1] += a * x0.y; acc[2] += a * x0.z; acc[3] += a * x0.w;
+    acc[4] += a * x1.x; acc[5] += a * x1.y; acc[6] += a * x1.z; acc[7] += a * x1.w;
+  };
+  if (it.x >= 0) {
+    const int r0 = it.x, r1 = it.y, nrows = r1 - r0;
+    const int cnt = it.w & ((1 << SPMV_CNT_BITS) - 1);
+    if (cnt >= SPMV_WAVE_ROW * nrows) {
+      for (int r = wv; r < nrows; r += SPMV_THREADS / WAVE) {
+        const int a = row_ptr[r0 + r], b = row_ptr[r0 + r + 1];
+        double acc[RG];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) acc[g] = 0.0;
+        for (int z = a + lane; z < b; z += WAVE) gather(col[z], acc, static_cast<double>(val[z]));
+#pragma unroll
+        for (int g = 0; g < RG; ++g) acc[g] = wave_sum(acc[g]);
+        if (lane == 0) {
+          const int64_t row = r0 + r;
+#pragma unroll
+          for (int g = 0; g < RG; ++g) {
+            const double d = acc[g] - sg[g] * Y[row * RG + g];
+            sq[g] += d * d;
+          }
+        }
+      }
+    } else {
+      for (int r = tid; r < nrows; r += SPMV_THREADS) {
+        const int a = row_ptr[r0 + r], b = row_ptr[r0 + r + 1];
+        double acc[RG];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) acc[g] = 0.0;
+        for (int z = a; z < b; ++z) gather(col[z], acc, static_cast<double>(val[z]));
+        const int64_t row = r0 + r;
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          const double d = acc[g] - sg[g] * Y[row * RG + g];
+          sq[g] += d * d;
+        }
+      }
+    }
+  } else {
+    double acc[RG];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) acc[g] = 0.0;
+    for (int z = it.z + tid; z < it.w; z += SPMV_THREADS) gather(col[z], acc, static_cast<double>(val[z]));
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      const double v = wave_sum(acc[g]);
+      if (lane == 0) wsum[wv][g] = v;
+    }
+    __syncthreads();
+    if (tid < RG) {
+      double t = 0;
+      for (int w = 0; w < SPMV_THREADS / WAVE; ++w) t += wsum[w][tid];
+      pieces[static_cast<int64_t>(it.y) * RG + tid] = t;
+    }
+    if (tid < RG) part[static_cast<int64_t>(blockIdx.x) * RG + tid] = 0.0;
+    return;
+  }
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const double v = wave_sum(sq[g]);
+    if (lane == 0) red[wv][g] = v;
+  }
+  __syncthreads();
+  if (tid < RG) {
+    double t = 0;
+    for (int w = 0; w < SPMV_THREADS / WAVE; ++w) t += red[w][tid];
+    part[static_cast<int64_t>(blockIdx.x) * RG + tid] = t;
+  }
+}
+
+// Long rows: the row's piece sums in piece order, minus s_g Y, squared, into
+// lpart[longrow][g].  One thread per (long row, g).
+static __global__ void resid_longrow_kernel(const LongRow *__restrict__ longrows, int nlong,
+                                            const double *__restrict__ pieces, const double *__restrict__ Y,
+                                            const double *__restrict__ s, double *__restrict__ lpart) {
+  const int i = blockIdx.x * (256 / RG) + threadIdx.x / RG, g = threadIdx.x % RG;
+  if (i >= nlong) return;
+  const LongRow L = longrows[i];
+  double t = 0;
+  for (int q = 0; q < L.npieces; ++q) t += pieces[static_cast<int64_t>(L.first_piece + q) * RG + g];
+  const double d = t - s[g] * Y[static_cast<int64_t>(L.row) * RG + g];
+  lpart[static_cast<int64_t>(i) * RG + g] = d * d;
+}
+
+// res[g] = sqrt(sum over items of part[item][g] + sum over long rows of
+// lpart[row][g]), in index order; one wave per g.
+static __global__ void resid_finish_kernel(const double *__restrict__ part, int nitems,
+                                           const double *__restrict__ lpart, int nlong, int ng,
+                                           double *__restrict__ res) {
+  const int g = blockIdx.x, lane = threadIdx.x;
+  if (g >= ng) return;
+  double t = 0;
+  for (int i = lane; i < nitems; i += WAVE) t += part[static_cast<int64_t>(i) * RG + g];
+  for (int i = lane; i < nlong; i += WAVE) t += lpart[static_cast<int64_t>(i) * RG + g];
+  t = wave_sum(t);
+  if (lane == 0) res[g] = sqrt(t);
+}
+
+// s8[g] = S[c0 + g] for c0 + g < nc, 0 beyond.
+static __global__ void resid_svals_kernel(const double *__restrict__ S, int c0, int nc, double *__restrict__ s8) {
+  const int g = threadIdx.x;
+  if (g < RG) s8[g] = c0 + g < nc ? S[c0 + g] : 0.0;
+}
+
+// Panel of RG columns, row-major: P[r * RG + g] = M[(c0 + g) * ld + r] for
+// c0 + g < nc, 0 beyond.
+static __global__ void resid_panel_kernel(int64_t L, const double *__restrict__ M, int64_t ld, int c0, int nc,
+                                          double *__restrict__ P) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < L * RG;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = i / RG;
+    const int g = static_cast<int>(i % RG);
+    P[i] = c0 + g < nc ? M[(c0 + g) * ld + r] : 0.0;
+  }
 }
 
 }  // namespace svds

@@ -69,7 +69,8 @@ void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp, const int64_t 
         z += l;
         ++r;
       }
-      sp.h_items.push_back(make_int4(static_cast<int>(r0), static_cast<int>(r), g, 0));
+      sp.h_items.push_back(make_int4(static_cast<int>(r0), static_cast<int>(r), rp[r0],
+                                     static_cast<int>(z) | (g << SPMV_CNT_BITS)));
     }
   }
   sp.nitems = static_cast<int>(sp.h_items.size());
@@ -201,6 +202,9 @@ struct svds_plan {
   Small sc{};
   double *tmp_nk = nullptr;  // n x k FP64 (mixed warm start), m-vector scratch
   double *tmp_m = nullptr, *tmp_n = nullptr;
+  // residual panels (CSR plans): row-major RG-column panels of U and V, partials
+  double *rs_pu = nullptr, *rs_pv = nullptr, *rs_part = nullptr, *rs_pieces = nullptr, *rs_lpart = nullptr,
+         *rs_s = nullptr;
   int *h_flags = nullptr;    // pinned
   Accounting acc;
   int64_t n_spmv = 0, n_spmvT = 0;
@@ -622,6 +626,13 @@ static int carve_all(svds_plan *P, Arena &a) {
     P->op.bwd.partials = a.take<double>(std::max(1, P->op.bwd.npieces));
     P->op.bwd.items = a.take<int4>(P->op.bwd.nitems);
     P->op.bwd.longrows = a.take<LongRow>(std::max(1, P->op.bwd.nlong));
+    P->rs_pu = a.take<double>(static_cast<size_t>(m) * RG);
+    P->rs_pv = a.take<double>(static_cast<size_t>(n) * RG);
+    P->rs_part = a.take<double>(static_cast<size_t>(std::max(P->op.fwd.nitems, P->op.bwd.nitems)) * RG);
+    P->rs_pieces =
+        a.take<double>(static_cast<size_t>(std::max(1, std::max(P->op.fwd.npieces, P->op.bwd.npieces))) * RG);
+    P->rs_lpart = a.take<double>(static_cast<size_t>(std::max(1, std::max(P->op.fwd.nlong, P->op.bwd.nlong))) * RG);
+    P->rs_s = a.take<double>(RG);
     P->op.trp = a.take<int32_t>(n + 1);
     P->op.tci = a.take<int32_t>(std::max<int64_t>(1, P->op.nnz));
     P->op.tval = a.take<char>(std::max<int64_t>(1, P->op.nnz) * static_cast<size_t>(vsize(P->op.vt)));
@@ -978,10 +989,50 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
 // Residuals (Proposition 1, eq. (2), evaluated explicitly in FP64)
 // ===========================================================================
 namespace svds {
+// Block residuals of a CSR plan: RG triplets per product pass (row-major
+// panels, see resid_spmm_kernel).
+template <typename TV>
+static int residuals_csr_block(svds_plan *P, int k, const double *U, const double *S, const double *V,
+                               double *res_av, double *res_atu) {
+  const Operator &op = P->op;
+  const int64_t m = op.m, n = op.n;
+  const TV *val = static_cast<const TV *>(op.val);
+  const TV *tval = static_cast<const TV *>(op.tval);
+  for (int j0 = 0; j0 < k; j0 += RG) {
+    const int nc = std::min(RG, k - j0);
+    ACC_BEFORE(SVDS_KC_OTHER);
+    hipLaunchKernelGGL(resid_svals_kernel, dim3(1), dim3(64), 0, P->stream, S, j0, k, P->rs_s);
+    hipLaunchKernelGGL(resid_panel_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(4096, ceil_div(m * RG, 256)))),
+                       dim3(256), 0, P->stream, m, U, m, j0, k, P->rs_pu);
+    hipLaunchKernelGGL(resid_panel_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(4096, ceil_div(n * RG, 256)))),
+                       dim3(256), 0, P->stream, n, V, n, j0, k, P->rs_pv);
+    // A v - s u over the rows of A, then A^T u - s v over the rows of A^T
+    for (int t = 0; t < 2; ++t) {
+      const SpmvPlan &sp = t ? op.bwd : op.fwd;
+      hipLaunchKernelGGL((resid_spmm_kernel<TV>), dim3(sp.nitems), dim3(SPMV_THREADS), 0, P->stream, sp.items,
+                         t ? op.trp : op.rp, t ? op.tci : op.ci, t ? tval : val, t ? P->rs_pu : P->rs_pv,
+                         t ? P->rs_pv : P->rs_pu, P->rs_s, P->rs_part, P->rs_pieces);
+      if (sp.nlong > 0)
+        hipLaunchKernelGGL(resid_longrow_kernel, dim3(static_cast<unsigned>(ceil_div(sp.nlong, 256 / RG))), dim3(256),
+                           0, P->stream, sp.longrows, sp.nlong, P->rs_pieces, t ? P->rs_pv : P->rs_pu, P->rs_s,
+                           P->rs_lpart);
+      hipLaunchKernelGGL(resid_finish_kernel, dim3(nc), dim3(WAVE), 0, P->stream, P->rs_part, sp.nitems,
+                         P->rs_lpart, sp.nlong, nc, (t ? res_atu : res_av) + j0);
+    }
+    LAUNCH_CHECK();
+    ACC_AFTER(SVDS_KC_OTHER, 2.0 * ((4.0 + sizeof(TV)) * op.nnz + 8.0 * RG * (m + n)), 4.0 * RG * op.nnz);
+  }
+  return SVDS_OK;
+}
+
 static int residuals_impl(svds_plan *P, int k, const double *U, const double *S, const double *V,
                           double *res_av, double *res_atu) {
   const int64_t m = P->op.m, n = P->op.n;
   const int64_t sv = P->n_spmv, st = P->n_spmvT;
+  if (!P->op.dense && P->rs_pu) {
+    return P->op.vt == SVDS_F64 ? residuals_csr_block<double>(P, k, U, S, V, res_av, res_atu)
+                                : residuals_csr_block<float>(P, k, U, S, V, res_av, res_atu);
+  }
   for (int j = 0; j < k; ++j) {
     // tmp_m = A v_j - s_j u_j
     int rc = matvec<double>(P, false, V + j * n, P->sc.one, S + j, U + j * m, P->tmp_m, nullptr, 0,
@@ -1108,27 +1159,24 @@ int bjac_launch_round(hipStream_t st, const double *T, int from_T, double *W, do
                                 hipFuncAttributeMaxDynamicSharedMemorySize, BJ_LDS));
     attr_set = true;
   }
-  hipLaunchKernelGGL((bjac_round_kernel<R>), dim3(nb / 2), dim3(c * WAVE), shm, st, T, from_T, W, Vh, p, c, nb,
-                     round, sweep, counters);
+  hipLaunchKernelGGL((bjac_round_kernel<R>), dim3(nb / 2), dim3(std::max(1, c / 4) * WAVE), shm, st, T, from_T, W,
+                     Vh, p, c, nb, round, sweep, counters);
   HIP_TRY(hipGetLastError());
   return SVDS_OK;
 }
 
-int bjac_round(hipStream_t st, int rpl, const double *T, int from_T, double *W, double *Vh, int p, int c,
+int bjac_round(hipStream_t st, int rpl16, const double *T, int from_T, double *W, double *Vh, int p, int c,
                int nb, int round, int sweep, int *counters) {
-  switch (rpl) {
-    case 1: return bjac_launch_round<1>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-    case 2: return bjac_launch_round<2>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-    case 3: return bjac_launch_round<3>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-    case 4: return bjac_launch_round<4>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-    case 5: case 6: return bjac_launch_round<6>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-    case 7: case 8: return bjac_launch_round<8>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-    case 9: case 10: case 11: case 12:
-      return bjac_launch_round<12>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-    case 13: case 14: case 15: case 16:
-      return bjac_launch_round<16>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-    default: return SVDS_EUNSUPPORTED;
-  }
+  // rpl16: rows per lane with 16 lanes per column pair
+  if (rpl16 <= 4) return bjac_launch_round<4>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+  if (rpl16 <= 8) return bjac_launch_round<8>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+  if (rpl16 <= 12) return bjac_launch_round<12>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+  if (rpl16 <= 16) return bjac_launch_round<16>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+  if (rpl16 <= 24) return bjac_launch_round<24>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+  if (rpl16 <= 32) return bjac_launch_round<32>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+  if (rpl16 <= 48) return bjac_launch_round<48>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+  if (rpl16 <= 64) return bjac_launch_round<64>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+  return SVDS_EUNSUPPORTED;
 }
 
 static __global__ void zero_i32_kernel(int n, int *__restrict__ out) {
@@ -1150,7 +1198,7 @@ int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, doub
   }
   int c, nb;
   bjac_shape(p, c, nb);
-  const int rpl = static_cast<int>(ceil_div(p, WAVE));
+  const int rpl = static_cast<int>(ceil_div(p, 16));
   double *W = work;
   double *Vh = work + static_cast<int64_t>(p) * nb * c;
   int *counters = reinterpret_cast<int *>(Vh + static_cast<int64_t>(p) * nb * c);

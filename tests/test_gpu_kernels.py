@@ -318,3 +318,27 @@ def test_small_svd_near_degenerate_pair(S):
     np.testing.assert_allclose(sg.cpu().numpy(), s_ref[:k], rtol=1e-13)
     assert np.abs(Vk.T @ Vk - np.eye(k)).max() < 1e-13
     assert np.abs(Uk.T @ Uk - np.eye(k)).max() < 1e-13
+
+
+# --- explicit residuals (block products over 8 triplets at a time) ---------------------
+
+@pytest.mark.parametrize("k", [1, 5, 8, 13])
+@pytest.mark.parametrize("vdt", ["f64", "f32"])
+def test_block_residuals_match_numpy(S, k, vdt):
+    """|A v_j - s_j u_j| and |A^T u_j - s_j v_j| for arbitrary (not singular)
+    triplets, on a Zipf matrix whose heaviest columns are long rows of A^T
+    (pieces + long-row fix-up)."""
+    A = inputs.sparse_zipf(30000, 9000, 12, 1.3, seed=k + 3)
+    if vdt == "f32":
+        A = inputs.round_values_f32(A)
+    rng = np.random.default_rng(k)
+    U = rng.standard_normal((A.m, k))
+    V = rng.standard_normal((A.n, k))
+    s = rng.uniform(1, 2, k)
+    Ad, keep = S.csr_to_device(A)
+    r1, r2 = S.svds_residuals_csr(Ad, _t(U), _t(s), _t(V))
+    Asp = svds_ref.as_operator(inputs.CSR(A.m, A.n, A.row_ptr, A.col_idx, A.val.astype(np.float64)))
+    e1 = np.linalg.norm(Asp @ V - U * s, axis=0)
+    e2 = np.linalg.norm(Asp.T @ U - V * s, axis=0)
+    np.testing.assert_allclose(r1.cpu().numpy(), e1, rtol=1e-12)
+    np.testing.assert_allclose(r2.cpu().numpy(), e2, rtol=1e-12)
