@@ -133,6 +133,7 @@ extern "C" int svds_op_dense_matvec(const svds_dense *A, int32_t transpose, cons
   o.p = 2;
   o.stream = stream;
   o.precision = basis_dtype == SVDS_F32 ? SVDS_PREC_MIXED : SVDS_PREC_FP64;
+  o.flags = SVDS_FLAG_NO_RESIDUALS;  // no residual workspace for a single product
   if (A->m < 2 || A->n < 3) return SVDS_EINVAL;
   svds_plan *P = nullptr;
   int rc = svds_plan_create_dense(A, &o, &P);

@@ -168,6 +168,36 @@ __global__ __launch_bounds__(DN_THREADS) void gemv_t_kernel(
   }
 }
 
+// Exact FP64 copy of a stored dense matrix (column-major, ld m).
+template <typename TV>
+__global__ void widen_dense_kernel(int64_t m, int64_t n, const TV *__restrict__ A, int64_t lda,
+                                   double *__restrict__ out) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < m * n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t c = i / m, r = i - c * m;
+    out[i] = widen<double>(A[c * lda + r]);
+  }
+}
+
+// R(:, j) = S[j] X(:, j), j < k (X, R column-major, ld L).
+static __global__ void scale_cols_kernel(int64_t L, int k, const double *__restrict__ X, const double *__restrict__ S,
+                                         double *__restrict__ R) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < L * k;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    R[i] = S[i / L] * X[i];
+}
+
+// out[j] = |R(:, j)|_2, one block per column, fixed-order block sum.
+static __global__ __launch_bounds__(256) void col_norms_kernel(int64_t L, const double *__restrict__ R,
+                                                               double *__restrict__ out) {
+  __shared__ double sh[256 / WAVE];
+  const double *c = R + static_cast<int64_t>(blockIdx.x) * L;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < L; i += 256) s += c[i] * c[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = sqrt(s);
+}
+
 // scratch of the A x kernel: partials (slabs x m of TB <= 8 bytes)
 inline int64_t dense_partial_doubles(int64_t m, int64_t n) { return ceil_div(n, DN_SLAB) * m; }
 

@@ -10,6 +10,8 @@
 #include <cstring>
 #include <mutex>
 
+#include <rocblas/rocblas.h>
+
 #include "plan.hpp"
 #include "kernels_cgs.hpp"
 #include "kernels_csc.hpp"
@@ -205,6 +207,9 @@ struct svds_plan {
   // residual panels (CSR plans): row-major RG-column panels of U and V, partials
   double *rs_pu = nullptr, *rs_pv = nullptr, *rs_part = nullptr, *rs_pieces = nullptr, *rs_lpart = nullptr,
          *rs_s = nullptr;
+  // dense residuals: R1 (m x k), R2 (n x k), exact FP64 copy of a low-precision A
+  double *dr1 = nullptr, *dr2 = nullptr, *da64 = nullptr;
+  bool da64_ready = false;
   int *h_flags = nullptr;    // pinned
   Accounting acc;
   int64_t n_spmv = 0, n_spmvT = 0;
@@ -619,6 +624,11 @@ static int carve_all(svds_plan *P, Arena &a) {
   if (P->mixed) P->tmp_nk = a.take<double>(static_cast<size_t>(n) * k);
   if (P->op.dense) {
     P->op.dpart = a.take<double>(dense_partial_doubles(m, n));
+    if (!(P->opts.flags & SVDS_FLAG_NO_RESIDUALS)) {
+      P->dr1 = a.take<double>(static_cast<size_t>(m) * k);
+      P->dr2 = a.take<double>(static_cast<size_t>(n) * k);
+      if (P->op.vt != SVDS_F64) P->da64 = a.take<double>(static_cast<size_t>(m) * n);
+    }
   } else {
     P->op.fwd.partials = a.take<double>(std::max(1, P->op.fwd.npieces));
     P->op.fwd.items = a.take<int4>(P->op.fwd.nitems);
@@ -1025,10 +1035,74 @@ static int residuals_csr_block(svds_plan *P, int k, const double *U, const doubl
   return SVDS_OK;
 }
 
+// rocBLAS handle per device, created on first use and kept for the process
+// (creation loads the library's kernels); calls are serialized by a mutex.
+static std::mutex g_blas_mu;
+static rocblas_handle g_blas[64] = {};
+
+// Dense residuals: R1 = A V - U diag(S), R2 = A^T U - V diag(S) as two FP64
+// GEMMs (one pass over A each, all k triplets), then column norms.
+static int residuals_dense(svds_plan *P, int k, const double *U, const double *S, const double *V,
+                           double *res_av, double *res_atu) {
+  const Operator &op = P->op;
+  const int64_t m = op.m, n = op.n;
+  const double *A = nullptr;
+  int64_t lda = m;
+  if (op.vt == SVDS_F64) {
+    A = static_cast<const double *>(op.a);
+    lda = op.lda;
+  } else {
+    if (!P->da64) return SVDS_EUNSUPPORTED;
+    if (!P->da64_ready) {
+      const unsigned g = static_cast<unsigned>(std::min<int64_t>(8192, ceil_div(m * n, 256)));
+      if (op.vt == SVDS_F32)
+        hipLaunchKernelGGL((widen_dense_kernel<float>), dim3(g), dim3(256), 0, P->stream, m, n,
+                           static_cast<const float *>(op.a), op.lda, P->da64);
+      else
+        hipLaunchKernelGGL((widen_dense_kernel<uint16_t>), dim3(g), dim3(256), 0, P->stream, m, n,
+                           static_cast<const uint16_t *>(op.a), op.lda, P->da64);
+      LAUNCH_CHECK();
+      P->da64_ready = true;
+    }
+    A = P->da64;
+  }
+  ACC_BEFORE(SVDS_KC_OTHER);
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(4096, ceil_div(m * k, 256)))),
+                     dim3(256), 0, P->stream, m, k, U, S, P->dr1);
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(4096, ceil_div(n * k, 256)))),
+                     dim3(256), 0, P->stream, n, k, V, S, P->dr2);
+  LAUNCH_CHECK();
+  {
+    std::lock_guard<std::mutex> lock(g_blas_mu);
+    rocblas_handle &h = g_blas[P->device & 63];
+    if (!h && rocblas_create_handle(&h) != rocblas_status_success) return SVDS_EDEVICE;
+    if (rocblas_set_stream(h, P->stream) != rocblas_status_success) return SVDS_EDEVICE;
+    const double one = 1.0, mone = -1.0;
+    if (rocblas_set_pointer_mode(h, rocblas_pointer_mode_host) != rocblas_status_success) return SVDS_EDEVICE;
+    if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, static_cast<rocblas_int>(m), k,
+                      static_cast<rocblas_int>(n), &one, A, static_cast<rocblas_int>(lda), V,
+                      static_cast<rocblas_int>(n), &mone, P->dr1, static_cast<rocblas_int>(m)) !=
+        rocblas_status_success)
+      return SVDS_EDEVICE;
+    if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, static_cast<rocblas_int>(n), k,
+                      static_cast<rocblas_int>(m), &one, A, static_cast<rocblas_int>(lda), U,
+                      static_cast<rocblas_int>(m), &mone, P->dr2, static_cast<rocblas_int>(n)) !=
+        rocblas_status_success)
+      return SVDS_EDEVICE;
+  }
+  hipLaunchKernelGGL(col_norms_kernel, dim3(k), dim3(256), 0, P->stream, m, P->dr1, res_av);
+  hipLaunchKernelGGL(col_norms_kernel, dim3(k), dim3(256), 0, P->stream, n, P->dr2, res_atu);
+  LAUNCH_CHECK();
+  ACC_AFTER(SVDS_KC_OTHER, 2.0 * 8.0 * m * n, 4.0 * m * n * k);
+  return SVDS_OK;
+}
+
 static int residuals_impl(svds_plan *P, int k, const double *U, const double *S, const double *V,
                           double *res_av, double *res_atu) {
   const int64_t m = P->op.m, n = P->op.n;
   const int64_t sv = P->n_spmv, st = P->n_spmvT;
+  if (P->op.dense && P->dr1 && m < (int64_t(1) << 31) && n < (int64_t(1) << 31) && P->op.lda < (int64_t(1) << 31))
+    return residuals_dense(P, k, U, S, V, res_av, res_atu);
   if (!P->op.dense && P->rs_pu) {
     return P->op.vt == SVDS_F64 ? residuals_csr_block<double>(P, k, U, S, V, res_av, res_atu)
                                 : residuals_csr_block<float>(P, k, U, S, V, res_av, res_atu);

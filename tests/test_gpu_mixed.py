@@ -133,3 +133,9 @@ def test_mixed_dense_bf16_full_size_against_stored_oracle(S):
     s = torch.from_numpy(Sg).cuda()
     r2 = torch.linalg.norm(A.T @ U - V * s, dim=0) / s
     assert float(r2.max()) <= 2e-8
+    # the library's FP64 residuals (GEMM form) agree with the independent ones;
+    # both are at rounding level here, so the agreement is absolute
+    assert abs(info["max_res_true"] - float(r2.max())) <= 1e-12
+    r1 = torch.linalg.norm(A @ V - U * s, dim=0) / s[0]
+    assert abs(info["max_res_av"] - float(r1.max())) <= 1e-12
+    assert info["max_res_true"] <= 2e-8 and info["max_res_av"] <= 2e-8
