@@ -43,24 +43,15 @@ template <> __device__ __forceinline__ double widen<double, uint16_t>(uint16_t b
 // Reductions.  Block sums combine waves in index order; all reductions in
 // this library are deterministic (no float atomics).
 //
-// The xor butterfly alone does NOT leave every lane with the same bits: the
-// compiler may fuse the caller's product into the first butterfly add
-// (fma(x, x, partner's rounded x*x)), so partners round differently.  Code
-// that branches on a reduced value (the Jacobi rotation test) needs a
-// wave-uniform result, so the sum of lane 0 is broadcast to all lanes.
-// ---------------------------------------------------------------------------
-template <typename T> __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return __shfl(v, 0, WAVE);
-}
-
-// Full-wave sum in a fixed order with the result held in a scalar register,
-// so every lane sees the same bits by construction.  DPP steps: swap lanes
+// Full-wave sums run in a fixed order with the result held in a scalar
+// register, so every lane sees the same bits by construction (a plain xor
+// butterfly does not guarantee that: the compiler may fuse the caller's
+// product into the first butterfly add, so partners round differently, and
+// the Jacobi rotation test branches on such sums).  DPP steps: swap lanes
 // within quads (xor 1, xor 2), mirror half-rows and rows (row sums in all 16
 // lanes), then row_bcast:15 / row_bcast:31 accumulate the four row sums into
-// row 3; lane 63 holds the total and is read out.  Every lane of the wave must
-// be active at the call.
+// row 3; lane 63 holds the total and is read out.  Every lane of the wave
+// must be active at the call.  No LDS traffic is involved.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
   return static_cast<uint32_t>(
@@ -71,6 +62,9 @@ template <int CTRL, int ROW_MASK = 0xF> __device__ __forceinline__ double dpp_f6
   const uint32_t lo = dpp_u32<CTRL, ROW_MASK>(static_cast<uint32_t>(u));
   const uint32_t hi = dpp_u32<CTRL, ROW_MASK>(static_cast<uint32_t>(u >> 32));
   return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+template <int CTRL, int ROW_MASK = 0xF> __device__ __forceinline__ float dpp_f32(float v) {
+  return __uint_as_float(dpp_u32<CTRL, ROW_MASK>(__float_as_uint(v)));
 }
 __device__ __forceinline__ double wave_sum_u(double v) {
   v += dpp_f64<0xB1>(v);        // quad_perm [1,0,3,2]
@@ -84,6 +78,16 @@ __device__ __forceinline__ double wave_sum_u(double v) {
   const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u >> 32)), WAVE - 1);
   return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
 }
+__device__ __forceinline__ float wave_sum_u(float v) {
+  v += dpp_f32<0xB1>(v);
+  v += dpp_f32<0x4E>(v);
+  v += dpp_f32<0x141>(v);
+  v += dpp_f32<0x140>(v);
+  v += dpp_f32<0x142, 0xA>(v);
+  v += dpp_f32<0x143, 0xC>(v);
+  return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(__float_as_uint(v)), WAVE - 1)));
+}
+template <typename T> __device__ __forceinline__ T wave_sum(T v) { return wave_sum_u(v); }
 
 // Sum over each row of 16 lanes (DPP rows): quad swaps, half-row and row
 // mirrors.  Every add combines two values in both orders on the two lanes
