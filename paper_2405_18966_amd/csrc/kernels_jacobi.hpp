@@ -120,6 +120,21 @@ __device__ __forceinline__ int jacobi_pair(double *__restrict__ wi, double *__re
   return 1;
 }
 
+// 1/x and 1/sqrt(x) from the hardware approximations plus two Newton steps
+// (quadratic convergence from the approximations' ~2^-23 to working precision).
+__device__ __forceinline__ double jac_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double jac_rsqrt(double q) {
+  double y = __builtin_amdgcn_rsq(q);
+  y = fma(0.5 * y, fma(-q * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-q * y, y, 1.0), y);
+  return y;
+}
+
 // Same rotation for one pair per group of 16 lanes (4 pairs per wave, RPL
 // rows per lane): the four pairs' sums and rotation parameters are computed
 // by the same instructions.  Every lane of the wave takes part (a group with
@@ -147,9 +162,18 @@ __device__ __forceinline__ int jacobi_pair16(double *__restrict__ wi, double *__
   b = row16_sum(b);
   c = row16_sum(c);
   if (!has || !(fabs(c) > tolJ * sqrt(a * b))) return 0;
-  const double z = (b - a) / (2.0 * c);
-  const double tt = (z >= 0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-  const double cs = 1.0 / sqrt(1.0 + tt * tt);
+  // Rutishauser's parameters with hardware reciprocal / reciprocal square
+  // root, each refined by two Newton steps (full double accuracy; the
+  // rotation only needs cs^2 + sn^2 = 1 to working precision)
+  const double z = (b - a) * jac_rcp(2.0 * c);
+  double tt;
+  if (fabs(z) < 1e100) {
+    const double q = fma(z, z, 1.0);
+    tt = (z >= 0 ? 1.0 : -1.0) * jac_rcp(fabs(z) + q * jac_rsqrt(q));
+  } else {
+    tt = 0.5 / z;  // sqrt(1 + z^2) = |z| to working precision
+  }
+  const double cs = jac_rsqrt(fma(tt, tt, 1.0));
   const double sn = cs * tt;
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
@@ -160,6 +184,54 @@ __device__ __forceinline__ int jacobi_pair16(double *__restrict__ wi, double *__
       vi[r] = cs * yi[t] - sn * yj[t];
       vj[r] = sn * yi[t] + cs * yj[t];
     }
+  }
+  return 1;
+}
+
+// As jacobi_pair16 with column i held in registers (xi, yi: this lane's RPL
+// rows of W and Vh): in the cross rounds of the block schedule a group keeps
+// its column for the whole round, so only column j travels through LDS.
+template <int RPL>
+__device__ __forceinline__ int jacobi_pair16_reg(double (&xi)[RPL], double (&yi)[RPL], double *__restrict__ wj,
+                                                 double *__restrict__ vj, int rows, int sl, double tolJ,
+                                                 bool has) {
+  double xj[RPL], yj[RPL];
+  double a = 0, b = 0, c = 0;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = sl + t * 16;
+    const bool ok = has && r < rows;
+    xj[t] = ok ? wj[r] : 0.0;
+    yj[t] = ok ? vj[r] : 0.0;
+    a += xi[t] * xi[t];
+    b += xj[t] * xj[t];
+    c += xi[t] * xj[t];
+  }
+  a = row16_sum(a);
+  b = row16_sum(b);
+  c = row16_sum(c);
+  if (!has || !(fabs(c) > tolJ * sqrt(a * b))) return 0;
+  const double z = (b - a) * jac_rcp(2.0 * c);
+  double tt;
+  if (fabs(z) < 1e100) {
+    const double q = fma(z, z, 1.0);
+    tt = (z >= 0 ? 1.0 : -1.0) * jac_rcp(fabs(z) + q * jac_rsqrt(q));
+  } else {
+    tt = 0.5 / z;
+  }
+  const double cs = jac_rsqrt(fma(tt, tt, 1.0));
+  const double sn = cs * tt;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = sl + t * 16;
+    const double wi = cs * xi[t] - sn * xj[t];
+    const double vi = cs * yi[t] - sn * yj[t];
+    if (r < rows) {
+      wj[r] = sn * xi[t] + cs * xj[t];
+      vj[r] = sn * yi[t] + cs * yj[t];
+    }
+    xi[t] = wi;
+    yi[t] = vi;
   }
   return 1;
 }
@@ -391,11 +463,31 @@ __global__ __launch_bounds__(256) void bjac_round_kernel(const double *__restric
       __syncthreads();
     }
   } else {
+    // column i = q stays with this group for the round: keep it in registers
+    double xi[RPL], yi[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int r = sl + t * 16;
+      const bool ok = own && r < p;
+      xi[t] = ok ? X[q * p + r] : 0.0;
+      yi[t] = ok ? Y[q * p + r] : 0.0;
+    }
     for (int step = 0; step < c; ++step) {
-      const int i = q, j = c + (q + step) % c;
-      nrot += jacobi_pair16<RPL>(own ? X + i * p : nullptr, X + j * p, Y + i * p, Y + j * p, p, sl, tolJ);
+      const int j = c + (q + step) % c;
+      nrot += jacobi_pair16_reg<RPL>(xi, yi, X + (own ? j : 0) * p, Y + (own ? j : 0) * p, p, sl, tolJ, own);
       __syncthreads();
     }
+    if (own) {
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = sl + t * 16;
+        if (r < p) {
+          X[q * p + r] = xi[t];
+          Y[q * p + r] = yi[t];
+        }
+      }
+    }
+    __syncthreads();
   }
   for (int idx = tid; idx < c2 * p; idx += blockDim.x) {
     const int lc = idx / p, r = idx - lc * p;
