@@ -140,3 +140,16 @@ def test_batched_full_size_256_problems(S):
         assert float((Vg.T @ Vg - eye).abs().max()) <= 1e-12
         Ur, Sr, Vr, info = svds_ref.svds(as_operator(As[b]), k, p, 1e-12, 2000, seed=seed + b)
         np.testing.assert_allclose(res[b].S.cpu().numpy(), Sr, rtol=1e-8)
+
+
+def test_batched_fp32_values(S):
+    """Problems stored with FP32 values (widened exactly): FP64 batched path
+    against the oracle on the widened matrices."""
+    As = [inputs.round_values_f32(A) for A in _uneven(4, 16)]
+    k, p, tol, seed = 5, 15, 1e-10, 40
+    res, rc = _batch(S, As, k, p, tol, seed=seed)
+    assert rc == 0
+    for b, (A, r) in enumerate(zip(As, res)):
+        A64 = inputs.CSR(A.m, A.n, A.row_ptr, A.col_idx, A.val.astype(np.float64))
+        Ur, Sr, Vr, info = svds_ref.svds(as_operator(A64), k, p, tol, 2000, seed=seed + b)
+        _check_problem(A64, r, Sr, tol, 1e-10)
