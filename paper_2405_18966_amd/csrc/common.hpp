@@ -101,11 +101,6 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
-template <typename T> __device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
-  return v;
-}
 
 // Sum over the block; result valid in every thread.  `sh` holds >= 16 T.
 template <typename T> __device__ __forceinline__ T block_sum(T v, T *sh) {
