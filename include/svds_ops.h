@@ -24,6 +24,23 @@ extern "C" {
 int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *x_scale, const double *coef,
                      const void *yprev, void *y, int32_t basis_dtype, void *stream);
 
+/* The sparse mat-vec as the solver runs it (Alg. 1 steps 2/5/7):
+ *   y = x_scale * op(A) x - coef * yprev, op(A) = A or A^T (transpose != 0),
+ * through a plan of A that is created, used once and destroyed: A^T x uses
+ * the plan's device transpose and, when x is long (more than 2 MiB of FP64
+ * entries) and A^T has enough entries per row, the column-panel form
+ * (sum over row panels A_g of A of A_g^T x_g, each XCD gathering from one
+ * slice of x; partial sums added in panel order).  x has op(A)'s column
+ * count, yprev and y its row count; device vectors of `basis_dtype`.
+ * x_scale, coef: DEVICE pointers to one double each, or NULL as in
+ * svds_op_spmv_csr.  *panels (host, may be NULL) receives the number of
+ * column panels used (1 = the plain product).  A needs m >= 2, n >= 3
+ * (a plan's smallest Lanczos dimension); EINVAL otherwise or on null
+ * pointers; ENOMEM if the plan does not fit. */
+int svds_op_csr_matvec(const svds_csr *A, int32_t transpose, const void *x, const double *x_scale,
+                       const double *coef, const void *yprev, void *y, int32_t basis_dtype,
+                       int32_t *panels, void *stream);
+
 /* Dense mat-vec (column-major A, F64/F32/BF16 storage widened exactly):
  *   y = x_scale * op(A) x - coef * yprev, op(A) = A or A^T (transpose != 0). */
 int svds_op_dense_matvec(const svds_dense *A, int32_t transpose, const void *x, const double *x_scale,

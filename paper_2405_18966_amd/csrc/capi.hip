@@ -143,6 +143,27 @@ extern "C" int svds_op_dense_matvec(const svds_dense *A, int32_t transpose, cons
   return rc;
 }
 
+extern "C" int svds_op_csr_matvec(const svds_csr *A, int32_t transpose, const void *x,
+                                  const double *x_scale, const double *coef, const void *yprev,
+                                  void *y, int32_t basis_dtype, int32_t *panels, void *stream) {
+  if (!A || !x || !y) return SVDS_EINVAL;
+  if (A->m < 2 || A->n < 3) return SVDS_EINVAL;
+  if (basis_dtype != SVDS_F64 && basis_dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
+  svds_opts o{};
+  o.k = 1;
+  o.p = 2;
+  o.stream = stream;
+  o.precision = basis_dtype == SVDS_F32 ? SVDS_PREC_MIXED : SVDS_PREC_FP64;
+  o.flags = SVDS_FLAG_NO_RESIDUALS;
+  svds_plan *P = nullptr;
+  int rc = svds_plan_create_csr(A, &o, &P);
+  if (rc) return rc;
+  if (panels) *panels = transpose ? svds_plan_panels(P) : 1;
+  rc = svds_plan_matvec(P, transpose, x, x_scale, coef, yprev, y, basis_dtype);
+  svds_plan_destroy(P);
+  return rc;
+}
+
 extern "C" int svds_op_csc_build(const svds_csr *A, int32_t *t_row_ptr, int32_t *t_col_idx,
                                  void *t_val, void *stream) {
   if (!A || !t_row_ptr || (A->nnz > 0 && (!t_col_idx || !t_val))) return SVDS_EINVAL;

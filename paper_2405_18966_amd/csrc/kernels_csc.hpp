@@ -1,5 +1,6 @@
 // Device construction of the CSR of A^T (a column-major copy of A) from the
-// CSR of A, for the product A^T u of Alg. 1 step 5.
+// CSR of A, for the product A^T u of Alg. 1 step 5; the same sort with
+// panel-offset keys builds the stacked transpose of the panelled product.
 //
 // The CSR of A lists entries in (row, col) order, so a *stable* sort by
 // column yields (col, row) order: every column's entries come out in
@@ -19,15 +20,20 @@ constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // keys per tile
 constexpr int RS_BITS = 8;
 constexpr int RS_BINS = 1 << RS_BITS;
 
-// rowof[z] = row of entry z; keys[z] = col[z]; perm[z] = z.
+// rowof[z] = row of entry z; keys[z] = col[z] + (row / rows_per_panel) * n;
+// perm[z] = z.  With rows_per_panel >= m every key is the column (the plain
+// transpose); with panels of rows the sort yields the stacked transpose
+// [A_0^T; A_1^T; ...], A_g = rows [g rpp, (g + 1) rpp) of A.
 static __global__ void csc_expand_kernel(int64_t m, const int32_t *__restrict__ row_ptr,
-                                  const int32_t *__restrict__ col, int32_t *__restrict__ rowof,
-                                  int32_t *__restrict__ keys, int32_t *__restrict__ perm) {
+                                  const int32_t *__restrict__ col, int64_t rows_per_panel, int64_t n,
+                                  int32_t *__restrict__ rowof, int32_t *__restrict__ keys,
+                                  int32_t *__restrict__ perm) {
   const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= m) return;
+  const int32_t off = static_cast<int32_t>((r / rows_per_panel) * n);
   for (int32_t z = row_ptr[r]; z < row_ptr[r + 1]; ++z) {
     rowof[z] = static_cast<int32_t>(r);
-    keys[z] = col[z];
+    keys[z] = col[z] + off;
     perm[z] = z;
   }
 }

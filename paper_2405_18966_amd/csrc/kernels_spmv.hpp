@@ -177,6 +177,29 @@ __global__ __launch_bounds__(WAVE) void spmv_longrow_fixup_kernel(const LongRow 
   if (threadIdx.x == 0) y[L.row] = xs * t - (yprev ? coef * yprev[L.row] : TB(0));
 }
 
+// Column panels of the transpose product.  When u is much larger than one
+// XCD's L2, A^T u is computed as sum_g A_g^T u_g over row panels A_g of A
+// (column panels of A^T): the stacked CSR [A_0^T; ...; A_{P-1}^T] runs
+// through spmv_csr_kernel with its work items interleaved so that block b
+// works on panel (b mod 8) mod P (workgroups are dispatched to the 8 XCDs
+// round-robin), so each XCD gathers from one slice of u that stays in its L2.
+// This kernel adds the panel partials in panel order and applies the
+// -coef * yprev term: y[r] = sum_g ypart[g n + r] - coef * yprev[r].
+template <typename TB>
+__global__ void spmv_panel_sum_kernel(int64_t n, int np, const TB *__restrict__ ypart,
+                                      const double *__restrict__ coef_ptr, const TB *__restrict__ yprev,
+                                      TB *__restrict__ y) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  TB s = 0;
+  for (int g = 0; g < np; ++g) s += ypart[g * n + r];
+  const TB coef = coef_ptr ? static_cast<TB>(*coef_ptr) : TB(0);
+  y[r] = s - (yprev ? coef * yprev[r] : TB(0));
+}
+constexpr int SPMV_MAX_PANELS = 8;
+constexpr int64_t SPMV_PANEL_BYTES = int64_t(2) << 20;  // FP64 slice of u per panel
+constexpr int SPMV_PANEL_MIN_NNZ = 4;                   // mean entries per stacked row
+
 }  // namespace svds
 
 namespace svds {

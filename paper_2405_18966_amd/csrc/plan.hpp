@@ -92,6 +92,16 @@ struct Operator {
   int32_t *trp = nullptr, *tci = nullptr;
   void *tval = nullptr;
   SpmvPlan fwd, bwd;
+  // A^T u by column panels (see spmv_panel_sum_kernel): npanel > 1 for a
+  // single problem whose u is large; stacked CSR (npanel n rows), partial
+  // products (npanel n), work items; in their own allocations
+  int npanel = 1;
+  int32_t *prp = nullptr, *pci = nullptr;
+  void *pval = nullptr;
+  double *ypart = nullptr;
+  SpmvPlan bwdp;
+  void *pbuf = nullptr, *pbuf_items = nullptr;
+  size_t pbuf_bytes = 0;
   // dense
   const void *a = nullptr;
   int64_t lda = 0;
@@ -105,6 +115,7 @@ int svds_plan_residuals(svds_plan *P, int k, const double *U, const double *S, c
                         double *res_av, double *res_atu);
 int svds_plan_matvec(svds_plan *P, int trans, const void *x, const double *xs, const double *coef,
                      const void *yprev, void *y, int basis_dtype);
+int svds_plan_panels(const svds_plan *P);
 int svds_plan_transpose_copy(svds_plan *P, int32_t *t_row_ptr, int32_t *t_col_idx, void *t_val);
 int svds_cgs2_op(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
                  double *norm_out, int32_t dtype, void *stream);

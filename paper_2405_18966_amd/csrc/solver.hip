@@ -214,7 +214,6 @@ struct svds_plan {
   Accounting acc;
   int64_t n_spmv = 0, n_spmvT = 0;
   int cycles32 = 0, cycles64 = 0, jac_sweeps = 0;
-  int32_t *own_blocks[4] = {};
 };
 
 namespace svds {
@@ -269,22 +268,31 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     LAUNCH_CHECK();
     bytes = vsize(op.vt) * op.m * op.n + sb * cols + (yprev ? 2.0 : 1.0) * sb * rows;
   } else {
-    const SpmvPlan &sp = trans ? op.bwd : op.fwd;
-    const int32_t *rp = trans ? op.trp : op.rp;
-    const int32_t *ci = trans ? op.tci : op.ci;
-    const void *val = trans ? op.tval : op.val;
+    // panelled transpose: partial products y_g = xs A_g^T u_g into ypart,
+    // then their fixed-order sum minus coef * yprev
+    const bool panels = trans && op.npanel > 1;
+    const SpmvPlan &sp = panels ? op.bwdp : trans ? op.bwd : op.fwd;
+    const int32_t *rp = panels ? op.prp : trans ? op.trp : op.rp;
+    const int32_t *ci = panels ? op.pci : trans ? op.tci : op.ci;
+    const void *val = panels ? op.pval : trans ? op.tval : op.val;
+    TB *yk = panels ? reinterpret_cast<TB *>(op.ypart) : y;
+    const double *ck = panels ? nullptr : coef;
+    const TB *ypk = panels ? nullptr : yprev;
     TB *parts = reinterpret_cast<TB *>(sp.partials);
     if (op.vt == SVDS_F64)
       hipLaunchKernelGGL((spmv_csr_kernel<double, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-                         P->stream, sp.items, rp, ci, static_cast<const double *>(val), x, xs, coef,
-                         yprev, y, parts, side_dst, side_len, sp.x_tile_inst, sp.active);
+                         P->stream, sp.items, rp, ci, static_cast<const double *>(val), x, xs, ck,
+                         ypk, yk, parts, side_dst, side_len, sp.x_tile_inst, sp.active);
     else
       hipLaunchKernelGGL((spmv_csr_kernel<float, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-                         P->stream, sp.items, rp, ci, static_cast<const float *>(val), x, xs, coef,
-                         yprev, y, parts, side_dst, side_len, sp.x_tile_inst, sp.active);
+                         P->stream, sp.items, rp, ci, static_cast<const float *>(val), x, xs, ck,
+                         ypk, yk, parts, side_dst, side_len, sp.x_tile_inst, sp.active);
     if (sp.nlong > 0)
       hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(sp.nlong), dim3(WAVE), 0,
-                         P->stream, sp.longrows, sp.nlong, parts, xs, coef, yprev, y, sp.active);
+                         P->stream, sp.longrows, sp.nlong, parts, xs, ck, ypk, yk, sp.active);
+    if (panels)
+      hipLaunchKernelGGL((spmv_panel_sum_kernel<TB>), dim3(ceil_div(op.n, 256)), dim3(256), 0, P->stream,
+                         op.n, op.npanel, yk, coef, yprev, y);
     LAUNCH_CHECK();
     bytes = 4.0 * (rows + 1) + (4.0 + vsize(op.vt)) * op.nnz + sb * cols +
             (yprev ? 2.0 : 1.0) * sb * rows;
@@ -673,12 +681,16 @@ static int alloc_arena(svds_plan *P) {
 }
 
 // Transposed copy: stable LSD radix sort of column keys (see kernels_csc.hpp).
-static int build_transpose(svds_plan *P) {
+// npanel = 1: the CSR of A^T; npanel > 1: the stacked transpose of the row
+// panels of A (rows_per_panel rows each), npanel n rows.
+static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int32_t *out_rp,
+                           int32_t *out_ci, void *out_val) {
   Operator &op = P->op;
-  const int64_t m = op.m, n = op.n, nnz = op.nnz;
+  const int64_t m = op.m, nnz = op.nnz;
+  const int64_t n = op.n * npanel;  // keys
   hipStream_t st = P->stream;
   if (nnz == 0) {
-    hipLaunchKernelGGL(fill_i32_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0, st, n + 1, 0, op.trp);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0, st, n + 1, 0, out_rp);
     LAUNCH_CHECK();
     return SVDS_OK;
   }
@@ -693,7 +705,7 @@ static int build_transpose(svds_plan *P) {
   int rc = SVDS_OK;
   do {
     hipLaunchKernelGGL(csc_expand_kernel, dim3(ceil_div(m, 256)), dim3(256), 0, st, m, op.rp, op.ci,
-                       rowof, k0, v0);
+                       rows_per_panel, op.n, rowof, k0, v0);
     if (hipGetLastError() != hipSuccess) { rc = SVDS_EDEVICE; break; }
     int bits = 1;
     while ((int64_t(1) << bits) < n) ++bits;
@@ -713,13 +725,13 @@ static int build_transpose(svds_plan *P) {
     if (rc) break;
     if (op.vt == SVDS_F64)
       hipLaunchKernelGGL((csc_gather_kernel<double>), dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz,
-                         vin, rowof, static_cast<const double *>(op.val), op.tci,
-                         static_cast<double *>(op.tval));
+                         vin, rowof, static_cast<const double *>(op.val), out_ci,
+                         static_cast<double *>(out_val));
     else
       hipLaunchKernelGGL((csc_gather_kernel<float>), dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz,
-                         vin, rowof, static_cast<const float *>(op.val), op.tci,
-                         static_cast<float *>(op.tval));
-    hipLaunchKernelGGL(csc_colptr_kernel, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz, n, kin, op.trp);
+                         vin, rowof, static_cast<const float *>(op.val), out_ci,
+                         static_cast<float *>(out_val));
+    hipLaunchKernelGGL(csc_colptr_kernel, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz, n, kin, out_rp);
     if (hipGetLastError() != hipSuccess) { rc = SVDS_EDEVICE; break; }
     if (hipStreamSynchronize(st) != hipSuccess) { rc = SVDS_EDEVICE; break; }
   } while (0);
@@ -736,6 +748,91 @@ static int upload_spmv(svds_plan *P, SpmvPlan &sp) {
   }
   HIP_TRY(hipStreamSynchronize(P->stream));
   return SVDS_OK;
+}
+
+
+// Column panels of the transpose product (see spmv_panel_sum_kernel).  The
+// count is the power of two that cuts u into FP64 slices of at most
+// SPMV_PANEL_BYTES, capped at SPMV_MAX_PANELS, and lowered while the stacked
+// rows would average fewer than SPMV_PANEL_MIN_NNZ entries (their row pointers
+// and partial sums would then outweigh the gathers saved).
+static int choose_panels(int64_t m, int64_t n, int64_t nnz) {
+  int np = 1;
+  while (np < SPMV_MAX_PANELS && m * 8 > SPMV_PANEL_BYTES * np) np *= 2;
+  while (np > 1 && nnz < SPMV_PANEL_MIN_NNZ * n * np) np /= 2;
+  while (np > 1 && n * np + 1 >= (int64_t(1) << 31)) np /= 2;
+  return np;
+}
+
+static int build_panels(svds_plan *P) {
+  Operator &op = P->op;
+  const int np = op.npanel;
+  const int64_t n = op.n, rows = n * np, nnz = std::max<int64_t>(1, op.nnz);
+  const int64_t rpp = ceil_div(op.m, np);
+  Arena a;
+  auto carve = [&](Arena &ar) {
+    op.prp = ar.take<int32_t>(rows + 1);
+    op.pci = ar.take<int32_t>(nnz);
+    op.pval = ar.take<char>(nnz * static_cast<size_t>(vsize(op.vt)));
+    op.ypart = ar.take<double>(rows);
+  };
+  carve(a);
+  if (hipMalloc(&op.pbuf, a.used) != hipSuccess) {
+    (void)hipGetLastError();
+    op.pbuf = nullptr;
+    return SVDS_ENOMEM;
+  }
+  op.pbuf_bytes = a.used;
+  a.base = static_cast<char *>(op.pbuf);
+  a.used = 0;
+  a.counting = false;
+  carve(a);
+  int rc = build_transpose(P, np, rpp, op.prp, op.pci, op.pval);
+  if (rc) return rc;
+  std::vector<int32_t> hrp(rows + 1);
+  HIP_TRY(hipMemcpy(hrp.data(), op.prp, sizeof(int32_t) * (rows + 1), hipMemcpyDeviceToHost));
+  // items per panel (never crossing a panel), untagged: one problem
+  std::vector<int64_t> ends(np);
+  for (int g = 0; g < np; ++g) ends[g] = n * (g + 1);
+  SpmvPlan &sp = op.bwdp;
+  build_spmv_items(hrp.data(), rows, sp, ends.data(), np);
+  for (auto &L : sp.h_long) L.inst = 0;
+  std::vector<std::vector<int4>> per(np);
+  for (int4 it : sp.h_items) {
+    const int64_t r = it.x >= 0 ? it.x : sp.h_long[-it.x - 1].row;
+    if (it.x >= 0) it.w &= (1 << SPMV_CNT_BITS) - 1;
+    per[r / n].push_back(it);
+  }
+  // slot b -> panel (b mod 8) mod np; a panel that has run out gets empty items
+  std::vector<size_t> next(np, 0);
+  sp.h_items.clear();
+  for (bool left = true; left;) {
+    for (int x = 0; x < 8; ++x) {
+      const int g = x % np;
+      sp.h_items.push_back(next[g] < per[g].size() ? per[g][next[g]++] : make_int4(0, 0, 0, 0));
+    }
+    left = false;
+    for (int g = 0; g < np; ++g) left = left || next[g] < per[g].size();
+  }
+  sp.nitems = static_cast<int>(sp.h_items.size());
+  Arena b;
+  auto carve_items = [&](Arena &ar) {
+    sp.items = ar.take<int4>(sp.nitems);
+    sp.longrows = ar.take<LongRow>(std::max(1, sp.nlong));
+    sp.partials = ar.take<double>(std::max(1, sp.npieces));
+  };
+  carve_items(b);
+  if (hipMalloc(&op.pbuf_items, b.used) != hipSuccess) {
+    (void)hipGetLastError();
+    op.pbuf_items = nullptr;
+    return SVDS_ENOMEM;
+  }
+  op.pbuf_bytes += b.used;
+  b.base = static_cast<char *>(op.pbuf_items);
+  b.used = 0;
+  b.counting = false;
+  carve_items(b);
+  return upload_spmv(P, sp);
 }
 
 namespace {
@@ -796,7 +893,7 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   op.bwd.npieces = static_cast<int>(std::max<int64_t>(1, ceil_div(A->nnz, SPMV_PIECE) + op.bwd.nlong));
   const int bwd_items_cap = op.bwd.nitems, bwd_long_cap = op.bwd.nlong, bwd_pieces_cap = op.bwd.npieces;
   if ((rc = alloc_arena(P))) return rc;
-  if ((rc = build_transpose(P))) return rc;
+  if ((rc = build_transpose(P, 1, op.m, op.trp, op.tci, op.tval))) return rc;
   std::vector<int32_t> htrp(A->n + 1);
   HIP_TRY(hipMemcpy(htrp.data(), op.trp, sizeof(int32_t) * (A->n + 1), hipMemcpyDeviceToHost));
   int4 *bi = op.bwd.items;
@@ -809,6 +906,7 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   op.bwd.longrows = bl;
   op.bwd.partials = bp;
   if ((rc = upload_spmv(P, op.fwd)) || (rc = upload_spmv(P, op.bwd))) return rc;
+  if (!seg_rows && (op.npanel = choose_panels(op.m, op.n, op.nnz)) > 1 && (rc = build_panels(P))) return rc;
   *plan = guard.release();
   return SVDS_OK;
 }
@@ -845,6 +943,8 @@ extern "C" int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts
 extern "C" void svds_plan_destroy(svds_plan *P) {
   if (!P) return;
   if (P->arena.base) (void)hipFree(P->arena.base);
+  if (P->op.pbuf) (void)hipFree(P->op.pbuf);
+  if (P->op.pbuf_items) (void)hipFree(P->op.pbuf_items);
   if (P->h_flags) (void)hipHostFree(P->h_flags);
   P->acc.destroy();
   delete P;
@@ -990,7 +1090,7 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
       info->kc_sampled_launches[c] = P->acc.sampled[c];
       info->kc_sampled_bytes[c] = P->acc.sampled_bytes[c];
     }
-    info->workspace_bytes = static_cast<int64_t>(P->arena.size);
+    info->workspace_bytes = static_cast<int64_t>(P->arena.size + P->op.pbuf_bytes);
   }
   return conv ? SVDS_OK : SVDS_NOT_CONVERGED;
 }
@@ -1143,6 +1243,8 @@ int svds_plan_residuals(svds_plan *P, int k, const double *U, const double *S, c
   HIP_TRY(hipStreamSynchronize(P->stream));
   return SVDS_OK;
 }
+
+int svds_plan_panels(const svds_plan *P) { return P->op.dense ? 1 : P->op.npanel; }
 
 int svds_plan_matvec(svds_plan *P, int trans, const void *x, const double *xs, const double *coef,
                      const void *yprev, void *y, int basis_dtype) {

@@ -83,6 +83,7 @@ def _load():
         "svds_version": (C.c_char_p, []),
         "svds_op_spmv_csr": (i32, [P(svds_csr), vp, vp, vp, vp, vp, i32, vp]),
         "svds_op_dense_matvec": (i32, [P(svds_dense), i32, vp, vp, vp, vp, vp, i32, vp]),
+        "svds_op_csr_matvec": (i32, [P(svds_csr), i32, vp, vp, vp, vp, vp, i32, P(i32), vp]),
         "svds_op_csc_build": (i32, [P(svds_csr), vp, vp, vp, vp]),
         "svds_op_cgs2": (i32, [i64, i32, vp, i64, vp, vp, P(d), i32, vp]),
         "svds_op_small_svd": (i32, [i32, i32, d, vp, vp, vp, vp, vp, vp, P(i32), vp]),
@@ -256,6 +257,18 @@ def svds_op_spmv_csr(A: svds_csr, x, x_scale=None, coef=None, yprev=None, y=None
     _check(lib.svds_op_spmv_csr(C.byref(A), _ptr(x), _ptr(x_scale), _ptr(coef), _ptr(yprev), _ptr(y), dt,
                                 _stream(stream)), "svds_op_spmv_csr")
     return y
+
+
+def svds_op_csr_matvec(A: svds_csr, transpose: bool, x, x_scale=None, coef=None, yprev=None, y=None,
+                       stream=None):
+    """Returns (y, panels): panels = column panels the transposed product used."""
+    dt = SVDS_F64 if x.dtype == torch.float64 else SVDS_F32
+    if y is None:
+        y = torch.empty(A.n if transpose else A.m, dtype=x.dtype, device=x.device)
+    np_ = C.c_int32(0)
+    _check(lib.svds_op_csr_matvec(C.byref(A), int(transpose), _ptr(x), _ptr(x_scale), _ptr(coef), _ptr(yprev),
+                                  _ptr(y), dt, C.byref(np_), _stream(stream)), "svds_op_csr_matvec")
+    return y, np_.value
 
 
 def svds_op_dense_matvec(A: svds_dense, transpose: bool, x, x_scale=None, coef=None, yprev=None,

@@ -33,7 +33,8 @@ def test_headers_declare_the_boundary():
     for must in ["svds_plan_create_csr", "svds_plan_create_dense", "svds_plan_execute",
                  "svds_plan_destroy", "svds_csr_solve", "svds_dense_solve", "svds_csr_solve_batched",
                  "svds_residuals_csr", "svds_strerror", "svds_op_spmv_csr", "svds_op_csc_build",
-                 "svds_op_cgs2", "svds_op_small_svd", "svds_op_rotate", "svds_op_philox_normal"]:
+                 "svds_op_cgs2", "svds_op_small_svd", "svds_op_rotate", "svds_op_philox_normal",
+                 "svds_op_csr_matvec"]:
         assert must in names
 
 

@@ -89,6 +89,27 @@ def test_parity_with_oracle(S, case):
     assert info["max_res_true"] <= 2 * tol and info["max_res_est"] < tol
 
 
+def test_parity_with_column_panel_transpose(S):
+    """A long u (300,001 rows of A): the transposed products run in the
+    column-panel form (two panels, power-law rows split into pieces).  Same
+    bar as the other parity cases."""
+    A = inputs.sparse_zipf(300_001, 30_000, 10, 1.1, seed=51)
+    Ad, keep = S.csr_to_device(A)
+    import torch
+    _, npan = S.svds_op_csr_matvec(Ad, True, torch.zeros(A.m, dtype=torch.float64, device="cuda"))
+    assert npan == 2
+    k, p, tol = 8, 24, 1e-10
+    v0 = inputs.start_vector(A.n, 52)
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), k, p, tol, 3000, v0=v0)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, tol, 3000, v0=v0)
+    assert st == 0 and info["converged"] == 1 and info_r.converged
+    np.testing.assert_allclose(Sg, Sr, rtol=1e-10)
+    _invariants(A, Ug, Sg, Vg, tol)
+    _counts_ok(info, p, k)
+    assert abs(info["cycles"] - info_r.cycles) <= 1
+    assert info["max_res_true"] <= 2 * tol and info["max_res_est"] < tol
+
+
 @pytest.mark.parametrize("law", ["decay1", "decay2", "decay3"])
 def test_prescribed_spectrum(S, law):
     nb, bs = 400, 5
