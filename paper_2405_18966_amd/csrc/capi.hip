@@ -106,7 +106,7 @@ extern "C" int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *
 #define SPMV_GO(TV, TB)                                                                             \
   do {                                                                                              \
     hipLaunchKernelGGL((spmv_csr_kernel<TV, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0, st, items, \
-                       A->row_ptr, A->col_idx, static_cast<const TV *>(A->val),                     \
+                       A->row_ptr, A->col_idx, static_cast<const TV *>(A->val), nullptr,            \
                        static_cast<const TB *>(x), x_scale, coef, static_cast<const TB *>(yprev),   \
                        static_cast<TB *>(y), reinterpret_cast<TB *>(parts), nullptr, 0, nullptr, nullptr); \
     if (sp.nlong)                                                                                   \

@@ -14,6 +14,13 @@
 //    spmv_longrow_fixup_kernel (next launch) adds the partials of each long
 //    row in piece order and writes y.  Power-law rows (the heaviest columns of
 //    a Zipf matrix seen through A^T) are spread over many blocks this way.
+//  * Column-sorted items (optional): a plan stores each MULTI item's nonzeros
+//    sorted by column with their row-order positions (spos), built once by
+//    sort_items_kernel.  Gathers of neighbouring lanes then often share a
+//    cache line (1.5x on a block-diagonal batch, 7% on a Zipf matrix, no
+//    change on uniformly random columns, measured on MI355X); the products
+//    are placed in LDS at their row-order positions, so the result is
+//    bit-identical to the row-ordered layout.  PIECE ranges stay in row order.
 //  * Optional side task: dst[i] = src[i] * xs for i < side_len, spread over
 //    the grid.  The solver uses it to write the normalized previous Lanczos
 //    vector into its basis column while the product consumes the
@@ -50,7 +57,8 @@ constexpr int SPMV_TILE_SHIFT = 8;  // 256-row tiles of the problem map
 template <typename TV, typename TB>
 __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     const int4 *__restrict__ items, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const TV *__restrict__ val, const TB *__restrict__ x, const double *__restrict__ xs_ptr,
+    const TV *__restrict__ val, const uint16_t *__restrict__ spos, const TB *__restrict__ x,
+    const double *__restrict__ xs_ptr,
     const double *__restrict__ coef_ptr, const TB *__restrict__ yprev, TB *__restrict__ y,
     TB *__restrict__ partials, TB *__restrict__ side_dst, int64_t side_len,
     const int32_t *__restrict__ x_tile_inst, const int32_t *__restrict__ active) {
@@ -90,7 +98,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     // gathers of x, so each thread has SPMV_NNZ_BLK / SPMV_THREADS loads in
     // flight per round trip instead of one dependent pair per iteration
     constexpr int UPT = SPMV_NNZ_BLK / SPMV_THREADS;
-    int ci[UPT];
+    int ci[UPT], ps[UPT];
     TV cv[UPT];
 #pragma unroll
     for (int u = 0; u < UPT; ++u) {
@@ -99,11 +107,15 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
       // from displacing the gathered x in L2
       ci[u] = z < cnt ? __builtin_nontemporal_load(col + base + z) : 0;
       cv[u] = z < cnt ? __builtin_nontemporal_load(val + base + z) : TV(0);
+      ps[u] = spos ? (z < cnt ? static_cast<int>(__builtin_nontemporal_load(spos + base + z)) : 0) : z;
     }
+    // with spos the item's nonzeros are stored sorted by column (neighbouring
+    // lanes gather from shared cache lines) and each product goes back to its
+    // row-order slot, so the row sums below are unchanged bit for bit
 #pragma unroll
     for (int u = 0; u < UPT; ++u) {
       const int z = tid + u * SPMV_THREADS;
-      if (z < cnt) prod[z] = widen<TB>(cv[u]) * x[ci[u]];
+      if (z < cnt) prod[ps[u]] = widen<TB>(cv[u]) * x[ci[u]];
     }
     __syncthreads();  // products and row pointers in LDS
     if (cnt >= SPMV_WAVE_ROW * nrows) {
@@ -175,6 +187,54 @@ __global__ __launch_bounds__(WAVE) void spmv_longrow_fixup_kernel(const LongRow 
   for (int q = threadIdx.x; q < L.npieces; q += WAVE) t += partials[L.first_piece + q];
   t = wave_sum(t);
   if (threadIdx.x == 0) y[L.row] = xs * t - (yprev ? coef * yprev[L.row] : TB(0));
+}
+
+// Column-sorted copy of a plan's nonzeros: for a MULTI item, (scol, sval)
+// = the item's (col, val) ordered by (column, position) and spos = the
+// position within the item; a PIECE range is copied as it is.  One block per
+// item: keys (column << 11 | position) and values staged in LDS, bitonic sort,
+// written back, so scol/sval may alias col/val (in-place sort).
+template <typename TV>
+__global__ __launch_bounds__(SPMV_THREADS) void sort_items_kernel(const int4 *__restrict__ items,
+                                                                  const int32_t *col, const TV *val,
+                                                                  int32_t *scol, TV *sval,
+                                                                  uint16_t *__restrict__ spos) {
+  static_assert(SPMV_NNZ_BLK <= 2048, "11-bit positions");
+  __shared__ uint64_t key[SPMV_NNZ_BLK];
+  __shared__ TV sv[SPMV_NNZ_BLK];
+  const int tid = threadIdx.x;
+  const int4 it = items[blockIdx.x];
+  if (it.x < 0) {
+    if (scol != col)
+      for (int z = it.z + tid; z < it.w; z += SPMV_THREADS) scol[z] = col[z], sval[z] = val[z];
+    return;
+  }
+  const int base = it.z, cnt = it.w & ((1 << SPMV_CNT_BITS) - 1);
+  int p2 = 1;
+  while (p2 < cnt) p2 <<= 1;
+  for (int i = tid; i < p2; i += SPMV_THREADS) {
+    key[i] = i < cnt ? (static_cast<uint64_t>(static_cast<uint32_t>(col[base + i])) << 11) | static_cast<uint64_t>(i)
+                     : ~0ull;
+    if (i < cnt) sv[i] = val[base + i];
+  }
+  __syncthreads();
+  for (int k = 2; k <= p2; k <<= 1)
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int i = tid; i < p2; i += SPMV_THREADS) {
+        const int l = i ^ jj;
+        if (l > i) {
+          const uint64_t a = key[i], b = key[l];
+          if ((a > b) == ((i & k) == 0)) key[i] = b, key[l] = a;
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = tid; i < cnt; i += SPMV_THREADS) {
+    const int pos = static_cast<int>(key[i] & 2047u);
+    scol[base + i] = static_cast<int32_t>(key[i] >> 11);
+    sval[base + i] = sv[pos];
+    spos[base + i] = static_cast<uint16_t>(pos);
+  }
 }
 
 // Column panels of the transpose product.  When u is much larger than one

@@ -36,6 +36,11 @@ struct SpmvPlan {
   double *partials = nullptr;  // npieces (TB <= 8 bytes)
   std::vector<int4> h_items;
   std::vector<LongRow> h_long;
+  // column-sorted nonzeros of the items (sort_items_kernel), or null: the
+  // product then reads the matrix's own arrays in row order
+  int32_t *scol = nullptr;
+  void *sval = nullptr;
+  uint16_t *spos = nullptr;
   const int32_t *x_tile_inst = nullptr;  // problem of each 256-entry tile of x (batched), or null
   const int32_t *active = nullptr;       // per-problem work mask (batched), or null
 };

@@ -275,17 +275,19 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     const int32_t *rp = panels ? op.prp : trans ? op.trp : op.rp;
     const int32_t *ci = panels ? op.pci : trans ? op.tci : op.ci;
     const void *val = panels ? op.pval : trans ? op.tval : op.val;
+    const int32_t *cs = sp.spos ? sp.scol : ci;
+    const void *vs = sp.spos ? sp.sval : val;
     TB *yk = panels ? reinterpret_cast<TB *>(op.ypart) : y;
     const double *ck = panels ? nullptr : coef;
     const TB *ypk = panels ? nullptr : yprev;
     TB *parts = reinterpret_cast<TB *>(sp.partials);
     if (op.vt == SVDS_F64)
       hipLaunchKernelGGL((spmv_csr_kernel<double, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-                         P->stream, sp.items, rp, ci, static_cast<const double *>(val), x, xs, ck,
+                         P->stream, sp.items, rp, cs, static_cast<const double *>(vs), sp.spos, x, xs, ck,
                          ypk, yk, parts, side_dst, side_len, sp.x_tile_inst, sp.active);
     else
       hipLaunchKernelGGL((spmv_csr_kernel<float, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-                         P->stream, sp.items, rp, ci, static_cast<const float *>(val), x, xs, ck,
+                         P->stream, sp.items, rp, cs, static_cast<const float *>(vs), sp.spos, x, xs, ck,
                          ypk, yk, parts, side_dst, side_len, sp.x_tile_inst, sp.active);
     if (sp.nlong > 0)
       hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(sp.nlong), dim3(WAVE), 0,
@@ -651,6 +653,18 @@ static int carve_all(svds_plan *P, Arena &a) {
         a.take<double>(static_cast<size_t>(std::max(1, std::max(P->op.fwd.npieces, P->op.bwd.npieces))) * RG);
     P->rs_lpart = a.take<double>(static_cast<size_t>(std::max(1, std::max(P->op.fwd.nlong, P->op.bwd.nlong))) * RG);
     P->rs_s = a.take<double>(RG);
+    // column-sorted copies for the products: A always, A^T unless the
+    // column-panel form replaces it (that one is sorted in place)
+    const int64_t nz = std::max<int64_t>(1, P->op.nnz);
+    const size_t vb = static_cast<size_t>(vsize(P->op.vt));
+    P->op.fwd.scol = a.take<int32_t>(nz);
+    P->op.fwd.sval = a.take<char>(nz * vb);
+    P->op.fwd.spos = a.take<uint16_t>(nz);
+    if (P->op.npanel == 1) {
+      P->op.bwd.scol = a.take<int32_t>(nz);
+      P->op.bwd.sval = a.take<char>(nz * vb);
+      P->op.bwd.spos = a.take<uint16_t>(nz);
+    }
     P->op.trp = a.take<int32_t>(n + 1);
     P->op.tci = a.take<int32_t>(std::max<int64_t>(1, P->op.nnz));
     P->op.tval = a.take<char>(std::max<int64_t>(1, P->op.nnz) * static_cast<size_t>(vsize(P->op.vt)));
@@ -739,6 +753,19 @@ static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int
   return rc;
 }
 
+// Column-sorted copy of a product's nonzeros (see sort_items_kernel).
+static int sort_spmv(svds_plan *P, SpmvPlan &sp, const int32_t *col, const void *val) {
+  if (!sp.spos || sp.nitems == 0) return SVDS_OK;
+  if (P->op.vt == SVDS_F64)
+    hipLaunchKernelGGL((sort_items_kernel<double>), dim3(sp.nitems), dim3(SPMV_THREADS), 0, P->stream, sp.items,
+                       col, static_cast<const double *>(val), sp.scol, static_cast<double *>(sp.sval), sp.spos);
+  else
+    hipLaunchKernelGGL((sort_items_kernel<float>), dim3(sp.nitems), dim3(SPMV_THREADS), 0, P->stream, sp.items,
+                       col, static_cast<const float *>(val), sp.scol, static_cast<float *>(sp.sval), sp.spos);
+  HIP_TRY(hipGetLastError());
+  return SVDS_OK;
+}
+
 static int upload_spmv(svds_plan *P, SpmvPlan &sp) {
   HIP_TRY(hipMemcpyAsync(sp.items, sp.h_items.data(), sizeof(int4) * sp.nitems, hipMemcpyHostToDevice,
                          P->stream));
@@ -775,6 +802,7 @@ static int build_panels(svds_plan *P) {
     op.pci = ar.take<int32_t>(nnz);
     op.pval = ar.take<char>(nnz * static_cast<size_t>(vsize(op.vt)));
     op.ypart = ar.take<double>(rows);
+    op.bwdp.spos = ar.take<uint16_t>(nnz);
   };
   carve(a);
   if (hipMalloc(&op.pbuf, a.used) != hipSuccess) {
@@ -832,7 +860,10 @@ static int build_panels(svds_plan *P) {
   b.used = 0;
   b.counting = false;
   carve_items(b);
-  return upload_spmv(P, sp);
+  if ((rc = upload_spmv(P, sp))) return rc;
+  sp.scol = op.pci;  // sorted in place: only the product reads the stacked copy
+  sp.sval = op.pval;
+  return sort_spmv(P, sp, op.pci, op.pval);
 }
 
 namespace {
@@ -886,6 +917,7 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   for (int64_t i = 0; i < A->m; ++i)
     if (hrp[i + 1] < hrp[i]) return SVDS_EINVAL;
   build_spmv_items(hrp.data(), A->m, op.fwd, seg_rows, nseg);
+  op.npanel = seg_rows ? 1 : choose_panels(op.m, op.n, op.nnz);
   // A^T items need the column counts: computed after the device transpose,
   // so size the arena with a bound first (one item per column is the max).
   op.bwd.nitems = static_cast<int>(std::max<int64_t>(1, A->n + ceil_div(A->nnz, SPMV_PIECE) + 1));
@@ -906,7 +938,9 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   op.bwd.longrows = bl;
   op.bwd.partials = bp;
   if ((rc = upload_spmv(P, op.fwd)) || (rc = upload_spmv(P, op.bwd))) return rc;
-  if (!seg_rows && (op.npanel = choose_panels(op.m, op.n, op.nnz)) > 1 && (rc = build_panels(P))) return rc;
+  if ((rc = sort_spmv(P, op.fwd, op.ci, op.val)) || (rc = sort_spmv(P, op.bwd, op.tci, op.tval))) return rc;
+  if (op.npanel > 1 && (rc = build_panels(P))) return rc;
+  HIP_TRY(hipStreamSynchronize(P->stream));
   *plan = guard.release();
   return SVDS_OK;
 }

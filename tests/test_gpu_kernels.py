@@ -145,6 +145,35 @@ def test_transposed_product_column_panels(S, m, panels):
     np.testing.assert_allclose(y.cpu().numpy(), Asp @ v, rtol=1e-12, atol=1e-12 * np.abs(Asp @ v).max())
 
 
+@pytest.mark.parametrize("maker", [
+    lambda: inputs.sparse_zipf(60000, 20000, 10, 1.1, seed=23),
+    lambda: inputs.sparse_uniform(9000, 7000, 300000, seed=24),
+    lambda: inputs.round_values_f32(inputs.sparse_uniform(3000, 2000, 60000, seed=25)),
+])
+def test_column_sorted_items_bit_identical(S, maker):
+    """A plan stores every work item's nonzeros sorted by column and puts the
+    products back at their row-order positions: A x and A^T x through a plan
+    equal, bit for bit, the row-ordered product over the same items."""
+    import torch
+    A = maker()
+    Ad, keep = S.csr_to_device(A)
+    rng = np.random.default_rng(26)
+    for tb in (torch.float64, torch.float32):
+        x = _t(rng.standard_normal(A.n), tb)
+        yp = _t(rng.standard_normal(A.m), tb)
+        y_plan, _ = S.svds_op_csr_matvec(Ad, False, x, _scalar(0.5), _scalar(2.0), yp)
+        y_rows = S.svds_op_spmv_csr(Ad, x, _scalar(0.5), _scalar(2.0), yp)
+        assert torch.equal(y_plan, y_rows)
+        vdt = torch.float64 if A.val.dtype == np.float64 else torch.float32
+        trp, tci, tv = S.svds_op_csc_build(Ad, vdt)
+        T = S.make_csr(trp, tci, tv, A.n, A.m)
+        u = _t(rng.standard_normal(A.m), tb)
+        z_plan, npan = S.svds_op_csr_matvec(Ad, True, u)
+        assert npan == 1
+        z_rows = S.svds_op_spmv_csr(T, u)
+        assert torch.equal(z_plan, z_rows)
+
+
 def test_transposed_product_no_panels_for_short_or_sparse(S):
     """Short x, or too few entries per row of A^T: the plain product."""
     for A in (inputs.sparse_zipf(200_000, 20_000, 10, 1.1, seed=19),
