@@ -65,11 +65,21 @@ struct Batch {
   int32_t *active = nullptr, *freeze = nullptr;  // per-problem work mask, problems to freeze
   double **optr = nullptr;  // output pointer tables U[nb], V[nb], S[nb]
   int *h_flags = nullptr;   // pinned, 4 per problem
+  // work lists of the active problems (rebuilt when the active set changes):
+  // product items of A and A^T, U-side and V-side tiles
+  char *wl_mem = nullptr;
+  int4 *wl_items[2] = {};
+  int32_t *wl_tiles[2] = {};
+  int wl_ntiles[2] = {};
+  std::vector<int> item_prob[2];  // problem of each full-list item
+  std::vector<int4> h_wl_items;
+  std::vector<int32_t> h_wl_tiles;
   std::vector<int32_t> h_active;
   std::vector<int> conv_cycle;  // cycle (of the current phase) at which each problem converged
   ~Batch() {
     if (P) svds_plan_destroy(P);
     if (mem) (void)hipFree(mem);
+    if (wl_mem) (void)hipFree(wl_mem);
     if (h_flags) (void)hipHostFree(h_flags);
   }
 };
@@ -110,13 +120,16 @@ static int b_cgs2(Batch &Bt, Lanczos<TB> &Lz, int side_v, const TB *Q, int j, co
   const int64_t L = side_v ? Bt.Ntot : Bt.Mtot, nt = side_v ? Bt.NT : Bt.MT;
   const int64_t ldq = side_v ? Lz.ldv : Lz.ldu;
   const int32_t *tile = side_v ? Bt.tile_v : Bt.tile_u;
+  const int32_t *tl = Bt.wl_tiles[side_v];
+  const unsigned ntl = static_cast<unsigned>(Bt.wl_ntiles[side_v]);
   TB *part = reinterpret_cast<TB *>(Bt.part);
   TB *h1 = reinterpret_cast<TB *>(Bt.h1), *h2 = reinterpret_cast<TB *>(Bt.h2);
   const double sb = sizeof(TB);
   const TB *src = w;
   if (j > 0) {
     ACC_BEFORE(SVDS_KC_CGS_PROJ);
-    hipLaunchKernelGGL((bproj_kernel<TB>), dim3(nt), dim3(BT), 0, P->stream, Q, ldq, j, w, tile, Bt.active, part);
+    hipLaunchKernelGGL((bproj_kernel<TB>), dim3(ntl), dim3(BT), 0, P->stream, Q, ldq, j, w, tile, Bt.active, tl, nt,
+                       part);
     B_LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_CGS_PROJ, sb * L * (j + 1), 2.0 * L * j);
     ACC_BEFORE(SVDS_KC_CGS_REDUCE);
@@ -126,11 +139,11 @@ static int b_cgs2(Batch &Bt, Lanczos<TB> &Lz, int side_v, const TB *Q, int j, co
     ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * nt * j, 0.0);
     ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
     if (j <= 32)
-      hipLaunchKernelGGL((bupd_proj_kernel<TB, 32>), dim3(nt), dim3(BT), 0, P->stream, Q, ldq, j, w, h1, BHJ, tile,
-                         Bt.active, w1, part);
+      hipLaunchKernelGGL((bupd_proj_kernel<TB, 32>), dim3(ntl), dim3(BT), 0, P->stream, Q, ldq, j, w, h1, BHJ, tile,
+                         Bt.active, tl, nt, w1, part);
     else
-      hipLaunchKernelGGL((bupd_proj_kernel<TB, 64>), dim3(nt), dim3(BT), 0, P->stream, Q, ldq, j, w, h1, BHJ, tile,
-                         Bt.active, w1, part);
+      hipLaunchKernelGGL((bupd_proj_kernel<TB, 64>), dim3(ntl), dim3(BT), 0, P->stream, Q, ldq, j, w, h1, BHJ, tile,
+                         Bt.active, tl, nt, w1, part);
     B_LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * (j + 2), 4.0 * L * j);
     ACC_BEFORE(SVDS_KC_CGS_REDUCE);
@@ -141,8 +154,8 @@ static int b_cgs2(Batch &Bt, Lanczos<TB> &Lz, int side_v, const TB *Q, int j, co
     src = w1;
   }
   ACC_BEFORE(SVDS_KC_CGS_UPDNORM);
-  hipLaunchKernelGGL((bupd_norm_kernel<TB>), dim3(nt), dim3(BT), 0, P->stream, Q, ldq, j, src, h2, BHJ, tile,
-                     Bt.active, out, Bt.npart);
+  hipLaunchKernelGGL((bupd_norm_kernel<TB>), dim3(ntl), dim3(BT), 0, P->stream, Q, ldq, j, src, h2, BHJ, tile,
+                     Bt.active, tl, out, Bt.npart);
   B_LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * (j + 2), 2.0 * L * j + 2.0 * L);
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
@@ -217,6 +230,46 @@ static int b_small_svd(Batch &Bt, double tol, bool &all_conv) {
   return P->acc.harvest();
 }
 
+// Work lists of the active problems: the product items of A and A^T (items
+// are grouped by problem) and the U-side / V-side tiles; an empty list gets
+// one inert entry (an empty item; a tile of an inactive problem).  Uploaded
+// synchronously (the host staging vectors are reused).
+static int b_update_worklists(Batch &Bt) {
+  svds_plan *P = Bt.P;
+  for (int t = 0; t < 2; ++t) {
+    SpmvPlan &sp = t ? P->op.bwd : P->op.fwd;
+    Bt.h_wl_items.clear();
+    for (size_t i = 0; i < sp.h_items.size(); ++i)
+      if (Bt.h_active[Bt.item_prob[t][i]]) Bt.h_wl_items.push_back(sp.h_items[i]);
+    if (Bt.h_wl_items.empty()) Bt.h_wl_items.push_back(make_int4(0, 0, 0, 0));
+    HIP_TRY(hipMemcpyAsync(Bt.wl_items[t], Bt.h_wl_items.data(), sizeof(int4) * Bt.h_wl_items.size(),
+                           hipMemcpyHostToDevice, P->stream));
+    sp.items = Bt.wl_items[t];
+    sp.nitems = static_cast<int>(Bt.h_wl_items.size());
+    HIP_TRY(hipStreamSynchronize(P->stream));
+  }
+  for (int side = 0; side < 2; ++side) {
+    Bt.h_wl_tiles.clear();
+    for (int b = 0; b < Bt.nb; ++b) {
+      if (!Bt.h_active[b]) continue;
+      const BProb &q = Bt.hp[b];
+      const int32_t t0 = side ? q.tv0 : q.tu0, nt = side ? q.ntv : q.ntu;
+      for (int32_t t = 0; t < nt; ++t) Bt.h_wl_tiles.push_back(t0 + t);
+    }
+    if (Bt.h_wl_tiles.empty()) Bt.h_wl_tiles.push_back(0);
+    HIP_TRY(hipMemcpyAsync(Bt.wl_tiles[side], Bt.h_wl_tiles.data(), sizeof(int32_t) * Bt.h_wl_tiles.size(),
+                           hipMemcpyHostToDevice, P->stream));
+    Bt.wl_ntiles[side] = static_cast<int>(Bt.h_wl_tiles.size());
+    HIP_TRY(hipStreamSynchronize(P->stream));
+  }
+  // side task of A v writes V-side rows, of A^T u U-side rows
+  P->op.fwd.side_tiles = Bt.wl_tiles[1];
+  P->op.fwd.side_ntiles = Bt.wl_ntiles[1];
+  P->op.bwd.side_tiles = Bt.wl_tiles[0];
+  P->op.bwd.side_ntiles = Bt.wl_ntiles[0];
+  return SVDS_OK;
+}
+
 // Problems whose test passed at the last small SVD and that are still
 // active: their Ritz vectors are now in the leading basis columns (the
 // restart rotation just ran); freeze them.
@@ -232,7 +285,7 @@ static int b_freeze_converged(Batch &Bt) {
                      P->p, P->k);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(P->stream));  // fz is a host temporary
-  return SVDS_OK;
+  return b_update_worklists(Bt);
 }
 
 static int b_activate_all(Batch &Bt) {
@@ -240,7 +293,7 @@ static int b_activate_all(Batch &Bt) {
   Bt.h_active.assign(Bt.nb, 1);
   HIP_TRY(hipMemcpyAsync(Bt.active, Bt.h_active.data(), sizeof(int32_t) * Bt.nb, hipMemcpyHostToDevice, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
-  return SVDS_OK;
+  return b_update_worklists(Bt);
 }
 
 template <typename TB> static int b_restart(Batch &Bt, Lanczos<TB> &Lz) {
@@ -263,8 +316,9 @@ template <typename TB> static int b_restart(Batch &Bt, Lanczos<TB> &Lz) {
   hipLaunchKernelGGL((cast_copy_kernel<double, TB>), dim3(ceil_div(static_cast<int64_t>(Bt.nb) * k, 256)), dim3(256),
                      0, P->stream, static_cast<int64_t>(Bt.nb) * k, Bt.rho, rho_b);
   ACC_BEFORE(SVDS_KC_OTHER);
-  hipLaunchKernelGGL((bupd_norm_kernel<TB>), dim3(Bt.MT), dim3(BT), 0, P->stream, Un, Lz.ldu, k, Lz.wu, rho_b, k,
-                     Bt.tile_u, Bt.active, Lz.w1u, static_cast<double *>(nullptr));
+  hipLaunchKernelGGL((bupd_norm_kernel<TB>), dim3(static_cast<unsigned>(Bt.wl_ntiles[0])), dim3(BT), 0, P->stream, Un,
+                     Lz.ldu, k, Lz.wu, rho_b, k, Bt.tile_u, Bt.active, Bt.wl_tiles[0], Lz.w1u,
+                     static_cast<double *>(nullptr));
   B_LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_OTHER, sizeof(TB) * double(Bt.Mtot) * (k + 2), 2.0 * Bt.Mtot * k);
   return b_cgs2<TB>(Bt, Lz, 0, Un, k, Lz.w1u, Lz.wu, Lz.bu, MODE_LANCZOS, static_cast<int64_t>(k) * ld + k, Bt.xs_u);
@@ -463,6 +517,34 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
   P->op.bwd.x_tile_inst = Bt.tile_u;
   P->op.fwd.active = Bt.active;
   P->op.bwd.active = Bt.active;
+  {
+    // problem of every product item, and the work-list buffers
+    for (int t = 0; t < 2; ++t) {
+      const SpmvPlan &sp = t ? P->op.bwd : P->op.fwd;
+      Bt.item_prob[t].resize(sp.h_items.size());
+      for (size_t i = 0; i < sp.h_items.size(); ++i) {
+        const int4 it = sp.h_items[i];
+        Bt.item_prob[t][i] = it.x >= 0 ? (it.w >> SPMV_CNT_BITS) : sp.h_long[-it.x - 1].inst;
+      }
+    }
+    Arena wa;
+    auto carve = [&](Arena &ar) {
+      Bt.wl_items[0] = ar.take<int4>(std::max<size_t>(1, P->op.fwd.h_items.size()));
+      Bt.wl_items[1] = ar.take<int4>(std::max<size_t>(1, P->op.bwd.h_items.size()));
+      Bt.wl_tiles[0] = ar.take<int32_t>(std::max<int64_t>(1, Bt.MT));
+      Bt.wl_tiles[1] = ar.take<int32_t>(std::max<int64_t>(1, Bt.NT));
+    };
+    carve(wa);
+    if (hipMalloc(&Bt.wl_mem, wa.used) != hipSuccess) {
+      (void)hipGetLastError();
+      Bt.wl_mem = nullptr;
+      return SVDS_ENOMEM;
+    }
+    wa = Arena{};
+    wa.base = Bt.wl_mem;
+    wa.counting = false;
+    carve(wa);
+  }
   HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&Bt.h_flags), sizeof(int) * 4 * count, hipHostMallocDefault));
   P->acc.reset();
   // ---- Alg. 2 for every problem ----

@@ -9,7 +9,9 @@
 // A 256-row tile therefore belongs to exactly one problem (tile maps
 // tile_inst); per-tile partial sums are added per problem in tile order
 // (deterministic).  Problems that have converged are masked out (active[b]
-// = 0): kernels skip their tiles.  Per-problem FP64 scalars are arrays indexed by problem;
+// = 0): kernels skip their tiles, and the per-step kernels take a list of
+// the active problems' tiles (tl, block i works on tile tl[i]) so that their
+// grids shrink as problems freeze.  Per-problem FP64 scalars are arrays indexed by problem;
 // the projected matrices are interleaved: entry (r, c) of problem b's T is
 // T[(r (p+1) + c) B + b], so one pointer per entry serves every problem.
 #pragma once
@@ -41,10 +43,11 @@ __device__ __forceinline__ void bside(const BProb &q, int side_v, int64_t &off, 
 template <typename T>
 __global__ __launch_bounds__(BT) void bproj_kernel(const T *__restrict__ Q, int64_t ldq, int j,
                                                   const T *__restrict__ w, const int32_t *__restrict__ tile_inst,
-                                                  const int32_t *__restrict__ active, T *__restrict__ part) {
+                                                  const int32_t *__restrict__ active, const int32_t *__restrict__ tl,
+                                                  int64_t ntiles, T *__restrict__ part) {
   __shared__ T red[BT / WAVE][BHJ];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-  const int64_t ntiles = gridDim.x, tile = blockIdx.x;
+  const int64_t tile = tl ? tl[blockIdx.x] : blockIdx.x;
   if (!active[tile_inst[tile]]) return;
   const int64_t r = tile * BT + tid;
   const T wr = w[r];
@@ -97,11 +100,12 @@ __global__ __launch_bounds__(BT) void bupd_proj_kernel(const T *__restrict__ Q, 
                                                       const T *__restrict__ w, const T *__restrict__ h, int hs,
                                                       const int32_t *__restrict__ tile_inst,
                                                       const int32_t *__restrict__ active,
+                                                      const int32_t *__restrict__ tl, int64_t ntiles,
                                                       T *__restrict__ w1out, T *__restrict__ part) {
   __shared__ T sh[BHJ];
   __shared__ T red[BT / WAVE][BHJ];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-  const int64_t ntiles = gridDim.x, tile = blockIdx.x;
+  const int64_t tile = tl ? tl[blockIdx.x] : blockIdx.x;
   const int inst = tile_inst[tile];
   if (!active[inst]) return;
   if (tid < j) sh[tid] = h[static_cast<int64_t>(inst) * hs + tid];
@@ -138,11 +142,12 @@ __global__ __launch_bounds__(BT) void bupd_norm_kernel(const T *__restrict__ Q, 
                                                       const T *__restrict__ w1, const T *__restrict__ h, int hs,
                                                       const int32_t *__restrict__ tile_inst,
                                                       const int32_t *__restrict__ active,
+                                                      const int32_t *__restrict__ tl,
                                                       T *__restrict__ out, double *__restrict__ npart) {
   __shared__ T sh[BHJ];
   __shared__ double shd[BT / WAVE];
   const int tid = threadIdx.x;
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = tl ? tl[blockIdx.x] : blockIdx.x;
   const int inst = tile_inst[tile];
   if (!active[inst]) return;
   if (tid < j) sh[tid] = h[static_cast<int64_t>(inst) * hs + tid];

@@ -31,7 +31,8 @@
 // problem's index (in item.w of a MULTI item, LongRow::inst of a long row) and
 // the scale factors xs, coef are per-problem arrays; the side task finds the
 // problem of entry i from x_tile_inst[i / 256] (problems are padded to
-// multiples of 256 rows).  A single problem has index 0 everywhere.
+// multiples of 256 rows), restricted to the tiles in side_tiles when given.
+// A single problem has index 0 everywhere.
 #pragma once
 #include "common.hpp"
 
@@ -61,7 +62,8 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     const double *__restrict__ xs_ptr,
     const double *__restrict__ coef_ptr, const TB *__restrict__ yprev, TB *__restrict__ y,
     TB *__restrict__ partials, TB *__restrict__ side_dst, int64_t side_len,
-    const int32_t *__restrict__ x_tile_inst, const int32_t *__restrict__ active) {
+    const int32_t *__restrict__ x_tile_inst, const int32_t *__restrict__ active,
+    const int32_t *__restrict__ side_tiles, int side_ntiles) {
   __shared__ TB prod[SPMV_NNZ_BLK];
   __shared__ TB red[SPMV_THREADS / WAVE];
   __shared__ int rps[SPMV_ROWS_BLK + 1];
@@ -70,7 +72,18 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
   const int lane = tid & (WAVE - 1);
   const int wv = tid / WAVE;
 
-  if (side_dst) {
+  if (side_dst && side_tiles) {
+    // only the listed 256-row tiles (the active problems' rows)
+    const int64_t len = static_cast<int64_t>(side_ntiles) << SPMV_TILE_SHIFT;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * SPMV_THREADS + tid; i < len;
+         i += static_cast<int64_t>(gridDim.x) * SPMV_THREADS) {
+      const int32_t t = side_tiles[i >> SPMV_TILE_SHIFT];
+      const int64_t r = (static_cast<int64_t>(t) << SPMV_TILE_SHIFT) + (i & ((1 << SPMV_TILE_SHIFT) - 1));
+      const int inst = x_tile_inst[t];
+      if (active && !active[inst]) continue;
+      side_dst[r] = x[r] * (xs_ptr ? static_cast<TB>(xs_ptr[inst]) : TB(1));
+    }
+  } else if (side_dst) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * SPMV_THREADS + tid; i < side_len;
          i += static_cast<int64_t>(gridDim.x) * SPMV_THREADS) {
       const int inst = x_tile_inst ? x_tile_inst[i >> SPMV_TILE_SHIFT] : 0;

@@ -43,6 +43,8 @@ struct SpmvPlan {
   uint16_t *spos = nullptr;
   const int32_t *x_tile_inst = nullptr;  // problem of each 256-entry tile of x (batched), or null
   const int32_t *active = nullptr;       // per-problem work mask (batched), or null
+  const int32_t *side_tiles = nullptr;   // tiles of x the side task covers (batched), or null: all
+  int side_ntiles = 0;
 };
 
 // Work items of a CSR product.  With seg_end (nseg consecutive row ranges

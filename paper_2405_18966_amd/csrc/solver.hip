@@ -284,11 +284,13 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     if (op.vt == SVDS_F64)
       hipLaunchKernelGGL((spmv_csr_kernel<double, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
                          P->stream, sp.items, rp, cs, static_cast<const double *>(vs), sp.spos, x, xs, ck,
-                         ypk, yk, parts, side_dst, side_len, sp.x_tile_inst, sp.active);
+                         ypk, yk, parts, side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles,
+                         sp.side_ntiles);
     else
       hipLaunchKernelGGL((spmv_csr_kernel<float, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
                          P->stream, sp.items, rp, cs, static_cast<const float *>(vs), sp.spos, x, xs, ck,
-                         ypk, yk, parts, side_dst, side_len, sp.x_tile_inst, sp.active);
+                         ypk, yk, parts, side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles,
+                         sp.side_ntiles);
     if (sp.nlong > 0)
       hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(sp.nlong), dim3(WAVE), 0,
                          P->stream, sp.longrows, sp.nlong, parts, xs, ck, ypk, yk, sp.active);
@@ -802,7 +804,6 @@ static int build_panels(svds_plan *P) {
     op.pci = ar.take<int32_t>(nnz);
     op.pval = ar.take<char>(nnz * static_cast<size_t>(vsize(op.vt)));
     op.ypart = ar.take<double>(rows);
-    op.bwdp.spos = ar.take<uint16_t>(nnz);
   };
   carve(a);
   if (hipMalloc(&op.pbuf, a.used) != hipSuccess) {
@@ -860,10 +861,9 @@ static int build_panels(svds_plan *P) {
   b.used = 0;
   b.counting = false;
   carve_items(b);
-  if ((rc = upload_spmv(P, sp))) return rc;
-  sp.scol = op.pci;  // sorted in place: only the product reads the stacked copy
-  sp.sval = op.pval;
-  return sort_spmv(P, sp, op.pci, op.pval);
+  // no column sort here: a panel's gathers come from an L2-sized slice and
+  // its items rarely share cache lines (sorting cost 3% on such matrices)
+  return upload_spmv(P, sp);
 }
 
 namespace {
