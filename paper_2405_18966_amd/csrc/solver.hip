@@ -338,6 +338,35 @@ static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int
   return SVDS_OK;
 }
 
+// out = w - Q h, with squared-norm partials in npart when non-null; returns
+// the number of partials.  Short vectors take the tile-per-block kernel.
+template <typename TB>
+static int launch_upd_norm(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, int j, const TB *w, const TB *h,
+                           TB *out, double *npart) {
+  constexpr int NV = 16 / sizeof(TB);
+  const bool vec = cgs_rows_per_lane<TB>(Q, ldq, w, out, nullptr) == NV;
+  const int nr = vec ? NV : 1;
+  if (j > 0 && cgs_tile_upd_ok(L, j, nr)) {
+    const int nt = static_cast<int>(ceil_div(L, static_cast<int64_t>(WAVE) * nr));
+    const int nw = static_cast<int>(ceil_div(j, CGS_TILE_CPW));
+    if (vec)
+      hipLaunchKernelGGL((cgs_tile_upd_kernel<TB, NV>), dim3(nt), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j, w, h,
+                         out, npart);
+    else
+      hipLaunchKernelGGL((cgs_tile_upd_kernel<TB, 1>), dim3(nt), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j, w, h,
+                         out, npart);
+    return nt;
+  }
+  const int nn = cgs_updnorm_blocks(L);
+  if (vec)
+    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, NV>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j, w, h,
+                       out, npart);
+  else
+    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, 1>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j, w, h,
+                       out, npart);
+  return nn;
+}
+
 template <typename TB>
 static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int64_t ldq, int64_t L, int j,
                        const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs) {
@@ -353,7 +382,7 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     // pass 2: w1 = w - Q h1, h2 = Q^T w1
     const int cpw = cgs_fused_cpw(j);
     if (cpw) {
-      const int nb = cgs_updproj_blocks(L);
+      const int nb = cgs_updproj_blocks(L, j);
       const int nw = static_cast<int>(ceil_div(j, cpw));
       ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
       // 8 columns per wave with prefetch: one row per lane (two rows per lane
@@ -377,12 +406,7 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     } else {
       // wide basis: separate update and projection passes
       ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
-      if (vec)
-        hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, NV>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
-                           P->stream, Q, ldq, L, j, w, h1, w1, static_cast<double *>(nullptr));
-      else
-        hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, 1>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
-                           P->stream, Q, ldq, L, j, w, h1, w1, static_cast<double *>(nullptr));
+      launch_upd_norm<TB>(P, Q, ldq, L, j, w, h1, w1, nullptr);
       LAUNCH_CHECK();
       ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 2.0 * L * j);
       if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w1, h2, SVDS_KC_CGS_UPDPROJ))) return rc;
@@ -390,14 +414,8 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     src = w1;
   }
   // pass 3: out = w1 - Q h2 and its norm
-  const int nn = cgs_updnorm_blocks(L);
   ACC_BEFORE(SVDS_KC_CGS_UPDNORM);
-  if (vec)
-    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, NV>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
-                       src, h2, out, s.npart);
-  else
-    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, 1>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
-                       src, h2, out, s.npart);
+  const int nn = launch_upd_norm<TB>(P, Q, ldq, L, j, src, h2, out, s.npart);
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * j + 2 * sb * L, 2.0 * L * j + 2.0 * L);
   FinishArgs fa{t_entry, xs, s.sigma_est, s.bd, P->opts.seed};
@@ -421,13 +439,7 @@ static int gemv_update(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, int j,
                        const TB *h, TB *out) {
   const double sb = sizeof(TB);
   ACC_BEFORE(SVDS_KC_OTHER);
-  constexpr int NV = 16 / sizeof(TB);
-  if (cgs_rows_per_lane<TB>(Q, ldq, w, out, nullptr) == NV)
-    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, NV>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
-                       P->stream, Q, ldq, L, j, w, h, out, static_cast<double *>(nullptr));
-  else
-    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, 1>), dim3(cgs_updnorm_blocks(L)), dim3(CGS_THREADS), 0,
-                       P->stream, Q, ldq, L, j, w, h, out, static_cast<double *>(nullptr));
+  launch_upd_norm<TB>(P, Q, ldq, L, j, w, h, out, nullptr);
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_OTHER, sb * L * j + 2 * sb * L, 2.0 * L * j);
   return SVDS_OK;
