@@ -448,7 +448,19 @@ inline void cgs_proj_shape(int64_t L, int j, int &nslab, int &ngrp_c) {
   const int64_t tiles = ceil_div(L, WAVE);
   const int64_t base = std::max<int64_t>(1, std::min<int64_t>(512, tiles / 32));
   const int64_t wide = std::min<int64_t>({ceil_div(2048, ngrp_c), ceil_div(L, 256), CGS_MAX_SLABS});
-  nslab = static_cast<int>(std::max(base, wide));
+  int64_t ns = std::max(base, wide);
+  // a grid of more than one round of the ~2048 blocks the chip holds at once
+  // is cut to a whole number (>= 2) of rounds, so that no partial last round
+  // leaves CUs idle (measured: 1,000,000 x 150 basis 214 -> 202 us,
+  // 500,000 x 150 117 -> 105 us)
+  constexpr int64_t RESIDENT = 2048;
+  const double rounds = static_cast<double>(ns * ngrp_c) / RESIDENT;
+  if (rounds > 1.0) {
+    const int64_t k = std::max<int64_t>(2, static_cast<int64_t>(rounds + 0.3));
+    const int64_t ns2 = ceil_div(RESIDENT * k, ngrp_c);
+    if (ns2 <= CGS_MAX_SLABS && ns2 <= ceil_div(L, 256)) ns = ns2;
+  }
+  nslab = static_cast<int>(ns);
 }
 inline int cgs_updproj_blocks(int64_t L, int j) {
   // a quarter of the 64-row tiles, at most 512 blocks; at least ~160 blocks
