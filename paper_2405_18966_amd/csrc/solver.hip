@@ -727,7 +727,10 @@ static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int
   const int64_t nsum = ceil_div(nh, SCAN_TILE);
   int32_t *buf = nullptr;
   const size_t words = 5 * static_cast<size_t>(nnz) + 2 * static_cast<size_t>(nh) + nsum + 64;
-  HIP_TRY(hipMalloc(&buf, words * sizeof(int32_t)));
+  if (hipMalloc(&buf, words * sizeof(int32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    return SVDS_ENOMEM;
+  }
   int32_t *rowof = buf, *k0 = buf + nnz, *v0 = buf + 2 * nnz, *k1 = buf + 3 * nnz, *v1 = buf + 4 * nnz;
   int32_t *hist = buf + 5 * nnz, *offs = hist + nh, *sums = offs + nh;
   int rc = SVDS_OK;
@@ -951,7 +954,15 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   op.bwd.partials = bp;
   if ((rc = upload_spmv(P, op.fwd)) || (rc = upload_spmv(P, op.bwd))) return rc;
   if ((rc = sort_spmv(P, op.fwd, op.ci, op.val)) || (rc = sort_spmv(P, op.bwd, op.tci, op.tval))) return rc;
-  if (op.npanel > 1 && (rc = build_panels(P))) return rc;
+  if (op.npanel > 1 && (rc = build_panels(P))) {
+    // no room for the panel copy: the plain transpose product (row order) serves
+    if (rc != SVDS_ENOMEM) return rc;
+    if (op.pbuf) (void)hipFree(op.pbuf);
+    if (op.pbuf_items) (void)hipFree(op.pbuf_items);
+    op.pbuf = op.pbuf_items = nullptr;
+    op.pbuf_bytes = 0;
+    op.npanel = 1;
+  }
   HIP_TRY(hipStreamSynchronize(P->stream));
   *plan = guard.release();
   return SVDS_OK;
