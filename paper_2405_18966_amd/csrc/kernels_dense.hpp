@@ -198,6 +198,26 @@ static __global__ __launch_bounds__(256) void col_norms_kernel(int64_t L, const 
   if (threadIdx.x == 0) out[blockIdx.x] = sqrt(s);
 }
 
+// out[j] = |C(j, :) - S[j] V(:, j)^T|_2 for C = U^T A (k x n, ld k) and V
+// (n x k, ld n): the norms of A^T u_j - s_j v_j.  One block per j, fixed-order
+// block sum.
+static __global__ __launch_bounds__(256) void row_resid_norms_kernel(int64_t n, int k, const double *__restrict__ C,
+                                                                     const double *__restrict__ V,
+                                                                     const double *__restrict__ S,
+                                                                     double *__restrict__ out) {
+  __shared__ double sh[256 / WAVE];
+  const int j = blockIdx.x;
+  const double sj = S[j];
+  const double *v = V + static_cast<int64_t>(j) * n;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double d = C[i * k + j] - sj * v[i];
+    s += d * d;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[j] = sqrt(s);
+}
+
 // scratch of the A x kernel: partials (slabs x m of TB <= 8 bytes)
 inline int64_t dense_partial_doubles(int64_t m, int64_t n) { return ceil_div(n, DN_SLAB) * m; }
 
