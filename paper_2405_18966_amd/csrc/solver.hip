@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <thread>
 
 #include <rocblas/rocblas.h>
 
@@ -835,18 +836,42 @@ static int build_panels(svds_plan *P) {
   if (rc) return rc;
   std::vector<int32_t> hrp(rows + 1);
   HIP_TRY(hipMemcpy(hrp.data(), op.prp, sizeof(int32_t) * (rows + 1), hipMemcpyDeviceToHost));
-  // items per panel (never crossing a panel), untagged: one problem
-  std::vector<int64_t> ends(np);
-  for (int g = 0; g < np; ++g) ends[g] = n * (g + 1);
+  // items per panel, built on one host thread per panel (rows relative to the
+  // panel, nonzero offsets absolute), then renumbered: rows + g n, long rows
+  // and pieces after those of the earlier panels
   SpmvPlan &sp = op.bwdp;
-  build_spmv_items(hrp.data(), rows, sp, ends.data(), np);
-  for (auto &L : sp.h_long) L.inst = 0;
-  std::vector<std::vector<int4>> per(np);
-  for (int4 it : sp.h_items) {
-    const int64_t r = it.x >= 0 ? it.x : sp.h_long[-it.x - 1].row;
-    if (it.x >= 0) it.w &= (1 << SPMV_CNT_BITS) - 1;
-    per[r / n].push_back(it);
+  std::vector<SpmvPlan> pp(np);
+  {
+    std::vector<std::thread> th;
+    for (int g = 0; g < np; ++g)
+      th.emplace_back([&, g] { build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g]); });
+    for (auto &t : th) t.join();
   }
+  std::vector<std::vector<int4>> per(np);
+  sp.h_long.clear();
+  int npieces = 0;
+  for (int g = 0; g < np; ++g) {
+    const int32_t r0 = static_cast<int32_t>(static_cast<int64_t>(g) * n);
+    const int lbase = static_cast<int>(sp.h_long.size());
+    for (LongRow L : pp[g].h_long) {
+      L.row += r0;
+      L.first_piece += npieces;
+      sp.h_long.push_back(L);
+    }
+    for (int4 it : pp[g].h_items) {
+      if (it.x >= 0) {
+        it.x += r0;
+        it.y += r0;
+      } else {
+        it.x = -((-it.x - 1) + lbase) - 1;
+        it.y += npieces;
+      }
+      per[g].push_back(it);
+    }
+    npieces += pp[g].npieces;
+  }
+  sp.nlong = static_cast<int>(sp.h_long.size());
+  sp.npieces = npieces;
   // slot b -> panel (b mod 8) mod np; a panel that has run out gets empty items
   std::vector<size_t> next(np, 0);
   sp.h_items.clear();

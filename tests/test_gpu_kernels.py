@@ -174,6 +174,24 @@ def test_column_sorted_items_bit_identical(S, maker):
         assert torch.equal(z_plan, z_rows)
 
 
+def test_transposed_product_column_panels_fp32_values(S):
+    """Column panels over a matrix stored with FP32 values (widened exactly),
+    FP64 and FP32 bases."""
+    import torch
+    A = inputs.round_values_f32(inputs.sparse_zipf(600_003, 30_000, 10, 1.1, seed=27))
+    Ad, keep = S.csr_to_device(A)
+    At = sp.csr_matrix((A.val.astype(np.float64), A.col_idx, A.row_ptr), shape=(A.m, A.n)).T.tocsr()
+    lens = np.diff(At.indptr).astype(np.float64)
+    x = np.random.default_rng(28).standard_normal(A.m)
+    for tb, u in ((torch.float64, 2.0**-53), (torch.float32, 2.0**-24)):
+        xr = x if tb == torch.float64 else x.astype(np.float32).astype(np.float64)
+        y, npan = S.svds_op_csr_matvec(Ad, True, _t(x, tb))
+        assert npan == 4
+        ref = At @ xr
+        bound = (lens + 4 + 3) * u * (np.abs(At) @ np.abs(xr)) + 1e-300
+        assert np.all(np.abs(y.cpu().numpy().astype(np.float64) - ref) <= bound)
+
+
 def test_transposed_product_no_panels_for_short_or_sparse(S):
     """Short x, or too few entries per row of A^T: the plain product."""
     for A in (inputs.sparse_zipf(200_000, 20_000, 10, 1.1, seed=19),
