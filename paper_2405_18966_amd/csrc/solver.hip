@@ -843,9 +843,17 @@ static int build_panels(svds_plan *P) {
   std::vector<SpmvPlan> pp(np);
   {
     std::vector<std::thread> th;
-    for (int g = 0; g < np; ++g)
-      th.emplace_back([&, g] { build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g]); });
+    std::vector<char> started(np, 0);
+    for (int g = 0; g < np; ++g) {
+      try {
+        th.emplace_back([&, g] { build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g]); });
+        started[g] = 1;
+      } catch (...) {
+      }
+    }
     for (auto &t : th) t.join();
+    for (int g = 0; g < np; ++g)  // any panel whose thread could not start
+      if (!started[g]) build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g]);
   }
   std::vector<std::vector<int4>> per(np);
   sp.h_long.clear();
@@ -956,13 +964,32 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   if (hrp[0] != 0 || hrp[A->m] != A->nnz) return SVDS_EINVAL;
   for (int64_t i = 0; i < A->m; ++i)
     if (hrp[i + 1] < hrp[i]) return SVDS_EINVAL;
-  build_spmv_items(hrp.data(), A->m, op.fwd, seg_rows, nseg);
   op.npanel = seg_rows ? 1 : choose_panels(op.m, op.n, op.nnz);
-  // A^T items need the column counts: computed after the device transpose,
-  // so size the arena with a bound first (one item per column is the max).
-  op.bwd.nitems = static_cast<int>(std::max<int64_t>(1, A->n + ceil_div(A->nnz, SPMV_PIECE) + 1));
-  op.bwd.nlong = static_cast<int>(std::max<int64_t>(1, ceil_div(A->nnz, SPMV_NNZ_BLK) + 1));
-  op.bwd.npieces = static_cast<int>(std::max<int64_t>(1, ceil_div(A->nnz, SPMV_PIECE) + op.bwd.nlong));
+  // The items of A are built on a helper thread while the arena is allocated
+  // and the transpose is built on the device; the items of A^T need the
+  // column counts from that transpose.  The arena is therefore sized with
+  // bounds for both (at most one item per row plus the pieces).
+  SpmvPlan fwd_items;
+  std::thread tf;
+  try {
+    tf = std::thread([&] { build_spmv_items(hrp.data(), A->m, fwd_items, seg_rows, nseg); });
+  } catch (...) {
+    build_spmv_items(hrp.data(), A->m, fwd_items, seg_rows, nseg);
+  }
+  struct Join {
+    std::thread &t;
+    ~Join() {
+      if (t.joinable()) t.join();
+    }
+  } join_fwd{tf};
+  auto set_caps = [](SpmvPlan &sp, int64_t rows, int64_t nnz) {
+    sp.nitems = static_cast<int>(std::max<int64_t>(1, rows + ceil_div(nnz, SPMV_PIECE) + 1));
+    sp.nlong = static_cast<int>(std::max<int64_t>(1, ceil_div(nnz, SPMV_NNZ_BLK) + 1));
+    sp.npieces = static_cast<int>(std::max<int64_t>(1, ceil_div(nnz, SPMV_PIECE) + sp.nlong));
+  };
+  set_caps(op.fwd, A->m, A->nnz);
+  set_caps(op.bwd, A->n, A->nnz);
+  const int fwd_items_cap = op.fwd.nitems, fwd_long_cap = op.fwd.nlong, fwd_pieces_cap = op.fwd.npieces;
   const int bwd_items_cap = op.bwd.nitems, bwd_long_cap = op.bwd.nlong, bwd_pieces_cap = op.bwd.npieces;
   if ((rc = alloc_arena(P))) return rc;
   if ((rc = build_transpose(P, 1, op.m, op.trp, op.tci, op.tval))) return rc;
@@ -977,6 +1004,14 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   op.bwd.items = bi;
   op.bwd.longrows = bl;
   op.bwd.partials = bp;
+  if (tf.joinable()) tf.join();
+  if (fwd_items.nitems > fwd_items_cap || fwd_items.nlong > fwd_long_cap || fwd_items.npieces > fwd_pieces_cap)
+    return SVDS_EDEVICE;
+  op.fwd.h_items = std::move(fwd_items.h_items);
+  op.fwd.h_long = std::move(fwd_items.h_long);
+  op.fwd.nitems = fwd_items.nitems;
+  op.fwd.nlong = fwd_items.nlong;
+  op.fwd.npieces = fwd_items.npieces;
   if ((rc = upload_spmv(P, op.fwd)) || (rc = upload_spmv(P, op.bwd))) return rc;
   if ((rc = sort_spmv(P, op.fwd, op.ci, op.val)) || (rc = sort_spmv(P, op.bwd, op.tci, op.tval))) return rc;
   if (op.npanel > 1 && (rc = build_panels(P))) {
