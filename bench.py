@@ -263,7 +263,8 @@ def main():
                 "avg_launch_us": round(kc_ms[dom] * 1e3 / max(kc_n[dom], 1), 2),
                 "alg_bytes_per_launch": round(kc_b[dom] / max(kc_n[dom], 1)),
                 "spmv_cgs2_gbs": round(hot_gbs, 1),
-                "timing_sample": "1 launch in 4 per class, rotating offset",
+                "timing_sample": "1 launch in 16 per class, rotating offset; events carried by the "
+                                 "dispatches of the products and CGS2 passes",
                 "per_class": {c: {"est_ms": round(kc_est[c] / args.steps, 3),
                                   "gbs": round(kc_b[c] / (kc_ms[c] * 1e-3) / 1e9, 1) if kc_ms[c] else None,
                                   "launches": kc_all[c] // args.steps} for c in S.KERNEL_CLASSES}}

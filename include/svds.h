@@ -102,9 +102,12 @@ typedef struct {
 } svds_opts;
 
 /* With SVDS_FLAG_TIMING, one launch in each group of SVDS_TIMING_SAMPLE
- * consecutive launches of a kernel class is bracketed by HIP events (launch
- * i is sampled when i mod 4 == (i / 4) mod 4). */
-enum { SVDS_TIMING_SAMPLE = 4 };
+ * consecutive launches of a kernel class is timed with HIP events on the
+ * solve's stream (launch i is sampled when i mod 16 == (i / 16) mod 16).
+ * The products and the three CGS2 passes carry the events on their own
+ * dispatches (hipExtLaunchKernel), so the sampled time is the kernels' own;
+ * the other classes are bracketed by event markers. */
+enum { SVDS_TIMING_SAMPLE = 16 };
 
 /* Kernel classes reported by SVDS_FLAG_TIMING. */
 enum {
@@ -133,7 +136,7 @@ typedef struct {
   double ms_total;      /* wall time of the execute call                    */
   double bytes_alg;     /* algorithmic HBM bytes of SpMV + CGS kernels      */
   /* Per kernel class.  With SVDS_FLAG_TIMING every SVDS_TIMING_SAMPLE-th
-   * launch of a class is bracketed by HIP events on the solve's stream:
+   * launch of a class is timed with HIP events on the solve's stream:
    * kc_ms is the device time of those sampled launches, kc_sampled_* their
    * count and algorithmic bytes; kc_bytes/kc_flops/kc_launches cover all. */
   double kc_ms[SVDS_KC_COUNT];

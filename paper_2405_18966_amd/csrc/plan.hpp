@@ -69,16 +69,22 @@ struct Accounting {
   int64_t sampled[SVDS_KC_COUNT] = {};
   double sampled_bytes[SVDS_KC_COUNT] = {};
   bool sampling = false;  // the launch between before() and after() is timed
+  // Attached timing: the sampled bracket's first launch carries att_start and
+  // its last launch att_stop as dispatch events (hipExtLaunchKernel), so the
+  // time is the kernels' own, without marker packets between launches.
+  bool attach = false;
+  hipEvent_t att_start = nullptr, att_stop = nullptr;
+  bool att_started = false, att_stopped = false;
 
   void reset() {
     for (int i = 0; i < SVDS_KC_COUNT; ++i)
       ms[i] = bytes[i] = flops[i] = sampled_bytes[i] = 0, launches[i] = sampled[i] = 0;
     next = 0;
     cls.clear();
-    sampling = false;
+    sampling = attach = false;
   }
   int harvest();
-  int before(int kc);
+  int before(int kc, bool attached = false);
   int after(int kc, double b, double f);
   void destroy() {
     for (auto e : pool) (void)hipEventDestroy(e);

@@ -10,7 +10,10 @@
 #include <cstring>
 #include <mutex>
 #include <thread>
+#include <tuple>
+#include <utility>
 
+#include <hip/hip_ext.h>
 #include <rocblas/rocblas.h>
 
 #include "plan.hpp"
@@ -97,12 +100,13 @@ int Accounting::harvest() {
   return SVDS_OK;
 }
 
-int Accounting::before(int kc) {
+int Accounting::before(int kc, bool attached) {
   // one launch in each group of SVDS_TIMING_SAMPLE, at an offset that
   // rotates from group to group, so launches that alternate between two
   // shapes (U side / V side) are both sampled
   const int64_t i = launches[kc];
   sampling = timing && (i % SVDS_TIMING_SAMPLE == (i / SVDS_TIMING_SAMPLE) % SVDS_TIMING_SAMPLE);
+  attach = false;
   if (!sampling) return SVDS_OK;
   if (next + 2 > pool.size()) {
     if (pool.size() < 16384) {
@@ -117,6 +121,14 @@ int Accounting::before(int kc) {
     }
   }
   cls.push_back(kc);
+  if (attached) {
+    attach = true;
+    att_start = pool[next];
+    att_stop = pool[next + 1];
+    att_started = att_stopped = false;
+    next += 2;
+    return SVDS_OK;
+  }
   HIP_TRY(hipEventRecord(pool[next++], stream));
   return SVDS_OK;
 }
@@ -127,15 +139,60 @@ int Accounting::after(int kc, double b, double f) {
   launches[kc] += 1;
   if (!sampling) return SVDS_OK;
   sampling = false;
+  if (attach) {
+    attach = false;
+    if (!att_started) {  // no launch carried the start event: drop the sample
+      next -= 2;
+      cls.pop_back();
+      return SVDS_OK;
+    }
+    if (!att_stopped) HIP_TRY(hipEventRecord(att_stop, stream));
+    sampled[kc] += 1;
+    sampled_bytes[kc] += b;
+    return SVDS_OK;
+  }
   sampled[kc] += 1;
   sampled_bytes[kc] += b;
   HIP_TRY(hipEventRecord(pool[next++], stream));
   return SVDS_OK;
 }
 
+// Kernel launch inside an accounting bracket: with attached timing, the
+// bracket's first launch carries the start event and its last launch the stop
+// event (hipExtLaunchKernel, arguments converted to the kernel's parameter
+// types); otherwise an ordinary launch.
+template <typename... Prm, typename... Arg, size_t... I>
+static hipError_t ext_launch(void (*k)(Prm...), dim3 g, dim3 b, uint32_t shm, hipStream_t st, hipEvent_t e0,
+                             hipEvent_t e1, std::index_sequence<I...>, Arg... a) {
+  std::tuple<Prm...> t(static_cast<Prm>(a)...);
+  void *argv[] = {static_cast<void *>(&std::get<I>(t))...};
+  return hipExtLaunchKernel(reinterpret_cast<const void *>(k), g, b, argv, shm, st, e0, e1, 0);
+}
+
+template <typename... Prm, typename... Arg>
+static void klaunch(Accounting &acc, bool first, bool last, void (*k)(Prm...), dim3 g, dim3 b, uint32_t shm,
+                    hipStream_t st, Arg... a) {
+  static_assert(sizeof...(Prm) == sizeof...(Arg), "kernel arity");
+  hipEvent_t e0 = (acc.attach && first) ? acc.att_start : nullptr;
+  hipEvent_t e1 = (acc.attach && last) ? acc.att_stop : nullptr;
+  if (!e0 && !e1) {
+    hipLaunchKernelGGL(k, g, b, shm, st, static_cast<Prm>(a)...);
+    return;
+  }
+  if (ext_launch(k, g, b, shm, st, e0, e1, std::index_sequence_for<Prm...>{}, a...) == hipSuccess) {
+    if (e0) acc.att_started = true;
+    if (e1) acc.att_stopped = true;
+  }
+}
+
 #define ACC_BEFORE(kc)                      \
   do {                                      \
     int rc_ = P->acc.before(kc);            \
+    if (rc_) return rc_;                    \
+  } while (0)
+#define ACC_BEFORE_ATT(kc)                  \
+  do {                                      \
+    int rc_ = P->acc.before(kc, true);      \
     if (rc_) return rc_;                    \
   } while (0)
 #define ACC_AFTER(kc, b, f)                 \
@@ -233,23 +290,23 @@ static void dense_launch(svds_plan *P, bool trans, const TB *x, const double *xs
   if (trans) {
     const dim3 g(static_cast<unsigned>(ceil_div(op.n, DN_TCOLS)));
     if (vec)
-      hipLaunchKernelGGL((gemv_t_kernel<TV, TB, true>), g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A, op.lda,
-                         x, xs, coef, yprev, y, side_dst, side_len);
+      klaunch(P->acc, true, true, gemv_t_kernel<TV, TB, true>, g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A,
+              op.lda, x, xs, coef, yprev, y, side_dst, side_len);
     else
-      hipLaunchKernelGGL((gemv_t_kernel<TV, TB, false>), g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A,
-                         op.lda, x, xs, coef, yprev, y, side_dst, side_len);
+      klaunch(P->acc, true, true, gemv_t_kernel<TV, TB, false>, g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A,
+              op.lda, x, xs, coef, yprev, y, side_dst, side_len);
   } else {
     const int nslab = static_cast<int>(ceil_div(op.n, DN_SLAB));
     TB *part = reinterpret_cast<TB *>(op.dpart);
     const dim3 g(static_cast<unsigned>(ceil_div(op.m, DN_ROWS)), nslab);
     if (vec)
-      hipLaunchKernelGGL((gemv_n_kernel<TV, TB, true>), g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A,
-                         op.lda, x, xs, part, side_dst, side_len);
+      klaunch(P->acc, true, false, gemv_n_kernel<TV, TB, true>, g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A,
+              op.lda, x, xs, part, side_dst, side_len);
     else
-      hipLaunchKernelGGL((gemv_n_kernel<TV, TB, false>), g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A,
-                         op.lda, x, xs, part, side_dst, side_len);
-    hipLaunchKernelGGL((gemv_n_fixup_kernel<TB>), dim3(ceil_div(op.m, 256)), dim3(256), 0, P->stream,
-                       op.m, nslab, part, xs, coef, yprev, y);
+      klaunch(P->acc, true, false, gemv_n_kernel<TV, TB, false>, g, dim3(DN_THREADS), 0, P->stream, op.m, op.n, A,
+              op.lda, x, xs, part, side_dst, side_len);
+    klaunch(P->acc, false, true, gemv_n_fixup_kernel<TB>, dim3(ceil_div(op.m, 256)), dim3(256), 0, P->stream, op.m,
+            nslab, part, xs, coef, yprev, y);
   }
 }
 
@@ -260,7 +317,7 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
   const int64_t rows = trans ? op.n : op.m, cols = trans ? op.m : op.n;
   const int kc = kc_over >= 0 ? kc_over : (trans ? SVDS_KC_SPMVT : SVDS_KC_SPMV);
   const double sb = sizeof(TB);
-  ACC_BEFORE(kc);
+  ACC_BEFORE_ATT(kc);
   double bytes;
   if (op.dense) {
     if (op.vt == SVDS_F64) dense_launch<double, TB>(P, trans, x, xs, coef, yprev, y, side_dst, side_len);
@@ -282,22 +339,21 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     const double *ck = panels ? nullptr : coef;
     const TB *ypk = panels ? nullptr : yprev;
     TB *parts = reinterpret_cast<TB *>(sp.partials);
+    const bool fix = sp.nlong > 0;
     if (op.vt == SVDS_F64)
-      hipLaunchKernelGGL((spmv_csr_kernel<double, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-                         P->stream, sp.items, rp, cs, static_cast<const double *>(vs), sp.spos, x, xs, ck,
-                         ypk, yk, parts, side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles,
-                         sp.side_ntiles);
+      klaunch(P->acc, true, !fix && !panels, spmv_csr_kernel<double, TB>, dim3(sp.nitems), dim3(SPMV_THREADS), 0,
+              P->stream, sp.items, rp, cs, static_cast<const double *>(vs), sp.spos, x, xs, ck, ypk, yk, parts,
+              side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles);
     else
-      hipLaunchKernelGGL((spmv_csr_kernel<float, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-                         P->stream, sp.items, rp, cs, static_cast<const float *>(vs), sp.spos, x, xs, ck,
-                         ypk, yk, parts, side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles,
-                         sp.side_ntiles);
-    if (sp.nlong > 0)
-      hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(sp.nlong), dim3(WAVE), 0,
-                         P->stream, sp.longrows, sp.nlong, parts, xs, ck, ypk, yk, sp.active);
+      klaunch(P->acc, true, !fix && !panels, spmv_csr_kernel<float, TB>, dim3(sp.nitems), dim3(SPMV_THREADS), 0,
+              P->stream, sp.items, rp, cs, static_cast<const float *>(vs), sp.spos, x, xs, ck, ypk, yk, parts,
+              side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles);
+    if (fix)
+      klaunch(P->acc, false, !panels, spmv_longrow_fixup_kernel<TB>, dim3(sp.nlong), dim3(WAVE), 0, P->stream,
+              sp.longrows, sp.nlong, parts, xs, ck, ypk, yk, sp.active);
     if (panels)
-      hipLaunchKernelGGL((spmv_panel_sum_kernel<TB>), dim3(ceil_div(op.n, 256)), dim3(256), 0, P->stream,
-                         op.n, op.npanel, yk, coef, yprev, y);
+      klaunch(P->acc, false, true, spmv_panel_sum_kernel<TB>, dim3(ceil_div(op.n, 256)), dim3(256), 0, P->stream,
+              op.n, op.npanel, yk, coef, yprev, y);
     LAUNCH_CHECK();
     bytes = 4.0 * (rows + 1) + (4.0 + vsize(op.vt)) * op.nnz + sb * cols +
             (yprev ? 2.0 : 1.0) * sb * rows;
@@ -322,13 +378,13 @@ static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int
   int nslab, ngc;
   cgs_proj_shape(L, j, nslab, ngc);
   constexpr int NV = 16 / sizeof(TB);
-  ACC_BEFORE(kc);
+  ACC_BEFORE_ATT(kc);
   if (cgs_rows_per_lane<TB>(Q, ldq, w, nullptr, nullptr) == NV)
-    hipLaunchKernelGGL((cgs_proj_kernel<TB, NV>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
-                       L, j, w, part);
+    klaunch(P->acc, true, true, cgs_proj_kernel<TB, NV>, dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
+            L, j, w, part);
   else
-    hipLaunchKernelGGL((cgs_proj_kernel<TB, 1>), dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
-                       L, j, w, part);
+    klaunch(P->acc, true, true, cgs_proj_kernel<TB, 1>, dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
+            L, j, w, part);
   LAUNCH_CHECK();
   ACC_AFTER(kc, sb * L * j + sb * L, 2.0 * L * j);
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
@@ -351,20 +407,20 @@ static int launch_upd_norm(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, in
     const int nt = static_cast<int>(ceil_div(L, static_cast<int64_t>(WAVE) * nr));
     const int nw = static_cast<int>(ceil_div(j, CGS_TILE_CPW));
     if (vec)
-      hipLaunchKernelGGL((cgs_tile_upd_kernel<TB, NV>), dim3(nt), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j, w, h,
-                         out, npart);
+      klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, NV>, dim3(nt), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j,
+              w, h, out, npart);
     else
-      hipLaunchKernelGGL((cgs_tile_upd_kernel<TB, 1>), dim3(nt), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j, w, h,
-                         out, npart);
+      klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, 1>, dim3(nt), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j,
+              w, h, out, npart);
     return nt;
   }
   const int nn = cgs_updnorm_blocks(L);
   if (vec)
-    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, NV>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j, w, h,
-                       out, npart);
+    klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, NV>, dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
+            w, h, out, npart);
   else
-    hipLaunchKernelGGL((cgs_upd_norm_kernel<TB, 1>), dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j, w, h,
-                       out, npart);
+    klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, 1>, dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
+            w, h, out, npart);
   return nn;
 }
 
@@ -385,18 +441,18 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     if (cpw) {
       const int nb = cgs_updproj_blocks(L, j);
       const int nw = static_cast<int>(ceil_div(j, cpw));
-      ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
+      ACC_BEFORE_ATT(SVDS_KC_CGS_UPDPROJ);
       // 8 columns per wave with prefetch: one row per lane (two rows per lane
       // raise register pressure and lose ~30%); 10 columns: 16-byte rows
       if (cpw == 8)
-        hipLaunchKernelGGL((cgs_upd_proj_kernel<TB, 8, true, 1>), dim3(nb), dim3(nw * WAVE), 0, P->stream, Q,
-                           ldq, L, j, w, h1, w1, part);
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 8, true, 1>, dim3(nb), dim3(nw * WAVE), 0, P->stream, Q,
+                ldq, L, j, w, h1, w1, part);
       else if (vec)
-        hipLaunchKernelGGL((cgs_upd_proj_kernel<TB, 10, false, NV>), dim3(nb), dim3(nw * WAVE), 0, P->stream,
-                           Q, ldq, L, j, w, h1, w1, part);
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, NV>, dim3(nb), dim3(nw * WAVE), 0, P->stream,
+                Q, ldq, L, j, w, h1, w1, part);
       else
-        hipLaunchKernelGGL((cgs_upd_proj_kernel<TB, 10, false, 1>), dim3(nb), dim3(nw * WAVE), 0, P->stream,
-                           Q, ldq, L, j, w, h1, w1, part);
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, 1>, dim3(nb), dim3(nw * WAVE), 0, P->stream,
+                Q, ldq, L, j, w, h1, w1, part);
       LAUNCH_CHECK();
       ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 4.0 * L * j);
       ACC_BEFORE(SVDS_KC_CGS_REDUCE);
@@ -406,7 +462,7 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
       ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * j * nb, 0.0);
     } else {
       // wide basis: separate update and projection passes
-      ACC_BEFORE(SVDS_KC_CGS_UPDPROJ);
+      ACC_BEFORE_ATT(SVDS_KC_CGS_UPDPROJ);
       launch_upd_norm<TB>(P, Q, ldq, L, j, w, h1, w1, nullptr);
       LAUNCH_CHECK();
       ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 2.0 * L * j);
@@ -415,7 +471,7 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     src = w1;
   }
   // pass 3: out = w1 - Q h2 and its norm
-  ACC_BEFORE(SVDS_KC_CGS_UPDNORM);
+  ACC_BEFORE_ATT(SVDS_KC_CGS_UPDNORM);
   const int nn = launch_upd_norm<TB>(P, Q, ldq, L, j, src, h2, out, s.npart);
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * j + 2 * sb * L, 2.0 * L * j + 2.0 * L);
