@@ -173,8 +173,8 @@ def main():
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of this solver is a design, not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver does not "
+              "shard a problem across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -50,7 +50,7 @@ enum {
   SVDS_EINVAL = -1,      /* bad sizes, null pointers, k/p out of range      */
   SVDS_ENOMEM = -2,      /* device workspace allocation failed              */
   SVDS_EDEVICE = -3,     /* a HIP runtime call failed                       */
-  SVDS_EUNSUPPORTED = -4 /* valid request this build does not implement     */
+  SVDS_EUNSUPPORTED = -4 /* valid request the library does not implement    */
 };
 
 /* Storage type of A's values. */
