@@ -51,10 +51,16 @@ def load_golden(path=GOLDEN_W2):
 
 
 def kernel_source_hash():
+    """Hash of the code (comments and whitespace removed) of the kernel
+    sources the stored PMC traffic figures were measured on."""
+    import re
     h = hashlib.sha256()
     for f in ("kernels_cgs.hpp", "kernels_spmv.hpp", "common.hpp"):
-        with open(os.path.join(ROOT, "paper_2405_18966_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2405_18966_amd", "csrc", f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -17,8 +17,8 @@
 //  * Column-sorted items (optional): a plan stores each MULTI item's nonzeros
 //    sorted by column with their row-order positions (spos), built once by
 //    sort_items_kernel.  Gathers of neighbouring lanes then often share a
-//    cache line (1.5x on a block-diagonal batch, 7% on a Zipf matrix, no
-//    change on uniformly random columns, measured on MI355X); the products
+//    cache line (1.5x on a block-diagonal batch, 7% on a Zipf matrix, 3%
+//    slower on uniformly random columns, measured on MI355X); the products
 //    are placed in LDS at their row-order positions, so the result is
 //    bit-identical to the row-ordered layout.  PIECE ranges stay in row order.
 //  * Optional side task: dst[i] = src[i] * xs for i < side_len, spread over
