@@ -363,6 +363,7 @@ static int b_run_cycles(Batch &Bt, Lanczos<TB> &Lz, double tol_c, int maxit, boo
 
 extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const svds_opts *opts, double *const *U,
                                       double *const *S, double *const *V, svds_info *infos) {
+  SVDS_ABI_TRY
   using namespace svds;
   if (count < 0 || (count > 0 && (!As || !opts || !U || !S || !V))) return SVDS_EINVAL;
   if (count == 0) return SVDS_OK;
@@ -678,4 +679,5 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
     in.workspace_bytes = static_cast<int64_t>(P->arena.size);
   }
   return worst;
+  SVDS_ABI_CATCH
 }

@@ -17,26 +17,31 @@ using namespace svds;
 
 extern "C" int svds_csr_solve(const svds_csr *A, const svds_opts *opts, double *U, double *S,
                               double *V, svds_info *info) {
+  SVDS_ABI_TRY
   svds_plan *P = nullptr;
   int rc = svds_plan_create_csr(A, opts, &P);
   if (rc) return rc;
   rc = svds_plan_execute(P, U, S, V, info);
   svds_plan_destroy(P);
   return rc;
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_dense_solve(const svds_dense *A, const svds_opts *opts, double *U, double *S,
                                 double *V, svds_info *info) {
+  SVDS_ABI_TRY
   svds_plan *P = nullptr;
   int rc = svds_plan_create_dense(A, opts, &P);
   if (rc) return rc;
   rc = svds_plan_execute(P, U, S, V, info);
   svds_plan_destroy(P);
   return rc;
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_residuals_csr(const svds_csr *A, int32_t k, const double *U, const double *S,
                                   const double *V, double *res_av, double *res_atu, void *stream) {
+  SVDS_ABI_TRY
   if (!A || k < 1 || !U || !S || !V || !res_av || !res_atu) return SVDS_EINVAL;
   svds_opts o{};
   o.k = 1;
@@ -49,6 +54,7 @@ extern "C" int svds_residuals_csr(const svds_csr *A, int32_t k, const double *U,
   rc = svds_plan_residuals(P, k, U, S, V, res_av, res_atu);
   svds_plan_destroy(P);
   return rc;
+  SVDS_ABI_CATCH
 }
 
 extern "C" const char *svds_strerror(int code) {
@@ -84,6 +90,7 @@ struct Scratch {
 extern "C" int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *x_scale,
                                 const double *coef, const void *yprev, void *y, int32_t basis_dtype,
                                 void *stream) {
+  SVDS_ABI_TRY
   if (!A || !x || !y || A->m < 1 || A->n < 1) return SVDS_EINVAL;
   if (A->dtype != SVDS_F64 && A->dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
   if (basis_dtype != SVDS_F64 && basis_dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
@@ -122,11 +129,13 @@ extern "C" int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   return SVDS_OK;
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_op_dense_matvec(const svds_dense *A, int32_t transpose, const void *x,
                                     const double *x_scale, const double *coef, const void *yprev,
                                     void *y, int32_t basis_dtype, void *stream) {
+  SVDS_ABI_TRY
   if (!A || !x || !y || A->m < 1 || A->n < 1 || A->ld < A->m) return SVDS_EINVAL;
   svds_opts o{};
   o.k = 1;
@@ -141,11 +150,13 @@ extern "C" int svds_op_dense_matvec(const svds_dense *A, int32_t transpose, cons
   rc = svds_plan_matvec(P, transpose, x, x_scale, coef, yprev, y, basis_dtype);
   svds_plan_destroy(P);
   return rc;
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_op_csr_matvec(const svds_csr *A, int32_t transpose, const void *x,
                                   const double *x_scale, const double *coef, const void *yprev,
                                   void *y, int32_t basis_dtype, int32_t *panels, void *stream) {
+  SVDS_ABI_TRY
   if (!A || !x || !y) return SVDS_EINVAL;
   if (A->m < 2 || A->n < 3) return SVDS_EINVAL;
   if (basis_dtype != SVDS_F64 && basis_dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
@@ -162,10 +173,12 @@ extern "C" int svds_op_csr_matvec(const svds_csr *A, int32_t transpose, const vo
   rc = svds_plan_matvec(P, transpose, x, x_scale, coef, yprev, y, basis_dtype);
   svds_plan_destroy(P);
   return rc;
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_op_csc_build(const svds_csr *A, int32_t *t_row_ptr, int32_t *t_col_idx,
                                  void *t_val, void *stream) {
+  SVDS_ABI_TRY
   if (!A || !t_row_ptr || (A->nnz > 0 && (!t_col_idx || !t_val))) return SVDS_EINVAL;
   if (A->m < 2 || A->n < 3) return SVDS_EINVAL;
   svds_opts o{};
@@ -178,18 +191,22 @@ extern "C" int svds_op_csc_build(const svds_csr *A, int32_t *t_row_ptr, int32_t 
   rc = svds_plan_transpose_copy(P, t_row_ptr, t_col_idx, t_val);
   svds_plan_destroy(P);
   return rc;
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_op_cgs2(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
                             double *norm_out, int32_t dtype, void *stream) {
+  SVDS_ABI_TRY
   if (L < 1 || j < 0 || j > CGS_MAXJ || (j > 0 && (!Q || ldq < L)) || !w || !out) return SVDS_EINVAL;
   if (dtype != SVDS_F64 && dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
   return svds_cgs2_op(L, j, Q, ldq, w, out, norm_out, dtype, stream);
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_op_small_svd(int32_t p, int32_t k, double tol, double *T, double *Uk, double *Vext,
                                  double *sig, double *res, double *rho, int32_t *flags_host,
                                  void *stream) {
+  SVDS_ABI_TRY
   if (p < 2 || k < 1 || k >= p || !T || !Uk || !Vext || !sig || !res || !rho) return SVDS_EINVAL;
   if (p > 1023) return SVDS_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -208,11 +225,13 @@ extern "C" int svds_op_small_svd(int32_t p, int32_t k, double tol, double *T, do
   HIP_TRY(hipStreamSynchronize(st));
   if (flags_host) std::memcpy(flags_host, hf, 3 * sizeof(int));
   return SVDS_OK;
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_op_rotate(int64_t L, int32_t pc, int32_t kc, const void *B, int64_t ldb,
                               int32_t btype, const double *Y, int64_t ldy, double *out, int64_t ldo,
                               void *stream) {
+  SVDS_ABI_TRY
   if (L < 1 || pc < 1 || kc < 1 || !B || !Y || !out || ldb < L || ldy < pc || ldo < L) return SVDS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   Scratch yt;
@@ -229,10 +248,12 @@ extern "C" int svds_op_rotate(int64_t L, int32_t pc, int32_t kc, const void *B, 
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   return SVDS_OK;
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_op_philox_normal(int64_t L, uint64_t seed, uint32_t stream_id, double *out,
                                      void *stream) {
+  SVDS_ABI_TRY
   if (L < 1 || !out) return SVDS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL((philox_fill_kernel<double>), dim3(ceil_div(ceil_div(L, 2), 256)), dim3(256), 0, st,
@@ -240,13 +261,16 @@ extern "C" int svds_op_philox_normal(int64_t L, uint64_t seed, uint32_t stream_i
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   return SVDS_OK;
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_op_copy_f64(int64_t L, const double *src, double *dst, void *stream) {
+  SVDS_ABI_TRY
   if (L < 1 || !src || !dst) return SVDS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(copy_f64_kernel, dim3(ceil_div(L, 256)), dim3(256), 0, st, L, src, dst);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   return SVDS_OK;
+  SVDS_ABI_CATCH
 }

@@ -1,6 +1,7 @@
 // Host-side plan: device workspace arena, operator (A and A^T), per-kernel
 // timing, and the Lanczos cycle driver of Alg. 2.
 #pragma once
+#include <new>
 #include <vector>
 #include <string>
 #include <chrono>
@@ -8,6 +9,18 @@
 #include "../../include/svds.h"
 #include "common.hpp"
 #include "kernels_spmv.hpp"
+
+// Around the body of every C entry point: no exception (a failed host
+// allocation) crosses the C ABI; it becomes an error code.
+#define SVDS_ABI_TRY try {
+#define SVDS_ABI_CATCH                                                        \
+  }                                                                           \
+  catch (const std::bad_alloc &) {                                            \
+    return SVDS_ENOMEM;                                                       \
+  }                                                                           \
+  catch (...) {                                                               \
+    return SVDS_EDEVICE;                                                      \
+  }
 
 namespace svds {
 

@@ -899,17 +899,25 @@ static int build_panels(svds_plan *P) {
   std::vector<SpmvPlan> pp(np);
   {
     std::vector<std::thread> th;
-    std::vector<char> started(np, 0);
+    std::vector<char> started(np, 0), failed(np, 0);
     for (int g = 0; g < np; ++g) {
       try {
-        th.emplace_back([&, g] { build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g]); });
+        th.emplace_back([&, g] {
+          try {
+            build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g]);
+          } catch (...) {
+            failed[g] = 1;
+          }
+        });
         started[g] = 1;
       } catch (...) {
       }
     }
     for (auto &t : th) t.join();
-    for (int g = 0; g < np; ++g)  // any panel whose thread could not start
-      if (!started[g]) build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g]);
+    for (int g = 0; g < np; ++g) {
+      if (failed[g]) return SVDS_ENOMEM;
+      if (!started[g]) build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g]);  // no thread
+    }
   }
   std::vector<std::vector<int4>> per(np);
   sp.h_long.clear();
@@ -1026,9 +1034,16 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   // column counts from that transpose.  The arena is therefore sized with
   // bounds for both (at most one item per row plus the pieces).
   SpmvPlan fwd_items;
+  bool fwd_failed = false;  // a failed host allocation on the helper thread
   std::thread tf;
   try {
-    tf = std::thread([&] { build_spmv_items(hrp.data(), A->m, fwd_items, seg_rows, nseg); });
+    tf = std::thread([&] {
+      try {
+        build_spmv_items(hrp.data(), A->m, fwd_items, seg_rows, nseg);
+      } catch (...) {
+        fwd_failed = true;
+      }
+    });
   } catch (...) {
     build_spmv_items(hrp.data(), A->m, fwd_items, seg_rows, nseg);
   }
@@ -1061,6 +1076,7 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   op.bwd.longrows = bl;
   op.bwd.partials = bp;
   if (tf.joinable()) tf.join();
+  if (fwd_failed) return SVDS_ENOMEM;
   if (fwd_items.nitems > fwd_items_cap || fwd_items.nlong > fwd_long_cap || fwd_items.npieces > fwd_pieces_cap)
     return SVDS_EDEVICE;
   op.fwd.h_items = std::move(fwd_items.h_items);
@@ -1085,10 +1101,13 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
 }
 
 extern "C" int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, svds_plan **plan) {
+  SVDS_ABI_TRY
   return plan_create_csr_impl(A, opts, plan, nullptr, nullptr, 0);
+  SVDS_ABI_CATCH
 }
 
 extern "C" int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts, svds_plan **plan) {
+  SVDS_ABI_TRY
   if (!A || !opts || !plan) return SVDS_EINVAL;
   *plan = nullptr;
   if (A->m < 1 || A->n < 1 || A->ld < A->m || !A->a) return SVDS_EINVAL;
@@ -1111,6 +1130,7 @@ extern "C" int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts
   if ((rc = alloc_arena(P))) return rc;
   *plan = guard.release();
   return SVDS_OK;
+  SVDS_ABI_CATCH
 }
 
 extern "C" void svds_plan_destroy(svds_plan *P) {
@@ -1177,6 +1197,7 @@ static int warm_start_vector(svds_plan *P) {
 }  // namespace svds
 
 extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, svds_info *info) {
+  SVDS_ABI_TRY
   if (!P || !U || !S || !V) return SVDS_EINVAL;
   const auto t0 = std::chrono::steady_clock::now();
   HIP_TRY(hipSetDevice(P->device));
@@ -1266,6 +1287,7 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
     info->workspace_bytes = static_cast<int64_t>(P->arena.size + P->op.pbuf_bytes);
   }
   return conv ? SVDS_OK : SVDS_NOT_CONVERGED;
+  SVDS_ABI_CATCH
 }
 
 // ===========================================================================
