@@ -131,8 +131,9 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restri
 // tiles of 64 N rows; wave v holds columns [CPW v, CPW v + CPW) of the tile in
 // registers, so Q is read once for both the update and the projection.  The
 // cross-wave row sums go through a double-buffered LDS array (one barrier per
-// tile).  Narrow register tiles (CPW <= 10) keep occupancy high: measured on
-// MI355X, 8-10 columns per wave stream at 4-5 TB/s, 12-16 at half that.
+// tile).  Narrow register tiles (CPW <= 12 with one row per lane) keep
+// occupancy high: measured on MI355X, two rows per lane with 12-16 columns
+// per wave stream at a third of the rate or less.
 // Bases wider than 16 * CPW use a separate update pass plus cgs_proj instead.
 // part: [j][nblk].
 // ---------------------------------------------------------------------------
@@ -475,8 +476,14 @@ inline int cgs_updproj_blocks(int64_t L, int j) {
 inline bool cgs_tile_upd_ok(int64_t L, int j, int rows_per_lane) {
   return j <= CGS_TILE_MAXJ && ceil_div(L, static_cast<int64_t>(WAVE) * rows_per_lane) <= NORM_MAX_BLOCKS;
 }
-// columns per wave of the fused pass for a basis of width j (0: use the split path)
-inline int cgs_fused_cpw(int j) { return j <= 128 ? 8 : (j <= CGS_FUSED_MAXJ ? 10 : 0); }
+// columns per wave of the fused pass for a basis of width j (0: use the split
+// path).  FP64: 8 up to j = 80, then 10 (both one row per lane with register
+// prefetch; measured on MI355X, 10 columns are 2-7% faster from j ~ 90 on).
+// FP32: 8 up to 128, then 10 with 16-byte rows.
+inline int cgs_fused_cpw(int j, int elem_bytes) {
+  if (j > CGS_FUSED_MAXJ) return 0;
+  return j <= (elem_bytes == 8 ? 80 : 128) ? 8 : 10;
+}
 inline int cgs_updnorm_blocks(int64_t L) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(NORM_MAX_BLOCKS, ceil_div(L, CGS_THREADS))));
 }

@@ -437,16 +437,19 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     // pass 1: h1 = Q^T w
     if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ))) return rc;
     // pass 2: w1 = w - Q h1, h2 = Q^T w1
-    const int cpw = cgs_fused_cpw(j);
+    const int cpw = cgs_fused_cpw(j, static_cast<int>(sizeof(TB)));
     if (cpw) {
       const int nb = cgs_updproj_blocks(L, j);
       const int nw = static_cast<int>(ceil_div(j, cpw));
       ACC_BEFORE_ATT(SVDS_KC_CGS_UPDPROJ);
-      // 8 columns per wave with prefetch: one row per lane (two rows per lane
-      // raise register pressure and lose ~30%); 10 columns: 16-byte rows
+      // one row per lane with register prefetch (two rows per lane raise
+      // register pressure); FP32 bases with 10 columns take 16-byte rows
       if (cpw == 8)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 8, true, 1>, dim3(nb), dim3(nw * WAVE), 0, P->stream, Q,
                 ldq, L, j, w, h1, w1, part);
+      else if (sizeof(TB) == 8)
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, true, 1>, dim3(nb), dim3(nw * WAVE), 0, P->stream,
+                Q, ldq, L, j, w, h1, w1, part);
       else if (vec)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, NV>, dim3(nb), dim3(nw * WAVE), 0, P->stream,
                 Q, ldq, L, j, w, h1, w1, part);
