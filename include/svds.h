@@ -70,8 +70,18 @@ enum { SVDS_PREC_FP64 = 0, SVDS_PREC_MIXED = 1 };
 enum {
   SVDS_FLAG_TIMING = 1,       /* record per-kernel-class device time in info   */
   SVDS_FLAG_NO_RESIDUALS = 2, /* skip the explicit FP64 residuals at the end   */
-  SVDS_FLAG_NO_SIGNFIX = 4    /* leave the signs of (u_j, v_j) as computed     */
+  SVDS_FLAG_NO_SIGNFIX = 4,   /* leave the signs of (u_j, v_j) as computed     */
+  SVDS_FLAG_GRAPH = 8         /* replay each restart cycle as a captured HIP graph */
 };
+
+/* SVDS_FLAG_GRAPH: the launches of a restart cycle that follow the small SVD
+ * (the restart vector of eq. (7) and the Lanczos steps k+1..p, Alg. 2 steps
+ * 10-13) are captured once per plan into a HIP graph and replayed with one
+ * hipGraphLaunch per cycle (the batched solver captures again when its set
+ * of unconverged problems changes).  Results are bit-identical to the
+ * ordinary launches.  The capture uses a private stream of the plan; the
+ * graph runs on opts->stream.  With SVDS_FLAG_TIMING the captured launches
+ * are counted but not timed. */
 
 typedef struct {
   int64_t m, n, nnz;
@@ -146,6 +156,8 @@ typedef struct {
   int64_t kc_sampled_launches[SVDS_KC_COUNT];
   double kc_sampled_bytes[SVDS_KC_COUNT];
   int64_t workspace_bytes;         /* device arena of the plan              */
+  int32_t graph_captures;          /* SVDS_FLAG_GRAPH: cycle graphs captured */
+  int32_t graph_replays;           /* ... and cycles run by replaying one    */
 } svds_info;
 
 typedef struct svds_plan svds_plan;

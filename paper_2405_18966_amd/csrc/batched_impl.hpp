@@ -76,6 +76,7 @@ struct Batch {
   std::vector<int32_t> h_wl_tiles;
   std::vector<int32_t> h_active;
   std::vector<int> conv_cycle;  // cycle (of the current phase) at which each problem converged
+  uint64_t wl_version = 0;      // bumped whenever the work lists change (captured cycles key on it)
   ~Batch() {
     if (P) svds_plan_destroy(P);
     if (mem) (void)hipFree(mem);
@@ -267,6 +268,7 @@ static int b_update_worklists(Batch &Bt) {
   P->op.fwd.side_ntiles = Bt.wl_ntiles[1];
   P->op.bwd.side_tiles = Bt.wl_tiles[0];
   P->op.bwd.side_ntiles = Bt.wl_ntiles[0];
+  ++Bt.wl_version;
   return SVDS_OK;
 }
 
@@ -296,9 +298,11 @@ static int b_activate_all(Batch &Bt) {
   return b_update_worklists(Bt);
 }
 
-template <typename TB> static int b_restart(Batch &Bt, Lanczos<TB> &Lz) {
+// Alg. 2 steps 8-9 for every active problem: Ritz vectors into the other
+// ping-pong buffer (V[:, k] = v_{p+1}), then the converged problems freeze.
+template <typename TB> static int b_restart_rotate(Batch &Bt, Lanczos<TB> &Lz) {
   svds_plan *P = Bt.P;
-  const int p = P->p, k = P->k, ld = p + 1;
+  const int p = P->p, k = P->k;
   const int nxt = 1 - Lz.cur;
   TB *U = Lz.U[Lz.cur], *V = Lz.V[Lz.cur];
   TB *Un = Lz.U[nxt], *Vn = Lz.V[nxt];
@@ -308,9 +312,17 @@ template <typename TB> static int b_restart(Batch &Bt, Lanczos<TB> &Lz) {
                         Lz.ldv);
   if (rc) return rc;
   Lz.cur = nxt;
-  rc = b_freeze_converged(Bt);
-  if (rc) return rc;
-  rc = matvec<TB>(P, false, Vn + k * Lz.ldv, Bt.ones, nullptr, nullptr, Lz.wu, nullptr, 0);
+  return b_freeze_converged(Bt);
+}
+
+// Alg. 2 steps 10-11 (eq. (7)): u_{k+1} = A v_{k+1} - Uk rho, re-orthogonalized
+// against Uk, alpha_{k+1}.  Only launches: this and the Lanczos steps after it
+// form the captured part of a cycle.
+template <typename TB> static int b_restart_tail(Batch &Bt, Lanczos<TB> &Lz) {
+  svds_plan *P = Bt.P;
+  const int p = P->p, k = P->k, ld = p + 1;
+  TB *Un = Lz.U[Lz.cur], *Vn = Lz.V[Lz.cur];
+  int rc = matvec<TB>(P, false, Vn + k * Lz.ldv, Bt.ones, nullptr, nullptr, Lz.wu, nullptr, 0);
   if (rc) return rc;
   TB *rho_b = reinterpret_cast<TB *>(Bt.rho_b);
   hipLaunchKernelGGL((cast_copy_kernel<double, TB>), dim3(ceil_div(static_cast<int64_t>(Bt.nb) * k, 256)), dim3(256),
@@ -352,9 +364,18 @@ static int b_run_cycles(Batch &Bt, Lanczos<TB> &Lz, double tol_c, int maxit, boo
       if (mx < best) best = mx, nodec = 0;
       else if (++nodec >= 2) break;
     }
-    rc = b_restart<TB>(Bt, Lz);
+    rc = b_restart_rotate<TB>(Bt, Lz);
     if (rc) break;
-    rc = b_lanczos<TB>(Bt, Lz, k);
+    if (P->opts.flags & SVDS_FLAG_GRAPH) {
+      rc = run_graphed<TB>(P, Lz, Bt.wl_version, [&] {
+        const int r = b_restart_tail<TB>(Bt, Lz);
+        return r ? r : b_lanczos<TB>(Bt, Lz, k);
+      });
+    } else {
+      rc = b_restart_tail<TB>(Bt, Lz);
+      if (rc) break;
+      rc = b_lanczos<TB>(Bt, Lz, k);
+    }
   }
   return rc;
 }
@@ -677,6 +698,8 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
       in.kc_sampled_bytes[c] = P->acc.sampled_bytes[c];
     }
     in.workspace_bytes = static_cast<int64_t>(P->arena.size);
+    in.graph_captures = static_cast<int32_t>(P->graphs.captures);
+    in.graph_replays = static_cast<int32_t>(P->graphs.replays);
   }
   return worst;
   SVDS_ABI_CATCH

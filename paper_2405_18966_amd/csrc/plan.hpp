@@ -106,6 +106,37 @@ struct Accounting {
 };
 
 // ---------------------------------------------------------------------------
+// Captured Lanczos cycles (SVDS_FLAG_GRAPH).  The launches of one cycle after
+// the small SVD (restart vector, Lanczos steps k+1..p) are captured once into
+// an executable HIP graph and replayed on every later cycle that starts from
+// the same ping-pong buffer: one graph per (basis type, buffer).  A graph is
+// valid for one work-list version (the batched solver changes its launch
+// grids when problems freeze; a single problem has one version for the
+// plan's lifetime).  The accounting and mat-vec counters a captured body adds
+// are recorded at capture and added again on every replay.
+// ---------------------------------------------------------------------------
+struct CycleGraphs {
+  hipStream_t cap = nullptr;       // capture stream (default priority)
+  hipGraphExec_t exec[2][2] = {};  // [basis is FP64][buffer the cycle starts from]
+  uint64_t ver[2][2] = {};         // work-list version captured (0: none)
+  int next_cur[2][2] = {};         // buffer after the body
+  double dbytes[2][2][SVDS_KC_COUNT] = {}, dflops[2][2][SVDS_KC_COUNT] = {};
+  int64_t dlaunch[2][2][SVDS_KC_COUNT] = {}, dspmv[2][2] = {}, dspmvT[2][2] = {};
+  int64_t captures = 0, replays = 0;
+  void drop(int t, int c) {
+    if (exec[t][c]) (void)hipGraphExecDestroy(exec[t][c]);
+    exec[t][c] = nullptr;
+    ver[t][c] = 0;
+  }
+  void destroy() {
+    for (int t = 0; t < 2; ++t)
+      for (int c = 0; c < 2; ++c) drop(t, c);
+    if (cap) (void)hipStreamDestroy(cap);
+    cap = nullptr;
+  }
+};
+
+// ---------------------------------------------------------------------------
 // The matrix operator: y = xs * A x - coef * yprev and the transpose.
 // ---------------------------------------------------------------------------
 struct Operator {

@@ -272,6 +272,7 @@ struct svds_plan {
   Accounting acc;
   int64_t n_spmv = 0, n_spmvT = 0;
   int cycles32 = 0, cycles64 = 0, jac_sweeps = 0;
+  CycleGraphs graphs;  // SVDS_FLAG_GRAPH
 };
 
 namespace svds {
@@ -620,6 +621,87 @@ template <typename TB> static int restart(svds_plan *P, Lanczos<TB> &Lz) {
                          s.T + k * ld + k, s.xs_u);
 }
 
+// One cycle body through the graph cache (CycleGraphs): captured at its first
+// use for this (basis type, starting buffer, work-list version), then replayed
+// with one hipGraphLaunch.  `body` enqueues on P->stream and may switch
+// Lz.cur; it must not synchronize or read device data on the host.
+template <typename TB, typename Body>
+static int run_graphed(svds_plan *P, Lanczos<TB> &Lz, uint64_t ver, Body &&body) {
+  CycleGraphs &G = P->graphs;
+  Accounting &acc = P->acc;
+  const int t = sizeof(TB) == 8 ? 1 : 0, c = Lz.cur;
+  if (G.ver[t][c] != ver) {
+    G.drop(t, c);
+    if (!G.cap) HIP_TRY(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+    double b0[SVDS_KC_COUNT], f0[SVDS_KC_COUNT];
+    int64_t l0[SVDS_KC_COUNT];
+    std::memcpy(b0, acc.bytes, sizeof b0);
+    std::memcpy(f0, acc.flops, sizeof f0);
+    std::memcpy(l0, acc.launches, sizeof l0);
+    const int64_t s0 = P->n_spmv, st0 = P->n_spmvT;
+    const bool timing = acc.timing;
+    hipStream_t user = P->stream;
+    acc.timing = false;  // no event records inside a capture
+    P->stream = G.cap;
+    int rc = SVDS_OK;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      set_last_error(e, "hipStreamBeginCapture", __FILE__, __LINE__);
+      rc = SVDS_EDEVICE;
+    } else {
+      rc = body();
+      e = hipStreamEndCapture(G.cap, &g);
+      if (!rc && e != hipSuccess) {
+        set_last_error(e, "hipStreamEndCapture", __FILE__, __LINE__);
+        rc = SVDS_EDEVICE;
+      }
+    }
+    P->stream = user;
+    acc.timing = timing;
+    // what the body added is counted per replay, not at capture
+    for (int kc = 0; kc < SVDS_KC_COUNT; ++kc) {
+      G.dbytes[t][c][kc] = acc.bytes[kc] - b0[kc];
+      G.dflops[t][c][kc] = acc.flops[kc] - f0[kc];
+      G.dlaunch[t][c][kc] = acc.launches[kc] - l0[kc];
+      acc.bytes[kc] = b0[kc];
+      acc.flops[kc] = f0[kc];
+      acc.launches[kc] = l0[kc];
+    }
+    G.dspmv[t][c] = P->n_spmv - s0;
+    G.dspmvT[t][c] = P->n_spmvT - st0;
+    P->n_spmv = s0;
+    P->n_spmvT = st0;
+    G.next_cur[t][c] = Lz.cur;
+    Lz.cur = c;
+    if (!rc) {
+      hipGraphExec_t x = nullptr;
+      e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        set_last_error(e, "hipGraphInstantiate", __FILE__, __LINE__);
+        rc = SVDS_EDEVICE;
+      } else {
+        G.exec[t][c] = x;
+        G.ver[t][c] = ver;
+        ++G.captures;
+      }
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipGraphLaunch(G.exec[t][c], P->stream));
+  ++G.replays;
+  for (int kc = 0; kc < SVDS_KC_COUNT; ++kc) {
+    acc.bytes[kc] += G.dbytes[t][c][kc];
+    acc.flops[kc] += G.dflops[t][c][kc];
+    acc.launches[kc] += G.dlaunch[t][c][kc];
+  }
+  P->n_spmv += G.dspmv[t][c];
+  P->n_spmvT += G.dspmvT[t][c];
+  Lz.cur = G.next_cur[t][c];
+  return SVDS_OK;
+}
+
 // Runs cycles of one precision until the test passes with `tol_c`, maxit is
 // reached, or (stagnate > 0) the largest estimate stops decreasing.
 template <typename TB>
@@ -646,9 +728,16 @@ static int run_cycles(svds_plan *P, Lanczos<TB> &Lz, double tol_c, int maxit, bo
       if (mx < best) best = mx, nodec = 0;
       else if (++nodec >= 2) break;
     }
-    rc = restart<TB>(P, Lz);
-    if (rc) break;
-    rc = lanczos<TB>(P, Lz, P->k);
+    if (P->opts.flags & SVDS_FLAG_GRAPH) {
+      rc = run_graphed<TB>(P, Lz, 1, [&] {
+        const int r = restart<TB>(P, Lz);
+        return r ? r : lanczos<TB>(P, Lz, P->k);
+      });
+    } else {
+      rc = restart<TB>(P, Lz);
+      if (rc) break;
+      rc = lanczos<TB>(P, Lz, P->k);
+    }
   }
   P->tol = tol_save;
   return rc;
@@ -1142,6 +1231,7 @@ extern "C" void svds_plan_destroy(svds_plan *P) {
   if (P->op.pbuf) (void)hipFree(P->op.pbuf);
   if (P->op.pbuf_items) (void)hipFree(P->op.pbuf_items);
   if (P->h_flags) (void)hipHostFree(P->h_flags);
+  P->graphs.destroy();
   P->acc.destroy();
   delete P;
 }
@@ -1207,6 +1297,7 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
   P->acc.reset();
   P->n_spmv = P->n_spmvT = 0;
   P->cycles32 = P->cycles64 = P->jac_sweeps = 0;
+  const int64_t cap0 = P->graphs.captures, rep0 = P->graphs.replays;
   HIP_TRY(hipMemsetAsync(P->sc.sigma_est, 0, sizeof(double), P->stream));
   HIP_TRY(hipMemsetAsync(P->sc.bd, 0, 4 * sizeof(int), P->stream));
   HIP_TRY(hipMemsetAsync(P->sc.T, 0, sizeof(double) * (P->p + 1) * (P->p + 1), P->stream));
@@ -1288,6 +1379,8 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
       info->kc_sampled_bytes[c] = P->acc.sampled_bytes[c];
     }
     info->workspace_bytes = static_cast<int64_t>(P->arena.size + P->op.pbuf_bytes);
+    info->graph_captures = static_cast<int32_t>(P->graphs.captures - cap0);
+    info->graph_replays = static_cast<int32_t>(P->graphs.replays - rep0);
   }
   return conv ? SVDS_OK : SVDS_NOT_CONVERGED;
   SVDS_ABI_CATCH

@@ -21,7 +21,7 @@ SVDS_OK, SVDS_NOT_CONVERGED = 0, 1
 SVDS_EINVAL, SVDS_ENOMEM, SVDS_EDEVICE, SVDS_EUNSUPPORTED = -1, -2, -3, -4
 SVDS_F64, SVDS_F32, SVDS_BF16 = 0, 1, 2
 SVDS_PREC_FP64, SVDS_PREC_MIXED = 0, 1
-SVDS_FLAG_TIMING, SVDS_FLAG_NO_RESIDUALS, SVDS_FLAG_NO_SIGNFIX = 1, 2, 4
+SVDS_FLAG_TIMING, SVDS_FLAG_NO_RESIDUALS, SVDS_FLAG_NO_SIGNFIX, SVDS_FLAG_GRAPH = 1, 2, 4, 8
 KERNEL_CLASSES = ["spmv", "spmvT", "cgs_proj", "cgs_updproj", "cgs_updnorm", "cgs_reduce", "smallsvd",
                   "rotate", "other"]
 KC_COUNT = len(KERNEL_CLASSES)
@@ -53,7 +53,8 @@ class svds_info(C.Structure):
                 ("kc_ms", C.c_double * KC_COUNT), ("kc_bytes", C.c_double * KC_COUNT),
                 ("kc_flops", C.c_double * KC_COUNT), ("kc_launches", C.c_int64 * KC_COUNT),
                 ("kc_sampled_launches", C.c_int64 * KC_COUNT), ("kc_sampled_bytes", C.c_double * KC_COUNT),
-                ("workspace_bytes", C.c_int64)]
+                ("workspace_bytes", C.c_int64), ("graph_captures", C.c_int32),
+                ("graph_replays", C.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("kc_")}
