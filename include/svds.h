@@ -71,8 +71,27 @@ enum {
   SVDS_FLAG_TIMING = 1,       /* record per-kernel-class device time in info   */
   SVDS_FLAG_NO_RESIDUALS = 2, /* skip the explicit FP64 residuals at the end   */
   SVDS_FLAG_NO_SIGNFIX = 4,   /* leave the signs of (u_j, v_j) as computed     */
-  SVDS_FLAG_GRAPH = 8         /* replay each restart cycle as a captured HIP graph */
+  SVDS_FLAG_GRAPH = 8,        /* replay each restart cycle as a captured HIP graph */
+  SVDS_FLAG_AUTOTUNE = 16,    /* pick launch shapes by timing them at plan time */
+  /* Fixed launch shapes of the CSR products (the tuner's candidates; with
+   * SVDS_FLAG_AUTOTUNE the tuner's choice replaces the first two, and
+   * SVDS_FLAG_NO_PANELS keeps panels out of its candidates): */
+  SVDS_FLAG_ITEMS_1K = 32,    /* work items of at most 1024 nonzeros, not 2048  */
+  SVDS_FLAG_UNSORTED = 64,    /* no column-sorted copy of the work items        */
+  SVDS_FLAG_NO_PANELS = 128   /* A^T y over the plain CSR of A^T, no panels     */
 };
+
+/* SVDS_FLAG_AUTOTUNE: plan creation times candidate launch shapes on the
+ * plan's own matrix and keeps the fastest (svds_tuning reports the choice).
+ *   - CSR products A x and A^T y: nonzeros per work item (2048 or 1024; rows
+ *     longer than that are split into pieces), column-sorted items on or
+ *     off, and for A^T y the column-panel form on or off.
+ *   - CGS2 (not for the batched solver, whose passes are segmented): the
+ *     first pass's row-slab count (x 1/2, 1, 2) and the fused pass's columns
+ *     per wave (8 or 10), timed at basis widths p/4, p/2 and p.
+ * The choice depends on measured times, so two plans of one matrix can pick
+ * differently and their results then differ by rounding (each is still
+ * deterministic); without the flag the built-in rules apply. */
 
 /* SVDS_FLAG_GRAPH: the launches of a restart cycle that follow the small SVD
  * (the restart vector of eq. (7) and the Lanczos steps k+1..p, Alg. 2 steps
@@ -133,6 +152,20 @@ enum {
   SVDS_KC_COUNT
 };
 
+/* Launch shapes chosen by SVDS_FLAG_AUTOTUNE (all zero without it). */
+typedef struct {
+  int32_t tuned;                     /* 1 if the tuner ran                       */
+  int32_t fwd_nnz_cap, fwd_sorted;   /* A x: nonzeros per item, column-sorted    */
+  int32_t bwd_nnz_cap, bwd_sorted;   /* A^T y: same                              */
+  int32_t bwd_panels;                /* A^T y column panels (1 = none)           */
+  int32_t cgs_slab_shift;            /* CGS2 pass-1 slabs x 2^shift              */
+  int32_t cgs_cpw;                   /* fused-pass columns per wave (0 = rule)   */
+  double fwd_us, fwd_default_us;     /* A x: chosen and built-in shape, us       */
+  double bwd_us, bwd_default_us;     /* A^T y: same                              */
+  double cgs_us, cgs_default_us;     /* CGS2 at widths p/4, p/2, p summed        */
+  double ms_tune;                    /* wall time of the tuning                  */
+} svds_tuning;
+
 typedef struct {
   int32_t nconv;        /* leading triplets with eq. (4) estimate < tol     */
   int32_t cycles;       /* Lanczos cycles run (FP32 + FP64)                 */
@@ -158,6 +191,7 @@ typedef struct {
   int64_t workspace_bytes;         /* device arena of the plan              */
   int32_t graph_captures;          /* SVDS_FLAG_GRAPH: cycle graphs captured */
   int32_t graph_replays;           /* ... and cycles run by replaying one    */
+  svds_tuning tuning;              /* SVDS_FLAG_AUTOTUNE choices of the plan */
 } svds_info;
 
 typedef struct svds_plan svds_plan;

@@ -700,6 +700,7 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
     in.workspace_bytes = static_cast<int64_t>(P->arena.size);
     in.graph_captures = static_cast<int32_t>(P->graphs.captures);
     in.graph_replays = static_cast<int32_t>(P->graphs.replays);
+    in.tuning = P->tuning;
   }
   return worst;
   SVDS_ABI_CATCH

@@ -41,6 +41,8 @@ struct Arena {
   }
 };
 
+constexpr int SPMV_TUNE_MIN_CAP = 1024;  // smallest item nnz cap a plan uses (SVDS_FLAG_ITEMS_1K, tuner)
+
 // Work decomposition of one CSR product (see kernels_spmv.hpp).
 struct SpmvPlan {
   int nitems = 0, nlong = 0, npieces = 0;
@@ -58,13 +60,17 @@ struct SpmvPlan {
   const int32_t *active = nullptr;       // per-problem work mask (batched), or null
   const int32_t *side_tiles = nullptr;   // tiles of x the side task covers (batched), or null: all
   int side_ntiles = 0;
+  bool sorted = true;  // use the column-sorted copy when it exists (the tuner may turn it off)
+  int cap_items = 0, cap_long = 0, cap_pieces = 0;  // sizes of the device item buffers
 };
 
 // Work items of a CSR product.  With seg_end (nseg consecutive row ranges
 // ending at seg_end[g], one per problem of a batch) items never cross a range
 // and carry the range index g; without it there is one range, index 0.
+// nnz_cap (<= SPMV_NNZ_BLK): largest nonzero count of a MULTI item; longer
+// rows become PIECE items.
 void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp, const int64_t *seg_end = nullptr,
-                      int nseg = 1);
+                      int nseg = 1, int nnz_cap = SPMV_NNZ_BLK);
 
 // ---------------------------------------------------------------------------
 // Per-kernel-class accounting and optional device timing with event pairs.

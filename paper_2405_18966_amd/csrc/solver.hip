@@ -45,7 +45,7 @@ static inline unsigned grid_for(int64_t work, int64_t per_block, int64_t gmax = 
 // ---------------------------------------------------------------------------
 // SpMV work items (host, at plan time)
 // ---------------------------------------------------------------------------
-void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp, const int64_t *seg_end, int nseg) {
+void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp, const int64_t *seg_end, int nseg, int nnz_cap) {
   sp.h_items.clear();
   sp.h_long.clear();
   int npieces = 0;
@@ -54,7 +54,7 @@ void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp, const int64_t 
     const int64_t e = seg_end ? seg_end[g] : m;  // items never cross a problem boundary
     while (r < e) {
       const int64_t len = rp[r + 1] - rp[r];
-      if (len > SPMV_NNZ_BLK) {
+      if (len > nnz_cap) {
         const int np = static_cast<int>(ceil_div(len, SPMV_PIECE));
         const int lr = static_cast<int>(sp.h_long.size());
         sp.h_long.push_back(LongRow{static_cast<int32_t>(r), npieces, np, g});
@@ -71,7 +71,7 @@ void build_spmv_items(const int32_t *rp, int64_t m, SpmvPlan &sp, const int64_t 
       int64_t z = 0;
       while (r < e && r - r0 < SPMV_ROWS_BLK) {
         const int64_t l = rp[r + 1] - rp[r];
-        if (l > SPMV_NNZ_BLK || z + l > SPMV_NNZ_BLK) break;
+        if (l > nnz_cap || z + l > nnz_cap) break;
         z += l;
         ++r;
       }
@@ -273,6 +273,11 @@ struct svds_plan {
   int64_t n_spmv = 0, n_spmvT = 0;
   int cycles32 = 0, cycles64 = 0, jac_sweeps = 0;
   CycleGraphs graphs;  // SVDS_FLAG_GRAPH
+  // launch-shape knobs of the CGS2 passes (SVDS_FLAG_AUTOTUNE; 0 = built-in
+  // rules): pass-1 slab count times 2^cgs_slab_shift, fused-pass columns per
+  // wave forced to cgs_cpw (8 or 10)
+  int cgs_slab_shift = 0, cgs_cpw = 0;
+  svds_tuning tuning{};  // what the tuner chose and measured
 };
 
 namespace svds {
@@ -334,8 +339,10 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     const int32_t *rp = panels ? op.prp : trans ? op.trp : op.rp;
     const int32_t *ci = panels ? op.pci : trans ? op.tci : op.ci;
     const void *val = panels ? op.pval : trans ? op.tval : op.val;
-    const int32_t *cs = sp.spos ? sp.scol : ci;
-    const void *vs = sp.spos ? sp.sval : val;
+    const bool srt = sp.sorted && sp.spos;
+    const uint16_t *spos = srt ? sp.spos : nullptr;
+    const int32_t *cs = srt ? sp.scol : ci;
+    const void *vs = srt ? sp.sval : val;
     TB *yk = panels ? reinterpret_cast<TB *>(op.ypart) : y;
     const double *ck = panels ? nullptr : coef;
     const TB *ypk = panels ? nullptr : yprev;
@@ -343,11 +350,11 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     const bool fix = sp.nlong > 0;
     if (op.vt == SVDS_F64)
       klaunch(P->acc, true, !fix && !panels, spmv_csr_kernel<double, TB>, dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-              P->stream, sp.items, rp, cs, static_cast<const double *>(vs), sp.spos, x, xs, ck, ypk, yk, parts,
+              P->stream, sp.items, rp, cs, static_cast<const double *>(vs), spos, x, xs, ck, ypk, yk, parts,
               side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles);
     else
       klaunch(P->acc, true, !fix && !panels, spmv_csr_kernel<float, TB>, dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-              P->stream, sp.items, rp, cs, static_cast<const float *>(vs), sp.spos, x, xs, ck, ypk, yk, parts,
+              P->stream, sp.items, rp, cs, static_cast<const float *>(vs), spos, x, xs, ck, ypk, yk, parts,
               side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles);
     if (fix)
       klaunch(P->acc, false, !panels, spmv_longrow_fixup_kernel<TB>, dim3(sp.nlong), dim3(WAVE), 0, P->stream,
@@ -378,6 +385,11 @@ static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int
   const double sb = sizeof(TB);
   int nslab, ngc;
   cgs_proj_shape(L, j, nslab, ngc);
+  if (P->cgs_slab_shift > 0)
+    nslab = static_cast<int>(std::min<int64_t>({int64_t(nslab) << P->cgs_slab_shift, CGS_MAX_SLABS,
+                                                 std::max<int64_t>(nslab, ceil_div(L, 256))}));
+  else if (P->cgs_slab_shift < 0)
+    nslab = std::max(1, nslab >> -P->cgs_slab_shift);
   constexpr int NV = 16 / sizeof(TB);
   ACC_BEFORE_ATT(kc);
   if (cgs_rows_per_lane<TB>(Q, ldq, w, nullptr, nullptr) == NV)
@@ -438,7 +450,9 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     // pass 1: h1 = Q^T w
     if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ))) return rc;
     // pass 2: w1 = w - Q h1, h2 = Q^T w1
-    const int cpw = cgs_fused_cpw(j, static_cast<int>(sizeof(TB)));
+    int cpw = cgs_fused_cpw(j, static_cast<int>(sizeof(TB)));
+    // a forced width must keep the block within 16 waves
+    if (cpw && P->cgs_cpw && ceil_div(j, P->cgs_cpw) <= 16) cpw = P->cgs_cpw;
     if (cpw) {
       const int nb = cgs_updproj_blocks(L, j);
       const int nw = static_cast<int>(ceil_div(j, cpw));
@@ -921,7 +935,7 @@ static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int
 
 // Column-sorted copy of a product's nonzeros (see sort_items_kernel).
 static int sort_spmv(svds_plan *P, SpmvPlan &sp, const int32_t *col, const void *val) {
-  if (!sp.spos || sp.nitems == 0) return SVDS_OK;
+  if (!sp.spos || !sp.sorted || sp.nitems == 0) return SVDS_OK;
   if (P->op.vt == SVDS_F64)
     hipLaunchKernelGGL((sort_items_kernel<double>), dim3(sp.nitems), dim3(SPMV_THREADS), 0, P->stream, sp.items,
                        col, static_cast<const double *>(val), sp.scol, static_cast<double *>(sp.sval), sp.spos);
@@ -930,6 +944,11 @@ static int sort_spmv(svds_plan *P, SpmvPlan &sp, const int32_t *col, const void 
                        col, static_cast<const float *>(val), sp.scol, static_cast<float *>(sp.sval), sp.spos);
   HIP_TRY(hipGetLastError());
   return SVDS_OK;
+}
+
+// Nonzeros per MULTI work item of the plan's products.
+static int item_cap(const svds_plan *P) {
+  return (P->opts.flags & SVDS_FLAG_ITEMS_1K) ? SPMV_TUNE_MIN_CAP : SPMV_NNZ_BLK;
 }
 
 static int upload_spmv(svds_plan *P, SpmvPlan &sp) {
@@ -996,7 +1015,7 @@ static int build_panels(svds_plan *P) {
       try {
         th.emplace_back([&, g] {
           try {
-            build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g]);
+            build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g], nullptr, 1, item_cap(P));
           } catch (...) {
             failed[g] = 1;
           }
@@ -1008,7 +1027,7 @@ static int build_panels(svds_plan *P) {
     for (auto &t : th) t.join();
     for (int g = 0; g < np; ++g) {
       if (failed[g]) return SVDS_ENOMEM;
-      if (!started[g]) build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g]);  // no thread
+      if (!started[g]) build_spmv_items(hrp.data() + static_cast<int64_t>(g) * n, n, pp[g], nullptr, 1, item_cap(P));  // no thread
     }
   }
   std::vector<std::vector<int4>> per(np);
@@ -1070,6 +1089,190 @@ static int build_panels(svds_plan *P) {
   return upload_spmv(P, sp);
 }
 
+// ---------------------------------------------------------------------------
+// Plan-time autotuner (SVDS_FLAG_AUTOTUNE): candidate launch shapes are timed
+// on the plan's own matrix and bases with HIP events and the fastest is kept.
+// ---------------------------------------------------------------------------
+namespace {
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+}  // namespace
+
+// Microseconds per call of fn: one warm-up call, then the better of two
+// brackets of `reps` calls.
+template <typename F> static int tune_time(svds_plan *P, EventPair &ev, int reps, F &&fn, double &us) {
+  int rc = fn();
+  if (rc) return rc;
+  us = INFINITY;
+  for (int t = 0; t < 2; ++t) {
+    HIP_TRY(hipEventRecord(ev.a, P->stream));
+    for (int i = 0; i < reps; ++i)
+      if ((rc = fn())) return rc;
+    HIP_TRY(hipEventRecord(ev.b, P->stream));
+    HIP_TRY(hipEventSynchronize(ev.b));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+    us = std::min(us, 1e3 * ms / reps);
+  }
+  return SVDS_OK;
+}
+
+// Work items of one product with a given nonzero cap, uploaded into the
+// plan's item buffers, and their column-sorted copy when one is kept.
+static int tune_build_items(svds_plan *P, bool trans, const int32_t *hrp, int64_t rows, const int64_t *seg,
+                            int nseg, int cap) {
+  Operator &op = P->op;
+  SpmvPlan &sp = trans ? op.bwd : op.fwd;
+  SpmvPlan tmp;
+  build_spmv_items(hrp, rows, tmp, seg, nseg, cap);
+  if (tmp.nitems > sp.cap_items || tmp.nlong > sp.cap_long || tmp.npieces > sp.cap_pieces) return SVDS_EDEVICE;
+  sp.h_items = std::move(tmp.h_items);
+  sp.h_long = std::move(tmp.h_long);
+  sp.nitems = tmp.nitems;
+  sp.nlong = tmp.nlong;
+  sp.npieces = tmp.npieces;
+  int rc = upload_spmv(P, sp);
+  if (rc) return rc;
+  return sort_spmv(P, sp, trans ? op.tci : op.ci, trans ? op.tval : op.val);
+}
+
+// Item cap and sorting of one product: caps 2048 (built in) then 1024, each
+// with and without the column-sorted copy (when the plan keeps one); with
+// column panels the panel form is the first candidate.
+static int tune_product(svds_plan *P, EventPair &ev, bool trans, const int32_t *hrp, int64_t rows,
+                        const int64_t *seg, int nseg) {
+  Operator &op = P->op;
+  SpmvPlan &sp = trans ? op.bwd : op.fwd;
+  Lanczos<double> &Lz = P->L64;
+  const double *x = trans ? Lz.bu : Lz.bv;
+  double *y = trans ? Lz.wv : Lz.wu;
+  auto prod = [&] { return matvec<double>(P, trans, x, nullptr, nullptr, nullptr, y, nullptr, 0, SVDS_KC_OTHER); };
+  const int reps = 5;
+  const int npanel = op.npanel;
+  double best = INFINITY, dflt = INFINITY;
+  int best_cap = SPMV_NNZ_BLK, best_panels = npanel;
+  bool best_sorted = sp.spos != nullptr;
+  int rc;
+  if (npanel > 1) {
+    if ((rc = tune_time(P, ev, reps, prod, best))) return rc;
+    dflt = best;
+    op.npanel = 1;
+  }
+  const int caps[2] = {SPMV_NNZ_BLK, SPMV_TUNE_MIN_CAP};
+  for (int ci = 0; ci < 2; ++ci) {
+    // the plan's own items serve when they have this cap and their sorted copy
+    const bool have = ci == 0 && item_cap(P) == caps[0] && (sp.sorted || !sp.spos);
+    sp.sorted = true;
+    if (!have && (rc = tune_build_items(P, trans, hrp, rows, seg, nseg, caps[ci]))) return rc;
+    for (int so = sp.spos ? 1 : 0; so >= 0; --so) {
+      sp.sorted = so != 0;
+      double t;
+      if ((rc = tune_time(P, ev, reps, prod, t))) return rc;
+      if (npanel == 1 && ci == 0 && so == (sp.spos ? 1 : 0)) dflt = t;
+      if (t < best) best = t, best_cap = caps[ci], best_sorted = so != 0, best_panels = 1;
+    }
+  }
+  sp.sorted = true;
+  if (best_cap != caps[1] && (rc = tune_build_items(P, trans, hrp, rows, seg, nseg, best_cap))) return rc;
+  sp.sorted = best_sorted;
+  op.npanel = best_panels;
+  if (npanel > 1 && best_panels == 1) {  // the panel copy is not used: release it
+    if (op.pbuf) (void)hipFree(op.pbuf);
+    if (op.pbuf_items) (void)hipFree(op.pbuf_items);
+    op.pbuf = op.pbuf_items = nullptr;
+    op.pbuf_bytes = 0;
+  }
+  svds_tuning &tu = P->tuning;
+  (trans ? tu.bwd_nnz_cap : tu.fwd_nnz_cap) = best_cap;
+  (trans ? tu.bwd_sorted : tu.fwd_sorted) = best_sorted && sp.spos ? 1 : 0;
+  (trans ? tu.bwd_us : tu.fwd_us) = best;
+  (trans ? tu.bwd_default_us : tu.fwd_default_us) = dflt;
+  if (trans) tu.bwd_panels = best_panels;
+  return SVDS_OK;
+}
+
+// CGS2 launch shapes, timed on the U-side basis (filled with normal deviates)
+// at widths p/4, p/2 and p: first the pass-1 slab count, then the fused
+// pass's columns per wave.
+static int tune_cgs(svds_plan *P, EventPair &ev) {
+  Lanczos<double> &Lz = P->L64;
+  const int p = P->p;
+  const int64_t m = Lz.m;
+  hipLaunchKernelGGL((philox_fill_kernel<double>), dim3(static_cast<unsigned>(ceil_div(ceil_div(Lz.ldu * (p + 1), 2), 256))),
+                     dim3(256), 0, P->stream, Lz.ldu * (p + 1), P->opts.seed ^ 0x7475u, 1u, Lz.U[0]);
+  hipLaunchKernelGGL((philox_fill_kernel<double>), dim3(static_cast<unsigned>(ceil_div(ceil_div(m, 2), 256))), dim3(256),
+                     0, P->stream, m, P->opts.seed ^ 0x7475u, 2u, Lz.wu);
+  HIP_TRY(hipGetLastError());
+  const int js[3] = {std::max(1, p / 4), std::max(1, p / 2), p};
+  auto eval = [&](double &total) {
+    total = 0;
+    for (int j : js) {
+      double t;
+      int rc = tune_time(P, ev, 3, [&] {
+        return cgs2_finish<double>(P, Lz, Lz.U[0], Lz.ldu, m, j, Lz.wu, Lz.w1u, Lz.bu, MODE_LANCZOS, P->sc.T,
+                                   P->sc.xs_u);
+      }, t);
+      if (rc) return rc;
+      total += t;
+    }
+    return static_cast<int>(SVDS_OK);
+  };
+  int rc;
+  double best, t;
+  P->cgs_slab_shift = 0;
+  P->cgs_cpw = 0;
+  if ((rc = eval(best))) return rc;
+  P->tuning.cgs_default_us = best;
+  int bs = 0, bc = 0;
+  for (int sh : {-1, 1}) {
+    P->cgs_slab_shift = sh;
+    if ((rc = eval(t))) return rc;
+    if (t < best) best = t, bs = sh;
+  }
+  P->cgs_slab_shift = bs;
+  for (int c : {8, 10}) {
+    P->cgs_cpw = c;
+    if ((rc = eval(t))) return rc;
+    if (t < best) best = t, bc = c;
+  }
+  P->cgs_cpw = bc;
+  P->tuning.cgs_slab_shift = bs;
+  P->tuning.cgs_cpw = bc;
+  P->tuning.cgs_us = best;
+  return SVDS_OK;
+}
+
+// The whole tuning of a plan (products only for CSR; CGS2 unless batched).
+static int autotune(svds_plan *P, const int32_t *hrp, const int32_t *htrp, const int64_t *seg_rows,
+                    const int64_t *seg_cols, int nseg) {
+  const auto t0 = std::chrono::steady_clock::now();
+  EventPair ev;
+  HIP_TRY(hipEventCreate(&ev.a));
+  HIP_TRY(hipEventCreate(&ev.b));
+  Lanczos<double> &Lz = P->L64;
+  // operands of the timed products: normal deviates
+  hipLaunchKernelGGL((philox_fill_kernel<double>), dim3(static_cast<unsigned>(ceil_div(ceil_div(Lz.n, 2), 256))), dim3(256),
+                     0, P->stream, Lz.n, P->opts.seed ^ 0x7475u, 3u, Lz.bv);
+  hipLaunchKernelGGL((philox_fill_kernel<double>), dim3(static_cast<unsigned>(ceil_div(ceil_div(Lz.m, 2), 256))), dim3(256),
+                     0, P->stream, Lz.m, P->opts.seed ^ 0x7475u, 4u, Lz.bu);
+  HIP_TRY(hipGetLastError());
+  int rc;
+  if (!P->op.dense) {
+    if ((rc = tune_product(P, ev, false, hrp, P->op.m, seg_rows, nseg))) return rc;
+    if ((rc = tune_product(P, ev, true, htrp, P->op.n, seg_cols, nseg))) return rc;
+  }
+  if (!seg_rows && (rc = tune_cgs(P, ev))) return rc;
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  P->tuning.tuned = 1;
+  P->tuning.ms_tune = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return SVDS_OK;
+}
+
 namespace {
 // Destroys a partially built plan on every early return of plan creation.
 struct PlanGuard {
@@ -1120,7 +1323,8 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   if (hrp[0] != 0 || hrp[A->m] != A->nnz) return SVDS_EINVAL;
   for (int64_t i = 0; i < A->m; ++i)
     if (hrp[i + 1] < hrp[i]) return SVDS_EINVAL;
-  op.npanel = seg_rows ? 1 : choose_panels(op.m, op.n, op.nnz);
+  op.npanel = (seg_rows || (opts->flags & SVDS_FLAG_NO_PANELS)) ? 1 : choose_panels(op.m, op.n, op.nnz);
+  op.fwd.sorted = op.bwd.sorted = !(opts->flags & SVDS_FLAG_UNSORTED);
   // The items of A are built on a helper thread while the arena is allocated
   // and the transpose is built on the device; the items of A^T need the
   // column counts from that transpose.  The arena is therefore sized with
@@ -1131,13 +1335,13 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   try {
     tf = std::thread([&] {
       try {
-        build_spmv_items(hrp.data(), A->m, fwd_items, seg_rows, nseg);
+        build_spmv_items(hrp.data(), A->m, fwd_items, seg_rows, nseg, item_cap(P));
       } catch (...) {
         fwd_failed = true;
       }
     });
   } catch (...) {
-    build_spmv_items(hrp.data(), A->m, fwd_items, seg_rows, nseg);
+    build_spmv_items(hrp.data(), A->m, fwd_items, seg_rows, nseg, item_cap(P));
   }
   struct Join {
     std::thread &t;
@@ -1145,10 +1349,15 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
       if (t.joinable()) t.join();
     }
   } join_fwd{tf};
+  // bounds for any item nnz cap >= SPMV_TUNE_MIN_CAP: at most one item per
+  // row plus the pieces, one long row per SPMV_TUNE_MIN_CAP nonzeros
   auto set_caps = [](SpmvPlan &sp, int64_t rows, int64_t nnz) {
     sp.nitems = static_cast<int>(std::max<int64_t>(1, rows + ceil_div(nnz, SPMV_PIECE) + 1));
-    sp.nlong = static_cast<int>(std::max<int64_t>(1, ceil_div(nnz, SPMV_NNZ_BLK) + 1));
+    sp.nlong = static_cast<int>(std::max<int64_t>(1, ceil_div(nnz, SPMV_TUNE_MIN_CAP) + 1));
     sp.npieces = static_cast<int>(std::max<int64_t>(1, ceil_div(nnz, SPMV_PIECE) + sp.nlong));
+    sp.cap_items = sp.nitems;
+    sp.cap_long = sp.nlong;
+    sp.cap_pieces = sp.npieces;
   };
   set_caps(op.fwd, A->m, A->nnz);
   set_caps(op.bwd, A->n, A->nnz);
@@ -1161,7 +1370,7 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   int4 *bi = op.bwd.items;
   LongRow *bl = op.bwd.longrows;
   double *bp = op.bwd.partials;
-  build_spmv_items(htrp.data(), A->n, op.bwd, seg_cols, nseg);
+  build_spmv_items(htrp.data(), A->n, op.bwd, seg_cols, nseg, item_cap(P));
   if (op.bwd.nitems > bwd_items_cap || op.bwd.nlong > bwd_long_cap || op.bwd.npieces > bwd_pieces_cap)
     return SVDS_EDEVICE;
   op.bwd.items = bi;
@@ -1187,6 +1396,8 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
     op.pbuf_bytes = 0;
     op.npanel = 1;
   }
+  if ((opts->flags & SVDS_FLAG_AUTOTUNE) && (rc = autotune(P, hrp.data(), htrp.data(), seg_rows, seg_cols, nseg)))
+    return rc;
   HIP_TRY(hipStreamSynchronize(P->stream));
   *plan = guard.release();
   return SVDS_OK;
@@ -1220,6 +1431,7 @@ extern "C" int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts
   P->acc.stream = P->stream;
   P->acc.timing = (opts->flags & SVDS_FLAG_TIMING) != 0;
   if ((rc = alloc_arena(P))) return rc;
+  if ((opts->flags & SVDS_FLAG_AUTOTUNE) && (rc = autotune(P, nullptr, nullptr, nullptr, nullptr, 0))) return rc;
   *plan = guard.release();
   return SVDS_OK;
   SVDS_ABI_CATCH
@@ -1381,6 +1593,7 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
     info->workspace_bytes = static_cast<int64_t>(P->arena.size + P->op.pbuf_bytes);
     info->graph_captures = static_cast<int32_t>(P->graphs.captures - cap0);
     info->graph_replays = static_cast<int32_t>(P->graphs.replays - rep0);
+    info->tuning = P->tuning;
   }
   return conv ? SVDS_OK : SVDS_NOT_CONVERGED;
   SVDS_ABI_CATCH

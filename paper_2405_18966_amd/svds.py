@@ -21,7 +21,8 @@ SVDS_OK, SVDS_NOT_CONVERGED = 0, 1
 SVDS_EINVAL, SVDS_ENOMEM, SVDS_EDEVICE, SVDS_EUNSUPPORTED = -1, -2, -3, -4
 SVDS_F64, SVDS_F32, SVDS_BF16 = 0, 1, 2
 SVDS_PREC_FP64, SVDS_PREC_MIXED = 0, 1
-SVDS_FLAG_TIMING, SVDS_FLAG_NO_RESIDUALS, SVDS_FLAG_NO_SIGNFIX, SVDS_FLAG_GRAPH = 1, 2, 4, 8
+SVDS_FLAG_TIMING, SVDS_FLAG_NO_RESIDUALS, SVDS_FLAG_NO_SIGNFIX, SVDS_FLAG_GRAPH, SVDS_FLAG_AUTOTUNE = 1, 2, 4, 8, 16
+SVDS_FLAG_ITEMS_1K, SVDS_FLAG_UNSORTED, SVDS_FLAG_NO_PANELS = 32, 64, 128
 KERNEL_CLASSES = ["spmv", "spmvT", "cgs_proj", "cgs_updproj", "cgs_updnorm", "cgs_reduce", "smallsvd",
                   "rotate", "other"]
 KC_COUNT = len(KERNEL_CLASSES)
@@ -44,6 +45,18 @@ class svds_opts(C.Structure):
                 ("stream", C.c_void_p), ("flags", C.c_int32)]
 
 
+class svds_tuning(C.Structure):
+    _fields_ = [("tuned", C.c_int32), ("fwd_nnz_cap", C.c_int32), ("fwd_sorted", C.c_int32),
+                ("bwd_nnz_cap", C.c_int32), ("bwd_sorted", C.c_int32), ("bwd_panels", C.c_int32),
+                ("cgs_slab_shift", C.c_int32), ("cgs_cpw", C.c_int32),
+                ("fwd_us", C.c_double), ("fwd_default_us", C.c_double), ("bwd_us", C.c_double),
+                ("bwd_default_us", C.c_double), ("cgs_us", C.c_double), ("cgs_default_us", C.c_double),
+                ("ms_tune", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class svds_info(C.Structure):
     _fields_ = [("nconv", C.c_int32), ("cycles", C.c_int32), ("cycles_fp32", C.c_int32),
                 ("cycles_fp64", C.c_int32), ("breakdowns", C.c_int32), ("converged", C.c_int32),
@@ -54,10 +67,11 @@ class svds_info(C.Structure):
                 ("kc_flops", C.c_double * KC_COUNT), ("kc_launches", C.c_int64 * KC_COUNT),
                 ("kc_sampled_launches", C.c_int64 * KC_COUNT), ("kc_sampled_bytes", C.c_double * KC_COUNT),
                 ("workspace_bytes", C.c_int64), ("graph_captures", C.c_int32),
-                ("graph_replays", C.c_int32)]
+                ("graph_replays", C.c_int32), ("tuning", svds_tuning)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("kc_")}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("kc_") and f != "tuning"}
+        d["tuning"] = self.tuning.as_dict()
         for f in ("kc_ms", "kc_bytes", "kc_flops", "kc_launches", "kc_sampled_launches", "kc_sampled_bytes"):
             d[f] = dict(zip(KERNEL_CLASSES, list(getattr(self, f))))
         return d

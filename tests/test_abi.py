@@ -76,7 +76,7 @@ def test_ctypes_structs_match_the_c_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"svds_csr": mod.svds_csr, "svds_dense": mod.svds_dense, "svds_opts": mod.svds_opts,
-               "svds_info": mod.svds_info}
+               "svds_info": mod.svds_info, "svds_tuning": mod.svds_tuning}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "svds.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
