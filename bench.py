@@ -14,7 +14,10 @@ stream the kernels run on), the headline SpMV+CGS2 GB/s, parity of the
 singular values against stored oracle values, and the CPU oracle timed on a
 complete solve of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--paper-dense]
+
+It also times the paper's synthetic Sparse1-3 suite (Sec. 3.1) against the
+closed-form singular values, with the paper's own CPU times as context.
 """
 from __future__ import annotations
 
@@ -167,6 +170,52 @@ def batched_vs_loop(S, inputs, np, torch):
     return out
 
 
+# The paper's own times for its synthetic suite: svds-C with MKL on 16
+# threads of 2x 8-core Intel Xeon @ 2.10 GHz, seconds (Table 2; FP64,
+# k = 100, t = 300, tol = 1e-10, r = 10).  Context only: another machine.
+PAPER_TABLE2_MKL16_S = {"sparse1": 2.14, "sparse2": 1.24, "sparse3": 1.33,
+                        "dense1": 16.5, "dense2": 10.7, "dense3": 10.2}
+
+
+def paper_suite(S, inputs, np, torch, dense: bool):
+    """Sparse1-3 (40,000 x 40,000, 5 nnz/row) and, with ``dense``, Dense1-3
+    (10,000 x 10,000) of Sec. 3.1 at the paper's shape and settings; best of
+    2 solves after one warm-up, singular values against the closed-form
+    Decay1/2/3 values."""
+    out = {}
+    c = inputs.PAPER_SUITE_SOLVE
+    names = ["sparse1", "sparse2", "sparse3"] + (["dense1", "dense2", "dense3"] if dense else [])
+    for name in names:
+        log(f"paper suite {name} ...")
+        A, sig = inputs.paper_suite(name)
+        N = len(sig)
+        v0 = torch.from_numpy(inputs.start_vector(N, inputs.PAPER_SUITE_SEEDS[name] + 1)).cuda()
+        opts = S.make_opts(c["k"], c["p"], c["tol"], c["maxit"], v0=v0)
+        if name.startswith("sparse"):
+            Ad, keep = S.csr_to_device(A)
+            run = lambda: S.svds_csr_solve(Ad, opts)
+        else:
+            Ad = S.make_dense(torch.from_numpy(A.ravel(order="F")).cuda(), N, N)
+            run = lambda: S.svds_dense_solve(Ad, opts)
+        r = run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            r = run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        sv = r.S.cpu().numpy()
+        t = min(ts)
+        out[name] = {"n": N, "ms": round(t * 1e3, 2), "solves_per_s": round(1 / t, 2), "cycles": r.info["cycles"],
+                     "status": r.status, "nconv": r.info["nconv"],
+                     "sigma_rel_err_vs_exact": float(np.max(np.abs(sv - sig[:c["k"]]) / sig[:c["k"]])),
+                     "paper_mkl16_s": PAPER_TABLE2_MKL16_S[name],
+                     "x_vs_paper_mkl16": round(PAPER_TABLE2_MKL16_S[name] / t, 1)}
+        del A, Ad
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +224,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed vs FP64 comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs looped comparison")
+    ap.add_argument("--no-suite", action="store_true", help="skip the paper's Sparse1-3 suite")
+    ap.add_argument("--paper-dense", action="store_true",
+                    help="add Dense1-3 (10,000 x 10,000) to the paper suite (about a minute of host "
+                         "time each to generate the Haar factors)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
     args = ap.parse_args()
@@ -285,6 +338,10 @@ def main():
         log("batched vs looped ...")
         batched = batched_vs_loop(S, inputs, np, torch)
 
+    suite = None
+    if not args.no_suite:
+        suite = paper_suite(S, inputs, np, torch, args.paper_dense)
+
     cpu = None
     if not args.no_cpu and rank == 0:
         cpu = cpu_baseline(A, v0, k, p, tol)
@@ -296,7 +353,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic", "config": dict(WORKLOAD, parallelism="single GPU"),
            "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "mixed_vs_fp64": mixed,
-           "batched_vs_looped": batched}
+           "batched_vs_looped": batched, "paper_suite": suite}
     print(json.dumps(out), flush=True)
 
 

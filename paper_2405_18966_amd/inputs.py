@@ -36,7 +36,7 @@ __all__ = [
     "CSR", "Dense", "start_vector", "sparse_uniform", "sparse_zipf",
     "dense_lowrank", "batch_uniform", "round_values_f32", "decay1", "decay2",
     "decay3", "haar_orthogonal", "prescribed_sparse", "prescribed_dense",
-    "diag_matrix", "config_matrix", "CONFIG_SEEDS",
+    "diag_matrix", "config_matrix", "CONFIG_SEEDS", "paper_suite", "PAPER_SUITE_SEEDS", "PAPER_SUITE_SOLVE",
 ]
 
 # Seed of workload c (1-based) is 2405000 + c; the start vector uses seed + 1.
@@ -305,6 +305,33 @@ def config_matrix(c: int):
     if c == 5:
         return batch_uniform(256, 500, 20000, 0.005, s)
     raise ValueError(c)
+
+
+# --- the paper's synthetic suite (Sec. 3.1) -----------------------------------
+# Sparse1-3: 40,000 x 40,000 with 5 nonzeros per row, Dense1-3: 10,000 x
+# 10,000, singular values from Decay1/2/3; every case is solved for k = 100
+# (so t = max(15, 3k) = 300), tol = 1e-10, at most 10 cycles (Sec. 3).  The
+# paper does not state its generator; here the sparse ones are the 5 x 5
+# block construction of prescribed_sparse and the dense ones Haar factors.
+PAPER_SUITE_SEEDS = {name: 2405100 + i for i, name in
+                     enumerate(("sparse1", "sparse2", "sparse3", "dense1", "dense2", "dense3"))}
+PAPER_SUITE_SOLVE = dict(k=100, p=300, tol=1e-10, maxit=10)
+
+
+def paper_suite(name: str, n: int | None = None):
+    """(A, sigma): the named case and its exact singular values (descending).
+    ``n`` overrides the order (40,000 sparse, 10,000 dense) for smaller runs;
+    sparse orders are rounded down to a multiple of 5.  A is a CSR for the
+    sparse cases and a column-major ndarray for the dense ones."""
+    law = {"1": decay1, "2": decay2, "3": decay3}[name[-1]]
+    seed = PAPER_SUITE_SEEDS[name]
+    if name.startswith("sparse"):
+        N = (n or 40000) // 5 * 5
+        sig = law(N)
+        return prescribed_sparse(N // 5, 5, sig, seed), sig
+    N = n or 10000
+    sig = law(N)
+    return prescribed_dense(N, N, sig, seed), sig
 
 
 CONFIG_SOLVE = {

@@ -366,3 +366,32 @@ def test_planted_transposed_operand_is_caught(monkeypatch):
     s_T = np.linalg.svd(T, compute_uv=False)
     s_A = np.linalg.svd(A, compute_uv=False)
     assert np.max(np.abs(s_T - s_A) / s_A[0]) > 1e-3
+
+
+# --- the paper's synthetic suite at reduced order (Sec. 3.1, Sec. 3 settings) ---
+
+@pytest.mark.parametrize("name,n", [("sparse1", 500), ("sparse3", 500), ("dense2", 200)])
+def test_paper_suite_generator_spectrum(name, n):
+    """The generator's matrices have exactly the decay law's singular values
+    (dense LAPACK SVD of the whole matrix), 5 nonzeros per row when sparse."""
+    A, sig = inputs.paper_suite(name, n)
+    if name.startswith("sparse"):
+        assert np.all(np.diff(A.row_ptr) == 5)
+        D = np.zeros((A.m, A.n))
+        for i in range(A.m):
+            D[i, A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]]] = A.val[A.row_ptr[i]:A.row_ptr[i + 1]]
+    else:
+        D = A
+    s = np.linalg.svd(D, compute_uv=False)
+    np.testing.assert_allclose(s, sig, rtol=1e-9, atol=1e-15 * sig[0])
+
+
+def test_paper_suite_settings_oracle():
+    """k = 100, t = 300, tol = 1e-10, at most 10 cycles, on Sparse2 at order
+    2000: the oracle reaches the closed-form values."""
+    A, sig = inputs.paper_suite("sparse2", 2000)
+    c = inputs.PAPER_SUITE_SOLVE
+    U, S, V, info = svds(as_operator(A), c["k"], c["p"], c["tol"], c["maxit"],
+                         v0=inputs.start_vector(A.n, 5))
+    assert info.converged
+    np.testing.assert_allclose(S, sig[:c["k"]], rtol=1e-10)
