@@ -78,8 +78,20 @@ enum {
    * SVDS_FLAG_NO_PANELS keeps panels out of its candidates): */
   SVDS_FLAG_ITEMS_1K = 32,    /* work items of at most 1024 nonzeros, not 2048  */
   SVDS_FLAG_UNSORTED = 64,    /* no column-sorted copy of the work items        */
-  SVDS_FLAG_NO_PANELS = 128   /* A^T y over the plain CSR of A^T, no panels     */
+  SVDS_FLAG_NO_PANELS = 128,  /* A^T y over the plain CSR of A^T, no panels     */
+  SVDS_FLAG_SMALLEST = 256    /* the k smallest triplets instead (see below)    */
 };
+
+/* SVDS_FLAG_SMALLEST: the bidiagonalization approximates the smallest
+ * singular values as well as the largest (Sec. 1).  Each cycle keeps the k
+ * smallest Ritz triplets of T instead of the k largest; the restart of eqs.
+ * (5)-(7) and the test of eq. (4) hold for any k Ritz triplets.  S is then
+ * ascending (U, V in the same order).  The test's sigma floor stays
+ * 2^-52 times the largest Ritz value, so exactly zero singular values never
+ * pass it.  This is plain Ritz augmentation (not the harmonic variant), so
+ * convergence is fast only when the wanted values are well separated
+ * relative to sigma_1.  FP64 path only: EUNSUPPORTED with SVDS_PREC_MIXED
+ * and in the batched solver. */
 
 /* SVDS_FLAG_AUTOTUNE: plan creation times candidate launch shapes on the
  * plan's own matrix and keeps the fastest (svds_tuning reports the choice).
@@ -207,7 +219,7 @@ int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, svds_plan **p
 int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts, svds_plan **plan);
 
 /* Runs Alg. 2 to convergence or opts->maxit cycles and writes
- * U (m x k, ld = m), S (k, descending), V (n x k, ld = n), all FP64 device
+ * U (m x k, ld = m), S (k, descending; ascending with SVDS_FLAG_SMALLEST), V (n x k, ld = n), all FP64 device
  * buffers owned by the caller (Alg. 2 steps 15-16).  `info` may be NULL. */
 int svds_plan_execute(svds_plan *plan, double *U, double *S, double *V, svds_info *info);
 

@@ -27,6 +27,12 @@ Readings of the paper used here (where it is silent or ambiguous):
   by CGS2 against the same basis, normalised, and 0 is stored in T.
 * Signs: each output pair (u_j, v_j) is flipped so that the entry of v_j of
   largest magnitude (lowest index on ties) is positive.
+* Smallest triplets (``which="smallest"``; Sec. 1 notes that the
+  bidiagonalization also approximates the smallest singular values): the
+  same cycle with the k smallest Ritz triplets of T kept instead of the k
+  largest (eqs. (5)-(7) hold for any k Ritz triplets), returned in ascending
+  order.  The sigma floor of eq. (4) still uses the largest Ritz value.  This
+  is plain Ritz augmentation, not the harmonic variant.
 
 t (the paper's Lanczos dimension) is called p here.
 """
@@ -144,9 +150,11 @@ def small_svd(Tp: np.ndarray):
     return Uh, s, Vht.T
 
 
-def residual_estimates(beta, Uh_last_row, s, k):
-    """eq. (4): |beta_t Uh(t, j)| / sigma_j, j < k, with the sigma floor."""
-    floor = max(EPS * s[0], TINY) if s.size else TINY
+def residual_estimates(beta, Uh_last_row, s, k, s_max=None):
+    """eq. (4): |beta_t Uh(t, j)| / sigma_j, j < k, with the sigma floor
+    (2^-52 times the largest singular value of T, ``s_max`` or s[0])."""
+    s1 = s[0] if s_max is None else s_max
+    floor = max(EPS * s1, TINY) if s.size else TINY
     return np.abs(beta * Uh_last_row[:k]) / np.maximum(s[:k], floor)
 
 
@@ -159,8 +167,10 @@ def sign_normalize(U, V):
 
 
 def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
-         v0: np.ndarray | None = None, seed: int = 0, callback=None):
-    """k largest singular triplets of A (scipy sparse matrix or dense array).
+         v0: np.ndarray | None = None, seed: int = 0, callback=None, which: str = "largest"):
+    """k largest (``which="largest"``, descending) or smallest
+    (``which="smallest"``, ascending) singular triplets of A (scipy sparse
+    matrix or dense array).
 
     Defaults follow Alg. 2 and Sec. 3: p = max(15, 3k), tol = 1e-10; the paper
     fixes no default for r, 10 (its experiments' value) is used.
@@ -175,6 +185,8 @@ def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
     tol = tol or 1e-10
     maxit = maxit or 10
     validate(m, n, k, p)
+    if which not in ("largest", "smallest"):
+        raise ValueError(which)
     info = SvdsInfo()
     op = _Op(A, info)
     st = _State(op, p, seed, info)
@@ -193,10 +205,13 @@ def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
         info.cycles += 1
         # Alg. 2 step 4: SVD of T(1:t, 1:t).
         Uh, s, Vh = small_svd(st.T[:p, :p])
-        info.sigma_est = max(info.sigma_est, float(s[0]))
+        s_max = float(s[0])
+        info.sigma_est = max(info.sigma_est, s_max)
+        if which == "smallest":  # Ritz triplets in ascending order
+            Uh, s, Vh = Uh[:, ::-1], s[::-1], Vh[:, ::-1]
         beta = st.T[p - 1, p]
         # Alg. 2 step 5 / eq. (4).
-        res = residual_estimates(beta, Uh[p - 1], s, k)
+        res = residual_estimates(beta, Uh[p - 1], s, k, s_max)
         info.res_est = res
         info.nconv = int(np.argmin(np.append(res < tol, False)))
         if callback:

@@ -238,6 +238,9 @@ __device__ __forceinline__ int jacobi_pair16_reg(double (&xi)[RPL], double (&yi)
 
 // Singular values from the converged W (column norms), descending order
 // (ties: lower column first), outputs, eq. (4) estimates, restarted T.
+// smallest != 0: the k smallest in ascending order are kept instead (Ritz
+// augmentation with the smallest Ritz triplets); the sigma floor of eq. (4)
+// still uses the largest.
 // W, Vh: p rows, leading dimensions ldw, ldv.  sv/rank: block-shared
 // scratch of p entries.  beta = T(p, p+1) read before T is rewritten.
 // Entry (r, c) of T is T[(r (p+1) + c) ts] (ts = 1, or the number of
@@ -248,7 +251,7 @@ __device__ inline void jacobi_finish(const double *W, int64_t ldw, const double 
                                      double *__restrict__ Uk, double *__restrict__ Vext,
                                      double *__restrict__ sig, double *__restrict__ res,
                                      double *__restrict__ rho, int *__restrict__ flags,
-                                     double *__restrict__ sigma_est, double *sv, int *rank) {
+                                     double *__restrict__ sigma_est, double *sv, int *rank, int smallest) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int nwaves = blockDim.x / WAVE;
   const int ld = p + 1;
@@ -262,7 +265,10 @@ __device__ inline void jacobi_finish(const double *W, int64_t ldw, const double 
   for (int c = tid; c < p; c += blockDim.x) {
     const double s = sv[c];
     int rk = 0;
-    for (int d = 0; d < p; ++d) rk += (sv[d] > s) || (sv[d] == s && d < c);
+    if (smallest)
+      for (int d = 0; d < p; ++d) rk += (sv[d] < s) || (sv[d] == s && d < c);
+    else
+      for (int d = 0; d < p; ++d) rk += (sv[d] > s) || (sv[d] == s && d < c);
     rank[c] = rk;
   }
   __syncthreads();
@@ -283,7 +289,9 @@ __device__ inline void jacobi_finish(const double *W, int64_t ldw, const double 
   for (int r = tid; r <= p; r += blockDim.x) Vext[k * ld + r] = (r == p) ? 1.0 : 0.0;
   __syncthreads();
   if (tid == 0) {
-    const double s1 = sig[0];
+    double s1 = sig[0];
+    if (smallest)
+      for (int c = 0; c < p; ++c) s1 = fmax(s1, sv[c]);
     const double floor_ = fmax(0x1.0p-52 * s1, 2.2250738585072014e-308);
     int all = 1, lead = 0, leading = 1;
     for (int r = 0; r < k; ++r) {
@@ -325,7 +333,7 @@ __device__ inline void small_svd_body(double *__restrict__ T, int64_t ts, int p,
                                       double *__restrict__ Uk, double *__restrict__ Vext,
                                       double *__restrict__ sig, double *__restrict__ res,
                                       double *__restrict__ rho, int *__restrict__ flags,
-                                      double *__restrict__ sigma_est) {
+                                      double *__restrict__ sigma_est, int smallest) {
   extern __shared__ double smem[];
   __shared__ int rot_count;
   __shared__ double s_beta;
@@ -366,14 +374,14 @@ __device__ inline void small_svd_body(double *__restrict__ T, int64_t ts, int p,
     __syncthreads();
   }
   jacobi_finish(W, pe, Vh, pe, p, k, tol, s_beta, sweeps, T, ts, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
-                rank);
+                rank, smallest);
 }
 
 static __global__ __launch_bounds__(JAC_THREADS) void small_svd_kernel(
     double *__restrict__ T, int p, int k, double tol, double *__restrict__ Uk, double *__restrict__ Vext,
     double *__restrict__ sig, double *__restrict__ res, double *__restrict__ rho, int *__restrict__ flags,
-    double *__restrict__ sigma_est) {
-  small_svd_body(T, 1, p, k, tol, Uk, Vext, sig, res, rho, flags, sigma_est);
+    double *__restrict__ sigma_est, int smallest) {
+  small_svd_body(T, 1, p, k, tol, Uk, Vext, sig, res, rho, flags, sigma_est, smallest);
 }
 
 // One workgroup per problem of a batch (interleaved T, per-problem outputs
@@ -386,7 +394,7 @@ static __global__ __launch_bounds__(JAC_THREADS) void bsmall_svd_kernel(
   const int64_t b = blockIdx.x;
   if (!active[b]) return;  // converged and frozen: outputs of its last small SVD stay
   small_svd_body(T + b, nb, p, k, tol, Uk + b * p * k, Vext + b * (p + 1) * (k + 1), sig + b * k, res + b * k,
-                 rho + b * k, flags + 4 * b, sigma_est + b);
+                 rho + b * k, flags + 4 * b, sigma_est + b, 0);
 }
 
 __host__ __device__ inline size_t small_svd_lds_bytes(int p) {
@@ -506,7 +514,7 @@ static __global__ __launch_bounds__(JAC_THREADS) void bjac_finish_kernel(
     const double *__restrict__ W, const double *__restrict__ Vh, const int *__restrict__ counters, int nsw,
     double *__restrict__ T, int p, int k, double tol, double *__restrict__ Uk, double *__restrict__ Vext,
     double *__restrict__ sig, double *__restrict__ res, double *__restrict__ rho, int *__restrict__ flags,
-    double *__restrict__ sigma_est) {
+    double *__restrict__ sigma_est, int smallest) {
   extern __shared__ double smem[];
   __shared__ double s_beta;
   __shared__ int s_sweeps;
@@ -524,7 +532,7 @@ static __global__ __launch_bounds__(JAC_THREADS) void bjac_finish_kernel(
   }
   __syncthreads();
   jacobi_finish(W, p, Vh, p, p, k, tol, s_beta, s_sweeps, T, 1, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
-                rank);
+                rank, smallest);
 }
 
 }  // namespace svds

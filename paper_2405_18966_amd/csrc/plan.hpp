@@ -183,10 +183,10 @@ int svds_plan_transpose_copy(svds_plan *P, int32_t *t_row_ptr, int32_t *t_col_id
 int svds_cgs2_op(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
                  double *norm_out, int32_t dtype, void *stream);
 // Small SVD of T (p x p block of the (p+1) x (p+1) row-major T) and restart
-// set-up, enqueued on `st`; `work` holds jacobi_work_bytes(p) bytes of device
+// set-up, enqueued on `st` (smallest != 0: keep the k smallest Ritz triplets); `work` holds jacobi_work_bytes(p) bytes of device
 // memory, `h_counts` JAC_MAX_SWEEPS host ints (pinned or not).  The
 // multi-workgroup schedule reads its sweep counters back between chunks of
 // sweeps (stream synchronizations).
 int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, double *work, double *Uk,
                        double *Vext, double *sig, double *res, double *rho, int *flags, double *sigma_est,
-                       int *h_counts);
+                       int *h_counts, int smallest = 0);

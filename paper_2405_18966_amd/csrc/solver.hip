@@ -278,6 +278,7 @@ struct svds_plan {
   // wave forced to cgs_cpw (8 or 10)
   int cgs_slab_shift = 0, cgs_cpw = 0;
   svds_tuning tuning{};  // what the tuner chose and measured
+  bool smallest = false;  // SVDS_FLAG_SMALLEST: k smallest triplets, ascending
 };
 
 namespace svds {
@@ -598,7 +599,7 @@ static int small_svd(svds_plan *P) {
   const Small &s = P->sc;
   ACC_BEFORE(SVDS_KC_SMALLSVD);
   int rc = svds_small_svd_run(P->stream, s.T, p, P->k, P->tol, s.jac, s.Uk, s.Vext, s.sig, s.res, s.rho,
-                              s.flags, s.sigma_est, P->h_flags + 16);
+                              s.flags, s.sigma_est, P->h_flags + 16, P->smallest ? 1 : 0);
   if (rc) return rc;
   ACC_AFTER(SVDS_KC_SMALLSVD, 16.0 * (p + 1) * (p + 1), 0.0);
   HIP_TRY(hipMemcpyAsync(P->h_flags, s.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
@@ -774,7 +775,10 @@ static int fill_defaults(const svds_opts *o, int64_t m, int64_t n, svds_plan *P)
   P->maxit = o->maxit > 0 ? o->maxit : 10;
   P->stream = static_cast<hipStream_t>(o->stream);
   P->mixed = o->precision == SVDS_PREC_MIXED;
+  P->smallest = (o->flags & SVDS_FLAG_SMALLEST) != 0;
   if (o->precision != SVDS_PREC_FP64 && o->precision != SVDS_PREC_MIXED) return SVDS_EINVAL;
+  // the FP32 phase cannot resolve values below ~1e-7 sigma_1
+  if (P->smallest && P->mixed) return SVDS_EUNSUPPORTED;
   if (P->k < 1 || P->p <= P->k || P->p > m || P->p + 1 > n) return SVDS_EINVAL;
   if (P->p + 1 > CGS_MAXJ) return SVDS_EUNSUPPORTED;
   return SVDS_OK;
@@ -1554,10 +1558,11 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
   if (!(P->opts.flags & SVDS_FLAG_NO_RESIDUALS)) {
     HIP_TRY(hipMemcpy(hav.data(), P->sc.resid_av, sizeof(double) * k, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(hatu.data(), P->sc.resid_atu, sizeof(double) * k, hipMemcpyDeviceToHost));
+    const double s1 = *std::max_element(hs.begin(), hs.end());  // hs is ascending for smallest triplets
     for (int j = 0; j < k; ++j) {
-      const double sj = std::max(hs[j], std::max(0x1.0p-52 * hs[0], 2.2250738585072014e-308));
+      const double sj = std::max(hs[j], std::max(0x1.0p-52 * s1, 2.2250738585072014e-308));
       res_true = std::max(res_true, hatu[j] / sj);
-      res_av = std::max(res_av, hav[j] / std::max(hs[0], 2.2250738585072014e-308));
+      res_av = std::max(res_av, hav[j] / std::max(s1, 2.2250738585072014e-308));
     }
   }
   const auto t1 = std::chrono::steady_clock::now();
@@ -1867,13 +1872,13 @@ static __global__ void zero_i32_kernel(int n, int *__restrict__ out) {
 
 int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, double *work, double *Uk,
                        double *Vext, double *sig, double *res, double *rho, int *flags, double *sigma_est,
-                       int *h_counts) {
+                       int *h_counts, int smallest) {
   if (p < 2 || k < 1 || k >= p || p > 1023) return SVDS_EINVAL;
   if (p <= JAC_SMALL_P) {
     const int pe = p + (p & 1);
     const int nthr = std::min(JAC_THREADS, (pe / 2) * WAVE);
     hipLaunchKernelGGL(small_svd_kernel, dim3(1), dim3(nthr), small_svd_lds_bytes(p), st, T, p, k, tol, Uk,
-                       Vext, sig, res, rho, flags, sigma_est);
+                       Vext, sig, res, rho, flags, sigma_est, smallest);
     HIP_TRY(hipGetLastError());
     return SVDS_OK;
   }
@@ -1903,7 +1908,7 @@ int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, doub
       if (h_counts[i] == 0) done = true;
   }
   hipLaunchKernelGGL(bjac_finish_kernel, dim3(1), dim3(JAC_THREADS), static_cast<size_t>(p) * 12, st, W, Vh,
-                     counters, enq, T, p, k, tol, Uk, Vext, sig, res, rho, flags, sigma_est);
+                     counters, enq, T, p, k, tol, Uk, Vext, sig, res, rho, flags, sigma_est, smallest);
   HIP_TRY(hipGetLastError());
   return SVDS_OK;
 }

@@ -22,7 +22,7 @@ SVDS_EINVAL, SVDS_ENOMEM, SVDS_EDEVICE, SVDS_EUNSUPPORTED = -1, -2, -3, -4
 SVDS_F64, SVDS_F32, SVDS_BF16 = 0, 1, 2
 SVDS_PREC_FP64, SVDS_PREC_MIXED = 0, 1
 SVDS_FLAG_TIMING, SVDS_FLAG_NO_RESIDUALS, SVDS_FLAG_NO_SIGNFIX, SVDS_FLAG_GRAPH, SVDS_FLAG_AUTOTUNE = 1, 2, 4, 8, 16
-SVDS_FLAG_ITEMS_1K, SVDS_FLAG_UNSORTED, SVDS_FLAG_NO_PANELS = 32, 64, 128
+SVDS_FLAG_ITEMS_1K, SVDS_FLAG_UNSORTED, SVDS_FLAG_NO_PANELS, SVDS_FLAG_SMALLEST = 32, 64, 128, 256
 KERNEL_CLASSES = ["spmv", "spmvT", "cgs_proj", "cgs_updproj", "cgs_updnorm", "cgs_reduce", "smallsvd",
                   "rotate", "other"]
 KC_COUNT = len(KERNEL_CLASSES)

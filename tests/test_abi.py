@@ -65,6 +65,23 @@ def test_validation_rejects_bad_sizes_before_touching_the_device(lib):
     assert mod.lib.svds_plan_create_csr(ctypes.byref(A), ctypes.byref(o), ctypes.byref(h)) == -1
 
 
+def test_smallest_triplets_unsupported_forms_rejected_on_the_host(lib):
+    """SVDS_FLAG_SMALLEST is FP64-only: mixed precision and the batched solver
+    return EUNSUPPORTED before any device call."""
+    import importlib
+    mod = importlib.import_module("paper_2405_18966_amd.svds")
+    fake = 4096  # never dereferenced
+    A = mod.svds_csr(100, 50, 0, fake, fake, fake, 0)
+    h = ctypes.c_void_p()
+    o = mod.svds_opts(2, 6, 0.0, 0, mod.SVDS_PREC_MIXED, 0, None, None, mod.SVDS_FLAG_SMALLEST)
+    assert mod.lib.svds_plan_create_csr(ctypes.byref(A), ctypes.byref(o), ctypes.byref(h)) == -4
+    o = mod.svds_opts(2, 6, 0.0, 0, mod.SVDS_PREC_FP64, 0, None, None, mod.SVDS_FLAG_SMALLEST)
+    outs = (ctypes.c_void_p * 1)(fake)
+    info = mod.svds_info()
+    assert mod.lib.svds_csr_solve_batched(1, ctypes.byref(A), ctypes.byref(o), outs, outs, outs,
+                                          ctypes.byref(info)) == -4
+
+
 def test_ctypes_structs_match_the_c_header(tmp_path):
     """The binding's ctypes structures have the sizes and field offsets that a
     C compiler gives the header's structs (a field added on one side only

@@ -395,3 +395,43 @@ def test_paper_suite_settings_oracle():
                          v0=inputs.start_vector(A.n, 5))
     assert info.converged
     np.testing.assert_allclose(S, sig[:c["k"]], rtol=1e-10)
+
+
+# --- smallest triplets (Ritz augmentation with the k smallest Ritz values) ---
+
+def _small_cluster_spectrum(N):
+    """Five small values well apart from the rest: [0.01 .. 0.08] then [1, 2]."""
+    return np.concatenate([[0.01, 0.02, 0.035, 0.05, 0.08], np.linspace(1.0, 2.0, N - 5)])
+
+
+@pytest.mark.parametrize("kind", ["sparse", "dense"])
+def test_smallest_triplets_against_lapack(kind):
+    """The k smallest singular values (ascending) equal LAPACK's, the
+    vectors are singular vectors (residuals), and the pairs are orthonormal."""
+    if kind == "sparse":
+        sig = _small_cluster_spectrum(600)
+        A = inputs.prescribed_sparse(120, 5, sig, seed=21)
+        op = as_operator(A)
+        D = op.toarray()
+    else:
+        sig = _small_cluster_spectrum(200)
+        D = inputs.prescribed_dense(260, 200, sig, seed=22)
+        op = D
+    k = 4
+    U, S, V, info = svds(op, k, 20, 1e-10, 3000, v0=inputs.start_vector(D.shape[1], 23), which="smallest")
+    assert info.converged
+    exact = np.sort(np.linalg.svd(D, compute_uv=False))[:k]
+    np.testing.assert_allclose(S, exact, rtol=1e-10)
+    assert np.all(np.diff(S) > 0)
+    r1, r2 = explicit_residuals(op, U, S, V)
+    assert r1.max() <= 1e-12 * sig.max() and (r2 / S).max() <= 2e-10
+    assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-12
+    assert np.abs(V.T @ V - np.eye(k)).max() <= 1e-12
+
+
+def test_smallest_on_diagonal_matrix():
+    """Rectangular diagonal: the smallest nonzero |d| values, exactly."""
+    d = np.concatenate([[0.5, 0.25, 0.125], np.linspace(3.0, 4.0, 147)])
+    A = inputs.diag_matrix(150, 150, d)
+    U, S, V, info = svds(as_operator(A), 3, 12, 1e-10, 5000, v0=inputs.start_vector(150, 24), which="smallest")
+    np.testing.assert_allclose(S, [0.125, 0.25, 0.5], rtol=1e-10)
