@@ -225,6 +225,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed vs FP64 comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs looped comparison")
     ap.add_argument("--no-suite", action="store_true", help="skip the paper's Sparse1-3 suite")
+    ap.add_argument("--no-selective", action="store_true", help="skip the selective re-orthogonalization run")
     ap.add_argument("--paper-dense", action="store_true",
                     help="add Dense1-3 (10,000 x 10,000) to the paper suite (about a minute of host "
                          "time each to generate the Haar factors)")
@@ -328,6 +329,25 @@ def main():
                                   "gbs": round(kc_b[c] / (kc_ms[c] * 1e-3) / 1e9, 1) if kc_ms[c] else None,
                                   "launches": kc_all[c] // args.steps} for c in S.KERNEL_CLASSES}}
 
+    # the same workload with the selective second pass (one projection per
+    # vector unless the DGKS test asks for a second): best of 3 solves
+    sel = None
+    if not args.no_selective:
+        log("selective re-orthogonalization ...")
+        ts, rs = [], None
+        for _ in range(3):
+            t1 = time.perf_counter()
+            rs = solve(S.SVDS_FLAG_SELECTIVE_REORTH)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        ss = rs.S.cpu().numpy()
+        sel = {"ms": round(min(ts) * 1e3, 2), "solves_per_s": round(1 / min(ts), 3),
+               "x_vs_cgs2": round((elapsed / args.steps) / min(ts), 3),
+               "second_passes": rs.info["reorth_second_passes"], "tests": rs.info["reorth_tests"],
+               "cycles": rs.info["cycles"], "status": rs.status, "max_res_true": rs.info["max_res_true"],
+               "sigma_rel_err_vs_oracle": float(np.max(np.abs(ss - golden[:k]) / golden[:k]))
+               if golden is not None else None}
+
     mixed = None
     if not args.no_mixed:
         log("mixed vs FP64 ...")
@@ -353,7 +373,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic", "config": dict(WORKLOAD, parallelism="single GPU"),
            "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "mixed_vs_fp64": mixed,
-           "batched_vs_looped": batched, "paper_suite": suite}
+           "batched_vs_looped": batched, "paper_suite": suite, "selective_reorth": sel}
     print(json.dumps(out), flush=True)
 
 

@@ -79,8 +79,21 @@ enum {
   SVDS_FLAG_ITEMS_1K = 32,    /* work items of at most 1024 nonzeros, not 2048  */
   SVDS_FLAG_UNSORTED = 64,    /* no column-sorted copy of the work items        */
   SVDS_FLAG_NO_PANELS = 128,  /* A^T y over the plain CSR of A^T, no panels     */
-  SVDS_FLAG_SMALLEST = 256    /* the k smallest triplets instead (see below)    */
+  SVDS_FLAG_SMALLEST = 256,   /* the k smallest triplets instead (see below)    */
+  SVDS_FLAG_SELECTIVE_REORTH = 512 /* second CGS pass only when needed (below) */
 };
+
+/* SVDS_FLAG_SELECTIVE_REORTH: the re-orthogonalization of each new vector w
+ * against its basis Q does the second classical Gram-Schmidt pass only when
+ * the first removed more than 1/sqrt(2) of w's norm, i.e. when
+ * |w - Q Q^T w|^2 < |w|^2 / 2 (the test of Daniel, Gragg, Kaufman and
+ * Stewart, 1976).  The paper's operation count for a Lanczos step (eq. (8))
+ * counts one projection per vector; the default (flag off) always does two.
+ * The decision is taken on the device in the basis precision from norms
+ * accumulated by the first two passes, so the passes over Q drop from three
+ * to two whenever it skips.  info->reorth_tests and
+ * info->reorth_second_passes count the tests and the second passes run.
+ * FP64 and mixed single solves; EUNSUPPORTED in the batched solver. */
 
 /* SVDS_FLAG_SMALLEST: the bidiagonalization approximates the smallest
  * singular values as well as the largest (Sec. 1).  Each cycle keeps the k
@@ -204,6 +217,8 @@ typedef struct {
   int32_t graph_captures;          /* SVDS_FLAG_GRAPH: cycle graphs captured */
   int32_t graph_replays;           /* ... and cycles run by replaying one    */
   svds_tuning tuning;              /* SVDS_FLAG_AUTOTUNE choices of the plan */
+  int32_t reorth_tests;            /* SVDS_FLAG_SELECTIVE_REORTH: tests made */
+  int32_t reorth_second_passes;    /* ... and second passes run             */
 } svds_info;
 
 typedef struct svds_plan svds_plan;

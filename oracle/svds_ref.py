@@ -27,6 +27,11 @@ Readings of the paper used here (where it is silent or ambiguous):
   by CGS2 against the same basis, normalised, and 0 is stored in T.
 * Signs: each output pair (u_j, v_j) is flipped so that the entry of v_j of
   largest magnitude (lowest index on ties) is positive.
+* Selective second pass (``selective=True``; eq. (8) counts one projection
+  per vector): after h = Q^T w, w1 = w - Q h, the second pass runs only when
+  |w1|^2 < |w|^2 / 2 (Daniel-Gragg-Kaufman-Stewart test); otherwise w1 is
+  the re-orthogonalised vector.  Breakdown replacement vectors still get
+  both passes.
 * Smallest triplets (``which="smallest"``; Sec. 1 notes that the
   bidiagonalization also approximates the smallest singular values): the
   same cycle with the k smallest Ritz triplets of T kept instead of the k
@@ -61,6 +66,8 @@ class SvdsInfo:
     nconv: int = 0
     res_est: np.ndarray = field(default_factory=lambda: np.zeros(0))
     sigma_est: float = 0.0
+    reorth_tests: int = 0          # selective mode: tests made
+    reorth_second_passes: int = 0  # ... and second passes run
 
 
 class _Op:
@@ -91,21 +98,40 @@ def cgs2(w: np.ndarray, Q: np.ndarray) -> np.ndarray:
     return w
 
 
+def cgs_selective(w: np.ndarray, Q: np.ndarray):
+    """One classical Gram-Schmidt pass, and a second one only when the first
+    removed more than 1/sqrt(2) of the norm (|w1|^2 < |w|^2 / 2).
+    Returns (vector, second pass taken)."""
+    if Q.shape[1] == 0:
+        return w, False
+    w1 = w - Q @ (Q.T @ w)
+    if float(w1 @ w1) >= 0.5 * float(w @ w):
+        return w1, False
+    return w1 - Q @ (Q.T @ w1), True
+
+
 class _State:
     """Workspace of one solve: U (m x p), V (n x (p+1)), T ((p+1) x (p+1))."""
 
-    def __init__(self, op: _Op, p: int, seed: int, info: SvdsInfo):
+    def __init__(self, op: _Op, p: int, seed: int, info: SvdsInfo, selective: bool = False):
         self.op = op
         self.p = p
         self.seed = seed
         self.info = info
+        self.selective = selective
         self.U = np.zeros((op.m, p), order="F")
         self.V = np.zeros((op.n, p + 1), order="F")
         self.T = np.zeros((p + 1, p + 1))
 
     def _finish(self, w, Q):
-        """CGS2 against Q, norm, breakdown handling; returns (vector, norm)."""
-        w = cgs2(w, Q)
+        """CGS2 (or the selective form) against Q, norm, breakdown handling;
+        returns (vector, norm)."""
+        if self.selective and Q.shape[1] > 0:
+            w, second = cgs_selective(w, Q)
+            self.info.reorth_tests += 1
+            self.info.reorth_second_passes += int(second)
+        else:
+            w = cgs2(w, Q)
         nrm = float(np.linalg.norm(w))
         if nrm <= BREAKDOWN_REL * self.info.sigma_est:
             self.info.breakdowns += 1
@@ -167,7 +193,8 @@ def sign_normalize(U, V):
 
 
 def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
-         v0: np.ndarray | None = None, seed: int = 0, callback=None, which: str = "largest"):
+         v0: np.ndarray | None = None, seed: int = 0, callback=None, which: str = "largest",
+         selective: bool = False):
     """k largest (``which="largest"``, descending) or smallest
     (``which="smallest"``, ascending) singular triplets of A (scipy sparse
     matrix or dense array).
@@ -189,7 +216,7 @@ def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
         raise ValueError(which)
     info = SvdsInfo()
     op = _Op(A, info)
-    st = _State(op, p, seed, info)
+    st = _State(op, p, seed, info, selective)
 
     # Alg. 1 step 1: v_1 = randn / norm.
     v = np.asarray(v0, dtype=np.float64).copy() if v0 is not None else normal_vector(n, seed, 0)

@@ -76,12 +76,13 @@ __global__ __launch_bounds__(256) void reduce_cols_kernel(const T *__restrict__ 
 // Each wave walks tiles of 64 N rows of its block's slab (N rows per lane)
 // keeping 8 column accumulators per lane (narrow groups and many blocks
 // stream fastest on MI355X; 32-column groups reach half the rate).
-// part: [j][nslab].
+// part: [j][nslab]; with normw the blocks of column group 0 also write the
+// partials of |w|^2 as column j (read by the selective second pass).
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restrict__ Q, int64_t ldq,
                                                               int64_t L, int j, const T *__restrict__ w,
-                                                              T *__restrict__ part) {
+                                                              T *__restrict__ part, int normw) {
   constexpr int NW = CGS_THREADS / WAVE;
   __shared__ T red[NW][CGS_PCG + 1];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
@@ -93,7 +94,8 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restri
   const int64_t per = ceil_div(tiles, nslab);
   const int64_t t0 = slab * per, t1 = min(tiles, t0 + per);
   const T *Qc = Q + c0 * ldq;
-  T acc[CGS_PCG];
+  const bool dn = normw && blockIdx.y == 0;
+  T acc[CGS_PCG], nw = 0;
 #pragma unroll
   for (int c = 0; c < CGS_PCG; ++c) acc[c] = 0;
   for (int64_t t = t0 + wv; t < t1; t += NW) {
@@ -101,6 +103,9 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restri
     if (r < L) {
       T wr[N];
       load_rows<T, N>(w + r, L - r, wr);
+      if (dn)
+#pragma unroll
+        for (int i = 0; i < N; ++i) nw += wr[i] * wr[i];
 #pragma unroll
       for (int c = 0; c < CGS_PCG; ++c) {
         if (c < nc) {
@@ -117,11 +122,20 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restri
     const T s = wave_sum(acc[c]);
     if (lane == 0) red[wv][c] = s;
   }
+  if (dn) {
+    const T s = wave_sum(nw);
+    if (lane == 0) red[wv][CGS_PCG] = s;
+  }
   __syncthreads();
   if (tid < nc) {
     T s = 0;
     for (int v = 0; v < NW; ++v) s += red[v][tid];
     part[static_cast<int64_t>(c0 + tid) * nslab + slab] = s;
+  }
+  if (dn && tid == CGS_PCG) {
+    T s = 0;
+    for (int v = 0; v < NW; ++v) s += red[v][CGS_PCG];
+    part[static_cast<int64_t>(j) * nslab + slab] = s;
   }
 }
 
@@ -135,13 +149,14 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restri
 // occupancy high: measured on MI355X, two rows per lane with 12-16 columns
 // per wave stream at a third of the rate or less.
 // Bases wider than 16 * CPW use a separate update pass plus cgs_proj instead.
-// part: [j][nblk].
+// part: [j][nblk]; with normw1 also the partials of |w1|^2 as column j.
 // ---------------------------------------------------------------------------
 template <typename T, int CPW, bool PF, int N>
 __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict__ Q, int64_t ldq,
                                                            int64_t L, int j, const T *__restrict__ w,
                                                            const T *__restrict__ h1,
-                                                           T *__restrict__ w1out, T *__restrict__ part) {
+                                                           T *__restrict__ w1out, T *__restrict__ part,
+                                                           int normw1) {
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ T xch[2][16][WAVE * N];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
@@ -159,7 +174,7 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict_
   const int64_t t1 = min(tiles, t0 + per);
   const T *Qc = Q + c0 * ldq;
   T acc[CPW], q[CPW][N], qn[CPW][N];
-  T wn[N];
+  T wn[N], nw1 = 0;
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
     acc[c] = 0;
@@ -206,6 +221,9 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict_
       w1[i] = (r + i < L) ? wr[i] - u : T(0);
     }
     if (wv == 0 && r < L) store_rows<T, N>(w1out + r, L - r, w1);
+    if (normw1 && wv == 0)
+#pragma unroll
+      for (int i = 0; i < N; ++i) nw1 += w1[i] * w1[i];
 #pragma unroll
     for (int c = 0; c < CPW; ++c)
 #pragma unroll
@@ -217,6 +235,24 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict_
     const T s = wave_sum(acc[c]);
     if (lane == 0 && c < nc) part[static_cast<int64_t>(c0 + c) * nblk + blk] = s;
   }
+  if (normw1 && wv == 0) {
+    const T s = wave_sum(nw1);
+    if (lane == 0) part[static_cast<int64_t>(j) * nblk + blk] = s;
+  }
+}
+
+// Selective second pass: with sel non-null the pass is skipped (out = w1, no
+// read of Q) when |w1|^2 >= |w|^2 / 2, i.e. the first projection removed at
+// most 1/sqrt(2) of w's norm (the test of Daniel, Gragg, Kaufman and Stewart,
+// 1976); sel[0] = |w|^2 and h[j] = |w1|^2 come from the first two passes.
+// Every block takes the same decision from the same two values; block 0
+// counts the passes that ran in *ran.
+template <typename T>
+__device__ __forceinline__ int cgs_second_pass_width(int j, const T *h, const T *sel, int *ran) {
+  if (!sel) return j;
+  const bool run = h[j] < T(0.5) * sel[0];
+  if (run && ran && blockIdx.x == 0 && threadIdx.x == 0) *ran += 1;
+  return run ? j : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -226,10 +262,12 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict_
 template <typename T, int N>
 __global__ __launch_bounds__(CGS_THREADS) void cgs_upd_norm_kernel(
     const T *__restrict__ Q, int64_t ldq, int64_t L, int j, const T *__restrict__ w1,
-    const T *__restrict__ h, T *__restrict__ out, double *__restrict__ npart) {
+    const T *__restrict__ h, T *__restrict__ out, double *__restrict__ npart, const T *__restrict__ sel,
+    int *__restrict__ ran) {
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ double sh_d[CGS_THREADS / WAVE];
   const int tid = threadIdx.x;
+  j = cgs_second_pass_width(j, h, sel, ran);
   for (int c = tid; c < j; c += CGS_THREADS) sh_h[c] = h[c];
   __syncthreads();
   double nrm2 = 0;
@@ -287,8 +325,10 @@ template <typename T, int N>
 __global__ __launch_bounds__(1024) void cgs_tile_upd_kernel(const T *__restrict__ Q, int64_t ldq, int64_t L,
                                                             int j, const T *__restrict__ w1,
                                                             const T *__restrict__ h, T *__restrict__ out,
-                                                            double *__restrict__ npart) {
+                                                            double *__restrict__ npart, const T *__restrict__ sel,
+                                                            int *__restrict__ ran) {
   constexpr int CPW = CGS_TILE_CPW;
+  j = cgs_second_pass_width(j, h, sel, ran);
   __shared__ T sh_h[CGS_TILE_MAXJ];
   __shared__ T xch[16][WAVE * N];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;

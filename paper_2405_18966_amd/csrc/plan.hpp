@@ -127,7 +127,7 @@ struct CycleGraphs {
   uint64_t ver[2][2] = {};         // work-list version captured (0: none)
   int next_cur[2][2] = {};         // buffer after the body
   double dbytes[2][2][SVDS_KC_COUNT] = {}, dflops[2][2][SVDS_KC_COUNT] = {};
-  int64_t dlaunch[2][2][SVDS_KC_COUNT] = {}, dspmv[2][2] = {}, dspmvT[2][2] = {};
+  int64_t dlaunch[2][2][SVDS_KC_COUNT] = {}, dspmv[2][2] = {}, dspmvT[2][2] = {}, dreorth[2][2] = {};
   int64_t captures = 0, replays = 0;
   void drop(int t, int c) {
     if (exec[t][c]) (void)hipGraphExecDestroy(exec[t][c]);

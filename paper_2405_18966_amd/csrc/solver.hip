@@ -279,6 +279,8 @@ struct svds_plan {
   int cgs_slab_shift = 0, cgs_cpw = 0;
   svds_tuning tuning{};  // what the tuner chose and measured
   bool smallest = false;  // SVDS_FLAG_SMALLEST: k smallest triplets, ascending
+  bool selective = false;  // SVDS_FLAG_SELECTIVE_REORTH: second CGS pass only when needed
+  int64_t reorth_calls = 0;  // re-orthogonalizations with the selective test
 };
 
 namespace svds {
@@ -382,7 +384,7 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
 // ---------------------------------------------------------------------------
 template <typename TB>
 static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int64_t L, int j,
-                           const TB *w, TB *h, int kc) {
+                           const TB *w, TB *h, int kc, int normw = 0) {
   const double sb = sizeof(TB);
   int nslab, ngc;
   cgs_proj_shape(L, j, nslab, ngc);
@@ -395,25 +397,27 @@ static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int
   ACC_BEFORE_ATT(kc);
   if (cgs_rows_per_lane<TB>(Q, ldq, w, nullptr, nullptr) == NV)
     klaunch(P->acc, true, true, cgs_proj_kernel<TB, NV>, dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
-            L, j, w, part);
+            L, j, w, part, normw);
   else
     klaunch(P->acc, true, true, cgs_proj_kernel<TB, 1>, dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
-            L, j, w, part);
+            L, j, w, part, normw);
   LAUNCH_CHECK();
   ACC_AFTER(kc, sb * L * j + sb * L, 2.0 * L * j);
+  // h[0:j], and with normw h[j] = |w|^2
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
-  hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j, 4)), dim3(256), 0, P->stream, part,
-                     static_cast<int64_t>(nslab), nslab, j, h);
+  hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j + normw, 4)), dim3(256), 0, P->stream, part,
+                     static_cast<int64_t>(nslab), nslab, j + normw, h);
   LAUNCH_CHECK();
-  ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * j * nslab, 0.0);
+  ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * (j + normw) * nslab, 0.0);
   return SVDS_OK;
 }
 
 // out = w - Q h, with squared-norm partials in npart when non-null; returns
 // the number of partials.  Short vectors take the tile-per-block kernel.
+// sel/ran: the selective second pass (see cgs_second_pass_width).
 template <typename TB>
 static int launch_upd_norm(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, int j, const TB *w, const TB *h,
-                           TB *out, double *npart) {
+                           TB *out, double *npart, const TB *sel = nullptr, int *ran = nullptr) {
   constexpr int NV = 16 / sizeof(TB);
   const bool vec = cgs_rows_per_lane<TB>(Q, ldq, w, out, nullptr) == NV;
   const int nr = vec ? NV : 1;
@@ -422,19 +426,19 @@ static int launch_upd_norm(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, in
     const int nw = static_cast<int>(ceil_div(j, CGS_TILE_CPW));
     if (vec)
       klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, NV>, dim3(nt), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j,
-              w, h, out, npart);
+              w, h, out, npart, sel, ran);
     else
       klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, 1>, dim3(nt), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j,
-              w, h, out, npart);
+              w, h, out, npart, sel, ran);
     return nt;
   }
   const int nn = cgs_updnorm_blocks(L);
   if (vec)
     klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, NV>, dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
-            w, h, out, npart);
+            w, h, out, npart, sel, ran);
   else
     klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, 1>, dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
-            w, h, out, npart);
+            w, h, out, npart, sel, ran);
   return nn;
 }
 
@@ -447,9 +451,12 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
   constexpr int NV = 16 / sizeof(TB);
   const bool vec = cgs_rows_per_lane<TB>(Q, ldq, w, w1, out) == NV;
   int rc;
+  // selective second pass: |w|^2 and |w1|^2 ride along as column j of the
+  // first two passes' reductions
+  const int sel = (P->selective && j > 0) ? 1 : 0;
   if (j > 0) {
     // pass 1: h1 = Q^T w
-    if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ))) return rc;
+    if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ, sel))) return rc;
     // pass 2: w1 = w - Q h1, h2 = Q^T w1
     int cpw = cgs_fused_cpw(j, static_cast<int>(sizeof(TB)));
     // a forced width must keep the block within 16 waves
@@ -462,38 +469,41 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
       // register pressure); FP32 bases with 10 columns take 16-byte rows
       if (cpw == 8)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 8, true, 1>, dim3(nb), dim3(nw * WAVE), 0, P->stream, Q,
-                ldq, L, j, w, h1, w1, part);
+                ldq, L, j, w, h1, w1, part, sel);
       else if (sizeof(TB) == 8)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, true, 1>, dim3(nb), dim3(nw * WAVE), 0, P->stream,
-                Q, ldq, L, j, w, h1, w1, part);
+                Q, ldq, L, j, w, h1, w1, part, sel);
       else if (vec)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, NV>, dim3(nb), dim3(nw * WAVE), 0, P->stream,
-                Q, ldq, L, j, w, h1, w1, part);
+                Q, ldq, L, j, w, h1, w1, part, sel);
       else
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, 1>, dim3(nb), dim3(nw * WAVE), 0, P->stream,
-                Q, ldq, L, j, w, h1, w1, part);
+                Q, ldq, L, j, w, h1, w1, part, sel);
       LAUNCH_CHECK();
       ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 4.0 * L * j);
       ACC_BEFORE(SVDS_KC_CGS_REDUCE);
-      hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j, 4)), dim3(256), 0, P->stream, part,
-                         static_cast<int64_t>(nb), nb, j, h2);
+      hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j + sel, 4)), dim3(256), 0, P->stream, part,
+                         static_cast<int64_t>(nb), nb, j + sel, h2);
       LAUNCH_CHECK();
-      ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * j * nb, 0.0);
+      ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * (j + sel) * nb, 0.0);
     } else {
       // wide basis: separate update and projection passes
       ACC_BEFORE_ATT(SVDS_KC_CGS_UPDPROJ);
       launch_upd_norm<TB>(P, Q, ldq, L, j, w, h1, w1, nullptr);
       LAUNCH_CHECK();
       ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 2.0 * L * j);
-      if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w1, h2, SVDS_KC_CGS_UPDPROJ))) return rc;
+      if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w1, h2, SVDS_KC_CGS_UPDPROJ, sel))) return rc;
     }
     src = w1;
   }
-  // pass 3: out = w1 - Q h2 and its norm
+  // pass 3: out = w1 - Q h2 and its norm (selective: only when the test asks
+  // for it; the accounting then counts the vector traffic alone)
   ACC_BEFORE_ATT(SVDS_KC_CGS_UPDNORM);
-  const int nn = launch_upd_norm<TB>(P, Q, ldq, L, j, src, h2, out, s.npart);
+  const int nn = launch_upd_norm<TB>(P, Q, ldq, L, j, src, h2, out, s.npart, sel ? h1 + j : nullptr,
+                                     sel ? s.bd + 1 : nullptr);
   LAUNCH_CHECK();
-  ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * j + 2 * sb * L, 2.0 * L * j + 2.0 * L);
+  ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * (sel ? 0 : j) + 2 * sb * L, 2.0 * L * (sel ? 0 : j) + 2.0 * L);
+  if (sel) ++P->reorth_calls;
   FinishArgs fa{t_entry, xs, s.sigma_est, s.bd, P->opts.seed};
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
   hipLaunchKernelGGL((finish_norm_kernel<TB>), dim3(1), dim3(CGS_THREADS), 0, P->stream, s.npart, nn,
@@ -653,7 +663,7 @@ static int run_graphed(svds_plan *P, Lanczos<TB> &Lz, uint64_t ver, Body &&body)
     std::memcpy(b0, acc.bytes, sizeof b0);
     std::memcpy(f0, acc.flops, sizeof f0);
     std::memcpy(l0, acc.launches, sizeof l0);
-    const int64_t s0 = P->n_spmv, st0 = P->n_spmvT;
+    const int64_t s0 = P->n_spmv, st0 = P->n_spmvT, rc0 = P->reorth_calls;
     const bool timing = acc.timing;
     hipStream_t user = P->stream;
     acc.timing = false;  // no event records inside a capture
@@ -685,8 +695,10 @@ static int run_graphed(svds_plan *P, Lanczos<TB> &Lz, uint64_t ver, Body &&body)
     }
     G.dspmv[t][c] = P->n_spmv - s0;
     G.dspmvT[t][c] = P->n_spmvT - st0;
+    G.dreorth[t][c] = P->reorth_calls - rc0;
     P->n_spmv = s0;
     P->n_spmvT = st0;
+    P->reorth_calls = rc0;
     G.next_cur[t][c] = Lz.cur;
     Lz.cur = c;
     if (!rc) {
@@ -713,6 +725,7 @@ static int run_graphed(svds_plan *P, Lanczos<TB> &Lz, uint64_t ver, Body &&body)
   }
   P->n_spmv += G.dspmv[t][c];
   P->n_spmvT += G.dspmvT[t][c];
+  P->reorth_calls += G.dreorth[t][c];
   Lz.cur = G.next_cur[t][c];
   return SVDS_OK;
 }
@@ -776,6 +789,7 @@ static int fill_defaults(const svds_opts *o, int64_t m, int64_t n, svds_plan *P)
   P->stream = static_cast<hipStream_t>(o->stream);
   P->mixed = o->precision == SVDS_PREC_MIXED;
   P->smallest = (o->flags & SVDS_FLAG_SMALLEST) != 0;
+  P->selective = (o->flags & SVDS_FLAG_SELECTIVE_REORTH) != 0;
   if (o->precision != SVDS_PREC_FP64 && o->precision != SVDS_PREC_MIXED) return SVDS_EINVAL;
   // the FP32 phase cannot resolve values below ~1e-7 sigma_1
   if (P->smallest && P->mixed) return SVDS_EUNSUPPORTED;
@@ -1514,6 +1528,7 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
   P->n_spmv = P->n_spmvT = 0;
   P->cycles32 = P->cycles64 = P->jac_sweeps = 0;
   const int64_t cap0 = P->graphs.captures, rep0 = P->graphs.replays;
+  P->reorth_calls = 0;
   HIP_TRY(hipMemsetAsync(P->sc.sigma_est, 0, sizeof(double), P->stream));
   HIP_TRY(hipMemsetAsync(P->sc.bd, 0, 4 * sizeof(int), P->stream));
   HIP_TRY(hipMemsetAsync(P->sc.T, 0, sizeof(double) * (P->p + 1) * (P->p + 1), P->stream));
@@ -1554,7 +1569,9 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
   int bd = 0;
   HIP_TRY(hipMemcpy(hs.data(), P->sc.sig, sizeof(double) * k, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(hres.data(), P->sc.res, sizeof(double) * k, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(&bd, P->sc.bd, sizeof(int), hipMemcpyDeviceToHost));
+  int bd2[2] = {0, 0};  // breakdowns, selective second passes run
+  HIP_TRY(hipMemcpy(bd2, P->sc.bd, 2 * sizeof(int), hipMemcpyDeviceToHost));
+  bd = bd2[0];
   if (!(P->opts.flags & SVDS_FLAG_NO_RESIDUALS)) {
     HIP_TRY(hipMemcpy(hav.data(), P->sc.resid_av, sizeof(double) * k, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(hatu.data(), P->sc.resid_atu, sizeof(double) * k, hipMemcpyDeviceToHost));
@@ -1598,6 +1615,8 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
     info->workspace_bytes = static_cast<int64_t>(P->arena.size + P->op.pbuf_bytes);
     info->graph_captures = static_cast<int32_t>(P->graphs.captures - cap0);
     info->graph_replays = static_cast<int32_t>(P->graphs.replays - rep0);
+    info->reorth_tests = static_cast<int32_t>(P->reorth_calls);
+    info->reorth_second_passes = bd2[1];
     info->tuning = P->tuning;
   }
   return conv ? SVDS_OK : SVDS_NOT_CONVERGED;

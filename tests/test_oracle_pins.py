@@ -435,3 +435,36 @@ def test_smallest_on_diagonal_matrix():
     A = inputs.diag_matrix(150, 150, d)
     U, S, V, info = svds(as_operator(A), 3, 12, 1e-10, 5000, v0=inputs.start_vector(150, 24), which="smallest")
     np.testing.assert_allclose(S, [0.125, 0.25, 0.5], rtol=1e-10)
+
+
+# --- selective second pass (DGKS test) ----------------------------------------
+
+def test_selective_pass_decision_and_orthogonality():
+    """A vector mostly inside span(Q) needs the second pass; a random one
+    against a few columns does not.  Either way the result is orthogonal to
+    Q to working precision and the component outside span(Q) is kept."""
+    rng = np.random.default_rng(31)
+    Q = svds_ref.np.linalg.qr(rng.standard_normal((4000, 30)))[0]
+    z = rng.standard_normal(4000)
+    zp = z - Q @ (Q.T @ z)
+    w_in = Q @ rng.standard_normal(30) * 1e6 + zp  # |w1| / |w| ~ 1e-5
+    x, second = svds_ref.cgs_selective(w_in, Q)
+    assert second
+    assert np.abs(Q.T @ x).max() <= 1e-13 * np.linalg.norm(x)
+    np.testing.assert_allclose(x, zp, rtol=0, atol=1e-8 * np.linalg.norm(zp))
+    x, second = svds_ref.cgs_selective(z, Q)
+    assert not second
+    assert np.abs(Q.T @ x).max() <= 1e-13 * np.linalg.norm(x)
+
+
+def test_selective_solve_matches_lapack_and_stays_orthogonal():
+    A = inputs.config_matrix(1)
+    op = as_operator(A)
+    v0 = inputs.start_vector(A.n, inputs.CONFIG_SEEDS[1] + 1)
+    U, S, V, info = svds(op, 10, 30, 1e-10, 3000, v0=v0, selective=True)
+    assert info.converged and info.reorth_tests > 0
+    assert info.reorth_second_passes < info.reorth_tests
+    exact = np.linalg.svd(op.toarray(), compute_uv=False)[:10]
+    np.testing.assert_allclose(S, exact, rtol=1e-10)
+    assert np.abs(U.T @ U - np.eye(10)).max() <= 1e-12
+    assert np.abs(V.T @ V - np.eye(10)).max() <= 1e-12
