@@ -73,7 +73,10 @@ int svds_op_small_svd(int32_t p, int32_t k, double tol, double *T, double *Uk, d
 
 /* Restart rotation (Alg. 2 steps 8 and 16): out(:, 0:kc) = B(:, 0:pc) Y,
  * B L x pc of `btype` (F64/F32, ld ldb), Y pc x kc FP64 (ld ldy),
- * out L x kc FP64 (ld ldo). */
+ * out L x kc FP64 (ld ldo).  Runs on the matrix cores (FP64 or FP32
+ * MFMA, as the solver does); btype | SVDS_ROTATE_VECTOR selects the vector
+ * FMA kernel instead (same arithmetic type, another summation order). */
+enum { SVDS_ROTATE_VECTOR = 256 };
 int svds_op_rotate(int64_t L, int32_t pc, int32_t kc, const void *B, int64_t ldb, int32_t btype,
                    const double *Y, int64_t ldy, double *out, int64_t ldo, void *stream);
 

@@ -234,17 +234,18 @@ extern "C" int svds_op_rotate(int64_t L, int32_t pc, int32_t kc, const void *B, 
   SVDS_ABI_TRY
   if (L < 1 || pc < 1 || kc < 1 || !B || !Y || !out || ldb < L || ldy < pc || ldo < L) return SVDS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool mfma = !(btype & SVDS_ROTATE_VECTOR);
+  btype &= ~SVDS_ROTATE_VECTOR;
+  if (btype != SVDS_F64 && btype != SVDS_F32) return SVDS_EUNSUPPORTED;
   Scratch yt;
   HIP_TRY(hipMalloc(&yt.p, sizeof(double) * rot_yt_doubles(pc, kc)));
   double *Yt = static_cast<double *>(yt.p);
   if (btype == SVDS_F64)
     HIP_TRY((rotate_launch<double, double>(st, L, pc, kc, static_cast<const double *>(B), ldb, Y, ldy, Yt,
-                                           out, ldo)));
-  else if (btype == SVDS_F32)
-    HIP_TRY((rotate_launch<float, double>(st, L, pc, kc, static_cast<const float *>(B), ldb, Y, ldy, Yt,
-                                          out, ldo)));
+                                           out, ldo, mfma)));
   else
-    return SVDS_EUNSUPPORTED;
+    HIP_TRY((rotate_launch<float, double>(st, L, pc, kc, static_cast<const float *>(B), ldb, Y, ldy, Yt,
+                                          out, ldo, mfma)));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   return SVDS_OK;

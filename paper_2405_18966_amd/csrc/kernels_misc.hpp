@@ -17,8 +17,8 @@ namespace svds {
 // kc <= 64).  Y is first transposed into a row-major, zero-padded copy Yt;
 // the kernel's loads of Yt are uniform across the wave (same q, same c) and
 // compile to scalar loads, so no LDS is involved.  Accumulation in q order.
-// This vector kernel serves FP32 bases (and their FP64 outputs); FP64 bases
-// use rotate_mfma_kernel below.
+// The solver uses the matrix-core kernel below; this vector kernel is kept
+// as the reference form (svds_op_rotate with its `vector` switch).
 // ---------------------------------------------------------------------------
 constexpr int ROT_THREADS = 256;
 constexpr int ROT_KC = 64;  // output columns per launch
@@ -74,72 +74,83 @@ static __global__ __launch_bounds__(ROT_THREADS) void rotate_kernel(int64_t L, i
 }
 
 // ---------------------------------------------------------------------------
-// FP64 rotation on the matrix cores (v_mfma_f64_16x16x4f64: D(16x16) +=
-// A(16x4) B(4x16)).  A block of ROTM_WAVES waves covers 16 ROTM_WAVES rows of
-// B; each wave owns one 16-row tile and NT 16-column tiles of out, and steps
-// through pc four columns of B at a time (four steps per loop iteration, all
-// their loads issued first): lane l loads A(l % 16, l / 16) =
-// B(r0 + l % 16, q + l / 16) and the B-operand entries
-// Yt(q + l / 16, 16 t + l % 16); it holds D(4 i + l / 16, l % 16) in
-// accumulator entry i (measured on gfx950 with one-hot A operands).  The
-// tile is written back through LDS so that each store covers 16 consecutive
-// rows of a column.  Out-of-range rows and k-steps read as 0.
-// Measured on MI355X for a 1,000,000 x 150 basis and 50 columns: ~610 us,
-// the same rate as the one-row-per-thread vector kernel (the strided reads
-// of B's row tiles, not the arithmetic, bound both); double-buffered loads
-// and four row tiles per wave were slower.
+// Rotation on the matrix cores: v_mfma_f64_16x16x4f64 for FP64 bases,
+// v_mfma_f32_16x16x4f32 for FP32 bases (FP32 accumulation, as the vector
+// kernel); D(16x16) += A(16x4) B(4x16).  A block of ROTM_WAVES waves covers
+// 16 ROTM_WAVES rows of B; each wave owns one 16-row tile and NT 16-column
+// tiles of out, and steps through pc four columns of B at a time (four steps
+// per loop iteration, all their loads issued first): lane l loads
+// A(l % 16, l / 16) = B(r0 + l % 16, q + l / 16) and the B-operand entries
+// Yt(q + l / 16, 16 t + l % 16).  Accumulator entry i of lane l holds
+// D(4 i + l / 16, l % 16) for FP64 and D(4 (l / 16) + i, l % 16) for FP32
+// (both measured on gfx950 with one-hot A operands).  The tile is written
+// back through LDS so that each store covers 16 consecutive rows of a
+// column.  Out-of-range rows and k-steps read as 0.
+// Measured on MI355X for a 1,000,000 x 150 FP64 basis and 50 columns: ~610
+// us, the same rate as the one-row-per-thread vector kernel (the strided
+// reads of B's row tiles, not the arithmetic, bound both); double-buffered
+// loads and four row tiles per wave were slower.
 // ---------------------------------------------------------------------------
 constexpr int ROTM_WAVES = 4;
 typedef double rot_v4d __attribute__((ext_vector_type(4)));
+typedef float rot_v4f __attribute__((ext_vector_type(4)));
 
-template <int NT>
+template <typename TB, typename TO, int NT>
 static __global__ __launch_bounds__(ROTM_WAVES * WAVE) void rotate_mfma_kernel(
-    int64_t L, int pc, int kcv, const double *__restrict__ B, int64_t ldb, const double *__restrict__ Yt,
-    int ldyt, double *__restrict__ out, int64_t ldo) {
-  __shared__ double tile[ROTM_WAVES][16 * NT][17];  // [wave][column][row], padded
+    int64_t L, int pc, int kcv, const TB *__restrict__ B, int64_t ldb, const double *__restrict__ Yt,
+    int ldyt, TO *__restrict__ out, int64_t ldo) {
+  constexpr bool F64 = sizeof(TB) == 8;
+  using acc_t = typename std::conditional<F64, rot_v4d, rot_v4f>::type;
+  __shared__ TB tile[ROTM_WAVES][16 * NT][17];  // [wave][column][row], padded
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const int64_t r0 = (static_cast<int64_t>(blockIdx.x) * ROTM_WAVES + wv) * 16;
   const bool live = r0 < L;  // wave-uniform; every wave reaches the barrier
   const int li = lane & 15, lk = lane >> 4;
   const int64_t ra = r0 + li;
   const bool rin = ra < L;
-  rot_v4d acc[NT];
+  acc_t acc[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = rot_v4d{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < NT; ++t) acc[t] = acc_t{TB(0), TB(0), TB(0), TB(0)};
   for (int q = 0; live && q < pc; q += 16) {
-    double a[4], b[4][NT];
+    TB a[4], b[4][NT];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int qk = q + 4 * u + lk;
       const bool kin = qk < pc;
-      a[u] = (rin && kin) ? B[static_cast<int64_t>(qk) * ldb + ra] : 0.0;
+      a[u] = (rin && kin) ? B[static_cast<int64_t>(qk) * ldb + ra] : TB(0);
       const double *y = Yt + static_cast<int64_t>(kin ? qk : 0) * ldyt + li;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b[u][t] = kin ? y[16 * t] : 0.0;
+      for (int t = 0; t < NT; ++t) b[u][t] = kin ? static_cast<TB>(y[16 * t]) : TB(0);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
+      for (int t = 0; t < NT; ++t) {
+        if constexpr (F64)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
+        else
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u][t], acc[t], 0, 0, 0);
+      }
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) tile[wv][16 * t + li][4 * i + lk] = acc[t][i];
+    for (int i = 0; i < 4; ++i) tile[wv][16 * t + li][F64 ? 4 * i + lk : 4 * lk + i] = acc[t][i];
   __syncthreads();
   // lanes: row li of the tile, columns lk, lk + 4, ...
   const int64_t row = r0 + li;
   if (live && row < L)
     for (int c = lk; c < 16 * NT; c += 4)
-      if (c < kcv) out[static_cast<int64_t>(c) * ldo + row] = tile[wv][c][li];
+      if (c < kcv) out[static_cast<int64_t>(c) * ldo + row] = static_cast<TO>(tile[wv][c][li]);
 }
 
 // Enqueues Yt = Y^T (padded) and the launches of all column groups.  Yt holds
-// rot_yt_doubles(pc, kc) doubles of device scratch.  An FP64 basis with FP64
-// output runs on the matrix cores (rotate_mfma_kernel).
+// rot_yt_doubles(pc, kc) doubles of device scratch.  use_mfma: the matrix
+// core kernel (default), else the vector kernel.
 template <typename TB, typename TO>
 inline hipError_t rotate_launch(hipStream_t st, int64_t L, int pc, int kc, const TB *B, int64_t ldb,
-                                const double *Y, int64_t ldy, double *Yt, TO *out, int64_t ldo) {
+                                const double *Y, int64_t ldy, double *Yt, TO *out, int64_t ldo,
+                                bool use_mfma = true) {
   const int ldyt = rot_ldyt(kc);
   hipLaunchKernelGGL(rot_transpose_kernel, dim3(static_cast<unsigned>(
                                                std::min<int64_t>(1024, ceil_div(rot_yt_doubles(pc, kc), 256)))),
@@ -149,11 +160,11 @@ inline hipError_t rotate_launch(hipStream_t st, int64_t L, int pc, int kc, const
     const int kcv = std::min(ROT_KC, kc - g0);
     const double *yt = Yt + g0;
     TO *o = out + g0 * ldo;
-    if constexpr (std::is_same<TB, double>::value && std::is_same<TO, double>::value) {
+    if (use_mfma) {
       const dim3 gm(static_cast<unsigned>(ceil_div(L, 16 * ROTM_WAVES)));
 #define ROTM_GO(NT)                                                                                          \
-  hipLaunchKernelGGL((rotate_mfma_kernel<NT>), gm, dim3(ROTM_WAVES * WAVE), 0, st, L, pc, kcv, B, ldb, yt, \
-                     ldyt, o, ldo)
+  hipLaunchKernelGGL((rotate_mfma_kernel<TB, TO, NT>), gm, dim3(ROTM_WAVES * WAVE), 0, st, L, pc, kcv, B, ldb, \
+                     yt, ldyt, o, ldo)
       if (kcv <= 16) ROTM_GO(1);
       else if (kcv <= 32) ROTM_GO(2);
       else if (kcv <= 48) ROTM_GO(3);

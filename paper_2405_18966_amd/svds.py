@@ -335,12 +335,16 @@ def svds_op_small_svd(T: torch.Tensor, p: int, k: int, tol: float, stream=None):
     return Uk, Vext, sig, res, rho, list(flags)
 
 
-def svds_op_rotate(B: torch.Tensor, pc: int, Y: torch.Tensor, kc: int, stream=None):
+SVDS_ROTATE_VECTOR = 256
+
+
+def svds_op_rotate(B: torch.Tensor, pc: int, Y: torch.Tensor, kc: int, stream=None, vector: bool = False):
     """B: (pc, L) tensor (column-major L x pc), Y: (kc, pc) FP64 (column-major
-    pc x kc).  Returns out as (kc, L)."""
+    pc x kc).  Returns out as (kc, L).  ``vector``: the vector-FMA kernel
+    instead of the matrix-core one."""
     L = B.shape[1]
     out = torch.empty((kc, L), dtype=torch.float64, device=B.device)
-    bt = SVDS_F64 if B.dtype == torch.float64 else SVDS_F32
+    bt = (SVDS_F64 if B.dtype == torch.float64 else SVDS_F32) | (SVDS_ROTATE_VECTOR if vector else 0)
     _check(lib.svds_op_rotate(L, pc, kc, _ptr(B), L, bt, _ptr(Y), Y.shape[1], _ptr(out), L, _stream(stream)),
            "svds_op_rotate")
     return out

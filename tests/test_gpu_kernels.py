@@ -349,19 +349,23 @@ def test_small_svd_repeated_and_zero_values(S):
 
 @pytest.mark.parametrize("L,pc,kc", [(1000, 30, 10), (1000, 31, 11), (65537, 150, 50), (3001, 251, 101),
                                      (100, 600, 3), (64, 1, 1)])
-def test_rotate_matches_numpy(S, L, pc, kc):
+@pytest.mark.parametrize("vector", [False, True])
+def test_rotate_matches_numpy(S, L, pc, kc, vector):
+    """Matrix-core (FP64 / FP32 MFMA) and vector-FMA kernels against numpy."""
     import torch
     rng = np.random.default_rng(L + pc)
     B = rng.standard_normal((L, pc))
     Y = rng.standard_normal((pc, kc))
-    out = S.svds_op_rotate(_t(np.ascontiguousarray(B.T)), pc, _t(np.ascontiguousarray(Y.T)), kc)
+    out = S.svds_op_rotate(_t(np.ascontiguousarray(B.T)), pc, _t(np.ascontiguousarray(Y.T)), kc, vector=vector)
     ref = B @ Y
     scale = np.abs(B) @ np.abs(Y)
     assert np.all(np.abs(out.cpu().numpy().T - ref) <= 4e-16 * pc * scale)
     out32 = S.svds_op_rotate(_t(np.ascontiguousarray(B.T), torch.float32), pc,
-                             _t(np.ascontiguousarray(Y.T)), kc)
+                             _t(np.ascontiguousarray(Y.T)), kc, vector=vector)
+    # FP32 arithmetic: B in FP32, Y rounded to FP32, FP32 accumulation
     B32 = B.astype(np.float32).astype(np.float64)
-    assert np.all(np.abs(out32.cpu().numpy().T - B32 @ Y) <= 3e-7 * pc * (np.abs(B32) @ np.abs(Y)))
+    Y32 = Y.astype(np.float32).astype(np.float64)
+    assert np.all(np.abs(out32.cpu().numpy().T - B32 @ Y32) <= 3e-7 * pc * (np.abs(B32) @ np.abs(Y32)))
 
 
 # --- dense mat-vecs -------------------------------------------------------------------
