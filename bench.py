@@ -162,7 +162,26 @@ def batched_vs_loop(S, inputs, np, torch):
             s1 = one.S.cpu().numpy()
             worst = max(worst, float(np.max(np.abs(s1 - sig_b[b]) / s1)))
         tl = time.perf_counter() - t0
-        out[name] = {"batched_ms": round(tb * 1e3, 2), "looped_ms": round(tl * 1e3, 2),
+        # the same batched call with each cycle replayed as a captured HIP graph,
+        # and with the plan-time autotuner (median of 3 after one warm-up)
+        variants = {}
+        for vname, vflag in (("graph", S.SVDS_FLAG_GRAPH), ("autotune", S.SVDS_FLAG_AUTOTUNE)):
+            vopts = S.make_opts(8, 24, 1e-8, 2000, precision=prec, seed=seed, flags=vflag)
+            vres, vrc = S.svds_csr_solve_batched([d[0] for d in dev], vopts)
+            torch.cuda.synchronize()
+            vts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                vres, vrc = S.svds_csr_solve_batched([d[0] for d in dev], vopts)
+                torch.cuda.synchronize()
+                vts.append(time.perf_counter() - t0)
+            vdiff = max(float(np.max(np.abs(r.S.cpu().numpy() - sig_b[b]) / sig_b[b])) for b, r in enumerate(vres))
+            variants[vname] = {"ms": round(sorted(vts)[1] * 1e3, 2), "status": vrc,
+                               "sigma_rel_diff_vs_plain": vdiff,
+                               "graph_captures": vres[0].info["graph_captures"],
+                               "graph_replays": vres[0].info["graph_replays"],
+                               "tuning_ms": round(vres[0].info["tuning"]["ms_tune"], 2)}
+        out[name] = {"batched_ms": round(tb * 1e3, 2), "looped_ms": round(tl * 1e3, 2), "variants": variants,
                      "batched_problems_per_s": round(len(As) / tb, 2),
                      "looped_problems_per_s": round(len(As) / tl, 2), "x": round(tl / tb, 2),
                      "cycles": res[0].info["cycles"], "all_converged": bool(ok),
