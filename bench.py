@@ -235,6 +235,28 @@ def paper_suite(S, inputs, np, torch, dense: bool):
     return out
 
 
+def profile_section(which, S, inputs, np, torch):
+    """Two solves of one workload for a kernel trace (see --profile-section)."""
+    if which == "dense":
+        d = inputs.config_matrix(3)
+        t = torch.from_numpy(d["bf16"].a.ravel(order="F").view(np.int16)).view(torch.uint16).cuda()
+        Ad = S.make_dense(t, 20000, 10000)
+        v0 = torch.from_numpy(inputs.start_vector(10000, inputs.CONFIG_SEEDS[3] + 1)).cuda()
+        for prec in (0, 1):
+            for _ in range(2):
+                r = S.svds_dense_solve(Ad, S.make_opts(100, 250, 1e-8, 2000, precision=prec, v0=v0))
+                torch.cuda.synchronize()
+                log(f"dense precision {prec}: {r.info['ms_total']:.1f} ms, cycles {r.info['cycles']}")
+    else:
+        As = inputs.config_matrix(5)
+        dev = [S.csr_to_device(A) for A in As]
+        opts = S.make_opts(8, 24, 1e-8, 2000, seed=inputs.CONFIG_SEEDS[5])
+        for _ in range(2):
+            res, rc = S.svds_csr_solve_batched([d[0] for d in dev], opts)
+            torch.cuda.synchronize()
+            log(f"batched: {res[0].info['ms_total']:.1f} ms, rc {rc}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +272,10 @@ def main():
                          "time each to generate the Haar factors)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
+    ap.add_argument("--profile-section", choices=["dense", "batched"],
+                    help="only two solves of one other workload, for a rocprofv3 kernel trace: the "
+                         "20000 x 10000 BF16 dense matrix (FP64 then mixed), or the 256-problem batch (FP64); "
+                         "no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver does not "
@@ -263,6 +289,9 @@ def main():
 
     rank = int(os.environ.get("RANK", "0"))
     torch.cuda.set_device(0)
+    if args.profile_section:
+        profile_section(args.profile_section, S, inputs, np, torch)
+        return
     log("generating workload ...")
     A = inputs.config_matrix(2)
     v0 = inputs.start_vector(A.n, inputs.CONFIG_SEEDS[2] + 1)
