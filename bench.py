@@ -247,6 +247,15 @@ def profile_section(which, S, inputs, np, torch):
                 r = S.svds_dense_solve(Ad, S.make_opts(100, 250, 1e-8, 2000, precision=prec, v0=v0))
                 torch.cuda.synchronize()
                 log(f"dense precision {prec}: {r.info['ms_total']:.1f} ms, cycles {r.info['cycles']}")
+    elif which == "sparse2":
+        A, sig = inputs.paper_suite("sparse2")
+        Ad, keep = S.csr_to_device(A)
+        v0 = torch.from_numpy(inputs.start_vector(A.n, inputs.PAPER_SUITE_SEEDS["sparse2"] + 1)).cuda()
+        c = inputs.PAPER_SUITE_SOLVE
+        for _ in range(2):
+            r = S.svds_csr_solve(Ad, S.make_opts(c["k"], c["p"], c["tol"], c["maxit"], v0=v0))
+            torch.cuda.synchronize()
+            log(f"sparse2: {r.info['ms_total']:.1f} ms, cycles {r.info['cycles']}")
     else:
         As = inputs.config_matrix(5)
         dev = [S.csr_to_device(A) for A in As]
@@ -272,10 +281,10 @@ def main():
                          "time each to generate the Haar factors)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
-    ap.add_argument("--profile-section", choices=["dense", "batched"],
+    ap.add_argument("--profile-section", choices=["dense", "batched", "sparse2"],
                     help="only two solves of one other workload, for a rocprofv3 kernel trace: the "
-                         "20000 x 10000 BF16 dense matrix (FP64 then mixed), or the 256-problem batch (FP64); "
-                         "no JSON")
+                         "20000 x 10000 BF16 dense matrix (FP64 then mixed), the 256-problem batch (FP64), "
+                         "or the paper's Sparse2 (40,000 x 40,000, k=100, p=300); no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver does not "

@@ -135,20 +135,29 @@ __device__ __forceinline__ double jac_rsqrt(double q) {
   return y;
 }
 
-// Same rotation for one pair per group of 16 lanes (4 pairs per wave, RPL
-// rows per lane): the four pairs' sums and rotation parameters are computed
-// by the same instructions.  Every lane of the wave takes part (a group with
-// no pair passes null columns); returns 1 if this lane's pair rotated.
-template <int RPL>
-__device__ __forceinline__ int jacobi_pair16(double *__restrict__ wi, double *__restrict__ wj,
-                                             double *__restrict__ vi, double *__restrict__ vj, int rows,
-                                             int sl, double tolJ) {
+// Sum over the LPP lanes of a pair group: a DPP row of 16 lanes, or the whole
+// wave (scalar result); either way every lane of the group gets the same bits.
+template <int LPP> __device__ __forceinline__ double group_sum(double v) {
+  static_assert(LPP == 16 || LPP == WAVE, "pair groups of 16 lanes or a whole wave");
+  if constexpr (LPP == 16) return row16_sum(v);
+  else return wave_sum_u(v);
+}
+
+// Same rotation for one pair per group of LPP lanes (16: four pairs per wave,
+// whose sums and rotation parameters are computed by the same instructions;
+// 64: one pair per wave), RPL rows per lane.  Every lane of the wave takes
+// part (a group with no pair passes null columns); returns 1 if this lane's
+// pair rotated.
+template <int RPL, int LPP>
+__device__ __forceinline__ int jacobi_pairg(double *__restrict__ wi, double *__restrict__ wj,
+                                            double *__restrict__ vi, double *__restrict__ vj, int rows,
+                                            int sl, double tolJ) {
   double xi[RPL], xj[RPL], yi[RPL], yj[RPL];
   double a = 0, b = 0, c = 0;
   const bool has = wi != nullptr;
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
-    const int r = sl + t * 16;
+    const int r = sl + t * LPP;
     const bool ok = has && r < rows;
     xi[t] = ok ? wi[r] : 0.0;
     xj[t] = ok ? wj[r] : 0.0;
@@ -158,9 +167,9 @@ __device__ __forceinline__ int jacobi_pair16(double *__restrict__ wi, double *__
     b += xj[t] * xj[t];
     c += xi[t] * xj[t];
   }
-  a = row16_sum(a);
-  b = row16_sum(b);
-  c = row16_sum(c);
+  a = group_sum<LPP>(a);
+  b = group_sum<LPP>(b);
+  c = group_sum<LPP>(c);
   if (!has || !(fabs(c) > tolJ * sqrt(a * b))) return 0;
   // Rutishauser's parameters with hardware reciprocal / reciprocal square
   // root, each refined by two Newton steps (full double accuracy; the
@@ -177,7 +186,7 @@ __device__ __forceinline__ int jacobi_pair16(double *__restrict__ wi, double *__
   const double sn = cs * tt;
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
-    const int r = sl + t * 16;
+    const int r = sl + t * LPP;
     if (r < rows) {
       wi[r] = cs * xi[t] - sn * xj[t];
       wj[r] = sn * xi[t] + cs * xj[t];
@@ -188,18 +197,18 @@ __device__ __forceinline__ int jacobi_pair16(double *__restrict__ wi, double *__
   return 1;
 }
 
-// As jacobi_pair16 with column i held in registers (xi, yi: this lane's RPL
+// As jacobi_pairg with column i held in registers (xi, yi: this lane's RPL
 // rows of W and Vh): in the cross rounds of the block schedule a group keeps
 // its column for the whole round, so only column j travels through LDS.
-template <int RPL>
-__device__ __forceinline__ int jacobi_pair16_reg(double (&xi)[RPL], double (&yi)[RPL], double *__restrict__ wj,
-                                                 double *__restrict__ vj, int rows, int sl, double tolJ,
-                                                 bool has) {
+template <int RPL, int LPP>
+__device__ __forceinline__ int jacobi_pairg_reg(double (&xi)[RPL], double (&yi)[RPL], double *__restrict__ wj,
+                                                double *__restrict__ vj, int rows, int sl, double tolJ,
+                                                bool has) {
   double xj[RPL], yj[RPL];
   double a = 0, b = 0, c = 0;
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
-    const int r = sl + t * 16;
+    const int r = sl + t * LPP;
     const bool ok = has && r < rows;
     xj[t] = ok ? wj[r] : 0.0;
     yj[t] = ok ? vj[r] : 0.0;
@@ -207,9 +216,9 @@ __device__ __forceinline__ int jacobi_pair16_reg(double (&xi)[RPL], double (&yi)
     b += xj[t] * xj[t];
     c += xi[t] * xj[t];
   }
-  a = row16_sum(a);
-  b = row16_sum(b);
-  c = row16_sum(c);
+  a = group_sum<LPP>(a);
+  b = group_sum<LPP>(b);
+  c = group_sum<LPP>(c);
   if (!has || !(fabs(c) > tolJ * sqrt(a * b))) return 0;
   const double z = (b - a) * jac_rcp(2.0 * c);
   double tt;
@@ -223,7 +232,7 @@ __device__ __forceinline__ int jacobi_pair16_reg(double (&xi)[RPL], double (&yi)
   const double sn = cs * tt;
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
-    const int r = sl + t * 16;
+    const int r = sl + t * LPP;
     const double wi = cs * xi[t] - sn * xj[t];
     const double vi = cs * yi[t] - sn * yj[t];
     if (r < rows) {
@@ -403,15 +412,15 @@ __host__ __device__ inline size_t small_svd_lds_bytes(int p) {
 }
 
 // ---------------------------------------------------------------------------
-// Block schedule: one round.  Grid nb/2 workgroups of c/4 waves (one pair per
-// 16-lane group, RPL rows per lane); dynamic LDS
+// Block schedule: one round.  Grid nb/2 workgroups of c LPP / 64 waves (one
+// pair per group of LPP lanes, RPL rows per lane); dynamic LDS
 // 2c columns of W then 2c columns of Vh, p rows each.  Block b holds global
 // columns [b c, b c + c); W and Vh in global memory are column-major with
 // ld = p and nb*c columns.  In the first round of the first sweep the blocks
 // are loaded from T (row-major, ld p+1) and the identity instead.
 // ---------------------------------------------------------------------------
-template <int RPL>
-__global__ __launch_bounds__(256) void bjac_round_kernel(const double *__restrict__ T, int from_T,
+template <int RPL, int LPP>
+__global__ __launch_bounds__(LPP == WAVE ? (RPL <= 6 ? 1024 : 512) : 256) void bjac_round_kernel(const double *__restrict__ T, int from_T,
                                                                  double *__restrict__ W,
                                                                  double *__restrict__ Vh, int p, int c,
                                                                  int nb, int round, int sweep,
@@ -459,15 +468,15 @@ __global__ __launch_bounds__(256) void bjac_round_kernel(const double *__restric
   }
   __syncthreads();
   const double tolJ = jacobi_tol(p + (p & 1));
-  // pair q of a step is handled by the 16-lane group q (4 per wave)
-  const int q = wv * 4 + (lane >> 4), sl = lane & 15;
+  // pair q of a step is handled by lane group q (WAVE / LPP groups per wave)
+  const int q = wv * (WAVE / LPP) + lane / LPP, sl = lane % LPP;
   const bool own = q < c;
   int nrot = 0;
   if (round == 0) {
     for (int step = 0; step < c2 - 1; ++step) {
       int i = 0, j = 0;
       if (own) rr_pair(c2, step, q, i, j);
-      nrot += jacobi_pair16<RPL>(own ? X + i * p : nullptr, X + j * p, Y + i * p, Y + j * p, p, sl, tolJ);
+      nrot += jacobi_pairg<RPL, LPP>(own ? X + i * p : nullptr, X + j * p, Y + i * p, Y + j * p, p, sl, tolJ);
       __syncthreads();
     }
   } else {
@@ -475,20 +484,20 @@ __global__ __launch_bounds__(256) void bjac_round_kernel(const double *__restric
     double xi[RPL], yi[RPL];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
-      const int r = sl + t * 16;
+      const int r = sl + t * LPP;
       const bool ok = own && r < p;
       xi[t] = ok ? X[q * p + r] : 0.0;
       yi[t] = ok ? Y[q * p + r] : 0.0;
     }
     for (int step = 0; step < c; ++step) {
       const int j = c + (q + step) % c;
-      nrot += jacobi_pair16_reg<RPL>(xi, yi, X + (own ? j : 0) * p, Y + (own ? j : 0) * p, p, sl, tolJ, own);
+      nrot += jacobi_pairg_reg<RPL, LPP>(xi, yi, X + (own ? j : 0) * p, Y + (own ? j : 0) * p, p, sl, tolJ, own);
       __syncthreads();
     }
     if (own) {
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
-        const int r = sl + t * 16;
+        const int r = sl + t * LPP;
         if (r < p) {
           X[q * p + r] = xi[t];
           Y[q * p + r] = yi[t];

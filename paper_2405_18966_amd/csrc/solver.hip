@@ -1854,33 +1854,39 @@ int svds_cgs2_op(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w
 }
 
 namespace {
-template <int R>
+template <int R, int LPP>
 int bjac_launch_round(hipStream_t st, const double *T, int from_T, double *W, double *Vh, int p, int c, int nb,
                       int round, int sweep, int *counters) {
   const size_t shm = static_cast<size_t>(4 * c) * p * sizeof(double);
   static bool attr_set = false;  // benign race: every caller sets the same value
   if (!attr_set) {
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&bjac_round_kernel<R>),
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&bjac_round_kernel<R, LPP>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, BJ_LDS));
     attr_set = true;
   }
-  hipLaunchKernelGGL((bjac_round_kernel<R>), dim3(nb / 2), dim3(std::max(1, c / 4) * WAVE), shm, st, T, from_T, W,
-                     Vh, p, c, nb, round, sweep, counters);
+  const int waves = LPP == WAVE ? c : std::max(1, c / 4);  // one lane group per pair of a step
+  hipLaunchKernelGGL((bjac_round_kernel<R, LPP>), dim3(nb / 2), dim3(waves * WAVE), shm, st, T, from_T, W, Vh, p,
+                     c, nb, round, sweep, counters);
   HIP_TRY(hipGetLastError());
   return SVDS_OK;
 }
 
-int bjac_round(hipStream_t st, int rpl16, const double *T, int from_T, double *W, double *Vh, int p, int c,
-               int nb, int round, int sweep, int *counters) {
-  // rpl16: rows per lane with 16 lanes per column pair
-  if (rpl16 <= 4) return bjac_launch_round<4>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-  if (rpl16 <= 8) return bjac_launch_round<8>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-  if (rpl16 <= 12) return bjac_launch_round<12>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-  if (rpl16 <= 16) return bjac_launch_round<16>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-  if (rpl16 <= 24) return bjac_launch_round<24>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-  if (rpl16 <= 32) return bjac_launch_round<32>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-  if (rpl16 <= 48) return bjac_launch_round<48>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
-  if (rpl16 <= 64) return bjac_launch_round<64>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters);
+// One wave per column pair (RPL = ceil(p / 64) rows per lane): the serial
+// work of a step shrinks four-fold against 16-lane groups, at the price of
+// four times the waves per workgroup (c waves, at most 1024 threads).
+int bjac_round(hipStream_t st, const double *T, int from_T, double *W, double *Vh, int p, int c, int nb,
+               int round, int sweep, int *counters) {
+  const int rpl = static_cast<int>(ceil_div(p, WAVE));
+#define BJ_GO(R) return bjac_launch_round<R, WAVE>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters)
+  if (rpl <= 2) BJ_GO(2);
+  if (rpl <= 3) BJ_GO(3);
+  if (rpl <= 4) BJ_GO(4);
+  if (rpl <= 5) BJ_GO(5);
+  if (rpl <= 6) BJ_GO(6);
+  if (rpl <= 8) BJ_GO(8);
+  if (rpl <= 12) BJ_GO(12);
+  if (rpl <= 16) BJ_GO(16);
+#undef BJ_GO
   return SVDS_EUNSUPPORTED;
 }
 
@@ -1903,7 +1909,6 @@ int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, doub
   }
   int c, nb;
   bjac_shape(p, c, nb);
-  const int rpl = static_cast<int>(ceil_div(p, 16));
   double *W = work;
   double *Vh = work + static_cast<int64_t>(p) * nb * c;
   int *counters = reinterpret_cast<int *>(Vh + static_cast<int64_t>(p) * nb * c);
@@ -1917,7 +1922,7 @@ int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, doub
     const int chunk = std::min(enq == 0 ? 10 : 2, JAC_MAX_SWEEPS - enq);
     for (int sw = enq; sw < enq + chunk; ++sw)
       for (int r = 0; r < nb - 1; ++r) {
-        const int rc = bjac_round(st, rpl, T, sw == 0 && r == 0, W, Vh, p, c, nb, r, sw, counters);
+        const int rc = bjac_round(st, T, sw == 0 && r == 0, W, Vh, p, c, nb, r, sw, counters);
         if (rc) return rc;
       }
     enq += chunk;
