@@ -67,7 +67,8 @@ def test_validation_rejects_bad_sizes_before_touching_the_device(lib):
 
 def test_smallest_triplets_unsupported_forms_rejected_on_the_host(lib):
     """SVDS_FLAG_SMALLEST is FP64-only: mixed precision and the batched solver
-    return EUNSUPPORTED before any device call."""
+    return EUNSUPPORTED before any device call; so does the batched solver for
+    SVDS_FLAG_SELECTIVE_REORTH."""
     import importlib
     mod = importlib.import_module("paper_2405_18966_amd.svds")
     fake = 4096  # never dereferenced
@@ -75,11 +76,12 @@ def test_smallest_triplets_unsupported_forms_rejected_on_the_host(lib):
     h = ctypes.c_void_p()
     o = mod.svds_opts(2, 6, 0.0, 0, mod.SVDS_PREC_MIXED, 0, None, None, mod.SVDS_FLAG_SMALLEST)
     assert mod.lib.svds_plan_create_csr(ctypes.byref(A), ctypes.byref(o), ctypes.byref(h)) == -4
-    o = mod.svds_opts(2, 6, 0.0, 0, mod.SVDS_PREC_FP64, 0, None, None, mod.SVDS_FLAG_SMALLEST)
     outs = (ctypes.c_void_p * 1)(fake)
     info = mod.svds_info()
-    assert mod.lib.svds_csr_solve_batched(1, ctypes.byref(A), ctypes.byref(o), outs, outs, outs,
-                                          ctypes.byref(info)) == -4
+    for flag in (mod.SVDS_FLAG_SMALLEST, mod.SVDS_FLAG_SELECTIVE_REORTH):
+        o = mod.svds_opts(2, 6, 0.0, 0, mod.SVDS_PREC_FP64, 0, None, None, flag)
+        assert mod.lib.svds_csr_solve_batched(1, ctypes.byref(A), ctypes.byref(o), outs, outs, outs,
+                                              ctypes.byref(info)) == -4
 
 
 def test_ctypes_structs_match_the_c_header(tmp_path):
