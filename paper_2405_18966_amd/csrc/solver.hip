@@ -261,6 +261,7 @@ struct svds_plan {
   bool mixed = false;
   Small sc{};
   double *tmp_nk = nullptr;  // n x k FP64 (mixed warm start), m-vector scratch
+  int32_t *tscratch = nullptr;  // device radix-sort scratch of the transposed copies (CSR plans)
   double *tmp_m = nullptr, *tmp_n = nullptr;
   // residual panels (CSR plans): row-major RG-column panels of U and V, partials
   double *rs_pu = nullptr, *rs_pv = nullptr, *rs_part = nullptr, *rs_pieces = nullptr, *rs_lpart = nullptr,
@@ -798,6 +799,16 @@ static int fill_defaults(const svds_opts *o, int64_t m, int64_t n, svds_plan *P)
   return SVDS_OK;
 }
 
+// int32 words of device scratch a transposed copy needs (build_transpose):
+// row of each nonzero, two key/value ping-pong pairs, digit histograms,
+// their scan offsets and tile sums
+static size_t transpose_scratch_words(int64_t nnz) {
+  const int64_t ntiles = ceil_div(std::max<int64_t>(nnz, 1), RS_TILE);
+  const int64_t nh = ntiles * RS_BINS;
+  const int64_t nsum = ceil_div(nh, SCAN_TILE);
+  return 5 * static_cast<size_t>(std::max<int64_t>(nnz, 1)) + 2 * static_cast<size_t>(nh) + nsum + 64;
+}
+
 static int carve_all(svds_plan *P, Arena &a) {
   const int p = P->p, k = P->k;
   const int64_t m = P->op.m, n = P->op.n;
@@ -860,6 +871,7 @@ static int carve_all(svds_plan *P, Arena &a) {
       P->op.bwd.sval = a.take<char>(nz * vb);
       P->op.bwd.spos = a.take<uint16_t>(nz);
     }
+    P->tscratch = a.take<int32_t>(transpose_scratch_words(P->op.nnz));
     P->op.trp = a.take<int32_t>(n + 1);
     P->op.tci = a.take<int32_t>(std::max<int64_t>(1, P->op.nnz));
     P->op.tval = a.take<char>(std::max<int64_t>(1, P->op.nnz) * static_cast<size_t>(vsize(P->op.vt)));
@@ -894,6 +906,8 @@ static int alloc_arena(svds_plan *P) {
 // panels of A (rows_per_panel rows each), npanel n rows.
 static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int32_t *out_rp,
                            int32_t *out_ci, void *out_val) {
+  // the scratch lives in the plan's arena (transpose_scratch_words), so the
+  // two transposes of a plan (A^T and its column-panel form) allocate nothing
   Operator &op = P->op;
   const int64_t m = op.m, nnz = op.nnz;
   const int64_t n = op.n * npanel;  // keys
@@ -906,12 +920,8 @@ static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int
   const int64_t ntiles = ceil_div(nnz, RS_TILE);
   const int64_t nh = ntiles * RS_BINS;
   const int64_t nsum = ceil_div(nh, SCAN_TILE);
-  int32_t *buf = nullptr;
-  const size_t words = 5 * static_cast<size_t>(nnz) + 2 * static_cast<size_t>(nh) + nsum + 64;
-  if (hipMalloc(&buf, words * sizeof(int32_t)) != hipSuccess) {
-    (void)hipGetLastError();
-    return SVDS_ENOMEM;
-  }
+  int32_t *buf = P->tscratch;
+  if (!buf) return SVDS_EINVAL;
   int32_t *rowof = buf, *k0 = buf + nnz, *v0 = buf + 2 * nnz, *k1 = buf + 3 * nnz, *v1 = buf + 4 * nnz;
   int32_t *hist = buf + 5 * nnz, *offs = hist + nh, *sums = offs + nh;
   int rc = SVDS_OK;
@@ -947,7 +957,6 @@ static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int
     if (hipGetLastError() != hipSuccess) { rc = SVDS_EDEVICE; break; }
     if (hipStreamSynchronize(st) != hipSuccess) { rc = SVDS_EDEVICE; break; }
   } while (0);
-  (void)hipFree(buf);
   return rc;
 }
 
