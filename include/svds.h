@@ -63,7 +63,10 @@ enum { SVDS_F64 = 0, SVDS_F32 = 1, SVDS_BF16 = 2 };
  *                  then FP64 cycles restarted from the FP32 Ritz vectors.
  * The small SVD of T, T itself and the final residuals are FP64 always.
  * A stored in FP32/BF16 is widened exactly; that widened matrix is the
- * matrix whose SVD is computed. */
+ * matrix whose SVD is computed.  A sparse A stored in FP64 is read, in the
+ * FP32 cycles, from FP32 copies of its values that the plan makes (4 bytes
+ * per nonzero and per copy of the values the plan holds, counted in
+ * workspace_bytes); the FP64 cycles and the residuals read the FP64 values. */
 enum { SVDS_PREC_FP64 = 0, SVDS_PREC_MIXED = 1 };
 
 /* Option flags. */
@@ -213,7 +216,7 @@ typedef struct {
   int64_t kc_launches[SVDS_KC_COUNT];
   int64_t kc_sampled_launches[SVDS_KC_COUNT];
   double kc_sampled_bytes[SVDS_KC_COUNT];
-  int64_t workspace_bytes;         /* device arena of the plan              */
+  int64_t workspace_bytes;         /* device memory the plan holds          */
   int32_t graph_captures;          /* SVDS_FLAG_GRAPH: cycle graphs captured */
   int32_t graph_replays;           /* ... and cycles run by replaying one    */
   svds_tuning tuning;              /* SVDS_FLAG_AUTOTUNE choices of the plan */

@@ -698,7 +698,7 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
       in.kc_sampled_launches[c] = P->acc.sampled[c];
       in.kc_sampled_bytes[c] = P->acc.sampled_bytes[c];
     }
-    in.workspace_bytes = static_cast<int64_t>(P->arena.size);
+    in.workspace_bytes = static_cast<int64_t>(P->arena.size + P->op.v32_bytes);
     in.graph_captures = static_cast<int32_t>(P->graphs.captures);
     in.graph_replays = static_cast<int32_t>(P->graphs.replays);
     in.tuning = P->tuning;

@@ -165,6 +165,12 @@ struct Operator {
   SpmvPlan bwdp;
   void *pbuf = nullptr, *pbuf_items = nullptr;
   size_t pbuf_bytes = 0;
+  // FP32 copies of the values of an FP64-stored CSR matrix for the FP32 phase
+  // of a mixed solve (A, A^T, the column-sorted copies, the panel copy; null
+  // where that array does not exist); one allocation, v32buf
+  float *val32 = nullptr, *tval32 = nullptr, *fsval32 = nullptr, *bsval32 = nullptr, *pval32 = nullptr;
+  void *v32buf = nullptr;
+  size_t v32_bytes = 0;
   // dense
   const void *a = nullptr;
   int64_t lda = 0;

@@ -347,12 +347,18 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     const uint16_t *spos = srt ? sp.spos : nullptr;
     const int32_t *cs = srt ? sp.scol : ci;
     const void *vs = srt ? sp.sval : val;
+    // FP32 phase of a mixed solve on FP64 values: the FP32 copies
+    const bool v32 = std::is_same<TB, float>::value && op.val32 != nullptr;
+    if (v32)
+      vs = panels ? static_cast<const void *>(op.pval32)
+                  : srt ? static_cast<const void *>(trans ? op.bsval32 : op.fsval32)
+                        : static_cast<const void *>(trans ? op.tval32 : op.val32);
     TB *yk = panels ? reinterpret_cast<TB *>(op.ypart) : y;
     const double *ck = panels ? nullptr : coef;
     const TB *ypk = panels ? nullptr : yprev;
     TB *parts = reinterpret_cast<TB *>(sp.partials);
     const bool fix = sp.nlong > 0;
-    if (op.vt == SVDS_F64)
+    if (op.vt == SVDS_F64 && !v32)
       klaunch(P->acc, true, !fix && !panels, spmv_csr_kernel<double, TB>, dim3(sp.nitems), dim3(SPMV_THREADS), 0,
               P->stream, sp.items, rp, cs, static_cast<const double *>(vs), spos, x, xs, ck, ypk, yk, parts,
               side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles);
@@ -367,7 +373,7 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
       klaunch(P->acc, false, true, spmv_panel_sum_kernel<TB>, dim3(ceil_div(op.n, 256)), dim3(256), 0, P->stream,
               op.n, op.npanel, yk, coef, yprev, y);
     LAUNCH_CHECK();
-    bytes = 4.0 * (rows + 1) + (4.0 + vsize(op.vt)) * op.nnz + sb * cols +
+    bytes = 4.0 * (rows + 1) + (4.0 + (v32 ? 4.0 : vsize(op.vt))) * op.nnz + sb * cols +
             (yprev ? 2.0 : 1.0) * sb * rows;
   }
   if (side_dst) bytes += 2.0 * sb * side_len;
@@ -1300,6 +1306,40 @@ static int autotune(svds_plan *P, const int32_t *hrp, const int32_t *htrp, const
   return SVDS_OK;
 }
 
+// FP32 copies of every FP64 value array a product reads (Operator::val32
+// and friends), made once the arrays are final (after any tuning): the FP32
+// phase of a mixed solve then streams 4-byte values.  The FP64 refinement
+// and the residuals keep reading the FP64 arrays.
+static int build_values32(svds_plan *P) {
+  Operator &op = P->op;
+  const int64_t nnz = op.nnz;
+  const bool fs = op.fwd.spos && op.fwd.sorted, bs = op.bwd.spos && op.bwd.sorted, pn = op.npanel > 1;
+  const int64_t count = 2 + (fs ? 1 : 0) + (bs ? 1 : 0) + (pn ? 1 : 0);
+  const size_t per = (static_cast<size_t>(nnz) * sizeof(float) + 255) & ~size_t(255);
+  if (hipMalloc(&op.v32buf, per * count) != hipSuccess) {
+    (void)hipGetLastError();
+    op.v32buf = nullptr;
+    return SVDS_ENOMEM;
+  }
+  op.v32_bytes = per * count;
+  char *b = static_cast<char *>(op.v32buf);
+  auto next = [&]() { float *q = reinterpret_cast<float *>(b); b += per; return q; };
+  auto cast = [&](const void *src, float *dst) {
+    // one element per thread
+    hipLaunchKernelGGL((cast_copy_kernel<double, float>), dim3(static_cast<unsigned>(ceil_div(nnz, 256))),
+                       dim3(256), 0, P->stream, nnz, static_cast<const double *>(src), dst);
+  };
+  op.val32 = next();
+  cast(op.val, op.val32);
+  op.tval32 = next();
+  cast(op.tval, op.tval32);
+  if (fs) cast(op.fwd.sval, op.fsval32 = next());
+  if (bs) cast(op.bwd.sval, op.bsval32 = next());
+  if (pn) cast(op.pval, op.pval32 = next());
+  HIP_TRY(hipGetLastError());
+  return SVDS_OK;
+}
+
 namespace {
 // Destroys a partially built plan on every early return of plan creation.
 struct PlanGuard {
@@ -1425,6 +1465,7 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   }
   if ((opts->flags & SVDS_FLAG_AUTOTUNE) && (rc = autotune(P, hrp.data(), htrp.data(), seg_rows, seg_cols, nseg)))
     return rc;
+  if (P->mixed && op.vt == SVDS_F64 && op.nnz > 0 && (rc = build_values32(P))) return rc;
   HIP_TRY(hipStreamSynchronize(P->stream));
   *plan = guard.release();
   return SVDS_OK;
@@ -1469,6 +1510,7 @@ extern "C" void svds_plan_destroy(svds_plan *P) {
   if (P->arena.base) (void)hipFree(P->arena.base);
   if (P->op.pbuf) (void)hipFree(P->op.pbuf);
   if (P->op.pbuf_items) (void)hipFree(P->op.pbuf_items);
+  if (P->op.v32buf) (void)hipFree(P->op.v32buf);
   if (P->h_flags) (void)hipHostFree(P->h_flags);
   P->graphs.destroy();
   P->acc.destroy();
@@ -1621,7 +1663,7 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
       info->kc_sampled_launches[c] = P->acc.sampled[c];
       info->kc_sampled_bytes[c] = P->acc.sampled_bytes[c];
     }
-    info->workspace_bytes = static_cast<int64_t>(P->arena.size + P->op.pbuf_bytes);
+    info->workspace_bytes = static_cast<int64_t>(P->arena.size + P->op.pbuf_bytes + P->op.v32_bytes);
     info->graph_captures = static_cast<int32_t>(P->graphs.captures - cap0);
     info->graph_replays = static_cast<int32_t>(P->graphs.replays - rep0);
     info->reorth_tests = static_cast<int32_t>(P->reorth_calls);
