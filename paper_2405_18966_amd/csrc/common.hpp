@@ -89,6 +89,24 @@ __device__ __forceinline__ float wave_sum_u(float v) {
 }
 template <typename T> __device__ __forceinline__ T wave_sum(T v) { return wave_sum_u(v); }
 
+// s + p[i0] + p[i0 + stride] + ... over i < n, added in increasing i.  The
+// loads are issued 16 at a time before their adds: partial sums are read
+// straight after the kernel that wrote them, from L2 or beyond, and one load
+// per dependent add would pay that latency once per entry.
+template <typename T>
+__device__ __forceinline__ T strided_sum(const T *__restrict__ p, int i0, int n, int stride, T s) {
+  constexpr int U = 16;
+  for (; i0 < n; i0 += U * stride) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = i0 + u * stride < n ? p[i0 + u * stride] : T(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * stride < n) s += v[u];
+  }
+  return s;
+}
+
 // Sum over each row of 16 lanes (DPP rows): quad swaps, half-row and row
 // mirrors.  Every add combines two values in both orders on the two lanes
 // involved, so all 16 lanes of a row end with the same bits.  Every lane of

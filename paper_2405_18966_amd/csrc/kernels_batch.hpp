@@ -187,8 +187,7 @@ __global__ __launch_bounds__(CGS_THREADS) void bfinish_norm_kernel(
   int64_t off;
   int32_t len, t0, nt;
   bside(pr[b], side_v, off, len, t0, nt);
-  double tot = 0;
-  for (int t = tid; t < nt; t += CGS_THREADS) tot += npart[t0 + t];
+  double tot = strided_sum(npart + t0, tid, nt, CGS_THREADS, 0.0);
   tot = block_sum(tot, sh_d);
   const double nrm = sqrt(tot);
   if (mode == MODE_NORM) {
@@ -396,8 +395,7 @@ static __global__ void bseg_norm_kernel(const double *__restrict__ npart, const 
   int64_t off;
   int32_t len, t0, nt;
   bside(pr[b], side_v, off, len, t0, nt);
-  double tot = 0;
-  for (int t = threadIdx.x; t < nt; t += CGS_THREADS) tot += npart[t0 + t];
+  double tot = strided_sum(npart + t0, static_cast<int>(threadIdx.x), nt, CGS_THREADS, 0.0);
   tot = block_sum(tot, sh_d);
   if (threadIdx.x == 0) out[static_cast<int64_t>(b) * os] = sqrt(tot);
 }

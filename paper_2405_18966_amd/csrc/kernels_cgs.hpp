@@ -65,8 +65,7 @@ __global__ __launch_bounds__(256) void reduce_cols_kernel(const T *__restrict__ 
   const int c = blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
   if (c >= nc) return;
   const T *p = src + static_cast<int64_t>(c) * ld;
-  T s = 0;
-  for (int i = lane; i < nv; i += WAVE) s += p[i];
+  T s = strided_sum(p, lane, nv, WAVE, T(0));
   s = wave_sum(s);
   if (lane == 0) out[c] = s;
 }
@@ -450,8 +449,7 @@ __global__ __launch_bounds__(CGS_THREADS) void finish_norm_kernel(const double *
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ int bd;
   const int tid = threadIdx.x;
-  double tot = 0;
-  for (int g = tid; g < nparts; g += CGS_THREADS) tot += npart[g];
+  double tot = strided_sum(npart, tid, nparts, CGS_THREADS, 0.0);
   tot = block_sum(tot, sh_d);
   const double nrm = sqrt(tot);
   if (mode == MODE_NORM) {

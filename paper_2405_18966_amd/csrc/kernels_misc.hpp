@@ -346,8 +346,7 @@ static __global__ __launch_bounds__(256) void norm_partials_kernel(int64_t L, co
 static __global__ __launch_bounds__(256) void norm_finish_kernel(const double *__restrict__ partials,
                                                                 int n, double *__restrict__ out) {
   __shared__ double sh[256 / WAVE];
-  double s = 0;
-  for (int g = threadIdx.x; g < n; g += 256) s += partials[g];
+  double s = strided_sum(partials, static_cast<int>(threadIdx.x), n, 256, 0.0);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) *out = sqrt(s);
 }

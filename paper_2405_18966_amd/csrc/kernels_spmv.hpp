@@ -230,8 +230,7 @@ __global__ __launch_bounds__(WAVE) void spmv_longrow_fixup_kernel(const LongRow 
   if (active && !active[L.inst]) return;
   const TB xs = xs_ptr ? static_cast<TB>(xs_ptr[L.inst]) : TB(1);
   const TB coef = coef_ptr ? static_cast<TB>(coef_ptr[L.inst]) : TB(0);
-  TB t = 0;
-  for (int q = threadIdx.x; q < L.npieces; q += WAVE) t += partials[L.first_piece + q];
+  TB t = strided_sum(partials + L.first_piece, static_cast<int>(threadIdx.x), L.npieces, WAVE, TB(0));
   t = wave_sum(t);
   if (threadIdx.x == 0) y[L.row] = xs * t - (yprev ? coef * yprev[L.row] : TB(0));
 }
