@@ -105,10 +105,9 @@ struct Accounting {
   int harvest();
   int before(int kc, bool attached = false);
   int after(int kc, double b, double f);
-  void destroy() {
-    for (auto e : pool) (void)hipEventDestroy(e);
-    pool.clear();
-  }
+  int device = 0;  // device the events belong to
+  int grow();      // adds events to the pool
+  void destroy();  // returns the pool's events to the process-wide cache
 };
 
 // ---------------------------------------------------------------------------

@@ -100,6 +100,40 @@ int Accounting::harvest() {
   return SVDS_OK;
 }
 
+// Timing events come from a process-wide cache per device: a plan made for
+// each solve would otherwise create and destroy its events every time, at
+// microseconds per event.
+static std::mutex g_ev_mu;
+static std::vector<hipEvent_t> g_ev_free[64];
+
+int Accounting::grow() {
+  constexpr size_t CHUNK = 64;
+  size_t got = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_ev_mu);
+    auto &f = g_ev_free[device & 63];
+    while (got < CHUNK && !f.empty()) {
+      pool.push_back(f.back());
+      f.pop_back();
+      ++got;
+    }
+  }
+  for (; got < CHUNK; ++got) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  return SVDS_OK;
+}
+
+void Accounting::destroy() {
+  if (pool.empty()) return;
+  std::lock_guard<std::mutex> lock(g_ev_mu);
+  auto &f = g_ev_free[device & 63];
+  f.insert(f.end(), pool.begin(), pool.end());
+  pool.clear();
+}
+
 int Accounting::before(int kc, bool attached) {
   // one launch in each group of SVDS_TIMING_SAMPLE, at an offset that
   // rotates from group to group, so launches that alternate between two
@@ -110,11 +144,8 @@ int Accounting::before(int kc, bool attached) {
   if (!sampling) return SVDS_OK;
   if (next + 2 > pool.size()) {
     if (pool.size() < 16384) {
-      for (int i = 0; i < 1024; ++i) {
-        hipEvent_t e;
-        HIP_TRY(hipEventCreate(&e));
-        pool.push_back(e);
-      }
+      int rc = grow();
+      if (rc) return rc;
     } else {
       int rc = harvest();
       if (rc) return rc;
@@ -1383,6 +1414,7 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   op.ci = A->col_idx;
   op.val = A->val;
   P->acc.stream = P->stream;
+  P->acc.device = P->device;
   P->acc.timing = (opts->flags & SVDS_FLAG_TIMING) != 0;
   // work items of A (row pointers read back once)
   std::vector<int32_t> hrp(A->m + 1);
@@ -1497,6 +1529,7 @@ extern "C" int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts
   op.a = A->a;
   op.lda = A->ld;
   P->acc.stream = P->stream;
+  P->acc.device = P->device;
   P->acc.timing = (opts->flags & SVDS_FLAG_TIMING) != 0;
   if ((rc = alloc_arena(P))) return rc;
   if ((opts->flags & SVDS_FLAG_AUTOTUNE) && (rc = autotune(P, nullptr, nullptr, nullptr, nullptr, 0))) return rc;
