@@ -378,12 +378,14 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     const uint16_t *spos = srt ? sp.spos : nullptr;
     const int32_t *cs = srt ? sp.scol : ci;
     const void *vs = srt ? sp.sval : val;
-    // FP32 phase of a mixed solve on FP64 values: the FP32 copies
-    const bool v32 = std::is_same<TB, float>::value && op.val32 != nullptr;
-    if (v32)
-      vs = panels ? static_cast<const void *>(op.pval32)
-                  : srt ? static_cast<const void *>(trans ? op.bsval32 : op.fsval32)
-                        : static_cast<const void *>(trans ? op.tval32 : op.val32);
+    // FP32 phase of a mixed solve on FP64 values: the FP32 copy of the array
+    // chosen above (none: the FP64 values serve)
+    const float *v32p = nullptr;
+    if (std::is_same<TB, float>::value && op.val32)
+      v32p = vs == op.val ? op.val32 : vs == op.tval ? op.tval32 : vs == op.pval ? op.pval32
+           : vs == op.fwd.sval ? op.fsval32 : vs == op.bwd.sval ? op.bsval32 : nullptr;
+    const bool v32 = v32p != nullptr;
+    if (v32) vs = v32p;
     TB *yk = panels ? reinterpret_cast<TB *>(op.ypart) : y;
     const double *ck = panels ? nullptr : coef;
     const TB *ypk = panels ? nullptr : yprev;
