@@ -139,3 +139,38 @@ def test_mixed_dense_bf16_full_size_against_stored_oracle(S):
     r1 = torch.linalg.norm(A @ V - U * s, dim=0) / s[0]
     assert abs(info["max_res_av"] - float(r1.max())) <= 1e-12
     assert info["max_res_true"] <= 2e-8 and info["max_res_av"] <= 2e-8
+
+
+def test_mixed_fp64_values_every_product_layout(S):
+    """FP64-stored values read in FP32 by the FP32 cycles: the plan's FP32
+    copies of A, A^T, the column-sorted copies and the column-panel copy.
+    300000 x 150000 Zipf(1.1), 10 draws per row: long rows (pieces) in A^T
+    and two column panels; each layout switch selects a different set of
+    copies, and the tuner may turn the sorted copies off."""
+    import torch
+    print("mixed fp64 values, layouts", flush=True)
+    A = inputs.sparse_zipf(300000, 150000, 10, 1.1, seed=331)
+    v0 = inputs.start_vector(A.n, 332)
+    Ur, Sr, Vr, _ = svds_ref.svds(as_operator(A), 6, 18, 1e-10, 2000, v0=v0)
+    Ad, keep = S.csr_to_device(A)
+    F = S
+    ws = {}
+    for name, fl in (("default", 0), ("unsorted", F.SVDS_FLAG_UNSORTED), ("nopanels", F.SVDS_FLAG_NO_PANELS),
+                     ("plain", F.SVDS_FLAG_UNSORTED | F.SVDS_FLAG_NO_PANELS), ("autotune", F.SVDS_FLAG_AUTOTUNE)):
+        print(f"layout {name}", flush=True)
+        r = S.svds_csr_solve(Ad, S.make_opts(6, 18, 1e-10, 2000, precision=MIXED, v0=torch.from_numpy(v0).cuda(),
+                                             flags=fl))
+        torch.cuda.synchronize()
+        assert r.status == 0, name
+        assert r.info["cycles_fp32"] >= 1 and r.info["cycles_fp64"] >= 1, name
+        np.testing.assert_allclose(r.S.cpu().numpy(), Sr, rtol=1e-10, err_msg=name)
+        assert r.info["max_res_true"] <= 2e-10, name
+        ws[name] = r.info["workspace_bytes"]
+    # four FP32 copies of the values (A, A^T and their sorted copies) plus the
+    # panel copy with panels, two without any sorted copy or panels
+    per = (A.nnz * 4 + 255) // 256 * 256
+    r64 = S.svds_csr_solve(Ad, S.make_opts(6, 18, 1e-10, 2000, v0=torch.from_numpy(v0).cuda(),
+                                           flags=F.SVDS_FLAG_UNSORTED | F.SVDS_FLAG_NO_PANELS))
+    torch.cuda.synchronize()
+    assert ws["plain"] - r64.info["workspace_bytes"] >= 2 * per
+    assert ws["default"] > ws["plain"]
