@@ -944,7 +944,7 @@ static int alloc_arena(svds_plan *P) {
 // npanel = 1: the CSR of A^T; npanel > 1: the stacked transpose of the row
 // panels of A (rows_per_panel rows each), npanel n rows.
 static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int32_t *out_rp,
-                           int32_t *out_ci, void *out_val) {
+                           int32_t *out_ci, void *out_val, bool sync = true) {
   // the scratch lives in the plan's arena (transpose_scratch_words), so the
   // two transposes of a plan (A^T and its column-panel form) allocate nothing
   Operator &op = P->op;
@@ -994,7 +994,7 @@ static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int
                          static_cast<float *>(out_val));
     hipLaunchKernelGGL(csc_colptr_kernel, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz, n, kin, out_rp);
     if (hipGetLastError() != hipSuccess) { rc = SVDS_EDEVICE; break; }
-    if (hipStreamSynchronize(st) != hipSuccess) { rc = SVDS_EDEVICE; break; }
+    if (sync && hipStreamSynchronize(st) != hipSuccess) { rc = SVDS_EDEVICE; break; }
   } while (0);
   return rc;
 }
@@ -1017,14 +1017,17 @@ static int item_cap(const svds_plan *P) {
   return (P->opts.flags & SVDS_FLAG_ITEMS_1K) ? SPMV_TUNE_MIN_CAP : SPMV_NNZ_BLK;
 }
 
-static int upload_spmv(svds_plan *P, SpmvPlan &sp) {
+// Uploads the host work items.  Without sync the copies may still read
+// sp.h_items / sp.h_long when this returns: neither may change before the
+// stream is synchronized.
+static int upload_spmv(svds_plan *P, SpmvPlan &sp, bool sync = true) {
   HIP_TRY(hipMemcpyAsync(sp.items, sp.h_items.data(), sizeof(int4) * sp.nitems, hipMemcpyHostToDevice,
                          P->stream));
   if (sp.nlong) {
     HIP_TRY(hipMemcpyAsync(sp.longrows, sp.h_long.data(), sizeof(LongRow) * sp.nlong,
                            hipMemcpyHostToDevice, P->stream));
   }
-  HIP_TRY(hipStreamSynchronize(P->stream));
+  if (sync) HIP_TRY(hipStreamSynchronize(P->stream));
   return SVDS_OK;
 }
 
@@ -1106,7 +1109,11 @@ struct HostInts {
 };
 }  // namespace
 
-static int build_panels(svds_plan *P) {
+// Column-panel copy, first stage: its buffer, then the stacked transpose and
+// the read-back of its row pointers into hrp, enqueued on the plan's stream
+// with `done` recorded after them (the host meanwhile builds the items of
+// A^T).  SVDS_ENOMEM: no room for the copy, nothing enqueued.
+static int panels_begin(svds_plan *P, HostInts &hrp, hipEvent_t done) {
   Operator &op = P->op;
   const int np = op.npanel;
   const int64_t n = op.n, rows = n * np, nnz = std::max<int64_t>(1, op.nnz);
@@ -1129,11 +1136,21 @@ static int build_panels(svds_plan *P) {
   a.used = 0;
   a.counting = false;
   carve(a);
-  int rc = build_transpose(P, np, rpp, op.prp, op.pci, op.pval);
+  const int rc = build_transpose(P, np, rpp, op.prp, op.pci, op.pval, false);
   if (rc) return rc;
-  HostInts hrp;
   hrp.take(rows + 1);
-  HIP_TRY(hipMemcpy(hrp.data(), op.prp, sizeof(int32_t) * (rows + 1), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpyAsync(hrp.data(), op.prp, sizeof(int32_t) * (rows + 1), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipEventRecord(done, P->stream));
+  return SVDS_OK;
+}
+
+// Column-panel copy, second stage: once `done` has completed, the panel work
+// items (built on the host) and their upload, left in flight on the stream.
+static int panels_finish(svds_plan *P, HostInts &hrp, hipEvent_t done) {
+  Operator &op = P->op;
+  const int np = op.npanel;
+  const int64_t n = op.n;
+  HIP_TRY(hipEventSynchronize(done));
   // items per panel, built on one host thread per panel (rows relative to the
   // panel, nonzero offsets absolute), then renumbered: rows + g n, long rows
   // and pieces after those of the earlier panels
@@ -1217,7 +1234,7 @@ static int build_panels(svds_plan *P) {
   carve_items(b);
   // no column sort here: a panel's gathers come from an L2-sized slice and
   // its items rarely share cache lines (sorting cost 3% on such matrices)
-  return upload_spmv(P, sp);
+  return upload_spmv(P, sp, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -1443,7 +1460,10 @@ namespace {
 struct PlanGuard {
   svds_plan *p;
   ~PlanGuard() {
-    if (p) svds_plan_destroy(p);
+    if (!p) return;
+    // work of the failed creation may still be in flight on its buffers
+    (void)hipStreamSynchronize(p->stream);
+    svds_plan_destroy(p);
   }
   svds_plan *release() {
     svds_plan *q = p;
@@ -1535,6 +1555,29 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   HostInts htrp;
   htrp.take(A->n + 1);
   HIP_TRY(hipMemcpy(htrp.data(), op.trp, sizeof(int32_t) * (A->n + 1), hipMemcpyDeviceToHost));
+  // The column-panel copy is built on the device while the host builds the
+  // items of A^T, and its items are built on the host while the device sorts
+  // the items of A and A^T.
+  struct EventGuard {
+    hipEvent_t e = nullptr;
+    ~EventGuard() {
+      if (e) (void)hipEventDestroy(e);
+    }
+  } pdone;
+  HostInts hprp;
+  auto drop_panels = [&]() {  // no room for the panel copy: the plain transpose product serves
+    if (op.pbuf) (void)hipFree(op.pbuf);
+    if (op.pbuf_items) (void)hipFree(op.pbuf_items);
+    op.pbuf = op.pbuf_items = nullptr;
+    op.pbuf_bytes = 0;
+    op.npanel = 1;
+  };
+  if (op.npanel > 1) {
+    HIP_TRY(hipEventCreateWithFlags(&pdone.e, hipEventDisableTiming));
+    rc = panels_begin(P, hprp, pdone.e);
+    if (rc == SVDS_ENOMEM) drop_panels();
+    else if (rc) return rc;
+  }
   int4 *bi = op.bwd.items;
   LongRow *bl = op.bwd.longrows;
   double *bp = op.bwd.partials;
@@ -1553,17 +1596,15 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   op.fwd.nitems = fwd_items.nitems;
   op.fwd.nlong = fwd_items.nlong;
   op.fwd.npieces = fwd_items.npieces;
-  if ((rc = upload_spmv(P, op.fwd)) || (rc = upload_spmv(P, op.bwd))) return rc;
+  if ((rc = upload_spmv(P, op.fwd, false)) || (rc = upload_spmv(P, op.bwd, false))) return rc;
   if ((rc = sort_spmv(P, op.fwd, op.ci, op.val)) || (rc = sort_spmv(P, op.bwd, op.tci, op.tval))) return rc;
-  if (op.npanel > 1 && (rc = build_panels(P))) {
-    // no room for the panel copy: the plain transpose product (row order) serves
+  if (op.npanel > 1 && (rc = panels_finish(P, hprp, pdone.e))) {
     if (rc != SVDS_ENOMEM) return rc;
-    if (op.pbuf) (void)hipFree(op.pbuf);
-    if (op.pbuf_items) (void)hipFree(op.pbuf_items);
-    op.pbuf = op.pbuf_items = nullptr;
-    op.pbuf_bytes = 0;
-    op.npanel = 1;
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    drop_panels();
   }
+  // the uploads above read the host item lists, which the tuner rebuilds
+  HIP_TRY(hipStreamSynchronize(P->stream));
   if ((opts->flags & SVDS_FLAG_AUTOTUNE) && (rc = autotune(P, hrp.data(), htrp.data(), seg_rows, seg_cols, nseg)))
     return rc;
   if (P->mixed && op.vt == SVDS_F64 && op.nnz > 0 && (rc = build_values32(P))) return rc;
