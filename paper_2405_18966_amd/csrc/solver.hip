@@ -1136,9 +1136,9 @@ static int panels_begin(svds_plan *P, HostInts &hrp, hipEvent_t done) {
   a.used = 0;
   a.counting = false;
   carve(a);
+  hrp.take(rows + 1);  // before the launches: pinning may wait for the device
   const int rc = build_transpose(P, np, rpp, op.prp, op.pci, op.pval, false);
   if (rc) return rc;
-  hrp.take(rows + 1);
   HIP_TRY(hipMemcpyAsync(hrp.data(), op.prp, sizeof(int32_t) * (rows + 1), hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipEventRecord(done, P->stream));
   return SVDS_OK;
