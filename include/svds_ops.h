@@ -31,7 +31,10 @@ int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *x_scale, co
  * entries) and A^T has enough entries per row, the column-panel form
  * (sum over row panels A_g of A of A_g^T x_g, each XCD gathering from one
  * slice of x; partial sums added in panel order).  x has op(A)'s column
- * count, yprev and y its row count; device vectors of `basis_dtype`.
+ * count, yprev and y its row count; device vectors of `basis_dtype`.  With
+ * FP32 vectors the plan is a mixed-precision one, so FP64 values are read
+ * from its FP32 copies (rounded to nearest), as in the FP32 cycles of a
+ * mixed solve.
  * x_scale, coef: DEVICE pointers to one double each, or NULL as in
  * svds_op_spmv_csr.  *panels (host, may be NULL) receives the number of
  * column panels used (1 = the plain product).  A needs m >= 2, n >= 3
