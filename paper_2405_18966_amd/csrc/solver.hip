@@ -1565,6 +1565,16 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
     }
   } pdone;
   HostInts hprp;
+  // declared after hprp, so destroyed before it: on an early return the
+  // read-back into hprp may still be in flight when hprp goes back to the
+  // process-wide cache
+  struct Drain {
+    hipStream_t s;
+    bool armed;
+    ~Drain() {
+      if (armed) (void)hipStreamSynchronize(s);
+    }
+  } drain{P->stream, false};
   auto drop_panels = [&]() {  // no room for the panel copy: the plain transpose product serves
     if (op.pbuf) (void)hipFree(op.pbuf);
     if (op.pbuf_items) (void)hipFree(op.pbuf_items);
@@ -1574,6 +1584,7 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   };
   if (op.npanel > 1) {
     HIP_TRY(hipEventCreateWithFlags(&pdone.e, hipEventDisableTiming));
+    drain.armed = true;
     rc = panels_begin(P, hprp, pdone.e);
     if (rc == SVDS_ENOMEM) drop_panels();
     else if (rc) return rc;
