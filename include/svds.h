@@ -27,10 +27,13 @@
  *     [row_ptr[i], row_ptr[i+1]) of col_idx/val, column indices strictly
  *     increasing within a row (the paper's `mat_csr` is the 1-based,
  *     pointerB/pointerE form of the same thing).
- *   - The caller owns every input and output buffer.  The library owns only
- *     the workspace of a plan (bases, transposed copy of A, T, scratch),
- *     allocated once at plan creation (as the paper allocates all buffers at
- *     the start, Sec. 2.2.2) and freed by svds_plan_destroy.
+ *   - The caller owns every input and output buffer.  The library owns the
+ *     device workspace of a plan (bases, transposed copies of A, FP32 value
+ *     copies of a mixed plan, T, scratch), allocated at plan creation (as the
+ *     paper allocates all buffers at the start, Sec. 2.2.2) and freed by
+ *     svds_plan_destroy, and process-wide caches of timing events and of the
+ *     pinned host buffers that plan creation reads row pointers into, kept
+ *     until the process ends (at most 512 MiB of pinned memory).
  *   - Return codes: 0 = success, 1 = SVDS_NOT_CONVERGED (outputs hold the
  *     current Ritz triplets; info->nconv of the leading ones meet tol),
  *     negative = error, outputs untouched.  Nothing is thrown across the ABI.
