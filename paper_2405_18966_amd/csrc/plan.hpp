@@ -155,15 +155,16 @@ struct Operator {
   void *tval = nullptr;
   SpmvPlan fwd, bwd;
   // A^T u by column panels (see spmv_panel_sum_kernel): npanel > 1 for a
-  // single problem whose u is large; stacked CSR (npanel n rows), partial
-  // products (npanel n), work items; in their own allocations
+  // single problem whose u is large; stacked CSR (npanel n rows) and partial
+  // products (npanel n) in the arena, work items in their own allocation
+  // (their count is known only once they are built)
   int npanel = 1;
   int32_t *prp = nullptr, *pci = nullptr;
   void *pval = nullptr;
   double *ypart = nullptr;
   SpmvPlan bwdp;
-  void *pbuf = nullptr, *pbuf_items = nullptr;
-  size_t pbuf_bytes = 0;
+  void *pbuf_items = nullptr;
+  size_t pbuf_bytes = 0;  // bytes of pbuf_items
   // FP32 copies of the values of an FP64-stored CSR matrix for the FP32 phase
   // of a mixed solve (A, A^T, the column-sorted copies, the panel copy; null
   // where that array does not exist); one allocation, v32buf

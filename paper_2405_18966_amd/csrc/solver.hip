@@ -899,7 +899,7 @@ static int carve_all(svds_plan *P, Arena &a) {
     P->rs_lpart = a.take<double>(static_cast<size_t>(std::max(1, std::max(P->op.fwd.nlong, P->op.bwd.nlong))) * RG);
     P->rs_s = a.take<double>(RG);
     // column-sorted copies for the products: A always, A^T unless the
-    // column-panel form replaces it (that one is sorted in place)
+    // column-panel form (unsorted) replaces it
     const int64_t nz = std::max<int64_t>(1, P->op.nnz);
     const size_t vb = static_cast<size_t>(vsize(P->op.vt));
     P->op.fwd.scol = a.take<int32_t>(nz);
@@ -914,6 +914,13 @@ static int carve_all(svds_plan *P, Arena &a) {
     P->op.trp = a.take<int32_t>(n + 1);
     P->op.tci = a.take<int32_t>(std::max<int64_t>(1, P->op.nnz));
     P->op.tval = a.take<char>(std::max<int64_t>(1, P->op.nnz) * static_cast<size_t>(vsize(P->op.vt)));
+    if (P->op.npanel > 1) {  // column-panel copy of A^T (see panels_begin) and its partial products
+      const int64_t prows = n * P->op.npanel;
+      P->op.prp = a.take<int32_t>(prows + 1);
+      P->op.pci = a.take<int32_t>(nz);
+      P->op.pval = a.take<char>(nz * vb);
+      P->op.ypart = a.take<double>(prows);
+    }
   }
   return SVDS_OK;
 }
@@ -1109,33 +1116,15 @@ struct HostInts {
 };
 }  // namespace
 
-// Column-panel copy, first stage: its buffer, then the stacked transpose and
-// the read-back of its row pointers into hrp, enqueued on the plan's stream
-// with `done` recorded after them (the host meanwhile builds the items of
-// A^T).  SVDS_ENOMEM: no room for the copy, nothing enqueued.
+// Column-panel copy, first stage: the stacked transpose (into the arrays the
+// arena holds for it) and the read-back of its row pointers into hrp,
+// enqueued on the plan's stream with `done` recorded after them (the host
+// meanwhile builds the items of A^T).
 static int panels_begin(svds_plan *P, HostInts &hrp, hipEvent_t done) {
   Operator &op = P->op;
   const int np = op.npanel;
-  const int64_t n = op.n, rows = n * np, nnz = std::max<int64_t>(1, op.nnz);
+  const int64_t rows = op.n * np;
   const int64_t rpp = ceil_div(op.m, np);
-  Arena a;
-  auto carve = [&](Arena &ar) {
-    op.prp = ar.take<int32_t>(rows + 1);
-    op.pci = ar.take<int32_t>(nnz);
-    op.pval = ar.take<char>(nnz * static_cast<size_t>(vsize(op.vt)));
-    op.ypart = ar.take<double>(rows);
-  };
-  carve(a);
-  if (hipMalloc(&op.pbuf, a.used) != hipSuccess) {
-    (void)hipGetLastError();
-    op.pbuf = nullptr;
-    return SVDS_ENOMEM;
-  }
-  op.pbuf_bytes = a.used;
-  a.base = static_cast<char *>(op.pbuf);
-  a.used = 0;
-  a.counting = false;
-  carve(a);
   hrp.take(rows + 1);  // before the launches: pinning may wait for the device
   const int rc = build_transpose(P, np, rpp, op.prp, op.pci, op.pval, false);
   if (rc) return rc;
@@ -1329,10 +1318,9 @@ static int tune_product(svds_plan *P, EventPair &ev, bool trans, const int32_t *
   if (best_cap != caps[1] && (rc = tune_build_items(P, trans, hrp, rows, seg, nseg, best_cap))) return rc;
   sp.sorted = best_sorted;
   op.npanel = best_panels;
-  if (npanel > 1 && best_panels == 1) {  // the panel copy is not used: release it
-    if (op.pbuf) (void)hipFree(op.pbuf);
+  if (npanel > 1 && best_panels == 1) {  // the panel items are not used: release them
     if (op.pbuf_items) (void)hipFree(op.pbuf_items);
-    op.pbuf = op.pbuf_items = nullptr;
+    op.pbuf_items = nullptr;
     op.pbuf_bytes = 0;
   }
   svds_tuning &tu = P->tuning;
@@ -1550,7 +1538,13 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   set_caps(op.bwd, A->n, A->nnz);
   const int fwd_items_cap = op.fwd.nitems, fwd_long_cap = op.fwd.nlong, fwd_pieces_cap = op.fwd.npieces;
   const int bwd_items_cap = op.bwd.nitems, bwd_long_cap = op.bwd.nlong, bwd_pieces_cap = op.bwd.npieces;
-  if ((rc = alloc_arena(P))) return rc;
+  rc = alloc_arena(P);
+  if (rc == SVDS_ENOMEM && op.npanel > 1) {
+    // no room with the column-panel copy: the plain transpose product serves
+    op.npanel = 1;
+    rc = alloc_arena(P);
+  }
+  if (rc) return rc;
   if ((rc = build_transpose(P, 1, op.m, op.trp, op.tci, op.tval))) return rc;
   HostInts htrp;
   htrp.take(A->n + 1);
@@ -1575,19 +1569,16 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
       if (armed) (void)hipStreamSynchronize(s);
     }
   } drain{P->stream, false};
-  auto drop_panels = [&]() {  // no room for the panel copy: the plain transpose product serves
-    if (op.pbuf) (void)hipFree(op.pbuf);
+  auto drop_panels = [&]() {  // no room for the panel items: the plain transpose product serves
     if (op.pbuf_items) (void)hipFree(op.pbuf_items);
-    op.pbuf = op.pbuf_items = nullptr;
+    op.pbuf_items = nullptr;
     op.pbuf_bytes = 0;
     op.npanel = 1;
   };
   if (op.npanel > 1) {
     HIP_TRY(hipEventCreateWithFlags(&pdone.e, hipEventDisableTiming));
     drain.armed = true;
-    rc = panels_begin(P, hprp, pdone.e);
-    if (rc == SVDS_ENOMEM) drop_panels();
-    else if (rc) return rc;
+    if ((rc = panels_begin(P, hprp, pdone.e))) return rc;
   }
   int4 *bi = op.bwd.items;
   LongRow *bl = op.bwd.longrows;
@@ -1662,7 +1653,6 @@ extern "C" int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts
 extern "C" void svds_plan_destroy(svds_plan *P) {
   if (!P) return;
   if (P->arena.base) (void)hipFree(P->arena.base);
-  if (P->op.pbuf) (void)hipFree(P->op.pbuf);
   if (P->op.pbuf_items) (void)hipFree(P->op.pbuf_items);
   if (P->op.v32buf) (void)hipFree(P->op.v32buf);
   if (P->h_flags) (void)hipHostFree(P->h_flags);
