@@ -280,6 +280,14 @@ int svds_csr_solve_batched(int32_t count, const svds_csr *As, const svds_opts *o
 int svds_residuals_csr(const svds_csr *A, int32_t k, const double *U, const double *S,
                        const double *V, double *res_av, double *res_atu, void *stream);
 
+/* The same for a dense A (column-major, F64/F32/BF16 storage widened
+ * exactly): both sides are FP64 block products over all k triplets at once
+ * (one pass over the stored A per side, FP64 matrix cores), with the
+ * partial sums added in a fixed order.  k + 1 <= m and k + 2 <= n, else
+ * EINVAL.  Synchronous on `stream`. */
+int svds_residuals_dense(const svds_dense *A, int32_t k, const double *U, const double *S,
+                         const double *V, double *res_av, double *res_atu, void *stream);
+
 const char *svds_strerror(int code);
 
 /* Library version string. */

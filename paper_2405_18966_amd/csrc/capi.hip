@@ -57,6 +57,24 @@ extern "C" int svds_residuals_csr(const svds_csr *A, int32_t k, const double *U,
   SVDS_ABI_CATCH
 }
 
+extern "C" int svds_residuals_dense(const svds_dense *A, int32_t k, const double *U, const double *S,
+                                    const double *V, double *res_av, double *res_atu, void *stream) {
+  SVDS_ABI_TRY
+  if (!A || k < 1 || !U || !S || !V || !res_av || !res_atu) return SVDS_EINVAL;
+  if (A->m < k + 1 || A->n < k + 2) return SVDS_EINVAL;
+  svds_opts o{};
+  o.k = k;  // the plan's residual scratch is sized for k triplets
+  o.p = k + 1;
+  o.stream = stream;
+  svds_plan *P = nullptr;
+  int rc = svds_plan_create_dense(A, &o, &P);
+  if (rc) return rc;
+  rc = svds_plan_residuals(P, k, U, S, V, res_av, res_atu);
+  svds_plan_destroy(P);
+  return rc;
+  SVDS_ABI_CATCH
+}
+
 extern "C" const char *svds_strerror(int code) {
   switch (code) {
     case SVDS_OK: return "ok";

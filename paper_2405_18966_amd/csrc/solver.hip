@@ -14,7 +14,6 @@
 #include <utility>
 
 #include <hip/hip_ext.h>
-#include <rocblas/rocblas.h>
 
 #include "plan.hpp"
 #include "kernels_cgs.hpp"
@@ -297,9 +296,9 @@ struct svds_plan {
   // residual panels (CSR plans): row-major RG-column panels of U and V, partials
   double *rs_pu = nullptr, *rs_pv = nullptr, *rs_part = nullptr, *rs_pieces = nullptr, *rs_lpart = nullptr,
          *rs_s = nullptr;
-  // dense residuals: R1 (m x k), R2 (n x k), exact FP64 copy of a low-precision A
-  double *dr1 = nullptr, *dr2 = nullptr, *da64 = nullptr;
-  bool da64_ready = false;
+  // dense residuals: partial tiles of the block products and column partials
+  // (resid_dense_doubles)
+  double *rd_part = nullptr;
   int *h_flags = nullptr;    // pinned
   Accounting acc;
   int64_t n_spmv = 0, n_spmvT = 0;
@@ -879,11 +878,7 @@ static int carve_all(svds_plan *P, Arena &a) {
   if (P->mixed) P->tmp_nk = a.take<double>(static_cast<size_t>(n) * k);
   if (P->op.dense) {
     P->op.dpart = a.take<double>(dense_partial_doubles(m, n));
-    if (!(P->opts.flags & SVDS_FLAG_NO_RESIDUALS)) {
-      P->dr1 = a.take<double>(static_cast<size_t>(m) * k);
-      P->dr2 = a.take<double>(static_cast<size_t>(n) * k);
-      if (P->op.vt != SVDS_F64) P->da64 = a.take<double>(static_cast<size_t>(m) * n);
-    }
+    if (!(P->opts.flags & SVDS_FLAG_NO_RESIDUALS)) P->rd_part = a.take<double>(resid_dense_doubles(m, n, k));
   } else {
     P->op.fwd.partials = a.take<double>(std::max(1, P->op.fwd.npieces));
     P->op.fwd.items = a.take<int4>(P->op.fwd.nitems);
@@ -1858,66 +1853,78 @@ static int residuals_csr_block(svds_plan *P, int k, const double *U, const doubl
   return SVDS_OK;
 }
 
-// rocBLAS handle per device, created on first use and kept for the process
-// (creation loads the library's kernels); calls are serialized by a mutex.
-static std::mutex g_blas_mu;
-static rocblas_handle g_blas[64] = {};
+// One side of the dense residuals: res[j] = |op(A) X(:, j) - S[j] Sub(:, j)|,
+// op(A) = A (X = V, Sub = U) or A^T (X = U, Sub = V); see resid_gemm_kernel.
+template <typename TV, bool TRANS>
+static int residuals_dense_side(svds_plan *P, int k, const double *X, int64_t ldx, const double *Sub,
+                                int64_t ldsub, const double *S, double *res) {
+  const Operator &op = P->op;
+  const int64_t M = TRANS ? op.n : op.m, K = TRANS ? op.m : op.n;
+  const TV *A = static_cast<const TV *>(op.a);
+  int nsplit;
+  int64_t kslice;
+  resid_split(M, K, nsplit, kslice);
+  const int nrb = static_cast<int>(ceil_div(M, RD_BM));
+  double *part = P->rd_part;
+  double *colpart = part + static_cast<int64_t>(nrb) * nsplit * RD_TILE;
+  const bool vec = dense_vec_ok<TV, double>(A, op.lda, X) && (ldx % 2) == 0;
+  const dim3 gg(nrb, nsplit);
+  for (int g0 = 0; g0 < k; g0 += RD_BN) {
+    const int kc = std::min(RD_BN, k - g0);
+    const int nt = static_cast<int>(ceil_div(kc, 16));
+    const double *Xg = X + g0 * ldx;
+    if (!vec) {
+      hipLaunchKernelGGL((resid_gemm_kernel<TV, TRANS, false, 8>), gg, dim3(RD_THREADS), 0, P->stream, M, K, A,
+                         op.lda, Xg, ldx, kc, kslice, part);
+    } else {
+      switch (nt) {
+#define RD_GO(NT)                                                                                              \
+  case NT:                                                                                                     \
+    hipLaunchKernelGGL((resid_gemm_kernel<TV, TRANS, true, NT>), gg, dim3(RD_THREADS), 0, P->stream, M, K, A, \
+                       op.lda, Xg, ldx, kc, kslice, part);                                                     \
+    break;
+        RD_GO(1) RD_GO(2) RD_GO(3) RD_GO(4) RD_GO(5) RD_GO(6) RD_GO(7) RD_GO(8)
+#undef RD_GO
+      }
+    }
+    LAUNCH_CHECK();
+    switch (nt) {
+#define RD_FIN(NT)                                                                                                 \
+  case NT:                                                                                                         \
+    hipLaunchKernelGGL((resid_finish_kernel<NT>), dim3(nrb), dim3(RD_THREADS), 0, P->stream, M, nsplit, nrb, part, \
+                       Sub, ldsub, S, g0, kc, colpart, k);                                                        \
+    break;
+      RD_FIN(1) RD_FIN(2) RD_FIN(3) RD_FIN(4) RD_FIN(5) RD_FIN(6) RD_FIN(7) RD_FIN(8)
+#undef RD_FIN
+    }
+    LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(resid_colnorm_kernel, dim3(k), dim3(256), 0, P->stream, nrb, colpart, k, res);
+  LAUNCH_CHECK();
+  return SVDS_OK;
+}
 
-// Dense residuals: R1 = A V - U diag(S), R2 = A^T U - V diag(S) as two FP64
-// GEMMs (one pass over A each, all k triplets), then column norms.
+// Dense residuals: R1 = A V - U diag(S), R2 = A^T U - V diag(S), one pass of
+// the FP64 matrix-core block product over the stored A per side (all k
+// triplets at once), then column norms.
 static int residuals_dense(svds_plan *P, int k, const double *U, const double *S, const double *V,
                            double *res_av, double *res_atu) {
   const Operator &op = P->op;
   const int64_t m = op.m, n = op.n;
-  const double *A = nullptr;
-  int64_t lda = m;
-  if (op.vt == SVDS_F64) {
-    A = static_cast<const double *>(op.a);
-    lda = op.lda;
-  } else {
-    if (!P->da64) return SVDS_EUNSUPPORTED;
-    if (!P->da64_ready) {
-      const unsigned g = static_cast<unsigned>(std::min<int64_t>(8192, ceil_div(m * n, 256)));
-      if (op.vt == SVDS_F32)
-        hipLaunchKernelGGL((widen_dense_kernel<float>), dim3(g), dim3(256), 0, P->stream, m, n,
-                           static_cast<const float *>(op.a), op.lda, P->da64);
-      else
-        hipLaunchKernelGGL((widen_dense_kernel<uint16_t>), dim3(g), dim3(256), 0, P->stream, m, n,
-                           static_cast<const uint16_t *>(op.a), op.lda, P->da64);
-      LAUNCH_CHECK();
-      P->da64_ready = true;
-    }
-    A = P->da64;
-  }
+  if (!P->rd_part) return SVDS_EUNSUPPORTED;
   ACC_BEFORE(SVDS_KC_OTHER);
-  hipLaunchKernelGGL(scale_cols_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(4096, ceil_div(m * k, 256)))),
-                     dim3(256), 0, P->stream, m, k, U, S, P->dr1);
-  LAUNCH_CHECK();
-  {
-    std::lock_guard<std::mutex> lock(g_blas_mu);
-    rocblas_handle &h = g_blas[P->device & 63];
-    if (!h && rocblas_create_handle(&h) != rocblas_status_success) return SVDS_EDEVICE;
-    if (rocblas_set_stream(h, P->stream) != rocblas_status_success) return SVDS_EDEVICE;
-    const double one = 1.0, mone = -1.0;
-    if (rocblas_set_pointer_mode(h, rocblas_pointer_mode_host) != rocblas_status_success) return SVDS_EDEVICE;
-    if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, static_cast<rocblas_int>(m), k,
-                      static_cast<rocblas_int>(n), &one, A, static_cast<rocblas_int>(lda), V,
-                      static_cast<rocblas_int>(n), &mone, P->dr1, static_cast<rocblas_int>(m)) !=
-        rocblas_status_success)
-      return SVDS_EDEVICE;
-    // A^T U as (U^T A)^T: rocBLAS's kernels for an untransposed A run ~3x faster
-    // here than those for A^T (measured 1.2 ms against 3.3 ms, 20000 x 10000,
-    // k = 100); C = U^T A is k x n, row j = (A^T u_j)^T
-    const double zero = 0.0;
-    if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, k, static_cast<rocblas_int>(n),
-                      static_cast<rocblas_int>(m), &one, U, static_cast<rocblas_int>(m), A,
-                      static_cast<rocblas_int>(lda), &zero, P->dr2, k) != rocblas_status_success)
-      return SVDS_EDEVICE;
+  int rc;
+  if (op.vt == SVDS_F64) {
+    if ((rc = residuals_dense_side<double, false>(P, k, V, n, U, m, S, res_av))) return rc;
+    if ((rc = residuals_dense_side<double, true>(P, k, U, m, V, n, S, res_atu))) return rc;
+  } else if (op.vt == SVDS_F32) {
+    if ((rc = residuals_dense_side<float, false>(P, k, V, n, U, m, S, res_av))) return rc;
+    if ((rc = residuals_dense_side<float, true>(P, k, U, m, V, n, S, res_atu))) return rc;
+  } else {
+    if ((rc = residuals_dense_side<uint16_t, false>(P, k, V, n, U, m, S, res_av))) return rc;
+    if ((rc = residuals_dense_side<uint16_t, true>(P, k, U, m, V, n, S, res_atu))) return rc;
   }
-  hipLaunchKernelGGL(col_norms_kernel, dim3(k), dim3(256), 0, P->stream, m, P->dr1, res_av);
-  hipLaunchKernelGGL(row_resid_norms_kernel, dim3(k), dim3(256), 0, P->stream, n, k, P->dr2, V, S, res_atu);
-  LAUNCH_CHECK();
-  ACC_AFTER(SVDS_KC_OTHER, 2.0 * 8.0 * m * n, 4.0 * m * n * k);
+  ACC_AFTER(SVDS_KC_OTHER, 2.0 * vsize(op.vt) * m * n + 16.0 * (m + n) * k, 4.0 * m * n * k);
   return SVDS_OK;
 }
 
@@ -1925,8 +1932,7 @@ static int residuals_impl(svds_plan *P, int k, const double *U, const double *S,
                           double *res_av, double *res_atu) {
   const int64_t m = P->op.m, n = P->op.n;
   const int64_t sv = P->n_spmv, st = P->n_spmvT;
-  if (P->op.dense && P->dr1 && m < (int64_t(1) << 31) && n < (int64_t(1) << 31) && P->op.lda < (int64_t(1) << 31))
-    return residuals_dense(P, k, U, S, V, res_av, res_atu);
+  if (P->op.dense && P->rd_part) return residuals_dense(P, k, U, S, V, res_av, res_atu);
   if (!P->op.dense && P->rs_pu) {
     return P->op.vt == SVDS_F64 ? residuals_csr_block<double>(P, k, U, S, V, res_av, res_atu)
                                 : residuals_csr_block<float>(P, k, U, S, V, res_av, res_atu);

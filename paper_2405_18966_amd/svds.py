@@ -96,6 +96,7 @@ def _load():
         "svds_csr_solve_batched": (i32, [i32, P(svds_csr), P(svds_opts), P(vp), P(vp), P(vp),
                                          P(svds_info)]),
         "svds_residuals_csr": (i32, [P(svds_csr), i32, vp, vp, vp, vp, vp, vp]),
+        "svds_residuals_dense": (i32, [P(svds_dense), i32, vp, vp, vp, vp, vp, vp]),
         "svds_strerror": (C.c_char_p, [i32]),
         "svds_version": (C.c_char_p, []),
         "svds_op_spmv_csr": (i32, [P(svds_csr), vp, vp, vp, vp, vp, i32, vp]),
@@ -262,6 +263,18 @@ def svds_residuals_csr(A: svds_csr, U: torch.Tensor, S: torch.Tensor, V: torch.T
     r2 = torch.empty(k, dtype=torch.float64, device=S.device)
     _check(lib.svds_residuals_csr(C.byref(A), k, _ptr(Uc), _ptr(S), _ptr(Vc), _ptr(r1), _ptr(r2),
                                   _stream(stream)), "svds_residuals_csr")
+    return r1, r2
+
+
+def svds_residuals_dense(A: svds_dense, U: torch.Tensor, S: torch.Tensor, V: torch.Tensor, stream=None):
+    """(|A v_j - s_j u_j|, |A^T u_j - s_j v_j|) for a dense A and column-major U (m x k), V (n x k)."""
+    k = S.numel()
+    Uc = U.T.contiguous()
+    Vc = V.T.contiguous()
+    r1 = torch.empty(k, dtype=torch.float64, device=S.device)
+    r2 = torch.empty(k, dtype=torch.float64, device=S.device)
+    _check(lib.svds_residuals_dense(C.byref(A), k, _ptr(Uc), _ptr(S), _ptr(Vc), _ptr(r1), _ptr(r2),
+                                    _stream(stream)), "svds_residuals_dense")
     return r1, r2
 
 

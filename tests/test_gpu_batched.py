@@ -1,6 +1,8 @@
 """Batched (lockstep) solver: many uneven CSR problems in one call, each
 against the FP64 CPU oracle run on that problem alone with the same start
 vector (Philox stream 0 of seed + problem index)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -9,6 +11,7 @@ from oracle import svds_ref
 from oracle.svds_ref import as_operator
 
 pytestmark = pytest.mark.gpu
+GOLDEN_W5 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "workload5_sigma.txt")
 
 
 @pytest.fixture(scope="module")
@@ -121,25 +124,47 @@ def test_batched_validation(S):
         _batch(S, As, 5, 70, 1e-8)  # p > 62: one-workgroup small SVD only
 
 
-def test_batched_full_size_256_problems(S):
+def _golden_w5():
+    rows = {}
+    for line in open(GOLDEN_W5):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        rows[int(f[0])] = (int(f[1]), int(f[2]), int(f[3]), np.array([float(x) for x in f[5:]]))
+    return rows
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN_W5), reason="stored oracle values not generated")
+@pytest.mark.parametrize("precision,rtol", [(1, 1e-8), (0, 1e-10)])
+def test_batched_full_size_256_problems(S, precision, rtol):
     """The 256-problem workload (m ~ U{500..20000}, n ~ U{m/2..m}, 0.5%
-    density, k=8, p=24, mixed): every problem's outputs checked by
-    orthogonality and by the library's FP64 residuals, a sample of problems
-    against the oracle."""
-    As = inputs.config_matrix(5)
-    k, p, tol, seed = 8, 24, 1e-8, 2405005
-    res, rc = _batch(S, As, k, p, tol, precision=1, seed=seed)
-    assert rc == 0
-    for r in res:
-        assert r.info["converged"] == 1 and r.info["max_res_true"] <= 2 * tol
+    density, k=8, p=24, tol=1e-8), mixed and FP64: every problem's singular
+    values against the stored oracle values of that problem solved alone
+    (tests/golden/make_workload5_sigma.py), every problem's U and V
+    orthonormal, every problem's FP64 residuals within tol."""
     import torch
-    for b in [0, 1, 37, 128, 255]:
-        Ug, Vg = res[b].U, res[b].V
-        eye = torch.eye(k, dtype=torch.float64, device=Ug.device)
-        assert float((Ug.T @ Ug - eye).abs().max()) <= 1e-12
-        assert float((Vg.T @ Vg - eye).abs().max()) <= 1e-12
-        Ur, Sr, Vr, info = svds_ref.svds(as_operator(As[b]), k, p, 1e-12, 2000, seed=seed + b)
-        np.testing.assert_allclose(res[b].S.cpu().numpy(), Sr, rtol=1e-8)
+    print(f"batched full size, precision {precision}", flush=True)
+    As = inputs.config_matrix(5)
+    gold = _golden_w5()
+    assert sorted(gold) == list(range(256))
+    k, p, tol, seed = 8, 24, 1e-8, 2405005
+    res, rc = _batch(S, As, k, p, tol, precision=precision, seed=seed)
+    assert rc == 0
+    eye = None
+    worst = 0.0
+    for b, (A, r) in enumerate(zip(As, res)):
+        m, n, nnz, sig = gold[b]
+        assert (A.m, A.n, A.nnz) == (m, n, nnz), b
+        assert r.info["converged"] == 1 and r.info["max_res_true"] <= 2 * tol, b
+        Ug, Vg = r.U, r.V
+        if eye is None:
+            eye = torch.eye(k, dtype=torch.float64, device=Ug.device)
+        assert float((Ug.T @ Ug - eye).abs().max()) <= 1e-12, b
+        assert float((Vg.T @ Vg - eye).abs().max()) <= 1e-12, b
+        err = float(np.max(np.abs(r.S.cpu().numpy() - sig) / sig))
+        worst = max(worst, err)
+        assert err <= rtol, (b, err)
+    print(f"largest sigma rel. err over 256 problems: {worst:.2e}", flush=True)
 
 
 def test_batched_fp32_values(S):

@@ -452,3 +452,51 @@ def test_block_residuals_match_numpy(S, k, vdt):
     e2 = np.linalg.norm(Asp.T @ U - V * s, axis=0)
     np.testing.assert_allclose(r1.cpu().numpy(), e1, rtol=1e-12)
     np.testing.assert_allclose(r2.cpu().numpy(), e2, rtol=1e-12)
+
+
+@pytest.mark.parametrize("m,n,k", [(1000, 700, 20), (513, 257, 7), (300, 2000, 150), (1001, 333, 9), (4100, 97, 1)])
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+def test_dense_block_residuals_match_numpy(S, m, n, k, store):
+    """|A v_j - s_j u_j| and |A^T u_j - s_j v_j| of the dense form for arbitrary
+    (not singular) triplets: FP64 matrix-core block products over the stored
+    matrix.  Ragged row blocks and K chunks, two column groups (k = 150), an
+    odd leading dimension (element-wise loads) and k = 1."""
+    import torch
+    rng = np.random.default_rng(m * 7 + n + k)
+    A = rng.standard_normal((m, n))
+    if store == "f64":
+        rec = np.asfortranarray(A)
+        at = _t(rec.ravel(order="F"))
+    elif store == "f32":
+        a = np.asfortranarray(A.astype(np.float32))
+        rec = a.astype(np.float64)
+        at = _t(a.ravel(order="F"))
+    else:
+        bits = inputs._f32_to_bf16_bits(np.asfortranarray(A.astype(np.float32)))
+        rec = inputs.bf16_bits_to_f64(bits)
+        at = _t(np.asfortranarray(bits).ravel(order="F").view(np.int16)).view(torch.bfloat16)
+    Ad = S.make_dense(at, m, n)
+    U = rng.standard_normal((m, k))
+    V = rng.standard_normal((n, k))
+    s = rng.uniform(1, 2, k)
+    r1, r2 = S.svds_residuals_dense(Ad, _t(U), _t(s), _t(V))
+    e1 = np.linalg.norm(rec @ V - U * s, axis=0)
+    e2 = np.linalg.norm(rec.T @ U - V * s, axis=0)
+    np.testing.assert_allclose(r1.cpu().numpy(), e1, rtol=1e-12)
+    np.testing.assert_allclose(r2.cpu().numpy(), e2, rtol=1e-12)
+
+
+def test_dense_block_residuals_of_exact_triplets(S):
+    """Exact singular triplets of a prescribed-spectrum matrix: the residuals
+    are at rounding level (no cancellation left uncovered)."""
+    import torch
+    sig = inputs.decay2(200)
+    A = inputs.prescribed_dense_dct(700, 500, sig, seed=5)
+    Uf, sf, Vtf = np.linalg.svd(A, full_matrices=False)
+    k = 40
+    Ad = S.make_dense(_t(np.asfortranarray(A).ravel(order="F")), 700, 500)
+    r1, r2 = S.svds_residuals_dense(Ad, _t(Uf[:, :k]), _t(sf[:k]), _t(Vtf[:k].T))
+    e1 = np.linalg.norm(A @ Vtf[:k].T - Uf[:, :k] * sf[:k], axis=0)
+    e2 = np.linalg.norm(A.T @ Uf[:, :k] - Vtf[:k].T * sf[:k], axis=0)
+    assert np.abs(r1.cpu().numpy() - e1).max() <= 1e-13 * sf[0]
+    assert np.abs(r2.cpu().numpy() - e2).max() <= 1e-13 * sf[0]

@@ -111,19 +111,19 @@ def _golden(path):
     return np.array([float(x) for x in open(path) if x.strip() and not x.startswith("#")])
 
 
-@pytest.mark.skipif(not os.path.exists(GOLDEN_W3), reason="stored oracle values not generated")
-def test_mixed_dense_bf16_full_size_against_stored_oracle(S):
+def _full_size_w3(S, precision, rtol):
     """Workload 3 at full size: 20000 x 10000 dense BF16, k=100, p=250,
-    tol=1e-8, mixed path; singular values against the stored FP64 oracle
-    values of the widened BF16 matrix, outputs orthonormal, and residuals
-    checked on the device in FP64 by an independent torch computation."""
+    tol=1e-8; singular values against the stored FP64 oracle values of the
+    widened BF16 matrix, outputs orthonormal, and residuals checked on the
+    device in FP64 by an independent torch computation."""
     import torch
+    print(f"workload 3 full size, precision {precision}", flush=True)
     d = inputs.config_matrix(3)
     v0 = inputs.start_vector(10000, inputs.CONFIG_SEEDS[3] + 1)
     gold = _golden(GOLDEN_W3)
-    Ug, Sg, Vg, info, st = _dense_solve(S, d["bf16"], 100, 250, 1e-8, v0, MIXED)
+    Ug, Sg, Vg, info, st = _dense_solve(S, d["bf16"], 100, 250, 1e-8, v0, precision)
     assert st == 0 and info["converged"] == 1
-    np.testing.assert_allclose(Sg, gold[:100], rtol=1e-8)
+    np.testing.assert_allclose(Sg, gold[:100], rtol=rtol)
     k = 100
     assert np.abs(Ug.T @ Ug - np.eye(k)).max() <= 1e-12
     assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-12
@@ -133,12 +133,28 @@ def test_mixed_dense_bf16_full_size_against_stored_oracle(S):
     s = torch.from_numpy(Sg).cuda()
     r2 = torch.linalg.norm(A.T @ U - V * s, dim=0) / s
     assert float(r2.max()) <= 2e-8
-    # the library's FP64 residuals (GEMM form) agree with the independent ones;
-    # both are at rounding level here, so the agreement is absolute
+    # the library's FP64 residuals (block products over the stored BF16
+    # matrix) agree with the independent ones; both are at rounding level
+    # here, so the agreement is absolute
     assert abs(info["max_res_true"] - float(r2.max())) <= 1e-12
     r1 = torch.linalg.norm(A @ V - U * s, dim=0) / s[0]
     assert abs(info["max_res_av"] - float(r1.max())) <= 1e-12
     assert info["max_res_true"] <= 2e-8 and info["max_res_av"] <= 2e-8
+    # the residuals read the stored BF16 matrix: no widened m x n FP64 copy
+    # is part of the plan
+    assert info["workspace_bytes"] < 8 * 20000 * 10000
+    return info
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN_W3), reason="stored oracle values not generated")
+def test_mixed_dense_bf16_full_size_against_stored_oracle(S):
+    _full_size_w3(S, MIXED, 1e-8)
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN_W3), reason="stored oracle values not generated")
+def test_fp64_dense_bf16_full_size_against_stored_oracle(S):
+    """The plain FP64 path on the same stored matrix, to the FP64 bound."""
+    _full_size_w3(S, 0, 1e-10)
 
 
 def test_mixed_fp64_values_every_product_layout(S):

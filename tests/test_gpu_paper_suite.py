@@ -1,5 +1,5 @@
-"""The paper's synthetic suite (Sec. 3.1): Sparse1-3 at the paper's shape
-(40,000 x 40,000, 5 nonzeros per row) and Dense1-3 at a reduced order, with
+"""The paper's synthetic suite (Sec. 3.1) at the paper's shape: Sparse1-3
+(40,000 x 40,000, 5 nonzeros per row) and Dense1-3 (10,000 x 10,000), with
 Decay1/2/3 spectra, solved as in Sec. 3 (k = 100, t = 300, tol = 1e-10, at
 most 10 cycles).  The singular values are known in closed form, so the GPU
 result is checked against them directly, and against the a-posteriori bound
@@ -24,7 +24,7 @@ def S():
 
 
 @pytest.mark.parametrize("name,n", [("sparse1", None), ("sparse2", None), ("sparse3", None),
-                                    ("dense1", 3000), ("dense2", 3000), ("dense3", 3000)])
+                                    ("dense1", None), ("dense2", None), ("dense3", None), ("dense2", 3000)])
 def test_paper_suite_exact_spectrum(S, name, n):
     import torch
     print(f"paper suite {name} n={n}", flush=True)
@@ -50,5 +50,8 @@ def test_paper_suite_exact_spectrum(S, name, n):
     r1, r2 = svds_ref.explicit_residuals(op, U, s, V)
     assert np.all(np.abs(s - sig[:k]) <= np.maximum(r1, r2) + 4e-16 * sig[0])
     assert r1.max() <= 1e-12 * sig[0]
+    # the library's own FP64 residuals (block products on the device) agree
+    # with the CPU ones; both sit at rounding level, so the agreement is absolute
+    assert abs(r.info["max_res_av"] - r1.max() / s.max()) <= 1e-13
     assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-12
     assert np.abs(V.T @ V - np.eye(k)).max() <= 1e-12

@@ -370,7 +370,8 @@ def test_planted_transposed_operand_is_caught(monkeypatch):
 
 # --- the paper's synthetic suite at reduced order (Sec. 3.1, Sec. 3 settings) ---
 
-@pytest.mark.parametrize("name,n", [("sparse1", 500), ("sparse3", 500), ("dense2", 200)])
+@pytest.mark.parametrize("name,n", [("sparse1", 500), ("sparse3", 500), ("dense1", 300), ("dense2", 200),
+                                    ("dense3", 300)])
 def test_paper_suite_generator_spectrum(name, n):
     """The generator's matrices have exactly the decay law's singular values
     (dense LAPACK SVD of the whole matrix), 5 nonzeros per row when sparse."""
