@@ -257,9 +257,12 @@ int svds_dense_solve(const svds_dense *A, const svds_opts *opts,
  * block-diagonal matrix (each padded to a multiple of 256 rows and columns)
  * and every kernel launch serves all of them; projections, norms and
  * residuals are reduced per problem, the small SVDs run one workgroup per
- * problem.  Problems that converge early keep iterating until all have
- * converged or maxit cycles ran; each reports its own estimates, breakdowns
- * and residuals, the cycle counts are those of the batch.
+ * problem.  A problem whose eq. (4) test passes is frozen at the next
+ * restart: its Ritz vectors stay in the leading basis columns and every
+ * later launch skips it, while the others go on until they converge or
+ * maxit cycles ran.  Each problem reports its own estimates, breakdowns,
+ * residuals and cycle counts (the cycles it ran before it froze, per
+ * precision phase).
  *   - U[i] (m_i x k, ld m_i), S[i] (k), V[i] (n_i x k, ld n_i): per-problem
  *     FP64 device outputs; infos (count entries) may be NULL.
  *   - All problems must share the value type (F64 or F32).
