@@ -63,6 +63,25 @@ int svds_op_csc_build(const svds_csr *A, int32_t *t_row_ptr, int32_t *t_col_idx,
 int svds_op_cgs2(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
                  double *norm_out, int32_t dtype, void *stream);
 
+/* svds_op_cgs2 for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results as svds_op_cgs2 (bit-identical), but
+ * no allocation of any kind: the call's scratch (column partials, the two
+ * coefficient vectors, the intermediate vector of L entries, norm partials)
+ * lives in one static device array of the library, about 24 MiB, that each
+ * GPU holds from the first call on it until the process ends.
+ *   - Limit: L * sizeof(element) <= SVDS_CGS2_NOALLOC_MAX_VECTOR_BYTES
+ *     (2^21 FP64 or 2^22 FP32 entries), j <= 1024; EINVAL beyond.
+ *   - Every call on one GPU shares that array, and a call leaves its
+ *     contents behind: calls that overlap on one GPU (from several host
+ *     threads or on several streams) race and give undefined results.
+ *     Serialize them.  No word of the array has to start at zero: each call
+ *     writes every word it reads before reading it.
+ *   - Synchronous on `stream` (the norm is read back to the host). */
+enum { SVDS_CGS2_NOALLOC_MAX_VECTOR_BYTES = 16 << 20 };
+int svds_op_cgs2_noalloc(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
+                         double *norm_out, int32_t dtype, void *stream);
+
 /* Alg. 2 steps 4-9 on the device: T is the (p+1) x (p+1) row-major FP64
  * matrix of the Lanczos process (T(i,i) = alpha, T(i,i+1) = beta); its
  * leading p x p block is decomposed by the one-sided Jacobi SVD.  Outputs:

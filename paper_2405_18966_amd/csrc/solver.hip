@@ -15,6 +15,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "../../include/svds_ops.h"
 #include "plan.hpp"
 #include "kernels_cgs.hpp"
 #include "kernels_csc.hpp"
@@ -2008,50 +2009,126 @@ int svds_plan_transpose_copy(svds_plan *P, int32_t *t_row_ptr, int32_t *t_col_id
 }
 
 // CGS2 of one vector against a caller basis, with the solver's own kernels
-// (single-step operation).  Scratch is allocated for the call.
-int svds_cgs2_op(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
-                 double *norm_out, int32_t dtype, void *stream) {
-  svds_plan tmp;
-  tmp.stream = static_cast<hipStream_t>(stream);
-  tmp.acc.stream = tmp.stream;
-  const size_t tb = dtype == SVDS_F64 ? 8 : 4;
+// (single-step operation).  Scratch layout: column partials of the two
+// projections, h1, h2, the intermediate vector w1, norm partials and a few
+// device scalars.  Every scratch word a call reads is written earlier in the
+// same call (each projection block writes its partial of every column, even
+// a zero one), so no part of it has to start at zero.
+namespace {
+struct Cgs2Scratch {
+  size_t parts, h1, h2, w1, np, dx, bd, total;
+};
+
+Cgs2Scratch cgs2_scratch_layout(int64_t L, size_t tb) {
+  Cgs2Scratch s{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
     off += (bytes + 255) & ~size_t(255);
     return o;
   };
-  const size_t o_parts = take(tb * CGS_MAXJ * CGS_MAX_SLABS), o_h1 = take(tb * CGS_MAXJ),
-               o_h2 = take(tb * CGS_MAXJ), o_w1 = take(tb * L), o_np = take(8 * NPART), o_dx = take(64),
-               o_bd = take(16);
+  s.parts = take(tb * CGS_MAXJ * CGS_MAX_SLABS);
+  s.h1 = take(tb * CGS_MAXJ);
+  s.h2 = take(tb * CGS_MAXJ);
+  s.np = take(8 * NPART);
+  s.dx = take(64);
+  s.bd = take(16);
+  s.w1 = take(tb * static_cast<size_t>(L));  // last: the only part that grows with L
+  s.total = off;
+  return s;
+}
+
+int cgs2_op_run(char *b, const Cgs2Scratch &lay, int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w,
+                void *out, double *norm_out, int32_t dtype, hipStream_t stream) {
+  svds_plan tmp;
+  tmp.stream = stream;
+  tmp.acc.stream = stream;
+  double *dx = reinterpret_cast<double *>(b + lay.dx);  // xs, t_entry, sigma_est
+  tmp.sc.npart = reinterpret_cast<double *>(b + lay.np);
+  tmp.sc.sigma_est = dx + 2;
+  tmp.sc.bd = reinterpret_cast<int *>(b + lay.bd);
+  int rc;
+  if (dtype == SVDS_F64)
+    rc = cgs2_finish<double>(&tmp, reinterpret_cast<double *>(b + lay.parts), reinterpret_cast<double *>(b + lay.h1),
+                             reinterpret_cast<double *>(b + lay.h2), static_cast<const double *>(Q), ldq, L, j,
+                             static_cast<const double *>(w), reinterpret_cast<double *>(b + lay.w1),
+                             static_cast<double *>(out), MODE_NORM, dx + 1, dx);
+  else
+    rc = cgs2_finish<float>(&tmp, reinterpret_cast<float *>(b + lay.parts), reinterpret_cast<float *>(b + lay.h1),
+                            reinterpret_cast<float *>(b + lay.h2), static_cast<const float *>(Q), ldq, L, j,
+                            static_cast<const float *>(w), reinterpret_cast<float *>(b + lay.w1),
+                            static_cast<float *>(out), MODE_NORM, dx + 1, dx);
+  if (rc) return rc;
+  double xs = 0;
+  HIP_TRY(hipMemcpyAsync(&xs, dx, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (norm_out) *norm_out = 1.0 / xs;
+  return SVDS_OK;
+}
+}  // namespace
+
+int svds_cgs2_op(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
+                 double *norm_out, int32_t dtype, void *stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Cgs2Scratch lay = cgs2_scratch_layout(L, dtype == SVDS_F64 ? 8 : 4);
   char *b = nullptr;
-  HIP_TRY(hipMalloc(reinterpret_cast<void **>(&b), off));
+  HIP_TRY(hipMalloc(reinterpret_cast<void **>(&b), lay.total));
   struct Free {
     char *p;
     ~Free() { (void)hipFree(p); }
   } guard{b};
-  HIP_TRY(hipMemsetAsync(b, 0, off, tmp.stream));
-  double *dx = reinterpret_cast<double *>(b + o_dx);  // xs, t_entry, sigma_est
-  tmp.sc.npart = reinterpret_cast<double *>(b + o_np);
-  tmp.sc.sigma_est = dx + 2;
-  tmp.sc.bd = reinterpret_cast<int *>(b + o_bd);
-  int rc;
-  if (dtype == SVDS_F64)
-    rc = cgs2_finish<double>(&tmp, reinterpret_cast<double *>(b + o_parts), reinterpret_cast<double *>(b + o_h1),
-                             reinterpret_cast<double *>(b + o_h2), static_cast<const double *>(Q), ldq, L, j,
-                             static_cast<const double *>(w), reinterpret_cast<double *>(b + o_w1),
-                             static_cast<double *>(out), MODE_NORM, dx + 1, dx);
-  else
-    rc = cgs2_finish<float>(&tmp, reinterpret_cast<float *>(b + o_parts), reinterpret_cast<float *>(b + o_h1),
-                            reinterpret_cast<float *>(b + o_h2), static_cast<const float *>(Q), ldq, L, j,
-                            static_cast<const float *>(w), reinterpret_cast<float *>(b + o_w1),
-                            static_cast<float *>(out), MODE_NORM, dx + 1, dx);
-  if (rc) return rc;
-  double xs = 0;
-  HIP_TRY(hipMemcpyAsync(&xs, dx, sizeof(double), hipMemcpyDeviceToHost, tmp.stream));
-  HIP_TRY(hipStreamSynchronize(tmp.stream));
-  if (norm_out) *norm_out = 1.0 / xs;
+  HIP_TRY(hipMemsetAsync(b, 0, lay.total, st));
+  return cgs2_op_run(b, lay, L, j, Q, ldq, w, out, norm_out, dtype, st);
+}
+
+// ---------------------------------------------------------------------------
+// CGS2 without allocation (svds_op_cgs2_noalloc).  Its scratch is the
+// file-scope device array below: each GPU the library runs on holds one copy
+// from the first call on that device until the process ends.  In host code
+// `scratch` names a host-side stand-in, not device memory, so the host takes
+// each device's address of it once (hipGetSymbolAddress, with that device
+// current) and passes only that address on.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_BYTES = size_t(SVDS_CGS2_NOALLOC_MAX_VECTOR_BYTES) + (size_t(8) << 20) + (size_t(64) << 10);
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+char *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device.
+int noalloc_scratch(char **ptr) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return SVDS_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return SVDS_EDEVICE;
+    g_noalloc_ptr[dev] = static_cast<char *>(p);
+  }
+  *ptr = g_noalloc_ptr[dev];
   return SVDS_OK;
+}
+}  // namespace
+
+extern "C" int svds_op_cgs2_noalloc(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w, void *out,
+                                    double *norm_out, int32_t dtype, void *stream) {
+  SVDS_ABI_TRY
+  if (L < 1 || j < 0 || j > CGS_MAXJ || (j > 0 && (!Q || ldq < L)) || !w || !out) return SVDS_EINVAL;
+  if (dtype != SVDS_F64 && dtype != SVDS_F32) return SVDS_EUNSUPPORTED;
+  const size_t tb = dtype == SVDS_F64 ? 8 : 4;
+  if (static_cast<size_t>(L) > size_t(SVDS_CGS2_NOALLOC_MAX_VECTOR_BYTES) / tb) return SVDS_EINVAL;
+  const Cgs2Scratch lay = cgs2_scratch_layout(L, tb);
+  if (lay.total > NOALLOC_BYTES) return SVDS_EINVAL;
+  char *b = nullptr;
+  const int rc = noalloc_scratch(&b);
+  if (rc) return rc;
+  return cgs2_op_run(b, lay, L, j, Q, ldq, w, out, norm_out, dtype, static_cast<hipStream_t>(stream));
+  SVDS_ABI_CATCH
 }
 
 namespace {

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsvds.so")
 SVDS_OK, SVDS_NOT_CONVERGED = 0, 1
 SVDS_EINVAL, SVDS_ENOMEM, SVDS_EDEVICE, SVDS_EUNSUPPORTED = -1, -2, -3, -4
 SVDS_F64, SVDS_F32, SVDS_BF16 = 0, 1, 2
+SVDS_CGS2_NOALLOC_MAX_VECTOR_BYTES = 16 << 20  # svds_op_cgs2_noalloc: L * element size
 SVDS_PREC_FP64, SVDS_PREC_MIXED = 0, 1
 SVDS_FLAG_TIMING, SVDS_FLAG_NO_RESIDUALS, SVDS_FLAG_NO_SIGNFIX, SVDS_FLAG_GRAPH, SVDS_FLAG_AUTOTUNE = 1, 2, 4, 8, 16
 SVDS_FLAG_ITEMS_1K, SVDS_FLAG_UNSORTED, SVDS_FLAG_NO_PANELS, SVDS_FLAG_SMALLEST = 32, 64, 128, 256
@@ -104,6 +105,7 @@ def _load():
         "svds_op_csr_matvec": (i32, [P(svds_csr), i32, vp, vp, vp, vp, vp, i32, P(i32), vp]),
         "svds_op_csc_build": (i32, [P(svds_csr), vp, vp, vp, vp]),
         "svds_op_cgs2": (i32, [i64, i32, vp, i64, vp, vp, P(d), i32, vp]),
+        "svds_op_cgs2_noalloc": (i32, [i64, i32, vp, i64, vp, vp, P(d), i32, vp]),
         "svds_op_small_svd": (i32, [i32, i32, d, vp, vp, vp, vp, vp, vp, P(i32), vp]),
         "svds_op_rotate": (i32, [i64, i32, i32, vp, i64, i32, vp, i64, vp, i64, vp]),
         "svds_op_philox_normal": (i32, [i64, u64, C.c_uint32, vp, vp]),
@@ -330,6 +332,18 @@ def svds_op_cgs2(Q: torch.Tensor, j: int, w: torch.Tensor, ldq: int | None = Non
     _check(lib.svds_op_cgs2(L, j, _ptr(Q) if j > 0 else None, ldq or (Q.shape[1] if j > 0 else L), _ptr(w),
                             _ptr(out), C.byref(nrm), dt, _stream(stream)), "svds_op_cgs2")
     return out, nrm.value
+
+
+def svds_op_cgs2_noalloc(Q: torch.Tensor, j: int, w: torch.Tensor, out: torch.Tensor,
+                         ldq: int | None = None, stream=None) -> float:
+    """svds_op_cgs2 into a caller-given `out` through the entry point that
+    allocates no device memory; returns the norm."""
+    dt = SVDS_F64 if w.dtype == torch.float64 else SVDS_F32
+    nrm = C.c_double()
+    _check(lib.svds_op_cgs2_noalloc(w.numel(), j, _ptr(Q) if j > 0 else None,
+                                    ldq or (Q.shape[1] if j > 0 else w.numel()), _ptr(w), _ptr(out),
+                                    C.byref(nrm), dt, _stream(stream)), "svds_op_cgs2_noalloc")
+    return nrm.value
 
 
 def svds_op_small_svd(T: torch.Tensor, p: int, k: int, tol: float, stream=None):
