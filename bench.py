@@ -14,10 +14,13 @@ stream the kernels run on), the headline SpMV+CGS2 GB/s, parity of the
 singular values against stored oracle values, and the CPU oracle timed on a
 complete solve of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--paper-dense]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-paper-dense]
 
-It also times the paper's synthetic Sparse1-3 suite (Sec. 3.1) against the
-closed-form singular values, with the paper's own CPU times as context.
+It also times the paper's synthetic Sparse1-3 and Dense1-3 suite (Sec. 3.1)
+against the closed-form singular values, with the paper's own CPU times as
+context, the other workloads (2000 x 1000 sparse; 20000 x 10000 dense BF16
+and 2000 x 1000 FP32-valued, FP64 and mixed; the 256-problem batch), and the
+CPU oracle on each of them.
 """
 from __future__ import annotations
 
@@ -89,7 +92,73 @@ def cpu_baseline(A, v0, k, p, tol):
             "sigma": S.tolist()}
 
 
-def mixed_vs_fp64(S, inputs, np, torch):
+def host_cpu():
+    """The bench host's CPU as lscpu reports it (model, sockets, cores,
+    threads), and the threads the oracle's BLAS may use."""
+    import subprocess
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)",
+                     "CPU max MHz", "NUMA node(s)"):
+                info[k] = v
+    except (OSError, subprocess.SubprocessError):
+        pass
+    info["blas_threads"] = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return info
+
+
+def oracle_rate(A, k, p, tol, v0=None, seed=0, reps=3, budget_s=20.0):
+    """Complete CPU-oracle solves of one matrix (same start vector or seed,
+    k, p, tol as the GPU run), repeated up to ``reps`` times while under
+    ``budget_s``; returns (median solves/s, cycles, singular values)."""
+    from oracle import svds_ref
+
+    op = svds_ref.as_operator(A)
+    ts, S_, info = [], None, None
+    while len(ts) < reps and (not ts or sum(ts) < budget_s):
+        t0 = time.perf_counter()
+        U, S_, V, info = svds_ref.svds(op, k, p, tol, 2000, v0=v0, seed=seed)
+        ts.append(time.perf_counter() - t0)
+    return 1.0 / sorted(ts)[len(ts) // 2], info.cycles, S_, len(ts)
+
+
+def config1(S, inputs, np, torch, cpu: bool):
+    """The 2000 x 1000 sparse workload (20,000 uniform positions, N(0,1)),
+    FP64, k=10, p=30, tol=1e-10: median of 5 GPU solves after one warm-up,
+    and the CPU oracle on the same matrix and start vector."""
+    A = inputs.config_matrix(1)
+    c = inputs.CONFIG_SOLVE[1]
+    v0 = inputs.start_vector(A.n, inputs.CONFIG_SEEDS[1] + 1)
+    Ad, keep = S.csr_to_device(A)
+    v0d = torch.from_numpy(v0).cuda()
+    run = lambda: S.svds_csr_solve(Ad, S.make_opts(c["k"], c["p"], c["tol"], 2000, v0=v0d))
+    r = run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        r = run()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t = sorted(ts)[2]
+    out = {"workload": "sparse 2000x1000, nnz 20000 uniform, N(0,1), fp64, k=10 p=30 tol=1e-10",
+           "gpu_ms": round(t * 1e3, 3), "gpu_solves_per_s": round(1 / t, 2), "cycles": r.info["cycles"],
+           "status": r.status}
+    if cpu:
+        rate, cyc, s_or, n = oracle_rate(A, c["k"], c["p"], c["tol"], v0=v0)
+        s = r.S.cpu().numpy()
+        out["cpu_oracle"] = {"solves_per_s": round(rate, 3), "cycles": cyc, "runs": n,
+                             "sample": f"median of {n} complete oracle solves"}
+        out["sigma_rel_err_vs_oracle"] = float(np.max(np.abs(s - s_or) / s_or))
+        out["x_vs_cpu_oracle"] = round(out["gpu_solves_per_s"] / rate, 1)
+    return out
+
+
+def mixed_vs_fp64(S, inputs, np, torch, cpu: bool = False):
     """Mixed (FP32 cycles + FP64 refinement) against the plain FP64 GPU path,
     same stored matrix, same start vector, tol=1e-8: median solve time of 3
     after one warm-up each.  The dense 20000 x 10000 BF16 workload and the
@@ -120,6 +189,14 @@ def mixed_vs_fp64(S, inputs, np, torch):
                      "sigma_rel_err_vs_oracle": float(np.max(np.abs(s - gold[:100]) / gold[:100]))
                      if gold is not None else None, "status": r.status}
     out["dense_20000x10000_bf16_k100_p250"] = dict(res, x=round(res["fp64"]["ms"] / res["mixed"]["ms"], 3))
+    if cpu:
+        # the CPU oracle on the stored matrix widened to FP64 (the matrix of
+        # record), same start vector, FP64, tol=1e-8: one complete solve
+        rate, cyc, s_or, n = oracle_rate(d["record_bf16"], 100, 250, 1e-8, v0=v0.cpu().numpy(), reps=1)
+        out["dense_20000x10000_bf16_k100_p250"]["cpu_oracle"] = {
+            "solves_per_s": round(rate, 4), "cycles": cyc, "runs": n,
+            "sample": "one complete FP64 oracle solve (dense BLAS mat-vecs)",
+            "x_fp64_gpu_vs_cpu": round(rate and (1e3 / res["fp64"]["ms"]) / rate, 1)}
     del d, t, Ad
     A = inputs.config_matrix(4)
     Ad4, keep = S.csr_to_device(A)
@@ -133,10 +210,16 @@ def mixed_vs_fp64(S, inputs, np, torch):
                      "sigma_rel_err_vs_oracle": float(np.max(np.abs(s - gold[:50]) / gold[:50]))
                      if gold is not None else None, "status": r.status}
     out["sparse_2000x1000_fp32_k50_p150"] = dict(res, x=round(res["fp64"]["ms"] / res["mixed"]["ms"], 3))
+    if cpu:
+        rate, cyc, s_or, n = oracle_rate(A, 50, 150, 1e-8, v0=v0.cpu().numpy())
+        out["sparse_2000x1000_fp32_k50_p150"]["cpu_oracle"] = {
+            "solves_per_s": round(rate, 3), "cycles": cyc, "runs": n,
+            "sample": f"median of {n} complete FP64 oracle solves of the FP32-valued matrix",
+            "x_fp64_gpu_vs_cpu": round((1e3 / res["fp64"]["ms"]) / rate, 1)}
     return out
 
 
-def batched_vs_loop(S, inputs, np, torch):
+def batched_vs_loop(S, inputs, np, torch, cpu: bool = False):
     """The 256-problem workload (m ~ U{500..20000}, n ~ U{m/2..m}, 0.5%
     density, N(0,1), k=8, p=24, tol=1e-8): one lockstep batched call against
     a loop of single-problem solves, mixed and FP64; median of 3 after one
@@ -190,6 +273,20 @@ def batched_vs_loop(S, inputs, np, torch):
                      "looped_problems_per_s": round(len(As) / tl, 2), "x": round(tl / tb, 2),
                      "cycles": res[0].info["cycles"], "all_converged": bool(ok),
                      "sigma_rel_diff_batched_vs_looped": worst}
+    if cpu:
+        # CPU oracle: problems solved alone, in order, until 15 s have passed
+        from oracle import svds_ref
+        t0, nb = time.perf_counter(), 0
+        while nb < len(As) and time.perf_counter() - t0 < 15.0:
+            svds_ref.svds(svds_ref.as_operator(As[nb]), 8, 24, 1e-8, 2000, seed=seed + nb)
+            nb += 1
+        dt = time.perf_counter() - t0
+        share = sum(A.nnz for A in As[:nb]) / out["nnz_total"]
+        out["cpu_oracle"] = {
+            "problems_per_s": round(nb / dt, 3),
+            "problems_per_s_nnz_weighted": round(len(As) * share / dt, 4),
+            "sample": f"problems 0..{nb - 1} solved alone by the FP64 oracle in {dt:.1f} s "
+                      f"({100 * share:.1f}% of the batch's nonzeros); nnz-weighted rate = 256 / (time / share)"}
     return out
 
 
@@ -280,9 +377,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched vs looped comparison")
     ap.add_argument("--no-suite", action="store_true", help="skip the paper's Sparse1-3 suite")
     ap.add_argument("--no-selective", action="store_true", help="skip the selective re-orthogonalization run")
-    ap.add_argument("--paper-dense", action="store_true",
-                    help="add Dense1-3 (10,000 x 10,000) to the paper suite (about a minute of host "
-                         "time each to generate the Haar factors)")
+    ap.add_argument("--no-paper-dense", action="store_true",
+                    help="leave Dense1-3 (10,000 x 10,000) out of the paper suite")
+    ap.add_argument("--no-config1", action="store_true",
+                    help="skip the 2000 x 1000 sparse workload (k=10, p=30, tol=1e-10)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
     ap.add_argument("--profile-section", choices=["dense", "batched", "sparse2"],
@@ -412,16 +510,21 @@ def main():
     mixed = None
     if not args.no_mixed:
         log("mixed vs FP64 ...")
-        mixed = mixed_vs_fp64(S, inputs, np, torch)
+        mixed = mixed_vs_fp64(S, inputs, np, torch, cpu=not args.no_cpu and rank == 0)
 
     batched = None
     if not args.no_batched:
         log("batched vs looped ...")
-        batched = batched_vs_loop(S, inputs, np, torch)
+        batched = batched_vs_loop(S, inputs, np, torch, cpu=not args.no_cpu and rank == 0)
+
+    c1 = None
+    if not args.no_config1:
+        log("2000 x 1000 sparse workload ...")
+        c1 = config1(S, inputs, np, torch, cpu=not args.no_cpu and rank == 0)
 
     suite = None
     if not args.no_suite:
-        suite = paper_suite(S, inputs, np, torch, args.paper_dense)
+        suite = paper_suite(S, inputs, np, torch, not args.no_paper_dense)
 
     cpu = None
     if not args.no_cpu and rank == 0:
@@ -439,6 +542,7 @@ def main():
            "data": "synthetic", "config": dict(WORKLOAD, parallelism="single GPU"),
            "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "mixed_vs_fp64": mixed,
            "batched_vs_looped": batched, "paper_suite": suite, "selective_reorth": sel,
+           "config_2000x1000": c1, "host_cpu": host_cpu(),
            "step_ms": {"execute": round(ms_exec, 2), "create_and_destroy": round(ms_step - ms_exec, 2)}}
     print(json.dumps(out), flush=True)
 
