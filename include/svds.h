@@ -120,9 +120,15 @@ enum {
  *   - CGS2 (not for the batched solver, whose passes are segmented): the
  *     first pass's row-slab count (x 1/2, 1, 2) and the fused pass's columns
  *     per wave (8 or 10), timed at basis widths p/4, p/2 and p.
- * The choice depends on measured times, so two plans of one matrix can pick
- * differently and their results then differ by rounding (each is still
- * deterministic); without the flag the built-in rules apply. */
+ * The choice depends on measured times; without the flag the built-in rules
+ * apply.  Choices are cached for the process, keyed by the device, the
+ * sizes, the value type, k, p, the precision and a hash of the row pointers
+ * of A and A^T: a later plan with the same key takes the stored choice
+ * without timing (svds_tuning.tuned = 2 instead of 1), so two tuned plans of
+ * one matrix run the same launch shapes and give bit-identical results.  If
+ * the environment variable SVDS_AUTOTUNE_CACHE names a file, the cache also
+ * persists there: entries are read from it at the first tuned plan and each
+ * new choice is appended as one text line. */
 
 /* SVDS_FLAG_GRAPH: the launches of a restart cycle that follow the small SVD
  * (the restart vector of eq. (7) and the Lanczos steps k+1..p, Alg. 2 steps
@@ -185,7 +191,7 @@ enum {
 
 /* Launch shapes chosen by SVDS_FLAG_AUTOTUNE (all zero without it). */
 typedef struct {
-  int32_t tuned;                     /* 1 if the tuner ran                       */
+  int32_t tuned;                     /* 1 tuner ran, 2 choice from the cache     */
   int32_t fwd_nnz_cap, fwd_sorted;   /* A x: nonzeros per item, column-sorted    */
   int32_t bwd_nnz_cap, bwd_sorted;   /* A^T y: same                              */
   int32_t bwd_panels;                /* A^T y column panels (1 = none)           */

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <thread>
@@ -1379,10 +1380,154 @@ static int tune_cgs(svds_plan *P, EventPair &ev) {
   return SVDS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Tuning cache.  A choice depends on the sparsity structure and sizes, the
+// plan's Lanczos dimension, the precision and the device, not on the values:
+// the key hashes all of them (FNV-1a over the row pointers of A and of A^T),
+// so a second plan of the same matrix (or of another one with the same
+// structure) takes the stored choice instead of timing candidates again.
+// The cache lives for the process; with the environment variable
+// SVDS_AUTOTUNE_CACHE naming a file it also persists: entries are read from
+// that file on first use and every new entry is appended to it, one text line
+// each ("svds-tune-v1 <key> <choice and times>").
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneChoice {
+  int fwd_cap = 0, fwd_sorted = 0, bwd_cap = 0, bwd_sorted = 0, bwd_panels = 1, slab_shift = 0, cpw = 0;
+  double fwd_us = 0, fwd_default_us = 0, bwd_us = 0, bwd_default_us = 0, cgs_us = 0, cgs_default_us = 0;
+};
+
+std::mutex g_tune_mu;
+std::vector<std::pair<uint64_t, TuneChoice>> g_tune;  // (key, choice)
+std::string g_tune_file;                              // file the entries were read from
+
+uint64_t fnv1a(uint64_t h, const void *data, size_t bytes) {
+  const unsigned char *c = static_cast<const unsigned char *>(data);
+  for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
+  return h;
+}
+
+uint64_t tune_key(const svds_plan *P, const int32_t *hrp, const int32_t *htrp, int nseg) {
+  const Operator &op = P->op;
+  uint64_t h = 0xcbf29ce484222325ull;
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) h = fnv1a(h, prop.gcnArchName, strlen(prop.gcnArchName));
+  const int64_t f[] = {op.dense ? 1 : 0, op.m, op.n, op.nnz, op.vt, op.dense ? op.lda : 0, P->p, P->k,
+                       P->mixed ? 1 : 0, nseg, P->op.npanel};
+  h = fnv1a(h, f, sizeof f);
+  if (hrp) h = fnv1a(h, hrp, sizeof(int32_t) * (op.m + 1));
+  if (htrp) h = fnv1a(h, htrp, sizeof(int32_t) * (op.n + 1));
+  return h;
+}
+
+// Entries of the cache file not yet read (called with g_tune_mu held).
+void tune_load_file(const std::string &path) {
+  if (path == g_tune_file) return;
+  g_tune_file = path;
+  FILE *f = fopen(path.c_str(), "r");
+  if (!f) return;
+  char tag[32];
+  unsigned long long key;
+  TuneChoice c;
+  while (fscanf(f, "%31s %llx %d %d %d %d %d %d %d %lf %lf %lf %lf %lf %lf", tag, &key, &c.fwd_cap, &c.fwd_sorted,
+                &c.bwd_cap, &c.bwd_sorted, &c.bwd_panels, &c.slab_shift, &c.cpw, &c.fwd_us, &c.fwd_default_us,
+                &c.bwd_us, &c.bwd_default_us, &c.cgs_us, &c.cgs_default_us) == 15) {
+    if (strcmp(tag, "svds-tune-v1") != 0) continue;
+    bool have = false;
+    for (auto &e : g_tune) have = have || e.first == key;
+    if (!have) g_tune.emplace_back(key, c);
+  }
+  fclose(f);
+}
+
+bool tune_lookup(uint64_t key, TuneChoice &c) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (const char *path = getenv("SVDS_AUTOTUNE_CACHE")) tune_load_file(path);
+  for (auto &e : g_tune)
+    if (e.first == key) {
+      c = e.second;
+      return true;
+    }
+  return false;
+}
+
+void tune_store(uint64_t key, const TuneChoice &c) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto &e : g_tune)
+    if (e.first == key) return;
+  g_tune.emplace_back(key, c);
+  const char *path = getenv("SVDS_AUTOTUNE_CACHE");
+  if (!path) return;
+  if (FILE *f = fopen(path, "a")) {
+    fprintf(f, "svds-tune-v1 %016llx %d %d %d %d %d %d %d %.6g %.6g %.6g %.6g %.6g %.6g\n",
+            static_cast<unsigned long long>(key), c.fwd_cap, c.fwd_sorted, c.bwd_cap, c.bwd_sorted, c.bwd_panels,
+            c.slab_shift, c.cpw, c.fwd_us, c.fwd_default_us, c.bwd_us, c.bwd_default_us, c.cgs_us, c.cgs_default_us);
+    fclose(f);
+  }
+}
+}  // namespace
+
+// A stored choice applied to a fresh plan: the same item caps, sorting and
+// panel use the tuner leaves behind, without timing anything.
+static int apply_product_choice(svds_plan *P, bool trans, const int32_t *hrp, int64_t rows, const int64_t *seg,
+                                int nseg, int cap, int sorted, int panels) {
+  Operator &op = P->op;
+  SpmvPlan &sp = trans ? op.bwd : op.fwd;
+  int rc;
+  if (!trans || panels == 1) {
+    if (trans) op.npanel = 1;
+    if (item_cap(P) != cap) {
+      sp.sorted = true;
+      if ((rc = tune_build_items(P, trans, hrp, rows, seg, nseg, cap))) return rc;
+    }
+    sp.sorted = sorted != 0 && sp.spos;
+  }
+  if (trans && panels == 1 && op.pbuf_items) {
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    (void)hipFree(op.pbuf_items);
+    op.pbuf_items = nullptr;
+    op.pbuf_bytes = 0;
+  }
+  return SVDS_OK;
+}
+
 // The whole tuning of a plan (products only for CSR; CGS2 unless batched).
 static int autotune(svds_plan *P, const int32_t *hrp, const int32_t *htrp, const int64_t *seg_rows,
                     const int64_t *seg_cols, int nseg) {
   const auto t0 = std::chrono::steady_clock::now();
+  const uint64_t key = tune_key(P, hrp, htrp, nseg);
+  TuneChoice c;
+  if (tune_lookup(key, c)) {
+    int rc;
+    if (!P->op.dense) {
+      if ((rc = apply_product_choice(P, false, hrp, P->op.m, seg_rows, nseg, c.fwd_cap, c.fwd_sorted, 1)))
+        return rc;
+      // panels are kept only when the plan has them and the choice used them
+      const int panels = P->op.npanel > 1 && c.bwd_panels > 1 ? P->op.npanel : 1;
+      if ((rc = apply_product_choice(P, true, htrp, P->op.n, seg_cols, nseg, c.bwd_cap, c.bwd_sorted, panels)))
+        return rc;
+    }
+    P->cgs_slab_shift = c.slab_shift;
+    P->cgs_cpw = c.cpw;
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    svds_tuning &tu = P->tuning;
+    tu.tuned = 2;
+    tu.fwd_nnz_cap = P->op.dense ? 0 : c.fwd_cap;
+    tu.fwd_sorted = P->op.dense ? 0 : c.fwd_sorted;
+    tu.bwd_nnz_cap = P->op.dense ? 0 : c.bwd_cap;
+    tu.bwd_sorted = P->op.dense ? 0 : c.bwd_sorted;
+    tu.bwd_panels = P->op.dense ? 0 : P->op.npanel;
+    tu.cgs_slab_shift = c.slab_shift;
+    tu.cgs_cpw = c.cpw;
+    tu.fwd_us = c.fwd_us;
+    tu.fwd_default_us = c.fwd_default_us;
+    tu.bwd_us = c.bwd_us;
+    tu.bwd_default_us = c.bwd_default_us;
+    tu.cgs_us = c.cgs_us;
+    tu.cgs_default_us = c.cgs_default_us;
+    tu.ms_tune = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return SVDS_OK;
+  }
   EventPair ev;
   HIP_TRY(hipEventCreate(&ev.a));
   HIP_TRY(hipEventCreate(&ev.b));
@@ -1400,8 +1545,23 @@ static int autotune(svds_plan *P, const int32_t *hrp, const int32_t *htrp, const
   }
   if (!seg_rows && (rc = tune_cgs(P, ev))) return rc;
   HIP_TRY(hipStreamSynchronize(P->stream));
-  P->tuning.tuned = 1;
-  P->tuning.ms_tune = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  svds_tuning &tu = P->tuning;
+  tu.tuned = 1;
+  tu.ms_tune = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  c.fwd_cap = tu.fwd_nnz_cap;
+  c.fwd_sorted = tu.fwd_sorted;
+  c.bwd_cap = tu.bwd_nnz_cap;
+  c.bwd_sorted = tu.bwd_sorted;
+  c.bwd_panels = P->op.dense ? 1 : tu.bwd_panels;
+  c.slab_shift = tu.cgs_slab_shift;
+  c.cpw = tu.cgs_cpw;
+  c.fwd_us = tu.fwd_us;
+  c.fwd_default_us = tu.fwd_default_us;
+  c.bwd_us = tu.bwd_us;
+  c.bwd_default_us = tu.bwd_default_us;
+  c.cgs_us = tu.cgs_us;
+  c.cgs_default_us = tu.cgs_default_us;
+  tune_store(key, c);
   return SVDS_OK;
 }
 

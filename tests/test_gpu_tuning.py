@@ -121,3 +121,66 @@ def test_autotune_batched(S):
         Ur, Sr, Vr, _ = svds_ref.svds(as_operator(A), 5, 15, 1e-10, 2000, seed=9 + b)
         np.testing.assert_allclose(out[1][b].S.cpu().numpy(), Sr, rtol=1e-10)
         np.testing.assert_allclose(out[1][b].S.cpu().numpy(), out[0][b].S.cpu().numpy(), rtol=1e-11)
+
+
+_CHOICE = ("fwd_nnz_cap", "fwd_sorted", "bwd_nnz_cap", "bwd_sorted", "bwd_panels", "cgs_slab_shift", "cgs_cpw")
+
+
+def test_autotune_cache_second_plan(S):
+    """A second tuned plan of the same matrix takes the stored choice (tuned
+    = 2) without timing candidates, and solves bit-identically to the
+    first (the same launch shapes)."""
+    import torch
+    print("autotune cache, same process", flush=True)
+    A = inputs.sparse_zipf(200000, 120000, 10, 1.1, seed=331)
+    v0 = inputs.start_vector(A.n, 332)
+    r1 = _solve(S, A, v0, S.SVDS_FLAG_AUTOTUNE, k=5, p=15)
+    r2 = _solve(S, A, v0, S.SVDS_FLAG_AUTOTUNE, k=5, p=15)
+    t1, t2 = r1.info["tuning"], r2.info["tuning"]
+    assert t1["tuned"] == 1 and t2["tuned"] == 2
+    assert {c: t1[c] for c in _CHOICE} == {c: t2[c] for c in _CHOICE}
+    assert t2["ms_tune"] < t1["ms_tune"]
+    assert torch.equal(r1.S, r2.S) and torch.equal(r1.U, r2.U) and torch.equal(r1.V, r2.V)
+    # another Lanczos dimension is another key
+    r3 = _solve(S, A, v0, S.SVDS_FLAG_AUTOTUNE, k=5, p=16)
+    assert r3.info["tuning"]["tuned"] == 1
+    Ur, Sr, Vr, _ = svds_ref.svds(as_operator(A), 5, 15, 1e-10, 2000, v0=v0)
+    np.testing.assert_allclose(r2.S.cpu().numpy(), Sr, rtol=1e-10)
+
+
+_CHILD = r"""
+import json, os, sys
+sys.path.insert(0, os.environ["SVDS_REPO"])
+import torch
+from paper_2405_18966_amd import inputs, svds as S
+A = inputs.sparse_uniform(3000, 2000, 60000, 341)
+Ad, keep = S.csr_to_device(A)
+v0 = torch.from_numpy(inputs.start_vector(A.n, 342)).cuda()
+r = S.svds_csr_solve(Ad, S.make_opts(5, 15, 1e-10, 2000, v0=v0, flags=S.SVDS_FLAG_AUTOTUNE))
+torch.cuda.synchronize()
+print(json.dumps({"tuning": r.info["tuning"], "S": r.S.cpu().tolist()}))
+"""
+
+
+def test_autotune_cache_file(S, tmp_path):
+    """SVDS_AUTOTUNE_CACHE: a first process tunes and appends its choice to
+    the file; a second process reads it and does not tune."""
+    import json
+    import os
+    import subprocess
+    import sys
+    print("autotune cache, file across processes", flush=True)
+    path = tmp_path / "tune.txt"
+    env = dict(os.environ, SVDS_AUTOTUNE_CACHE=str(path),
+               SVDS_REPO=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    outs = []
+    for i in range(2):
+        p = subprocess.run([sys.executable, "-c", _CHILD], env=env, capture_output=True, text=True, timeout=120)
+        assert p.returncode == 0, p.stderr[-2000:]
+        outs.append(json.loads(p.stdout.strip().splitlines()[-1]))
+        if i == 0:
+            lines = [ln for ln in path.read_text().splitlines() if ln.strip()]
+            assert len(lines) == 1 and lines[0].startswith("svds-tune-v1 ")
+    assert outs[0]["tuning"]["tuned"] == 1 and outs[1]["tuning"]["tuned"] == 2
+    assert {c: outs[0]["tuning"][c] for c in _CHOICE} == {c: outs[1]["tuning"][c] for c in _CHOICE}
+    assert outs[0]["S"] == outs[1]["S"]
