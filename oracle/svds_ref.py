@@ -39,6 +39,21 @@ Readings of the paper used here (where it is silent or ambiguous):
   order.  The sigma floor of eq. (4) still uses the largest Ritz value.  This
   is plain Ritz augmentation, not the harmonic variant.
 
+* Partial re-orthogonalisation (``partial=True``; the PROPACK-style
+  alternative that Sec. 1 names): instead of re-orthogonalising every new
+  vector against its whole basis, the loss of orthogonality of the newest
+  vector against each earlier one of its side is estimated by recurrences
+  that follow from the two Lanczos relations A V = U T and A^T U = V T^T
+  (see ``_omega_v`` / ``_omega_u``), plus a local rounding term
+  EPS * sigma_est per step divided by the new norm.  When an estimate
+  exceeds sqrt(EPS), the vector is re-orthogonalised by CGS2 against the
+  earlier vectors whose estimate exceeds EPS^(3/4), those estimates are reset
+  to EPS, and the next vector of the same side is re-orthogonalised against
+  the same set as well (its estimates grew from the same pair).  The restart
+  vector of eq. (7) is re-orthogonalised against all k kept vectors, as in
+  the full mode; the estimates of v_{k+1} = v_{p+1} against the kept Ritz
+  vectors are the old estimates rotated by the same right singular vectors.
+
 t (the paper's Lanczos dimension) is called p here.
 """
 from __future__ import annotations
@@ -53,6 +68,8 @@ from .philox import normal_vector
 BREAKDOWN_REL = 1e-14
 TINY = np.finfo(np.float64).tiny
 EPS = 2.0 ** -52
+OMEGA_TRIGGER = EPS ** 0.5   # an estimate above this triggers a re-orthogonalisation
+OMEGA_SELECT = EPS ** 0.75   # ... against the earlier vectors whose estimate is above this
 
 
 @dataclass
@@ -68,6 +85,9 @@ class SvdsInfo:
     sigma_est: float = 0.0
     reorth_tests: int = 0          # selective mode: tests made
     reorth_second_passes: int = 0  # ... and second passes run
+    partial_steps: int = 0         # partial mode: vectors re-orthogonalised ...
+    partial_columns: int = 0       # ... against this many basis columns in all
+    partial_possible: int = 0      # ... out of this many (the full mode's count)
 
 
 class _Op:
@@ -110,18 +130,43 @@ def cgs_selective(w: np.ndarray, Q: np.ndarray):
     return w1 - Q @ (Q.T @ w1), True
 
 
+def omega_v_inner(T, mu, nu, i):
+    """v_l^T w for l <= i, w = A^T u_i - T(i,i) v_i (the unnormalised v_{i+1},
+    0-based), from the inner products mu[r] = u_r^T u_i (mu[i] = 1) and
+    nu[l] = v_l^T v_i (nu[i] = 1): A V = U T gives A v_l = sum_r T(r,l) u_r,
+    so v_l^T A^T u_i = sum_{r<=l} T(r,l) mu[r]."""
+    return np.array([T[:l + 1, l] @ mu[:l + 1] - T[i, i] * nu[l] for l in range(i + 1)])
+
+
+def omega_u_inner(T, mu, nu, i):
+    """u_l^T w for l < i, w = A v_i - T(i-1,i) u_{i-1} (the unnormalised u_i),
+    from nu[c] = v_c^T v_i (nu[i] = 1) and mu[l] = u_l^T u_{i-1}
+    (mu[i-1] = 1): A^T U = V T^T (rows up to i-1) gives
+    A^T u_l = sum_c T(l,c) v_c, so u_l^T A v_i = sum_{c<=i} T(l,c) nu[c]."""
+    return np.array([T[l, :i + 1] @ nu[:i + 1] - T[i - 1, i] * mu[l] for l in range(i)])
+
+
 class _State:
     """Workspace of one solve: U (m x p), V (n x (p+1)), T ((p+1) x (p+1))."""
 
-    def __init__(self, op: _Op, p: int, seed: int, info: SvdsInfo, selective: bool = False):
+    def __init__(self, op: _Op, p: int, seed: int, info: SvdsInfo, selective: bool = False,
+                 partial: bool = False):
         self.op = op
         self.p = p
         self.seed = seed
         self.info = info
         self.selective = selective
+        self.partial = partial
         self.U = np.zeros((op.m, p), order="F")
         self.V = np.zeros((op.n, p + 1), order="F")
         self.T = np.zeros((p + 1, p + 1))
+        # partial mode: estimates of u_i^T u_l and v_i^T v_l for the newest
+        # u_i and v_i against every earlier vector of their side (entry i = 1),
+        # and the columns the next vector of each side must be taken against
+        self.mu = np.zeros(p + 1)
+        self.nu = np.zeros(p + 2)
+        self.force_u = np.zeros(0, dtype=int)
+        self.force_v = np.zeros(0, dtype=int)
 
     def _finish(self, w, Q):
         """CGS2 (or the selective form) against Q, norm, breakdown handling;
@@ -141,16 +186,78 @@ class _State:
         self.info.sigma_est = max(self.info.sigma_est, nrm)
         return w / nrm, nrm
 
-    def u_step(self, i, w):
-        """u_i from w (0-based column i): re-orthogonalise against U[:, :i]."""
-        self.U[:, i], a = self._finish(w, self.U[:, :i])
+    def u_step(self, i, w, full=False):
+        """u_i from w (0-based column i): re-orthogonalise against U[:, :i]
+        (partial mode, unless ``full``: against the columns the estimates pick)."""
+        if self.partial and not full and i > 0:
+            self.U[:, i], a = self._partial(w, self.U, i, self._omega_u(i, w), "u")
+        else:
+            self.U[:, i], a = self._finish(w, self.U[:, :i])
+            self.mu[:i] = EPS
+        self.mu[i] = 1.0
         self.T[i, i] = a
 
     def v_step(self, i):
         """Alg. 1 steps 5-6: v_{i+1} = A^T u_i - alpha_i v_i, reorth, beta_i."""
         w = self.op.rmv(self.U[:, i]) - self.T[i, i] * self.V[:, i]
-        self.V[:, i + 1], b = self._finish(w, self.V[:, :i + 1])
+        if self.partial:
+            self.V[:, i + 1], b = self._partial(w, self.V, i + 1, self._omega_v(i, w), "v")
+        else:
+            self.V[:, i + 1], b = self._finish(w, self.V[:, :i + 1])
+        self.nu[i + 1] = 1.0
         self.T[i, i + 1] = b
+
+    # --- partial re-orthogonalisation ---------------------------------------
+    def _rounding(self, x, nrm):
+        """Local rounding term of one step, with the sign of the estimate."""
+        return (x + np.where(x >= 0, 1.0, -1.0) * EPS * self.info.sigma_est) / nrm
+
+    def _omega_v(self, i, w):
+        nrm = float(np.linalg.norm(w))
+        x = omega_v_inner(self.T, self.mu, self.nu, i)
+        return self._rounding(x, nrm) if nrm > 0 else np.full(i + 1, np.inf)
+
+    def _omega_u(self, i, w):
+        nrm = float(np.linalg.norm(w))
+        x = omega_u_inner(self.T, self.mu, self.nu, i)
+        return self._rounding(x, nrm) if nrm > 0 else np.full(i, np.inf)
+
+    def _partial(self, w, Q, j, om, side):
+        """Re-orthogonalise w against the columns of Q[:, :j] that the
+        estimates ``om`` pick (plus the set forced by the previous vector of
+        this side); store the new estimate row; return (vector, norm)."""
+        forced = self.force_u if side == "u" else self.force_v
+        self.info.partial_possible += j
+        if np.all(np.abs(om) <= OMEGA_TRIGGER) and forced.size == 0:
+            sel = np.zeros(0, dtype=int)
+            nxt = sel
+        else:
+            sel = np.union1d(np.flatnonzero(np.abs(om) > OMEGA_SELECT), forced[forced < j]).astype(int)
+            nxt = sel if np.any(np.abs(om) > OMEGA_TRIGGER) else np.zeros(0, dtype=int)
+        nrm0 = float(np.linalg.norm(w))
+        if sel.size:
+            self.info.partial_steps += 1
+            self.info.partial_columns += sel.size
+            w = cgs2(w, Q[:, sel])
+        nrm = float(np.linalg.norm(w))
+        if nrm <= BREAKDOWN_REL * self.info.sigma_est:
+            # invariant subspace: the full form (CGS2 against the whole basis,
+            # replacement vector, 0 stored in T), so every estimate restarts at EPS
+            vec, nrm = self._finish(w, Q[:, :j])
+            om = np.full(j, EPS)
+            nxt = np.zeros(0, dtype=int)
+        else:
+            om = om * (nrm0 / nrm)
+            om[sel] = EPS
+            self.info.sigma_est = max(self.info.sigma_est, nrm)
+            vec = w / nrm
+        if side == "u":
+            self.mu[:j] = om
+            self.force_u = nxt
+        else:
+            self.nu[:j] = om
+            self.force_v = nxt
+        return vec, nrm
 
     def lanczos(self, i0):
         """Alg. 1 loop from 0-based column i0 (u_{i0}, v_{i0} already set)
@@ -194,7 +301,7 @@ def sign_normalize(U, V):
 
 def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
          v0: np.ndarray | None = None, seed: int = 0, callback=None, which: str = "largest",
-         selective: bool = False):
+         selective: bool = False, partial: bool = False):
     """k largest (``which="largest"``, descending) or smallest
     (``which="smallest"``, ascending) singular triplets of A (scipy sparse
     matrix or dense array).
@@ -216,7 +323,9 @@ def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
         raise ValueError(which)
     info = SvdsInfo()
     op = _Op(A, info)
-    st = _State(op, p, seed, info, selective)
+    if selective and partial:
+        raise ValueError("selective and partial re-orthogonalisation exclude each other")
+    st = _State(op, p, seed, info, selective, partial)
 
     # Alg. 1 step 1: v_1 = randn / norm.
     v = np.asarray(v0, dtype=np.float64).copy() if v0 is not None else normal_vector(n, seed, 0)
@@ -261,9 +370,16 @@ def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
         st.V[:, :k] = Vk
         # Alg. 2 step 10: v_{k+1} = v_{t+1}; u_{k+1} = A v_{k+1} - Uk rho (eq. (7)).
         st.V[:, k] = vnext
+        if partial:
+            # estimates of v_{t+1} against the kept Ritz vectors V Vh_k
+            nu_old = st.nu[:p].copy()
+            st.nu[:] = 0.0
+            st.nu[:k] = Vh[:, :k].T @ nu_old
+            st.nu[k] = 1.0
+            st.force_u = st.force_v = np.zeros(0, dtype=int)
         w = op.mv(st.V[:, k]) - Uk @ rho
         # Alg. 2 step 11 (with re-orthogonalisation, as the text after Alg. 2 asks).
-        st.u_step(k, w)
+        st.u_step(k, w, full=True)
         info.restarts += 1
         if callback:
             callback("restart", st, dict(Uk=Uk, rho=rho))
