@@ -86,8 +86,28 @@ enum {
   SVDS_FLAG_UNSORTED = 64,    /* no column-sorted copy of the work items        */
   SVDS_FLAG_NO_PANELS = 128,  /* A^T y over the plain CSR of A^T, no panels     */
   SVDS_FLAG_SMALLEST = 256,   /* the k smallest triplets instead (see below)    */
-  SVDS_FLAG_SELECTIVE_REORTH = 512 /* second CGS pass only when needed (below) */
+  SVDS_FLAG_SELECTIVE_REORTH = 512, /* second CGS pass only when needed (below) */
+  SVDS_FLAG_PARTIAL_REORTH = 1024   /* omega-recurrence partial re-orth. (below) */
 };
+
+/* SVDS_FLAG_PARTIAL_REORTH: partial re-orthogonalization in the manner of
+ * PROPACK (the alternative to full re-orthogonalization that Sec. 1 names).
+ * The loss of orthogonality of each new vector against every earlier one of
+ * its basis is estimated on the device from the two Lanczos relations
+ * A V = U T and A^T U = V T^T (a recurrence over T and the estimates of the
+ * previous vectors, plus a local rounding term eps * sigma_est / |w|).  Only
+ * when an estimate exceeds sqrt(eps) is the vector re-orthogonalized (CGS2),
+ * and then only against the columns whose estimate exceeds eps^(3/4), plus
+ * the same columns for the next vector of that basis.  The restart vector of
+ * eq. (7) is still taken against all k kept vectors.  Singular values come
+ * out as accurate as with full re-orthogonalization; the bases, and so U and
+ * V, are only semi-orthogonal (|U^T U - I|, |V^T V - I| up to ~sqrt(eps)),
+ * and the explicit residuals |A^T u_j - s_j v_j| can exceed tol * s_j by up
+ * to ~sqrt(eps) * s_1 / s_j.  info->partial_steps, partial_columns and
+ * partial_possible count the vectors re-orthogonalized, the columns taken
+ * and the columns full re-orthogonalization would take.  FP64 single solves
+ * only (EUNSUPPORTED with SVDS_PREC_MIXED and in the batched solver); EINVAL
+ * together with SVDS_FLAG_SELECTIVE_REORTH. */
 
 /* SVDS_FLAG_SELECTIVE_REORTH: the re-orthogonalization of each new vector w
  * against its basis Q does the second classical Gram-Schmidt pass only when
@@ -231,6 +251,9 @@ typedef struct {
   svds_tuning tuning;              /* SVDS_FLAG_AUTOTUNE choices of the plan */
   int32_t reorth_tests;            /* SVDS_FLAG_SELECTIVE_REORTH: tests made */
   int32_t reorth_second_passes;    /* ... and second passes run             */
+  int64_t partial_steps;           /* SVDS_FLAG_PARTIAL_REORTH: vectors re-orthogonalized */
+  int64_t partial_columns;         /* ... basis columns they were taken against */
+  int64_t partial_possible;        /* ... columns full re-orthogonalization takes */
 } svds_info;
 
 typedef struct svds_plan svds_plan;

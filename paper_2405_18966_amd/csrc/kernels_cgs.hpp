@@ -77,17 +77,33 @@ __global__ __launch_bounds__(256) void reduce_cols_kernel(const T *__restrict__ 
 // stream fastest on MI355X; 32-column groups reach half the rate).
 // part: [j][nslab]; with normw the blocks of column group 0 also write the
 // partials of |w|^2 as column j (read by the selective second pass).
+// MASK: only the columns c with cmask[c] != 0 are read (partial
+// re-orthogonalization); the others get zero partials, and a block none of
+// whose columns is selected writes its zeros without reading anything.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+template <typename T, int N, bool MASK = false>
 __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restrict__ Q, int64_t ldq,
                                                               int64_t L, int j, const T *__restrict__ w,
-                                                              T *__restrict__ part, int normw) {
+                                                              T *__restrict__ part, int normw,
+                                                              const int *__restrict__ cmask) {
   constexpr int NW = CGS_THREADS / WAVE;
   __shared__ T red[NW][CGS_PCG + 1];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int nslab = gridDim.x, slab = blockIdx.x;
   const int c0 = blockIdx.y * CGS_PCG;
-  const int nc = min(CGS_PCG, j - c0);
+  int nc = min(CGS_PCG, j - c0);
+  bool en[CGS_PCG];
+#pragma unroll
+  for (int c = 0; c < CGS_PCG; ++c) en[c] = c < nc && (!MASK || cmask[c0 + c] != 0);
+  if (MASK) {
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < CGS_PCG; ++c) any = any || en[c];
+    if (!any && !(normw && blockIdx.y == 0)) {
+      if (tid < nc) part[static_cast<int64_t>(c0 + tid) * nslab + slab] = T(0);
+      return;
+    }
+  }
   const int64_t R = static_cast<int64_t>(WAVE) * N;
   const int64_t tiles = ceil_div(L, R);
   const int64_t per = ceil_div(tiles, nslab);
@@ -107,7 +123,7 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restri
         for (int i = 0; i < N; ++i) nw += wr[i] * wr[i];
 #pragma unroll
       for (int c = 0; c < CGS_PCG; ++c) {
-        if (c < nc) {
+        if (MASK ? en[c] : c < nc) {
           T q[N];
           load_rows<T, N>(Qc + c * ldq + r, L - r, q);
 #pragma unroll
@@ -149,13 +165,15 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restri
 // per wave stream at a third of the rate or less.
 // Bases wider than 16 * CPW use a separate update pass plus cgs_proj instead.
 // part: [j][nblk]; with normw1 also the partials of |w1|^2 as column j.
+// MASK: only the columns with cmask[c] != 0 are read (the others have h1 = 0
+// and get zero partials).
 // ---------------------------------------------------------------------------
-template <typename T, int CPW, bool PF, int N>
+template <typename T, int CPW, bool PF, int N, bool MASK = false>
 __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict__ Q, int64_t ldq,
                                                            int64_t L, int j, const T *__restrict__ w,
                                                            const T *__restrict__ h1,
                                                            T *__restrict__ w1out, T *__restrict__ part,
-                                                           int normw1) {
+                                                           int normw1, const int *__restrict__ cmask) {
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ T xch[2][16][WAVE * N];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
@@ -165,6 +183,9 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict_
   const int c0 = wv * CPW;
   const int nc = max(0, min(CPW, j - c0));
   for (int c = j + tid; c < NW * CPW; c += blockDim.x) sh_h[c] = T(0);  // padding columns
+  bool en[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) en[c] = c < nc && (!MASK || cmask[c0 + c] != 0);
   __syncthreads();
   const int64_t R = static_cast<int64_t>(WAVE) * N;
   const int64_t tiles = ceil_div(L, R);
@@ -187,7 +208,7 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict_
     if (r < L) {
 #pragma unroll
       for (int c = 0; c < CPW; ++c)
-        if (c < nc) load_rows<T, N>(Qc + c * ldq + r, L - r, qn[c]);
+        if (MASK ? en[c] : c < nc) load_rows<T, N>(Qc + c * ldq + r, L - r, qn[c]);
       load_rows<T, N>(w + r, L - r, wn);
     }
   };
@@ -258,16 +279,35 @@ __device__ __forceinline__ int cgs_second_pass_width(int j, const T *h, const T 
 // Pass 3: out = w1 - Q h; with `npart` non-null, partials of |out|^2 (FP64).
 // Grid-stride rows, the column loop unrolled 8-wide for loads in flight.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+// MASK: only the columns with cmask[c] != 0 are read.
+template <typename T, int N, bool MASK = false>
 __global__ __launch_bounds__(CGS_THREADS) void cgs_upd_norm_kernel(
     const T *__restrict__ Q, int64_t ldq, int64_t L, int j, const T *__restrict__ w1,
     const T *__restrict__ h, T *__restrict__ out, double *__restrict__ npart, const T *__restrict__ sel,
-    int *__restrict__ ran) {
+    int *__restrict__ ran, const int *__restrict__ cmask) {
   __shared__ T sh_h[CGS_MAXJ];
+  __shared__ int sh_c[MASK ? CGS_MAXJ : 1];
   __shared__ double sh_d[CGS_THREADS / WAVE];
   const int tid = threadIdx.x;
   j = cgs_second_pass_width(j, h, sel, ran);
   for (int c = tid; c < j; c += CGS_THREADS) sh_h[c] = h[c];
+  if (MASK) {
+    // the selected columns, in increasing order (one wave compacts them)
+    __shared__ int sh_n;
+    if (tid < WAVE) {
+      int base = 0;
+      for (int c0 = 0; c0 < j; c0 += WAVE) {
+        const int c = c0 + tid;
+        const bool on = c < j && cmask[c] != 0;
+        const uint64_t bal = __ballot(on);
+        if (on) sh_c[base + __popcll(bal & ((uint64_t(1) << tid) - 1))] = c;
+        base += __popcll(bal);
+      }
+      if (tid == 0) sh_n = base;
+    }
+    __syncthreads();
+    j = sh_n;
+  }
   __syncthreads();
   double nrm2 = 0;
   for (int64_t r = (static_cast<int64_t>(blockIdx.x) * CGS_THREADS + tid) * N; r < L;
@@ -281,17 +321,19 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_upd_norm_kernel(
     for (; c + 8 <= j; c += 8) {
 #pragma unroll
       for (int g = 0; g < 8; ++g) {
+        const int col = MASK ? sh_c[c + g] : c + g;
         T q[N];
-        load_rows<T, N>(Q + (c + g) * ldq + r, L - r, q);
+        load_rows<T, N>(Q + col * ldq + r, L - r, q);
 #pragma unroll
-        for (int i = 0; i < N; ++i) u[g][i] += q[i] * sh_h[c + g];
+        for (int i = 0; i < N; ++i) u[g][i] += q[i] * sh_h[col];
       }
     }
     for (; c < j; ++c) {
+      const int col = MASK ? sh_c[c] : c;
       T q[N];
-      load_rows<T, N>(Q + c * ldq + r, L - r, q);
+      load_rows<T, N>(Q + col * ldq + r, L - r, q);
 #pragma unroll
-      for (int i = 0; i < N; ++i) u[0][i] += q[i] * sh_h[c];
+      for (int i = 0; i < N; ++i) u[0][i] += q[i] * sh_h[col];
     }
     T wv[N], x[N];
     load_rows<T, N>(w1 + r, L - r, wv);
@@ -320,12 +362,12 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_upd_norm_kernel(
 constexpr int CGS_TILE_CPW = 16;
 constexpr int CGS_TILE_MAXJ = 16 * CGS_TILE_CPW;  // 16 waves
 
-template <typename T, int N>
+template <typename T, int N, bool MASK = false>
 __global__ __launch_bounds__(1024) void cgs_tile_upd_kernel(const T *__restrict__ Q, int64_t ldq, int64_t L,
                                                             int j, const T *__restrict__ w1,
                                                             const T *__restrict__ h, T *__restrict__ out,
                                                             double *__restrict__ npart, const T *__restrict__ sel,
-                                                            int *__restrict__ ran) {
+                                                            int *__restrict__ ran, const int *__restrict__ cmask) {
   constexpr int CPW = CGS_TILE_CPW;
   j = cgs_second_pass_width(j, h, sel, ran);
   __shared__ T sh_h[CGS_TILE_MAXJ];
@@ -345,7 +387,7 @@ __global__ __launch_bounds__(1024) void cgs_tile_upd_kernel(const T *__restrict_
     T q[CPW][N];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
-      if (c < nc) load_rows<T, N>(Q + (c0 + c) * ldq + r, L - r, q[c]);
+      if (c < nc && (!MASK || cmask[c0 + c] != 0)) load_rows<T, N>(Q + (c0 + c) * ldq + r, L - r, q[c]);
       else
 #pragma unroll
         for (int i = 0; i < N; ++i) q[c][i] = 0;
@@ -402,7 +444,32 @@ struct FinishArgs {
   double *sigma_est;    // running max of alpha, beta, sigma_1
   int *breakdowns;      // breakdown counter of the solve
   uint64_t seed;
+  // partial re-orthogonalization (om_row non-null): the new vector's
+  // orthogonality estimates against the j earlier ones of its side become
+  // om_row[0..j) and om_row[j] = 1: the pending estimates (om_pend, made
+  // with the norm *om_nrm0 before re-orthogonalization) rescaled to the final
+  // norm, EPS for the columns it was re-orthogonalized against (om_mask), and
+  // EPS everywhere when om_full or on a breakdown (taken against the whole
+  // basis; a breakdown also clears the side's forced set om_force).
+  double *om_row;
+  const double *om_pend;
+  const int *om_mask;
+  const double *om_nrm0;
+  int *om_force;
+  int om_full;
 };
+
+constexpr double OMEGA_EPS = 0x1.0p-52;
+
+__device__ __forceinline__ void omega_fix(const FinishArgs &fa, int j, double nrm, bool all_eps) {
+  if (!fa.om_row) return;
+  const double scale = (!all_eps && nrm > 0) ? *fa.om_nrm0 / nrm : 0.0;
+  for (int l = threadIdx.x; l < j; l += blockDim.x) {
+    fa.om_row[l] = (all_eps || fa.om_full || fa.om_mask[l]) ? OMEGA_EPS : fa.om_pend[l] * scale;
+    if (all_eps) fa.om_force[l] = 0;
+  }
+  if (threadIdx.x == 0) fa.om_row[j] = 1.0;
+}
 
 template <typename T>
 __device__ void breakdown_repair(const T *__restrict__ Q, int64_t ldq, int64_t L, int j,
@@ -463,8 +530,10 @@ __global__ __launch_bounds__(CGS_THREADS) void finish_norm_kernel(const double *
       *fa.xs = 1.0 / nrm;
       *fa.sigma_est = fmax(sig, nrm);
     }
+    omega_fix(fa, j, nrm, false);
     return;
   }
+  omega_fix(fa, j, 0.0, true);
   // Breakdown: the new vector lies in the span of Q (an invariant subspace was
   // found).  Replace it by a re-orthogonalized random vector, store 0 in T.
   if (tid == 0) {
@@ -475,6 +544,118 @@ __global__ __launch_bounds__(CGS_THREADS) void finish_norm_kernel(const double *
   }
   __syncthreads();
   breakdown_repair<T>(Q, ldq, L, j, out, static_cast<uint32_t>(bd), fa.seed, sh_d, sh_h);
+}
+
+// ---------------------------------------------------------------------------
+// Partial re-orthogonalization (one block of CGS_THREADS threads per step).
+// The loss of orthogonality of the new, unnormalized vector w against every
+// earlier vector of its side follows from the two Lanczos relations
+// A V = U T and A^T U = V T^T (T row-major, leading dimension ld):
+//   V side, w = A^T u_i - T(i,i) v_i, estimates for l <= i:
+//     v_l^T w = sum_{r<=l} T(r,l) mu[r] - T(i,i) nu[l]
+//   U side, w = A v_i - T(i-1,i) u_{i-1}, estimates for l < i:
+//     u_l^T w = sum_{c<=i} T(l,c) nu[c] - T(i-1,i) mu[l]
+// with mu / nu the estimate rows of the newest u and v (their own entry 1),
+// plus a local rounding term EPS sigma_est with the sign of the sum, divided
+// by |w| (from the norm partials of w).  An estimate above `tau` triggers a
+// re-orthogonalization against the columns whose estimate is above `eta`,
+// together with the columns `force` holds (the set of the previous vector of
+// this side, when that one triggered); a trigger also sets `force` for the
+// next vector of the side.  Outputs: cmask (the columns to take w against),
+// the pending estimates and |w| for the finish step (omega_fix), and
+// counters stats[0] += 1 and stats[1] += selected columns when any column is
+// selected, stats[2] += j.
+// ---------------------------------------------------------------------------
+struct OmegaArgs {
+  const double *T;
+  int ld;
+  int side;  // 0: the new vector is v_{i+1}; 1: it is u_i
+  int i;
+  const double *npart;
+  int nparts;
+  const double *sigma_est;
+  const double *mu, *nu;
+  int *force, *cmask;
+  double *pend, *nrm0;
+  long long *stats;
+  double tau, eta;
+};
+
+static __global__ __launch_bounds__(CGS_THREADS) void omega_kernel(OmegaArgs a) {
+  __shared__ double sh_d[CGS_THREADS / WAVE];
+  const int tid = threadIdx.x;
+  double tot = strided_sum(a.npart, tid, a.nparts, CGS_THREADS, 0.0);
+  tot = block_sum(tot, sh_d);
+  const double nrm = sqrt(tot);
+  const double rnd = OMEGA_EPS * *a.sigma_est;
+  const int i = a.i, ld = a.ld;
+  const int j = a.side == 0 ? i + 1 : i;  // earlier vectors of the side
+  int trig = 0, forced = 0;
+  for (int l = tid; l < j; l += CGS_THREADS) {
+    double x;
+    if (a.side == 0) {
+      x = -a.T[i * ld + i] * a.nu[l];
+      for (int r = 0; r <= l; ++r) x += a.T[r * ld + l] * a.mu[r];
+    } else {
+      x = -a.T[(i - 1) * ld + i] * a.mu[l];
+      for (int c = 0; c <= i; ++c) x += a.T[l * ld + c] * a.nu[c];
+    }
+    const double om = nrm > 0 ? (x + (x >= 0 ? rnd : -rnd)) / nrm : INFINITY;
+    a.pend[l] = om;
+    trig |= fabs(om) > a.tau;
+    forced |= a.force[l] != 0;
+  }
+  trig = __syncthreads_or(trig);
+  forced = __syncthreads_or(forced);
+  int cnt = 0;
+  for (int l = tid; l < j; l += CGS_THREADS) {
+    const bool on = (trig || forced) && (fabs(a.pend[l]) > a.eta || a.force[l] != 0);
+    a.cmask[l] = on ? 1 : 0;
+    a.force[l] = (trig && on) ? 1 : 0;
+    cnt += on ? 1 : 0;
+  }
+  cnt = static_cast<int>(block_sum(static_cast<double>(cnt), sh_d));
+  if (tid == 0) {
+    *a.nrm0 = nrm;
+    if (cnt > 0) {
+      a.stats[0] += 1;
+      a.stats[1] += cnt;
+    }
+    a.stats[2] += j;
+  }
+}
+
+// Restart (Alg. 2 step 10): v_{k+1} = v_{p+1}, so its estimates against the
+// kept Ritz vectors V Vh(:, l) are nu_new[l] = sum_c Vh(c, l) nu[c], c < p
+// (Vext column-major, leading dimension p + 1); nu[k] = 1, the rest 0; the
+// forced sets of both sides are cleared.  One block; pend is scratch.
+static __global__ __launch_bounds__(CGS_THREADS) void omega_restart_kernel(const double *__restrict__ Vext, int p, int k,
+                                                                   double *nu, double *pend, int *force_u,
+                                                                   int *force_v) {
+  const int tid = threadIdx.x;
+  for (int l = tid; l < k; l += CGS_THREADS) {
+    double x = 0;
+    for (int c = 0; c < p; ++c) x += Vext[static_cast<int64_t>(l) * (p + 1) + c] * nu[c];
+    pend[l] = x;
+  }
+  __syncthreads();
+  for (int l = tid; l <= p + 1; l += CGS_THREADS) {
+    nu[l] = l < k ? pend[l] : (l == k ? 1.0 : 0.0);
+    force_u[l] = 0;
+    force_v[l] = 0;
+  }
+}
+
+// Start of a solve: estimate rows of u_1 and v_1 (their own entry 1), no
+// forced sets, the 8 counters (both sides) zero.
+static __global__ void omega_init_kernel(int p, double *mu, double *nu, int *force_u, int *force_v, long long *stats) {
+  for (int l = threadIdx.x; l <= p + 1; l += blockDim.x) {
+    mu[l] = l == 0 ? 1.0 : 0.0;
+    nu[l] = l == 0 ? 1.0 : 0.0;
+    force_u[l] = 0;
+    force_v[l] = 0;
+  }
+  if (threadIdx.x < 8) stats[threadIdx.x] = 0;
 }
 
 // Launch shapes (host side), tuned on MI355X.

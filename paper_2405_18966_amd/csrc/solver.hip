@@ -272,7 +272,17 @@ struct Small {
   double *sgn, *sgn_val;            // sign normalization
   int64_t *sgn_idx;
   int *bd, *flags;
+  // partial re-orthogonalization: estimate rows of the newest u and v,
+  // pending estimates and |w| of the vector in progress, its column mask,
+  // the forced sets of both sides, counters (U side [0..3), V side [4..7))
+  double *om_mu, *om_nu, *om_pend, *om_nrm0;
+  int *om_mask, *om_fu, *om_fv;
+  long long *om_stats;
 };
+
+// thresholds of the partial re-orthogonalization: trigger sqrt(eps), select eps^(3/4)
+constexpr double OMEGA_TAU = 1.4901161193847656e-08;
+constexpr double OMEGA_ETA = 1.8189894035458565e-12;
 
 constexpr int NPART = NORM_MAX_BLOCKS;  // norm partials
 
@@ -313,6 +323,7 @@ struct svds_plan {
   svds_tuning tuning{};  // what the tuner chose and measured
   bool smallest = false;  // SVDS_FLAG_SMALLEST: k smallest triplets, ascending
   bool selective = false;  // SVDS_FLAG_SELECTIVE_REORTH: second CGS pass only when needed
+  bool partial = false;    // SVDS_FLAG_PARTIAL_REORTH: omega-recurrence partial re-orthogonalization
   int64_t reorth_calls = 0;  // re-orthogonalizations with the selective test
 };
 
@@ -425,7 +436,7 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
 // ---------------------------------------------------------------------------
 template <typename TB>
 static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int64_t L, int j,
-                           const TB *w, TB *h, int kc, int normw = 0) {
+                           const TB *w, TB *h, int kc, int normw = 0, const int *cmask = nullptr) {
   const double sb = sizeof(TB);
   int nslab, ngc;
   cgs_proj_shape(L, j, nslab, ngc);
@@ -436,14 +447,20 @@ static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int
     nslab = std::max(1, nslab >> -P->cgs_slab_shift);
   constexpr int NV = 16 / sizeof(TB);
   ACC_BEFORE_ATT(kc);
-  if (cgs_rows_per_lane<TB>(Q, ldq, w, nullptr, nullptr) == NV)
-    klaunch(P->acc, true, true, cgs_proj_kernel<TB, NV>, dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
-            L, j, w, part, normw);
+  const bool vec = cgs_rows_per_lane<TB>(Q, ldq, w, nullptr, nullptr) == NV;
+  const dim3 g(nslab, ngc), b(CGS_THREADS);
+  if (cmask && vec)
+    klaunch(P->acc, true, true, cgs_proj_kernel<TB, NV, true>, g, b, 0, P->stream, Q, ldq, L, j, w, part, normw, cmask);
+  else if (cmask)
+    klaunch(P->acc, true, true, cgs_proj_kernel<TB, 1, true>, g, b, 0, P->stream, Q, ldq, L, j, w, part, normw, cmask);
+  else if (vec)
+    klaunch(P->acc, true, true, cgs_proj_kernel<TB, NV>, g, b, 0, P->stream, Q, ldq, L, j, w, part, normw, cmask);
   else
-    klaunch(P->acc, true, true, cgs_proj_kernel<TB, 1>, dim3(nslab, ngc), dim3(CGS_THREADS), 0, P->stream, Q, ldq,
-            L, j, w, part, normw);
+    klaunch(P->acc, true, true, cgs_proj_kernel<TB, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, part, normw, cmask);
   LAUNCH_CHECK();
-  ACC_AFTER(kc, sb * L * j + sb * L, 2.0 * L * j);
+  // with a column mask the columns read are counted at the end of the solve
+  const double jc = cmask ? 0.0 : static_cast<double>(j);
+  ACC_AFTER(kc, sb * L * jc + sb * L, 2.0 * L * jc);
   // h[0:j], and with normw h[j] = |w|^2
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
   hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j + normw, 4)), dim3(256), 0, P->stream, part,
@@ -458,34 +475,59 @@ static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int
 // sel/ran: the selective second pass (see cgs_second_pass_width).
 template <typename TB>
 static int launch_upd_norm(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, int j, const TB *w, const TB *h,
-                           TB *out, double *npart, const TB *sel = nullptr, int *ran = nullptr) {
+                           TB *out, double *npart, const TB *sel = nullptr, int *ran = nullptr,
+                           const int *cmask = nullptr) {
   constexpr int NV = 16 / sizeof(TB);
   const bool vec = cgs_rows_per_lane<TB>(Q, ldq, w, out, nullptr) == NV;
   const int nr = vec ? NV : 1;
   if (j > 0 && cgs_tile_upd_ok(L, j, nr)) {
     const int nt = static_cast<int>(ceil_div(L, static_cast<int64_t>(WAVE) * nr));
     const int nw = static_cast<int>(ceil_div(j, CGS_TILE_CPW));
-    if (vec)
-      klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, NV>, dim3(nt), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j,
-              w, h, out, npart, sel, ran);
+    const dim3 g(nt), b(nw * WAVE);
+    if (cmask && vec)
+      klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, NV, true>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out,
+              npart, sel, ran, cmask);
+    else if (cmask)
+      klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, 1, true>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out,
+              npart, sel, ran, cmask);
+    else if (vec)
+      klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, NV>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out, npart,
+              sel, ran, cmask);
     else
-      klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, 1>, dim3(nt), dim3(nw * WAVE), 0, P->stream, Q, ldq, L, j,
-              w, h, out, npart, sel, ran);
+      klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out, npart,
+              sel, ran, cmask);
     return nt;
   }
   const int nn = cgs_updnorm_blocks(L);
-  if (vec)
-    klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, NV>, dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
-            w, h, out, npart, sel, ran);
+  const dim3 g(nn), b(CGS_THREADS);
+  if (cmask && j > 0 && vec)
+    klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, NV, true>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out,
+            npart, sel, ran, cmask);
+  else if (cmask && j > 0)
+    klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, 1, true>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out,
+            npart, sel, ran, cmask);
+  else if (vec)
+    klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, NV>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out, npart, sel,
+            ran, cmask);
   else
-    klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, 1>, dim3(nn), dim3(CGS_THREADS), 0, P->stream, Q, ldq, L, j,
-            w, h, out, npart, sel, ran);
+    klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out, npart, sel,
+            ran, cmask);
   return nn;
 }
 
+// Partial re-orthogonalization of one new vector (SVDS_FLAG_PARTIAL_REORTH):
+// side 0 = v_{i+1} from A^T u_i, side 1 = u_i from A v_i; full = the vector
+// is taken against the whole basis (restart vector of eq. (7)) and only its
+// estimate row is reset.
+struct OmegaStep {
+  int side, i;
+  bool full;
+};
+
 template <typename TB>
 static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int64_t ldq, int64_t L, int j,
-                       const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs) {
+                       const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs,
+                       const OmegaStep *om = nullptr) {
   const double sb = sizeof(TB);
   const Small &s = P->sc;
   const TB *src = w;
@@ -495,9 +537,23 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
   // selective second pass: |w|^2 and |w1|^2 ride along as column j of the
   // first two passes' reductions
   const int sel = (P->selective && j > 0) ? 1 : 0;
+  // partial re-orthogonalization: |w| and the estimates pick the columns
+  const int *cmask = nullptr;
+  if (om && !om->full && j > 0) {
+    const int nb = static_cast<int>(std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(L, 2048))));
+    ACC_BEFORE(SVDS_KC_CGS_REDUCE);
+    hipLaunchKernelGGL((norm_partials_kernel<TB>), dim3(nb), dim3(256), 0, P->stream, L, w, s.npart);
+    OmegaArgs oa{s.T, P->p + 1, om->side, om->i, s.npart, nb, s.sigma_est, s.om_mu, s.om_nu,
+                 om->side ? s.om_fu : s.om_fv, s.om_mask, s.om_pend, s.om_nrm0,
+                 s.om_stats + (om->side ? 0 : 4), OMEGA_TAU, OMEGA_ETA};
+    hipLaunchKernelGGL(omega_kernel, dim3(1), dim3(CGS_THREADS), 0, P->stream, oa);
+    LAUNCH_CHECK();
+    ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * L + 8.0 * nb, 2.0 * L);
+    cmask = s.om_mask;
+  }
   if (j > 0) {
     // pass 1: h1 = Q^T w
-    if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ, sel))) return rc;
+    if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ, sel, cmask))) return rc;
     // pass 2: w1 = w - Q h1, h2 = Q^T w1
     int cpw = cgs_fused_cpw(j, static_cast<int>(sizeof(TB)));
     // a forced width must keep the block within 16 waves
@@ -508,20 +564,34 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
       ACC_BEFORE_ATT(SVDS_KC_CGS_UPDPROJ);
       // one row per lane with register prefetch (two rows per lane raise
       // register pressure); FP32 bases with 10 columns take 16-byte rows
-      if (cpw == 8)
-        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 8, true, 1>, dim3(nb), dim3(nw * WAVE), 0, P->stream, Q,
-                ldq, L, j, w, h1, w1, part, sel);
+      const dim3 g(nb), b(nw * WAVE);
+      if (cmask && cpw == 8)
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 8, true, 1, true>, g, b, 0, P->stream, Q, ldq, L, j, w,
+                h1, w1, part, sel, cmask);
+      else if (cmask && sizeof(TB) == 8)
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, true, 1, true>, g, b, 0, P->stream, Q, ldq, L, j, w,
+                h1, w1, part, sel, cmask);
+      else if (cmask && vec)
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, NV, true>, g, b, 0, P->stream, Q, ldq, L, j,
+                w, h1, w1, part, sel, cmask);
+      else if (cmask)
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, 1, true>, g, b, 0, P->stream, Q, ldq, L, j,
+                w, h1, w1, part, sel, cmask);
+      else if (cpw == 8)
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 8, true, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, h1, w1,
+                part, sel, cmask);
       else if (sizeof(TB) == 8)
-        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, true, 1>, dim3(nb), dim3(nw * WAVE), 0, P->stream,
-                Q, ldq, L, j, w, h1, w1, part, sel);
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, true, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, h1,
+                w1, part, sel, cmask);
       else if (vec)
-        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, NV>, dim3(nb), dim3(nw * WAVE), 0, P->stream,
-                Q, ldq, L, j, w, h1, w1, part, sel);
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, NV>, g, b, 0, P->stream, Q, ldq, L, j, w, h1,
+                w1, part, sel, cmask);
       else
-        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, 1>, dim3(nb), dim3(nw * WAVE), 0, P->stream,
-                Q, ldq, L, j, w, h1, w1, part, sel);
+        klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, h1,
+                w1, part, sel, cmask);
       LAUNCH_CHECK();
-      ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 4.0 * L * j);
+      const double jc = cmask ? 0.0 : static_cast<double>(j);
+      ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * jc + 2 * sb * L, 4.0 * L * jc);
       ACC_BEFORE(SVDS_KC_CGS_REDUCE);
       hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j + sel, 4)), dim3(256), 0, P->stream, part,
                          static_cast<int64_t>(nb), nb, j + sel, h2);
@@ -530,10 +600,11 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     } else {
       // wide basis: separate update and projection passes
       ACC_BEFORE_ATT(SVDS_KC_CGS_UPDPROJ);
-      launch_upd_norm<TB>(P, Q, ldq, L, j, w, h1, w1, nullptr);
+      launch_upd_norm<TB>(P, Q, ldq, L, j, w, h1, w1, nullptr, nullptr, nullptr, cmask);
       LAUNCH_CHECK();
-      ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * j + 2 * sb * L, 2.0 * L * j);
-      if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w1, h2, SVDS_KC_CGS_UPDPROJ, sel))) return rc;
+      const double jc = cmask ? 0.0 : static_cast<double>(j);
+      ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * jc + 2 * sb * L, 2.0 * L * jc);
+      if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w1, h2, SVDS_KC_CGS_UPDPROJ, sel, cmask))) return rc;
     }
     src = w1;
   }
@@ -541,11 +612,20 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
   // for it; the accounting then counts the vector traffic alone)
   ACC_BEFORE_ATT(SVDS_KC_CGS_UPDNORM);
   const int nn = launch_upd_norm<TB>(P, Q, ldq, L, j, src, h2, out, s.npart, sel ? h1 + j : nullptr,
-                                     sel ? s.bd + 1 : nullptr);
+                                     sel ? s.bd + 1 : nullptr, cmask);
   LAUNCH_CHECK();
-  ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * (sel ? 0 : j) + 2 * sb * L, 2.0 * L * (sel ? 0 : j) + 2.0 * L);
+  const int jn = (sel || cmask) ? 0 : j;
+  ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * jn + 2 * sb * L, 2.0 * L * jn + 2.0 * L);
   if (sel) ++P->reorth_calls;
   FinishArgs fa{t_entry, xs, s.sigma_est, s.bd, P->opts.seed};
+  if (om) {
+    fa.om_row = om->side ? s.om_mu : s.om_nu;
+    fa.om_pend = s.om_pend;
+    fa.om_mask = s.om_mask;
+    fa.om_nrm0 = s.om_nrm0;
+    fa.om_force = om->side ? s.om_fu : s.om_fv;
+    fa.om_full = (om->full || j == 0) ? 1 : 0;
+  }
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
   hipLaunchKernelGGL((finish_norm_kernel<TB>), dim3(1), dim3(CGS_THREADS), 0, P->stream, s.npart, nn,
                      mode, fa, Q, ldq, L, j, out);
@@ -556,8 +636,9 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
 
 template <typename TB>
 static int cgs2_finish(svds_plan *P, Lanczos<TB> &Lz, const TB *Q, int64_t ldq, int64_t L, int j,
-                       const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs) {
-  return cgs2_finish<TB>(P, Lz.partials, Lz.h1, Lz.h2, Q, ldq, L, j, w, w1, out, mode, t_entry, xs);
+                       const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs,
+                       const OmegaStep *om = nullptr) {
+  return cgs2_finish<TB>(P, Lz.partials, Lz.h1, Lz.h2, Q, ldq, L, j, w, w1, out, mode, t_entry, xs, om);
 }
 
 // Update only: out = w - Q h (restart, eq. (7)).
@@ -599,8 +680,9 @@ template <typename TB> static int lanczos(svds_plan *P, Lanczos<TB> &Lz, int i0)
     int rc = matvec<TB>(P, true, Lz.bu, s.xs_u, s.T + i * ld + i, V + i * Lz.ldv, Lz.wv,
                         U + i * Lz.ldu, m);
     if (rc) return rc;
+    const OmegaStep omv{0, i, false};
     rc = cgs2_finish<TB>(P, Lz, V, Lz.ldv, n, i + 1, Lz.wv, Lz.w1v, Lz.bv, MODE_LANCZOS,
-                         s.T + i * ld + i + 1, s.xs_v);
+                         s.T + i * ld + i + 1, s.xs_v, P->partial ? &omv : nullptr);
     if (rc) return rc;
     if (i == p - 1) {
       // v_{p+1}: normalized into V[:, p] (no product consumes it in this cycle)
@@ -613,8 +695,9 @@ template <typename TB> static int lanczos(svds_plan *P, Lanczos<TB> &Lz, int i0)
     rc = matvec<TB>(P, false, Lz.bv, s.xs_v, s.T + i * ld + i + 1, U + i * Lz.ldu, Lz.wu,
                     V + (i + 1) * Lz.ldv, n);
     if (rc) return rc;
+    const OmegaStep omu{1, i + 1, false};
     rc = cgs2_finish<TB>(P, Lz, U, Lz.ldu, m, i + 1, Lz.wu, Lz.w1u, Lz.bu, MODE_LANCZOS,
-                         s.T + (i + 1) * ld + i + 1, s.xs_u);
+                         s.T + (i + 1) * ld + i + 1, s.xs_u, P->partial ? &omu : nullptr);
     if (rc) return rc;
   }
   return SVDS_OK;
@@ -641,7 +724,14 @@ template <typename TB> static int start(svds_plan *P, Lanczos<TB> &Lz, const dou
   rc = matvec<TB>(P, false, Lz.bv, s.xs_v, nullptr, nullptr, Lz.wu, Lz.V[0], n);
   if (rc) return rc;
   // alpha_1 (no re-orthogonalization for the first vector)
-  return cgs2_finish<TB>(P, Lz, nullptr, 0, m, 0, Lz.wu, nullptr, Lz.bu, MODE_LANCZOS, s.T, s.xs_u);
+  if (P->partial) {
+    hipLaunchKernelGGL(omega_init_kernel, dim3(1), dim3(256), 0, P->stream, P->p, s.om_mu, s.om_nu, s.om_fu,
+                       s.om_fv, s.om_stats);
+    LAUNCH_CHECK();
+  }
+  const OmegaStep om0{1, 0, true};
+  return cgs2_finish<TB>(P, Lz, nullptr, 0, m, 0, Lz.wu, nullptr, Lz.bu, MODE_LANCZOS, s.T, s.xs_u,
+                         P->partial ? &om0 : nullptr);
 }
 
 // Alg. 2 steps 4-7: small SVD, eq. (4) test; returns converged flag via h_flags.
@@ -672,6 +762,11 @@ template <typename TB> static int restart(svds_plan *P, Lanczos<TB> &Lz) {
   rc = rotate<TB, TB>(P, Lz.n, p + 1, k + 1, V, Lz.ldv, s.Vext, ld, Vn, Lz.ldv);
   if (rc) return rc;
   Lz.cur = nxt;
+  if (P->partial) {  // estimates of v_{k+1} = v_{p+1} against the kept Ritz vectors
+    hipLaunchKernelGGL(omega_restart_kernel, dim3(1), dim3(CGS_THREADS), 0, P->stream, s.Vext, p, k, s.om_nu,
+                       s.om_pend, s.om_fu, s.om_fv);
+    LAUNCH_CHECK();
+  }
   // w = A v_{k+1}
   rc = matvec<TB>(P, false, Vn + k * Lz.ldv, s.one, nullptr, nullptr, Lz.wu, nullptr, 0);
   if (rc) return rc;
@@ -683,8 +778,9 @@ template <typename TB> static int restart(svds_plan *P, Lanczos<TB> &Lz) {
   rc = gemv_update<TB>(P, Un, Lz.ldu, Lz.m, k, Lz.wu, rho_b, Lz.w1u);
   if (rc) return rc;
   // CGS2 against Uk, alpha_{k+1} = T(k, k)
+  const OmegaStep omr{1, k, true};
   return cgs2_finish<TB>(P, Lz, Un, Lz.ldu, Lz.m, k, Lz.w1u, Lz.wu, Lz.bu, MODE_LANCZOS,
-                         s.T + k * ld + k, s.xs_u);
+                         s.T + k * ld + k, s.xs_u, P->partial ? &omr : nullptr);
 }
 
 // One cycle body through the graph cache (CycleGraphs): captured at its first
@@ -831,9 +927,13 @@ static int fill_defaults(const svds_opts *o, int64_t m, int64_t n, svds_plan *P)
   P->mixed = o->precision == SVDS_PREC_MIXED;
   P->smallest = (o->flags & SVDS_FLAG_SMALLEST) != 0;
   P->selective = (o->flags & SVDS_FLAG_SELECTIVE_REORTH) != 0;
+  P->partial = (o->flags & SVDS_FLAG_PARTIAL_REORTH) != 0;
   if (o->precision != SVDS_PREC_FP64 && o->precision != SVDS_PREC_MIXED) return SVDS_EINVAL;
+  if (P->selective && P->partial) return SVDS_EINVAL;
   // the FP32 phase cannot resolve values below ~1e-7 sigma_1
   if (P->smallest && P->mixed) return SVDS_EUNSUPPORTED;
+  // the partial form's thresholds are those of FP64 arithmetic
+  if (P->partial && P->mixed) return SVDS_EUNSUPPORTED;
   if (P->k < 1 || P->p <= P->k || P->p > m || P->p + 1 > n) return SVDS_EINVAL;
   if (P->p + 1 > CGS_MAXJ) return SVDS_EUNSUPPORTED;
   return SVDS_OK;
@@ -875,6 +975,16 @@ static int carve_all(svds_plan *P, Arena &a) {
   s.sgn = a.take<double>(k);
   s.sgn_val = a.take<double>(static_cast<size_t>(k) * SIGN_MAX_SLABS);
   s.sgn_idx = a.take<int64_t>(static_cast<size_t>(k) * SIGN_MAX_SLABS);
+  if (P->partial) {
+    s.om_mu = a.take<double>(p + 2);
+    s.om_nu = a.take<double>(p + 2);
+    s.om_pend = a.take<double>(p + 2);
+    s.om_nrm0 = a.take<double>(1);
+    s.om_mask = a.take<int>(p + 2);
+    s.om_fu = a.take<int>(p + 2);
+    s.om_fv = a.take<int>(p + 2);
+    s.om_stats = a.take<long long>(8);
+  }
   P->tmp_m = a.take<double>(m);
   P->tmp_n = a.take<double>(n);
   if (P->mixed) P->tmp_nk = a.take<double>(static_cast<size_t>(n) * k);
@@ -1923,6 +2033,17 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
   int bd2[2] = {0, 0};  // breakdowns, selective second passes run
   HIP_TRY(hipMemcpy(bd2, P->sc.bd, 2 * sizeof(int), hipMemcpyDeviceToHost));
   bd = bd2[0];
+  long long om[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // partial form: U side, V side counters
+  if (P->partial) {
+    HIP_TRY(hipMemcpy(om, P->sc.om_stats, sizeof om, hipMemcpyDeviceToHost));
+    // the masked passes were counted with their vector traffic only: each
+    // column taken is read by all three passes
+    const double sb = 8.0, cu = static_cast<double>(om[1]) * P->op.m, cv = static_cast<double>(om[5]) * P->op.n;
+    for (int c : {SVDS_KC_CGS_PROJ, SVDS_KC_CGS_UPDPROJ, SVDS_KC_CGS_UPDNORM}) {
+      P->acc.bytes[c] += sb * (cu + cv);
+      P->acc.flops[c] += (c == SVDS_KC_CGS_UPDPROJ ? 4.0 : 2.0) * (cu + cv);
+    }
+  }
   if (!(P->opts.flags & SVDS_FLAG_NO_RESIDUALS)) {
     HIP_TRY(hipMemcpy(hav.data(), P->sc.resid_av, sizeof(double) * k, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(hatu.data(), P->sc.resid_atu, sizeof(double) * k, hipMemcpyDeviceToHost));
@@ -1969,6 +2090,9 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
     info->reorth_tests = static_cast<int32_t>(P->reorth_calls);
     info->reorth_second_passes = bd2[1];
     info->tuning = P->tuning;
+    info->partial_steps = om[0] + om[4];
+    info->partial_columns = om[1] + om[5];
+    info->partial_possible = om[2] + om[6];
   }
   return conv ? SVDS_OK : SVDS_NOT_CONVERGED;
   SVDS_ABI_CATCH
