@@ -36,8 +36,29 @@ Readings of the paper used here (where it is silent or ambiguous):
   bidiagonalization also approximates the smallest singular values): the
   same cycle with the k smallest Ritz triplets of T kept instead of the k
   largest (eqs. (5)-(7) hold for any k Ritz triplets), returned in ascending
-  order.  The sigma floor of eq. (4) still uses the largest Ritz value.  This
-  is plain Ritz augmentation, not the harmonic variant.
+  order.  The sigma floor of eq. (4) still uses the largest Ritz value.
+  ``harmonic=False`` restarts with the k smallest Ritz vectors (plain Ritz
+  augmentation).
+* Harmonic-Ritz augmentation (``which="smallest", harmonic=True``; the
+  augmented restart of Baglama and Reichel that Sec. 1 cites, for the
+  smallest values).  The convergence test and the outputs stay those of the
+  Ritz triplets of T (eq. (4) holds for them at any cycle); only the restart
+  subspace changes.  With A V_t = U_t T and A^T U_t = V_t T^T + beta_t
+  v_{t+1} e_t^T, the harmonic Ritz values of A^T A on span(V_t) are the
+  squared singular values of B = [T, beta_t e_t] (t x (t+1)); for the k
+  smallest, with right singular vectors y_j of B, the harmonic Ritz vectors
+  are V_t g_j, g_j = y_j(1:t) + beta_t y_j(t+1) z, z = T^{-1} e_t, and all
+  their residuals (for A^T A) are parallel to f = v_{t+1} - beta_t V_t z.
+  The restart keeps span{V_t g_1..V_t g_k, f}: the columns of
+  C = [[G, -beta_t z], [0, 1]] are orthonormalized (QR, C = Q_C R_C), V
+  becomes V_{t+1} Q_C (its first k columns lie in span(V_t)), the QR of
+  T Q_C(1:t, 1:k) = Q_M R_M gives U_k = U_t Q_M with A V_k = U_k R_M, so the
+  new T starts as R_M (upper triangular, k x k).  The restart vector u_{k+1}
+  is A v_{k+1} re-orthogonalized (CGS2) against U_k, its two projections'
+  coefficients summed into T(1:k, k+1) (A V_{k+1} = U_{k+1} T(1:k+1, 1:k+1));
+  the Lanczos steps then go on from k+1 as usual.  When T is singular to
+  working precision (z not finite, or beta_t |z| > 1/sqrt(eps)), that cycle
+  restarts with the plain Ritz vectors instead.
 
 * Partial re-orthogonalisation (``partial=True``; the PROPACK-style
   alternative that Sec. 1 names): instead of re-orthogonalising every new
@@ -88,6 +109,7 @@ class SvdsInfo:
     partial_steps: int = 0         # partial mode: vectors re-orthogonalised ...
     partial_columns: int = 0       # ... against this many basis columns in all
     partial_possible: int = 0      # ... out of this many (the full mode's count)
+    harmonic_restarts: int = 0     # harmonic mode: restarts with harmonic Ritz vectors
 
 
 class _Op:
@@ -299,9 +321,37 @@ def sign_normalize(U, V):
     return U * sgn, V * sgn
 
 
+def harmonic_restart_basis(T: np.ndarray, p: int, k: int):
+    """The harmonic-Ritz restart of the smallest triplets (see the module
+    notes): from the (p+1) x (p+1) Lanczos T (leading p x p block, beta_p at
+    T[p-1, p]) the coefficient matrices Q_C ((p+1) x (k+1), V_{p+1} Q_C is
+    the new V_{k+1}), Q_M (p x k, U_p Q_M is the new U_k) and R_M (k x k, the
+    new T(1:k, 1:k)); None when T is singular to working precision."""
+    Tp = T[:p, :p]
+    beta = T[p - 1, p]
+    B = T[:p, :p + 1]
+    _, sb, Yt = sla.svd(B, full_matrices=False, lapack_driver="gesvd")
+    Y = Yt.T                                   # (p+1) x p, descending sb
+    idx = np.argsort(sb, kind="stable")[:k]    # the k smallest harmonic values
+    e = np.zeros(p)
+    e[p - 1] = 1.0
+    with np.errstate(all="ignore"):
+        z = sla.solve_triangular(Tp, e, lower=False)
+    if not np.all(np.isfinite(z)) or abs(beta) * np.linalg.norm(z) > 1.0 / np.sqrt(EPS):
+        return None
+    G = Y[:p, idx] + beta * np.outer(z, Y[p, idx])
+    C = np.zeros((p + 1, k + 1))
+    C[:p, :k] = G
+    C[:p, k] = -beta * z
+    C[p, k] = 1.0
+    QC, _ = np.linalg.qr(C)
+    QM, RM = np.linalg.qr(Tp @ QC[:p, :k])
+    return QC, QM, RM
+
+
 def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
          v0: np.ndarray | None = None, seed: int = 0, callback=None, which: str = "largest",
-         selective: bool = False, partial: bool = False):
+         selective: bool = False, partial: bool = False, harmonic: bool = False):
     """k largest (``which="largest"``, descending) or smallest
     (``which="smallest"``, ascending) singular triplets of A (scipy sparse
     matrix or dense array).
@@ -325,6 +375,8 @@ def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
     op = _Op(A, info)
     if selective and partial:
         raise ValueError("selective and partial re-orthogonalisation exclude each other")
+    if harmonic and (which != "smallest" or selective or partial):
+        raise ValueError("harmonic augmentation is for the smallest triplets with full re-orthogonalisation")
     st = _State(op, p, seed, info, selective, partial)
 
     # Alg. 1 step 1: v_1 = randn / norm.
@@ -357,6 +409,35 @@ def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
             break
         if info.cycles >= maxit:
             break
+        hb = harmonic_restart_basis(st.T, p, k) if harmonic else None
+        if hb is not None:
+            QC, QM, RM = hb
+            Un = st.U[:, :p] @ QM
+            Vn = st.V[:, :p + 1] @ QC
+            st.T[:] = 0.0
+            st.T[:k, :k] = RM
+            st.U[:, :k] = Un
+            st.V[:, :k + 1] = Vn
+            # u_{k+1}: A v_{k+1} against U_k, coefficients into T(1:k, k+1)
+            w = op.mv(st.V[:, k])
+            Uk = st.U[:, :k]
+            h1 = Uk.T @ w
+            w = w - Uk @ h1
+            h2 = Uk.T @ w
+            w = w - Uk @ h2
+            st.T[:k, k] = h1 + h2
+            nrm = float(np.linalg.norm(w))
+            if nrm <= BREAKDOWN_REL * info.sigma_est:
+                st.U[:, k], st.T[k, k] = st._finish(w, Uk)  # replacement vector, 0 in T
+            else:
+                info.sigma_est = max(info.sigma_est, nrm)
+                st.U[:, k], st.T[k, k] = w / nrm, nrm
+            info.restarts += 1
+            info.harmonic_restarts += 1
+            if callback:
+                callback("restart", st, dict(Uk=Un, rho=None))
+            st.lanczos(k)
+            continue
         # Alg. 2 step 8: Ritz vectors (Proposition 1, eq. (2)).
         Uk = st.U[:, :p] @ Uh[:, :k]
         Vk = st.V[:, :p] @ Vh[:, :k]

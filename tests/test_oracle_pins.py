@@ -560,3 +560,76 @@ def test_partial_reorth_mode_exclusive_with_selective():
     A = inputs.sparse_uniform(100, 80, 800, seed=75)
     with pytest.raises(ValueError):
         svds(as_operator(A), 3, 10, 1e-10, 10, selective=True, partial=True)
+
+
+# --- harmonic-Ritz augmentation (smallest triplets) ---------------------------
+
+def _harmonic_case():
+    sig = _small_cluster_spectrum(600)
+    A = inputs.prescribed_sparse(120, 5, sig, seed=21)
+    return as_operator(A), sig
+
+
+def test_harmonic_residuals_share_one_direction():
+    """The textbook property the augmentation rests on: the residuals
+    A^T A V_t s_j - theta_j V_t s_j of all harmonic Ritz pairs (theta_j the
+    squared singular values of [T, beta_t e_t], s_j = T^{-1} x_j) are
+    parallel to f = v_{t+1} - beta_t V_t T^{-1} e_t."""
+    op, sig = _harmonic_case()
+    D = op.toarray()
+    p = 20
+    U, Tp, V, beta, _ = lbp(op, p, inputs.start_vector(600, 81))
+    Vfull = np.zeros((600, p + 1))
+    Vfull[:, :p] = V
+    # v_{t+1} from the relation A^T u_t = alpha_t v_t + beta_t v_{t+1}
+    Vfull[:, p] = (D.T @ U[:, p - 1] - Tp[p - 1, p - 1] * V[:, p - 1]) / beta
+    B = np.hstack([Tp, np.zeros((p, 1))])
+    B[p - 1, p] = beta
+    X, sb, _ = np.linalg.svd(B, full_matrices=False)
+    z = np.linalg.solve(Tp, np.eye(p)[:, p - 1])
+    f = Vfull[:, p] - beta * V @ z
+    f /= np.linalg.norm(f)
+    for j in range(p):
+        s_j = np.linalg.solve(Tp, X[:, j])
+        x = V @ s_j
+        r = D.T @ (D @ x) - sb[j] ** 2 * x
+        rn = np.linalg.norm(r)
+        if rn > 1e-10 * np.linalg.norm(x) * sb[0] ** 2:
+            assert abs(abs(r @ f) / rn - 1.0) <= 1e-8, j
+
+
+def test_harmonic_restart_keeps_the_lanczos_relations():
+    """After harmonic restarts, A V_t = U_t T and A^T U_t = V_t T^T +
+    beta_t v_{t+1} e_t^T still hold to rounding, the bases stay orthonormal,
+    and T starts with the upper-triangular R of the QR of T Q_C."""
+    op, sig = _harmonic_case()
+    D = op.toarray()
+    k, p = 4, 12
+    checks = []
+
+    def cb(stage, st, extra):
+        if stage == "svd" and st.info.harmonic_restarts > 0:
+            U, V, T = st.U, st.V, st.T
+            e1 = np.abs(D @ V[:, :p] - U @ T[:p, :p]).max()
+            R = D.T @ U - V[:, :p] @ T[:p, :p].T
+            R[:, p - 1] -= T[p - 1, p] * V[:, p]
+            checks.append((e1, np.abs(R).max(), np.abs(U.T @ U - np.eye(p)).max(),
+                           np.abs(V.T @ V - np.eye(p + 1)).max(), np.abs(np.tril(T[:k, :k], -1)).max()))
+    U, S, V, info = svds(op, k, p, 1e-10, 5000, v0=inputs.start_vector(600, 23), which="smallest", harmonic=True,
+                         callback=cb)
+    assert info.converged and info.harmonic_restarts > 0 and checks
+    for e1, e2, ou, ov, low in checks:
+        assert e1 <= 1e-12 * 2.0 and e2 <= 1e-12 * 2.0
+        assert ou <= 1e-12 and ov <= 1e-12
+        assert low == 0.0
+    exact = np.sort(sig)[:k]
+    np.testing.assert_allclose(S, exact, rtol=1e-10)
+    r1, r2 = explicit_residuals(op, U, S, V)
+    assert (r2 / S).max() <= 2e-10
+
+
+def test_harmonic_needs_smallest_and_full_reorth():
+    A = as_operator(inputs.sparse_uniform(100, 80, 800, seed=82))
+    for kw in (dict(harmonic=True), dict(harmonic=True, which="smallest", partial=True)):
+        with pytest.raises(ValueError):
+            svds(A, 3, 10, 1e-10, 10, **kw)
