@@ -182,13 +182,17 @@ def mixed_vs_fp64(S, inputs, np, torch, cpu: bool = False):
     v0 = torch.from_numpy(inputs.start_vector(10000, inputs.CONFIG_SEEDS[3] + 1)).cuda()
     gold = load_golden(GOLDEN_W3)
     res = {}
-    for name, prec in (("fp64", 0), ("mixed", 1)):
-        ms, r = timed(lambda: S.svds_dense_solve(Ad, S.make_opts(100, 250, 1e-8, 2000, precision=prec, v0=v0)))
+    E = S.SVDS_FLAG_EARLY_STOP
+    for name, prec, fl in (("fp64", 0, 0), ("mixed", 1, 0), ("fp64_early", 0, E), ("mixed_early", 1, E)):
+        ms, r = timed(lambda: S.svds_dense_solve(Ad, S.make_opts(100, 250, 1e-8, 2000, precision=prec, v0=v0,
+                                                                 flags=fl)))
         s = r.S.cpu().numpy()
         res[name] = {"ms": round(ms, 2), "cycles_fp32": r.info["cycles_fp32"], "cycles_fp64": r.info["cycles_fp64"],
+                     "lanczos_dim_last": r.info["lanczos_dim_last"],
                      "sigma_rel_err_vs_oracle": float(np.max(np.abs(s - gold[:100]) / gold[:100]))
                      if gold is not None else None, "status": r.status}
-    out["dense_20000x10000_bf16_k100_p250"] = dict(res, x=round(res["fp64"]["ms"] / res["mixed"]["ms"], 3))
+    out["dense_20000x10000_bf16_k100_p250"] = dict(res, x=round(res["fp64"]["ms"] / res["mixed"]["ms"], 3),
+                                                   x_early=round(res["fp64_early"]["ms"] / res["mixed_early"]["ms"], 3))
     if cpu:
         # the CPU oracle on the stored matrix widened to FP64 (the matrix of
         # record), same start vector, FP64, tol=1e-8: one complete solve
@@ -203,13 +207,16 @@ def mixed_vs_fp64(S, inputs, np, torch, cpu: bool = False):
     v0 = torch.from_numpy(inputs.start_vector(A.n, inputs.CONFIG_SEEDS[4] + 1)).cuda()
     gold = load_golden(GOLDEN_W4)
     res = {}
-    for name, prec in (("fp64", 0), ("mixed", 1)):
-        ms, r = timed(lambda: S.svds_csr_solve(Ad4, S.make_opts(50, 150, 1e-8, 2000, precision=prec, v0=v0)))
+    for name, prec, fl in (("fp64", 0, 0), ("mixed", 1, 0), ("fp64_early", 0, E), ("mixed_early", 1, E)):
+        ms, r = timed(lambda: S.svds_csr_solve(Ad4, S.make_opts(50, 150, 1e-8, 2000, precision=prec, v0=v0,
+                                                               flags=fl)))
         s = r.S.cpu().numpy()
         res[name] = {"ms": round(ms, 2), "cycles_fp32": r.info["cycles_fp32"], "cycles_fp64": r.info["cycles_fp64"],
+                     "lanczos_dim_last": r.info["lanczos_dim_last"],
                      "sigma_rel_err_vs_oracle": float(np.max(np.abs(s - gold[:50]) / gold[:50]))
                      if gold is not None else None, "status": r.status}
-    out["sparse_2000x1000_fp32_k50_p150"] = dict(res, x=round(res["fp64"]["ms"] / res["mixed"]["ms"], 3))
+    out["sparse_2000x1000_fp32_k50_p150"] = dict(res, x=round(res["fp64"]["ms"] / res["mixed"]["ms"], 3),
+                                                 x_early=round(res["fp64_early"]["ms"] / res["mixed_early"]["ms"], 3))
     if cpu:
         rate, cyc, s_or, n = oracle_rate(A, 50, 150, 1e-8, v0=v0.cpu().numpy())
         out["sparse_2000x1000_fp32_k50_p150"]["cpu_oracle"] = {
@@ -327,11 +334,29 @@ def paper_suite(S, inputs, np, torch, dense: bool):
             ts.append(time.perf_counter() - t0)
         sv = r.S.cpu().numpy()
         t = min(ts)
+        # the same case with the eq. (4) test checked inside the cycle
+        opts_e = S.make_opts(c["k"], c["p"], c["tol"], c["maxit"], v0=v0, flags=S.SVDS_FLAG_EARLY_STOP)
+        if name.startswith("sparse"):
+            run_e = lambda: S.svds_csr_solve(Ad, opts_e)
+        else:
+            run_e = lambda: S.svds_dense_solve(Ad, opts_e)
+        re_ = run_e()
+        torch.cuda.synchronize()
+        tes = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            re_ = run_e()
+            torch.cuda.synchronize()
+            tes.append(time.perf_counter() - t0)
+        se = re_.S.cpu().numpy()
         out[name] = {"n": N, "ms": round(t * 1e3, 2), "solves_per_s": round(1 / t, 2), "cycles": r.info["cycles"],
                      "status": r.status, "nconv": r.info["nconv"],
                      "sigma_rel_err_vs_exact": float(np.max(np.abs(sv - sig[:c["k"]]) / sig[:c["k"]])),
                      "paper_mkl16_s": PAPER_TABLE2_MKL16_S[name],
-                     "x_vs_paper_mkl16": round(PAPER_TABLE2_MKL16_S[name] / t, 1)}
+                     "x_vs_paper_mkl16": round(PAPER_TABLE2_MKL16_S[name] / t, 1),
+                     "early_stop": {"ms": round(min(tes) * 1e3, 2), "lanczos_dim_last": re_.info["lanczos_dim_last"],
+                                    "cycles": re_.info["cycles"], "status": re_.status,
+                                    "sigma_rel_err_vs_exact": float(np.max(np.abs(se - sig[:c["k"]]) / sig[:c["k"]]))}}
         del A, Ad
     return out
 
@@ -530,6 +555,33 @@ def main():
                 "sigma_rel_err_vs_oracle": float(np.max(np.abs(sp_ - golden[:k]) / golden[:k]))
                 if golden is not None else None}
 
+    # the same workload with the eq. (4) test checked inside the cycle
+    # (SVDS_FLAG_EARLY_STOP), alone and with partial re-orthogonalization:
+    # best of 3 solves each
+    early = None
+    if not args.no_selective:
+        log("early stop ...")
+        early = {}
+        for ename, efl in (("early_stop", S.SVDS_FLAG_EARLY_STOP),
+                           ("early_stop_partial_reorth", S.SVDS_FLAG_EARLY_STOP | S.SVDS_FLAG_PARTIAL_REORTH)):
+            ts, re_ = [], None
+            for _ in range(3):
+                t1 = time.perf_counter()
+                re_ = solve(efl)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t1)
+            se = re_.S.cpu().numpy()
+            eye = torch.eye(k, dtype=torch.float64, device="cuda")
+            early[ename] = {
+                "ms": round(min(ts) * 1e3, 2), "solves_per_s": round(1 / min(ts), 3),
+                "x_vs_cgs2": round((elapsed / args.steps) / min(ts), 3),
+                "lanczos_dim_last": re_.info["lanczos_dim_last"], "early_checks": re_.info["early_checks"],
+                "cycles": re_.info["cycles"], "status": re_.status, "max_res_true": re_.info["max_res_true"],
+                "orthogonality": max(float((re_.U.T @ re_.U - eye).abs().max()),
+                                     float((re_.V.T @ re_.V - eye).abs().max())),
+                "sigma_rel_err_vs_oracle": float(np.max(np.abs(se - golden[:k]) / golden[:k]))
+                if golden is not None else None}
+
     mixed = None
     if not args.no_mixed:
         log("mixed vs FP64 ...")
@@ -565,7 +617,7 @@ def main():
            "data": "synthetic", "config": dict(WORKLOAD, parallelism="single GPU"),
            "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "mixed_vs_fp64": mixed,
            "batched_vs_looped": batched, "paper_suite": suite, "selective_reorth": sel,
-           "partial_reorth": part,
+           "partial_reorth": part, "early_stop": early,
            "config_2000x1000": c1, "host_cpu": host_cpu(),
            "step_ms": {"execute": round(ms_exec, 2), "create_and_destroy": round(ms_step - ms_exec, 2)}}
     print(json.dumps(out), flush=True)

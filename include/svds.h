@@ -87,8 +87,25 @@ enum {
   SVDS_FLAG_NO_PANELS = 128,  /* A^T y over the plain CSR of A^T, no panels     */
   SVDS_FLAG_SMALLEST = 256,   /* the k smallest triplets instead (see below)    */
   SVDS_FLAG_SELECTIVE_REORTH = 512, /* second CGS pass only when needed (below) */
-  SVDS_FLAG_PARTIAL_REORTH = 1024   /* omega-recurrence partial re-orth. (below) */
+  SVDS_FLAG_PARTIAL_REORTH = 1024,  /* omega-recurrence partial re-orth. (below) */
+  SVDS_FLAG_EARLY_STOP = 2048       /* eq. (4) test inside a cycle (below)        */
 };
+
+/* SVDS_FLAG_EARLY_STOP: Proposition 1 holds for the leading block T(1:j,1:j)
+ * of a cycle at every Lanczos dimension j, so the test of eq. (4) can pass
+ * before the cycle reaches p.  While the Lanczos steps go on, the library
+ * copies T(1:j,1:j) and beta_j and runs the small SVD and the test on a
+ * second stream of its own from a host thread of its own (checks start at
+ * j = k + 1 + max(2, (p - k)/8); after a failed check the next one is placed
+ * by the decrease of the largest estimate between the last two checks).  A
+ * passing check at j ends the cycle: the outputs are the Ritz triplets of
+ * T(1:j,1:j) with the first j basis vectors, so every estimate is below tol
+ * exactly as at a full cycle's end.  The host enqueues at most 4 Lanczos
+ * steps ahead of the device, so the steps run after j are few.
+ * info->early_checks counts the checks, info->lanczos_dim_last is the Lanczos
+ * dimension of the small SVD the outputs come from (p without an early stop).
+ * Single and mixed solves; ignored with SVDS_FLAG_GRAPH (a captured cycle is
+ * a fixed sequence) and by the batched solver. */
 
 /* SVDS_FLAG_PARTIAL_REORTH: partial re-orthogonalization in the manner of
  * PROPACK (the alternative to full re-orthogonalization that Sec. 1 names).
@@ -254,6 +271,8 @@ typedef struct {
   int64_t partial_steps;           /* SVDS_FLAG_PARTIAL_REORTH: vectors re-orthogonalized */
   int64_t partial_columns;         /* ... basis columns they were taken against */
   int64_t partial_possible;        /* ... columns full re-orthogonalization takes */
+  int32_t early_checks;            /* SVDS_FLAG_EARLY_STOP: checks made       */
+  int32_t lanczos_dim_last;        /* Lanczos dimension of the last small SVD */
 } svds_info;
 
 typedef struct svds_plan svds_plan;

@@ -5,6 +5,7 @@
 // the kernels of kernels_*.hpp; the host only enqueues kernels and reads one
 // convergence flag per cycle.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -286,6 +287,31 @@ constexpr double OMEGA_ETA = 1.8189894035458565e-12;
 
 constexpr int NPART = NORM_MAX_BLOCKS;  // norm partials
 
+// SVDS_FLAG_EARLY_STOP: the eq. (4) test on the leading block T(1:j,1:j) of a
+// cycle still in progress (Proposition 1 holds at every Lanczos dimension j).
+// A check copies the block on a side stream and runs the small SVD there from
+// a worker thread, while the main stream goes on with the Lanczos steps; the
+// host stays at most EARLY_LAG steps ahead of the device, so a passing check
+// stops the cycle a few steps after j.  The cycle's outputs are then formed
+// from that check's SVD of T(1:j,1:j) and the first j basis vectors.
+constexpr int EARLY_LAG = 4;
+struct EarlyCheck {
+  double *T = nullptr, *Uk = nullptr, *Vext = nullptr, *sig = nullptr, *res = nullptr, *rho = nullptr,
+         *sigma_est = nullptr, *jac = nullptr;
+  int *flags = nullptr;
+  int *h_flags = nullptr;          // pinned: 4 flags, then the Jacobi sweep counters
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_check = nullptr;
+  hipEvent_t ev_step[EARLY_LAG] = {};
+  std::thread worker;
+  std::atomic<int> state{0};       // 0 idle, 1 running, 2 finished
+  int j_run = 0, rc = 0, passed = 0, sweeps = 0;
+  double max_res = 0;
+  int checks = 0, stop_j = 0;      // checks made in this execute; j of a passing check
+  int next_j = 0, j_prev = 0;      // scheduling within the current cycle
+  double r_prev = 0;
+};
+
 }  // namespace svds
 
 using namespace svds;
@@ -325,6 +351,13 @@ struct svds_plan {
   bool selective = false;  // SVDS_FLAG_SELECTIVE_REORTH: second CGS pass only when needed
   bool partial = false;    // SVDS_FLAG_PARTIAL_REORTH: omega-recurrence partial re-orthogonalization
   int64_t reorth_calls = 0;  // re-orthogonalizations with the selective test
+  bool early = false;      // SVDS_FLAG_EARLY_STOP
+  EarlyCheck ec;
+  // the small SVD the outputs (and a mixed solve's warm start) use: its
+  // Lanczos dimension and its Uk (p_eff x k, ld p_eff) and Vext
+  // ((p_eff+1) x (k+1), ld p_eff+1)
+  int p_eff = 0;
+  double *out_Uk = nullptr, *out_Vext = nullptr;
 };
 
 namespace svds {
@@ -664,17 +697,127 @@ static int rotate(svds_plan *P, int64_t L, int pc, int kc, const TB *B, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// Early stop (SVDS_FLAG_EARLY_STOP): checks of the eq. (4) test at an
+// intermediate Lanczos dimension j.
+// ---------------------------------------------------------------------------
+// Tc ((j+1) x (j+1), row-major) = the leading j x j block of T with
+// beta_j = T(j-1, j) in its last column and a zero last row: the layout the
+// small SVD takes for dimension j.  One block; also copies sigma_est.
+static __global__ void early_tblock_kernel(const double *__restrict__ T, int ld, int j, double *__restrict__ Tc,
+                                           const double *__restrict__ sig_in, double *__restrict__ sig_out) {
+  const int n = (j + 1) * (j + 1);
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const int r = idx / (j + 1), c = idx - r * (j + 1);
+    Tc[idx] = r < j ? T[r * ld + c] : 0.0;
+  }
+  if (threadIdx.x == 0) *sig_out = *sig_in;
+}
+
+// Worker thread of one check: the small SVD of the copied block on the side
+// stream, then the flags and the largest estimate for the host.
+static void early_worker(svds_plan *P, int j, double tol) {
+  EarlyCheck &e = P->ec;
+  int rc = SVDS_OK;
+  double mx = 0;
+  if (hipSetDevice(P->device) != hipSuccess) {
+    rc = SVDS_EDEVICE;
+  } else {
+    rc = svds_small_svd_run(e.stream, e.T, j, P->k, tol, e.jac, e.Uk, e.Vext, e.sig, e.res, e.rho, e.flags,
+                            e.sigma_est, e.h_flags + 4, P->smallest ? 1 : 0);
+    std::vector<double> r(P->k);
+    if (!rc && (hipMemcpyAsync(e.h_flags, e.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, e.stream) != hipSuccess ||
+                hipMemcpyAsync(r.data(), e.res, sizeof(double) * P->k, hipMemcpyDeviceToHost, e.stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(e.stream) != hipSuccess))
+      rc = SVDS_EDEVICE;
+    for (double v : r) mx = std::max(mx, v);
+  }
+  e.rc = rc;
+  e.passed = (!rc && e.h_flags[0]) ? 1 : 0;
+  e.sweeps = rc ? 0 : e.h_flags[2];
+  e.max_res = mx;
+  e.state.store(2, std::memory_order_release);
+}
+
+// Collects a finished check: a passing one ends the cycle (stop_j); a failed
+// one schedules the next check from the decrease of the largest estimate
+// between the last two checks (their steps per decade, extrapolated to tol).
+static int early_collect(svds_plan *P, double tol) {
+  EarlyCheck &e = P->ec;
+  if (e.state.load(std::memory_order_acquire) != 2) return SVDS_OK;
+  e.worker.join();
+  e.state.store(0);
+  ++e.checks;
+  P->jac_sweeps += e.sweeps;
+  if (e.rc) return e.rc;
+  if (e.passed) {
+    e.stop_j = e.j_run;
+    return SVDS_OK;
+  }
+  int step = 8;
+  if (e.j_prev > 0 && e.r_prev > e.max_res && e.max_res > 0) {
+    const double per_decade = (e.j_run - e.j_prev) / std::log10(e.r_prev / e.max_res);
+    const double need = per_decade * std::log10(e.max_res / tol);
+    step = static_cast<int>(std::min(16.0, std::max(2.0, std::floor(need))));
+  }
+  e.j_prev = e.j_run;
+  e.r_prev = e.max_res;
+  e.next_j = e.j_run + step;
+  return SVDS_OK;
+}
+
+// Starts a check of dimension j = (V steps done) once the device has finished
+// them (event on the main stream).
+static int early_start(svds_plan *P, int j) {
+  EarlyCheck &e = P->ec;
+  HIP_TRY(hipEventRecord(e.ev_check, P->stream));
+  HIP_TRY(hipStreamWaitEvent(e.stream, e.ev_check, 0));
+  hipLaunchKernelGGL(early_tblock_kernel, dim3(1), dim3(256), 0, e.stream, P->sc.T, P->p + 1, j, e.T,
+                     P->sc.sigma_est, e.sigma_est);
+  HIP_TRY(hipGetLastError());
+  e.j_run = j;
+  e.state.store(1);
+  e.worker = std::thread(early_worker, P, j, P->tol);
+  return SVDS_OK;
+}
+
+// Waits for a check still running (its result is dropped: the cycle ended).
+static int early_drain(svds_plan *P) {
+  EarlyCheck &e = P->ec;
+  if (e.worker.joinable()) e.worker.join();
+  if (e.state.load() == 2) {
+    ++e.checks;
+    P->jac_sweeps += e.sweeps;
+  }
+  e.state.store(0);
+  return e.rc;
+}
+
+// ---------------------------------------------------------------------------
 // Alg. 1 loop from 0-based column i0 until v_p and beta_{p-1} exist.
 // On entry: V[:, i0] is in the basis; the unnormalized u_{i0} is in bu with
 // reciprocal norm xs_u and T(i0, i0) set.
 // ---------------------------------------------------------------------------
-template <typename TB> static int lanczos(svds_plan *P, Lanczos<TB> &Lz, int i0) {
+template <typename TB> static int lanczos(svds_plan *P, Lanczos<TB> &Lz, int i0, bool early = false) {
   const int p = P->p;
   const int64_t m = Lz.m, n = Lz.n;
   const int ld = p + 1;
   const Small &s = P->sc;
   TB *U = Lz.U[Lz.cur], *V = Lz.V[Lz.cur];
+  EarlyCheck &e = P->ec;
+  if (early) {
+    e.stop_j = 0;
+    e.j_prev = 0;
+    e.next_j = P->k + 1 + std::max(2, (p - P->k) / 8);
+  }
   for (int i = i0; i < p; ++i) {
+    if (early) {
+      int rc = early_collect(P, P->tol);
+      if (rc) return rc;
+      if (e.stop_j) return SVDS_OK;  // converged at e.stop_j: the steps after it are not needed
+      // stay at most EARLY_LAG steps ahead of the device
+      if (i - i0 >= EARLY_LAG) HIP_TRY(hipEventSynchronize(e.ev_step[i % EARLY_LAG]));
+    }
     // Alg. 1 steps 5-6: v_{i+1} = A^T u_i - alpha_i v_i, CGS2 against V[:, 0..i], beta_i.
     // The product also writes the normalized u_i into U[:, i].
     int rc = matvec<TB>(P, true, Lz.bu, s.xs_u, s.T + i * ld + i, V + i * Lz.ldv, Lz.wv,
@@ -684,6 +827,11 @@ template <typename TB> static int lanczos(svds_plan *P, Lanczos<TB> &Lz, int i0)
     rc = cgs2_finish<TB>(P, Lz, V, Lz.ldv, n, i + 1, Lz.wv, Lz.w1v, Lz.bv, MODE_LANCZOS,
                          s.T + i * ld + i + 1, s.xs_v, P->partial ? &omv : nullptr);
     if (rc) return rc;
+    if (early) {
+      HIP_TRY(hipEventRecord(e.ev_step[i % EARLY_LAG], P->stream));
+      // T(1:j, 1:j) and beta_j exist for j = i + 1
+      if (i + 1 < p && i + 1 >= e.next_j && e.state.load() == 0 && (rc = early_start(P, i + 1))) return rc;
+    }
     if (i == p - 1) {
       // v_{p+1}: normalized into V[:, p] (no product consumes it in this cycle)
       hipLaunchKernelGGL((scale_copy_kernel<TB>), dim3(ceil_div(n, 256)), dim3(256), 0, P->stream,
@@ -700,7 +848,8 @@ template <typename TB> static int lanczos(svds_plan *P, Lanczos<TB> &Lz, int i0)
                          s.T + (i + 1) * ld + i + 1, s.xs_u, P->partial ? &omu : nullptr);
     if (rc) return rc;
   }
-  return SVDS_OK;
+  // the cycle ran to p: a check still running is no longer needed
+  return early ? early_drain(P) : SVDS_OK;
 }
 
 // Alg. 1 steps 1-3: v_1 = v0 / |v0| (v0 given as FP64 or drawn from Philox),
@@ -746,7 +895,27 @@ static int small_svd(svds_plan *P) {
   HIP_TRY(hipMemcpyAsync(P->h_flags, s.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   P->jac_sweeps += P->h_flags[2];
+  P->p_eff = p;
+  P->out_Uk = s.Uk;
+  P->out_Vext = s.Vext;
   return P->acc.harvest();
+}
+
+// A cycle that an early check ended at dimension j: that check's small SVD
+// becomes the cycle's (flags, estimates, singular values; Uk and Vext for the
+// outputs, with leading dimensions j and j + 1).
+static int early_adopt(svds_plan *P) {
+  EarlyCheck &e = P->ec;
+  const Small &s = P->sc;
+  const int k = P->k;
+  HIP_TRY(hipMemcpyAsync(s.sig, e.sig, sizeof(double) * k, hipMemcpyDeviceToDevice, P->stream));
+  HIP_TRY(hipMemcpyAsync(s.res, e.res, sizeof(double) * k, hipMemcpyDeviceToDevice, P->stream));
+  HIP_TRY(hipMemcpyAsync(s.flags, e.flags, 4 * sizeof(int), hipMemcpyDeviceToDevice, P->stream));
+  std::memcpy(P->h_flags, e.h_flags, 4 * sizeof(int));
+  P->p_eff = e.stop_j;
+  P->out_Uk = e.Uk;
+  P->out_Vext = e.Vext;
+  return SVDS_OK;
 }
 
 // Alg. 2 steps 8-12: Ritz vectors into the other ping-pong buffer, v_{k+1} =
@@ -878,9 +1047,15 @@ static int run_cycles(svds_plan *P, Lanczos<TB> &Lz, double tol_c, int maxit, bo
   int nodec = 0;
   const double tol_save = P->tol;
   P->tol = tol_c;
-  int rc = lanczos<TB>(P, Lz, 0);
+  const bool early = P->early;
+  int rc = lanczos<TB>(P, Lz, 0, early);
   while (rc == SVDS_OK) {
     ++cycles;
+    if (early && P->ec.stop_j) {  // converged inside the cycle
+      rc = early_adopt(P);
+      conv = true;
+      break;
+    }
     rc = small_svd(P);
     if (rc) break;
     conv = P->h_flags[0] != 0;
@@ -901,8 +1076,12 @@ static int run_cycles(svds_plan *P, Lanczos<TB> &Lz, double tol_c, int maxit, bo
     } else {
       rc = restart<TB>(P, Lz);
       if (rc) break;
-      rc = lanczos<TB>(P, Lz, P->k);
+      rc = lanczos<TB>(P, Lz, P->k, early);
     }
+  }
+  if (early) {
+    const int rd = early_drain(P);
+    if (!rc) rc = rd;
   }
   P->tol = tol_save;
   return rc;
@@ -928,6 +1107,8 @@ static int fill_defaults(const svds_opts *o, int64_t m, int64_t n, svds_plan *P)
   P->smallest = (o->flags & SVDS_FLAG_SMALLEST) != 0;
   P->selective = (o->flags & SVDS_FLAG_SELECTIVE_REORTH) != 0;
   P->partial = (o->flags & SVDS_FLAG_PARTIAL_REORTH) != 0;
+  // captured cycles replay a fixed sequence of launches: no early stop there
+  P->early = (o->flags & SVDS_FLAG_EARLY_STOP) != 0 && !(o->flags & SVDS_FLAG_GRAPH);
   if (o->precision != SVDS_PREC_FP64 && o->precision != SVDS_PREC_MIXED) return SVDS_EINVAL;
   if (P->selective && P->partial) return SVDS_EINVAL;
   // the FP32 phase cannot resolve values below ~1e-7 sigma_1
@@ -975,6 +1156,18 @@ static int carve_all(svds_plan *P, Arena &a) {
   s.sgn = a.take<double>(k);
   s.sgn_val = a.take<double>(static_cast<size_t>(k) * SIGN_MAX_SLABS);
   s.sgn_idx = a.take<int64_t>(static_cast<size_t>(k) * SIGN_MAX_SLABS);
+  if (P->early) {
+    EarlyCheck &e = P->ec;
+    e.T = a.take<double>(static_cast<size_t>(p + 1) * (p + 1));
+    e.Uk = a.take<double>(static_cast<size_t>(p) * k);
+    e.Vext = a.take<double>(static_cast<size_t>(p + 1) * (k + 1));
+    e.sig = a.take<double>(k);
+    e.res = a.take<double>(k);
+    e.rho = a.take<double>(k);
+    e.sigma_est = a.take<double>(1);
+    e.jac = a.take<double>(jacobi_work_bytes(p) / 8 + 8);
+    e.flags = a.take<int>(4);
+  }
   if (P->partial) {
     s.om_mu = a.take<double>(p + 2);
     s.om_nu = a.take<double>(p + 2);
@@ -1049,6 +1242,17 @@ static int alloc_arena(svds_plan *P) {
   carve_all(P, P->arena);
   HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&P->h_flags), (16 + JAC_MAX_SWEEPS) * sizeof(int),
                         hipHostMallocDefault));
+  if (P->early) {
+    EarlyCheck &e = P->ec;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&e.h_flags), (4 + JAC_MAX_SWEEPS) * sizeof(int),
+                          hipHostMallocDefault));
+    HIP_TRY(hipStreamCreateWithFlags(&e.stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&e.ev_check, hipEventDisableTiming));
+    for (auto &ev : e.ev_step) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  }
+  P->p_eff = P->p;
+  P->out_Uk = P->sc.Uk;
+  P->out_Vext = P->sc.Vext;
   const double one = 1.0;
   HIP_TRY(hipMemcpyAsync(P->sc.one, &one, sizeof one, hipMemcpyHostToDevice, P->stream));
   return SVDS_OK;
@@ -1922,6 +2126,12 @@ extern "C" void svds_plan_destroy(svds_plan *P) {
   if (P->op.pbuf_items) (void)hipFree(P->op.pbuf_items);
   if (P->op.v32buf) (void)hipFree(P->op.v32buf);
   if (P->h_flags) (void)hipHostFree(P->h_flags);
+  if (P->ec.worker.joinable()) P->ec.worker.join();
+  if (P->ec.h_flags) (void)hipHostFree(P->ec.h_flags);
+  if (P->ec.ev_check) (void)hipEventDestroy(P->ec.ev_check);
+  for (auto &ev : P->ec.ev_step)
+    if (ev) (void)hipEventDestroy(ev);
+  if (P->ec.stream) (void)hipStreamDestroy(P->ec.stream);
   P->graphs.destroy();
   P->acc.destroy();
   delete P;
@@ -1934,12 +2144,13 @@ namespace svds {
 
 template <typename TB>
 static int outputs(svds_plan *P, Lanczos<TB> &Lz, double *U, double *S, double *V) {
-  const int p = P->p, k = P->k;
+  const int p = P->p_eff, k = P->k;  // p_eff < p when an early check ended the cycle
   const int64_t m = P->op.m, n = P->op.n;
   const Small &s = P->sc;
+  double *Uk = P->out_Uk, *Vext = P->out_Vext;
   // Alg. 2 steps 15-16; V first, so that its sign normalization can be
   // folded into Uk before U is formed
-  int rc = rotate<TB, double>(P, n, p, k, Lz.V[Lz.cur], Lz.ldv, s.Vext, p + 1, V, n);
+  int rc = rotate<TB, double>(P, n, p, k, Lz.V[Lz.cur], Lz.ldv, Vext, p + 1, V, n);
   if (rc) return rc;
   if (!(P->opts.flags & SVDS_FLAG_NO_SIGNFIX)) {
     const int64_t slab = sign_slab_rows(n);
@@ -1949,14 +2160,14 @@ static int outputs(svds_plan *P, Lanczos<TB> &Lz, double *U, double *S, double *
                        s.sgn_val, s.sgn_idx);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(sign_pick_kernel, dim3(k), dim3(WAVE), 0, P->stream, nslab, s.sgn_val, s.sgn_idx, V, n,
-                       n, s.sgn, s.Uk, p);
+                       n, s.sgn, Uk, p);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(flip_cols_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(256, ceil_div(n, 2048))), k),
                        dim3(256), 0, P->stream, n, V, n, s.sgn);
     LAUNCH_CHECK();
     ACC_AFTER(SVDS_KC_OTHER, 8.0 * n * k * 2, 0.0);
   }
-  rc = rotate<TB, double>(P, m, p, k, Lz.U[Lz.cur], Lz.ldu, s.Uk, p, U, m);
+  rc = rotate<TB, double>(P, m, p, k, Lz.U[Lz.cur], Lz.ldu, Uk, p, U, m);
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(S, s.sig, sizeof(double) * k, hipMemcpyDeviceToDevice, P->stream));
   return SVDS_OK;
@@ -1964,9 +2175,9 @@ static int outputs(svds_plan *P, Lanczos<TB> &Lz, double *U, double *S, double *
 
 // v1 of the FP64 phase from the FP32 Ritz vectors: sum_j Vk(:, j) / sqrt(k).
 static int warm_start_vector(svds_plan *P) {
-  const int p = P->p, k = P->k;
+  const int p = P->p_eff, k = P->k;
   const int64_t n = P->op.n;
-  int rc = rotate<float, double>(P, n, p, k, P->L32.V[P->L32.cur], P->L32.ldv, P->sc.Vext, p + 1,
+  int rc = rotate<float, double>(P, n, p, k, P->L32.V[P->L32.cur], P->L32.ldv, P->out_Vext, p + 1,
                                  P->tmp_nk, n);
   if (rc) return rc;
   // tmp_n = Vk * (1/sqrt(k) * ones): a rotation with a k x 1 panel
@@ -1990,6 +2201,7 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
   P->cycles32 = P->cycles64 = P->jac_sweeps = 0;
   const int64_t cap0 = P->graphs.captures, rep0 = P->graphs.replays;
   P->reorth_calls = 0;
+  P->ec.checks = 0;
   HIP_TRY(hipMemsetAsync(P->sc.sigma_est, 0, sizeof(double), P->stream));
   HIP_TRY(hipMemsetAsync(P->sc.bd, 0, 4 * sizeof(int), P->stream));
   HIP_TRY(hipMemsetAsync(P->sc.T, 0, sizeof(double) * (P->p + 1) * (P->p + 1), P->stream));
@@ -2090,6 +2302,8 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
     info->reorth_tests = static_cast<int32_t>(P->reorth_calls);
     info->reorth_second_passes = bd2[1];
     info->tuning = P->tuning;
+    info->early_checks = P->ec.checks;
+    info->lanczos_dim_last = P->p_eff;
     info->partial_steps = om[0] + om[4];
     info->partial_columns = om[1] + om[5];
     info->partial_possible = om[2] + om[6];

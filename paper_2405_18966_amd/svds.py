@@ -26,6 +26,7 @@ SVDS_FLAG_TIMING, SVDS_FLAG_NO_RESIDUALS, SVDS_FLAG_NO_SIGNFIX, SVDS_FLAG_GRAPH,
 SVDS_FLAG_ITEMS_1K, SVDS_FLAG_UNSORTED, SVDS_FLAG_NO_PANELS, SVDS_FLAG_SMALLEST = 32, 64, 128, 256
 SVDS_FLAG_SELECTIVE_REORTH = 512
 SVDS_FLAG_PARTIAL_REORTH = 1024
+SVDS_FLAG_EARLY_STOP = 2048
 KERNEL_CLASSES = ["spmv", "spmvT", "cgs_proj", "cgs_updproj", "cgs_updnorm", "cgs_reduce", "smallsvd",
                   "rotate", "other"]
 KC_COUNT = len(KERNEL_CLASSES)
@@ -72,7 +73,8 @@ class svds_info(C.Structure):
                 ("workspace_bytes", C.c_int64), ("graph_captures", C.c_int32),
                 ("graph_replays", C.c_int32), ("tuning", svds_tuning), ("reorth_tests", C.c_int32),
                 ("reorth_second_passes", C.c_int32), ("partial_steps", C.c_int64),
-                ("partial_columns", C.c_int64), ("partial_possible", C.c_int64)]
+                ("partial_columns", C.c_int64), ("partial_possible", C.c_int64),
+                ("early_checks", C.c_int32), ("lanczos_dim_last", C.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("kc_") and f != "tuning"}
