@@ -633,3 +633,34 @@ def test_harmonic_needs_smallest_and_full_reorth():
     for kw in (dict(harmonic=True), dict(harmonic=True, which="smallest", partial=True)):
         with pytest.raises(ValueError):
             svds(A, 3, 10, 1e-10, 10, **kw)
+
+
+# --- eq. (4) inside a cycle (the reading behind the early stop) -----------------
+
+def test_proposition1_holds_at_every_lanczos_dimension():
+    """Proposition 1 for the leading block: after j Lanczos steps (first
+    cycle or after a restart), the Ritz triplets of T(1:j,1:j) with the first
+    j basis vectors have |A^T u_i - s_i v_i| = |beta_j Uh(j, i)| and
+    A v_i = s_i u_i, so testing eq. (4) at any j is testing the triplets that
+    would be output at j."""
+    A = inputs.config_matrix(1)
+    op = as_operator(A)
+    D = op.toarray()
+    k, p = 10, 30
+    states = []
+
+    def cb(stage, st, extra):
+        if stage in ("lbp", "svd"):
+            states.append((st.U.copy(), st.V.copy(), st.T.copy(), stage))
+    svds(op, k, p, 1e-14, 3, v0=inputs.start_vector(A.n, inputs.CONFIG_SEEDS[1] + 1), callback=cb)
+    # the first LBP and the second cycle (arrow T after a restart)
+    for U, V, T, stage in (states[0], states[2]):
+        for j in range(k + 2, p + 1, 3):
+            Uh, s, Vht = np.linalg.svd(T[:j, :j])
+            beta = T[j - 1, j]
+            Ut = U[:, :j] @ Uh[:, :k]
+            Vt = V[:, :j] @ Vht.T[:, :k]
+            est = np.abs(beta * Uh[j - 1, :k])
+            true = np.linalg.norm(D.T @ Ut - Vt * s[:k], axis=0)
+            np.testing.assert_allclose(true, est, rtol=0, atol=1e-12 * s[0])
+            assert np.abs(D @ Vt - Ut * s[:k]).max() <= 1e-12 * s[0]
