@@ -471,12 +471,18 @@ __device__ __forceinline__ void omega_fix(const FinishArgs &fa, int j, double nr
   if (threadIdx.x == 0) fa.om_row[j] = 1.0;
 }
 
+// Breakdown replacement (one block): out = a Philox normal vector (stream
+// `stream` of `seed`), taken twice against Q[:, 0:j] by classical
+// Gram-Schmidt, then normalized.  The projections run eight columns at a
+// time (one read of the eight columns and of out per chunk, eight block sums
+// in column order), the updates add the columns eight at a time per row: each
+// pass reads Q once, whatever j is.
 template <typename T>
 __device__ void breakdown_repair(const T *__restrict__ Q, int64_t ldq, int64_t L, int j,
                                  T *__restrict__ out, uint32_t stream, uint64_t seed,
                                  double *sh_d, T *sh_h) {
-  const int tid = threadIdx.x;
-  for (int64_t b = tid; 2 * b < L; b += blockDim.x) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int64_t b = tid; 2 * b < L; b += nt) {
     double z0, z1;
     philox_normal_pair(seed, stream, static_cast<uint64_t>(b), z0, z1);
     out[2 * b] = static_cast<T>(z0);
@@ -484,39 +490,59 @@ __device__ void breakdown_repair(const T *__restrict__ Q, int64_t ldq, int64_t L
   }
   __threadfence_block();
   __syncthreads();
+  constexpr int CH = 8;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int c = 0; c < j; ++c) {
-      T s = 0;
-      for (int64_t r = tid; r < L; r += blockDim.x) s += Q[c * ldq + r] * out[r];
-      s = block_sum(s, reinterpret_cast<T *>(sh_d));
-      if (tid == 0) sh_h[c] = s;
+    for (int c0 = 0; c0 < j; c0 += CH) {
+      const int nc = min(CH, j - c0);
+      T acc[CH];
+#pragma unroll
+      for (int g = 0; g < CH; ++g) acc[g] = 0;
+      for (int64_t r = tid; r < L; r += nt) {
+        const T x = out[r];
+#pragma unroll
+        for (int g = 0; g < CH; ++g)
+          if (g < nc) acc[g] += Q[static_cast<int64_t>(c0 + g) * ldq + r] * x;
+      }
+#pragma unroll
+      for (int g = 0; g < CH; ++g) {
+        const T sg = block_sum(acc[g], reinterpret_cast<T *>(sh_d));
+        if (tid == 0 && g < nc) sh_h[c0 + g] = sg;
+      }
     }
     __syncthreads();
-    for (int64_t r = tid; r < L; r += blockDim.x) {
-      T u = 0;
-      for (int c = 0; c < j; ++c) u += Q[c * ldq + r] * sh_h[c];
-      out[r] -= u;
+    for (int64_t r = tid; r < L; r += nt) {
+      T u[CH];
+#pragma unroll
+      for (int g = 0; g < CH; ++g) u[g] = 0;
+      int c = 0;
+      for (; c + CH <= j; c += CH)
+#pragma unroll
+        for (int g = 0; g < CH; ++g) u[g] += Q[static_cast<int64_t>(c + g) * ldq + r] * sh_h[c + g];
+      for (; c < j; ++c) u[0] += Q[static_cast<int64_t>(c) * ldq + r] * sh_h[c];
+      out[r] -= ((u[0] + u[1]) + (u[2] + u[3])) + ((u[4] + u[5]) + (u[6] + u[7]));
     }
     __threadfence_block();
     __syncthreads();
   }
   double s = 0;
-  for (int64_t r = tid; r < L; r += blockDim.x) s += static_cast<double>(out[r]) * out[r];
+  for (int64_t r = tid; r < L; r += nt) s += static_cast<double>(out[r]) * out[r];
   s = block_sum(s, sh_d);
   const double inv = 1.0 / sqrt(s);
-  for (int64_t r = tid; r < L; r += blockDim.x) out[r] = static_cast<T>(out[r] * inv);
+  for (int64_t r = tid; r < L; r += nt) out[r] = static_cast<T>(out[r] * inv);
 }
 
+constexpr int FINISH_THREADS = 1024;  // a breakdown's repair streams the basis with one block
+
 template <typename T>
-__global__ __launch_bounds__(CGS_THREADS) void finish_norm_kernel(const double *__restrict__ npart,
-                                                                 int nparts, int mode, FinishArgs fa,
-                                                                 const T *__restrict__ Q, int64_t ldq,
-                                                                 int64_t L, int j, T *__restrict__ out) {
-  __shared__ double sh_d[CGS_THREADS / WAVE];
+__global__ __launch_bounds__(FINISH_THREADS) void finish_norm_kernel(const double *__restrict__ npart,
+                                                                    int nparts, int mode, FinishArgs fa,
+                                                                    const T *__restrict__ Q, int64_t ldq,
+                                                                    int64_t L, int j, T *__restrict__ out) {
+  __shared__ double sh_d[FINISH_THREADS / WAVE];
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ int bd;
   const int tid = threadIdx.x;
-  double tot = strided_sum(npart, tid, nparts, CGS_THREADS, 0.0);
+  double tot = strided_sum(npart, tid, nparts, static_cast<int>(blockDim.x), 0.0);
   tot = block_sum(tot, sh_d);
   const double nrm = sqrt(tot);
   if (mode == MODE_NORM) {

@@ -660,7 +660,7 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     fa.om_full = (om->full || j == 0) ? 1 : 0;
   }
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
-  hipLaunchKernelGGL((finish_norm_kernel<TB>), dim3(1), dim3(CGS_THREADS), 0, P->stream, s.npart, nn,
+  hipLaunchKernelGGL((finish_norm_kernel<TB>), dim3(1), dim3(FINISH_THREADS), 0, P->stream, s.npart, nn,
                      mode, fa, Q, ldq, L, j, out);
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_REDUCE, 8.0 * nn, 0.0);

@@ -265,3 +265,28 @@ def test_full_size_zipf_workload_against_stored_oracle(S):
     res_av = torch.linalg.norm(AV - r.U * r.S, dim=0) / r.S[0]
     assert float(res_av.max()) <= 1e-8
     assert abs(r.info["max_res_av"] - float(res_av.max())) <= 1e-12
+
+
+def test_breakdowns_at_scale(S):
+    """A 1,000,000 x 500,000 matrix of rank 30 (diagonal, distinct values):
+    the Krylov space is exhausted after 31 steps, so the rest of the first
+    cycle runs on breakdown replacement vectors (each re-orthogonalized
+    against the whole basis in the finish step).  Values against the exact
+    ones and the oracle's."""
+    import time
+    import torch
+    print("breakdowns at 1e6 rows", flush=True)
+    d = np.zeros(500000)
+    d[:30] = np.arange(30, 0, -1, dtype=np.float64)
+    A = inputs.diag_matrix(1_000_000, 500_000, d)
+    k, p = 5, 40
+    v0 = inputs.start_vector(500_000, 31)
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), k, p, 1e-10, 50, v0=v0)
+    t0 = time.perf_counter()
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, 1e-10, 50, v0=v0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert st == 0 and info["breakdowns"] > 0 and info_r.breakdowns > 0
+    np.testing.assert_allclose(Sg, [30, 29, 28, 27, 26], rtol=1e-12)
+    np.testing.assert_allclose(Sg, Sr, rtol=1e-12)
+    print(f"breakdowns gpu {info['breakdowns']} oracle {info_r.breakdowns}, {dt * 1e3:.1f} ms", flush=True)
