@@ -217,9 +217,8 @@ template <typename TB> static int b_start(Batch &Bt, Lanczos<TB> &Lz, const doub
 static int b_small_svd(Batch &Bt, double tol, bool &all_conv) {
   svds_plan *P = Bt.P;
   const int p = P->p, k = P->k;
-  const int pe = p + (p & 1);
   ACC_BEFORE(SVDS_KC_SMALLSVD);
-  hipLaunchKernelGGL(bsmall_svd_kernel, dim3(Bt.nb), dim3(std::min(JAC_THREADS, (pe / 2) * WAVE)),
+  hipLaunchKernelGGL(bsmall_svd_kernel, dim3(Bt.nb), dim3(small_svd_threads(p)),
                      small_svd_lds_bytes(p), P->stream, Bt.T, Bt.nb, p, k, tol, Bt.Uk, Bt.Vext, Bt.sig, Bt.res,
                      Bt.rho, Bt.flags, Bt.sigma_est, Bt.active);
   B_LAUNCH_CHECK();

@@ -170,7 +170,10 @@ __device__ __forceinline__ int jacobi_pairg(double *__restrict__ wi, double *__r
   a = group_sum<LPP>(a);
   b = group_sum<LPP>(b);
   c = group_sum<LPP>(c);
-  if (!has || !(fabs(c) > tolJ * sqrt(a * b))) return 0;
+  // |c| below 2^-1000 counts as orthogonal: the hardware reciprocal flushes
+  // a subnormal 2c to infinity (then the rotation would be NaN), and such a
+  // pair (a column that has converged to nothing) needs no rotation
+  if (!has || !(fabs(c) > tolJ * sqrt(a * b)) || !(fabs(c) >= 0x1.0p-1000)) return 0;
   // Rutishauser's parameters with hardware reciprocal / reciprocal square
   // root, each refined by two Newton steps (full double accuracy; the
   // rotation only needs cs^2 + sn^2 = 1 to working precision)
@@ -219,7 +222,7 @@ __device__ __forceinline__ int jacobi_pairg_reg(double (&xi)[RPL], double (&yi)[
   a = group_sum<LPP>(a);
   b = group_sum<LPP>(b);
   c = group_sum<LPP>(c);
-  if (!has || !(fabs(c) > tolJ * sqrt(a * b))) return 0;
+  if (!has || !(fabs(c) > tolJ * sqrt(a * b)) || !(fabs(c) >= 0x1.0p-1000)) return 0;  // as jacobi_pairg
   const double z = (b - a) * jac_rcp(2.0 * c);
   double tt;
   if (fabs(z) < 1e100) {
@@ -369,13 +372,24 @@ __device__ inline void small_svd_body(double *__restrict__ T, int64_t ts, int p,
     if (tid == 0) rot_count = 0;
     __syncthreads();
     for (int step = 0; step < pe - 1; ++step) {
+      // four pairs per wave, one per row of 16 lanes (pe <= 64: at most four
+      // rows of each column per lane)
       int nrot = 0;
-      for (int q = wv; q < npairs; q += nwaves) {
-        int i, j;
-        rr_pair(pe, step, q, i, j);
-        nrot += jacobi_pair<1>(W + i * pe, W + j * pe, Vh + i * pe, Vh + j * pe, pe, lane, tolJ);
+      const int lg = lane >> 4, sl = lane & 15;
+      for (int q0 = wv * 4; q0 < npairs; q0 += nwaves * 4) {
+        const int q = q0 + lg;
+        double *wi = nullptr, *wj = nullptr, *vi = nullptr, *vj = nullptr;
+        if (q < npairs) {
+          int i, j;
+          rr_pair(pe, step, q, i, j);
+          wi = W + i * pe;
+          wj = W + j * pe;
+          vi = Vh + i * pe;
+          vj = Vh + j * pe;
+        }
+        nrot += jacobi_pairg<4, 16>(wi, wj, vi, vj, pe, sl, tolJ);
       }
-      if (lane == 0 && nrot) atomicAdd(&rot_count, nrot);
+      if (sl == 0 && nrot) atomicAdd(&rot_count, nrot);
       __syncthreads();
     }
     sweeps = sweep + 1;
@@ -404,6 +418,12 @@ static __global__ __launch_bounds__(JAC_THREADS) void bsmall_svd_kernel(
   if (!active[b]) return;  // converged and frozen: outputs of its last small SVD stay
   small_svd_body(T + b, nb, p, k, tol, Uk + b * p * k, Vext + b * (p + 1) * (k + 1), sig + b * k, res + b * k,
                  rho + b * k, flags + 4 * b, sigma_est + b, 0);
+}
+
+// threads of the single-workgroup schedule: four pairs per wave
+__host__ __device__ inline int small_svd_threads(int p) {
+  const int pe = p + (p & 1);
+  return static_cast<int>(ceil_div(pe / 2, 4)) * WAVE;
 }
 
 __host__ __device__ inline size_t small_svd_lds_bytes(int p) {

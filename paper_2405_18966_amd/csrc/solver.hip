@@ -2681,8 +2681,7 @@ int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, doub
                        int *h_counts, int smallest) {
   if (p < 2 || k < 1 || k >= p || p > 1023) return SVDS_EINVAL;
   if (p <= JAC_SMALL_P) {
-    const int pe = p + (p & 1);
-    const int nthr = std::min(JAC_THREADS, (pe / 2) * WAVE);
+    const int nthr = small_svd_threads(p);
     hipLaunchKernelGGL(small_svd_kernel, dim3(1), dim3(nthr), small_svd_lds_bytes(p), st, T, p, k, tol, Uk,
                        Vext, sig, res, rho, flags, sigma_est, smallest);
     HIP_TRY(hipGetLastError());
