@@ -290,3 +290,22 @@ def test_breakdowns_at_scale(S):
     np.testing.assert_allclose(Sg, [30, 29, 28, 27, 26], rtol=1e-12)
     np.testing.assert_allclose(Sg, Sr, rtol=1e-12)
     print(f"breakdowns gpu {info['breakdowns']} oracle {info_r.breakdowns}, {dt * 1e3:.1f} ms", flush=True)
+
+
+@pytest.mark.parametrize("p", [40, 70])
+def test_rank_deficient_small_svd_stays_finite(S, p):
+    """Rank 30 with p = 40 (one-workgroup Jacobi) and p = 70 (block Jacobi):
+    T holds exact zeros from the breakdowns, so Jacobi meets pairs whose
+    columns have converged to (sub)normal nothing; such pairs must not be
+    rotated (a subnormal inner product made the reciprocal infinite and the
+    whole SVD NaN).  Values exact, as the oracle's."""
+    d = np.zeros(1000)
+    d[:30] = np.arange(30, 0, -1, dtype=np.float64)
+    A = inputs.diag_matrix(2000, 1000, d)
+    v0 = inputs.start_vector(1000, 32)
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), 5, p, 1e-10, 50, v0=v0)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, 5, p, 1e-10, 50, v0=v0)
+    assert st == 0 and info["breakdowns"] > 0
+    assert np.all(np.isfinite(Ug)) and np.all(np.isfinite(Vg))
+    np.testing.assert_allclose(Sg, [30, 29, 28, 27, 26], rtol=1e-12)
+    np.testing.assert_allclose(Sg, Sr, rtol=1e-12)
