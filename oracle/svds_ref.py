@@ -49,16 +49,26 @@ Readings of the paper used here (where it is silent or ambiguous):
   smallest, with right singular vectors y_j of B, the harmonic Ritz vectors
   are V_t g_j, g_j = y_j(1:t) + beta_t y_j(t+1) z, z = T^{-1} e_t, and all
   their residuals (for A^T A) are parallel to f = v_{t+1} - beta_t V_t z.
-  The restart keeps span{V_t g_1..V_t g_k, f}: the columns of
-  C = [[G, -beta_t z], [0, 1]] are orthonormalized (QR, C = Q_C R_C), V
-  becomes V_{t+1} Q_C (its first k columns lie in span(V_t)), the QR of
-  T Q_C(1:t, 1:k) = Q_M R_M gives U_k = U_t Q_M with A V_k = U_k R_M, so the
-  new T starts as R_M (upper triangular, k x k).  The restart vector u_{k+1}
+  The restart keeps span{V_t g_1..V_t g_k, f} = V_{t+1} span{y_1..y_k, y_0}
+  with y_0 the null vector of B ([-beta_t z; 1] normalized): the same
+  subspace, written with B's orthonormal right singular vectors and no
+  solve with T.  M = [y_1..y_k, y_0] is turned by the Householder
+  reflection H that maps its last row r onto e_{k+1} (H r^T = -sign(r_{k+1})
+  |r| e_{k+1}), so Q_C = M H has a zero last row in its first k columns
+  (those lie in span(V_t)); its last column is taken with a positive last
+  entry.  V becomes V_{t+1} Q_C and U_k = U_t Q_M with Q_M = [x_1..x_k] the
+  matching left singular vectors of B (B y_j = s_j x_j): since
+  B Q_C(:, 1:k) = [s_1 x_1 .. s_k x_k, B y_0] H(:, 1:k) and B y_0 = 0,
+  A V_k = U_k R_M with R_M = Q_M^T B Q_C(:, 1:k) (k x k, in general full),
+  and A^T U_k = V_{t+1} B^T Q_M = V_{t+1} [y_1 s_1 .. y_k s_k] lies in the
+  kept span; both relations inherit only the backward error of the SVD of
+  B, whatever the size of s_j.  (Building U_k from the QR of T Q_C(1:t,
+  1:k) instead spans the same space in exact arithmetic, but its rounding
+  errors are amplified by |B| / s_k, which for small wanted values stalls
+  the eq. (4) test.)  The new T starts as R_M.  The restart vector u_{k+1}
   is A v_{k+1} re-orthogonalized (CGS2) against U_k, its two projections'
-  coefficients summed into T(1:k, k+1) (A V_{k+1} = U_{k+1} T(1:k+1, 1:k+1));
-  the Lanczos steps then go on from k+1 as usual.  When T is singular to
-  working precision (z not finite, or beta_t |z| > 1/sqrt(eps)), that cycle
-  restarts with the plain Ritz vectors instead.
+  coefficients summed into T(1:k, k+1) (A V_{k+1} = U_{k+1} T(1:k+1,
+  1:k+1)); the Lanczos steps then go on from k+1 as usual.
 
 * Partial re-orthogonalisation (``partial=True``; the PROPACK-style
   alternative that Sec. 1 names): instead of re-orthogonalising every new
@@ -326,26 +336,22 @@ def harmonic_restart_basis(T: np.ndarray, p: int, k: int):
     notes): from the (p+1) x (p+1) Lanczos T (leading p x p block, beta_p at
     T[p-1, p]) the coefficient matrices Q_C ((p+1) x (k+1), V_{p+1} Q_C is
     the new V_{k+1}), Q_M (p x k, U_p Q_M is the new U_k) and R_M (k x k, the
-    new T(1:k, 1:k)); None when T is singular to working precision."""
-    Tp = T[:p, :p]
-    beta = T[p - 1, p]
+    new T(1:k, 1:k))."""
     B = T[:p, :p + 1]
-    _, sb, Yt = sla.svd(B, full_matrices=False, lapack_driver="gesvd")
-    Y = Yt.T                                   # (p+1) x p, descending sb
+    Ub, sb, Yt = sla.svd(B, full_matrices=True, lapack_driver="gesvd")
+    Y = Yt.T                                   # (p+1) x (p+1); column p spans null(B)
     idx = np.argsort(sb, kind="stable")[:k]    # the k smallest harmonic values
-    e = np.zeros(p)
-    e[p - 1] = 1.0
-    with np.errstate(all="ignore"):
-        z = sla.solve_triangular(Tp, e, lower=False)
-    if not np.all(np.isfinite(z)) or abs(beta) * np.linalg.norm(z) > 1.0 / np.sqrt(EPS):
-        return None
-    G = Y[:p, idx] + beta * np.outer(z, Y[p, idx])
-    C = np.zeros((p + 1, k + 1))
-    C[:p, :k] = G
-    C[:p, k] = -beta * z
-    C[p, k] = 1.0
-    QC, _ = np.linalg.qr(C)
-    QM, RM = np.linalg.qr(Tp @ QC[:p, :k])
+    M = np.column_stack([Y[:, idx], Y[:, p]])
+    r = M[p].copy()
+    v = r.copy()
+    v[k] += np.copysign(np.linalg.norm(r), r[k])
+    H = np.eye(k + 1) - (2.0 / (v @ v)) * np.outer(v, v)
+    QC = M @ H
+    QC[p, :k] = 0.0
+    if QC[p, k] < 0:
+        QC[:, k] = -QC[:, k]
+    QM = Ub[:, idx]
+    RM = QM.T @ (B @ QC[:, :k])
     return QC, QM, RM
 
 
@@ -409,9 +415,8 @@ def svds(A, k: int, p: int = 0, tol: float = 0.0, maxit: int = 0,
             break
         if info.cycles >= maxit:
             break
-        hb = harmonic_restart_basis(st.T, p, k) if harmonic else None
-        if hb is not None:
-            QC, QM, RM = hb
+        if harmonic:
+            QC, QM, RM = harmonic_restart_basis(st.T, p, k)
             Un = st.U[:, :p] @ QM
             Vn = st.V[:, :p + 1] @ QC
             st.T[:] = 0.0

@@ -13,7 +13,7 @@ import scipy.sparse as sp
 
 from paper_2405_18966_amd import inputs
 from oracle import jacobi, philox, svds_ref
-from oracle.svds_ref import svds, lbp, explicit_residuals, as_operator
+from oracle.svds_ref import svds, lbp, explicit_residuals, as_operator, harmonic_restart_basis
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -600,8 +600,8 @@ def test_harmonic_residuals_share_one_direction():
 
 def test_harmonic_restart_keeps_the_lanczos_relations():
     """After harmonic restarts, A V_t = U_t T and A^T U_t = V_t T^T +
-    beta_t v_{t+1} e_t^T still hold to rounding, the bases stay orthonormal,
-    and T starts with the upper-triangular R of the QR of T Q_C."""
+    beta_t v_{t+1} e_t^T still hold to rounding and the bases stay
+    orthonormal (T starts with the full k x k block R_M)."""
     op, sig = _harmonic_case()
     D = op.toarray()
     k, p = 4, 12
@@ -614,18 +614,72 @@ def test_harmonic_restart_keeps_the_lanczos_relations():
             R = D.T @ U - V[:, :p] @ T[:p, :p].T
             R[:, p - 1] -= T[p - 1, p] * V[:, p]
             checks.append((e1, np.abs(R).max(), np.abs(U.T @ U - np.eye(p)).max(),
-                           np.abs(V.T @ V - np.eye(p + 1)).max(), np.abs(np.tril(T[:k, :k], -1)).max()))
+                           np.abs(V.T @ V - np.eye(p + 1)).max()))
     U, S, V, info = svds(op, k, p, 1e-10, 5000, v0=inputs.start_vector(600, 23), which="smallest", harmonic=True,
                          callback=cb)
     assert info.converged and info.harmonic_restarts > 0 and checks
-    for e1, e2, ou, ov, low in checks:
-        assert e1 <= 1e-12 * 2.0 and e2 <= 1e-12 * 2.0
-        assert ou <= 1e-12 and ov <= 1e-12
-        assert low == 0.0
+    for e1, e2, ou, ov in checks:
+        assert e1 <= 1e-13 and e2 <= 1e-13
+        assert ou <= 1e-13 and ov <= 1e-13
     exact = np.sort(sig)[:k]
     np.testing.assert_allclose(S, exact, rtol=1e-10)
     r1, r2 = explicit_residuals(op, U, S, V)
     assert (r2 / S).max() <= 2e-10
+
+
+def test_harmonic_restart_basis_spans_the_harmonic_ritz_vectors():
+    """The restart coefficients against their textbook definition, built
+    here through the solve with T: span(Q_C) = span{[g_j; 0], [-beta z; 1]}
+    with g_j = y_j(1:t) + beta y_j(t+1) z, z = T^{-1} e_t; the first k
+    columns of Q_C lie in span(V_t); Q_C and Q_M are orthonormal;
+    B Q_C(:, 1:k) = Q_M R_M and B^T Q_M lies in span(Q_C) to rounding."""
+    op, sig = _harmonic_case()
+    p, k = 20, 4
+    _, Tp, _, beta, _ = lbp(op, p, inputs.start_vector(600, 84))
+    T = np.zeros((p + 1, p + 1))
+    T[:p, :p] = Tp
+    T[p - 1, p] = beta
+    QC, QM, RM = harmonic_restart_basis(T, p, k)
+    B = T[:p, :p + 1]
+    _, sb, Yt = np.linalg.svd(B)
+    idx = np.argsort(sb)[:k]
+    z = np.linalg.solve(Tp, np.eye(p)[:, p - 1])
+    C = np.zeros((p + 1, k + 1))
+    C[:p, :k] = Yt.T[:p, idx] + beta * np.outer(z, Yt.T[p, idx])
+    C[:p, k] = -beta * z
+    C[p, k] = 1.0
+    Qc, _ = np.linalg.qr(C)
+    assert np.abs(Qc @ Qc.T - QC @ QC.T).max() <= 1e-10
+    assert np.all(QC[p, :k] == 0.0) and QC[p, k] > 0
+    assert np.abs(QC.T @ QC - np.eye(k + 1)).max() <= 1e-14
+    assert np.abs(QM.T @ QM - np.eye(k)).max() <= 1e-14
+    assert np.abs(B @ QC[:, :k] - QM @ RM).max() <= 1e-14 * sb[0]
+    G = B.T @ QM
+    assert np.abs(G - QC @ (QC.T @ G)).max() <= 1e-14 * sb[0]
+    # B restricted to the kept spans, Q_M^T B Q_C = [R_M, coupling], has
+    # exactly the k harmonic values as its singular values
+    assert np.allclose(np.sort(np.linalg.svd(QM.T @ B @ QC, compute_uv=False)), np.sort(sb[idx]), rtol=1e-12)
+
+
+def test_harmonic_fewer_cycles_on_clustered_small_values():
+    """Six clustered small values 1e-4 (1 + 0.01 i) below a bulk in [0.5, 1]
+    (1000 x 1000, five nonzeros per row): the harmonic restart converges in
+    far fewer cycles than plain Ritz augmentation, to the prescribed values
+    within 1e-10 relative."""
+    N = 1000
+    sig = np.concatenate([1e-4 * (1 + 0.01 * np.arange(6)), np.linspace(0.5, 1.0, N - 6)])
+    op = as_operator(inputs.prescribed_sparse(N // 5, 5, sig, seed=1))
+    exact = np.sort(sig)[:4]
+    res = {}
+    for h in (False, True):
+        U, S, V, info = svds(op, 4, 20, 1e-10, 3000, v0=inputs.start_vector(N, 23), which="smallest", harmonic=h)
+        assert info.converged
+        np.testing.assert_allclose(S, exact, rtol=1e-10)
+        r1, r2 = explicit_residuals(op, U, S, V)
+        assert (r1 / S).max() <= 1e-9 and (r2 / S).max() <= 1e-9
+        res[h] = info
+    assert res[True].harmonic_restarts == res[True].cycles - 1
+    assert res[True].cycles * 5 < res[False].cycles
 
 
 def test_harmonic_needs_smallest_and_full_reorth():
