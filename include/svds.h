@@ -88,8 +88,29 @@ enum {
   SVDS_FLAG_SMALLEST = 256,   /* the k smallest triplets instead (see below)    */
   SVDS_FLAG_SELECTIVE_REORTH = 512, /* second CGS pass only when needed (below) */
   SVDS_FLAG_PARTIAL_REORTH = 1024,  /* omega-recurrence partial re-orth. (below) */
-  SVDS_FLAG_EARLY_STOP = 2048       /* eq. (4) test inside a cycle (below)        */
+  SVDS_FLAG_EARLY_STOP = 2048,      /* eq. (4) test inside a cycle (below)        */
+  SVDS_FLAG_HARMONIC = 4096         /* harmonic-Ritz restarts, smallest (below)   */
 };
+
+/* SVDS_FLAG_HARMONIC (with SVDS_FLAG_SMALLEST): restarts keep harmonic Ritz
+ * vectors instead of Ritz vectors (the augmented restart of Baglama and
+ * Reichel that Sec. 1 cites for the smallest values).  With A V = U T and
+ * A^T U = V T^T + beta v e^T, the harmonic Ritz values of A^T A on span(V)
+ * are the squared singular values of B = [T, beta e] (p x (p+1)); the
+ * harmonic Ritz vectors of the k smallest and the common direction of their
+ * residuals span [V v_{p+1}] span{y_1..y_k, y_0} (y_j B's right singular
+ * vectors, y_0 its null vector).  Each cycle runs one more one-sided Jacobi
+ * SVD, of the stored (p+1) x (p+1) matrix [B; 0], then: V_{k+1} = [V v_{p+1}]
+ * Q_C (Q_C = [y_1..y_k, y_0] times the Householder reflection that zeroes
+ * the last row of its first k columns), U_k = U Q_M (B's matching left
+ * singular vectors), T(1:k,1:k) = Q_M^T B Q_C(:,1:k), and u_{k+1} = A v_{k+1}
+ * re-orthogonalized against U_k with its two CGS coefficient vectors as
+ * T(1:k, k+1).  The test of eq. (4) and the outputs stay those of the Ritz
+ * triplets of T.  Converges in fewer cycles than plain Ritz augmentation on
+ * some spectra (clustered small values), in more on others.  EINVAL without
+ * SVDS_FLAG_SMALLEST or with SVDS_FLAG_SELECTIVE_REORTH /
+ * SVDS_FLAG_PARTIAL_REORTH; EUNSUPPORTED for p > 1022 and in the batched
+ * solver. */
 
 /* SVDS_FLAG_EARLY_STOP: Proposition 1 holds for the leading block T(1:j,1:j)
  * of a cycle at every Lanczos dimension j, so the test of eq. (4) can pass
@@ -144,10 +165,10 @@ enum {
  * (5)-(7) and the test of eq. (4) hold for any k Ritz triplets.  S is then
  * ascending (U, V in the same order).  The test's sigma floor stays
  * 2^-52 times the largest Ritz value, so exactly zero singular values never
- * pass it.  This is plain Ritz augmentation (not the harmonic variant), so
- * convergence is fast only when the wanted values are well separated
- * relative to sigma_1.  FP64 path only: EUNSUPPORTED with SVDS_PREC_MIXED
- * and in the batched solver. */
+ * pass it.  This is plain Ritz augmentation unless SVDS_FLAG_HARMONIC is
+ * set, so convergence is fast only when the wanted values are well
+ * separated relative to sigma_1.  FP64 path only: EUNSUPPORTED with
+ * SVDS_PREC_MIXED and in the batched solver. */
 
 /* SVDS_FLAG_AUTOTUNE: plan creation times candidate launch shapes on the
  * plan's own matrix and keeps the fastest (svds_tuning reports the choice).

@@ -93,6 +93,20 @@ int svds_op_cgs2_noalloc(int64_t L, int32_t j, const void *Q, int64_t ldq, const
 int svds_op_small_svd(int32_t p, int32_t k, double tol, double *T, double *Uk, double *Vext,
                       double *sig, double *res, double *rho, int32_t *flags_host, void *stream);
 
+/* The harmonic-Ritz restart coefficients of SVDS_FLAG_HARMONIC (the
+ * augmented restart for the smallest values that Sec. 1 cites): T is the
+ * (p+1) x (p+1) row-major FP64 Lanczos matrix (B = [T(1:p,1:p), beta e_p] =
+ * its first p rows; row p+1 is read as zero), only read.  Outputs (device,
+ * FP64, column-major unless stated): QC ((p+1) x (k+1), ld p+1: [y_1..y_k,
+ * y_0] H, y_j the right singular vectors of the k smallest singular values
+ * of B, y_0 its null vector, H the Householder reflection that zeroes
+ * QC(p+1, 1:k); QC(p+1, k+1) > 0), QM (p x k, ld p: the matching left
+ * singular vectors), R (k x k, row-major: QM^T B QC(:, 1:k)).  Each y_j
+ * (with x_j) is determined up to sign, and within a repeated value up to
+ * rotation.  EINVAL unless 1 <= k < p <= 1022 and all pointers are set. */
+int svds_op_harmonic_basis(int32_t p, int32_t k, const double *T, double *QC, double *QM, double *R,
+                           void *stream);
+
 /* Restart rotation (Alg. 2 steps 8 and 16): out(:, 0:kc) = B(:, 0:pc) Y,
  * B L x pc of `btype` (F64/F32, ld ldb), Y pc x kc FP64 (ld ldy),
  * out L x kc FP64 (ld ldo).  Runs on the matrix cores (FP64 or FP32

@@ -393,7 +393,7 @@ extern "C" int svds_csr_solve_batched(int32_t count, const svds_csr *As, const s
   const int32_t vt = As[0].dtype;
   if (vt != SVDS_F64 && vt != SVDS_F32) return SVDS_EUNSUPPORTED;
   if (opts->precision != SVDS_PREC_FP64 && opts->precision != SVDS_PREC_MIXED) return SVDS_EINVAL;
-  if (opts->flags & (SVDS_FLAG_SMALLEST | SVDS_FLAG_SELECTIVE_REORTH | SVDS_FLAG_PARTIAL_REORTH))
+  if (opts->flags & (SVDS_FLAG_SMALLEST | SVDS_FLAG_SELECTIVE_REORTH | SVDS_FLAG_PARTIAL_REORTH | SVDS_FLAG_HARMONIC))
     return SVDS_EUNSUPPORTED;
   if (k < 1 || p <= k) return SVDS_EINVAL;
   if (p > JAC_SMALL_P || k + 1 > 64) return SVDS_EUNSUPPORTED;

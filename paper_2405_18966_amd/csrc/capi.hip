@@ -246,6 +246,21 @@ extern "C" int svds_op_small_svd(int32_t p, int32_t k, double tol, double *T, do
   SVDS_ABI_CATCH
 }
 
+extern "C" int svds_op_harmonic_basis(int32_t p, int32_t k, const double *T, double *QC, double *QM, double *R,
+                                      void *stream) {
+  SVDS_ABI_TRY
+  if (p < 2 || k < 1 || k >= p || p > 1022 || !T || !QC || !QM || !R) return SVDS_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Scratch s;
+  HIP_TRY(hipMalloc(&s.p, jacobi_work_bytes(p + 1) + 256));
+  std::vector<int> counts(JAC_MAX_SWEEPS);
+  const int rc = svds_harmonic_basis_run(st, T, p, k, static_cast<double *>(s.p), QC, QM, R, counts.data());
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(st));
+  return SVDS_OK;
+  SVDS_ABI_CATCH
+}
+
 extern "C" int svds_op_rotate(int64_t L, int32_t pc, int32_t kc, const void *B, int64_t ldb,
                               int32_t btype, const double *Y, int64_t ldy, double *out, int64_t ldo,
                               void *stream) {

@@ -341,35 +341,17 @@ __device__ __forceinline__ double jacobi_tol(int rows) {
 // Single-workgroup schedule (p <= JAC_SMALL_P, one row per lane).  Dynamic
 // LDS: W and Vh (pe x pe each, pe = p rounded up to even), sv, rank.
 // ---------------------------------------------------------------------------
-__device__ inline void small_svd_body(double *__restrict__ T, int64_t ts, int p, int k, double tol,
-                                      double *__restrict__ Uk, double *__restrict__ Vext,
-                                      double *__restrict__ sig, double *__restrict__ res,
-                                      double *__restrict__ rho, int *__restrict__ flags,
-                                      double *__restrict__ sigma_est, int smallest) {
-  extern __shared__ double smem[];
-  __shared__ int rot_count;
-  __shared__ double s_beta;
+// Sweeps over W and Vh (pe x pe each, in LDS) until one passes without a
+// rotation or JAC_MAX_SWEEPS are done; returns the sweeps used.  rot_count:
+// an int in LDS.
+__device__ inline int lds_jacobi_sweeps(double *__restrict__ W, double *__restrict__ Vh, int pe, int *rot_count) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int nwaves = blockDim.x / WAVE;
-  const int pe = p + (p & 1);
-  const int ld = p + 1;
-  double *W = smem;
-  double *Vh = smem + pe * pe;
-  double *sv = Vh + pe * pe;
-  int *rank = reinterpret_cast<int *>(sv + pe);
-
-  if (tid == 0) s_beta = T[((p - 1) * ld + p) * ts];
-  for (int idx = tid; idx < pe * pe; idx += blockDim.x) {
-    const int r = idx % pe, c = idx / pe;
-    W[idx] = (r < p && c < p) ? T[(r * ld + c) * ts] : 0.0;
-    Vh[idx] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
   const double tolJ = jacobi_tol(pe);
   const int npairs = pe / 2;
   int sweeps = 0;
   for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
-    if (tid == 0) rot_count = 0;
+    if (tid == 0) *rot_count = 0;
     __syncthreads();
     for (int step = 0; step < pe - 1; ++step) {
       // four pairs per wave, one per row of 16 lanes (pe <= 64: at most four
@@ -389,13 +371,41 @@ __device__ inline void small_svd_body(double *__restrict__ T, int64_t ts, int p,
         }
         nrot += jacobi_pairg<4, 16>(wi, wj, vi, vj, pe, sl, tolJ);
       }
-      if (sl == 0 && nrot) atomicAdd(&rot_count, nrot);
+      if (sl == 0 && nrot) atomicAdd(rot_count, nrot);
       __syncthreads();
     }
     sweeps = sweep + 1;
-    if (rot_count == 0) break;
+    const int done = *rot_count == 0;
     __syncthreads();
+    if (done) break;
   }
+  return sweeps;
+}
+
+__device__ inline void small_svd_body(double *__restrict__ T, int64_t ts, int p, int k, double tol,
+                                      double *__restrict__ Uk, double *__restrict__ Vext,
+                                      double *__restrict__ sig, double *__restrict__ res,
+                                      double *__restrict__ rho, int *__restrict__ flags,
+                                      double *__restrict__ sigma_est, int smallest) {
+  extern __shared__ double smem[];
+  __shared__ int rot_count;
+  __shared__ double s_beta;
+  const int tid = threadIdx.x;
+  const int pe = p + (p & 1);
+  const int ld = p + 1;
+  double *W = smem;
+  double *Vh = smem + pe * pe;
+  double *sv = Vh + pe * pe;
+  int *rank = reinterpret_cast<int *>(sv + pe);
+
+  if (tid == 0) s_beta = T[((p - 1) * ld + p) * ts];
+  for (int idx = tid; idx < pe * pe; idx += blockDim.x) {
+    const int r = idx % pe, c = idx / pe;
+    W[idx] = (r < p && c < p) ? T[(r * ld + c) * ts] : 0.0;
+    Vh[idx] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int sweeps = lds_jacobi_sweeps(W, Vh, pe, &rot_count);
   jacobi_finish(W, pe, Vh, pe, p, k, tol, s_beta, sweeps, T, ts, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
                 rank, smallest);
 }
@@ -437,11 +447,14 @@ __host__ __device__ inline size_t small_svd_lds_bytes(int p) {
 // 2c columns of W then 2c columns of Vh, p rows each.  Block b holds global
 // columns [b c, b c + c); W and Vh in global memory are column-major with
 // ld = p and nb*c columns.  In the first round of the first sweep the blocks
-// are loaded from T (row-major, ld p+1) and the identity instead.
+// are loaded from T (row-major, row stride ldt; rows from tr on read as
+// zero) and the identity instead: ldt = p + 1, tr = p for the small SVD of
+// T(1:p, 1:p), ldt = p, tr = p - 1 for the harmonic SVD of the whole stored
+// matrix ([T, beta e] and a zero row).
 // ---------------------------------------------------------------------------
 template <int RPL, int LPP>
-__global__ __launch_bounds__(LPP == WAVE ? (RPL <= 6 ? 1024 : 512) : 256) void bjac_round_kernel(const double *__restrict__ T, int from_T,
-                                                                 double *__restrict__ W,
+__global__ __launch_bounds__(LPP == WAVE ? (RPL <= 6 ? 1024 : 512) : 256) void bjac_round_kernel(const double *__restrict__ T, int ldt, int tr,
+                                                                 int from_T, double *__restrict__ W,
                                                                  double *__restrict__ Vh, int p, int c,
                                                                  int nb, int round, int sweep,
                                                                  int *__restrict__ counters) {
@@ -455,7 +468,6 @@ __global__ __launch_bounds__(LPP == WAVE ? (RPL <= 6 ? 1024 : 512) : 256) void b
   int ba, bb;
   rr_pair(nb, round, blockIdx.x, ba, bb);
   if (tid == 0) s_rot = 0;
-  const int ldt = p + 1;
   // staging: a thread issues BJ_LU loads of each matrix before it writes
   // any of them to LDS, so the global-memory latency is paid once per batch
   const int ntot = c2 * p;
@@ -469,7 +481,7 @@ __global__ __launch_bounds__(LPP == WAVE ? (RPL <= 6 ? 1024 : 512) : 256) void b
         const int lc = idx / p, r = idx - lc * p;
         const int gc = lc < c ? ba * c + lc : bb * c + (lc - c);
         if (from_T) {
-          vx[u] = gc < p ? T[static_cast<int64_t>(r) * ldt + gc] : 0.0;
+          vx[u] = (gc < p && r < tr) ? T[static_cast<int64_t>(r) * ldt + gc] : 0.0;
           vy[u] = (r == gc) ? 1.0 : 0.0;
         } else {
           vx[u] = W[static_cast<int64_t>(gc) * p + r];
@@ -562,6 +574,178 @@ static __global__ __launch_bounds__(JAC_THREADS) void bjac_finish_kernel(
   __syncthreads();
   jacobi_finish(W, p, Vh, p, p, k, tol, s_beta, s_sweeps, T, 1, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
                 rank, smallest);
+}
+
+
+// ---------------------------------------------------------------------------
+// Harmonic-Ritz restart (SVDS_FLAG_HARMONIC, smallest triplets).  With
+// A V_p = U_p T and A^T U_p = V_p T^T + beta_p v_{p+1} e_p^T, the harmonic
+// Ritz values of A^T A on span(V_p) are the squared singular values of
+// B = [T, beta_p e_p] (p x (p+1)); the harmonic Ritz vectors and the common
+// direction of their residuals span V_{p+1} span{y_1..y_k, y_0}, y_j the right
+// singular vectors of the k smallest values and y_0 the null vector of B.
+// One-sided Jacobi of the stored (p+1) x (p+1) matrix (B and a zero row)
+// gives them all: B Vh = W, column norms s_c (one of them ~0: y_0).
+// From W and Vh (q = p + 1 columns, rows 0..p; row p of W is zero):
+//   M = [y_1..y_k, y_0] (Vh columns); H = I - tau v v^T the Householder
+//   reflection with r H = -sign(r_{k+1}) |r| e_{k+1}^T for the last row r of
+//   M; Q_C = M H with Q_C(p, 0:k) = 0 and a positive Q_C(p, k)
+//   ((p+1) x (k+1), ld p+1: [V_p v_{p+1}] Q_C is the new V_{k+1});
+//   Q_M = [x_1..x_k], x_j = W(:, y_j) / s_j the left singular vectors
+//   (p x k, ld p: U_p Q_M is the new U_k);
+//   R = Q_M^T B Q_C(:, 0:k) = Q_M^T (W_M H)(:, 0:k), W_M = B M the W columns
+//   of M (k x k row-major: the new T(1:k, 1:k)).
+// Both Lanczos relations then hold with the backward error of the SVD
+// alone.  Scratch: sd 4 q doubles, si 2 q ints (block-shared).
+// ---------------------------------------------------------------------------
+__device__ inline void harm_finish(const double *W, int64_t ldw, const double *Vh, int64_t ldv, int p, int k,
+                                   double *__restrict__ QC, double *__restrict__ QM, double *__restrict__ R,
+                                   double *sd, int *si) {
+  __shared__ double s_tau, s_sgn;
+  __shared__ int s_null;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int nwaves = blockDim.x / WAVE;
+  const int q = p + 1;
+  double *sv = sd, *y = sd + q, *z = sd + 2 * q, *v = sd + 3 * q;
+  int *sel = si;
+  for (int c = wv; c < q; c += nwaves) {
+    double a = 0;
+    for (int r = lane; r < q; r += WAVE) a += W[c * ldw + r] * W[c * ldw + r];
+    a = wave_sum_u(a);
+    if (lane == 0) sv[c] = sqrt(a);
+  }
+  __syncthreads();
+  if (tid == 0) {  // y_0: the column of least norm (ties: the lower one)
+    int nl = 0;
+    for (int c = 1; c < q; ++c)
+      if (sv[c] < sv[nl]) nl = c;
+    s_null = nl;
+    sel[k] = nl;
+  }
+  __syncthreads();
+  const int nl = s_null;
+  for (int c = tid; c < q; c += blockDim.x) {  // the k smallest of the others, ascending
+    if (c == nl) continue;
+    const double s = sv[c];
+    int rk = 0;
+    for (int d = 0; d < q; ++d) rk += (d != nl) && ((sv[d] < s) || (sv[d] == s && d < c));
+    if (rk < k) sel[rk] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {  // Householder vector from the last row of M
+    double n2 = 0;
+    for (int j = 0; j <= k; ++j) {
+      const double r = Vh[sel[j] * ldv + p];
+      v[j] = r;
+      n2 += r * r;
+    }
+    v[k] += copysign(sqrt(n2), v[k]);
+    double vv = 0;
+    for (int j = 0; j <= k; ++j) vv += v[j] * v[j];
+    s_tau = vv > 0 ? 2.0 / vv : 0.0;
+  }
+  __syncthreads();
+  const double tau = s_tau;
+  for (int i = tid; i < q; i += blockDim.x) {  // y = M v
+    double a = 0;
+    for (int j = 0; j <= k; ++j) a += Vh[sel[j] * ldv + i] * v[j];
+    y[i] = a;
+  }
+  for (int r = tid; r < p; r += blockDim.x) {  // z = W_M v
+    double a = 0;
+    for (int j = 0; j <= k; ++j) a += W[sel[j] * ldw + r] * v[j];
+    z[r] = a;
+  }
+  __syncthreads();
+  if (tid == 0) s_sgn = (Vh[nl * ldv + p] - tau * y[p] * v[k]) < 0 ? -1.0 : 1.0;
+  __syncthreads();
+  const double sg = s_sgn;
+  for (int idx = tid; idx < q * (k + 1); idx += blockDim.x) {
+    const int j = idx / q, i = idx - j * q;
+    double x = (i == p && j < k) ? 0.0 : Vh[sel[j] * ldv + i] - tau * y[i] * v[j];
+    if (j == k) x *= sg;
+    QC[static_cast<int64_t>(j) * q + i] = x;
+  }
+  for (int idx = tid; idx < p * k; idx += blockDim.x) {
+    const int j = idx / p, r = idx - j * p;
+    const double s = sv[sel[j]];
+    QM[static_cast<int64_t>(j) * p + r] = s > 0 ? W[sel[j] * ldw + r] / s : 0.0;
+  }
+  for (int idx = wv; idx < k * k; idx += nwaves) {  // R(i, j), one wave each
+    const int i = idx / k, j = idx - i * k;
+    const double *wi = W + sel[i] * ldw, *wj = W + sel[j] * ldw;
+    const double tv = tau * v[j];
+    double a = 0;
+    for (int r = lane; r < p; r += WAVE) a += wi[r] * (wj[r] - tv * z[r]);
+    a = wave_sum_u(a);
+    if (lane == 0) {
+      const double s = sv[sel[i]];
+      R[idx] = s > 0 ? a / s : 0.0;
+    }
+  }
+}
+
+// LDS of the harmonic finish: 4 q doubles and 2 q ints
+__host__ __device__ inline size_t harm_scratch_bytes(int q) { return static_cast<size_t>(q) * (4 * 8 + 2 * 4); }
+
+// Single-workgroup schedule of the harmonic SVD (p + 1 <= JAC_SMALL_P):
+// W <- the stored T (rows 0..p-1; row p zero), Vh <- I, pe = p + 1 rounded
+// up to even (a padding column stays zero and is never rotated).
+static __global__ __launch_bounds__(JAC_THREADS) void harm_small_kernel(const double *__restrict__ T, int p, int k,
+                                                                        double *__restrict__ QC,
+                                                                        double *__restrict__ QM,
+                                                                        double *__restrict__ R) {
+  extern __shared__ double smem[];
+  __shared__ int rot_count;
+  const int q = p + 1, pe = q + (q & 1);
+  double *W = smem;
+  double *Vh = smem + pe * pe;
+  double *sd = Vh + pe * pe;
+  int *si = reinterpret_cast<int *>(sd + 4 * q);
+  for (int idx = threadIdx.x; idx < pe * pe; idx += blockDim.x) {
+    const int r = idx % pe, c = idx / pe;
+    W[idx] = (r < p && c < q) ? T[r * q + c] : 0.0;
+    Vh[idx] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  (void)lds_jacobi_sweeps(W, Vh, pe, &rot_count);
+  harm_finish(W, pe, Vh, pe, p, k, QC, QM, R, sd, si);
+}
+
+__host__ __device__ inline size_t harm_small_lds_bytes(int p) {
+  const int q = p + 1, pe = q + (q & 1);
+  return static_cast<size_t>(2 * pe * pe) * 8 + harm_scratch_bytes(q);
+}
+
+// Block schedule of the harmonic SVD: outputs after the last round (one
+// workgroup); W and Vh column-major with ld q = p + 1.
+static __global__ __launch_bounds__(JAC_THREADS) void harm_bjac_finish_kernel(const double *__restrict__ W,
+                                                                              const double *__restrict__ Vh, int p,
+                                                                              int k, double *__restrict__ QC,
+                                                                              double *__restrict__ QM,
+                                                                              double *__restrict__ R) {
+  extern __shared__ double smem[];
+  const int q = p + 1;
+  harm_finish(W, q, Vh, q, p, k, QC, QM, R, smem, reinterpret_cast<int *>(smem + 4 * q));
+}
+
+// The restarted T of a harmonic restart: zeros, R in the leading k x k block
+// (the arrow column T(0:k, k) is filled after the restart vector's CGS2).
+static __global__ void harm_tset_kernel(double *__restrict__ T, int p, int k, const double *__restrict__ R) {
+  const int ld = p + 1;
+  for (int idx = threadIdx.x; idx < ld * ld; idx += blockDim.x) {
+    const int r = idx / ld, c = idx - r * ld;
+    T[idx] = (r < k && c < k) ? R[r * k + c] : 0.0;
+  }
+}
+
+// T(0:k, k) = the two CGS projections of A v_{k+1} on U_k (u_{k+1} =
+// (A v_{k+1} - U_k T(0:k, k)) / T(k, k)).
+template <typename TB>
+__global__ void harm_couple_kernel(double *__restrict__ T, int p, int k, const TB *__restrict__ h1,
+                                   const TB *__restrict__ h2) {
+  for (int r = threadIdx.x; r < k; r += blockDim.x)
+    T[r * (p + 1) + k] = static_cast<double>(h1[r]) + static_cast<double>(h2[r]);
 }
 
 }  // namespace svds

@@ -196,3 +196,8 @@ int svds_cgs2_op(int64_t L, int32_t j, const void *Q, int64_t ldq, const void *w
 int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, double *work, double *Uk,
                        double *Vext, double *sig, double *res, double *rho, int *flags, double *sigma_est,
                        int *h_counts, int smallest = 0);
+// Harmonic-Ritz restart coefficients from the stored (p+1) x (p+1) T (see
+// harm_finish): QC ((p+1) x (k+1)), QM (p x k), R (k x k row-major); `work`
+// holds jacobi_work_bytes(p + 1) bytes.  T is only read.
+int svds_harmonic_basis_run(hipStream_t st, const double *T, int p, int k, double *work, double *QC, double *QM,
+                            double *R, int *h_counts);

@@ -279,6 +279,8 @@ struct Small {
   double *om_mu, *om_nu, *om_pend, *om_nrm0;
   int *om_mask, *om_fu, *om_fv;
   long long *om_stats;
+  // harmonic restart coefficients: Q_C ((p+1) x (k+1)), Q_M (p x k), R (k x k)
+  double *hQC, *hQM, *hR;
 };
 
 // thresholds of the partial re-orthogonalization: trigger sqrt(eps), select eps^(3/4)
@@ -350,6 +352,7 @@ struct svds_plan {
   bool smallest = false;  // SVDS_FLAG_SMALLEST: k smallest triplets, ascending
   bool selective = false;  // SVDS_FLAG_SELECTIVE_REORTH: second CGS pass only when needed
   bool partial = false;    // SVDS_FLAG_PARTIAL_REORTH: omega-recurrence partial re-orthogonalization
+  bool harmonic = false;   // SVDS_FLAG_HARMONIC: harmonic-Ritz restarts (with SVDS_FLAG_SMALLEST)
   int64_t reorth_calls = 0;  // re-orthogonalizations with the selective test
   bool early = false;      // SVDS_FLAG_EARLY_STOP
   EarlyCheck ec;
@@ -888,8 +891,13 @@ static int small_svd(svds_plan *P) {
   const int p = P->p;
   const Small &s = P->sc;
   ACC_BEFORE(SVDS_KC_SMALLSVD);
-  int rc = svds_small_svd_run(P->stream, s.T, p, P->k, P->tol, s.jac, s.Uk, s.Vext, s.sig, s.res, s.rho,
-                              s.flags, s.sigma_est, P->h_flags + 16, P->smallest ? 1 : 0);
+  int rc;
+  // the harmonic restart's SVD reads T before the Ritz SVD rewrites it
+  if (P->harmonic &&
+      (rc = svds_harmonic_basis_run(P->stream, s.T, p, P->k, s.jac, s.hQC, s.hQM, s.hR, P->h_flags + 16)))
+    return rc;
+  rc = svds_small_svd_run(P->stream, s.T, p, P->k, P->tol, s.jac, s.Uk, s.Vext, s.sig, s.res, s.rho, s.flags,
+                          s.sigma_est, P->h_flags + 16, P->smallest ? 1 : 0);
   if (rc) return rc;
   ACC_AFTER(SVDS_KC_SMALLSVD, 16.0 * (p + 1) * (p + 1), 0.0);
   HIP_TRY(hipMemcpyAsync(P->h_flags, s.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
@@ -926,6 +934,26 @@ template <typename TB> static int restart(svds_plan *P, Lanczos<TB> &Lz) {
   const int nxt = 1 - Lz.cur;
   TB *U = Lz.U[Lz.cur], *V = Lz.V[Lz.cur];
   TB *Un = Lz.U[nxt], *Vn = Lz.V[nxt];
+  if (P->harmonic) {
+    // U_k = U_p Q_M, V_{k+1} = [V_p v_{p+1}] Q_C, T(1:k, 1:k) = R; u_{k+1}
+    // from A v_{k+1} by CGS2 against U_k, whose two coefficient vectors
+    // form T(1:k, k+1)
+    int rc = rotate<TB, TB>(P, Lz.m, p, k, U, Lz.ldu, s.hQM, p, Un, Lz.ldu);
+    if (rc) return rc;
+    rc = rotate<TB, TB>(P, Lz.n, p + 1, k + 1, V, Lz.ldv, s.hQC, ld, Vn, Lz.ldv);
+    if (rc) return rc;
+    Lz.cur = nxt;
+    hipLaunchKernelGGL(harm_tset_kernel, dim3(1), dim3(256), 0, P->stream, s.T, p, k, s.hR);
+    LAUNCH_CHECK();
+    rc = matvec<TB>(P, false, Vn + k * Lz.ldv, s.one, nullptr, nullptr, Lz.wu, nullptr, 0);
+    if (rc) return rc;
+    rc = cgs2_finish<TB>(P, Lz, Un, Lz.ldu, Lz.m, k, Lz.wu, Lz.w1u, Lz.bu, MODE_LANCZOS, s.T + k * ld + k,
+                         s.xs_u);
+    if (rc) return rc;
+    hipLaunchKernelGGL((harm_couple_kernel<TB>), dim3(1), dim3(256), 0, P->stream, s.T, p, k, Lz.h1, Lz.h2);
+    LAUNCH_CHECK();
+    return SVDS_OK;
+  }
   int rc = rotate<TB, TB>(P, Lz.m, p, k, U, Lz.ldu, s.Uk, p, Un, Lz.ldu);
   if (rc) return rc;
   rc = rotate<TB, TB>(P, Lz.n, p + 1, k + 1, V, Lz.ldv, s.Vext, ld, Vn, Lz.ldv);
@@ -1107,16 +1135,20 @@ static int fill_defaults(const svds_opts *o, int64_t m, int64_t n, svds_plan *P)
   P->smallest = (o->flags & SVDS_FLAG_SMALLEST) != 0;
   P->selective = (o->flags & SVDS_FLAG_SELECTIVE_REORTH) != 0;
   P->partial = (o->flags & SVDS_FLAG_PARTIAL_REORTH) != 0;
+  P->harmonic = (o->flags & SVDS_FLAG_HARMONIC) != 0;
   // captured cycles replay a fixed sequence of launches: no early stop there
   P->early = (o->flags & SVDS_FLAG_EARLY_STOP) != 0 && !(o->flags & SVDS_FLAG_GRAPH);
   if (o->precision != SVDS_PREC_FP64 && o->precision != SVDS_PREC_MIXED) return SVDS_EINVAL;
   if (P->selective && P->partial) return SVDS_EINVAL;
+  // harmonic restarts: smallest triplets, full re-orthogonalization
+  if (P->harmonic && (!P->smallest || P->selective || P->partial)) return SVDS_EINVAL;
   // the FP32 phase cannot resolve values below ~1e-7 sigma_1
   if (P->smallest && P->mixed) return SVDS_EUNSUPPORTED;
   // the partial form's thresholds are those of FP64 arithmetic
   if (P->partial && P->mixed) return SVDS_EUNSUPPORTED;
   if (P->k < 1 || P->p <= P->k || P->p > m || P->p + 1 > n) return SVDS_EINVAL;
   if (P->p + 1 > CGS_MAXJ) return SVDS_EUNSUPPORTED;
+  if (P->harmonic && P->p + 2 > CGS_MAXJ) return SVDS_EUNSUPPORTED;  // SVD of p + 1 columns
   return SVDS_OK;
 }
 
@@ -1146,7 +1178,7 @@ static int carve_all(svds_plan *P, Arena &a) {
   s.res = a.take<double>(k);
   s.Uk = a.take<double>(static_cast<size_t>(p) * k);
   s.Vext = a.take<double>(static_cast<size_t>(p + 1) * (k + 1));
-  s.jac = a.take<double>(jacobi_work_bytes(p) / 8 + 8);
+  s.jac = a.take<double>(std::max(jacobi_work_bytes(p), P->harmonic ? jacobi_work_bytes(p + 1) : 0) / 8 + 8);
   s.npart = a.take<double>(NPART);
   s.resid_av = a.take<double>(k);
   s.resid_atu = a.take<double>(k);
@@ -1167,6 +1199,11 @@ static int carve_all(svds_plan *P, Arena &a) {
     e.sigma_est = a.take<double>(1);
     e.jac = a.take<double>(jacobi_work_bytes(p) / 8 + 8);
     e.flags = a.take<int>(4);
+  }
+  if (P->harmonic) {
+    s.hQC = a.take<double>(static_cast<size_t>(p + 1) * (k + 1));
+    s.hQM = a.take<double>(static_cast<size_t>(p) * k);
+    s.hR = a.take<double>(static_cast<size_t>(k) * k);
   }
   if (P->partial) {
     s.om_mu = a.take<double>(p + 2);
@@ -2631,8 +2668,8 @@ extern "C" int svds_op_cgs2_noalloc(int64_t L, int32_t j, const void *Q, int64_t
 
 namespace {
 template <int R, int LPP>
-int bjac_launch_round(hipStream_t st, const double *T, int from_T, double *W, double *Vh, int p, int c, int nb,
-                      int round, int sweep, int *counters) {
+int bjac_launch_round(hipStream_t st, const double *T, int ldt, int tr, int from_T, double *W, double *Vh, int p,
+                      int c, int nb, int round, int sweep, int *counters) {
   const size_t shm = static_cast<size_t>(4 * c) * p * sizeof(double);
   static bool attr_set = false;  // benign race: every caller sets the same value
   if (!attr_set) {
@@ -2641,8 +2678,8 @@ int bjac_launch_round(hipStream_t st, const double *T, int from_T, double *W, do
     attr_set = true;
   }
   const int waves = LPP == WAVE ? c : std::max(1, c / 4);  // one lane group per pair of a step
-  hipLaunchKernelGGL((bjac_round_kernel<R, LPP>), dim3(nb / 2), dim3(waves * WAVE), shm, st, T, from_T, W, Vh, p,
-                     c, nb, round, sweep, counters);
+  hipLaunchKernelGGL((bjac_round_kernel<R, LPP>), dim3(nb / 2), dim3(waves * WAVE), shm, st, T, ldt, tr, from_T, W,
+                     Vh, p, c, nb, round, sweep, counters);
   HIP_TRY(hipGetLastError());
   return SVDS_OK;
 }
@@ -2653,10 +2690,11 @@ int bjac_launch_round(hipStream_t st, const double *T, int from_T, double *W, do
 // wave per pair against 47.2 us with 16-lane groups; at p = 150 and 250 the
 // 16-lane groups are as fast or faster (and p = 150 converged in fewer
 // sweeps with them).
-int bjac_round(hipStream_t st, const double *T, int from_T, double *W, double *Vh, int p, int c, int nb,
-               int round, int sweep, int *counters) {
+int bjac_round(hipStream_t st, const double *T, int ldt, int tr, int from_T, double *W, double *Vh, int p, int c,
+               int nb, int round, int sweep, int *counters) {
   const int rpl16 = static_cast<int>(ceil_div(p, 16));
-#define BJ_GO(R, LPP) return bjac_launch_round<R, LPP>(st, T, from_T, W, Vh, p, c, nb, round, sweep, counters)
+#define BJ_GO(R, LPP) \
+  return bjac_launch_round<R, LPP>(st, T, ldt, tr, from_T, W, Vh, p, c, nb, round, sweep, counters)
   if (rpl16 <= 4) BJ_GO(4, 16);
   if (rpl16 <= 8) BJ_GO(8, 16);
   if (rpl16 <= 12) BJ_GO(12, 16);
@@ -2674,6 +2712,39 @@ int bjac_round(hipStream_t st, const double *T, int from_T, double *W, double *V
 static __global__ void zero_i32_kernel(int n, int *__restrict__ out) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = 0;
 }
+
+// Block-schedule sweeps of W Vh (p rows, nb*c columns each, in `work`) from
+// the rows of T (row stride ldt, rows from tr on zero) until a sweep passes
+// without a rotation; returns the sweeps enqueued in *nsw.  Sweeps are
+// enqueued in chunks (10, then 2 at a time) and the rotation counters read
+// back after each chunk.
+static int bjac_sweeps(hipStream_t st, const double *T, int ldt, int tr, double *work, int p, int *h_counts,
+                       int *nsw) {
+  int c, nb;
+  bjac_shape(p, c, nb);
+  double *W = work;
+  double *Vh = work + static_cast<int64_t>(p) * nb * c;
+  int *counters = reinterpret_cast<int *>(Vh + static_cast<int64_t>(p) * nb * c);
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, JAC_MAX_SWEEPS, counters);
+  HIP_TRY(hipGetLastError());
+  int enq = 0;
+  bool done = false;
+  while (!done && enq < JAC_MAX_SWEEPS) {
+    const int chunk = std::min(enq == 0 ? 10 : 2, JAC_MAX_SWEEPS - enq);
+    for (int sw = enq; sw < enq + chunk; ++sw)
+      for (int r = 0; r < nb - 1; ++r) {
+        const int rc = bjac_round(st, T, ldt, tr, sw == 0 && r == 0, W, Vh, p, c, nb, r, sw, counters);
+        if (rc) return rc;
+      }
+    enq += chunk;
+    HIP_TRY(hipMemcpyAsync(h_counts, counters, sizeof(int) * enq, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < enq; ++i)
+      if (h_counts[i] == 0) done = true;
+  }
+  *nsw = enq;
+  return SVDS_OK;
+}
 }  // namespace
 
 int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, double *work, double *Uk,
@@ -2687,32 +2758,40 @@ int svds_small_svd_run(hipStream_t st, double *T, int p, int k, double tol, doub
     HIP_TRY(hipGetLastError());
     return SVDS_OK;
   }
+  int enq = 0;
+  const int rc = bjac_sweeps(st, T, p + 1, p, work, p, h_counts, &enq);
+  if (rc) return rc;
   int c, nb;
   bjac_shape(p, c, nb);
-  double *W = work;
-  double *Vh = work + static_cast<int64_t>(p) * nb * c;
-  int *counters = reinterpret_cast<int *>(Vh + static_cast<int64_t>(p) * nb * c);
-  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, JAC_MAX_SWEEPS, counters);
-  HIP_TRY(hipGetLastError());
-  // sweeps are enqueued in chunks (10, then 2 at a time) and the rotation
-  // counters read back after each chunk
-  int enq = 0;
-  bool done = false;
-  while (!done && enq < JAC_MAX_SWEEPS) {
-    const int chunk = std::min(enq == 0 ? 10 : 2, JAC_MAX_SWEEPS - enq);
-    for (int sw = enq; sw < enq + chunk; ++sw)
-      for (int r = 0; r < nb - 1; ++r) {
-        const int rc = bjac_round(st, T, sw == 0 && r == 0, W, Vh, p, c, nb, r, sw, counters);
-        if (rc) return rc;
-      }
-    enq += chunk;
-    HIP_TRY(hipMemcpyAsync(h_counts, counters, sizeof(int) * enq, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    for (int i = 0; i < enq; ++i)
-      if (h_counts[i] == 0) done = true;
-  }
+  const double *W = work;
+  const double *Vh = work + static_cast<int64_t>(p) * nb * c;
+  const int *counters = reinterpret_cast<const int *>(Vh + static_cast<int64_t>(p) * nb * c);
   hipLaunchKernelGGL(bjac_finish_kernel, dim3(1), dim3(JAC_THREADS), static_cast<size_t>(p) * 12, st, W, Vh,
                      counters, enq, T, p, k, tol, Uk, Vext, sig, res, rho, flags, sigma_est, smallest);
+  HIP_TRY(hipGetLastError());
+  return SVDS_OK;
+}
+
+int svds_harmonic_basis_run(hipStream_t st, const double *T, int p, int k, double *work, double *QC, double *QM,
+                            double *R, int *h_counts) {
+  const int q = p + 1;
+  if (p < 2 || k < 1 || k >= p || q > 1023) return SVDS_EINVAL;
+  if (q <= JAC_SMALL_P) {
+    hipLaunchKernelGGL(harm_small_kernel, dim3(1), dim3(small_svd_threads(q)), harm_small_lds_bytes(p), st, T, p,
+                       k, QC, QM, R);
+    HIP_TRY(hipGetLastError());
+    return SVDS_OK;
+  }
+  // the stored (p+1) x (p+1) matrix, row stride p + 1, row p zero
+  int enq = 0;
+  const int rc = bjac_sweeps(st, T, q, p, work, q, h_counts, &enq);
+  if (rc) return rc;
+  int c, nb;
+  bjac_shape(q, c, nb);
+  const double *W = work;
+  const double *Vh = work + static_cast<int64_t>(q) * nb * c;
+  hipLaunchKernelGGL(harm_bjac_finish_kernel, dim3(1), dim3(JAC_THREADS), harm_scratch_bytes(q), st, W, Vh, p, k,
+                     QC, QM, R);
   HIP_TRY(hipGetLastError());
   return SVDS_OK;
 }

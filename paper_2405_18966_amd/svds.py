@@ -27,6 +27,7 @@ SVDS_FLAG_ITEMS_1K, SVDS_FLAG_UNSORTED, SVDS_FLAG_NO_PANELS, SVDS_FLAG_SMALLEST 
 SVDS_FLAG_SELECTIVE_REORTH = 512
 SVDS_FLAG_PARTIAL_REORTH = 1024
 SVDS_FLAG_EARLY_STOP = 2048
+SVDS_FLAG_HARMONIC = 4096
 KERNEL_CLASSES = ["spmv", "spmvT", "cgs_proj", "cgs_updproj", "cgs_updnorm", "cgs_reduce", "smallsvd",
                   "rotate", "other"]
 KC_COUNT = len(KERNEL_CLASSES)
@@ -111,6 +112,7 @@ def _load():
         "svds_op_cgs2": (i32, [i64, i32, vp, i64, vp, vp, P(d), i32, vp]),
         "svds_op_cgs2_noalloc": (i32, [i64, i32, vp, i64, vp, vp, P(d), i32, vp]),
         "svds_op_small_svd": (i32, [i32, i32, d, vp, vp, vp, vp, vp, vp, P(i32), vp]),
+        "svds_op_harmonic_basis": (i32, [i32, i32, vp, vp, vp, vp, vp]),
         "svds_op_rotate": (i32, [i64, i32, i32, vp, i64, i32, vp, i64, vp, i64, vp]),
         "svds_op_philox_normal": (i32, [i64, u64, C.c_uint32, vp, vp]),
         "svds_op_copy_f64": (i32, [i64, vp, vp, vp]),
@@ -152,25 +154,37 @@ _VT = {torch.float64: SVDS_F64, torch.float32: SVDS_F32, torch.uint16: SVDS_BF16
 
 
 def make_csr(row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, m: int, n: int) -> svds_csr:
-    """C struct for a device CSR (int32 row_ptr/col_idx, FP64/FP32 values)."""
+    """C struct for a device CSR (int32 row_ptr/col_idx, FP64/FP32 values);
+    it holds references to the three tensors (see make_dense)."""
     assert row_ptr.dtype == torch.int32 and col_idx.dtype == torch.int32
     assert row_ptr.is_cuda and col_idx.is_cuda and val.is_cuda
     assert row_ptr.numel() == m + 1
-    return svds_csr(m, n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr(), val.data_ptr(),
-                    _VT[val.dtype])
+    c = svds_csr(m, n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr(), val.data_ptr(),
+                 _VT[val.dtype])
+    c._keep = (row_ptr, col_idx, val)
+    return c
 
 
 def make_dense(a: torch.Tensor, m: int, n: int) -> svds_dense:
     """C struct for a column-major device matrix given as a 1-D tensor of
-    m*n (ld = m) FP64/FP32 values or BF16 bit patterns (uint16/bfloat16)."""
+    m*n (ld = m) FP64/FP32 values or BF16 bit patterns (uint16/bfloat16).
+    The struct holds a reference to `a`, so the memory stays allocated while
+    the struct lives (a tensor made inline would otherwise go back to
+    torch's caching allocator at once and be handed to the next tensor)."""
     assert a.is_cuda and a.numel() == m * n
-    return svds_dense(m, n, m, a.data_ptr(), _VT[a.dtype])
+    d = svds_dense(m, n, m, a.data_ptr(), _VT[a.dtype])
+    d._keep = a
+    return d
 
 
 def make_opts(k, p=0, tol=0.0, maxit=0, precision=SVDS_PREC_FP64, seed=0, v0=None, flags=0,
               stream=None) -> svds_opts:
-    return svds_opts(k, p, tol, maxit, precision, seed, None if v0 is None else v0.data_ptr(),
-                     _stream(stream), flags)
+    """Solver options; the struct holds a reference to the device tensor v0
+    (see make_dense)."""
+    o = svds_opts(k, p, tol, maxit, precision, seed, None if v0 is None else v0.data_ptr(),
+                  _stream(stream), flags)
+    o._keep = v0
+    return o
 
 
 def _outputs(m, n, k, device):
@@ -213,7 +227,7 @@ class Plan:
     """svds_plan_create_* / svds_plan_execute / svds_plan_destroy."""
 
     def __init__(self, A, opts: svds_opts):
-        self._A = A      # keep the struct (and its tensors, held by the caller) alive
+        self._A = A      # keep the struct (and the tensors it holds) alive
         self._opts = opts
         self.m, self.n, self.k = A.m, A.n, opts.k
         h = C.c_void_p()
@@ -364,6 +378,19 @@ def svds_op_small_svd(T: torch.Tensor, p: int, k: int, tol: float, stream=None):
     _check(lib.svds_op_small_svd(p, k, tol, _ptr(T), _ptr(Uk), _ptr(Vext), _ptr(sig), _ptr(res), _ptr(rho),
                                  flags, _stream(stream)), "svds_op_small_svd")
     return Uk, Vext, sig, res, rho, list(flags)
+
+
+def svds_op_harmonic_basis(T: torch.Tensor, p: int, k: int, stream=None):
+    """T: (p+1) x (p+1) row-major FP64 device tensor (only read).  Returns
+    QC ((k+1) x (p+1): row j = column j of Q_C), QM (k x p: row j = column j
+    of Q_M) and R (k x k)."""
+    dev = T.device
+    QC = torch.empty((k + 1, p + 1), dtype=torch.float64, device=dev)
+    QM = torch.empty((k, p), dtype=torch.float64, device=dev)
+    R = torch.empty((k, k), dtype=torch.float64, device=dev)
+    _check(lib.svds_op_harmonic_basis(p, k, _ptr(T), _ptr(QC), _ptr(QM), _ptr(R), _stream(stream)),
+           "svds_op_harmonic_basis")
+    return QC, QM, R
 
 
 SVDS_ROTATE_VECTOR = 256
