@@ -304,6 +304,37 @@ PAPER_TABLE2_MKL16_S = {"sparse1": 2.14, "sparse2": 1.24, "sparse3": 1.33,
                         "dense1": 16.5, "dense2": 10.7, "dense3": 10.2}
 
 
+def smallest_harmonic(S, inputs, np, torch):
+    """The k = 4 smallest triplets (p = 20, tol = 1e-10, at most 3000 cycles)
+    of square matrices with six clustered small values 1e-4 (1 + 0.01 i) below
+    a bulk in [0.5, 1], five nonzeros per row: plain Ritz restarts
+    (SVDS_FLAG_SMALLEST) against harmonic-Ritz restarts (+ SVDS_FLAG_HARMONIC),
+    one timed solve each after a warm-up of the harmonic one."""
+    out = {}
+    for N, seed in ((1000, 1), (2000, 3)):
+        sig = np.concatenate([1e-4 * (1 + 0.01 * np.arange(6)), np.linspace(0.5, 1.0, N - 6)])
+        A = inputs.prescribed_sparse(N // 5, 5, sig, seed=seed)
+        exact = np.sort(sig)[:4]
+        Ad, keep = S.csr_to_device(A)
+        v0d = torch.from_numpy(inputs.start_vector(N, 23)).cuda()
+        res = {}
+        for name, f in (("harmonic", S.SVDS_FLAG_SMALLEST | S.SVDS_FLAG_HARMONIC), ("plain", S.SVDS_FLAG_SMALLEST)):
+            if name == "harmonic":
+                S.svds_csr_solve(Ad, S.make_opts(4, 20, 1e-10, 3000, v0=v0d, flags=f))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = S.svds_csr_solve(Ad, S.make_opts(4, 20, 1e-10, 3000, v0=v0d, flags=f))
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            s = r.S.cpu().numpy()
+            res[name] = {"ms": round(t * 1e3, 2), "cycles": r.info["cycles"], "converged": r.info["nconv"] == 4,
+                         "sigma_rel_err_vs_exact": float(np.max(np.abs(s - exact) / exact))}
+        out[f"sparse_{N}x{N}_k4_p20"] = dict(res, cycles_ratio=round(res["plain"]["cycles"] /
+                                                                     res["harmonic"]["cycles"], 2))
+        log(f"smallest {N}: {out[f'sparse_{N}x{N}_k4_p20']}")
+    return out
+
+
 def paper_suite(S, inputs, np, torch, dense: bool):
     """Sparse1-3 (40,000 x 40,000, 5 nnz/row) and, with ``dense``, Dense1-3
     (10,000 x 10,000) of Sec. 3.1 at the paper's shape and settings; best of
@@ -404,6 +435,8 @@ def main():
     ap.add_argument("--no-selective", action="store_true", help="skip the selective re-orthogonalization run")
     ap.add_argument("--no-paper-dense", action="store_true",
                     help="leave Dense1-3 (10,000 x 10,000) out of the paper suite")
+    ap.add_argument("--no-harmonic", action="store_true",
+                    help="skip the smallest-triplet runs (plain vs harmonic-Ritz restarts)")
     ap.add_argument("--no-config1", action="store_true",
                     help="skip the 2000 x 1000 sparse workload (k=10, p=30, tol=1e-10)")
     ap.add_argument("--profile-run", action="store_true",
@@ -597,6 +630,11 @@ def main():
         log("2000 x 1000 sparse workload ...")
         c1 = config1(S, inputs, np, torch, cpu=not args.no_cpu and rank == 0)
 
+    harm = None
+    if not args.no_harmonic:
+        log("smallest triplets, plain vs harmonic restarts ...")
+        harm = smallest_harmonic(S, inputs, np, torch)
+
     suite = None
     if not args.no_suite:
         suite = paper_suite(S, inputs, np, torch, not args.no_paper_dense)
@@ -618,7 +656,7 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "mixed_vs_fp64": mixed,
            "batched_vs_looped": batched, "paper_suite": suite, "selective_reorth": sel,
            "partial_reorth": part, "early_stop": early,
-           "config_2000x1000": c1, "host_cpu": host_cpu(),
+           "config_2000x1000": c1, "smallest_harmonic": harm, "host_cpu": host_cpu(),
            "step_ms": {"execute": round(ms_exec, 2), "create_and_destroy": round(ms_step - ms_exec, 2)}}
     print(json.dumps(out), flush=True)
 
