@@ -392,6 +392,59 @@ def paper_suite(S, inputs, np, torch, dense: bool):
     return out
 
 
+def gather_ceiling(S, inputs, np, torch):
+    """The sparse products of the Zipf workload against the gather-copy
+    reference over the same index streams (svds_op_gather_copy): A v gathers
+    v through A's column indices; A^T u, in the column-panel form the solver
+    runs, gathers u through the row indices of each of 8 row panels of A,
+    panel g on XCD g.  Each stream also in a chunk-sorted order (the indices
+    of every 2048-entry chunk sorted: the same entries, gathered in address
+    order).  Two plain solves run first, so a kernel trace of this section
+    holds the products' own durations (per-dispatch timing events are left
+    off: they change the caches the products find).  Prints one line per
+    reference (no JSON)."""
+    import scipy.sparse as sp
+    A = inputs.config_matrix(2)
+    m, n = A.m, A.n
+    Ad, keep = S.csr_to_device(A)
+    v0 = torch.from_numpy(inputs.start_vector(n, inputs.CONFIG_SEEDS[2] + 1)).cuda()
+    for _ in range(2):
+        r = S.svds_csr_solve(Ad, S.make_opts(WORKLOAD["k"], WORKLOAD["p"], WORKLOAD["tol"], 2000, v0=v0))
+        torch.cuda.synchronize()
+        print(f"solve: {r.info['ms_total']:.1f} ms, {r.info['n_spmv']} + {r.info['n_spmvT']} products", flush=True)
+    nnz = A.nnz
+    print(f"{nnz} nonzeros", flush=True)
+    csr = sp.csr_matrix((A.val, A.col_idx, A.row_ptr), shape=(m, n))
+    rpp = -(-m // 8)
+    parts, seg = [], [0]
+    for g in range(8):
+        t = csr[g * rpp:min(m, (g + 1) * rpp)].T.tocsr()
+        parts.append(t.indices.astype(np.int32) + g * rpp)
+        seg.append(seg[-1] + t.nnz)
+    panel_idx = np.concatenate(parts)
+
+    def chunk_sorted(ix, seg_):
+        out = ix.copy()
+        for a, b in zip(seg_[:-1], seg_[1:]):
+            for c0 in range(a, b, 2048):
+                out[c0:min(b, c0 + 2048)].sort()
+        return out
+
+    xv = torch.rand(n, dtype=torch.float64, device="cuda")
+    xu = torch.rand(m, dtype=torch.float64, device="cuda")
+    cases = [("A v, column indices of A", A.col_idx.astype(np.int32), xv, 1, None),
+             ("A v, chunk-sorted", chunk_sorted(A.col_idx.astype(np.int32), [0, nnz]), xv, 1, None),
+             ("A^T u, 8 row panels (XCD g: panel g)", panel_idx, xu, 8, seg),
+             ("A^T u, 8 row panels, chunk-sorted", chunk_sorted(panel_idx, seg), xu, 8, seg)]
+    for name, ix, x, nseg, sg in cases:
+        it = torch.from_numpy(np.ascontiguousarray(ix)).cuda()
+        out, _ = S.svds_op_gather_copy(it, x, nseg, sg, reps=3)
+        assert torch.equal(out, x[it.long()])
+        _, t = S.svds_op_gather_copy(it, x, nseg, sg, out=out, reps=50)
+        us = t * 1e3
+        print(f"gather copy  : {name}: {us:.2f} us per launch, {nnz / us / 1e3:.1f} G entries/s", flush=True)
+
+
 def profile_section(which, S, inputs, np, torch):
     """Two solves of one workload for a kernel trace (see --profile-section)."""
     if which == "dense":
@@ -413,6 +466,8 @@ def profile_section(which, S, inputs, np, torch):
             r = S.svds_csr_solve(Ad, S.make_opts(c["k"], c["p"], c["tol"], c["maxit"], v0=v0))
             torch.cuda.synchronize()
             log(f"sparse2: {r.info['ms_total']:.1f} ms, cycles {r.info['cycles']}")
+    elif which == "gather":
+        gather_ceiling(S, inputs, np, torch)
     else:
         As = inputs.config_matrix(5)
         dev = [S.csr_to_device(A) for A in As]
@@ -441,10 +496,11 @@ def main():
                     help="skip the 2000 x 1000 sparse workload (k=10, p=30, tol=1e-10)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
-    ap.add_argument("--profile-section", choices=["dense", "batched", "sparse2"],
+    ap.add_argument("--profile-section", choices=["dense", "batched", "sparse2", "gather"],
                     help="only two solves of one other workload, for a rocprofv3 kernel trace: the "
                          "20000 x 10000 BF16 dense matrix (FP64 then mixed), the 256-problem batch (FP64), "
-                         "or the paper's Sparse2 (40,000 x 40,000, k=100, p=300); no JSON")
+                         "or the paper's Sparse2 (40,000 x 40,000, k=100, p=300); 'gather': the Zipf "
+                         "workload's products against the gather-copy reference; no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver does not "

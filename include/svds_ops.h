@@ -121,6 +121,21 @@ int svds_op_rotate(int64_t L, int32_t pc, int32_t kc, const void *B, int64_t ldb
  * counter (b_lo, b_hi, q, 0) and key (seed_lo, seed_hi). */
 int svds_op_philox_normal(int64_t L, uint64_t seed, uint32_t stream_id, double *out, void *stream);
 
+/* Gather copy out[i] = x[idx[i]], i < L (idx int32, x and out FP64,
+ * device): the gather-rate reference for the sparse products.  Per entry it
+ * streams what the CSR product streams (a 4-byte index in, an 8-byte value:
+ * here out instead of A's value) plus the gather of x, without the product's
+ * row sums.  seg (HOST, nseg + 1 offsets from 0 to L, non-decreasing; NULL =
+ * nseg equal parts) cuts the entries into nseg <= 64 segments; workgroup b
+ * takes chunk b / nseg (2048 entries) of segment b % nseg, so with nseg = 8
+ * the workgroups of one XCD gather one segment only, as those of the
+ * column-panel product A^T y do.  Every idx[i] must index x: not checked.
+ * The kernel runs reps >= 1 times back to back; *ms_per_launch (host, may
+ * be NULL) receives their average duration from events around the
+ * launches.  Synchronous on `stream`; EINVAL on bad arguments. */
+int svds_op_gather_copy(int64_t L, const int32_t *idx, const double *x, double *out, int32_t nseg,
+                        const int64_t *seg, int32_t reps, double *ms_per_launch, void *stream);
+
 /* Plain device copy dst = src (L doubles): the bandwidth reference used to
  * calibrate hardware traffic counters. */
 int svds_op_copy_f64(int64_t L, const double *src, double *dst, void *stream);

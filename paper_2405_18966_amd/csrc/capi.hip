@@ -298,6 +298,50 @@ extern "C" int svds_op_philox_normal(int64_t L, uint64_t seed, uint32_t stream_i
   SVDS_ABI_CATCH
 }
 
+extern "C" int svds_op_gather_copy(int64_t L, const int32_t *idx, const double *x, double *out, int32_t nseg,
+                                   const int64_t *seg, int32_t reps, double *ms_per_launch, void *stream) {
+  SVDS_ABI_TRY
+  if (L < 1 || !idx || !x || !out || nseg < 1 || nseg > 64 || reps < 1) return SVDS_EINVAL;
+  std::vector<int64_t> hs(nseg + 1);
+  if (seg) {
+    for (int g = 0; g <= nseg; ++g) hs[g] = seg[g];
+    if (hs[0] != 0 || hs[nseg] != L) return SVDS_EINVAL;
+    for (int g = 0; g < nseg; ++g)
+      if (hs[g + 1] < hs[g]) return SVDS_EINVAL;
+  } else {
+    for (int g = 0; g <= nseg; ++g) hs[g] = L * g / nseg;
+  }
+  int64_t chunks = 0;
+  for (int g = 0; g < nseg; ++g) chunks = std::max<int64_t>(chunks, ceil_div(hs[g + 1] - hs[g], GATHER_CHUNK));
+  if (chunks * nseg > INT32_MAX) return SVDS_EUNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Scratch d;
+  HIP_TRY(hipMalloc(&d.p, sizeof(int64_t) * (nseg + 1)));
+  HIP_TRY(hipMemcpyAsync(d.p, hs.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, st));
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  struct Ev {
+    hipEvent_t *e;
+    ~Ev() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+  HIP_TRY(hipEventCreate(&ev[0]));
+  HIP_TRY(hipEventCreate(&ev[1]));
+  HIP_TRY(hipEventRecord(ev[0], st));
+  for (int r = 0; r < reps && chunks > 0; ++r)
+    hipLaunchKernelGGL(gather_copy_kernel, dim3(static_cast<unsigned>(chunks * nseg)), dim3(256), 0, st, idx, x,
+                       out, nseg, static_cast<const int64_t *>(d.p));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(ev[1], st));
+  HIP_TRY(hipStreamSynchronize(st));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  if (ms_per_launch) *ms_per_launch = static_cast<double>(ms) / reps;
+  return SVDS_OK;
+  SVDS_ABI_CATCH
+}
+
 extern "C" int svds_op_copy_f64(int64_t L, const double *src, double *dst, void *stream) {
   SVDS_ABI_TRY
   if (L < 1 || !src || !dst) return SVDS_EINVAL;

@@ -220,6 +220,39 @@ static __global__ void copy_f64_kernel(int64_t L, const double *__restrict__ src
   if (i < L) dst[i] = src[i];
 }
 
+// Gather copy out[i] = x[idx[i]] (gather-rate reference for the sparse
+// products: per entry it streams the same 12 bytes as the CSR product, a
+// 4-byte index and an 8-byte value, plus the gather).  Entries are cut into
+// segments (seg[0..nseg]) and each segment into chunks of GATHER_CHUNK; block
+// b takes chunk b / nseg of segment b % nseg, so with nseg = 8 the blocks of
+// one XCD gather one segment only, as the column-panel product's do.  Each
+// thread keeps its 8 index loads, then its 8 gathers, in flight.
+constexpr int GATHER_CHUNK = 2048;
+static __global__ __launch_bounds__(256) void gather_copy_kernel(const int32_t *__restrict__ idx,
+                                                                 const double *__restrict__ x,
+                                                                 double *__restrict__ out, int nseg,
+                                                                 const int64_t *__restrict__ seg) {
+  const int g = static_cast<int>(blockIdx.x % nseg);
+  const int64_t c = blockIdx.x / nseg;
+  const int64_t start = seg[g] + c * GATHER_CHUNK;
+  const int64_t end = min(start + GATHER_CHUNK, seg[g + 1]);
+  if (start >= end) return;
+  int32_t id[8];
+  double v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t i = start + threadIdx.x + u * 256;
+    id[u] = i < end ? idx[i] : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) v[u] = id[u] >= 0 ? x[id[u]] : 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t i = start + threadIdx.x + u * 256;
+    if (i < end) out[i] = v[u];
+  }
+}
+
 // Sign convention: flip (u_j, v_j) so the entry of v_j of largest magnitude
 // (lowest index on ties) is positive.  Three steps over V (n x k):
 //  absmax_partials_kernel  grid (nslab, k): max |v| and its first index per

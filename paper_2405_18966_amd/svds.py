@@ -113,6 +113,7 @@ def _load():
         "svds_op_cgs2_noalloc": (i32, [i64, i32, vp, i64, vp, vp, P(d), i32, vp]),
         "svds_op_small_svd": (i32, [i32, i32, d, vp, vp, vp, vp, vp, vp, P(i32), vp]),
         "svds_op_harmonic_basis": (i32, [i32, i32, vp, vp, vp, vp, vp]),
+        "svds_op_gather_copy": (i32, [i64, vp, vp, vp, i32, vp, i32, P(d), vp]),
         "svds_op_rotate": (i32, [i64, i32, i32, vp, i64, i32, vp, i64, vp, i64, vp]),
         "svds_op_philox_normal": (i32, [i64, u64, C.c_uint32, vp, vp]),
         "svds_op_copy_f64": (i32, [i64, vp, vp, vp]),
@@ -391,6 +392,20 @@ def svds_op_harmonic_basis(T: torch.Tensor, p: int, k: int, stream=None):
     _check(lib.svds_op_harmonic_basis(p, k, _ptr(T), _ptr(QC), _ptr(QM), _ptr(R), _stream(stream)),
            "svds_op_harmonic_basis")
     return QC, QM, R
+
+
+def svds_op_gather_copy(idx: torch.Tensor, x: torch.Tensor, nseg: int = 1, seg=None, out=None, reps: int = 1,
+                        stream=None):
+    """out[i] = x[idx[i]]; seg: host sequence of nseg + 1 offsets (or None).
+    Returns (out, average ms per launch over `reps` back-to-back launches)."""
+    assert idx.dtype == torch.int32 and x.dtype == torch.float64
+    if out is None:
+        out = torch.empty(idx.numel(), dtype=torch.float64, device=x.device)
+    sp = None if seg is None else (C.c_int64 * (nseg + 1))(*[int(v) for v in seg])
+    ms = C.c_double()
+    _check(lib.svds_op_gather_copy(idx.numel(), _ptr(idx), _ptr(x), _ptr(out), nseg, sp, reps, C.byref(ms),
+                                   _stream(stream)), "svds_op_gather_copy")
+    return out, ms.value
 
 
 SVDS_ROTATE_VECTOR = 256

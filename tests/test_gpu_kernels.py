@@ -500,3 +500,22 @@ def test_dense_block_residuals_of_exact_triplets(S):
     e2 = np.linalg.norm(A.T @ Uf[:, :k] - Vtf[:k].T * sf[:k], axis=0)
     assert np.abs(r1.cpu().numpy() - e1).max() <= 1e-13 * sf[0]
     assert np.abs(r2.cpu().numpy() - e2).max() <= 1e-13 * sf[0]
+
+
+@pytest.mark.parametrize("L,nseg,uneven", [(1, 1, False), (5000, 1, False), (123457, 8, True), (40000, 3, False)])
+def test_gather_copy_matches_indexing(S, L, nseg, uneven):
+    """The gather-rate reference: out[i] = x[idx[i]] bit for bit, over
+    segments that are uneven, empty or shorter than a chunk."""
+    import torch
+    print(f"gather copy L={L} nseg={nseg}", flush=True)
+    rng = np.random.default_rng(L)
+    x = torch.from_numpy(rng.standard_normal(7001)).cuda()
+    idx = torch.from_numpy(rng.integers(0, 7001, L).astype(np.int32)).cuda()
+    seg = None
+    if uneven:
+        cuts = np.sort(rng.integers(0, L, nseg - 1))
+        cuts[1] = cuts[0]  # an empty segment
+        seg = [0] + [int(c) for c in cuts] + [L]
+    out, ms = S.svds_op_gather_copy(idx, x, nseg, seg, reps=2)
+    torch.cuda.synchronize()
+    assert torch.equal(out, x[idx.long()]) and ms > 0
