@@ -21,7 +21,7 @@ namespace svds {
 
 constexpr int CGS_THREADS = 256;
 constexpr int CGS_PCG = 8;      // columns per block column-group in cgs_proj
-constexpr int CGS_FUSED_MAXJ = 160;  // widest basis of the fused pass (16 waves x 10 columns)
+constexpr int CGS_FUSED_MAXJ = 320;  // widest basis of the fused pass (16 waves x 20 columns)
 constexpr int CGS_MAXJ = 1024;  // largest basis width supported
 constexpr int CGS_MAX_SLABS = 1024;  // partials per column (cgs_proj / cgs_upd_proj)
 constexpr int NORM_MAX_BLOCKS = 2048;
@@ -162,8 +162,9 @@ __global__ __launch_bounds__(CGS_THREADS) void cgs_proj_kernel(const T *__restri
 // cross-wave row sums go through a double-buffered LDS array (one barrier per
 // tile).  Narrow register tiles (CPW <= 12 with one row per lane) keep
 // occupancy high: measured on MI355X, two rows per lane with 12-16 columns
-// per wave stream at a third of the rate or less.
-// Bases wider than 16 * CPW use a separate update pass plus cgs_proj instead.
+// per wave stream at a third of the rate or less.  Bases of 161-320 columns
+// take CPW = 20 without prefetch (one 16-wave block per CU, as with
+// CPW = 10); wider ones use a separate update pass plus cgs_proj instead.
 // part: [j][nblk]; with normw1 also the partials of |w1|^2 as column j.
 // MASK: only the columns with cmask[c] != 0 are read (the others have h1 = 0
 // and get zero partials).
@@ -258,6 +259,73 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict_
   if (normw1 && wv == 0) {
     const T s = wave_sum(nw1);
     if (lane == 0) part[static_cast<int64_t>(j) * nblk + blk] = s;
+  }
+}
+
+// The fused pass for bases of 161-320 columns: 20 columns per wave, one row
+// per lane, each tile's 20 loads issued together (no prefetch of the next
+// tile, so the 20 columns and 20 accumulators fit the 128 VGPRs a 16-wave
+// block may use).  Same outputs as cgs_upd_proj_kernel.
+template <typename T, bool MASK = false>
+__global__ __launch_bounds__(1024) void cgs_upd_proj_wide_kernel(const T *__restrict__ Q, int64_t ldq, int64_t L,
+                                                                int j, const T *__restrict__ w,
+                                                                const T *__restrict__ h1, T *__restrict__ w1out,
+                                                                T *__restrict__ part, int normw1,
+                                                                const int *__restrict__ cmask) {
+  constexpr int CPW = 20;
+  __shared__ T sh_h[CGS_MAXJ];
+  __shared__ T xch[2][16][WAVE];
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int NW = blockDim.x / WAVE;
+  const int nblk = gridDim.x, blk = blockIdx.x;
+  for (int c = tid; c < j; c += blockDim.x) sh_h[c] = h1[c];
+  const int c0 = wv * CPW;
+  const int nc = max(0, min(CPW, j - c0));
+  for (int c = j + tid; c < NW * CPW; c += blockDim.x) sh_h[c] = T(0);  // padding columns
+  unsigned en = 0;  // bit c: column c0 + c is read
+  for (int c = 0; c < nc; ++c)
+    if (!MASK || cmask[c0 + c] != 0) en |= 1u << c;
+  en = __builtin_amdgcn_readfirstlane(en);
+  __syncthreads();
+  const int64_t tiles = ceil_div(L, static_cast<int64_t>(WAVE));
+  const int64_t per = ceil_div(tiles, nblk);
+  const int64_t t0 = static_cast<int64_t>(blk) * per;
+  const int64_t t1 = min(tiles, t0 + per);
+  const T *Qc = Q + c0 * ldq;
+  T acc[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) acc[c] = 0;
+  T nw1 = 0;
+  int buf = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t r = t * WAVE + lane;
+    const bool ok = r < L;
+    T q[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) q[c] = (ok && ((en >> c) & 1u)) ? Qc[c * ldq + r] : T(0);
+    const T wr = ok ? w[r] : T(0);
+    T s = 0;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) s += q[c] * sh_h[c0 + c];
+    xch[buf][wv][lane] = s;
+    __syncthreads();
+    T u = 0;
+    for (int v = 0; v < NW; ++v) u += xch[buf][v][lane];
+    const T w1 = ok ? wr - u : T(0);
+    if (wv == 0 && ok) w1out[r] = w1;
+    if (normw1 && wv == 0) nw1 += w1 * w1;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) acc[c] += q[c] * w1;
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const T sc = wave_sum(acc[c]);
+    if (lane == 0 && c < nc) part[static_cast<int64_t>(c0 + c) * nblk + blk] = sc;
+  }
+  if (normw1 && wv == 0) {
+    const T sc = wave_sum(nw1);
+    if (lane == 0) part[static_cast<int64_t>(j) * nblk + blk] = sc;
   }
 }
 
@@ -725,8 +793,12 @@ inline bool cgs_tile_upd_ok(int64_t L, int j, int rows_per_lane) {
 // path).  FP64: 8 up to j = 80, then 10 (both one row per lane with register
 // prefetch; measured on MI355X, 10 columns are 2-7% faster from j ~ 90 on).
 // FP32: 8 up to 128, then 10 with 16-byte rows.
+// Columns per wave of the fused pass: 8, 10, or 20 (no register prefetch:
+// with it 20 columns would not fit the 128 VGPRs of a 16-wave block) for
+// 160 < j <= 320.
 inline int cgs_fused_cpw(int j, int elem_bytes) {
   if (j > CGS_FUSED_MAXJ) return 0;
+  if (j > 160) return 20;
   return j <= (elem_bytes == 8 ? 80 : 128) ? 8 : 10;
 }
 inline int cgs_updnorm_blocks(int64_t L) {

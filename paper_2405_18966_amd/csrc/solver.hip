@@ -471,8 +471,12 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
 // w is the input; w1 is scratch; out receives the re-orthogonalized vector.
 // ---------------------------------------------------------------------------
 template <typename TB>
+// q_alg = false: this read of Q repeats one the same CGS2 already counted
+// (the split second pass of a basis wider than CGS_FUSED_MAXJ), so only the
+// vector counts as algorithmic bytes.
 static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int64_t L, int j,
-                           const TB *w, TB *h, int kc, int normw = 0, const int *cmask = nullptr) {
+                           const TB *w, TB *h, int kc, int normw = 0, const int *cmask = nullptr,
+                           bool q_alg = true) {
   const double sb = sizeof(TB);
   int nslab, ngc;
   cgs_proj_shape(L, j, nslab, ngc);
@@ -496,7 +500,7 @@ static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int
   LAUNCH_CHECK();
   // with a column mask the columns read are counted at the end of the solve
   const double jc = cmask ? 0.0 : static_cast<double>(j);
-  ACC_AFTER(kc, sb * L * jc + sb * L, 2.0 * L * jc);
+  ACC_AFTER(kc, sb * L * (q_alg ? jc : 0.0) + sb * L, 2.0 * L * jc);
   // h[0:j], and with normw h[j] = |w|^2
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
   hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j + normw, 4)), dim3(256), 0, P->stream, part,
@@ -601,7 +605,13 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
       // one row per lane with register prefetch (two rows per lane raise
       // register pressure); FP32 bases with 10 columns take 16-byte rows
       const dim3 g(nb), b(nw * WAVE);
-      if (cmask && cpw == 8)
+      if (cmask && cpw == 20)
+        klaunch(P->acc, true, true, cgs_upd_proj_wide_kernel<TB, true>, g, b, 0, P->stream, Q, ldq, L, j, w, h1, w1,
+                part, sel, cmask);
+      else if (cpw == 20)
+        klaunch(P->acc, true, true, cgs_upd_proj_wide_kernel<TB>, g, b, 0, P->stream, Q, ldq, L, j, w, h1, w1, part,
+                sel, cmask);
+      else if (cmask && cpw == 8)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 8, true, 1, true>, g, b, 0, P->stream, Q, ldq, L, j, w,
                 h1, w1, part, sel, cmask);
       else if (cmask && sizeof(TB) == 8)
@@ -640,7 +650,8 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
       LAUNCH_CHECK();
       const double jc = cmask ? 0.0 : static_cast<double>(j);
       ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * jc + 2 * sb * L, 2.0 * L * jc);
-      if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w1, h2, SVDS_KC_CGS_UPDPROJ, sel, cmask))) return rc;
+      if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w1, h2, SVDS_KC_CGS_UPDPROJ, sel, cmask, false)))
+        return rc;
     }
     src = w1;
   }

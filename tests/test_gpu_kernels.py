@@ -237,8 +237,8 @@ def test_transpose_bit_exact(S, maker):
 # short vectors (<= 2048 row tiles, j <= 256) take the tile-per-block update,
 # longer ones or wider bases the row-per-thread update: both, at the limits
 @pytest.mark.parametrize("L,j", [(1000, 0), (1000, 1), (1000, 16), (1000, 17), (2049, 100),
-                                 (100003, 150), (5000, 256), (6000, 300), (70, 60),
-                                 (262144, 200), (400000, 60)])
+                                 (100003, 150), (5000, 161), (5000, 256), (6000, 300), (70, 60),
+                                 (262144, 200), (400000, 60), (4000, 320), (5000, 321), (3000, 700)])
 def test_cgs2_matches_oracle(S, L, j):
     import torch
     rng = np.random.default_rng(L + j)

@@ -45,7 +45,7 @@ def _case(name):
         d = np.zeros(400)
         d[:40] = np.repeat(np.arange(10, 0, -1), 4)
         return inputs.diag_matrix(500, 400, d), 8, 24, 1e-10, np.sort(d)[::-1]
-    if name == "wide":  # j > 160: the split update + projection path
+    if name == "wide":  # j > 160: the 20-column fused second pass
         A = inputs.sparse_uniform(6000, 4000, 60000, seed=602)
         return A, 60, 180, 1e-10, None
     if name == "zipf":  # long vectors: row-per-thread update kernel
