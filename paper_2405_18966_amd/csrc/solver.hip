@@ -25,6 +25,7 @@
 #include "kernels_misc.hpp"
 #include "kernels_dense.hpp"
 #include "kernels_batch.hpp"
+#include "kernels_small.hpp"
 
 namespace svds {
 
@@ -812,7 +813,51 @@ static int early_drain(svds_plan *P) {
 // On entry: V[:, i0] is in the basis; the unnormalized u_{i0} is in bu with
 // reciprocal norm xs_u and T(i0, i0) set.
 // ---------------------------------------------------------------------------
+// Small CSR problems (vectors of at most LZS_MAX_L entries, at most
+// LZS_MAX_NNZ nonzeros, both bases within LZS_MAX_BASIS_BYTES, FP64 bases,
+// full re-orthogonalization) run a cycle's
+// Lanczos steps in one workgroup (lanczos_small_kernel); the early stop keeps
+// the step-by-step launches, whose per-step events it needs.
+static bool small_lanczos_ok(const svds_plan *P) {
+  const Operator &op = P->op;
+  return !op.dense && op.npanel == 1 && op.trp && !P->partial && !P->selective &&
+         std::max(op.m, op.n) <= LZS_MAX_L && op.nnz <= LZS_MAX_NNZ &&
+         8 * (op.m + op.n) * (P->p + 1) <= LZS_MAX_BASIS_BYTES;
+}
+
+static int lanczos_small(svds_plan *P, Lanczos<double> &Lz, int i0) {
+  const Operator &op = P->op;
+  const Small &s = P->sc;
+  const int p = P->p;
+  const size_t lds = sizeof(double) * static_cast<size_t>(std::max(op.m, op.n));
+  ACC_BEFORE(SVDS_KC_OTHER);
+  if (op.vt == SVDS_F64)
+    hipLaunchKernelGGL(lanczos_small_kernel<double>, dim3(1), dim3(LZS_THREADS), lds, P->stream,
+                       static_cast<int>(op.m), static_cast<int>(op.n), op.rp, op.ci,
+                       static_cast<const double *>(op.val), op.trp, op.tci, static_cast<const double *>(op.tval),
+                       Lz.U[Lz.cur], Lz.ldu, Lz.V[Lz.cur], Lz.ldv, s.T, p + 1, i0, p, Lz.bu, Lz.bv, s.xs_u,
+                       s.xs_v, s.sigma_est, s.bd, P->opts.seed);
+  else
+    hipLaunchKernelGGL(lanczos_small_kernel<float>, dim3(1), dim3(LZS_THREADS), lds, P->stream,
+                       static_cast<int>(op.m), static_cast<int>(op.n), op.rp, op.ci,
+                       static_cast<const float *>(op.val), op.trp, op.tci, static_cast<const float *>(op.tval),
+                       Lz.U[Lz.cur], Lz.ldu, Lz.V[Lz.cur], Lz.ldv, s.T, p + 1, i0, p, Lz.bu, Lz.bv, s.xs_u,
+                       s.xs_v, s.sigma_est, s.bd, P->opts.seed);
+  LAUNCH_CHECK();
+  const int nv = p - i0, nu = p - i0 - 1;  // A^T u and A v products of the steps
+  P->n_spmvT += nv;
+  P->n_spmv += nu;
+  // algorithmic bytes: each product streams A once; each CGS2 reads its basis three times
+  const double vb = op.vt == SVDS_F64 ? 8.0 : 4.0;
+  double bytes = (nv + nu) * (12.0 + vb) * op.nnz;
+  for (int i = i0; i < p; ++i) bytes += 24.0 * op.n * (i + 1) + (i + 1 < p ? 24.0 * op.m * (i + 1) : 0.0);
+  ACC_AFTER(SVDS_KC_OTHER, bytes, 2.0 * bytes / 8.0);
+  return SVDS_OK;
+}
+
 template <typename TB> static int lanczos(svds_plan *P, Lanczos<TB> &Lz, int i0, bool early = false) {
+  if constexpr (std::is_same<TB, double>::value)
+    if (!early && small_lanczos_ok(P)) return lanczos_small(P, Lz, i0);
   const int p = P->p;
   const int64_t m = Lz.m, n = Lz.n;
   const int ld = p + 1;
