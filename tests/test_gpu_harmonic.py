@@ -172,3 +172,26 @@ def test_harmonic_flag_validation(S):
     with pytest.raises(S.SvdsError) as e:
         S.svds_csr_solve_batched([Ad, Ad], S.make_opts(4, 12, 1e-10, 100, flags=H | S.SVDS_FLAG_SMALLEST))
     assert e.value.code == S.SVDS_EUNSUPPORTED
+
+
+def test_harmonic_with_early_stop(S):
+    """The early stop ends a cycle at the first dimension where the Ritz
+    triplets of T(1:j, 1:j) pass eq. (4); the cycles that do not end early
+    restart with harmonic Ritz vectors as before."""
+    import torch
+    print("harmonic + early stop, clustered 1000x1000 k=4 p=20", flush=True)
+    A, sig = _cluster_case(1000, 1)
+    Ad, keep = S.csr_to_device(A)
+    v0 = torch.from_numpy(inputs.start_vector(1000, 23)).cuda()
+    f = S.SVDS_FLAG_SMALLEST | S.SVDS_FLAG_HARMONIC
+    a = S.svds_csr_solve(Ad, S.make_opts(4, 20, 1e-10, 3000, v0=v0, flags=f))
+    b = S.svds_csr_solve(Ad, S.make_opts(4, 20, 1e-10, 3000, v0=v0, flags=f | S.SVDS_FLAG_EARLY_STOP))
+    torch.cuda.synchronize()
+    assert a.status == 0 and b.status == 0 and b.info["nconv"] == 4
+    exact = np.sort(sig)[:4]
+    np.testing.assert_allclose(b.S.cpu().numpy(), exact, rtol=1e-10)
+    assert b.info["early_checks"] > 0 and b.info["lanczos_dim_last"] <= 20
+    assert b.info["cycles"] <= a.info["cycles"] + 2
+    U, V, s = b.U.cpu().numpy(), b.V.cpu().numpy(), b.S.cpu().numpy()
+    r1, r2 = svds_ref.explicit_residuals(as_operator(A), U, s, V)
+    assert (r1 / s).max() <= 1e-9 and (r2 / s).max() <= 1e-9
