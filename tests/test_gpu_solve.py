@@ -60,8 +60,11 @@ def _counts_ok(info, p, k):
     assert info["n_spmvT"] == p + R * (p - k)
 
 
-@pytest.mark.parametrize("case", ["w1", "tall", "wide", "square_small"])
+@pytest.mark.parametrize("case", ["w1", "tall", "wide", "square_small", "lds_max"])
 def test_parity_with_oracle(S, case):
+    """w1 and tall take the step-by-step launches, wide, square_small and
+    lds_max the one-workgroup cycles (lds_max: the longest vector those hold
+    in LDS, 6144 entries)."""
     if case == "w1":
         A = inputs.config_matrix(1)
         k, p, tol = 10, 30, 1e-10
@@ -74,6 +77,10 @@ def test_parity_with_oracle(S, case):
         A = inputs.sparse_uniform(700, 3000, 30000, seed=5)
         k, p, tol = 5, 15, 1e-10
         v0 = inputs.start_vector(A.n, 6)
+    elif case == "lds_max":
+        A = inputs.sparse_uniform(6144, 200, 60000, seed=9)
+        k, p, tol = 3, 12, 1e-10
+        v0 = inputs.start_vector(A.n, 10)
     else:
         A = inputs.sparse_uniform(60, 60, 900, seed=7)
         k, p, tol = 3, 9, 1e-12
