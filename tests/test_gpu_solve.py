@@ -96,6 +96,57 @@ def test_parity_with_oracle(S, case):
     assert info["max_res_true"] <= 2 * tol and info["max_res_est"] < tol
 
 
+@pytest.mark.parametrize("case", ["ragged", "g21", "breakdowns", "zero"])
+def test_mid_size_cycles(S, case):
+    """Mid-size sparse problems past the one-workgroup limits (bases of 0.7
+    to 10.5 MB), in the step-by-step launches.  ragged: row counts that 64
+    does not divide; g21: 20,011 x 12,003 (10.5 MB of bases); breakdowns: a
+    diagonal matrix with six distinct values, whose Krylov space ends after a
+    few steps, so replacement vectors enter the basis; zero: every step breaks
+    down.  Same bar as the oracle parity cases."""
+    if case == "ragged":
+        A = inputs.sparse_uniform(2003, 997, 20000, seed=61)
+        k, p, tol, maxit = 10, 30, 1e-10, 3000
+    elif case == "g21":
+        A = inputs.sparse_uniform(20011, 12003, 200000, seed=63)
+        k, p, tol, maxit = 5, 40, 1e-10, 3000
+    elif case == "breakdowns":
+        d = np.repeat([6.0, 5.0, 4.0, 3.0, 2.0, 1.0], [3, 2, 2, 2, 2, 2988])
+        A = inputs.diag_matrix(3001, 2999, d)
+        k, p, tol, maxit = 8, 20, 1e-10, 200
+    else:
+        A = inputs.CSR(3000, 2000, np.zeros(3001, np.int32), np.zeros(0, np.int32), np.zeros(0))
+        k, p, tol, maxit = 2, 20, 1e-10, 3
+    v0 = inputs.start_vector(A.n, 62)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, tol, maxit, v0=v0)
+    if case == "zero":
+        assert np.all(Sg == 0) and st == 0 and info["breakdowns"] >= p
+        assert np.all(np.isfinite(Ug)) and np.all(np.isfinite(Vg))
+        return
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), k, p, tol, maxit, v0=v0)
+    assert st == 0 and info["converged"] == 1 and info_r.converged
+    if case == "breakdowns":
+        assert info["breakdowns"] > 0 and info_r.breakdowns > 0
+        np.testing.assert_allclose(Sg, np.sort(d)[::-1][:k], rtol=1e-12)
+        # values wholly inside the k: the same invariant subspaces
+        for val in (6.0, 5.0, 4.0):
+            cols = np.nonzero(np.abs(Sg - val) < 1e-9)[0]
+            colsr = np.nonzero(np.abs(Sr - val) < 1e-9)[0]
+            qg, _ = np.linalg.qr(Vg[:, cols])
+            qr, _ = np.linalg.qr(Vr[:, colsr])
+            assert np.linalg.norm(qg - qr @ (qr.T @ qg), 2) < 1e-9
+        # one of the two copies of 3: any unit vector of its subspace
+        assert np.linalg.norm(Vg[d != 3.0, k - 1]) < 1e-9
+    elif case == "g21":
+        np.testing.assert_allclose(Sg, Sr, rtol=1e-10)
+    else:
+        s_all = np.linalg.svd(as_operator(A).toarray(), compute_uv=False)
+        _compare(Ug, Sg, Vg, Ur, Sr, Vr, s_all, 1e-10, 10 * tol)
+    _invariants(A, Ug, Sg, Vg, tol)
+    _counts_ok(info, p, k)
+    assert abs(info["cycles"] - info_r.cycles) <= 1
+
+
 def test_parity_with_column_panel_transpose(S):
     """A long u (300,001 rows of A): the transposed products run in the
     column-panel form (two panels, power-law rows split into pieces).  Same
