@@ -89,7 +89,8 @@ enum {
   SVDS_FLAG_SELECTIVE_REORTH = 512, /* second CGS pass only when needed (below) */
   SVDS_FLAG_PARTIAL_REORTH = 1024,  /* omega-recurrence partial re-orth. (below) */
   SVDS_FLAG_EARLY_STOP = 2048,      /* eq. (4) test inside a cycle (below)        */
-  SVDS_FLAG_HARMONIC = 4096         /* harmonic-Ritz restarts, smallest (below)   */
+  SVDS_FLAG_HARMONIC = 4096,        /* harmonic-Ritz restarts, smallest (below)   */
+  SVDS_FLAG_EXPECT_BREAKDOWNS = 8192 /* wide breakdown repairs from step 1 (below) */
 };
 
 /* SVDS_FLAG_HARMONIC (with SVDS_FLAG_SMALLEST): restarts keep harmonic Ritz
@@ -111,6 +112,21 @@ enum {
  * SVDS_FLAG_SMALLEST or with SVDS_FLAG_SELECTIVE_REORTH /
  * SVDS_FLAG_PARTIAL_REORTH; EUNSUPPORTED for p > 1022 and in the batched
  * solver. */
+
+/* SVDS_FLAG_EXPECT_BREAKDOWNS: a breakdown (Alg. 1 steps 6 and 8 meet an
+ * invariant subspace: the re-orthogonalized vector's norm is at most 2^-40
+ * times the largest value seen) replaces the vector by a Philox normal
+ * vector taken twice against the whole basis.  With a basis of more than
+ * 2^21 entries (rows x columns) that repair runs over up to 128 workgroups of
+ * a cooperative launch instead of one workgroup: 575 -> 48 ms for the twenty
+ * breakdowns of a rank-30 1,000,000 x 500,000 matrix at p = 40 on MI355X.
+ * A cooperative dispatch costs ~17 us more than a plain one, paid at every
+ * Lanczos step whether or not it breaks down (+7 % at 1,000,000 x 500,000,
+ * p = 150), so the wide form is the default only from the cycle after one
+ * that saw a breakdown; this flag turns it on from the first step, for
+ * matrices known to be rank-deficient.  Never inside captured cycles
+ * (SVDS_FLAG_GRAPH keeps the one-workgroup repair there); ignored by the
+ * batched solver. */
 
 /* SVDS_FLAG_EARLY_STOP: Proposition 1 holds for the leading block T(1:j,1:j)
  * of a cycle at every Lanczos dimension j, so the test of eq. (4) can pass

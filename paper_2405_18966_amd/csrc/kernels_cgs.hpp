@@ -15,6 +15,7 @@
 // far more than one extra launch.  Sums are in fixed order (deterministic).
 #pragma once
 #include <algorithm>
+#include <hip/hip_cooperative_groups.h>
 #include "common.hpp"
 
 namespace svds {
@@ -638,6 +639,114 @@ __global__ __launch_bounds__(FINISH_THREADS) void finish_norm_kernel(const doubl
   }
   __syncthreads();
   breakdown_repair<T>(Q, ldq, L, j, out, static_cast<uint32_t>(bd), fa.seed, sh_d, sh_h);
+}
+
+// The finish step over G workgroups of a cooperative launch, for long bases
+// (the one-workgroup finish_norm_kernel streams a 10^6 x 40 basis for a
+// breakdown at one CU's bandwidth, ~26 ms).  Every workgroup forms |w| from
+// the same partials in the same order, so all take the same branch; on the
+// usual path workgroup 0 does what finish_norm_kernel does and the others
+// return.  On a breakdown workgroup b owns rows [L b / G, L (b+1) / G): it
+// draws those rows of the same Philox vector, and for each of the two
+// classical Gram-Schmidt passes and for the norm writes its partial sums to
+// `part` (double; two halves of G x (j + 1) used alternately, so a workgroup
+// never overwrites sums another is still adding), passes a grid barrier, and
+// adds the G partials in workgroup order: every workgroup holds the same
+// coefficients.  Three grid barriers per breakdown.  The breakdown counter is
+// read by all before the first barrier and advanced after it.
+template <typename T>
+__global__ __launch_bounds__(FINISH_THREADS) void finish_norm_coop_kernel(
+    const double *__restrict__ npart, int nparts, int mode, FinishArgs fa, const T *__restrict__ Q, int64_t ldq,
+    int64_t L, int j, T *__restrict__ out, double *__restrict__ part) {
+  __shared__ double sh_d[FINISH_THREADS / WAVE];
+  __shared__ T sh_h[CGS_MAXJ];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int G = gridDim.x, b = blockIdx.x;
+  double tot = strided_sum(npart, tid, nparts, nt, 0.0);
+  tot = block_sum(tot, sh_d);
+  const double nrm = sqrt(tot);
+  if (mode == MODE_NORM) {
+    if (b == 0 && tid == 0) *fa.xs = 1.0 / nrm;
+    return;
+  }
+  // workgroup 0 raises sigma_est only on the usual path, where the others
+  // return whichever value they read (nrm > REL sig implies nrm > REL max(sig, nrm))
+  const double sig = *fa.sigma_est;
+  if (nrm > BREAKDOWN_REL * sig) {
+    if (b != 0) return;
+    if (tid == 0) {
+      *fa.t_entry = nrm;
+      *fa.xs = 1.0 / nrm;
+      *fa.sigma_est = fmax(sig, nrm);
+    }
+    omega_fix(fa, j, nrm, false);
+    return;
+  }
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int bd = *fa.breakdowns + 1;
+  if (b == 0) omega_fix(fa, j, 0.0, true);
+  const int64_t r0 = L * b / G, r1 = L * (b + 1) / G;
+  for (int64_t r = r0 + tid; r < r1; r += nt) {
+    double z0, z1;
+    philox_normal_pair(fa.seed, static_cast<uint32_t>(bd), static_cast<uint64_t>(r >> 1), z0, z1);
+    out[r] = static_cast<T>((r & 1) ? z1 : z0);
+  }
+  __syncthreads();
+  const int ps = j + 1;
+  constexpr int CH = 8;
+  for (int pass = 0; pass < 2; ++pass) {
+    double *P = part + (pass & 1) * G * ps;
+    for (int c0 = 0; c0 < j; c0 += CH) {
+      const int nc = min(CH, j - c0);
+      T acc[CH];
+#pragma unroll
+      for (int g = 0; g < CH; ++g) acc[g] = 0;
+      for (int64_t r = r0 + tid; r < r1; r += nt) {
+        const T x = out[r];
+#pragma unroll
+        for (int g = 0; g < CH; ++g)
+          if (g < nc) acc[g] += Q[static_cast<int64_t>(c0 + g) * ldq + r] * x;
+      }
+#pragma unroll
+      for (int g = 0; g < CH; ++g) {
+        const T sg = block_sum(acc[g], reinterpret_cast<T *>(sh_d));
+        if (tid == 0 && g < nc) P[b * ps + c0 + g] = static_cast<double>(sg);
+      }
+    }
+    grid.sync();
+    if (pass == 0 && b == 0 && tid == 0) {
+      *fa.breakdowns = bd;
+      *fa.t_entry = 0.0;
+      *fa.xs = 1.0;
+    }
+    for (int c = tid; c < j; c += nt) {
+      double h = 0;
+      for (int q = 0; q < G; ++q) h += P[q * ps + c];
+      sh_h[c] = static_cast<T>(h);
+    }
+    __syncthreads();
+    for (int64_t r = r0 + tid; r < r1; r += nt) {
+      T u[CH];
+#pragma unroll
+      for (int g = 0; g < CH; ++g) u[g] = 0;
+      int c = 0;
+      for (; c + CH <= j; c += CH)
+#pragma unroll
+        for (int g = 0; g < CH; ++g) u[g] += Q[static_cast<int64_t>(c + g) * ldq + r] * sh_h[c + g];
+      for (; c < j; ++c) u[0] += Q[static_cast<int64_t>(c) * ldq + r] * sh_h[c];
+      out[r] -= ((u[0] + u[1]) + (u[2] + u[3])) + ((u[4] + u[5]) + (u[6] + u[7]));
+    }
+    __syncthreads();
+  }
+  double s = 0;
+  for (int64_t r = r0 + tid; r < r1; r += nt) s += static_cast<double>(out[r]) * out[r];
+  s = block_sum(s, sh_d);
+  if (tid == 0) part[b * ps] = s;  // first half again: its last readers passed the second barrier
+  grid.sync();
+  double n2 = 0;
+  for (int q = 0; q < G; ++q) n2 += part[q * ps];
+  const double inv = 1.0 / sqrt(n2);
+  for (int64_t r = r0 + tid; r < r1; r += nt) out[r] = static_cast<T>(out[r] * inv);
 }
 
 // ---------------------------------------------------------------------------

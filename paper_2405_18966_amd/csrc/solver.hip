@@ -330,6 +330,7 @@ struct svds_plan {
   Lanczos<double> L64;
   Lanczos<float> L32;
   bool mixed = false;
+  bool capturing = false;  // a cycle body is being captured into a graph
   Small sc{};
   double *tmp_nk = nullptr;  // n x k FP64 (mixed warm start), m-vector scratch
   int32_t *tscratch = nullptr;  // device radix-sort scratch of the transposed copies (CSR plans)
@@ -354,6 +355,7 @@ struct svds_plan {
   bool selective = false;  // SVDS_FLAG_SELECTIVE_REORTH: second CGS pass only when needed
   bool partial = false;    // SVDS_FLAG_PARTIAL_REORTH: omega-recurrence partial re-orthogonalization
   bool harmonic = false;   // SVDS_FLAG_HARMONIC: harmonic-Ritz restarts (with SVDS_FLAG_SMALLEST)
+  bool wide_repair = false;  // breakdown repairs over many workgroups (finish_blocks)
   int64_t reorth_calls = 0;  // re-orthogonalizations with the selective test
   bool early = false;      // SVDS_FLAG_EARLY_STOP
   EarlyCheck ec;
@@ -565,6 +567,27 @@ struct OmegaStep {
   bool full;
 };
 
+// Workgroups of the finish step (finish_norm_coop_kernel when above one):
+// one unless wide repairs are on (SVDS_FLAG_EXPECT_BREAKDOWNS, or a
+// breakdown in an earlier cycle of the solve: a cooperative dispatch costs
+// ~17 us more than a plain one on MI355X, at every step), for short bases,
+// for the start-vector norm and while the stream is being captured (a grid
+// barrier needs a cooperative launch, which a captured graph does not
+// promise); otherwise one per FINISH_ROWS_COLS entries of the basis, up to
+// FINISH_MAX_BLOCKS, so that a breakdown's repair streams the basis over
+// that many CUs.
+constexpr int64_t FINISH_ROWS_COLS = int64_t(1) << 20;
+constexpr int FINISH_MAX_BLOCKS = 128;
+static_assert(2 * FINISH_MAX_BLOCKS * (CGS_MAXJ + 1) * 8 <= CGS_MAXJ * CGS_MAX_SLABS * 4,
+              "the finish partials must fit the projection partials of FP32 bases");
+
+static int finish_blocks(const svds_plan *P, int64_t L, int j, int mode) {
+  if (!P->wide_repair || mode != MODE_LANCZOS || P->capturing || L * j < 2 * FINISH_ROWS_COLS) return 1;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(P->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 1;
+  return static_cast<int>(std::min<int64_t>(FINISH_MAX_BLOCKS, L * j / FINISH_ROWS_COLS));
+}
+
 template <typename TB>
 static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int64_t ldq, int64_t L, int j,
                        const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs,
@@ -675,8 +698,19 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     fa.om_full = (om->full || j == 0) ? 1 : 0;
   }
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
-  hipLaunchKernelGGL((finish_norm_kernel<TB>), dim3(1), dim3(FINISH_THREADS), 0, P->stream, s.npart, nn,
-                     mode, fa, Q, ldq, L, j, out);
+  const int G = finish_blocks(P, L, j, mode);
+  if (G > 1) {
+    double *cpart = reinterpret_cast<double *>(part);
+    const double *np = s.npart;
+    int64_t ldq_ = ldq, L_ = L;
+    int nn_ = nn, mode_ = mode, j_ = j;
+    void *args[] = {&np, &nn_, &mode_, &fa, &Q, &ldq_, &L_, &j_, &out, &cpart};
+    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&finish_norm_coop_kernel<TB>), dim3(G),
+                                       dim3(FINISH_THREADS), args, 0, P->stream));
+  } else {
+    hipLaunchKernelGGL((finish_norm_kernel<TB>), dim3(1), dim3(FINISH_THREADS), 0, P->stream, s.npart, nn,
+                       mode, fa, Q, ldq, L, j, out);
+  }
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_REDUCE, 8.0 * nn, 0.0);
   return SVDS_OK;
@@ -957,8 +991,10 @@ static int small_svd(svds_plan *P) {
   if (rc) return rc;
   ACC_AFTER(SVDS_KC_SMALLSVD, 16.0 * (p + 1) * (p + 1), 0.0);
   HIP_TRY(hipMemcpyAsync(P->h_flags, s.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipMemcpyAsync(P->h_flags + 8, s.bd, sizeof(int), hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   P->jac_sweeps += P->h_flags[2];
+  if (P->h_flags[8] > 0) P->wide_repair = true;  // the matrix is rank-deficient (or nearly)
   P->p_eff = p;
   P->out_Uk = s.Uk;
   P->out_Vext = s.Vext;
@@ -1065,7 +1101,9 @@ static int run_graphed(svds_plan *P, Lanczos<TB> &Lz, uint64_t ver, Body &&body)
       set_last_error(e, "hipStreamBeginCapture", __FILE__, __LINE__);
       rc = SVDS_EDEVICE;
     } else {
+      P->capturing = true;
       rc = body();
+      P->capturing = false;
       e = hipStreamEndCapture(G.cap, &g);
       if (!rc && e != hipSuccess) {
         set_last_error(e, "hipStreamEndCapture", __FILE__, __LINE__);
@@ -2298,6 +2336,7 @@ extern "C" int svds_plan_execute(svds_plan *P, double *U, double *S, double *V, 
   HIP_TRY(hipMemsetAsync(P->sc.sigma_est, 0, sizeof(double), P->stream));
   HIP_TRY(hipMemsetAsync(P->sc.bd, 0, 4 * sizeof(int), P->stream));
   HIP_TRY(hipMemsetAsync(P->sc.T, 0, sizeof(double) * (P->p + 1) * (P->p + 1), P->stream));
+  P->wide_repair = (P->opts.flags & SVDS_FLAG_EXPECT_BREAKDOWNS) != 0;
   int rc = SVDS_OK;
   bool conv = false;
   int cyc = 0;

@@ -28,6 +28,7 @@ SVDS_FLAG_SELECTIVE_REORTH = 512
 SVDS_FLAG_PARTIAL_REORTH = 1024
 SVDS_FLAG_EARLY_STOP = 2048
 SVDS_FLAG_HARMONIC = 4096
+SVDS_FLAG_EXPECT_BREAKDOWNS = 8192
 KERNEL_CLASSES = ["spmv", "spmvT", "cgs_proj", "cgs_updproj", "cgs_updnorm", "cgs_reduce", "smallsvd",
                   "rotate", "other"]
 KC_COUNT = len(KERNEL_CLASSES)

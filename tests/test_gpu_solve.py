@@ -325,28 +325,43 @@ def test_full_size_zipf_workload_against_stored_oracle(S):
     assert abs(r.info["max_res_av"] - float(res_av.max())) <= 1e-12
 
 
-def test_breakdowns_at_scale(S):
+@pytest.mark.parametrize("form", ["plain", "wide", "graph_wide", "mixed_auto"])
+def test_breakdowns_at_scale(S, form):
     """A 1,000,000 x 500,000 matrix of rank 30 (diagonal, distinct values):
-    the Krylov space is exhausted after 31 steps, so the rest of the first
-    cycle runs on breakdown replacement vectors (each re-orthogonalized
-    against the whole basis in the finish step).  Values against the exact
-    ones and the oracle's."""
+    the Krylov space is exhausted after 31 steps, so the rest of the cycle
+    runs on breakdown replacement vectors, each re-orthogonalized against the
+    whole basis in the finish step.  plain: one workgroup per repair; wide:
+    SVDS_FLAG_EXPECT_BREAKDOWNS, up to 128 workgroups of a cooperative launch;
+    graph_wide: the same with captured cycles (the first cycle runs before
+    any capture); mixed_auto: no flag, an FP32 cycle with one-workgroup
+    repairs, then an FP64 cycle with wide ones (switched on by the FP32
+    cycle's breakdowns).  Values against the exact ones and the oracle's; the
+    replacement vectors are the oracle's (same Philox streams), so the FP64
+    solves also match its breakdown count."""
     import time
     import torch
-    print("breakdowns at 1e6 rows", flush=True)
+    print(f"breakdowns at 1e6 rows, {form}", flush=True)
     d = np.zeros(500000)
     d[:30] = np.arange(30, 0, -1, dtype=np.float64)
     A = inputs.diag_matrix(1_000_000, 500_000, d)
     k, p = 5, 40
     v0 = inputs.start_vector(500_000, 31)
     Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), k, p, 1e-10, 50, v0=v0)
+    precision = S.SVDS_PREC_MIXED if form == "mixed_auto" else 0
+    flags = {"plain": 0, "wide": S.SVDS_FLAG_EXPECT_BREAKDOWNS, "mixed_auto": 0,
+             "graph_wide": S.SVDS_FLAG_EXPECT_BREAKDOWNS | S.SVDS_FLAG_GRAPH}[form]
     t0 = time.perf_counter()
-    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, 1e-10, 50, v0=v0)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, 1e-10, 50, v0=v0, precision=precision, flags=flags)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert st == 0 and info["breakdowns"] > 0 and info_r.breakdowns > 0
+    if form == "mixed_auto":
+        assert info["cycles_fp32"] >= 1 and info["cycles_fp64"] >= 1
+    else:
+        assert info["breakdowns"] == info_r.breakdowns
     np.testing.assert_allclose(Sg, [30, 29, 28, 27, 26], rtol=1e-12)
     np.testing.assert_allclose(Sg, Sr, rtol=1e-12)
+    _invariants(A, Ug, Sg, Vg, 1e-10)
     print(f"breakdowns gpu {info['breakdowns']} oracle {info_r.breakdowns}, {dt * 1e3:.1f} ms", flush=True)
 
 
