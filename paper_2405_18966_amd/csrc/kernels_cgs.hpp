@@ -12,7 +12,10 @@
 // Cross-block sums are finished by small kernels at the kernel boundary
 // (reduce_cols_kernel, finish_norm_kernel): on MI355X a device-scope fence or
 // a shared arrival counter in every block costs ~0.1 us per block, serialized,
-// far more than one extra launch.  Sums are in fixed order (deterministic).
+// far more than one extra launch.  For short vectors, whose passes leave at
+// most CGS_FUSE_NP partials per column, the next pass sums them itself
+// (CgsCoef) and the reduction launch is skipped.  Sums are in fixed order
+// (deterministic).
 #pragma once
 #include <algorithm>
 #include <hip/hip_cooperative_groups.h>
@@ -69,6 +72,39 @@ __global__ __launch_bounds__(256) void reduce_cols_kernel(const T *__restrict__ 
   T s = strided_sum(p, lane, nv, WAVE, T(0));
   s = wave_sum(s);
   if (lane == 0) out[c] = s;
+}
+
+// Where a pass finds the coefficients of the previous projection: h (global,
+// from reduce_cols_kernel) or, with hp non-null, that projection's np
+// partials per column (column-major, [j][np]), which the pass sums itself:
+// for short vectors the partials are few and the summing costs less than a
+// reduction launch.  Workgroup 0 then also stores the sums to hout.
+template <typename T>
+struct CgsCoef {
+  const T *hp;
+  int np;
+  T *hout;
+};
+
+// sh[c] = h[c] for c < j and 0 for j <= c < npad; one thread per column,
+// partials added in order (every workgroup gets the same sums).  Ends with
+// a barrier.
+constexpr int CGS_FUSE_NP = 32;  // at most two batches of 16 loads per thread
+template <typename T>
+__device__ inline void cgs_load_coeffs(T *sh, int j, int npad, const T *__restrict__ h, const CgsCoef<T> &cf) {
+  for (int c = threadIdx.x; c < npad; c += blockDim.x) {
+    T v = 0;
+    if (c < j) {
+      if (cf.hp) {
+        v = strided_sum(cf.hp + static_cast<int64_t>(c) * cf.np, 0, cf.np, 1, T(0));
+        if (blockIdx.x == 0) cf.hout[c] = v;
+      } else {
+        v = h[c];
+      }
+    }
+    sh[c] = v;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -175,16 +211,16 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_kernel(const T *__restrict_
                                                            int64_t L, int j, const T *__restrict__ w,
                                                            const T *__restrict__ h1,
                                                            T *__restrict__ w1out, T *__restrict__ part,
-                                                           int normw1, const int *__restrict__ cmask) {
+                                                           int normw1, const int *__restrict__ cmask,
+                                                           CgsCoef<T> cf) {
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ T xch[2][16][WAVE * N];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int NW = blockDim.x / WAVE;
   const int nblk = gridDim.x, blk = blockIdx.x;
-  for (int c = tid; c < j; c += blockDim.x) sh_h[c] = h1[c];
+  cgs_load_coeffs(sh_h, j, NW * CPW, h1, cf);  // padding columns 0
   const int c0 = wv * CPW;
   const int nc = max(0, min(CPW, j - c0));
-  for (int c = j + tid; c < NW * CPW; c += blockDim.x) sh_h[c] = T(0);  // padding columns
   bool en[CPW];
 #pragma unroll
   for (int c = 0; c < CPW; ++c) en[c] = c < nc && (!MASK || cmask[c0 + c] != 0);
@@ -272,17 +308,16 @@ __global__ __launch_bounds__(1024) void cgs_upd_proj_wide_kernel(const T *__rest
                                                                 int j, const T *__restrict__ w,
                                                                 const T *__restrict__ h1, T *__restrict__ w1out,
                                                                 T *__restrict__ part, int normw1,
-                                                                const int *__restrict__ cmask) {
+                                                                const int *__restrict__ cmask, CgsCoef<T> cf) {
   constexpr int CPW = 20;
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ T xch[2][16][WAVE];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int NW = blockDim.x / WAVE;
   const int nblk = gridDim.x, blk = blockIdx.x;
-  for (int c = tid; c < j; c += blockDim.x) sh_h[c] = h1[c];
+  cgs_load_coeffs(sh_h, j, NW * CPW, h1, cf);  // padding columns 0
   const int c0 = wv * CPW;
   const int nc = max(0, min(CPW, j - c0));
-  for (int c = j + tid; c < NW * CPW; c += blockDim.x) sh_h[c] = T(0);  // padding columns
   unsigned en = 0;  // bit c: column c0 + c is read
   for (int c = 0; c < nc; ++c)
     if (!MASK || cmask[c0 + c] != 0) en |= 1u << c;
@@ -353,13 +388,13 @@ template <typename T, int N, bool MASK = false>
 __global__ __launch_bounds__(CGS_THREADS) void cgs_upd_norm_kernel(
     const T *__restrict__ Q, int64_t ldq, int64_t L, int j, const T *__restrict__ w1,
     const T *__restrict__ h, T *__restrict__ out, double *__restrict__ npart, const T *__restrict__ sel,
-    int *__restrict__ ran, const int *__restrict__ cmask) {
+    int *__restrict__ ran, const int *__restrict__ cmask, CgsCoef<T> cf) {
   __shared__ T sh_h[CGS_MAXJ];
   __shared__ int sh_c[MASK ? CGS_MAXJ : 1];
   __shared__ double sh_d[CGS_THREADS / WAVE];
   const int tid = threadIdx.x;
   j = cgs_second_pass_width(j, h, sel, ran);
-  for (int c = tid; c < j; c += CGS_THREADS) sh_h[c] = h[c];
+  cgs_load_coeffs(sh_h, j, j, h, cf);
   if (MASK) {
     // the selected columns, in increasing order (one wave compacts them)
     __shared__ int sh_n;
@@ -436,15 +471,15 @@ __global__ __launch_bounds__(1024) void cgs_tile_upd_kernel(const T *__restrict_
                                                             int j, const T *__restrict__ w1,
                                                             const T *__restrict__ h, T *__restrict__ out,
                                                             double *__restrict__ npart, const T *__restrict__ sel,
-                                                            int *__restrict__ ran, const int *__restrict__ cmask) {
+                                                            int *__restrict__ ran, const int *__restrict__ cmask,
+                                                            CgsCoef<T> cf) {
   constexpr int CPW = CGS_TILE_CPW;
   j = cgs_second_pass_width(j, h, sel, ran);
   __shared__ T sh_h[CGS_TILE_MAXJ];
   __shared__ T xch[16][WAVE * N];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int NW = blockDim.x / WAVE;
-  for (int c = tid; c < NW * CPW; c += blockDim.x) sh_h[c] = c < j ? h[c] : T(0);
-  __syncthreads();
+  cgs_load_coeffs(sh_h, j, NW * CPW, h, cf);
   const int64_t tile = blockIdx.x;
   const int64_t r = tile * (WAVE * N) + lane * N;
   const int c0 = wv * CPW;

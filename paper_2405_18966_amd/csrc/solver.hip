@@ -477,9 +477,11 @@ template <typename TB>
 // q_alg = false: this read of Q repeats one the same CGS2 already counted
 // (the split second pass of a basis wider than CGS_FUSED_MAXJ), so only the
 // vector counts as algorithmic bytes.
+// np_out non-null: with at most CGS_FUSE_NP slabs the reduction is left to
+// the next pass (*np_out = nslab, partials in part); otherwise *np_out = 0.
 static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int64_t L, int j,
                            const TB *w, TB *h, int kc, int normw = 0, const int *cmask = nullptr,
-                           bool q_alg = true) {
+                           bool q_alg = true, int *np_out = nullptr) {
   const double sb = sizeof(TB);
   int nslab, ngc;
   cgs_proj_shape(L, j, nslab, ngc);
@@ -504,6 +506,10 @@ static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int
   // with a column mask the columns read are counted at the end of the solve
   const double jc = cmask ? 0.0 : static_cast<double>(j);
   ACC_AFTER(kc, sb * L * (q_alg ? jc : 0.0) + sb * L, 2.0 * L * jc);
+  if (np_out) {
+    *np_out = nslab <= CGS_FUSE_NP ? nslab : 0;
+    if (*np_out) return SVDS_OK;
+  }
   // h[0:j], and with normw h[j] = |w|^2
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
   hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j + normw, 4)), dim3(256), 0, P->stream, part,
@@ -519,7 +525,7 @@ static int proj_and_reduce(svds_plan *P, TB *part, const TB *Q, int64_t ldq, int
 template <typename TB>
 static int launch_upd_norm(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, int j, const TB *w, const TB *h,
                            TB *out, double *npart, const TB *sel = nullptr, int *ran = nullptr,
-                           const int *cmask = nullptr) {
+                           const int *cmask = nullptr, CgsCoef<TB> cf = {nullptr, 0, nullptr}) {
   constexpr int NV = 16 / sizeof(TB);
   const bool vec = cgs_rows_per_lane<TB>(Q, ldq, w, out, nullptr) == NV;
   const int nr = vec ? NV : 1;
@@ -529,32 +535,32 @@ static int launch_upd_norm(svds_plan *P, const TB *Q, int64_t ldq, int64_t L, in
     const dim3 g(nt), b(nw * WAVE);
     if (cmask && vec)
       klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, NV, true>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out,
-              npart, sel, ran, cmask);
+              npart, sel, ran, cmask, cf);
     else if (cmask)
       klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, 1, true>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out,
-              npart, sel, ran, cmask);
+              npart, sel, ran, cmask, cf);
     else if (vec)
       klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, NV>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out, npart,
-              sel, ran, cmask);
+              sel, ran, cmask, cf);
     else
       klaunch(P->acc, true, true, cgs_tile_upd_kernel<TB, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out, npart,
-              sel, ran, cmask);
+              sel, ran, cmask, cf);
     return nt;
   }
   const int nn = cgs_updnorm_blocks(L);
   const dim3 g(nn), b(CGS_THREADS);
   if (cmask && j > 0 && vec)
     klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, NV, true>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out,
-            npart, sel, ran, cmask);
+            npart, sel, ran, cmask, cf);
   else if (cmask && j > 0)
     klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, 1, true>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out,
-            npart, sel, ran, cmask);
+            npart, sel, ran, cmask, cf);
   else if (vec)
     klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, NV>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out, npart, sel,
-            ran, cmask);
+            ran, cmask, cf);
   else
     klaunch(P->acc, true, true, cgs_upd_norm_kernel<TB, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, h, out, npart, sel,
-            ran, cmask);
+            ran, cmask, cf);
   return nn;
 }
 
@@ -576,6 +582,10 @@ struct OmegaStep {
 // promise); otherwise one per FINISH_ROWS_COLS entries of the basis, up to
 // FINISH_MAX_BLOCKS, so that a breakdown's repair streams the basis over
 // that many CUs.
+// Second half of the projection partials (a pass writes there while it
+// sums the first pass's partials).  A fused second pass has at most 512
+// workgroups of partials for up to CGS_MAXJ columns, or 1024 for 16.
+constexpr int64_t CGS_PART_HALF = int64_t(CGS_MAXJ) * CGS_MAX_SLABS / 2;
 constexpr int64_t FINISH_ROWS_COLS = int64_t(1) << 20;
 constexpr int FINISH_MAX_BLOCKS = 128;
 static_assert(2 * FINISH_MAX_BLOCKS * (CGS_MAXJ + 1) * 8 <= CGS_MAXJ * CGS_MAX_SLABS * 4,
@@ -615,9 +625,21 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
     ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * L + 8.0 * nb, 2.0 * L);
     cmask = s.om_mask;
   }
+  // Short vectors (at most CGS_FUSE_NP partials per column), without the
+  // selective or partial forms: each pass sums the previous projection's
+  // partials itself and the reduction launches are skipped; its workgroup 0
+  // still stores h1 / h2 (the harmonic restart reads them).
+  const bool fuse = !sel && !cmask;
+  CgsCoef<TB> cf2{nullptr, 0, nullptr};
   if (j > 0) {
     // pass 1: h1 = Q^T w
-    if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ, sel, cmask))) return rc;
+    int np1 = 0;
+    if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ, sel, cmask, true,
+                                  fuse ? &np1 : nullptr)))
+      return rc;
+    const CgsCoef<TB> cf1{np1 ? part : nullptr, np1, h1};
+    // pass 2 writes its partials past pass 1's while those are being read
+    TB *part2 = np1 ? part + CGS_PART_HALF : part;
     // pass 2: w1 = w - Q h1, h2 = Q^T w1
     int cpw = cgs_fused_cpw(j, static_cast<int>(sizeof(TB)));
     // a forced width must keep the block within 16 waves
@@ -631,46 +653,50 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
       const dim3 g(nb), b(nw * WAVE);
       if (cmask && cpw == 20)
         klaunch(P->acc, true, true, cgs_upd_proj_wide_kernel<TB, true>, g, b, 0, P->stream, Q, ldq, L, j, w, h1, w1,
-                part, sel, cmask);
+                part2, sel, cmask, cf1);
       else if (cpw == 20)
-        klaunch(P->acc, true, true, cgs_upd_proj_wide_kernel<TB>, g, b, 0, P->stream, Q, ldq, L, j, w, h1, w1, part,
-                sel, cmask);
+        klaunch(P->acc, true, true, cgs_upd_proj_wide_kernel<TB>, g, b, 0, P->stream, Q, ldq, L, j, w, h1, w1, part2,
+                sel, cmask, cf1);
       else if (cmask && cpw == 8)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 8, true, 1, true>, g, b, 0, P->stream, Q, ldq, L, j, w,
-                h1, w1, part, sel, cmask);
+                h1, w1, part2, sel, cmask, cf1);
       else if (cmask && sizeof(TB) == 8)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, true, 1, true>, g, b, 0, P->stream, Q, ldq, L, j, w,
-                h1, w1, part, sel, cmask);
+                h1, w1, part2, sel, cmask, cf1);
       else if (cmask && vec)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, NV, true>, g, b, 0, P->stream, Q, ldq, L, j,
-                w, h1, w1, part, sel, cmask);
+                w, h1, w1, part2, sel, cmask, cf1);
       else if (cmask)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, 1, true>, g, b, 0, P->stream, Q, ldq, L, j,
-                w, h1, w1, part, sel, cmask);
+                w, h1, w1, part2, sel, cmask, cf1);
       else if (cpw == 8)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 8, true, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, h1, w1,
-                part, sel, cmask);
+                part2, sel, cmask, cf1);
       else if (sizeof(TB) == 8)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, true, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, h1,
-                w1, part, sel, cmask);
+                w1, part2, sel, cmask, cf1);
       else if (vec)
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, NV>, g, b, 0, P->stream, Q, ldq, L, j, w, h1,
-                w1, part, sel, cmask);
+                w1, part2, sel, cmask, cf1);
       else
         klaunch(P->acc, true, true, cgs_upd_proj_kernel<TB, 10, false, 1>, g, b, 0, P->stream, Q, ldq, L, j, w, h1,
-                w1, part, sel, cmask);
+                w1, part2, sel, cmask, cf1);
       LAUNCH_CHECK();
       const double jc = cmask ? 0.0 : static_cast<double>(j);
       ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * jc + 2 * sb * L, 4.0 * L * jc);
-      ACC_BEFORE(SVDS_KC_CGS_REDUCE);
-      hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j + sel, 4)), dim3(256), 0, P->stream, part,
-                         static_cast<int64_t>(nb), nb, j + sel, h2);
-      LAUNCH_CHECK();
-      ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * (j + sel) * nb, 0.0);
+      if (fuse && nb <= CGS_FUSE_NP) {
+        cf2 = {part2, nb, h2};
+      } else {
+        ACC_BEFORE(SVDS_KC_CGS_REDUCE);
+        hipLaunchKernelGGL((reduce_cols_kernel<TB>), dim3(ceil_div(j + sel, 4)), dim3(256), 0, P->stream, part2,
+                           static_cast<int64_t>(nb), nb, j + sel, h2);
+        LAUNCH_CHECK();
+        ACC_AFTER(SVDS_KC_CGS_REDUCE, sb * (j + sel) * nb, 0.0);
+      }
     } else {
       // wide basis: separate update and projection passes
       ACC_BEFORE_ATT(SVDS_KC_CGS_UPDPROJ);
-      launch_upd_norm<TB>(P, Q, ldq, L, j, w, h1, w1, nullptr, nullptr, nullptr, cmask);
+      launch_upd_norm<TB>(P, Q, ldq, L, j, w, h1, w1, nullptr, nullptr, nullptr, cmask, cf1);
       LAUNCH_CHECK();
       const double jc = cmask ? 0.0 : static_cast<double>(j);
       ACC_AFTER(SVDS_KC_CGS_UPDPROJ, sb * L * jc + 2 * sb * L, 2.0 * L * jc);
@@ -683,7 +709,7 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
   // for it; the accounting then counts the vector traffic alone)
   ACC_BEFORE_ATT(SVDS_KC_CGS_UPDNORM);
   const int nn = launch_upd_norm<TB>(P, Q, ldq, L, j, src, h2, out, s.npart, sel ? h1 + j : nullptr,
-                                     sel ? s.bd + 1 : nullptr, cmask);
+                                     sel ? s.bd + 1 : nullptr, cmask, cf2);
   LAUNCH_CHECK();
   const int jn = (sel || cmask) ? 0 : j;
   ACC_AFTER(SVDS_KC_CGS_UPDNORM, sb * L * jn + 2 * sb * L, 2.0 * L * jn + 2.0 * L);
