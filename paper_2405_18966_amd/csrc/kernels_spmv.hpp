@@ -103,13 +103,24 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
       if (active && !active[inst]) continue;
       side_dst[r] = x[r] * (xs_ptr ? static_cast<TB>(xs_ptr[inst]) : TB(1));
     }
-  } else if (side_dst) {
+  } else if (side_dst && active) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * SPMV_THREADS + tid; i < side_len;
          i += static_cast<int64_t>(gridDim.x) * SPMV_THREADS) {
       const int inst = x_tile_inst ? x_tile_inst[i >> SPMV_TILE_SHIFT] : 0;
-      if (active && !active[inst]) continue;
+      if (!active[inst]) continue;
       side_dst[i] = x[i] * (xs_ptr ? static_cast<TB>(xs_ptr[inst]) : TB(1));
     }
+  }
+  // Without a problem mask (no block returns early) the side task's first
+  // entry per thread is loaded here, with the item's loads in flight, and
+  // stored at the end (the loads of short products are one dependent round
+  // trip fewer); further entries follow it there.
+  const bool side_late = side_dst && !side_tiles && !active;
+  const int64_t side_i0 = static_cast<int64_t>(blockIdx.x) * SPMV_THREADS + tid;
+  TB side_v0 = 0;
+  if (side_late && side_i0 < side_len) {
+    const int inst = x_tile_inst ? x_tile_inst[side_i0 >> SPMV_TILE_SHIFT] : 0;
+    side_v0 = x[side_i0] * (xs_ptr ? static_cast<TB>(xs_ptr[inst]) : TB(1));
   }
 
   const int4 it = items[blockIdx.x];
@@ -210,6 +221,14 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
       TB t = 0;
       for (int i = 0; i < SPMV_THREADS / WAVE; ++i) t += red[i];
       partials[it.y] = t;
+    }
+  }
+  if (side_late) {
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * SPMV_THREADS;
+    if (side_i0 < side_len) side_dst[side_i0] = side_v0;
+    for (int64_t i = side_i0 + gs; i < side_len; i += gs) {
+      const int inst = x_tile_inst ? x_tile_inst[i >> SPMV_TILE_SHIFT] : 0;
+      side_dst[i] = x[i] * (xs_ptr ? static_cast<TB>(xs_ptr[inst]) : TB(1));
     }
   }
 }
