@@ -133,7 +133,8 @@ extern "C" int svds_op_spmv_csr(const svds_csr *A, const void *x, const double *
     hipLaunchKernelGGL((spmv_csr_kernel<TV, TB>), dim3(sp.nitems), dim3(SPMV_THREADS), 0, st, items, \
                        A->row_ptr, A->col_idx, static_cast<const TV *>(A->val), nullptr,            \
                        static_cast<const TB *>(x), x_scale, coef, static_cast<const TB *>(yprev),   \
-                       static_cast<TB *>(y), reinterpret_cast<TB *>(parts), nullptr, 0, nullptr, nullptr, nullptr, 0); \
+                       static_cast<TB *>(y), reinterpret_cast<TB *>(parts), nullptr, 0, nullptr, nullptr, nullptr, 0, \
+                       SpmvProj<TB>{nullptr, 0, 0, nullptr});                                       \
     if (sp.nlong)                                                                                   \
       hipLaunchKernelGGL((spmv_longrow_fixup_kernel<TB>), dim3(sp.nlong), dim3(WAVE), 0, \
                          st, lr, sp.nlong, reinterpret_cast<TB *>(parts), x_scale, coef,            \

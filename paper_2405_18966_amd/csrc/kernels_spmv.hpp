@@ -75,6 +75,20 @@ struct LongRow {
 };
 constexpr int SPMV_TILE_SHIFT = 8;  // 256-row tiles of the problem map
 
+// Optional epilogue of a MULTI item, for short products of a single problem
+// without long rows: the item's rows of y projected on the first jq columns
+// of Q (column-major, leading dimension ldq),
+//   qpart[c * gridDim.x + item] = sum over the item's rows r of Q[r, c] y[r],
+// the partials of the first CGS pass over the vector y becomes (the pass
+// then needs no launch of its own).  Q == nullptr: no epilogue.
+template <typename TB>
+struct SpmvProj {
+  const TB *Q;
+  int64_t ldq;
+  int jq;
+  TB *qpart;
+};
+
 template <typename TV, typename TB>
 __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     const int4 *__restrict__ items, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
@@ -83,7 +97,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     const double *__restrict__ coef_ptr, const TB *__restrict__ yprev, TB *__restrict__ y,
     TB *__restrict__ partials, TB *__restrict__ side_dst, int64_t side_len,
     const int32_t *__restrict__ x_tile_inst, const int32_t *__restrict__ active,
-    const int32_t *__restrict__ side_tiles, int side_ntiles) {
+    const int32_t *__restrict__ side_tiles, int side_ntiles, SpmvProj<TB> pj) {
   __shared__ TB prod[SPMV_NNZ_BLK];
   __shared__ TB red[SPMV_THREADS / WAVE];
   __shared__ int rps[SPMV_ROWS_BLK + 1];
@@ -195,7 +209,27 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
       }
     }
     __syncthreads();
-    if (tid < nrows) y[r0 + tid] = xs * rsum[tid] - coef * yp;  // nrows <= SPMV_THREADS
+    const TB yv = xs * rsum[tid] - coef * yp;  // nrows <= SPMV_THREADS = SPMV_ROWS_BLK
+    if (tid < nrows) y[r0 + tid] = yv;
+    if (pj.Q) {
+      rsum[tid] = yv;  // each thread rereads only its own entry above
+      __syncthreads();
+      // four columns per wave at a time, lanes over the item's rows
+      for (int c0 = wv * 4; c0 < pj.jq; c0 += (SPMV_THREADS / WAVE) * 4) {
+        TB acc[4] = {TB(0), TB(0), TB(0), TB(0)};
+        for (int r = lane; r < nrows; r += WAVE) {
+          const TB yr = rsum[r];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (c0 + u < pj.jq) acc[u] += pj.Q[static_cast<int64_t>(c0 + u) * pj.ldq + r0 + r] * yr;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const TB sv = wave_sum(acc[u]);
+          if (lane == 0 && c0 + u < pj.jq) pj.qpart[static_cast<int64_t>(c0 + u) * gridDim.x + blockIdx.x] = sv;
+        }
+      }
+    }
   } else {
     const int z0 = it.z, z1 = it.w;
     TB s = 0;

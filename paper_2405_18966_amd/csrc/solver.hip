@@ -402,9 +402,24 @@ static void dense_launch(svds_plan *P, bool trans, const TB *x, const double *xs
   }
 }
 
+// Products whose first CGS pass can ride on them (spmv_csr_kernel's SpmvProj
+// epilogue): a single CSR problem without the partial or selective forms,
+// a product without column panels or long rows, at most CGS_FUSE_NP items
+// (the next pass sums the items' partials) and at most 2^18 basis entries
+// (the items read them).  Returns the number of partials per column, or 0.
+static int spmv_proj_np(const svds_plan *P, bool trans, int j) {
+  const Operator &op = P->op;
+  if (op.dense || P->partial || P->selective || j < 1 || (trans && op.npanel > 1)) return 0;
+  const SpmvPlan &sp = trans ? op.bwd : op.fwd;
+  const int64_t rows = trans ? op.n : op.m;
+  if (sp.nlong > 0 || sp.nitems > CGS_FUSE_NP || rows * j > (int64_t(1) << 18)) return 0;
+  return sp.nitems;
+}
+
 template <typename TB>
 static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const double *coef,
-                  const TB *yprev, TB *y, TB *side_dst, int64_t side_len, int kc_over = -1) {
+                  const TB *yprev, TB *y, TB *side_dst, int64_t side_len, int kc_over = -1,
+                  SpmvProj<TB> pj = {nullptr, 0, 0, nullptr}) {
   const Operator &op = P->op;
   const int64_t rows = trans ? op.n : op.m, cols = trans ? op.m : op.n;
   const int kc = kc_over >= 0 ? kc_over : (trans ? SVDS_KC_SPMVT : SVDS_KC_SPMV);
@@ -445,11 +460,11 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     if (op.vt == SVDS_F64 && !v32)
       klaunch(P->acc, true, !fix && !panels, spmv_csr_kernel<double, TB>, dim3(sp.nitems), dim3(SPMV_THREADS), 0,
               P->stream, sp.items, rp, cs, static_cast<const double *>(vs), spos, x, xs, ck, ypk, yk, parts,
-              side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles);
+              side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles, pj);
     else
       klaunch(P->acc, true, !fix && !panels, spmv_csr_kernel<float, TB>, dim3(sp.nitems), dim3(SPMV_THREADS), 0,
               P->stream, sp.items, rp, cs, static_cast<const float *>(vs), spos, x, xs, ck, ypk, yk, parts,
-              side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles);
+              side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles, pj);
     if (fix)
       klaunch(P->acc, false, !panels, spmv_longrow_fixup_kernel<TB>, dim3(sp.nlong), dim3(WAVE), 0, P->stream,
               sp.longrows, sp.nlong, parts, xs, ck, ypk, yk, sp.active);
@@ -461,7 +476,8 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
             (yprev ? 2.0 : 1.0) * sb * rows;
   }
   if (side_dst) bytes += 2.0 * sb * side_len;
-  ACC_AFTER(kc, bytes, 2.0 * (op.dense ? op.m * op.n : op.nnz));
+  if (pj.Q) bytes += sb * static_cast<double>(rows) * pj.jq;  // the first CGS pass's read of the basis
+  ACC_AFTER(kc, bytes, 2.0 * (op.dense ? op.m * op.n : op.nnz) + 2.0 * static_cast<double>(rows) * pj.jq);
   if (kc_over < 0) {
     if (trans) ++P->n_spmvT;
     else ++P->n_spmv;
@@ -599,9 +615,11 @@ static int finish_blocks(const svds_plan *P, int64_t L, int j, int mode) {
 }
 
 template <typename TB>
+// pre_np > 0: the product that formed w also left the first pass's pre_np
+// partials per column in part (spmv_proj_np), so pass 1 runs no launch.
 static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int64_t ldq, int64_t L, int j,
                        const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs,
-                       const OmegaStep *om = nullptr) {
+                       const OmegaStep *om = nullptr, int pre_np = 0) {
   const double sb = sizeof(TB);
   const Small &s = P->sc;
   const TB *src = w;
@@ -633,9 +651,9 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
   CgsCoef<TB> cf2{nullptr, 0, nullptr};
   if (j > 0) {
     // pass 1: h1 = Q^T w
-    int np1 = 0;
-    if ((rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ, sel, cmask, true,
-                                  fuse ? &np1 : nullptr)))
+    int np1 = fuse ? pre_np : 0;
+    if (!np1 && (rc = proj_and_reduce<TB>(P, part, Q, ldq, L, j, w, h1, SVDS_KC_CGS_PROJ, sel, cmask, true,
+                                          fuse ? &np1 : nullptr)))
       return rc;
     const CgsCoef<TB> cf1{np1 ? part : nullptr, np1, h1};
     // pass 2 writes its partials past pass 1's while those are being read
@@ -745,8 +763,8 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
 template <typename TB>
 static int cgs2_finish(svds_plan *P, Lanczos<TB> &Lz, const TB *Q, int64_t ldq, int64_t L, int j,
                        const TB *w, TB *w1, TB *out, int mode, double *t_entry, double *xs,
-                       const OmegaStep *om = nullptr) {
-  return cgs2_finish<TB>(P, Lz.partials, Lz.h1, Lz.h2, Q, ldq, L, j, w, w1, out, mode, t_entry, xs, om);
+                       const OmegaStep *om = nullptr, int pre_np = 0) {
+  return cgs2_finish<TB>(P, Lz.partials, Lz.h1, Lz.h2, Q, ldq, L, j, w, w1, out, mode, t_entry, xs, om, pre_np);
 }
 
 // Update only: out = w - Q h (restart, eq. (7)).
@@ -939,12 +957,14 @@ template <typename TB> static int lanczos(svds_plan *P, Lanczos<TB> &Lz, int i0,
     }
     // Alg. 1 steps 5-6: v_{i+1} = A^T u_i - alpha_i v_i, CGS2 against V[:, 0..i], beta_i.
     // The product also writes the normalized u_i into U[:, i].
+    // Short products also form the first CGS pass's partials (spmv_proj_np).
+    const int npv = spmv_proj_np(P, true, i + 1);
     int rc = matvec<TB>(P, true, Lz.bu, s.xs_u, s.T + i * ld + i, V + i * Lz.ldv, Lz.wv,
-                        U + i * Lz.ldu, m);
+                        U + i * Lz.ldu, m, -1, SpmvProj<TB>{npv ? V : nullptr, Lz.ldv, i + 1, Lz.partials});
     if (rc) return rc;
     const OmegaStep omv{0, i, false};
     rc = cgs2_finish<TB>(P, Lz, V, Lz.ldv, n, i + 1, Lz.wv, Lz.w1v, Lz.bv, MODE_LANCZOS,
-                         s.T + i * ld + i + 1, s.xs_v, P->partial ? &omv : nullptr);
+                         s.T + i * ld + i + 1, s.xs_v, P->partial ? &omv : nullptr, npv);
     if (rc) return rc;
     if (early) {
       HIP_TRY(hipEventRecord(e.ev_step[i % EARLY_LAG], P->stream));
@@ -959,12 +979,13 @@ template <typename TB> static int lanczos(svds_plan *P, Lanczos<TB> &Lz, int i0,
       break;
     }
     // Alg. 1 steps 7-8: u_{i+1} = A v_{i+1} - beta_i u_i, CGS2 against U[:, 0..i], alpha_{i+1}.
+    const int npu = spmv_proj_np(P, false, i + 1);
     rc = matvec<TB>(P, false, Lz.bv, s.xs_v, s.T + i * ld + i + 1, U + i * Lz.ldu, Lz.wu,
-                    V + (i + 1) * Lz.ldv, n);
+                    V + (i + 1) * Lz.ldv, n, -1, SpmvProj<TB>{npu ? U : nullptr, Lz.ldu, i + 1, Lz.partials});
     if (rc) return rc;
     const OmegaStep omu{1, i + 1, false};
     rc = cgs2_finish<TB>(P, Lz, U, Lz.ldu, m, i + 1, Lz.wu, Lz.w1u, Lz.bu, MODE_LANCZOS,
-                         s.T + (i + 1) * ld + i + 1, s.xs_u, P->partial ? &omu : nullptr);
+                         s.T + (i + 1) * ld + i + 1, s.xs_u, P->partial ? &omu : nullptr, npu);
     if (rc) return rc;
   }
   // the cycle ran to p: a check still running is no longer needed
