@@ -80,7 +80,7 @@ constexpr int SPMV_TILE_SHIFT = 8;  // 256-row tiles of the problem map
 // of Q (column-major, leading dimension ldq),
 //   qpart[c * gridDim.x + item] = sum over the item's rows r of Q[r, c] y[r],
 // the partials of the first CGS pass over the vector y becomes (the pass
-// then needs no launch of its own).  Q == nullptr: no epilogue.
+// then needs no launch of its own).  Only in the PROJ instantiation.
 template <typename TB>
 struct SpmvProj {
   const TB *Q;
@@ -89,7 +89,7 @@ struct SpmvProj {
   TB *qpart;
 };
 
-template <typename TV, typename TB>
+template <typename TV, typename TB, bool PROJ = false>
 __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     const int4 *__restrict__ items, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const TV *__restrict__ val, const uint16_t *__restrict__ spos, const TB *__restrict__ x,
@@ -102,6 +102,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
   __shared__ TB red[SPMV_THREADS / WAVE];
   __shared__ int rps[SPMV_ROWS_BLK + 1];
   __shared__ TB rsum[SPMV_ROWS_BLK];
+  __shared__ TB pred[SPMV_THREADS / WAVE][PROJ ? 16 : 1];  // SpmvProj epilogue
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1);
   const int wv = tid / WAVE;
@@ -209,25 +210,31 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
       }
     }
     __syncthreads();
-    const TB yv = xs * rsum[tid] - coef * yp;  // nrows <= SPMV_THREADS = SPMV_ROWS_BLK
+    const TB yv = tid < nrows ? xs * rsum[tid] - coef * yp : TB(0);  // nrows <= SPMV_THREADS
     if (tid < nrows) y[r0 + tid] = yv;
-    if (pj.Q) {
-      rsum[tid] = yv;  // each thread rereads only its own entry above
-      __syncthreads();
-      // four columns per wave at a time, lanes over the item's rows
-      for (int c0 = wv * 4; c0 < pj.jq; c0 += (SPMV_THREADS / WAVE) * 4) {
-        TB acc[4] = {TB(0), TB(0), TB(0), TB(0)};
-        for (int r = lane; r < nrows; r += WAVE) {
-          const TB yr = rsum[r];
+    if constexpr (PROJ) {
+      // one row per thread, sixteen columns' loads in flight, a wave sum per
+      // column, then the four waves' sums in wave order (loading the columns
+      // with the item's loads instead was slower: they then delay the gathers)
+      for (int c0 = 0; c0 < pj.jq; c0 += 16) {
+        const int nc = min(16, pj.jq - c0);
+        TB q[16];
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (c0 + u < pj.jq) acc[u] += pj.Q[static_cast<int64_t>(c0 + u) * pj.ldq + r0 + r] * yr;
-        }
+        for (int u = 0; u < 16; ++u)
+          q[u] = (tid < nrows && u < nc) ? pj.Q[static_cast<int64_t>(c0 + u) * pj.ldq + r0 + tid] : TB(0);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const TB sv = wave_sum(acc[u]);
-          if (lane == 0 && c0 + u < pj.jq) pj.qpart[static_cast<int64_t>(c0 + u) * gridDim.x + blockIdx.x] = sv;
+        for (int u = 0; u < 16; ++u) {
+          const TB sv = wave_sum(q[u] * yv);
+          if (lane == 0) pred[wv][u] = sv;
         }
+        __syncthreads();
+        if (tid < nc) {
+          TB t = 0;
+#pragma unroll
+          for (int v = 0; v < SPMV_THREADS / WAVE; ++v) t += pred[v][tid];
+          pj.qpart[static_cast<int64_t>(c0 + tid) * gridDim.x + blockIdx.x] = t;
+        }
+        __syncthreads();
       }
     }
   } else {

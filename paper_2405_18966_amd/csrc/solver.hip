@@ -457,14 +457,18 @@ static int matvec(svds_plan *P, bool trans, const TB *x, const double *xs, const
     const TB *ypk = panels ? nullptr : yprev;
     TB *parts = reinterpret_cast<TB *>(sp.partials);
     const bool fix = sp.nlong > 0;
-    if (op.vt == SVDS_F64 && !v32)
-      klaunch(P->acc, true, !fix && !panels, spmv_csr_kernel<double, TB>, dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-              P->stream, sp.items, rp, cs, static_cast<const double *>(vs), spos, x, xs, ck, ypk, yk, parts,
-              side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles, pj);
-    else
-      klaunch(P->acc, true, !fix && !panels, spmv_csr_kernel<float, TB>, dim3(sp.nitems), dim3(SPMV_THREADS), 0,
-              P->stream, sp.items, rp, cs, static_cast<const float *>(vs), spos, x, xs, ck, ypk, yk, parts,
-              side_dst, side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles, pj);
+#define SPMV_LAUNCH(TV, PROJ)                                                                              \
+  klaunch(P->acc, true, !fix && !panels, spmv_csr_kernel<TV, TB, PROJ>, dim3(sp.nitems), dim3(SPMV_THREADS), 0,  \
+          P->stream, sp.items, rp, cs, static_cast<const TV *>(vs), spos, x, xs, ck, ypk, yk, parts, side_dst,  \
+          side_len, sp.x_tile_inst, sp.active, sp.side_tiles, sp.side_ntiles, pj)
+    if (op.vt == SVDS_F64 && !v32) {
+      if (pj.Q) SPMV_LAUNCH(double, true);
+      else SPMV_LAUNCH(double, false);
+    } else {
+      if (pj.Q) SPMV_LAUNCH(float, true);
+      else SPMV_LAUNCH(float, false);
+    }
+#undef SPMV_LAUNCH
     if (fix)
       klaunch(P->acc, false, !panels, spmv_longrow_fixup_kernel<TB>, dim3(sp.nlong), dim3(WAVE), 0, P->stream,
               sp.longrows, sp.nlong, parts, xs, ck, ypk, yk, sp.active);
