@@ -342,44 +342,47 @@ __device__ __forceinline__ double jacobi_tol(int rows) {
 // LDS: W and Vh (pe x pe each, pe = p rounded up to even), sv, rank.
 // ---------------------------------------------------------------------------
 // Sweeps over W and Vh (pe x pe each, in LDS) until one passes without a
-// rotation or JAC_MAX_SWEEPS are done; returns the sweeps used.  rot_count:
-// an int in LDS.
-__device__ inline int lds_jacobi_sweeps(double *__restrict__ W, double *__restrict__ Vh, int pe, int *rot_count) {
+// rotation or JAC_MAX_SWEEPS are done; returns the sweeps used.
+template <int RPL>
+__device__ inline int lds_jacobi_sweeps_r(double *__restrict__ W, double *__restrict__ Vh, int pe) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-  const int nwaves = blockDim.x / WAVE;
   const double tolJ = jacobi_tol(pe);
-  const int npairs = pe / 2;
+  const int npairs = pe / 2, n1 = pe - 1;
+  // four pairs per wave, one per row of 16 lanes; the launch has one lane
+  // group per pair (small_svd_threads), so each group keeps its pair q for
+  // every step and steps its ring positions (rr_pair's players) by one
+  const int lg = lane >> 4, sl = lane & 15;
+  const int q = wv * 4 + lg;
+  const bool has = q < npairs;
   int sweeps = 0;
   for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
-    if (tid == 0) *rot_count = 0;
-    __syncthreads();
-    for (int step = 0; step < pe - 1; ++step) {
-      // four pairs per wave, one per row of 16 lanes (pe <= 64: at most four
-      // rows of each column per lane)
-      int nrot = 0;
-      const int lg = lane >> 4, sl = lane & 15;
-      for (int q0 = wv * 4; q0 < npairs; q0 += nwaves * 4) {
-        const int q = q0 + lg;
-        double *wi = nullptr, *wj = nullptr, *vi = nullptr, *vj = nullptr;
-        if (q < npairs) {
-          int i, j;
-          rr_pair(pe, step, q, i, j);
-          wi = W + i * pe;
-          wj = W + j * pe;
-          vi = Vh + i * pe;
-          vj = Vh + j * pe;
-        }
-        nrot += jacobi_pairg<4, 16>(wi, wj, vi, vj, pe, sl, tolJ);
+    int ia = q % n1, ib = (n1 - q) % n1;  // (step + q) mod n1 and (step + n1 - q) mod n1 at step 0
+    int any = 0;
+    for (int step = 0; step < n1; ++step) {
+      double *wi = nullptr, *wj = nullptr, *vi = nullptr, *vj = nullptr;
+      if (has) {
+        const int i = q == 0 ? 0 : 1 + ia, j = 1 + ib;  // as rr_pair(pe, step, q, i, j)
+        wi = W + i * pe;
+        wj = W + j * pe;
+        vi = Vh + i * pe;
+        vj = Vh + j * pe;
       }
-      if (sl == 0 && nrot) atomicAdd(rot_count, nrot);
+      any |= jacobi_pairg<RPL, 16>(wi, wj, vi, vj, pe, sl, tolJ);
+      ia = ia + 1 == n1 ? 0 : ia + 1;
+      ib = ib + 1 == n1 ? 0 : ib + 1;
       __syncthreads();
     }
     sweeps = sweep + 1;
-    const int done = *rot_count == 0;
-    __syncthreads();
-    if (done) break;
+    if (!__syncthreads_or(any)) break;
   }
   return sweeps;
+}
+
+// One-sided Jacobi sweeps of the pe x pe LDS matrices (pe even, <= 64) until
+// a sweep rotates no pair; returns the number of sweeps.  Rows per lane of
+// a 16-lane pair group: two up to 32 rows, four above.
+__device__ inline int lds_jacobi_sweeps(double *__restrict__ W, double *__restrict__ Vh, int pe) {
+  return pe <= 32 ? lds_jacobi_sweeps_r<2>(W, Vh, pe) : lds_jacobi_sweeps_r<4>(W, Vh, pe);
 }
 
 __device__ inline void small_svd_body(double *__restrict__ T, int64_t ts, int p, int k, double tol,
@@ -388,7 +391,6 @@ __device__ inline void small_svd_body(double *__restrict__ T, int64_t ts, int p,
                                       double *__restrict__ rho, int *__restrict__ flags,
                                       double *__restrict__ sigma_est, int smallest) {
   extern __shared__ double smem[];
-  __shared__ int rot_count;
   __shared__ double s_beta;
   const int tid = threadIdx.x;
   const int pe = p + (p & 1);
@@ -405,7 +407,7 @@ __device__ inline void small_svd_body(double *__restrict__ T, int64_t ts, int p,
     Vh[idx] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int sweeps = lds_jacobi_sweeps(W, Vh, pe, &rot_count);
+  const int sweeps = lds_jacobi_sweeps(W, Vh, pe);
   jacobi_finish(W, pe, Vh, pe, p, k, tol, s_beta, sweeps, T, ts, Uk, Vext, sig, res, rho, flags, sigma_est, sv,
                 rank, smallest);
 }
@@ -696,7 +698,6 @@ static __global__ __launch_bounds__(JAC_THREADS) void harm_small_kernel(const do
                                                                         double *__restrict__ QM,
                                                                         double *__restrict__ R) {
   extern __shared__ double smem[];
-  __shared__ int rot_count;
   const int q = p + 1, pe = q + (q & 1);
   double *W = smem;
   double *Vh = smem + pe * pe;
@@ -708,7 +709,7 @@ static __global__ __launch_bounds__(JAC_THREADS) void harm_small_kernel(const do
     Vh[idx] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  (void)lds_jacobi_sweeps(W, Vh, pe, &rot_count);
+  (void)lds_jacobi_sweeps(W, Vh, pe);
   harm_finish(W, pe, Vh, pe, p, k, QC, QM, R, sd, si);
 }
 
