@@ -28,12 +28,16 @@ namespace svds {
 
 constexpr int LZS_THREADS = 1024;
 constexpr int64_t LZS_MAX_L = 6144;      // longest vector: w (LDS) plus the static arrays stay below 64 KB
-constexpr int64_t LZS_MAX_NNZ = 65536;   // one thread per row: short products only
-// One CU reads the bases from L2 at ~0.1 TB/s: measured on MI355X against
-// the step-by-step launches, the kernel is 35-40% faster with 2 x 1000 x 21
-// FP64 bases (336 KB; 1000 x 1000, p = 20), 2-12% faster at 672 KB (2000 x
-// 2000, p = 20) and 5-10% slower at 744 KB (2000 x 1000, p = 30).
-constexpr int64_t LZS_MAX_BASIS_BYTES = 704 << 10;
+// One CU reads the bases from L2 at ~0.1 TB/s and runs the products one
+// thread per row.  Measured on MI355X against the step-by-step launches
+// (whose short products carry the first CGS pass and whose short passes sum
+// their partials themselves): 19% faster with 2 x 1000 x 21 FP64 bases
+// (328 KB; 1000 x 1000, 5 nonzeros per row, p = 20), even at 492 KB (1500 x
+// 1500, 7500 nonzeros), 6% slower at 656 KB (2000 x 2000, 10,000 nonzeros)
+// and 13-16% slower on 2000 x 1000 with 20,000 nonzeros at p = 20-28
+// (492-680 KB).
+constexpr int64_t LZS_MAX_NNZ = 8192;
+constexpr int64_t LZS_MAX_BASIS_BYTES = 512 << 10;
 
 // w (LDS, L entries) <- (I - Q Q^T)(I - Q Q^T) w, Q = columns 0..j-1 (ld ldq)
 __device__ inline void lzs_cgs2(const double *__restrict__ Q, int64_t ldq, int L, int j, double *w,
