@@ -89,6 +89,9 @@ struct SpmvProj {
   TB *qpart;
 };
 
+constexpr int SPMV_PT_LD = SPMV_THREADS + 8;  // padded: the four groups of a wave on other banks
+static_assert(SPMV_THREADS == 16 * 16, "one 16-lane group per column of a 16-column chunk");
+
 template <typename TV, typename TB, bool PROJ = false>
 __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     const int4 *__restrict__ items, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
   __shared__ TB red[SPMV_THREADS / WAVE];
   __shared__ int rps[SPMV_ROWS_BLK + 1];
   __shared__ TB rsum[SPMV_ROWS_BLK];
-  __shared__ TB pred[SPMV_THREADS / WAVE][PROJ ? 16 : 1];  // SpmvProj epilogue
+  __shared__ TB ptr_[PROJ ? 16 * SPMV_PT_LD : 1];  // SpmvProj epilogue: products by column
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1);
   const int wv = tid / WAVE;
@@ -213,9 +216,12 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
     const TB yv = tid < nrows ? xs * rsum[tid] - coef * yp : TB(0);  // nrows <= SPMV_THREADS
     if (tid < nrows) y[r0 + tid] = yv;
     if constexpr (PROJ) {
-      // one row per thread, sixteen columns' loads in flight, a wave sum per
-      // column, then the four waves' sums in wave order (loading the columns
-      // with the item's loads instead was slower: they then delay the gathers)
+      // one row per thread, sixteen columns' loads in flight; the products
+      // go to LDS column by column and each 16-lane group adds one column's
+      // 256 rows (16 each, then a DPP row sum), so a chunk costs one row sum
+      // per group instead of a wave sum per column (loading the columns with
+      // the item's loads was slower: they then delay the gathers)
+      const int g = tid >> 4, l = tid & 15;
       for (int c0 = 0; c0 < pj.jq; c0 += 16) {
         const int nc = min(16, pj.jq - c0);
         TB q[16];
@@ -223,17 +229,13 @@ __global__ __launch_bounds__(SPMV_THREADS) void spmv_csr_kernel(
         for (int u = 0; u < 16; ++u)
           q[u] = (tid < nrows && u < nc) ? pj.Q[static_cast<int64_t>(c0 + u) * pj.ldq + r0 + tid] : TB(0);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const TB sv = wave_sum(q[u] * yv);
-          if (lane == 0) pred[wv][u] = sv;
-        }
+        for (int u = 0; u < 16; ++u) ptr_[u * SPMV_PT_LD + tid] = q[u] * yv;
         __syncthreads();
-        if (tid < nc) {
-          TB t = 0;
+        TB t = 0;
 #pragma unroll
-          for (int v = 0; v < SPMV_THREADS / WAVE; ++v) t += pred[v][tid];
-          pj.qpart[static_cast<int64_t>(c0 + tid) * gridDim.x + blockIdx.x] = t;
-        }
+        for (int e = 0; e < SPMV_THREADS / 16; ++e) t += ptr_[g * SPMV_PT_LD + l + 16 * e];
+        t = spmv_row16_sum(t);
+        if (l == 0 && g < nc) pj.qpart[static_cast<int64_t>(c0 + g) * gridDim.x + blockIdx.x] = t;
         __syncthreads();
       }
     }
