@@ -468,6 +468,15 @@ def profile_section(which, S, inputs, np, torch):
             log(f"sparse2: {r.info['ms_total']:.1f} ms, cycles {r.info['cycles']}")
     elif which == "gather":
         gather_ceiling(S, inputs, np, torch)
+    elif which == "config1":
+        A = inputs.config_matrix(1)
+        c = inputs.CONFIG_SOLVE[1]
+        Ad, keep = S.csr_to_device(A)
+        v0 = torch.from_numpy(inputs.start_vector(A.n, inputs.CONFIG_SEEDS[1] + 1)).cuda()
+        for _ in range(3):
+            r = S.svds_csr_solve(Ad, S.make_opts(c["k"], c["p"], c["tol"], 2000, v0=v0))
+            torch.cuda.synchronize()
+            log(f"2000 x 1000: {r.info['ms_total']:.2f} ms, cycles {r.info['cycles']}")
     else:
         As = inputs.config_matrix(5)
         dev = [S.csr_to_device(A) for A in As]
@@ -496,11 +505,12 @@ def main():
                     help="skip the 2000 x 1000 sparse workload (k=10, p=30, tol=1e-10)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
-    ap.add_argument("--profile-section", choices=["dense", "batched", "sparse2", "gather"],
+    ap.add_argument("--profile-section", choices=["dense", "batched", "sparse2", "gather", "config1"],
                     help="only two solves of one other workload, for a rocprofv3 kernel trace: the "
                          "20000 x 10000 BF16 dense matrix (FP64 then mixed), the 256-problem batch (FP64), "
                          "or the paper's Sparse2 (40,000 x 40,000, k=100, p=300); 'gather': the Zipf "
-                         "workload's products against the gather-copy reference; no JSON")
+                         "workload's products against the gather-copy reference; 'config1': three solves "
+                         "of the 2000 x 1000 workload; no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver does not "
