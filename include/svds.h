@@ -123,8 +123,10 @@ enum {
  * A cooperative dispatch costs ~17 us more than a plain one, paid at every
  * Lanczos step whether or not it breaks down (+7 % at 1,000,000 x 500,000,
  * p = 150), so the wide form is the default only from the cycle after one
- * that saw a breakdown; this flag turns it on from the first step, for
- * matrices known to be rank-deficient.  Never inside captured cycles
+ * that saw a breakdown (the count is read back with the cycle's small-SVD
+ * flags; cycles ended by SVDS_FLAG_EARLY_STOP, whose small SVD runs on a
+ * side stream, do not switch it on); this flag turns it on from the first
+ * step, for matrices known to be rank-deficient.  Never inside captured cycles
  * (SVDS_FLAG_GRAPH keeps the one-workgroup repair there); ignored by the
  * batched solver. */
 
