@@ -112,3 +112,16 @@ def test_ctypes_structs_match_the_c_header(tmp_path):
         assert int(out[name]) == ctypes.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"
+
+
+def test_binding_constants_match_the_header():
+    """Every SVDS_FLAG_*, SVDS_PREC_* and dtype value the binding defines is
+    the one include/svds.h gives it, and every flag of the header is bound."""
+    import paper_2405_18966_amd.svds as mod
+    text = re.sub(r"/\*.*?\*/", "", open(HEADERS[0]).read(), flags=re.S)
+    header = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(SVDS_(?:FLAG|PREC)_\w+)\s*=\s*(\d+)", text)}
+    flags = [n for n in header if n.startswith("SVDS_FLAG_")]
+    assert len(flags) >= 14
+    for name, value in header.items():
+        assert hasattr(mod, name), name
+        assert getattr(mod, name) == value, (name, getattr(mod, name), value)
