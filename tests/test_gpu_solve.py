@@ -365,6 +365,24 @@ def test_breakdowns_at_scale(S, form):
     print(f"breakdowns gpu {info['breakdowns']} oracle {info_r.breakdowns}, {dt * 1e3:.1f} ms", flush=True)
 
 
+def test_wide_repair_few_workgroups(S):
+    """SVDS_FLAG_EXPECT_BREAKDOWNS on a 100,003 x 50,001 matrix of rank 30:
+    the u-side repairs run over two to three workgroups (100,003 rows do not
+    divide evenly), the v-side ones below the size limit in one workgroup.
+    Same values, breakdown count and invariants as the oracle."""
+    d = np.zeros(50_001)
+    d[:30] = np.linspace(3.0, 1.0, 30)
+    A = inputs.diag_matrix(100_003, 50_001, d)
+    k, p = 5, 40
+    v0 = inputs.start_vector(50_001, 33)
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), k, p, 1e-10, 50, v0=v0)
+    Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, 1e-10, 50, v0=v0, flags=S.SVDS_FLAG_EXPECT_BREAKDOWNS)
+    assert st == 0 and info["breakdowns"] == info_r.breakdowns > 0
+    np.testing.assert_allclose(Sg, np.sort(d)[::-1][:k], rtol=1e-12)
+    np.testing.assert_allclose(Sg, Sr, rtol=1e-12)
+    _invariants(A, Ug, Sg, Vg, 1e-10)
+
+
 @pytest.mark.parametrize("p", [40, 70])
 def test_rank_deficient_small_svd_stays_finite(S, p):
     """Rank 30 with p = 40 (one-workgroup Jacobi) and p = 70 (block Jacobi):
