@@ -468,6 +468,18 @@ def profile_section(which, S, inputs, np, torch):
             log(f"sparse2: {r.info['ms_total']:.1f} ms, cycles {r.info['cycles']}")
     elif which == "gather":
         gather_ceiling(S, inputs, np, torch)
+    elif which == "breakdowns":
+        d = np.zeros(500000)
+        d[:30] = np.arange(30, 0, -1, dtype=np.float64)
+        A = inputs.diag_matrix(1_000_000, 500_000, d)
+        Ad, keep = S.csr_to_device(A)
+        v0 = torch.from_numpy(inputs.start_vector(500_000, 31)).cuda()
+        for flags, name in ((0, "one-workgroup repairs"), (S.SVDS_FLAG_EXPECT_BREAKDOWNS, "wide repairs")):
+            for _ in range(2):
+                r = S.svds_csr_solve(Ad, S.make_opts(5, 40, 1e-10, 50, v0=v0, flags=flags))
+                torch.cuda.synchronize()
+                log(f"rank-30 1,000,000 x 500,000, {name}: {r.info['ms_total']:.1f} ms, "
+                    f"breakdowns {r.info['breakdowns']}")
     elif which == "config1":
         A = inputs.config_matrix(1)
         c = inputs.CONFIG_SOLVE[1]
@@ -505,12 +517,13 @@ def main():
                     help="skip the 2000 x 1000 sparse workload (k=10, p=30, tol=1e-10)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
-    ap.add_argument("--profile-section", choices=["dense", "batched", "sparse2", "gather", "config1"],
+    ap.add_argument("--profile-section", choices=["dense", "batched", "sparse2", "gather", "config1", "breakdowns"],
                     help="only two solves of one other workload, for a rocprofv3 kernel trace: the "
                          "20000 x 10000 BF16 dense matrix (FP64 then mixed), the 256-problem batch (FP64), "
                          "or the paper's Sparse2 (40,000 x 40,000, k=100, p=300); 'gather': the Zipf "
                          "workload's products against the gather-copy reference; 'config1': three solves "
-                         "of the 2000 x 1000 workload; no JSON")
+                         "of the 2000 x 1000 workload; 'breakdowns': a rank-30 1,000,000 x 500,000 matrix "
+                         "with one-workgroup and with wide breakdown repairs; no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver does not "

@@ -210,16 +210,21 @@ static __global__ void csc_gather_kernel(int64_t nnz, const int32_t *__restrict_
   t_val[q] = val[z];
 }
 
-// Column pointers from the sorted keys: t_rowptr[c] = first q with key >= c.
+// Column pointers from the sorted keys: t_rowptr[c] = first q with key >= c,
+// for c = 0..n, one thread per column by binary search (a thread per
+// nonzero filling the gap before it wrote long runs of empty columns
+// serially: 13 ms for a 500,000-column matrix of 30 nonzeros).
 static __global__ void csc_colptr_kernel(int64_t nnz, int64_t n, const int32_t *__restrict__ skeys,
                                   int32_t *__restrict__ t_rowptr) {
-  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= nnz) return;
-  const int32_t c = skeys[q];
-  const int32_t cp = (q == 0) ? -1 : skeys[q - 1];
-  for (int32_t cc = cp + 1; cc <= c; ++cc) t_rowptr[cc] = static_cast<int32_t>(q);
-  if (q == nnz - 1)
-    for (int64_t cc = c + 1; cc <= n; ++cc) t_rowptr[cc] = static_cast<int32_t>(nnz);
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c > n) return;
+  int64_t lo = 0, hi = nnz;  // first q in [lo, hi) with skeys[q] >= c
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (skeys[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  t_rowptr[c] = static_cast<int32_t>(lo);
 }
 
 static __global__ void fill_i32_kernel(int64_t n, int32_t v, int32_t *__restrict__ out) {

@@ -1492,7 +1492,7 @@ static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int
       hipLaunchKernelGGL((csc_gather_kernel<float>), dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz,
                          vin, rowof, static_cast<const float *>(op.val), out_ci,
                          static_cast<float *>(out_val));
-    hipLaunchKernelGGL(csc_colptr_kernel, dim3(ceil_div(nnz, 256)), dim3(256), 0, st, nnz, n, kin, out_rp);
+    hipLaunchKernelGGL(csc_colptr_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0, st, nnz, n, kin, out_rp);
     if (hipGetLastError() != hipSuccess) { rc = SVDS_EDEVICE; break; }
     if (sync && hipStreamSynchronize(st) != hipSuccess) { rc = SVDS_EDEVICE; break; }
   } while (0);
