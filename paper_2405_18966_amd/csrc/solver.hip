@@ -747,18 +747,22 @@ static int cgs2_finish(svds_plan *P, TB *part, TB *h1, TB *h2, const TB *Q, int6
   }
   ACC_BEFORE(SVDS_KC_CGS_REDUCE);
   const int G = finish_blocks(P, L, j, mode);
+  bool wide = false;
   if (G > 1) {
     double *cpart = reinterpret_cast<double *>(part);
     const double *np = s.npart;
     int64_t ldq_ = ldq, L_ = L;
     int nn_ = nn, mode_ = mode, j_ = j;
     void *args[] = {&np, &nn_, &mode_, &fa, &Q, &ldq_, &L_, &j_, &out, &cpart};
-    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&finish_norm_coop_kernel<TB>), dim3(G),
-                                       dim3(FINISH_THREADS), args, 0, P->stream));
-  } else {
+    // a cooperative launch the runtime refuses (its workgroups cannot all be
+    // resident) leaves the step to the one-workgroup finish
+    wide = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&finish_norm_coop_kernel<TB>), dim3(G),
+                                      dim3(FINISH_THREADS), args, 0, P->stream) == hipSuccess;
+    if (!wide) (void)hipGetLastError();
+  }
+  if (!wide)
     hipLaunchKernelGGL((finish_norm_kernel<TB>), dim3(1), dim3(FINISH_THREADS), 0, P->stream, s.npart, nn,
                        mode, fa, Q, ldq, L, j, out);
-  }
   LAUNCH_CHECK();
   ACC_AFTER(SVDS_KC_CGS_REDUCE, 8.0 * nn, 0.0);
   return SVDS_OK;
