@@ -2,9 +2,9 @@
 // 5-8 with the full re-orthogonalization by CGS2 that Sec. 2.1 asks for).
 //
 // For vectors of a few thousand entries a Lanczos half-step (one product,
-// three CGS2 passes, two cross-block sums, the norm) costs about seven
-// dependent launches of ~4 us each while the work itself is a few hundred
-// KB.  This kernel runs steps i0..p-1 of a cycle in one workgroup instead:
+// three CGS2 passes, the norm) costs four dependent launches of 3-10 us
+// each while the work itself is a few hundred KB.  This kernel runs steps
+// i0..p-1 of a cycle in one workgroup instead:
 // the vector being orthogonalized stays in LDS, the bases (U m x (p+1),
 // V n x (p+1), a few hundred KB) are read from L2, and the stages are
 // separated by barriers, not launches.  It computes what the multi-launch
