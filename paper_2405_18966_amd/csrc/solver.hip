@@ -1411,12 +1411,23 @@ static int carve_all(svds_plan *P, Arena &a) {
   return SVDS_OK;
 }
 
+// Test hook for the two out-of-memory fallbacks of plan creation: the
+// environment variable SVDS_TEST_NO_ROOM = "arena" makes the arena with a
+// column-panel copy fail to allocate (the plan is then carved without
+// panels), = "panel_items" makes the panel work items fail (the panels are
+// dropped after the arena was carved).  Unset in normal use.
+static bool test_no_room(const char *what) {
+  const char *e = std::getenv("SVDS_TEST_NO_ROOM");
+  return e && std::strcmp(e, what) == 0;
+}
+
 static int alloc_arena(svds_plan *P) {
   Arena a;
   a.counting = true;
   carve_all(P, a);
   const size_t bytes = a.used;
   void *base = nullptr;
+  if (P->op.npanel > 1 && test_no_room("arena")) return SVDS_ENOMEM;
   if (hipMalloc(&base, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return SVDS_ENOMEM;
@@ -1514,6 +1525,38 @@ static int sort_spmv(svds_plan *P, SpmvPlan &sp, const int32_t *col, const void 
                        col, static_cast<const float *>(val), sp.scol, static_cast<float *>(sp.sval), sp.spos);
   HIP_TRY(hipGetLastError());
   return SVDS_OK;
+}
+
+// Column panels dropped after the arena was carved: their region (row
+// pointers, indices, values and partial products of the stacked transpose)
+// takes the column-sorted copy of A^T instead when it fits (it does when
+// the stacked rows number at least about nnz / 6), so that the plain
+// transpose product runs as in a plan made without panels.  prows = the
+// stacked rows (n times the panel count the region was carved for).
+static int sorted_bwd_in_panel_region(svds_plan *P, int64_t prows) {
+  Operator &op = P->op;
+  char *r0 = reinterpret_cast<char *>(op.prp);
+  char *r1 = op.ypart ? reinterpret_cast<char *>(op.ypart + prows) : nullptr;
+  op.prp = op.pci = nullptr;
+  op.pval = nullptr;
+  op.ypart = nullptr;
+  if (!r0 || !r1 || op.bwd.spos || op.nnz == 0) return SVDS_OK;
+  const int64_t nz = op.nnz;
+  const size_t vb = static_cast<size_t>(vsize(op.vt));
+  Arena a;
+  a.take<int32_t>(nz);
+  a.take<char>(nz * vb);
+  a.take<uint16_t>(nz);
+  if (a.used > static_cast<size_t>(r1 - r0)) return SVDS_OK;
+  a.base = r0;
+  a.size = static_cast<size_t>(r1 - r0);
+  a.used = 0;
+  a.counting = false;
+  op.bwd.scol = a.take<int32_t>(nz);
+  op.bwd.sval = a.take<char>(nz * vb);
+  op.bwd.spos = a.take<uint16_t>(nz);
+  op.bwd.sorted = true;
+  return sort_spmv(P, op.bwd, op.tci, op.tval);
 }
 
 // Nonzeros per MULTI work item of the plan's products.
@@ -1708,6 +1751,7 @@ static int panels_finish(svds_plan *P, HostInts &hrp, hipEvent_t done) {
     sp.partials = ar.take<double>(std::max(1, sp.npieces));
   };
   carve_items(b);
+  if (test_no_room("panel_items")) return SVDS_ENOMEM;
   if (hipMalloc(&op.pbuf_items, b.used) != hipSuccess) {
     (void)hipGetLastError();
     op.pbuf_items = nullptr;
@@ -2259,7 +2303,9 @@ static int plan_create_csr_impl(const svds_csr *A, const svds_opts *opts, svds_p
   if (op.npanel > 1 && (rc = panels_finish(P, hprp, pdone.e))) {
     if (rc != SVDS_ENOMEM) return rc;
     HIP_TRY(hipStreamSynchronize(P->stream));
+    const int64_t prows = op.n * op.npanel;
     drop_panels();
+    if ((rc = sorted_bwd_in_panel_region(P, prows))) return rc;
   }
   // the uploads above read the host item lists, which the tuner rebuilds
   HIP_TRY(hipStreamSynchronize(P->stream));

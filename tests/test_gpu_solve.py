@@ -168,6 +168,41 @@ def test_parity_with_column_panel_transpose(S):
     assert info["max_res_true"] <= 2 * tol and info["max_res_est"] < tol
 
 
+@pytest.mark.parametrize("mode,draws", [("arena", 10), ("panel_items", 10), ("panel_items", 1)])
+def test_panel_fallbacks(S, mode, draws):
+    """The two out-of-memory fallbacks of plan creation, forced through the
+    SVDS_TEST_NO_ROOM hook on 300,001-row matrices that take two column
+    panels: 'arena' (no room for the arena with the panel copy: the plan is
+    carved without panels) and 'panel_items' (no room for the panel work
+    items: the panels are dropped after the arena was carved; their region
+    takes the column-sorted copy of A^T where it fits, as with one Zipf draw
+    per row, 5 nonzeros per stacked row, and not with ten draws).  Either
+    way the transposed product runs without panels and the solve is
+    bit-identical to a plan made without panels (SVDS_FLAG_NO_PANELS), with
+    oracle parity."""
+    import os
+    import torch
+    A = inputs.sparse_zipf(300_001, 30_000, draws, 1.1, seed=51 if draws == 10 else 53)
+    Ad, keep = S.csr_to_device(A)
+    k, p, tol = 8, 24, 1e-10
+    v0 = inputs.start_vector(A.n, 52 if draws == 10 else 54)
+    Ur, Sr, Vr, info_r = svds_ref.svds(as_operator(A), k, p, tol, 3000, v0=v0)
+    Un, Sn, Vn, info_n, st_n = _gpu_solve(S, A, k, p, tol, 3000, v0=v0, flags=S.SVDS_FLAG_NO_PANELS)
+    os.environ["SVDS_TEST_NO_ROOM"] = mode
+    try:
+        _, npan = S.svds_op_csr_matvec(Ad, True, torch.zeros(A.m, dtype=torch.float64, device="cuda"))
+        Ug, Sg, Vg, info, st = _gpu_solve(S, A, k, p, tol, 3000, v0=v0)
+    finally:
+        del os.environ["SVDS_TEST_NO_ROOM"]
+    assert npan == 1
+    assert st == 0 and st_n == 0 and info["converged"] == 1
+    assert np.array_equal(Sg, Sn) and np.array_equal(Ug, Un) and np.array_equal(Vg, Vn)
+    np.testing.assert_allclose(Sg, Sr, rtol=1e-10)
+    _invariants(A, Ug, Sg, Vg, tol)
+    if mode == "arena":
+        assert info["workspace_bytes"] == info_n["workspace_bytes"]
+
+
 @pytest.mark.parametrize("law", ["decay1", "decay2", "decay3"])
 def test_prescribed_spectrum(S, law):
     nb, bs = 400, 5
