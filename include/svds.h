@@ -322,7 +322,10 @@ typedef struct svds_plan svds_plan;
  * buffers are allocated at the start), and for CSR builds the transposed
  * copy A^T (CSR of A^T, entries of each column in increasing row order) on
  * the device.  `A` and the buffers it points to must stay alive and
- * unchanged until svds_plan_destroy.  `opts` is copied. */
+ * unchanged until svds_plan_destroy.  `opts` is copied.  Without room for
+ * the column-panel copy of A^T (or its work items) the plan falls back to
+ * the plain transpose product; the environment variable SVDS_TEST_NO_ROOM
+ * ("arena" or "panel_items") forces those fallbacks for tests. */
 int svds_plan_create_csr(const svds_csr *A, const svds_opts *opts, svds_plan **plan);
 int svds_plan_create_dense(const svds_dense *A, const svds_opts *opts, svds_plan **plan);
 
