@@ -24,14 +24,21 @@ constexpr int RS_BINS = 1 << RS_BITS;
 // perm[z] = z.  With rows_per_panel >= m every key is the column (the plain
 // transpose); with panels of rows the sort yields the stacked transpose
 // [A_0^T; A_1^T; ...], A_g = rows [g rpp, (g + 1) rpp) of A.
+// CSC_EXPAND_LANES lanes per row, each taking every CSC_EXPAND_LANES-th
+// entry, so that neighbouring lanes write neighbouring entries (one thread
+// per row wrote rows of ~100 entries with strided stores: 5.7 ms for the
+// 128M nonzeros of a 256-problem batch).
+constexpr int CSC_EXPAND_LANES = 16;
 static __global__ void csc_expand_kernel(int64_t m, const int32_t *__restrict__ row_ptr,
                                   const int32_t *__restrict__ col, int64_t rows_per_panel, int64_t n,
                                   int32_t *__restrict__ rowof, int32_t *__restrict__ keys,
                                   int32_t *__restrict__ perm) {
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = t / CSC_EXPAND_LANES;
   if (r >= m) return;
   const int32_t off = static_cast<int32_t>((r / rows_per_panel) * n);
-  for (int32_t z = row_ptr[r]; z < row_ptr[r + 1]; ++z) {
+  const int32_t z1 = row_ptr[r + 1];
+  for (int32_t z = row_ptr[r] + static_cast<int32_t>(t % CSC_EXPAND_LANES); z < z1; z += CSC_EXPAND_LANES) {
     rowof[z] = static_cast<int32_t>(r);
     keys[z] = col[z] + off;
     perm[z] = z;

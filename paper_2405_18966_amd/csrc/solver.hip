@@ -1480,8 +1480,8 @@ static int build_transpose(svds_plan *P, int npanel, int64_t rows_per_panel, int
   int32_t *hist = buf + 5 * nnz, *offs = hist + nh, *sums = offs + nh;
   int rc = SVDS_OK;
   do {
-    hipLaunchKernelGGL(csc_expand_kernel, dim3(ceil_div(m, 256)), dim3(256), 0, st, m, op.rp, op.ci,
-                       rows_per_panel, op.n, rowof, k0, v0);
+    hipLaunchKernelGGL(csc_expand_kernel, dim3(ceil_div(m * CSC_EXPAND_LANES, 256)), dim3(256), 0, st, m, op.rp,
+                       op.ci, rows_per_panel, op.n, rowof, k0, v0);
     if (hipGetLastError() != hipSuccess) { rc = SVDS_EDEVICE; break; }
     int bits = 1;
     while ((int64_t(1) << bits) < n) ++bits;
