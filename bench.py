@@ -468,6 +468,18 @@ def profile_section(which, S, inputs, np, torch):
             log(f"sparse2: {r.info['ms_total']:.1f} ms, cycles {r.info['cycles']}")
     elif which == "gather":
         gather_ceiling(S, inputs, np, torch)
+    elif which == "stream":
+        # attainable streaming rates on this GPU, beside which the CGS passes
+        # are judged: the library's FP64 copy (read + write) and a plain FP64
+        # read reduction (torch sum), both over 1.2 GB
+        n = 150 * 1_000_000
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            S.svds_op_copy_f64(src, dst)
+            s_ = src.sum()
+        torch.cuda.synchronize()
+        log(f"stream: {n * 8 / 1e9:.2f} GB copied and summed 5 times, sum {s_.item():.6e}")
     elif which == "breakdowns":
         d = np.zeros(500000)
         d[:30] = np.arange(30, 0, -1, dtype=np.float64)
@@ -517,13 +529,15 @@ def main():
                     help="skip the 2000 x 1000 sparse workload (k=10, p=30, tol=1e-10)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve + one plain copy (for rocprofv3 counter runs); no JSON")
-    ap.add_argument("--profile-section", choices=["dense", "batched", "sparse2", "gather", "config1", "breakdowns"],
+    ap.add_argument("--profile-section", choices=["dense", "batched", "sparse2", "gather", "config1", "breakdowns",
+                                                  "stream"],
                     help="only two solves of one other workload, for a rocprofv3 kernel trace: the "
                          "20000 x 10000 BF16 dense matrix (FP64 then mixed), the 256-problem batch (FP64), "
                          "or the paper's Sparse2 (40,000 x 40,000, k=100, p=300); 'gather': the Zipf "
                          "workload's products against the gather-copy reference; 'config1': three solves "
                          "of the 2000 x 1000 workload; 'breakdowns': a rank-30 1,000,000 x 500,000 matrix "
-                         "with one-workgroup and with wide breakdown repairs; no JSON")
+                         "with one-workgroup and with wide breakdown repairs; 'stream': the FP64 copy and "
+                         "read-reduction rates over 1.2 GB; no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver does not "
